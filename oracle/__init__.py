@@ -1,0 +1,316 @@
+"""CPU oracle for delta-based accumulative iterative computation (DAIC).
+
+TEST INFRASTRUCTURE ONLY: plain, slow, obviously correct implementations of
+what the GPU path computes, written from the paper (Zhang, Gao, Gao, Wang,
+"Maiter: An Asynchronous Graph Processing Framework for Delta-based Accumulative
+Iterative Computation"). Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package. It shares no code with
+the GPU library; only the seeded input generators (``daic_gen``) serve both.
+
+Contents
+--------
+* ``jacobi_sum``     -- traditional synchronous iteration (Eq. concurrent in the
+  form of Eq. decompose), FP64 pull over in-edges (C, OpenMP).
+* ``sync_daic_sum``  -- synchronous DAIC, Eq. sync (C, one thread).
+* ``async_run``      -- asynchronous DAIC, Eq. async, with priority (Sec. 3.4)
+  or round-robin (Sec. 5.1) scheduling, for sum, min and max (C, one thread).
+* ``dijkstra``       -- SSSP distances, the min problem's textbook answer.
+* ``maxlabel``       -- max-id reachability, the max problem's answer.
+* ``priority``       -- |v (+) dv - v| per vertex (Sec. 3.4 and Table 1 rows).
+* ``sampled_threshold`` / ``topk_exact`` -- the two selection rules of a round.
+* ``mlp_*``          -- FP64 forward/backward of the scheduler network.
+
+Parity status: every function here is pinned by tests under ``tests/`` except
+the ones listed as "parity unpinned" in their docstrings.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+OP_SUM, OP_MIN, OP_MAX = 0, 1, 2
+G_SRC_SCALE, G_EDGE_SCALE, G_EDGE_ADD, G_COPY, G_DEG_SCALE = 0, 1, 2, 3, 4
+SCHED_PRIORITY, SCHED_ROUND_ROBIN, SCHED_SWEEP = 0, 1, 2
+INF_U32 = 0xFFFFFFFF
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C++ part with g++ (OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        import subprocess
+
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+                               "-ffp-contract=off", os.path.join(_HERE, "oracle.cpp"), "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _get():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.orc_jacobi_sum.argtypes = [ctypes.c_uint64, _u64p, _u32p, _f64p, ctypes.c_int,
+                                       ctypes.c_double, _f64p, _f64p, _f64p, ctypes.c_double,
+                                       ctypes.c_int64, ctypes.c_int, _f64p, _f64p]
+        lib.orc_jacobi_sum.restype = ctypes.c_int64
+        lib.orc_sync_daic_sum.argtypes = [ctypes.c_uint64, _u64p, _u32p, _f64p, ctypes.c_int,
+                                          ctypes.c_double, _f64p, ctypes.c_double, ctypes.c_int64,
+                                          _f64p, _f64p, _f64p]
+        lib.orc_sync_daic_sum.restype = ctypes.c_int64
+        lib.orc_async.argtypes = [ctypes.c_uint64, _u64p, _u32p, _f64p, _u32p, ctypes.c_int,
+                                  ctypes.c_int, ctypes.c_double, _f64p, ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_int64, _f64p, _f64p, _u32p, _u32p,
+                                  _i32p, _i32p, _f64p, _f64p, ctypes.c_int64, ctypes.c_int64]
+        lib.orc_async.restype = ctypes.c_int64
+        lib.orc_dijkstra.argtypes = [ctypes.c_uint64, _u64p, _u32p, _u32p, ctypes.c_uint32, _u32p]
+        lib.orc_dijkstra.restype = ctypes.c_int
+        lib.orc_maxlabel.argtypes = [ctypes.c_uint64, _u64p, _u32p, _i32p]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _csr(g):
+    return (np.ascontiguousarray(g.row_ptr, dtype=np.uint64),
+            np.ascontiguousarray(g.col, dtype=np.uint32))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Graph solvers (C).
+# ---------------------------------------------------------------------------
+
+def jacobi_sum(g, gkind, alpha, dv1, v0=None, w=None, alpha_pv=None, eps=1e-13,
+               max_iter=100000, threads=0):
+    """Traditional synchronous iteration of a linear (sum) DAIC problem.
+
+    v^k_j = c_j + sum_{i->j} coef_ij v^{k-1}_i with c = v0 + dv1 - M^T v0 (the
+    fourth condition, Sec. 3.1), until sum|v^k - v^{k-1}| <= eps.
+    Returns (v, sweeps, last_diff).
+    """
+    rp, col = _csr(g)
+    n = g.n
+    dv1 = _f64(dv1)
+    v0 = np.zeros(n) if v0 is None else _f64(v0)
+    w, alpha_pv = _f64(w), _f64(alpha_pv)
+    out = np.empty(n, dtype=np.float64)
+    last = ctypes.c_double(0)
+    it = _get().orc_jacobi_sum(n, _ptr(rp, _u64p), _ptr(col, _u32p), _ptr(w, _f64p), gkind,
+                               alpha, _ptr(alpha_pv, _f64p), _ptr(v0, _f64p), _ptr(dv1, _f64p),
+                               eps, max_iter, threads, _ptr(out, _f64p), ctypes.byref(last))
+    return out, int(it), float(last.value)
+
+
+def sync_daic_sum(g, gkind, alpha, v0, dv1, w=None, alpha_pv=None, eps=1e-13, max_rounds=100000):
+    """Synchronous DAIC (Eq. sync). Returns (v, dv, rounds, residual)."""
+    rp, col = _csr(g)
+    v = np.array(v0, dtype=np.float64, copy=True)
+    dv = np.array(dv1, dtype=np.float64, copy=True)
+    w, alpha_pv = _f64(w), _f64(alpha_pv)
+    r = ctypes.c_double(0)
+    k = _get().orc_sync_daic_sum(g.n, _ptr(rp, _u64p), _ptr(col, _u32p), _ptr(w, _f64p), gkind,
+                                 alpha, _ptr(alpha_pv, _f64p), eps, max_rounds, _ptr(v, _f64p),
+                                 _ptr(dv, _f64p), ctypes.byref(r))
+    return v, dv, int(k), float(r.value)
+
+
+def async_run(g, op, gkind, v0, dv1, alpha=0.0, alpha_pv=None, w=None, sched=SCHED_PRIORITY,
+              eps=1e-13, max_updates=2**62, trace_every=0, trace_len=0):
+    """Asynchronous DAIC (Eq. async), one update at a time.
+
+    Returns dict(v, dv, updates, residual, trace). For op=sum the state is
+    FP64; for min it is uint32 (0xFFFFFFFF = infinity); for max int32.
+    """
+    rp, col = _csr(g)
+    n = g.n
+    lib = _get()
+    trace = np.zeros(max(trace_len, 0), dtype=np.float64)
+    r = ctypes.c_double(0)
+    wf = wu = None
+    if op == OP_SUM:
+        v = np.array(v0, dtype=np.float64, copy=True)
+        dv = np.array(dv1, dtype=np.float64, copy=True)
+        wf = _f64(w)
+        args = (_ptr(v, _f64p), _ptr(dv, _f64p), None, None, None, None)
+    elif op == OP_MIN:
+        v = np.array(v0, dtype=np.uint32, copy=True)
+        dv = np.array(dv1, dtype=np.uint32, copy=True)
+        wu = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
+        args = (None, None, _ptr(v, _u32p), _ptr(dv, _u32p), None, None)
+    else:
+        v = np.array(v0, dtype=np.int32, copy=True)
+        dv = np.array(dv1, dtype=np.int32, copy=True)
+        args = (None, None, None, None, _ptr(v, _i32p), _ptr(dv, _i32p))
+    upd = lib.orc_async(n, _ptr(rp, _u64p), _ptr(col, _u32p), _ptr(wf, _f64p), _ptr(wu, _u32p),
+                        op, gkind, alpha, _ptr(_f64(alpha_pv), _f64p), sched, eps, max_updates,
+                        *args, ctypes.byref(r), _ptr(trace, _f64p) if trace_len else None,
+                        trace_len, trace_every)
+    return dict(v=v, dv=dv, updates=int(upd), residual=float(r.value), trace=trace)
+
+
+def dijkstra(g, w, source):
+    """SSSP distances (uint32, 0xFFFFFFFF = unreachable) by Dijkstra."""
+    rp, col = _csr(g)
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    out = np.empty(g.n, dtype=np.uint32)
+    rc = _get().orc_dijkstra(g.n, _ptr(rp, _u64p), _ptr(col, _u32p), _ptr(w, _u32p), source,
+                             _ptr(out, _u32p))
+    if rc != 0:
+        raise OverflowError("a shortest distance does not fit in 32 bits")
+    return out
+
+
+def maxlabel(g):
+    """label_j = max({i : i reaches j} U {j}) (int32)."""
+    rp, col = _csr(g)
+    out = np.empty(g.n, dtype=np.int32)
+    _get().orc_maxlabel(g.n, _ptr(rp, _u64p), _ptr(col, _u32p), _ptr(out, _i32p))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Problem set-up helpers for the paper's algorithm table (Table 1).
+# ---------------------------------------------------------------------------
+
+def pagerank_init(n, d):
+    """PageRank: v0 = 0, dv1 = 1 - d (Sec. 3.1, fourth condition)."""
+    return np.zeros(n), np.full(n, 1.0 - d)
+
+
+def sssp_init(n, source):
+    """SSSP: v0 = inf, dv1 = 0 at the source, inf elsewhere (Table 1)."""
+    v0 = np.full(n, INF_U32, dtype=np.uint32)
+    dv1 = np.full(n, INF_U32, dtype=np.uint32)
+    dv1[source] = 0
+    return v0, dv1
+
+
+def cc_init(n):
+    """Connected components: v0 = -1, dv1_j = j (Table 1)."""
+    return np.full(n, -1, dtype=np.int32), np.arange(n, dtype=np.int32)
+
+
+def priority(op, v, dv):
+    """Scheduling priority |v (+) dv - v| (Sec. 3.4); SSSP form d - min(d, dd)
+    with inf - x taken as 0xFFFFFFFF (Sec. 4.2.1)."""
+    if op == OP_SUM:
+        return np.abs(np.asarray(dv, dtype=np.float64))
+    if op == OP_MIN:
+        v = np.asarray(v, dtype=np.uint64)
+        dv = np.asarray(dv, dtype=np.uint64)
+        mn = np.minimum(v, dv)
+        p = v - mn
+        first = (v == INF_U32) & (mn < INF_U32)
+        p = np.where(v == INF_U32, np.where(first, INF_U32, 0), p)
+        return p.astype(np.uint64)
+    v = np.asarray(v, dtype=np.int64)
+    dv = np.asarray(dv, dtype=np.int64)
+    return (np.maximum(v, dv) - v).astype(np.int64)
+
+
+def topk_exact(p, q):
+    """Exact selection of a round: the k = ceil(q n) largest priorities, ties to
+    the smaller id, restricted to pending vertices (p > 0) (Sec. 5.1, priority
+    queue as a portion of the state table)."""
+    p = np.asarray(p)
+    n = p.shape[0]
+    k = int(np.ceil(q * n))
+    order = np.lexsort((np.arange(n), -p.astype(np.float64)))
+    chosen = order[:k]
+    return np.sort(chosen[p[chosen] > 0])
+
+
+def splitmix64(seed, counters):
+    """SplitMix64 outputs (Steele, Lea, Flood 2014): output number c of the
+    generator seeded with `seed` is mix(seed + (c + 1) * 0x9E3779B97F4A7C15)."""
+    g = np.uint64(0x9E3779B97F4A7C15)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.asarray(counters, dtype=np.uint64) + np.uint64(1)) * g
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def sample_indices(n, n_samples, seed, round_no):
+    """Indices sampled in a round: sample i of round t is output number
+    t*S + i of SplitMix64(seed), reduced mod n."""
+    c = np.uint64(round_no) * np.uint64(n_samples) + np.arange(n_samples, dtype=np.uint64)
+    return (splitmix64(seed, c) % np.uint64(n)).astype(np.int64)
+
+
+def sampled_threshold(p, q, n_samples, seed, round_no):
+    """Sampled selection threshold (the PrIter-style O(N) extraction cited in
+    Sec. 5.1): tau = the ceil(q S)-th largest of the S sampled priorities; when
+    that is not positive, tau = the smallest positive priority (take all
+    pending). A round selects p_j >= tau with p_j > 0."""
+    p = np.asarray(p)
+    idx = sample_indices(p.shape[0], n_samples, seed, round_no)
+    s = np.sort(p[idx])[::-1]
+    rank = max(1, int(np.ceil(q * n_samples)))
+    tau = s[rank - 1]
+    if not tau > 0:
+        pos = p[p > 0]
+        tau = pos.min() if pos.size else 0
+    return tau
+
+
+# ---------------------------------------------------------------------------
+# Scheduler network: 3 -> 64 -> 64 -> 1, ReLU, BCE-with-logits, FP64.
+# ---------------------------------------------------------------------------
+
+def mlp_forward(params, x):
+    """Returns (logits[N], cache). params = dict(W1[64,3], b1[64], W2[64,64],
+    b2[64], W3[1,64], b3[1]); x = [N, 3]."""
+    x = np.asarray(x, dtype=np.float64)
+    z1 = x @ params["W1"].T + params["b1"]
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ params["W2"].T + params["b2"]
+    h2 = np.maximum(z2, 0.0)
+    z3 = h2 @ params["W3"].T + params["b3"]
+    return z3[:, 0], (x, z1, h1, z2, h2)
+
+
+def bce_with_logits(logits, y):
+    """Mean binary cross-entropy of sigmoid(logits) against labels y."""
+    z = np.asarray(logits, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    return float(np.mean(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
+
+
+def mlp_backward(params, cache, logits, y):
+    """Gradients of the mean BCE-with-logits loss w.r.t. every parameter."""
+    x, z1, h1, z2, h2 = cache
+    n = x.shape[0]
+    y = np.asarray(y, dtype=np.float64)
+    dz3 = (1.0 / (1.0 + np.exp(-logits)) - y)[:, None] / n          # [N,1]
+    g = {"W3": dz3.T @ h2, "b3": dz3.sum(0)}
+    dh2 = dz3 @ params["W3"]
+    dz2 = dh2 * (z2 > 0)
+    g["W2"] = dz2.T @ h1
+    g["b2"] = dz2.sum(0)
+    dh1 = dz2 @ params["W2"]
+    dz1 = dh1 * (z1 > 0)
+    g["W1"] = dz1.T @ x
+    g["b1"] = dz1.sum(0)
+    return g

@@ -1,0 +1,515 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check here compares the oracle with something other than itself: a value
+worked out by hand from the paper's equations (tests/golden), a closed form, a
+library routine (LAPACK solve, scipy's Dijkstra and connected components), a
+brute-force search on tiny inputs, or an invariant that holds exactly.
+
+Which plausible oracle mistake each pin catches:
+* dense-solve / golden PageRank: wrong divisor (receiver's instead of sender's
+  out-degree, Table 1 typo), dropped constant c, transposed operand;
+* mass conservation and the per-vertex state identity: a lost or double-counted
+  delta in the update step (Eq. async);
+* Dijkstra / Bellman-Ford / golden SSSP: wrong (+) or g for the min problem;
+* brute-force reachability / golden CC: wrong direction of propagation;
+* Katz closed form: missing l = 0 term, wrong power of beta.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import daic_gen
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def read_golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            key, *vals = line.split()
+            out[key] = vals
+    return out
+
+
+def random_graph(n, m, seed, self_loops=True):
+    """Small multigraph with duplicates, self-loops and dangling vertices."""
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, m)
+    dst = rng.integers(0, n, m)
+    if not self_loops:
+        keep = src != dst
+        src, dst = src[keep], dst[keep]
+    # leave a few vertices without out-edges
+    dead = rng.choice(n, max(1, n // 10), replace=False)
+    keep = ~np.isin(src, dead)
+    return daic_gen.from_edges(n, src[keep], dst[keep])
+
+
+def dense_pagerank(g, d):
+    """Solve (I - M^T) v = (1-d) 1 with M_jk = d * (#edges j->k) / outdeg_j."""
+    n = g.n
+    deg = g.outdeg()
+    M = np.zeros((n, n))
+    for j in range(n):
+        for e in range(int(g.row_ptr[j]), int(g.row_ptr[j + 1])):
+            M[j, g.col[e]] += d / deg[j]
+    return np.linalg.solve(np.eye(n) - M.T, np.full(n, 1.0 - d))
+
+
+# ---------------------------------------------------------------------------
+# Sum problems (PageRank, Katz)
+# ---------------------------------------------------------------------------
+
+def test_golden_pagerank_3node():
+    gd = read_golden("pagerank_3node.txt")
+    e = list(map(int, gd["edges"]))
+    g = daic_gen.from_edges(3, e[0::2], e[1::2])
+    d = float(gd["d"][0])
+    want = np.array(list(map(float, gd["fixed_point_num"]))) / float(gd["fixed_point_den"][0])
+    v0, dv1 = oracle.pagerank_init(3, d)
+    v, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1, eps=1e-15)
+    np.testing.assert_allclose(v, want, rtol=0, atol=1e-13)
+    for sched in (oracle.SCHED_PRIORITY, oracle.SCHED_ROUND_ROBIN):
+        r = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d, sched=sched,
+                             eps=1e-15)
+        np.testing.assert_allclose(r["v"], want, rtol=0, atol=1e-13)
+    vs, _, _, _ = oracle.sync_daic_sum(g, oracle.G_DEG_SCALE, d, v0, dv1, eps=1e-15)
+    np.testing.assert_allclose(vs, want, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pagerank_matches_dense_solve(seed):
+    g = random_graph(150, 900, seed)
+    d = 0.8
+    want = dense_pagerank(g, d)
+    v0, dv1 = oracle.pagerank_init(g.n, d)
+    vj, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1, eps=1e-14)
+    vs, _, _, _ = oracle.sync_daic_sum(g, oracle.G_DEG_SCALE, d, v0, dv1, eps=1e-14)
+    vp = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d, eps=1e-14)["v"]
+    vr = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d, eps=1e-14,
+                          sched=oracle.SCHED_ROUND_ROBIN)["v"]
+    for v in (vj, vs, vp, vr):
+        assert np.abs(v - want).sum() <= 1e-12 * g.n
+
+
+def test_pagerank_north_star_normalization():
+    """(I - d W^T) x = (1-d)/n 1 is the paper's solution divided by n."""
+    g = daic_gen.powerlaw(n=300, seed=11)
+    d = 0.8
+    n = g.n
+    W = np.zeros((n, n))
+    deg = g.outdeg()
+    for j in range(n):
+        for e in range(int(g.row_ptr[j]), int(g.row_ptr[j + 1])):
+            W[j, g.col[e]] += 1.0 / deg[j]
+    x = np.linalg.solve(np.eye(n) - d * W.T, np.full(n, (1 - d) / n))
+    v, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, np.full(n, 1 - d), eps=1e-14)
+    np.testing.assert_allclose(v / n, x, rtol=1e-11, atol=1e-15)
+
+
+def test_closed_forms_pagerank():
+    d = 0.8
+    # directed cycle: every vertex keeps rank 1
+    n = 17
+    cyc = daic_gen.from_edges(n, np.arange(n), (np.arange(n) + 1) % n)
+    v, _, _ = oracle.jacobi_sum(cyc, oracle.G_DEG_SCALE, d, np.full(n, 1 - d), eps=1e-15)
+    np.testing.assert_allclose(v, 1.0, atol=1e-13)
+    # edgeless: only the constant remains
+    empty = daic_gen.from_edges(5, [], [])
+    v, _, _ = oracle.jacobi_sum(empty, oracle.G_DEG_SCALE, d, np.full(5, 1 - d))
+    np.testing.assert_allclose(v, 1 - d, atol=0)
+    # no dangling vertex: total rank equals n (Sec. 6.4: sum R grows from 0.2 N to N)
+    g = random_graph(200, 1500, 7)
+    deg = g.outdeg()
+    if (deg == 0).any():  # add a self-loop to every dangling vertex
+        extra = np.nonzero(deg == 0)[0]
+        src = np.concatenate([np.repeat(np.arange(g.n), deg), extra])
+        dst = np.concatenate([g.col, extra])
+        g = daic_gen.from_edges(g.n, src, dst)
+    r = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, np.zeros(g.n),
+                         np.full(g.n, 1 - d), alpha=d, eps=1e-12)
+    assert abs(r["v"].sum() - g.n) <= 1e-11 * g.n
+
+
+def test_golden_katz_cycle():
+    gd = read_golden("katz_cycle4.txt")
+    e = list(map(int, gd["edges"]))
+    g = daic_gen.from_edges(4, e[0::2], e[1::2])
+    beta = float(gd["beta"][0])
+    s = int(gd["source"][0])
+    want = np.array(list(map(float, gd["fixed_point_num"]))) / float(gd["fixed_point_den"][0])
+    dv1 = np.zeros(4)
+    dv1[s] = 1.0
+    v, _, _ = oracle.jacobi_sum(g, oracle.G_SRC_SCALE, beta, dv1, eps=1e-16)
+    np.testing.assert_allclose(v, want, atol=1e-14)
+    r = oracle.async_run(g, oracle.OP_SUM, oracle.G_SRC_SCALE, np.zeros(4), dv1, alpha=beta,
+                         eps=1e-16)
+    np.testing.assert_allclose(r["v"], want, atol=1e-14)
+
+
+def test_edge_scale_matches_dense_solve():
+    """Adsorption-style g(x) = a_j w_jk x with per-vertex a_j and log-normal w."""
+    g = random_graph(80, 500, 3)
+    w = daic_gen.lognormal_f64(17, g.m, 0.4, 0.8)
+    deg = g.outdeg()
+    # scale so that every row sums to at most 0.9: a contraction
+    rowsum = np.add.reduceat(w, g.row_ptr[:-1].astype(np.int64)) if g.m else np.zeros(g.n)
+    rowsum = np.where(deg > 0, rowsum, 1.0)
+    a = 0.9 / rowsum
+    M = np.zeros((g.n, g.n))
+    for j in range(g.n):
+        for e in range(int(g.row_ptr[j]), int(g.row_ptr[j + 1])):
+            M[j, g.col[e]] += a[j] * w[e]
+    c = daic_gen.lognormal_f64(18, g.n, 0.0, 1.0)
+    want = np.linalg.solve(np.eye(g.n) - M.T, c)
+    v, _, _ = oracle.jacobi_sum(g, oracle.G_EDGE_SCALE, 0.0, c, w=w, alpha_pv=a, eps=1e-14)
+    np.testing.assert_allclose(v, want, rtol=1e-11)
+    r = oracle.async_run(g, oracle.OP_SUM, oracle.G_EDGE_SCALE, np.zeros(g.n), c, alpha_pv=a,
+                         w=w, eps=1e-14)
+    np.testing.assert_allclose(r["v"], want, rtol=1e-11)
+
+
+def test_nonzero_v0_uses_fourth_condition():
+    """Any (v0, dv1) with v0 + dv1 = f(v0) reaches the same fixed point."""
+    g = random_graph(60, 300, 5)
+    d = 0.8
+    want = dense_pagerank(g, d)
+    rng = np.random.default_rng(0)
+    v0 = rng.uniform(0, 2, g.n)
+    # f(v0) = c + M^T v0, so dv1 = f(v0) - v0
+    deg = g.outdeg()
+    mtv = np.zeros(g.n)
+    for j in range(g.n):
+        for e in range(int(g.row_ptr[j]), int(g.row_ptr[j + 1])):
+            mtv[g.col[e]] += d / deg[j] * v0[j]
+    dv1 = (1 - d) + mtv - v0
+    v, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1, v0=v0, eps=1e-14)
+    np.testing.assert_allclose(v, want, atol=1e-11)
+    r = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d, eps=1e-14)
+    np.testing.assert_allclose(r["v"], want, atol=1e-11)
+
+
+@pytest.mark.parametrize("updates", [1, 37, 400, 5000])
+@pytest.mark.parametrize("sched", [oracle.SCHED_PRIORITY, oracle.SCHED_ROUND_ROBIN])
+def test_mass_conservation_and_state_identity(updates, sched):
+    """At every point of an asynchronous run (Eq. async), exactly in reals:
+    sum_j dv_j + sum_j (1 - s_j) v_j = sum_j dv1_j   (s_j = d, or 0 if dangling)
+    and per vertex v + dv = c + M^T v with c = dv1 (v0 = 0)."""
+    g = random_graph(120, 700, 9)
+    d = 0.8
+    n = g.n
+    deg = g.outdeg()
+    v0, dv1 = oracle.pagerank_init(n, d)
+    r = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d, sched=sched,
+                         eps=0.0, max_updates=updates)
+    v, dv = r["v"], r["dv"]
+    s = np.where(deg > 0, d, 0.0)
+    lhs = dv.sum() + ((1 - s) * v).sum()
+    assert abs(lhs - dv1.sum()) <= 1e-12 * dv1.sum()
+    mtv = np.zeros(n)
+    for j in range(n):
+        for e in range(int(g.row_ptr[j]), int(g.row_ptr[j + 1])):
+            mtv[g.col[e]] += d / deg[j] * v[j]
+    np.testing.assert_allclose(v + dv, dv1 + mtv, rtol=1e-12, atol=1e-13)
+
+
+def test_progress_is_monotone_and_bounded():
+    """sum_j v_j grows monotonically from 0.2 N towards its limit (Sec. 3.4, 6.4)."""
+    g = daic_gen.powerlaw(n=400, seed=4)
+    d = 0.8
+    v0, dv1 = oracle.pagerank_init(g.n, d)
+    r = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d, eps=1e-12,
+                         trace_every=1, trace_len=20000)
+    tr = r["trace"][: min(r["updates"], 20000)]
+    assert np.all(np.diff(tr) >= -1e-12)
+    want = dense_pagerank(g, d)
+    assert tr[-1] <= want.sum() + 1e-9
+
+
+def test_residual_bound():
+    """For PageRank ||v* - v||_1 <= r / (1 - d) at any state (r = sum |dv|)."""
+    g = random_graph(100, 600, 12)
+    d = 0.8
+    want = dense_pagerank(g, d)
+    v0, dv1 = oracle.pagerank_init(g.n, d)
+    for upd in (10, 100, 1000):
+        r = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d, eps=0.0,
+                             max_updates=upd)
+        err = np.abs(want - r["v"]).sum()
+        assert err <= r["residual"] / (1 - d) * (1 + 1e-9) + 1e-12
+
+
+def test_theorem2_async_closer_than_sync_per_vertex():
+    """Same synchronous update sequence: after k subsequences the asynchronous
+    state is per vertex at least as close to the fixed point (Theorem 2)."""
+    g = daic_gen.powerlaw(n=300, seed=21)
+    d = 0.8
+    want = dense_pagerank(g, d)
+    v0, dv1 = oracle.pagerank_init(g.n, d)
+    for k in (1, 2, 5, 10):
+        vs, _, _, _ = oracle.sync_daic_sum(g, oracle.G_DEG_SCALE, d, v0, dv1, eps=0.0,
+                                           max_rounds=k)
+        ra = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d,
+                              sched=oracle.SCHED_SWEEP, eps=0.0, max_updates=k * g.n)
+        assert np.all(np.abs(want - ra["v"]) <= np.abs(want - vs) + 1e-12)
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33])
+def test_theorem4_priority_ahead_of_round_robin_in_l1(seed):
+    """After the same number of updates, priority scheduling is at least as
+    close to the fixed point as round-robin, in aggregate L1 (Theorem 4)."""
+    g = daic_gen.powerlaw(n=500, seed=seed)
+    d = 0.8
+    want = dense_pagerank(g, d)
+    v0, dv1 = oracle.pagerank_init(g.n, d)
+    for upd in (250, 1000, 4000):
+        rp = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d, eps=0.0,
+                              max_updates=upd)
+        rr = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d, eps=0.0,
+                              max_updates=upd, sched=oracle.SCHED_ROUND_ROBIN)
+        assert np.abs(want - rp["v"]).sum() <= np.abs(want - rr["v"]).sum()
+
+
+# ---------------------------------------------------------------------------
+# Min problem (SSSP)
+# ---------------------------------------------------------------------------
+
+def bellman_ford(n, src, dst, w, s):
+    inf = float("inf")
+    dist = [inf] * n
+    dist[s] = 0
+    for _ in range(n):
+        changed = False
+        for a, b, c in zip(src, dst, w):
+            if dist[a] + c < dist[b]:
+                dist[b] = dist[a] + c
+                changed = True
+        if not changed:
+            break
+    return [0xFFFFFFFF if x == inf else int(x) for x in dist]
+
+
+def test_golden_sssp():
+    gd = read_golden("sssp_5node.txt")
+    e = list(map(int, gd["edges"]))
+    src, dst, w = e[0::3], e[1::3], e[2::3]
+    g = daic_gen.from_edges(5, src, dst)
+    # from_edges sorts edges by (src, dst); carry the weights along
+    order = np.lexsort((dst, src))
+    w = np.asarray(w, dtype=np.uint32)[order]
+    want = np.array(list(map(int, gd["dist"])), dtype=np.uint32)
+    s = int(gd["source"][0])
+    np.testing.assert_array_equal(oracle.dijkstra(g, w, s), want)
+    v0, dv1 = oracle.sssp_init(5, s)
+    for sched in (oracle.SCHED_PRIORITY, oracle.SCHED_ROUND_ROBIN):
+        r = oracle.async_run(g, oracle.OP_MIN, oracle.G_EDGE_ADD, v0, dv1, w=w, sched=sched)
+        np.testing.assert_array_equal(r["v"], want)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dijkstra_vs_bellman_ford_and_scipy(seed):
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra as sp_dijkstra
+
+    rng = np.random.default_rng(seed)
+    n, m = 60, 240
+    src = rng.integers(0, n, m)
+    dst = rng.integers(0, n, m)
+    w = rng.integers(1, 256, m).astype(np.uint32)
+    order = np.lexsort((dst, src))
+    src, dst, w = src[order], dst[order], w[order]
+    g = daic_gen.from_edges(n, src, dst)
+    got = oracle.dijkstra(g, w, 0)
+    np.testing.assert_array_equal(got, bellman_ford(n, src, dst, w, 0))
+    # scipy sums duplicate entries, so keep only the lightest parallel edge
+    best = {}
+    for a, b, c in zip(src, dst, w):
+        if a != b:
+            best[(a, b)] = min(best.get((a, b), 1 << 40), int(c))
+    keys = list(best)
+    A = csr_matrix(([best[k] for k in keys], ([k[0] for k in keys], [k[1] for k in keys])),
+                   shape=(n, n))
+    ref = sp_dijkstra(A, indices=0)
+    ref = np.where(np.isinf(ref), 0xFFFFFFFF, ref).astype(np.uint64)
+    np.testing.assert_array_equal(got.astype(np.uint64), ref)
+
+
+def test_async_min_matches_dijkstra_on_rmat():
+    g = daic_gen.rmat(12, 8, seed=42)
+    w = daic_gen.sssp_weights(g.m, seed=43)
+    want = oracle.dijkstra(g, w, 0)
+    v0, dv1 = oracle.sssp_init(g.n, 0)
+    for sched in (oracle.SCHED_PRIORITY, oracle.SCHED_ROUND_ROBIN):
+        r = oracle.async_run(g, oracle.OP_MIN, oracle.G_EDGE_ADD, v0, dv1, w=w, sched=sched)
+        np.testing.assert_array_equal(r["v"], want)
+        assert r["residual"] == 0
+
+
+def test_sssp_path_graph_prefix_sums():
+    n = 50
+    g = daic_gen.from_edges(n, np.arange(n - 1), np.arange(1, n))
+    w = daic_gen.sssp_weights(g.m, seed=5)
+    want = np.concatenate([[0], np.cumsum(w.astype(np.uint64))]).astype(np.uint32)
+    np.testing.assert_array_equal(oracle.dijkstra(g, w, 0), want)
+
+
+# ---------------------------------------------------------------------------
+# Max problem (connected components)
+# ---------------------------------------------------------------------------
+
+def test_golden_cc():
+    gd = read_golden("cc_6node.txt")
+    e = list(map(int, gd["edges"]))
+    g = daic_gen.from_edges(6, e[0::2], e[1::2])
+    want = np.array(list(map(int, gd["directed_labels"])), dtype=np.int32)
+    np.testing.assert_array_equal(oracle.maxlabel(g), want)
+    v0, dv1 = oracle.cc_init(6)
+    r = oracle.async_run(g, oracle.OP_MAX, oracle.G_COPY, v0, dv1)
+    np.testing.assert_array_equal(r["v"], want)
+
+
+def test_maxlabel_vs_bruteforce_reachability():
+    rng = np.random.default_rng(3)
+    n, m = 40, 70
+    src, dst = rng.integers(0, n, m), rng.integers(0, n, m)
+    g = daic_gen.from_edges(n, src, dst)
+    adj = [[] for _ in range(n)]
+    for a, b in zip(src, dst):
+        adj[a].append(b)
+    want = np.arange(n, dtype=np.int32)
+    for s in range(n):
+        seen, stack = {s}, [s]
+        while stack:
+            u = stack.pop()
+            for x in adj[u]:
+                if x not in seen:
+                    seen.add(x)
+                    stack.append(x)
+        for x in seen:
+            want[x] = max(want[x], s)
+    np.testing.assert_array_equal(oracle.maxlabel(g), want)
+
+
+def test_maxlabel_symmetric_equals_components():
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    g0 = daic_gen.rmat(10, 2, seed=8)
+    src = np.repeat(np.arange(g0.n), g0.outdeg())
+    dst = g0.col.astype(np.int64)
+    g = daic_gen.from_edges(g0.n, np.concatenate([src, dst]), np.concatenate([dst, src]))
+    A = csr_matrix((np.ones(len(src)), (src, dst)), shape=(g0.n, g0.n))
+    ncomp, lab = connected_components(A, directed=True, connection="weak")
+    comp_max = np.full(ncomp, -1)
+    np.maximum.at(comp_max, lab, np.arange(g0.n))
+    want = comp_max[lab].astype(np.int32)
+    np.testing.assert_array_equal(oracle.maxlabel(g), want)
+    v0, dv1 = oracle.cc_init(g.n)
+    r = oracle.async_run(g, oracle.OP_MAX, oracle.G_COPY, v0, dv1)
+    np.testing.assert_array_equal(r["v"], want)
+
+
+# ---------------------------------------------------------------------------
+# Selection rules and priorities
+# ---------------------------------------------------------------------------
+
+def test_priority_rows_of_table1():
+    # sum: |dv|
+    np.testing.assert_array_equal(oracle.priority(oracle.OP_SUM, [1.0, 2.0], [-0.5, 0.25]),
+                                  [0.5, 0.25])
+    # SSSP: d - min(d, dd), first reach -> 0xFFFFFFFF, nothing pending -> 0
+    inf = oracle.INF_U32
+    p = oracle.priority(oracle.OP_MIN, [inf, inf, 10, 10], [inf, 7, 3, 12])
+    np.testing.assert_array_equal(p, [0, inf, 7, 0])
+    # CC: max(v, dv) - v
+    np.testing.assert_array_equal(oracle.priority(oracle.OP_MAX, [-1, 5, 5], [3, 9, 2]),
+                                  [4, 4, 0])
+
+
+def test_topk_exact_bruteforce():
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        n = int(rng.integers(1, 60))
+        p = rng.integers(0, 5, n).astype(np.float64)  # many ties and zeros
+        q = float(rng.uniform(0.01, 1.0))
+        k = int(np.ceil(q * n))
+        ranked = sorted(range(n), key=lambda j: (-p[j], j))[:k]
+        want = sorted(j for j in ranked if p[j] > 0)
+        np.testing.assert_array_equal(oracle.topk_exact(p, q), want)
+
+
+def test_splitmix64_reference_values():
+    """First outputs of SplitMix64 seeded with 1234567, the published test
+    sequence of the Rosetta Code "Pseudo-random numbers/Splitmix64" task."""
+    got = oracle.splitmix64(1234567, np.arange(5))
+    want = np.array([6457827717110365317, 3203168211198807973, 9817491932198370423,
+                     4593380528125082431, 16408922859458223821], dtype=np.uint64)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_sampled_threshold_properties():
+    rng = np.random.default_rng(2)
+    p = rng.exponential(1.0, 100000)
+    p[rng.random(p.size) < 0.3] = 0.0
+    # q = 1: every pending vertex is selected
+    tau = oracle.sampled_threshold(p, 1.0, 4096, 9, 0)
+    assert tau == p[p > 0].min()
+    # q = 0.1: the selected fraction is close to q (sampling error ~ 1/sqrt(S))
+    tau = oracle.sampled_threshold(p, 0.1, 4096, 9, 3)
+    frac = np.mean(p >= tau)
+    assert abs(frac - 0.1) < 0.02
+    # no positive sample: take all pending
+    p2 = np.zeros(1000)
+    p2[5] = 1.0
+    assert oracle.sampled_threshold(p2, 0.01, 64, 1, 0) == 1.0
+
+
+# ---------------------------------------------------------------------------
+# Scheduler network
+# ---------------------------------------------------------------------------
+
+def test_mlp_gradients_match_finite_differences():
+    rng = np.random.default_rng(0)
+    params = {"W1": rng.normal(0, 0.5, (64, 3)), "b1": rng.normal(0, 0.1, 64),
+              "W2": rng.normal(0, 0.2, (64, 64)), "b2": rng.normal(0, 0.1, 64),
+              "W3": rng.normal(0, 0.2, (1, 64)), "b3": rng.normal(0, 0.1, 1)}
+    x = rng.normal(0, 1, (32, 3))
+    y = (rng.random(32) < 0.4).astype(np.float64)
+    z, cache = oracle.mlp_forward(params, x)
+    grads = oracle.mlp_backward(params, cache, z, y)
+    h = 1e-6
+    for name, p in params.items():
+        flat = p.reshape(-1)
+        for idx in rng.choice(flat.size, min(flat.size, 12), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = oracle.bce_with_logits(oracle.mlp_forward(params, x)[0], y)
+            flat[idx] = old - h
+            lm = oracle.bce_with_logits(oracle.mlp_forward(params, x)[0], y)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = grads[name].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (name, idx, fd, an)
+
+
+def test_generators_are_deterministic_and_shaped():
+    a = daic_gen.rmat(10, 4, seed=3)
+    b = daic_gen.rmat(10, 4, seed=3)
+    np.testing.assert_array_equal(a.row_ptr, b.row_ptr)
+    np.testing.assert_array_equal(a.col, b.col)
+    assert a.m == 4 * 1024 and a.row_ptr[-1] == a.m
+    assert all(np.all(np.diff(a.col[a.row_ptr[i]:a.row_ptr[i + 1]].astype(np.int64)) >= 0)
+               for i in range(a.n))
+    pl = daic_gen.powerlaw(n=2000, seed=1)
+    deg = pl.outdeg()
+    assert deg.max() <= 500
+    for j in range(pl.n):  # no self-loop, no duplicate per source
+        row = pl.col[pl.row_ptr[j]:pl.row_ptr[j + 1]]
+        assert j not in row and len(set(row.tolist())) == len(row)
