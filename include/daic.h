@@ -1,0 +1,175 @@
+/*
+ * daic.h -- C ABI of libdaic, an MI355X (gfx950) implementation of the
+ * per-round delta propagation of delta-based accumulative iterative
+ * computation (DAIC).
+ *
+ * Method: Zhang, Gao, Gao, Wang, "Maiter: An Asynchronous Graph Processing
+ * Framework for Delta-based Accumulative Iterative Computation".
+ *   - A problem is the tuple (g_{j,k}, (+), v^0, dv^1) of Sec. 3.1 and Table 1:
+ *     an operator (+) that is commutative and associative with an identity 0
+ *     (third condition; identity property in Sec. 3.2), a per-edge function g
+ *     distributive over (+) (second condition), and initial values that meet
+ *     the fourth condition v^0 (+) dv^1 = f(v^0).
+ *   - One round applies the asynchronous update of Eq. async (Sec. 3.2) to the
+ *     vertices chosen by priority |v_j (+) dv_j - v_j| (Sec. 3.4):
+ *        delta = dv_j;  dv_j = 0;  v_j = v_j (+) delta;
+ *        for every out-edge (j,k): dv_k = dv_k (+) g_{j,k}(delta)   [skip if = 0]
+ *     The chosen set is the top portion q of the state table (Sec. 5.1,
+ *     priority queue), found exactly or by sampling.
+ *   - The run stops when the pending residual falls to eps (sum problems) or
+ *     when no vertex is pending (min/max problems); cf. the termination check
+ *     of Sec. 5.1 and Sec. 6.1.3.
+ *
+ * The three calls of the paper's API (Sec. 5.2) map as follows: the
+ * Partitioner's input parsing is the CSR load (daic_graph_create*), the
+ * IterateKernel's init/accumulate/send are set by daic_problem_create (op, g)
+ * and daic_problem_set_init, and the TermChecker is the residual threshold of
+ * daic_run_opts.
+ *
+ * Conventions
+ *   - Status: 0 = success; 1 = DAIC_NOT_CONVERGED (a warning, the state is
+ *     valid); negative = failure, in which case no output buffer is written.
+ *     daic_last_error() returns a thread-local message for the last failure.
+ *   - Ownership: host arrays passed in are copied; the caller keeps them.
+ *     daic_graph_create_device borrows device pointers that must outlive the
+ *     graph handle. Handles are released by the matching *_destroy call.
+ *   - Threads: calls on one handle must not run concurrently; distinct handles
+ *     are independent.
+ *   - CSR: row_ptr[n+1] (uint64, monotone, row_ptr[0] = 0, row_ptr[n] = m),
+ *     col[m] (uint32, every entry < n). Each entry is one edge: duplicates and
+ *     self-loops are kept and count towards the out-degree.
+ */
+#ifndef DAIC_H
+#define DAIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DAIC_OK = 0,
+  DAIC_NOT_CONVERGED = 1, /* max_rounds reached; state valid, stats filled */
+  DAIC_E_INVALID = -1,    /* bad argument (message in daic_last_error)     */
+  DAIC_E_UNSUPPORTED = -2,/* (+)/g/dtype combination not offered           */
+  DAIC_E_OOM = -3,        /* device allocation failed                      */
+  DAIC_E_DEVICE = -4      /* HIP runtime error                             */
+} daic_status;
+
+/* The accumulation operator (+) (Sec. 3.1, third condition) and its identity
+ * 0: 0 for SUM, 0xFFFFFFFF (infinity) for MIN, -1 for MAX. */
+typedef enum { DAIC_SUM = 0, DAIC_MIN = 1, DAIC_MAX = 2 } daic_op;
+
+/* The per-edge function g_{j,k} (Table 1). a_j is alpha_per_vertex[j] when
+ * given, else alpha_scalar.
+ *   SRC_SCALE : g(x) = a_j * x               Katz (beta), HITS-like rows
+ *   DEG_SCALE : g(x) = alpha * x / outdeg_j  PageRank (d / |N(j)|, sender degree)
+ *   EDGE_SCALE: g(x) = a_j * w_jk * x        Adsorption, weighted linear sums
+ *   EDGE_ADD  : g(x) = x + w_jk (saturating) SSSP
+ *   COPY      : g(x) = x                     connected components            */
+typedef enum {
+  DAIC_G_SRC_SCALE = 0,
+  DAIC_G_EDGE_SCALE = 1,
+  DAIC_G_EDGE_ADD = 2,
+  DAIC_G_COPY = 3,
+  DAIC_G_DEG_SCALE = 4
+} daic_g;
+
+/* Element types. F32_KAHAN keeps v in FP32 with a compensation term (Kahan
+ * summation); deltas and pushes are FP32 and the residual is reduced in FP64. */
+typedef enum {
+  DAIC_F64 = 0,
+  DAIC_F32 = 1,
+  DAIC_F32_KAHAN = 2,
+  DAIC_U32 = 3,
+  DAIC_I32 = 4,
+  DAIC_NONE = 5
+} daic_dtype;
+
+/* Selection rule of a round (Sec. 3.4 priority scheduling, Sec. 5.1 queue).
+ *   ALL          : every pending vertex (a synchronous DAIC round, Eq. sync)
+ *   TOPK_EXACT   : the ceil(q n) largest priorities, ties to the smaller id
+ *   TOPK_SAMPLED : threshold = ceil(q S)-th largest of S sampled priorities
+ *   LEARNED      : top ceil(q n) by priority x sigmoid(network score)        */
+typedef enum {
+  DAIC_SCHED_ALL = 0,
+  DAIC_SCHED_TOPK_EXACT = 1,
+  DAIC_SCHED_TOPK_SAMPLED = 2,
+  DAIC_SCHED_LEARNED = 3
+} daic_sched;
+
+typedef struct daic_graph daic_graph;
+typedef struct daic_problem daic_problem;
+typedef struct daic_batch daic_batch;
+typedef struct daic_trace daic_trace;
+typedef struct daic_sched_model daic_sched_model;
+
+typedef struct {
+  double eps;                 /* stop when the residual <= eps (sum problems)  */
+  double priority_fraction;   /* q in (0, 1]; portion of the state table      */
+  daic_sched sched;           /* selection rule                                */
+  uint64_t max_rounds;        /* DAIC_NOT_CONVERGED once reached               */
+  uint32_t rounds_per_check;  /* rounds per host check of the residual (>= 1)  */
+  uint32_t n_samples;         /* S for TOPK_SAMPLED (0 = 4096; max 4096)       */
+  uint64_t seed;              /* sampling seed                                 */
+  void* hip_stream;           /* hipStream_t to run on (NULL = default stream) */
+  const daic_sched_model* model; /* network for DAIC_SCHED_LEARNED           */
+} daic_run_opts;
+
+typedef struct {
+  uint64_t rounds;            /* rounds that did work                          */
+  uint64_t activations;       /* vertex updates performed                      */
+  uint64_t pushed_edges;      /* messages sent (out-edges of updated vertices) */
+  double final_residual;      /* sum |dv| (sum) or pending count (min/max)     */
+  double time_ms;             /* device time of the round loop                 */
+  double gteps;               /* pushed_edges / time / 1e9                     */
+  double alg_bytes;           /* algorithmic bytes moved by the round loop     */
+} daic_stats;
+
+/* ---- Graphs --------------------------------------------------------------
+ * daic_graph_create: host CSR, copied to the device. w may be NULL (w_type
+ * DAIC_NONE) or hold m weights of type w_type (F64, F32 or U32).
+ * daic_graph_create_device: the same arrays already on the device (e.g. torch
+ * tensors); they are borrowed, not copied, and validated on the device.   */
+daic_status daic_graph_create(uint64_t n, uint64_t m, const uint64_t* row_ptr, const uint32_t* col,
+                              const void* w, daic_dtype w_type, daic_graph** out);
+daic_status daic_graph_create_device(uint64_t n, uint64_t m, const uint64_t* d_row_ptr,
+                                     const uint32_t* d_col, const void* d_w, daic_dtype w_type,
+                                     void* hip_stream, daic_graph** out);
+void daic_graph_destroy(daic_graph* g);
+
+/* ---- Problems ------------------------------------------------------------
+ * Allowed combinations (second and third conditions):
+ *   SUM x {SRC_SCALE, DEG_SCALE, EDGE_SCALE} x {F64, F32, F32_KAHAN}
+ *   MIN x EDGE_ADD x U32 (weights U32)      MAX x COPY x I32
+ * alpha_per_vertex: NULL or n doubles (SRC_SCALE and EDGE_SCALE only).
+ * The new problem holds v = 0 and dv = 0 (identity); call set_init.       */
+daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, double alpha_scalar,
+                                const double* alpha_per_vertex, daic_dtype state,
+                                daic_problem** out);
+/* v0, dv1: n host values each, typed double for FP states, uint32 for U32,
+ * int32 for I32. The fourth condition v0 (+) dv1 = f(v0) is the caller's. */
+daic_status daic_problem_set_init(daic_problem* p, const void* v0, const void* dv1);
+/* Run rounds until the stop rule holds (DAIC_OK) or max_rounds (warning). */
+daic_status daic_run(daic_problem* p, const daic_run_opts* opts, daic_stats* stats);
+/* Copy the state out: v_out (n values; double for FP states, where F32_KAHAN
+ * reports v - c in FP64), dv_out nullable (same type). */
+daic_status daic_problem_get(const daic_problem* p, void* v_out, void* dv_out);
+void daic_problem_destroy(daic_problem* p);
+
+const char* daic_last_error(void);
+
+/* ---- Device-side round pieces, exposed for unit tests --------------------
+ * daic_select_frontier runs the selection of one round on the current state
+ * without updating it and writes the 0/1 selection of every vertex to
+ * sel_out (n host bytes). threshold_out (nullable) receives the threshold as
+ * a double. round selects the sample stream of TOPK_SAMPLED.              */
+daic_status daic_select_frontier(daic_problem* p, const daic_run_opts* opts, uint64_t round,
+                                 uint8_t* sel_out, double* threshold_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DAIC_H */

@@ -1,0 +1,97 @@
+// Internal declarations shared by the translation units of libdaic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "daic.h"
+
+namespace daic {
+
+// ---- error handling --------------------------------------------------------
+void set_error(const char* fmt, ...);
+daic_status fail(daic_status s, const char* fmt, ...);
+
+#define DAIC_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t _e = (call);                                                              \
+    if (_e != hipSuccess)                                                                \
+      return ::daic::fail(_e == hipErrorOutOfMemory ? DAIC_E_OOM : DAIC_E_DEVICE,        \
+                          "%s failed: %s (%s:%d)", #call, hipGetErrorString(_e), __FILE__, \
+                          __LINE__);                                                     \
+  } while (0)
+
+// ---- tuning constants --------------------------------------------------------
+constexpr int kScanBlock = 256;       // threads per block of the per-vertex kernels
+constexpr int kMaxScanBlocks = 2048;  // blocks of the per-vertex kernels (upper bound)
+constexpr uint32_t kSmallMaxDeg = 32; // out-degree bound of the small bin
+constexpr uint32_t kChunk = 1024;     // edges per item of the large bin
+constexpr uint32_t kMaxSamples = 4096;
+constexpr uint32_t kInfU32 = 0xFFFFFFFFu;
+
+// ---- device control block -----------------------------------------------------
+// One per problem, in device memory. Written by the round kernels, read by the
+// host once per check.
+struct Ctl {
+  double r;              // residual of the current state
+  double eps;            // stop threshold for sum problems
+  uint64_t pending;      // number of pending vertices of the current state
+  uint64_t rounds;       // rounds that did work
+  uint64_t max_rounds;   // absolute round limit
+  uint64_t activations;  // vertex updates performed
+  uint64_t pushed;       // messages sent
+  uint64_t n_small;      // items in the small bin this round
+  uint64_t n_large;      // items in the large bin this round
+  uint32_t done;         // stop rule holds
+  uint32_t stop;         // round limit reached
+  uint32_t ticket;       // last-block detection
+  uint32_t sel_mode;     // 0 all pending; 1 key >= tau; 2 key > tau, or == tau within ties
+  uint64_t tau;          // threshold key of this round
+  uint64_t ties_left;    // keys equal to tau to take (sel_mode 2)
+  uint64_t k_rem;        // radix select: rank still to place
+  uint64_t radix_prefix; // radix select: key bits fixed so far
+  uint32_t radix_skip;   // radix select: nothing to do (all pending fit)
+  uint32_t pad;
+  uint32_t hist[256];    // radix select histogram
+};
+
+// Compile-time identity of a (op, g, state, row) instantiation.
+enum StateKind { ST_F64 = 0, ST_F32 = 1, ST_F32K = 2, ST_U32 = 3, ST_I32 = 4 };
+
+struct GraphDev {
+  uint64_t n = 0, m = 0;
+  const void* row = nullptr;   // uint32 or uint64 row offsets (n+1)
+  bool row32 = false;
+  const uint32_t* col = nullptr;
+  const void* w = nullptr;     // weights as given
+  daic_dtype w_type = DAIC_NONE;
+};
+
+// Vertex partition of the per-vertex kernels: block b owns vertices
+// [b*per_block, min(n, (b+1)*per_block)).
+struct Partition {
+  uint32_t blocks = 0;
+  uint64_t per_block = 0;
+};
+
+// Learned scheduler hooks (defined with the scheduler network).
+daic_status learned_prepare(daic_problem* p, const daic_sched_model* model, hipStream_t s);
+daic_status learned_scores(daic_problem* p, const daic_sched_model* model, hipStream_t s,
+                           const float** score);
+void learned_after_round(daic_problem* p, hipStream_t s);
+
+}  // namespace daic
+
+struct daic_graph {
+  daic::GraphDev dev;
+  void* own_row = nullptr;      // owned allocations (null when borrowed)
+  void* own_col = nullptr;
+  void* own_w = nullptr;
+  void* row32 = nullptr;        // narrowed copy of row_ptr when m < 2^32
+  daic::Partition part;
+  uint64_t* large_off = nullptr;  // device [blocks+1]: large-bin region start per block
+  uint64_t large_cap = 0;
+};

@@ -1,0 +1,715 @@
+// Device code of one DAIC round on gfx950 (64-lane wavefronts).
+//
+// A round (Eq. async of the paper applied to a selected set, Sec. 3.2/3.4):
+//   A2 k_sample / k_radix_* : threshold of the priority keys (sampled or exact)
+//   A3+A4 k_claim           : select, claim dv_j, fold v_j (+)= delta, compute
+//                             the message base mu_j, compact into degree bins
+//   k_bin_scan              : prefix of the per-block bin counts
+//   A5 k_push_small/large   : atomic (+) of g(mu_j) into dv_k for every out-edge
+//   A1 k_residual           : residual of the new state and the stop rule
+// The claim happens in a kernel of its own, before any push of the round, so
+// every message of the round lands in dv after the claim: it is folded in a
+// later round and never lost (the receive/update split of Eq. async).
+#pragma once
+
+#include "daic_internal.h"
+
+namespace daic {
+
+// ---------------------------------------------------------------------------
+// Element types of each state kind.
+// ---------------------------------------------------------------------------
+template <int ST> struct Tr;
+template <> struct Tr<ST_F64> { using S = double;   using Key = uint64_t; static constexpr bool sum = true;  static constexpr bool kahan = false; };
+template <> struct Tr<ST_F32> { using S = float;    using Key = uint32_t; static constexpr bool sum = true;  static constexpr bool kahan = false; };
+template <> struct Tr<ST_F32K>{ using S = float;    using Key = uint32_t; static constexpr bool sum = true;  static constexpr bool kahan = true;  };
+template <> struct Tr<ST_U32> { using S = uint32_t; using Key = uint32_t; static constexpr bool sum = false; static constexpr bool kahan = false; };
+template <> struct Tr<ST_I32> { using S = int32_t;  using Key = uint32_t; static constexpr bool sum = false; static constexpr bool kahan = false; };
+
+// Kernel arguments (passed by value).
+struct KArgs {
+  Ctl* ctl;
+  const void* row;          // RowT[n+1]
+  const uint32_t* col;      // [m]
+  const void* w;            // S[m] (EDGE_SCALE) or uint32[m] (EDGE_ADD)
+  void* v;                  // S[n]
+  void* dv;                 // S[n]
+  float* c;                 // Kahan compensation [n]
+  const void* alpha_pv;     // S[n] or null
+  double alpha;
+  uint64_t n;
+  uint64_t per_block;
+  uint32_t blocks;
+  uint32_t* small_vid;      // [n], block b's region starts at b*per_block
+  void* small_mu;           // S[n]
+  uint32_t* large_vid;      // [large_cap], block b's region starts at large_off[b]
+  uint32_t* large_chunk;
+  void* large_mu;
+  const uint64_t* large_off;  // [blocks+1]
+  uint32_t* blk_small;      // per-block counts of this round
+  uint32_t* blk_large;
+  uint64_t* off_small;      // [blocks+1] prefix of blk_small
+  uint64_t* off_large;      // [blocks+1] prefix of blk_large
+  uint64_t* blk_act;        // per-block activations / pushed edges
+  uint64_t* blk_push;
+  uint32_t* blk_ties;       // exact top-k: keys equal to tau per block
+  uint64_t* off_ties;       // exclusive prefix of blk_ties
+  double* part_r;           // residual partials per block
+  uint64_t* part_n;         // pending-count partials per block
+  uint8_t* sel_out;         // dry selection output [n]
+  const float* score;       // learned scheduler: multiplier in (0,1) per vertex, or null
+};
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ bool ctl_halted(const Ctl* ctl) {
+  return (ctl->done | ctl->stop) != 0;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output number c of the generator
+// seeded with `seed`.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// Priority |v (+) dv - v| as an unsigned key whose integer order is the order
+// of the priority (Sec. 3.4; SSSP form d - min(d, dd) of Sec. 4.2.1 with
+// inf - x taken as 0xFFFFFFFF; CC form max(v, dv) - v). Key 0 = not pending.
+// ---------------------------------------------------------------------------
+template <int ST>
+__device__ __forceinline__ typename Tr<ST>::Key prio_key(typename Tr<ST>::S v, typename Tr<ST>::S dv) {
+  if constexpr (ST == ST_F64) {
+    return (uint64_t)__double_as_longlong(fabs(dv));
+  } else if constexpr (ST == ST_F32 || ST == ST_F32K) {
+    return __float_as_uint(fabsf(dv));
+  } else if constexpr (ST == ST_U32) {
+    if (v == kInfU32) return dv < kInfU32 ? kInfU32 : 0u;
+    return v - (dv < v ? dv : v);
+  } else {
+    int64_t mx = (int64_t)(dv > v ? dv : v);
+    return (uint32_t)(mx - (int64_t)v);
+  }
+}
+
+// Key used by the selection: the priority, or for the learned scheduler the
+// priority scaled by the network's multiplier (FP32, same bit-order trick).
+template <int ST>
+__device__ __forceinline__ typename Tr<ST>::Key sel_key(const KArgs& a, uint64_t j, typename Tr<ST>::S v,
+                                                         typename Tr<ST>::S dv) {
+  using Key = typename Tr<ST>::Key;
+  Key k = prio_key<ST>(v, dv);
+  if (a.score != nullptr && k != 0) {
+    float p;
+    if constexpr (ST == ST_F64) p = (float)fabs(dv);
+    else if constexpr (ST == ST_F32 || ST == ST_F32K) p = fabsf(dv);
+    else p = (float)k;
+    float s = p * a.score[j];
+    uint32_t b = __float_as_uint(s);
+    return (Key)(b == 0 ? 1u : b);  // a pending vertex keeps a positive key
+  }
+  return k;
+}
+
+// ---------------------------------------------------------------------------
+// Wave and block scans (64-lane waves, blocks of 256 threads = 4 waves).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+// Exclusive block scan of up to three counters at once; returns the block
+// totals through tot[]. Every thread of the block must call it.
+template <int NV>
+__device__ __forceinline__ void block_excl_scan(uint32_t (&x)[NV], uint32_t (&tot)[NV]) {
+  __shared__ uint32_t s_w[4][NV];
+  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  uint32_t incl[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    incl[i] = wave_incl_scan(x[i]);
+    if (lane == 63) s_w[wave][i] = incl[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    uint32_t off = 0, t = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      uint32_t c = s_w[w][i];
+      off += (w < (int)wave) ? c : 0u;
+      t += c;
+    }
+    x[i] = off + incl[i] - x[i];
+    tot[i] = t;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum256(T x) {
+  __shared__ T s_w[4];
+  x = wave_sum(x);
+  if (lane_id() == 0) s_w[threadIdx.x >> 6] = x;
+  __syncthreads();
+  T t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+  __syncthreads();
+  return t;
+}
+
+template <typename RowT>
+__device__ __forceinline__ uint64_t row_at(const void* row, uint64_t j) {
+  return (uint64_t)static_cast<const RowT*>(row)[j];
+}
+
+// Index b with off[b] <= i < off[b+1] (off has nb+1 entries, off[0] = 0).
+__device__ __forceinline__ uint32_t find_block(const uint64_t* off, uint32_t nb, uint64_t i) {
+  uint32_t lo = 0, hi = nb;  // invariant: off[lo] <= i < off[hi]
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// A4: claim and fold. Returns whether j sends, and the message base mu.
+// ---------------------------------------------------------------------------
+template <int ST, int G>
+__device__ __forceinline__ bool claim_fold(const KArgs& a, uint64_t j, uint64_t deg,
+                                           typename Tr<ST>::S v_old, typename Tr<ST>::S delta,
+                                           typename Tr<ST>::S& mu) {
+  using S = typename Tr<ST>::S;
+  S* v = static_cast<S*>(a.v);
+  S* dv = static_cast<S*>(a.dv);
+  if constexpr (Tr<ST>::sum) {
+    dv[j] = (S)0;
+    if constexpr (Tr<ST>::kahan) {
+      // Compensated summation (Kahan 1965): the rounding error of each fold
+      // is carried in c_j and subtracted from the next delta.
+#pragma clang fp contract(off)
+      float cj = a.c[j];
+      float y = delta - cj;
+      float t = v_old + y;
+      a.c[j] = (t - v_old) - y;
+      v[j] = t;
+    } else {
+      v[j] = v_old + delta;
+    }
+    double coef;
+    if constexpr (G == DAIC_G_DEG_SCALE) {
+      coef = a.alpha / (double)deg;
+    } else {
+      coef = a.alpha_pv ? (double)static_cast<const S*>(a.alpha_pv)[j] : a.alpha;
+    }
+    mu = (S)(coef * (double)delta);
+    return delta != (S)0;
+  } else if constexpr (ST == ST_U32) {
+    dv[j] = kInfU32;
+    if (delta < v_old) {
+      v[j] = delta;
+      mu = delta;
+      return true;
+    }
+    return false;
+  } else {
+    dv[j] = -1;
+    if (delta > v_old) {
+      v[j] = delta;
+      mu = delta;
+      return true;
+    }
+    return false;
+  }
+}
+
+// A5: one message along edge e into dv[k] (skipping identity messages and,
+// for min/max, messages that cannot change the receiver).
+template <int ST, int G>
+__device__ __forceinline__ void push_edge(const KArgs& a, uint64_t e, typename Tr<ST>::S mu) {
+  using S = typename Tr<ST>::S;
+  const uint32_t k = a.col[e];
+  S* dv = static_cast<S*>(a.dv);
+  if constexpr (Tr<ST>::sum) {
+    S m = mu;
+    if constexpr (G == DAIC_G_EDGE_SCALE) m = mu * static_cast<const S*>(a.w)[e];
+    if (m != (S)0) unsafeAtomicAdd(&dv[k], m);
+  } else if constexpr (ST == ST_U32) {
+    uint64_t s = (uint64_t)mu + static_cast<const uint32_t*>(a.w)[e];
+    uint32_t m = s >= kInfU32 ? kInfU32 : (uint32_t)s;
+    const uint32_t* v = static_cast<const uint32_t*>(a.v);
+    if (m < v[k] && m < dv[k]) atomicMin(&dv[k], m);
+  } else {
+    const int32_t* v = static_cast<const int32_t*>(a.v);
+    if (mu > v[k] && mu > dv[k]) atomicMax(&dv[k], mu);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A1: residual of the current state and the stop rule. Deterministic: block
+// partials are summed by the last block in a fixed order.
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round) {
+  using S = typename Tr<ST>::S;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  const uint32_t b = blockIdx.x;
+  const uint64_t lo = (uint64_t)b * a.per_block;
+  const uint64_t hi = min(a.n, lo + a.per_block);
+  const S* v = static_cast<const S*>(a.v);
+  const S* dv = static_cast<const S*>(a.dv);
+  double r = 0.0;
+  uint64_t cnt = 0;
+  for (uint64_t j = lo + threadIdx.x; j < hi; j += 256) {
+    S dj = dv[j];
+    if constexpr (Tr<ST>::sum) {
+      double x = fabs((double)dj);
+      r += x;
+      cnt += x > 0.0;
+    } else {
+      cnt += prio_key<ST>(v[j], dj) != 0;
+    }
+  }
+  r = block_sum256(r);
+  cnt = block_sum256(cnt);
+  __shared__ uint32_t s_last;
+  if (threadIdx.x == 0) {
+    a.part_r[b] = r;
+    a.part_n[b] = cnt;
+    __threadfence();
+    uint32_t t = atomicAdd(&ctl->ticket, 1u);
+    s_last = (t == a.blocks - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double rr = 0.0;
+  uint64_t nn = 0;
+  for (uint32_t i = threadIdx.x; i < a.blocks; i += 256) {
+    rr += __hip_atomic_load(&a.part_r[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    nn += __hip_atomic_load(&a.part_n[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  rr = block_sum256(rr);
+  nn = block_sum256(nn);
+  if (threadIdx.x == 0) {
+    if constexpr (Tr<ST>::sum) ctl->r = rr; else ctl->r = (double)nn;
+    ctl->pending = nn;
+    ctl->rounds += (uint64_t)count_round;
+    bool done = Tr<ST>::sum ? (rr <= ctl->eps || nn == 0) : (nn == 0);
+    ctl->done = done ? 1u : 0u;
+    ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
+    ctl->ticket = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A2 (sampled): threshold = the rank-th largest of S sampled keys; a
+// threshold of 0 (no positive sample) selects every pending vertex.
+// ---------------------------------------------------------------------------
+template <int ST>
+__global__ __launch_bounds__(1024) void k_sample(KArgs a, uint32_t S_n, uint32_t rank, uint64_t seed,
+                                                 uint64_t round_override) {
+  using S = typename Tr<ST>::S;
+  using Key = typename Tr<ST>::Key;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  __shared__ Key keys[kMaxSamples];
+  const uint64_t round = round_override != ~0ull ? round_override : ctl->rounds;
+  const S* v = static_cast<const S*>(a.v);
+  const S* dv = static_cast<const S*>(a.dv);
+  uint32_t P = 1;
+  while (P < S_n) P <<= 1;
+  for (uint32_t i = threadIdx.x; i < P; i += 1024) {
+    Key k = 0;
+    if (i < S_n) {
+      uint64_t j = splitmix64_at(seed, round * (uint64_t)S_n + i) % a.n;
+      k = sel_key<ST>(a, j, v[j], dv[j]);
+    }
+    keys[i] = k;
+  }
+  __syncthreads();
+  // bitonic sort, descending
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < P; i += 1024) {
+        uint32_t pr = i ^ stride;
+        if (pr > i) {
+          bool desc = (i & size) == 0;
+          Key x = keys[i], y = keys[pr];
+          if (desc ? (x < y) : (x > y)) {
+            keys[i] = y;
+            keys[pr] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    Key tau = keys[rank - 1];
+    ctl->sel_mode = tau == 0 ? 0u : 1u;
+    ctl->tau = (uint64_t)tau;
+  }
+}
+
+// Selection of every pending vertex (DAIC_SCHED_ALL).
+__global__ void k_select_all(Ctl* ctl) {
+  ctl->sel_mode = 0;
+  ctl->tau = 0;
+}
+
+// ---------------------------------------------------------------------------
+// A2 (exact): radix select of the k-th largest key, 8 bits per pass, most
+// significant digit first. Ties at the k-th key go to the smaller ids.
+// ---------------------------------------------------------------------------
+__global__ void k_topk_init(Ctl* ctl, uint64_t k) {
+  if (ctl_halted(ctl)) return;
+  if (ctl->pending <= k) {
+    ctl->sel_mode = 0;
+    ctl->radix_skip = 1;
+  } else {
+    ctl->sel_mode = 2;
+    ctl->radix_skip = 0;
+    ctl->k_rem = k;
+    ctl->radix_prefix = 0;
+  }
+  for (int i = 0; i < 256; ++i) ctl->hist[i] = 0;
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_radix_hist(KArgs a, int pass) {
+  using S = typename Tr<ST>::S;
+  using Key = typename Tr<ST>::Key;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl) || ctl->radix_skip) return;
+  constexpr int kBits = sizeof(Key) * 8;
+  const int shift = kBits - 8 * (pass + 1);
+  const Key hi_mask = pass == 0 ? (Key)0 : (Key)(~(Key)0 << (shift + 8));
+  const Key prefix = (Key)ctl->radix_prefix;
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const S* v = static_cast<const S*>(a.v);
+  const S* dv = static_cast<const S*>(a.dv);
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < a.n; j += stride) {
+    Key k = sel_key<ST>(a, j, v[j], dv[j]);
+    if (k != 0 && (k & hi_mask) == prefix) atomicAdd(&h[(k >> shift) & 255], 1u);
+  }
+  __syncthreads();
+  uint32_t c = h[threadIdx.x];
+  if (c) atomicAdd(&ctl->hist[threadIdx.x], c);
+}
+
+template <int ST>
+__global__ void k_radix_pick(Ctl* ctl, int pass) {
+  using Key = typename Tr<ST>::Key;
+  if (ctl_halted(ctl) || ctl->radix_skip) return;
+  constexpr int kBits = sizeof(Key) * 8;
+  const int shift = kBits - 8 * (pass + 1);
+  uint64_t k = ctl->k_rem;
+  uint64_t cum = 0;
+  int d = 255;
+  for (; d > 0; --d) {
+    uint64_t c = ctl->hist[d];
+    if (cum + c >= k) break;
+    cum += c;
+  }
+  ctl->k_rem = k - cum;
+  ctl->radix_prefix |= (uint64_t)d << shift;
+  for (int i = 0; i < 256; ++i) ctl->hist[i] = 0;
+  if (shift == 0) {
+    ctl->tau = ctl->radix_prefix;
+    ctl->ties_left = ctl->k_rem;
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_tie_count(KArgs a) {
+  using S = typename Tr<ST>::S;
+  using Key = typename Tr<ST>::Key;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl) || ctl->sel_mode != 2) return;
+  const Key tau = (Key)ctl->tau;
+  const uint64_t lo = (uint64_t)blockIdx.x * a.per_block;
+  const uint64_t hi = min(a.n, lo + a.per_block);
+  const S* v = static_cast<const S*>(a.v);
+  const S* dv = static_cast<const S*>(a.dv);
+  uint32_t cnt = 0;
+  for (uint64_t j = lo + threadIdx.x; j < hi; j += 256) cnt += sel_key<ST>(a, j, v[j], dv[j]) == tau;
+  cnt = block_sum256(cnt);
+  if (threadIdx.x == 0) a.blk_ties[blockIdx.x] = cnt;
+}
+
+// Exclusive prefix of per-block counts (one block of 1024 threads).
+__device__ __forceinline__ void excl_prefix_1024(const uint32_t* in, uint64_t* out, uint32_t nb,
+                                                 uint64_t* total) {
+  __shared__ uint64_t s_w[16];
+  __shared__ uint64_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < nb; base += 1024) {
+    uint32_t i = base + threadIdx.x;
+    uint64_t x = i < nb ? in[i] : 0;
+    // wave inclusive scan in 64 bits
+    uint64_t s = x;
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint64_t y = __shfl_up(s, d, 64);
+      if (lane >= (uint32_t)d) s += y;
+    }
+    if (lane == 63) s_w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    uint64_t off = s_carry;
+    for (uint32_t w = 0; w < (threadIdx.x >> 6); ++w) off += s_w[w];
+    if (i < nb) out[i] = off + s - x;
+    __syncthreads();
+    if (threadIdx.x == 1023) s_carry = off + s;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[nb] = s_carry;
+    if (total) *total = s_carry;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_tie_scan(KArgs a) {
+  if (ctl_halted(a.ctl) || a.ctl->sel_mode != 2) return;
+  excl_prefix_1024(a.blk_ties, a.off_ties, a.blocks, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// A3+A4: select, claim, fold and compact into the two degree bins. Block b
+// owns a fixed vertex range and writes its items into fixed regions, so no
+// global atomics are needed and the item order is the vertex order.
+// DRY = true only writes the selection (unit tests).
+// ---------------------------------------------------------------------------
+template <int ST, int G, typename RowT, bool DRY>
+__global__ __launch_bounds__(256) void k_claim(KArgs a) {
+  using S = typename Tr<ST>::S;
+  using Key = typename Tr<ST>::Key;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  const uint32_t b = blockIdx.x;
+  const uint64_t lo = (uint64_t)b * a.per_block;
+  const uint64_t hi = min(a.n, lo + a.per_block);
+  const uint32_t mode = ctl->sel_mode;
+  const Key tau = (Key)ctl->tau;
+  const uint64_t ties_left = ctl->ties_left;
+  const uint64_t tie_base = mode == 2 ? a.off_ties[b] : 0;
+  const S* v = static_cast<const S*>(a.v);
+  const S* dv = static_cast<const S*>(a.dv);
+  S* small_mu = static_cast<S*>(a.small_mu);
+  S* large_mu = static_cast<S*>(a.large_mu);
+  const uint64_t large_base = DRY ? 0 : a.large_off[b];
+  uint64_t ties_seen = 0, n_small = 0, n_large = 0, act = 0, pushed = 0;
+
+  for (uint64_t base = lo; base < hi; base += 256) {
+    const uint64_t j = base + threadIdx.x;
+    const bool in = j < hi;
+    S vj{}, dj{};
+    Key key = 0;
+    if (in) {
+      vj = v[j];
+      dj = dv[j];
+      key = sel_key<ST>(a, j, vj, dj);
+    }
+    const bool pend = key != 0;
+    uint32_t tie[1] = {(mode == 2 && pend && key == tau) ? 1u : 0u};
+    uint32_t tie_tot[1];
+    if (mode == 2) block_excl_scan<1>(tie, tie_tot); else tie_tot[0] = 0;
+    bool sel = false;
+    if (pend) {
+      if (mode == 0) sel = true;
+      else if (mode == 1) sel = key >= tau;
+      else sel = key > tau || (key == tau && tie_base + ties_seen + tie[0] < ties_left);
+    }
+    ties_seen += tie_tot[0];
+    if constexpr (DRY) {
+      if (in) a.sel_out[j] = sel ? 1 : 0;
+      continue;
+    }
+    uint64_t beg = 0, deg = 0;
+    bool send = false;
+    S mu{};
+    if (sel) {
+      beg = row_at<RowT>(a.row, j);
+      deg = row_at<RowT>(a.row, j + 1) - beg;
+      send = claim_fold<ST, G>(a, j, deg, vj, dj, mu) && deg > 0;
+    }
+    uint32_t cnt[2] = {(send && deg <= kSmallMaxDeg) ? 1u : 0u,
+                       (send && deg > kSmallMaxDeg) ? (uint32_t)((deg + kChunk - 1) / kChunk) : 0u};
+    uint32_t tot[2];
+    block_excl_scan<2>(cnt, tot);
+    if (send) {
+      if (deg <= kSmallMaxDeg) {
+        uint64_t pos = lo + n_small + cnt[0];
+        a.small_vid[pos] = (uint32_t)j;
+        small_mu[pos] = mu;
+      } else {
+        uint32_t nch = (uint32_t)((deg + kChunk - 1) / kChunk);
+        uint64_t pos = large_base + n_large + cnt[1];
+        for (uint32_t c = 0; c < nch; ++c) {
+          a.large_vid[pos + c] = (uint32_t)j;
+          a.large_chunk[pos + c] = c;
+          large_mu[pos + c] = mu;
+        }
+      }
+    }
+    n_small += tot[0];
+    n_large += tot[1];
+    act += sel ? 1 : 0;
+    pushed += send ? deg : 0;
+  }
+  if constexpr (!DRY) {
+    act = block_sum256(act);
+    pushed = block_sum256(pushed);
+    if (threadIdx.x == 0) {
+      a.blk_small[b] = (uint32_t)n_small;
+      a.blk_large[b] = (uint32_t)n_large;
+      a.blk_act[b] = act;
+      a.blk_push[b] = pushed;
+    }
+  }
+}
+
+// Prefix of the bin counts and the round's work counters (one block).
+__global__ __launch_bounds__(1024) void k_bin_scan(KArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  excl_prefix_1024(a.blk_small, a.off_small, a.blocks, &ctl->n_small);
+  __syncthreads();
+  excl_prefix_1024(a.blk_large, a.off_large, a.blocks, &ctl->n_large);
+  __syncthreads();
+  uint64_t act = 0, push = 0;
+  for (uint32_t i = threadIdx.x; i < a.blocks; i += 1024) {
+    act += a.blk_act[i];
+    push += a.blk_push[i];
+  }
+  act = wave_sum(act);
+  push = wave_sum(push);
+  __shared__ uint64_t s_a[16], s_p[16];
+  if (lane_id() == 0) {
+    s_a[threadIdx.x >> 6] = act;
+    s_p[threadIdx.x >> 6] = push;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t ta = 0, tp = 0;
+    for (int w = 0; w < 16; ++w) {
+      ta += s_a[w];
+      tp += s_p[w];
+    }
+    ctl->activations += ta;
+    ctl->pushed += tp;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A5, small bin (out-degree 1..32): one wave (= one block of 64) takes 64
+// items and spreads their concatenated edges over its lanes, so lanes stay
+// busy whatever the degree mix and column reads stay contiguous.
+// ---------------------------------------------------------------------------
+template <int ST, int G, typename RowT>
+__global__ __launch_bounds__(64) void k_push_small(KArgs a) {
+  using S = typename Tr<ST>::S;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  const uint64_t total = ctl->n_small;
+  __shared__ uint8_t owner[64 * kSmallMaxDeg];
+  __shared__ uint32_t s_excl[64];
+  __shared__ uint64_t s_beg[64];
+  __shared__ S s_mu[64];
+  const uint32_t lane = threadIdx.x;
+  const S* small_mu = static_cast<const S*>(a.small_mu);
+  for (uint64_t g = blockIdx.x; g * 64 < total; g += gridDim.x) {
+    const uint64_t i = g * 64 + lane;
+    uint32_t deg = 0;
+    uint64_t beg = 0;
+    S mu{};
+    if (i < total) {
+      uint32_t blk = find_block(a.off_small, a.blocks, i);
+      uint64_t idx = (uint64_t)blk * a.per_block + (i - a.off_small[blk]);
+      uint32_t vid = a.small_vid[idx];
+      mu = small_mu[idx];
+      beg = row_at<RowT>(a.row, vid);
+      deg = (uint32_t)(row_at<RowT>(a.row, vid + 1) - beg);
+    }
+    const uint32_t incl = wave_incl_scan(deg);
+    const uint32_t excl = incl - deg;
+    const uint32_t E = __shfl(incl, 63, 64);
+    s_excl[lane] = excl;
+    s_beg[lane] = beg;
+    s_mu[lane] = mu;
+    for (uint32_t k = 0; k < deg; ++k) owner[excl + k] = (uint8_t)lane;
+    __syncthreads();
+    for (uint32_t e = lane; e < E; e += 64) {
+      const uint32_t o = owner[e];
+      push_edge<ST, G>(a, s_beg[o] + (e - s_excl[o]), s_mu[o]);
+    }
+    __syncthreads();
+  }
+}
+
+// A5, large bin: one wave per item of up to kChunk consecutive out-edges.
+template <int ST, int G, typename RowT>
+__global__ __launch_bounds__(64) void k_push_large(KArgs a) {
+  using S = typename Tr<ST>::S;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  const uint64_t total = ctl->n_large;
+  const S* large_mu = static_cast<const S*>(a.large_mu);
+  for (uint64_t i = blockIdx.x; i < total; i += gridDim.x) {
+    uint32_t blk = find_block(a.off_large, a.blocks, i);
+    uint64_t idx = a.large_off[blk] + (i - a.off_large[blk]);
+    uint32_t vid = a.large_vid[idx];
+    uint32_t ch = a.large_chunk[idx];
+    S mu = large_mu[idx];
+    uint64_t rb = row_at<RowT>(a.row, vid);
+    uint64_t re = row_at<RowT>(a.row, vid + 1);
+    uint64_t beg = rb + (uint64_t)ch * kChunk;
+    uint64_t end = min(re, beg + kChunk);
+    for (uint64_t e = beg + threadIdx.x; e < end; e += 64) push_edge<ST, G>(a, e, mu);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up kernels.
+// ---------------------------------------------------------------------------
+// Per-block capacity of the large bin: the chunks of every vertex of the
+// block's range whose degree exceeds the small-bin bound.
+template <typename RowT>
+__global__ __launch_bounds__(256) void k_large_capacity(const void* row, uint64_t n, uint64_t per_block,
+                                                        uint64_t* cap) {
+  const uint64_t lo = (uint64_t)blockIdx.x * per_block;
+  const uint64_t hi = min(n, lo + per_block);
+  uint64_t c = 0;
+  for (uint64_t j = lo + threadIdx.x; j < hi; j += 256) {
+    uint64_t d = row_at<RowT>(row, j + 1) - row_at<RowT>(row, j);
+    if (d > kSmallMaxDeg) c += (d + kChunk - 1) / kChunk;
+  }
+  c = block_sum256(c);
+  if (threadIdx.x == 0) cap[blockIdx.x] = c;
+}
+
+}  // namespace daic

@@ -1,0 +1,776 @@
+// Host runtime and C ABI of libdaic: graphs, problems, the round loop
+// (hipGraph-captured), selection, and state transfer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "daic_internal.h"
+#include "daic_kernels.h"
+
+namespace daic {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+daic_status fail(daic_status s, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+static size_t state_size(int st) {
+  switch (st) {
+    case ST_F64: return 8;
+    case ST_F32:
+    case ST_F32K: return 4;
+    default: return 4;
+  }
+}
+
+static Partition make_partition(uint64_t n) {
+  Partition p;
+  if (n == 0) return p;
+  uint64_t blocks = std::min<uint64_t>(kMaxScanBlocks, (n + kScanBlock - 1) / kScanBlock);
+  uint64_t per = (n + blocks - 1) / blocks;
+  per = (per + kScanBlock - 1) / kScanBlock * kScanBlock;
+  p.per_block = per;
+  p.blocks = (uint32_t)((n + per - 1) / per);
+  return p;
+}
+
+template <typename T>
+static daic_status dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(DAIC_E_OOM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+  }
+  return DAIC_OK;
+}
+
+static void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+}  // namespace daic
+
+using namespace daic;
+
+// ---------------------------------------------------------------------------
+// Problem object.
+// ---------------------------------------------------------------------------
+struct GraphCacheKey {
+  int sched = -1;
+  uint64_t k = 0;
+  uint32_t S = 0;
+  double q = 0.0;
+  uint64_t seed = 0;
+  uint32_t K = 0;
+  const void* stream = nullptr;
+  const float* score = nullptr;
+  bool operator==(const GraphCacheKey& o) const {
+    return sched == o.sched && k == o.k && S == o.S && q == o.q && seed == o.seed && K == o.K &&
+           stream == o.stream && score == o.score;
+  }
+};
+
+struct daic_problem {
+  const daic_graph* g = nullptr;
+  daic_op op = DAIC_SUM;
+  daic_g gk = DAIC_G_SRC_SCALE;
+  daic_dtype state = DAIC_F64;
+  int st = ST_F64;
+  double alpha = 0.0;
+  KArgs a{};
+  void* alpha_pv = nullptr;
+  void* w_conv = nullptr;
+  Ctl* h_ctl = nullptr;   // pinned mirror
+  hipStream_t own_stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  GraphCacheKey key;
+  std::vector<void*> allocs;
+};
+
+namespace daic {
+
+// Enqueue functions per instantiation.
+struct Ops {
+  void (*residual)(daic_problem*, hipStream_t, int);
+  void (*round)(daic_problem*, const daic_run_opts*, hipStream_t, const float* score);
+  void (*select)(daic_problem*, const daic_run_opts*, hipStream_t, uint64_t round_override);
+};
+
+static uint32_t push_grid() { return 256 * 16; }
+
+template <int ST, int G, typename RowT>
+struct Impl {
+  using Key = typename Tr<ST>::Key;
+
+  static void residual(daic_problem* p, hipStream_t s, int count_round) {
+    hipLaunchKernelGGL(k_residual<ST>, dim3(p->a.blocks), dim3(256), 0, s, p->a, count_round);
+  }
+
+  // Threshold of a round (A2) for the given rule.
+  static void threshold(daic_problem* p, const daic_run_opts* o, hipStream_t s, const KArgs& a,
+                        uint64_t round_override) {
+    const uint64_t n = p->a.n;
+    if (o->sched == DAIC_SCHED_ALL) {
+      hipLaunchKernelGGL(k_select_all, dim3(1), dim3(1), 0, s, a.ctl);
+    } else if (o->sched == DAIC_SCHED_TOPK_SAMPLED) {
+      uint32_t S = o->n_samples ? o->n_samples : kMaxSamples;
+      uint32_t rank = (uint32_t)std::max(1.0, std::ceil(o->priority_fraction * (double)S));
+      hipLaunchKernelGGL(k_sample<ST>, dim3(1), dim3(1024), 0, s, a, S, rank, o->seed, round_override);
+    } else {  // exact top-k (also the learned rule, on the learned keys)
+      uint64_t k = (uint64_t)std::ceil(o->priority_fraction * (double)n);
+      if (k < 1) k = 1;
+      hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(1), 0, s, a.ctl, k);
+      const int passes = (int)sizeof(Key);
+      uint32_t hgrid = (uint32_t)std::min<uint64_t>(2048, (n + 255) / 256);
+      for (int pass = 0; pass < passes; ++pass) {
+        hipLaunchKernelGGL(k_radix_hist<ST>, dim3(hgrid), dim3(256), 0, s, a, pass);
+        hipLaunchKernelGGL(k_radix_pick<ST>, dim3(1), dim3(1), 0, s, a.ctl, pass);
+      }
+      hipLaunchKernelGGL(k_tie_count<ST>, dim3(a.blocks), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(k_tie_scan, dim3(1), dim3(1024), 0, s, a);
+    }
+  }
+
+  static void round(daic_problem* p, const daic_run_opts* o, hipStream_t s, const float* score) {
+    KArgs a = p->a;
+    a.score = score;
+    threshold(p, o, s, a, ~0ull);
+    hipLaunchKernelGGL((k_claim<ST, G, RowT, false>), dim3(a.blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL((k_push_small<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_push_large<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_residual<ST>, dim3(a.blocks), dim3(256), 0, s, a, 1);
+  }
+
+  static void select(daic_problem* p, const daic_run_opts* o, hipStream_t s, uint64_t round_override) {
+    KArgs a = p->a;
+    threshold(p, o, s, a, round_override);
+    hipLaunchKernelGGL((k_claim<ST, G, RowT, true>), dim3(a.blocks), dim3(256), 0, s, a);
+  }
+
+  static Ops ops() { return Ops{&residual, &round, &select}; }
+};
+
+template <int ST, int G>
+static bool pick_row(const daic_problem* p, Ops* out) {
+  if (p->g->dev.row32) *out = Impl<ST, G, uint32_t>::ops();
+  else *out = Impl<ST, G, uint64_t>::ops();
+  return true;
+}
+
+static bool get_ops(const daic_problem* p, Ops* out) {
+  switch (p->st) {
+    case ST_F64:
+      if (p->gk == DAIC_G_SRC_SCALE) return pick_row<ST_F64, DAIC_G_SRC_SCALE>(p, out);
+      if (p->gk == DAIC_G_DEG_SCALE) return pick_row<ST_F64, DAIC_G_DEG_SCALE>(p, out);
+      if (p->gk == DAIC_G_EDGE_SCALE) return pick_row<ST_F64, DAIC_G_EDGE_SCALE>(p, out);
+      return false;
+    case ST_F32:
+      if (p->gk == DAIC_G_SRC_SCALE) return pick_row<ST_F32, DAIC_G_SRC_SCALE>(p, out);
+      if (p->gk == DAIC_G_DEG_SCALE) return pick_row<ST_F32, DAIC_G_DEG_SCALE>(p, out);
+      if (p->gk == DAIC_G_EDGE_SCALE) return pick_row<ST_F32, DAIC_G_EDGE_SCALE>(p, out);
+      return false;
+    case ST_F32K:
+      if (p->gk == DAIC_G_SRC_SCALE) return pick_row<ST_F32K, DAIC_G_SRC_SCALE>(p, out);
+      if (p->gk == DAIC_G_DEG_SCALE) return pick_row<ST_F32K, DAIC_G_DEG_SCALE>(p, out);
+      if (p->gk == DAIC_G_EDGE_SCALE) return pick_row<ST_F32K, DAIC_G_EDGE_SCALE>(p, out);
+      return false;
+    case ST_U32:
+      if (p->gk == DAIC_G_EDGE_ADD) return pick_row<ST_U32, DAIC_G_EDGE_ADD>(p, out);
+      return false;
+    case ST_I32:
+      if (p->gk == DAIC_G_COPY) return pick_row<ST_I32, DAIC_G_COPY>(p, out);
+      return false;
+  }
+  return false;
+}
+
+// Set-up kernels that are not per instantiation.
+__global__ void k_init_ctl(Ctl* ctl, double eps, uint64_t max_rounds) {
+  ctl->eps = eps;
+  ctl->rounds = 0;
+  ctl->max_rounds = max_rounds;
+  ctl->activations = 0;
+  ctl->pushed = 0;
+  ctl->done = 0;
+  ctl->stop = 0;
+  ctl->ticket = 0;
+  ctl->sel_mode = 0;
+  ctl->tau = 0;
+  ctl->radix_skip = 1;
+  for (int i = 0; i < 256; ++i) ctl->hist[i] = 0;
+}
+
+__global__ void k_clear_done(Ctl* ctl) {
+  ctl->done = 0;
+  ctl->stop = 0;
+}
+
+template <typename From, typename To>
+__global__ void k_convert(const From* in, To* out, uint64_t count) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += st) out[i] = (To)in[i];
+}
+
+__global__ void k_narrow_rows(const uint64_t* in, uint32_t* out, uint64_t count) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += st) out[i] = (uint32_t)in[i];
+}
+
+// Device-side CSR validation for borrowed arrays: flags[0] = bad row_ptr,
+// flags[1] = column out of range.
+__global__ void k_validate(const uint64_t* row, const uint32_t* col, uint64_t n, uint64_t m, uint32_t* flags) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t j = i; j < n; j += st)
+    if (row[j + 1] < row[j]) flags[0] = 1;
+  if (i == 0 && (row[0] != 0 || row[n] != m)) flags[0] = 1;
+  for (uint64_t e = i; e < m; e += st)
+    if (col[e] >= n) flags[1] = 1;
+}
+
+template <typename T>
+__global__ void k_fill(T* p, T val, uint64_t count) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += st) p[i] = val;
+}
+
+static uint32_t grid_for(uint64_t count, uint32_t block = 256) {
+  uint64_t g = (count + block - 1) / block;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, 8192));
+}
+
+// Finish graph set-up: narrowed rows, partition and large-bin regions.
+static daic_status graph_finish(daic_graph* g, hipStream_t s) {
+  GraphDev& d = g->dev;
+  d.row32 = d.m < 0xFFFFFFFFull;
+  if (d.row32 && d.n > 0) {
+    uint32_t* r32;
+    daic_status st = dalloc(&r32, d.n + 1);
+    if (st) return st;
+    g->row32 = r32;
+    hipLaunchKernelGGL(k_narrow_rows, dim3(grid_for(d.n + 1)), dim3(256), 0, s,
+                       static_cast<const uint64_t*>(d.row), r32, d.n + 1);
+    d.row = r32;
+  }
+  g->part = make_partition(d.n);
+  const uint32_t nb = g->part.blocks;
+  std::vector<uint64_t> cap(nb + 1, 0);
+  if (nb > 0) {
+    uint64_t* dcap;
+    daic_status st = dalloc(&dcap, nb);
+    if (st) return st;
+    if (d.row32)
+      hipLaunchKernelGGL(k_large_capacity<uint32_t>, dim3(nb), dim3(256), 0, s, d.row, d.n, g->part.per_block, dcap);
+    else
+      hipLaunchKernelGGL(k_large_capacity<uint64_t>, dim3(nb), dim3(256), 0, s, d.row, d.n, g->part.per_block, dcap);
+    hipError_t e = hipMemcpyAsync(cap.data() + 1, dcap, nb * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(dcap);
+    if (e != hipSuccess) return fail(DAIC_E_DEVICE, "large-bin capacity: %s", hipGetErrorString(e));
+  }
+  for (uint32_t b = 0; b < nb; ++b) cap[b + 1] += cap[b];
+  g->large_cap = cap[nb];
+  daic_status st = dalloc(&g->large_off, nb + 1);
+  if (st) return st;
+  DAIC_HIP(hipMemcpyAsync(g->large_off, cap.data(), (nb + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  DAIC_HIP(hipStreamSynchronize(s));
+  return DAIC_OK;
+}
+
+}  // namespace daic
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* daic_last_error(void) { return daic::g_err.c_str(); }
+
+daic_status daic_graph_create(uint64_t n, uint64_t m, const uint64_t* row_ptr, const uint32_t* col,
+                              const void* w, daic_dtype w_type, daic_graph** out) {
+  if (!out) return fail(DAIC_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!row_ptr) return fail(DAIC_E_INVALID, "row_ptr is null");
+  if (m > 0 && !col) return fail(DAIC_E_INVALID, "col is null");
+  if (n >= 0xFFFFFFFFull) return fail(DAIC_E_INVALID, "n must be below 2^32-1");
+  if (row_ptr[0] != 0 || row_ptr[n] != m) return fail(DAIC_E_INVALID, "row_ptr[0] must be 0 and row_ptr[n] must be m");
+  for (uint64_t j = 0; j < n; ++j)
+    if (row_ptr[j + 1] < row_ptr[j]) return fail(DAIC_E_INVALID, "row_ptr not monotone at %llu", (unsigned long long)j);
+  for (uint64_t e = 0; e < m; ++e)
+    if (col[e] >= n) return fail(DAIC_E_INVALID, "col[%llu] = %u out of range", (unsigned long long)e, col[e]);
+  size_t wsz = 0;
+  if (w) {
+    if (w_type == DAIC_F64) wsz = 8;
+    else if (w_type == DAIC_F32 || w_type == DAIC_U32) wsz = 4;
+    else return fail(DAIC_E_INVALID, "weight type must be F64, F32 or U32");
+  } else {
+    w_type = DAIC_NONE;
+  }
+  std::unique_ptr<daic_graph> g(new daic_graph());
+  g->dev.n = n;
+  g->dev.m = m;
+  g->dev.w_type = w_type;
+  uint64_t* drow;
+  uint32_t* dcol;
+  daic_status st = dalloc(&drow, n + 1);
+  if (st) return st;
+  g->own_row = drow;
+  st = dalloc(&dcol, m);
+  if (st) { daic_graph_destroy(g.release()); return st; }
+  g->own_col = dcol;
+  DAIC_HIP(hipMemcpy(drow, row_ptr, (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice));
+  if (m) DAIC_HIP(hipMemcpy(dcol, col, m * sizeof(uint32_t), hipMemcpyHostToDevice));
+  if (w) {
+    uint8_t* dw;
+    st = dalloc(&dw, m * wsz);
+    if (st) { daic_graph_destroy(g.release()); return st; }
+    g->own_w = dw;
+    if (m) DAIC_HIP(hipMemcpy(dw, w, m * wsz, hipMemcpyHostToDevice));
+    g->dev.w = dw;
+  }
+  g->dev.row = drow;
+  g->dev.col = dcol;
+  st = graph_finish(g.get(), nullptr);
+  if (st) { daic_graph_destroy(g.release()); return st; }
+  *out = g.release();
+  return DAIC_OK;
+}
+
+daic_status daic_graph_create_device(uint64_t n, uint64_t m, const uint64_t* d_row_ptr, const uint32_t* d_col,
+                                     const void* d_w, daic_dtype w_type, void* hip_stream, daic_graph** out) {
+  if (!out) return fail(DAIC_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!d_row_ptr || (m > 0 && !d_col)) return fail(DAIC_E_INVALID, "null device array");
+  if (n >= 0xFFFFFFFFull) return fail(DAIC_E_INVALID, "n must be below 2^32-1");
+  if (d_w && !(w_type == DAIC_F64 || w_type == DAIC_F32 || w_type == DAIC_U32))
+    return fail(DAIC_E_INVALID, "weight type must be F64, F32 or U32");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  uint32_t* flags;
+  daic_status st = dalloc(&flags, 2);
+  if (st) return st;
+  DAIC_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(uint32_t), s));
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(std::max(n, m))), dim3(256), 0, s, d_row_ptr, d_col, n, m, flags);
+  uint32_t hf[2] = {0, 0};
+  DAIC_HIP(hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, s));
+  DAIC_HIP(hipStreamSynchronize(s));
+  dfree(flags);
+  if (hf[0]) return fail(DAIC_E_INVALID, "row_ptr is not a valid CSR offset array");
+  if (hf[1]) return fail(DAIC_E_INVALID, "a column index is out of range");
+  std::unique_ptr<daic_graph> g(new daic_graph());
+  g->dev.n = n;
+  g->dev.m = m;
+  g->dev.row = d_row_ptr;
+  g->dev.col = d_col;
+  g->dev.w = d_w;
+  g->dev.w_type = d_w ? w_type : DAIC_NONE;
+  st = graph_finish(g.get(), s);
+  if (st) { daic_graph_destroy(g.release()); return st; }
+  *out = g.release();
+  return DAIC_OK;
+}
+
+void daic_graph_destroy(daic_graph* g) {
+  if (!g) return;
+  dfree(g->own_row);
+  dfree(g->own_col);
+  dfree(g->own_w);
+  dfree(g->row32);
+  dfree(g->large_off);
+  delete g;
+}
+
+daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, double alpha_scalar,
+                                const double* alpha_per_vertex, daic_dtype state, daic_problem** out) {
+  if (!out) return fail(DAIC_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!g) return fail(DAIC_E_INVALID, "graph is null");
+  int st;
+  if (op == DAIC_SUM) {
+    if (!(gk == DAIC_G_SRC_SCALE || gk == DAIC_G_DEG_SCALE || gk == DAIC_G_EDGE_SCALE))
+      return fail(DAIC_E_UNSUPPORTED, "sum takes SRC_SCALE, DEG_SCALE or EDGE_SCALE");
+    if (state == DAIC_F64) st = ST_F64;
+    else if (state == DAIC_F32) st = ST_F32;
+    else if (state == DAIC_F32_KAHAN) st = ST_F32K;
+    else return fail(DAIC_E_UNSUPPORTED, "sum takes F64, F32 or F32_KAHAN state");
+    if (gk == DAIC_G_EDGE_SCALE && !g->dev.w) return fail(DAIC_E_INVALID, "EDGE_SCALE needs edge weights");
+    if (gk == DAIC_G_DEG_SCALE && alpha_per_vertex)
+      return fail(DAIC_E_INVALID, "DEG_SCALE takes a scalar alpha only");
+  } else if (op == DAIC_MIN) {
+    if (gk != DAIC_G_EDGE_ADD) return fail(DAIC_E_UNSUPPORTED, "min takes EDGE_ADD");
+    if (state != DAIC_U32) return fail(DAIC_E_UNSUPPORTED, "min takes U32 state");
+    if (!g->dev.w || g->dev.w_type != DAIC_U32) return fail(DAIC_E_INVALID, "EDGE_ADD needs U32 edge weights");
+    st = ST_U32;
+  } else if (op == DAIC_MAX) {
+    if (gk != DAIC_G_COPY) return fail(DAIC_E_UNSUPPORTED, "max takes COPY");
+    if (state != DAIC_I32) return fail(DAIC_E_UNSUPPORTED, "max takes I32 state");
+    st = ST_I32;
+  } else {
+    return fail(DAIC_E_INVALID, "unknown op");
+  }
+  if (alpha_per_vertex && !(gk == DAIC_G_SRC_SCALE || gk == DAIC_G_EDGE_SCALE))
+    return fail(DAIC_E_INVALID, "per-vertex alpha only for SRC_SCALE and EDGE_SCALE");
+  if (!std::isfinite(alpha_scalar)) return fail(DAIC_E_INVALID, "alpha must be finite");
+
+  std::unique_ptr<daic_problem> p(new daic_problem());
+  p->g = g;
+  p->op = op;
+  p->gk = gk;
+  p->state = state;
+  p->st = st;
+  p->alpha = alpha_scalar;
+  const GraphDev& d = g->dev;
+  const uint64_t n = d.n, m = d.m;
+  const size_t S = state_size(st);
+  const uint32_t nb = g->part.blocks;
+  auto grab = [&](void** ptr, size_t bytes) -> daic_status {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+    if (e != hipSuccess) return fail(DAIC_E_OOM, "hipMalloc of %zu bytes failed", bytes);
+    p->allocs.push_back(q);
+    *ptr = q;
+    return DAIC_OK;
+  };
+  daic_status rc;
+  KArgs& a = p->a;
+  void* ptr;
+#define GRAB(field, type, bytes)                            \
+  do {                                                      \
+    rc = grab(&ptr, (bytes));                               \
+    if (rc) { daic_problem_destroy(p.release()); return rc; } \
+    a.field = static_cast<type>(ptr);                       \
+  } while (0)
+  GRAB(ctl, Ctl*, sizeof(Ctl));
+  GRAB(v, void*, n * S);
+  GRAB(dv, void*, n * S);
+  if (st == ST_F32K) GRAB(c, float*, n * sizeof(float));
+  GRAB(small_vid, uint32_t*, n * 4);
+  GRAB(small_mu, void*, n * S);
+  GRAB(large_vid, uint32_t*, g->large_cap * 4);
+  GRAB(large_chunk, uint32_t*, g->large_cap * 4);
+  GRAB(large_mu, void*, g->large_cap * S);
+  GRAB(blk_small, uint32_t*, nb * 4);
+  GRAB(blk_large, uint32_t*, nb * 4);
+  GRAB(blk_ties, uint32_t*, nb * 4);
+  GRAB(off_small, uint64_t*, (nb + 1) * 8);
+  GRAB(off_large, uint64_t*, (nb + 1) * 8);
+  GRAB(off_ties, uint64_t*, (nb + 1) * 8);
+  GRAB(blk_act, uint64_t*, nb * 8);
+  GRAB(blk_push, uint64_t*, nb * 8);
+  GRAB(part_r, double*, nb * 8);
+  GRAB(part_n, uint64_t*, nb * 8);
+#undef GRAB
+  a.row = d.row;
+  a.col = d.col;
+  a.alpha = alpha_scalar;
+  a.n = n;
+  a.per_block = g->part.per_block;
+  a.blocks = nb;
+  a.large_off = g->large_off;
+  a.sel_out = nullptr;
+  a.score = nullptr;
+
+  hipStream_t s = nullptr;
+  // weights in the element type the push needs
+  if (gk == DAIC_G_EDGE_SCALE) {
+    bool same = (st == ST_F64 && d.w_type == DAIC_F64) || (st != ST_F64 && d.w_type == DAIC_F32);
+    if (same) {
+      a.w = d.w;
+    } else {
+      rc = grab(&p->w_conv, m * S);
+      if (rc) { daic_problem_destroy(p.release()); return rc; }
+      uint32_t gr = grid_for(m);
+      if (st == ST_F64) {
+        if (d.w_type == DAIC_F32) hipLaunchKernelGGL((k_convert<float, double>), dim3(gr), dim3(256), 0, s, (const float*)d.w, (double*)p->w_conv, m);
+        else hipLaunchKernelGGL((k_convert<uint32_t, double>), dim3(gr), dim3(256), 0, s, (const uint32_t*)d.w, (double*)p->w_conv, m);
+      } else {
+        if (d.w_type == DAIC_F64) hipLaunchKernelGGL((k_convert<double, float>), dim3(gr), dim3(256), 0, s, (const double*)d.w, (float*)p->w_conv, m);
+        else hipLaunchKernelGGL((k_convert<uint32_t, float>), dim3(gr), dim3(256), 0, s, (const uint32_t*)d.w, (float*)p->w_conv, m);
+      }
+      a.w = p->w_conv;
+    }
+  } else if (gk == DAIC_G_EDGE_ADD) {
+    a.w = d.w;
+  }
+  if (alpha_per_vertex) {
+    rc = grab(&p->alpha_pv, n * S);
+    if (rc) { daic_problem_destroy(p.release()); return rc; }
+    if (st == ST_F64) {
+      DAIC_HIP(hipMemcpy(p->alpha_pv, alpha_per_vertex, n * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> tmp(n);
+      for (uint64_t j = 0; j < n; ++j) tmp[j] = (float)alpha_per_vertex[j];
+      DAIC_HIP(hipMemcpy(p->alpha_pv, tmp.data(), n * 4, hipMemcpyHostToDevice));
+    }
+    a.alpha_pv = p->alpha_pv;
+  }
+  // identity state
+  const uint32_t gr = grid_for(n);
+  if (st == ST_F64) {
+    hipLaunchKernelGGL(k_fill<double>, dim3(gr), dim3(256), 0, s, (double*)a.v, 0.0, n);
+    hipLaunchKernelGGL(k_fill<double>, dim3(gr), dim3(256), 0, s, (double*)a.dv, 0.0, n);
+  } else if (st == ST_F32 || st == ST_F32K) {
+    hipLaunchKernelGGL(k_fill<float>, dim3(gr), dim3(256), 0, s, (float*)a.v, 0.0f, n);
+    hipLaunchKernelGGL(k_fill<float>, dim3(gr), dim3(256), 0, s, (float*)a.dv, 0.0f, n);
+    if (a.c) hipLaunchKernelGGL(k_fill<float>, dim3(gr), dim3(256), 0, s, a.c, 0.0f, n);
+  } else if (st == ST_U32) {
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(gr), dim3(256), 0, s, (uint32_t*)a.v, kInfU32, n);
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(gr), dim3(256), 0, s, (uint32_t*)a.dv, kInfU32, n);
+  } else {
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(gr), dim3(256), 0, s, (int32_t*)a.v, -1, n);
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(gr), dim3(256), 0, s, (int32_t*)a.dv, -1, n);
+  }
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, a.ctl, 0.0, 0ull);
+  DAIC_HIP(hipHostMalloc((void**)&p->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  DAIC_HIP(hipStreamCreateWithFlags(&p->own_stream, hipStreamNonBlocking));
+  DAIC_HIP(hipEventCreate(&p->ev0));
+  DAIC_HIP(hipEventCreate(&p->ev1));
+  DAIC_HIP(hipDeviceSynchronize());
+  Ops ops;
+  if (!get_ops(p.get(), &ops)) {
+    daic_problem_destroy(p.release());
+    return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");
+  }
+  *out = p.release();
+  return DAIC_OK;
+}
+
+daic_status daic_problem_set_init(daic_problem* p, const void* v0, const void* dv1) {
+  if (!p || !v0 || !dv1) return fail(DAIC_E_INVALID, "null argument");
+  const uint64_t n = p->g->dev.n;
+  if (n == 0) return DAIC_OK;
+  if (p->st == ST_F64 || p->st == ST_U32 || p->st == ST_I32) {
+    size_t S = state_size(p->st);
+    DAIC_HIP(hipMemcpy(p->a.v, v0, n * S, hipMemcpyHostToDevice));
+    DAIC_HIP(hipMemcpy(p->a.dv, dv1, n * S, hipMemcpyHostToDevice));
+  } else {
+    const double* a = static_cast<const double*>(v0);
+    const double* b = static_cast<const double*>(dv1);
+    std::vector<float> tv(n), td(n), tc(n, 0.0f);
+    for (uint64_t j = 0; j < n; ++j) {
+      tv[j] = (float)a[j];
+      td[j] = (float)b[j];
+      // carry the FP32 rounding of v0 in the compensation term
+      tc[j] = (float)((double)tv[j] - a[j]);
+    }
+    DAIC_HIP(hipMemcpy(p->a.v, tv.data(), n * 4, hipMemcpyHostToDevice));
+    DAIC_HIP(hipMemcpy(p->a.dv, td.data(), n * 4, hipMemcpyHostToDevice));
+    if (p->a.c) DAIC_HIP(hipMemcpy(p->a.c, tc.data(), n * 4, hipMemcpyHostToDevice));
+  }
+  return DAIC_OK;
+}
+
+static daic_status check_opts(const daic_problem* p, const daic_run_opts* o) {
+  if (!o) return fail(DAIC_E_INVALID, "opts is null");
+  if (!(o->priority_fraction > 0.0 && o->priority_fraction <= 1.0))
+    return fail(DAIC_E_INVALID, "priority_fraction must be in (0, 1]");
+  if (!(o->eps >= 0.0)) return fail(DAIC_E_INVALID, "eps must be >= 0");
+  if (o->sched < DAIC_SCHED_ALL || o->sched > DAIC_SCHED_LEARNED) return fail(DAIC_E_INVALID, "unknown sched");
+  if (o->sched == DAIC_SCHED_TOPK_SAMPLED && o->n_samples > kMaxSamples)
+    return fail(DAIC_E_INVALID, "n_samples must be <= %u", kMaxSamples);
+  if (o->sched == DAIC_SCHED_LEARNED && !o->model) return fail(DAIC_E_INVALID, "LEARNED needs a model");
+  (void)p;
+  return DAIC_OK;
+}
+
+static double per_edge_bytes(const daic_problem* p) {
+  const double S = (double)state_size(p->st);
+  double b = 4.0 + 2.0 * S;  // col + RMW of dv_k
+  if (p->gk == DAIC_G_EDGE_SCALE) b += S;
+  if (p->gk == DAIC_G_EDGE_ADD) b += 4.0;
+  return b;
+}
+
+static double per_vertex_bytes(const daic_problem* p) {
+  const double S = (double)state_size(p->st);
+  const double R = p->g->dev.row32 ? 4.0 : 8.0;
+  double b = 2.0 * R + 2.0 * S + 2.0 * S;  // row offsets, dv claim, v fold
+  if (p->st == ST_F32K) b += 8.0;           // c fold
+  b += 2.0 * (4.0 + S);                     // frontier item write + read
+  return b;
+}
+
+daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats) {
+  if (!p) return fail(DAIC_E_INVALID, "problem is null");
+  daic_status rc = check_opts(p, o);
+  if (rc) return rc;
+  const uint64_t n = p->g->dev.n;
+  hipStream_t s = o->hip_stream ? static_cast<hipStream_t>(o->hip_stream) : p->own_stream;
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (n == 0) return DAIC_OK;
+  Ops ops;
+  if (!get_ops(p, &ops)) return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");
+  const uint32_t K = o->rounds_per_check ? o->rounds_per_check : 1;
+  const uint64_t max_rounds = o->max_rounds ? o->max_rounds : ~0ull;
+  const float* score = nullptr;
+  if (o->sched == DAIC_SCHED_LEARNED) {
+    rc = learned_prepare(p, o->model, s);
+    if (rc) return rc;
+  }
+
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, p->a.ctl, o->eps, max_rounds);
+  ops.residual(p, s, 0);
+  DAIC_HIP(hipEventRecord(p->ev0, s));
+
+  const bool use_graph = o->sched != DAIC_SCHED_LEARNED && std::getenv("DAIC_NO_GRAPH") == nullptr;
+  GraphCacheKey key;
+  key.sched = o->sched;
+  key.k = (uint64_t)std::ceil(o->priority_fraction * (double)n);
+  key.S = o->n_samples;
+  key.q = o->priority_fraction;
+  key.seed = o->seed;
+  key.K = K;
+  key.stream = s;
+  if (use_graph && !(p->exec && p->key == key)) {
+    if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    DAIC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (uint32_t r = 0; r < K; ++r) ops.round(p, o, s, nullptr);
+    hipGraph_t graph;
+    DAIC_HIP(hipStreamEndCapture(s, &graph));
+    p->graph = graph;
+    DAIC_HIP(hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0));
+    p->key = key;
+  }
+  for (;;) {
+    if (o->sched == DAIC_SCHED_LEARNED) {
+      for (uint32_t r = 0; r < K; ++r) {
+        rc = learned_scores(p, o->model, s, &score);
+        if (rc) return rc;
+        ops.round(p, o, s, score);
+        learned_after_round(p, s);
+      }
+    } else if (use_graph) {
+      DAIC_HIP(hipGraphLaunch(p->exec, s));
+    } else {
+      for (uint32_t r = 0; r < K; ++r) ops.round(p, o, s, nullptr);
+    }
+    DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DAIC_HIP(hipStreamSynchronize(s));
+    if (p->h_ctl->done || p->h_ctl->stop) break;
+  }
+  DAIC_HIP(hipEventRecord(p->ev1, s));
+  DAIC_HIP(hipEventSynchronize(p->ev1));
+  float ms = 0.f;
+  DAIC_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+  const Ctl& c = *p->h_ctl;
+  if (stats) {
+    stats->rounds = c.rounds;
+    stats->activations = c.activations;
+    stats->pushed_edges = c.pushed;
+    stats->final_residual = c.r;
+    stats->time_ms = ms;
+    stats->gteps = ms > 0 ? (double)c.pushed / (ms * 1e-3) / 1e9 : 0.0;
+    stats->alg_bytes = (double)c.pushed * per_edge_bytes(p) + (double)c.activations * per_vertex_bytes(p) +
+                       (double)c.rounds * (double)n * (double)state_size(p->st) * 2.0;
+  }
+  return c.done ? DAIC_OK : DAIC_NOT_CONVERGED;
+}
+
+daic_status daic_select_frontier(daic_problem* p, const daic_run_opts* o, uint64_t round, uint8_t* sel_out,
+                                 double* threshold_out) {
+  if (!p || !sel_out) return fail(DAIC_E_INVALID, "null argument");
+  daic_status rc = check_opts(p, o);
+  if (rc) return rc;
+  if (o->sched == DAIC_SCHED_LEARNED) return fail(DAIC_E_UNSUPPORTED, "select_frontier takes the plain rules");
+  const uint64_t n = p->g->dev.n;
+  if (n == 0) return DAIC_OK;
+  Ops ops;
+  if (!get_ops(p, &ops)) return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");
+  hipStream_t s = o->hip_stream ? static_cast<hipStream_t>(o->hip_stream) : p->own_stream;
+  void* sel;
+  DAIC_HIP(hipMalloc(&sel, n));
+  p->a.sel_out = static_cast<uint8_t*>(sel);
+  DAIC_HIP(hipMemsetAsync(sel, 0, n, s));
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, p->a.ctl, 0.0, ~0ull);
+  ops.residual(p, s, 0);
+  // the residual may declare the state finished; the selection still runs
+  hipLaunchKernelGGL(k_clear_done, dim3(1), dim3(1), 0, s, p->a.ctl);
+  ops.select(p, o, s, round);
+  hipError_t e = hipMemcpyAsync(sel_out, sel, n, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  p->a.sel_out = nullptr;
+  (void)hipFree(sel);
+  if (e != hipSuccess) return fail(DAIC_E_DEVICE, "select_frontier: %s", hipGetErrorString(e));
+  if (threshold_out) {
+    const Ctl& c = *p->h_ctl;
+    uint64_t t = c.tau;
+    double tv;
+    if (c.sel_mode == 0) tv = 0.0;
+    else if (p->st == ST_F64) { double d; std::memcpy(&d, &t, 8); tv = d; }
+    else if (p->st == ST_F32 || p->st == ST_F32K) { uint32_t u = (uint32_t)t; float f; std::memcpy(&f, &u, 4); tv = f; }
+    else tv = (double)t;
+    *threshold_out = tv;
+  }
+  return DAIC_OK;
+}
+
+daic_status daic_problem_get(const daic_problem* p, void* v_out, void* dv_out) {
+  if (!p || !v_out) return fail(DAIC_E_INVALID, "null argument");
+  const uint64_t n = p->g->dev.n;
+  if (n == 0) return DAIC_OK;
+  DAIC_HIP(hipDeviceSynchronize());
+  if (p->st == ST_F64 || p->st == ST_U32 || p->st == ST_I32) {
+    size_t S = state_size(p->st);
+    DAIC_HIP(hipMemcpy(v_out, p->a.v, n * S, hipMemcpyDeviceToHost));
+    if (dv_out) DAIC_HIP(hipMemcpy(dv_out, p->a.dv, n * S, hipMemcpyDeviceToHost));
+    return DAIC_OK;
+  }
+  std::vector<float> tv(n), tc(n, 0.0f);
+  DAIC_HIP(hipMemcpy(tv.data(), p->a.v, n * 4, hipMemcpyDeviceToHost));
+  if (p->a.c) DAIC_HIP(hipMemcpy(tc.data(), p->a.c, n * 4, hipMemcpyDeviceToHost));
+  double* vo = static_cast<double*>(v_out);
+  for (uint64_t j = 0; j < n; ++j) vo[j] = (double)tv[j] - (double)tc[j];
+  if (dv_out) {
+    DAIC_HIP(hipMemcpy(tv.data(), p->a.dv, n * 4, hipMemcpyDeviceToHost));
+    double* d = static_cast<double*>(dv_out);
+    for (uint64_t j = 0; j < n; ++j) d[j] = (double)tv[j];
+  }
+  return DAIC_OK;
+}
+
+void daic_problem_destroy(daic_problem* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (void* q : p->allocs) dfree(q);
+  if (p->h_ctl) (void)hipHostFree(p->h_ctl);
+  if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
+  if (p->ev0) (void)hipEventDestroy(p->ev0);
+  if (p->ev1) (void)hipEventDestroy(p->ev1);
+  delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+"""ctypes binding of libdaic (argument marshalling only).
+
+Every step of a run executes in the library's HIP kernels; this module only
+converts arguments. It refuses to work without the compiled library: there is
+no CPU fallback.
+
+Names follow the C ABI in include/daic.h: a problem is the DAIC tuple
+(g, (+), v0, dv1) of the paper's Table 1 on a CSR graph.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdaic.so")
+
+OK, NOT_CONVERGED = 0, 1
+SUM, MIN, MAX = 0, 1, 2
+G_SRC_SCALE, G_EDGE_SCALE, G_EDGE_ADD, G_COPY, G_DEG_SCALE = 0, 1, 2, 3, 4
+F64, F32, F32_KAHAN, U32, I32, NONE = 0, 1, 2, 3, 4, 5
+SCHED_ALL, SCHED_TOPK_EXACT, SCHED_TOPK_SAMPLED, SCHED_LEARNED = 0, 1, 2, 3
+INF_U32 = 0xFFFFFFFF
+
+_SCHED_NAMES = {"all": SCHED_ALL, "exact": SCHED_TOPK_EXACT, "sampled": SCHED_TOPK_SAMPLED,
+                "learned": SCHED_LEARNED}
+_STATE_NAMES = {"f64": F64, "f32": F32, "f32_kahan": F32_KAHAN, "u32": U32, "i32": I32}
+
+_vp = ctypes.c_void_p
+
+
+class DaicError(RuntimeError):
+    pass
+
+
+class RunOpts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("priority_fraction", ctypes.c_double),
+                ("sched", ctypes.c_int), ("max_rounds", ctypes.c_uint64),
+                ("rounds_per_check", ctypes.c_uint32), ("n_samples", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("hip_stream", _vp), ("model", _vp)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint64), ("activations", ctypes.c_uint64),
+                ("pushed_edges", ctypes.c_uint64), ("final_residual", ctypes.c_double),
+                ("time_ms", ctypes.c_double), ("gteps", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DaicError(f"{LIB_PATH} is missing: build it with "
+                            "`python -m paper_1710_05785_amd.build` (no CPU fallback exists)")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 with
+        # the same soname, so loading torch first makes libdaic bind to that
+        # runtime and share device memory and streams with it.
+        import torch  # noqa: F401
+
+        L = ctypes.CDLL(LIB_PATH)
+        L.daic_last_error.restype = ctypes.c_char_p
+        L.daic_graph_create.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp, ctypes.c_int,
+                                        ctypes.POINTER(_vp)]
+        L.daic_graph_create_device.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp,
+                                               ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+        L.daic_graph_destroy.argtypes = [_vp]
+        L.daic_graph_destroy.restype = None
+        L.daic_problem_create.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp,
+                                          ctypes.c_int, ctypes.POINTER(_vp)]
+        L.daic_problem_set_init.argtypes = [_vp, _vp, _vp]
+        L.daic_run.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.POINTER(Stats)]
+        L.daic_problem_get.argtypes = [_vp, _vp, _vp]
+        L.daic_problem_destroy.argtypes = [_vp]
+        L.daic_problem_destroy.restype = None
+        L.daic_select_frontier.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint64, _vp,
+                                           ctypes.POINTER(ctypes.c_double)]
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str) -> int:
+    if rc < 0:
+        msg = lib().daic_last_error().decode(errors="replace")
+        raise DaicError(f"{what} failed ({rc}): {msg}")
+    return rc
+
+
+def _addr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Graph:
+    """A CSR graph on the device (daic_graph)."""
+
+    def __init__(self, row_ptr, col, w=None, *, _handle=None, _keep=()):
+        self._h = None
+        self._keep = _keep
+        if _handle is not None:
+            self._h = _handle
+            return
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.uint64)
+        col = np.ascontiguousarray(col, dtype=np.uint32)
+        n = row_ptr.shape[0] - 1
+        m = col.shape[0]
+        wt = NONE
+        if w is not None:
+            w = np.ascontiguousarray(w)
+            wt = {np.dtype(np.float64): F64, np.dtype(np.float32): F32,
+                  np.dtype(np.uint32): U32}[w.dtype]
+        h = _vp()
+        check(lib().daic_graph_create(n, m, _addr(row_ptr), _addr(col), _addr(w), wt,
+                                      ctypes.byref(h)), "daic_graph_create")
+        self._h = h
+        self.n, self.m = n, m
+
+    @classmethod
+    def from_device(cls, row_ptr, col, w=None, stream=None):
+        """Borrow torch device tensors (uint64/int64 row_ptr, int32 col)."""
+        n = row_ptr.shape[0] - 1
+        m = col.shape[0]
+        wt = NONE
+        if w is not None:
+            import torch
+
+            wt = {torch.float64: F64, torch.float32: F32, torch.int32: U32}[w.dtype]
+        h = _vp()
+        check(lib().daic_graph_create_device(n, m, _addr(row_ptr), _addr(col), _addr(w), wt,
+                                             _stream_handle(stream), ctypes.byref(h)),
+              "daic_graph_create_device")
+        g = cls(None, None, _handle=h, _keep=(row_ptr, col, w))
+        g.n, g.m = n, m
+        return g
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            lib().daic_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class RunResult:
+    status: int
+    stats: dict
+
+    @property
+    def converged(self):
+        return self.status == OK
+
+
+class Problem:
+    """A DAIC problem (daic_problem) on a Graph."""
+
+    def __init__(self, graph: Graph, op: int, g: int, alpha: float = 0.0, alpha_pv=None,
+                 state="f64"):
+        self.graph = graph
+        self.op = op
+        self.state = _STATE_NAMES[state] if isinstance(state, str) else state
+        self.n = graph.n
+        apv = None if alpha_pv is None else np.ascontiguousarray(alpha_pv, dtype=np.float64)
+        h = _vp()
+        check(lib().daic_problem_create(graph.handle, op, g, float(alpha), _addr(apv), self.state,
+                                        ctypes.byref(h)), "daic_problem_create")
+        self._h = h
+
+    def _host_dtype(self):
+        return {F64: np.float64, F32: np.float64, F32_KAHAN: np.float64, U32: np.uint32,
+                I32: np.int32}[self.state]
+
+    def set_init(self, v0, dv1):
+        dt = self._host_dtype()
+        v0 = np.ascontiguousarray(v0, dtype=dt)
+        dv1 = np.ascontiguousarray(dv1, dtype=dt)
+        if v0.shape != (self.n,) or dv1.shape != (self.n,):
+            raise ValueError("v0 and dv1 must have n entries")
+        check(lib().daic_problem_set_init(self._h, _addr(v0), _addr(dv1)), "daic_problem_set_init")
+
+    @staticmethod
+    def make_opts(eps=0.0, q=1.0, sched="all", max_rounds=0, rounds_per_check=8, n_samples=4096,
+                  seed=0, stream=None, model=None):
+        o = RunOpts()
+        o.eps = eps
+        o.priority_fraction = q
+        o.sched = _SCHED_NAMES[sched] if isinstance(sched, str) else sched
+        o.max_rounds = max_rounds
+        o.rounds_per_check = rounds_per_check
+        o.n_samples = n_samples
+        o.seed = seed
+        o.hip_stream = _stream_handle(stream)
+        o.model = None if model is None else model.handle
+        return o
+
+    def run(self, **kw) -> RunResult:
+        o = self.make_opts(**kw)
+        st = Stats()
+        rc = check(lib().daic_run(self._h, ctypes.byref(o), ctypes.byref(st)), "daic_run")
+        return RunResult(rc, st.as_dict())
+
+    def get(self, with_dv=False):
+        dt = self._host_dtype()
+        v = np.empty(self.n, dtype=dt)
+        dv = np.empty(self.n, dtype=dt) if with_dv else None
+        check(lib().daic_problem_get(self._h, _addr(v), _addr(dv)), "daic_problem_get")
+        return (v, dv) if with_dv else v
+
+    def select_frontier(self, round_no=0, **kw):
+        o = self.make_opts(**kw)
+        sel = np.zeros(self.n, dtype=np.uint8)
+        tau = ctypes.c_double(0)
+        check(lib().daic_select_frontier(self._h, ctypes.byref(o), round_no, _addr(sel),
+                                         ctypes.byref(tau)), "daic_select_frontier")
+        return sel.astype(bool), tau.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().daic_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

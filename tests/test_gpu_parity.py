@@ -1,0 +1,329 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances:
+* integer (+) (SSSP min, components max): bit-exact, three repeats;
+* FP64 sum problems: L1 distance to the oracle's fixed point <= 1e-9, with the
+  GPU stopped at residual 1e-10 (bound r/(1-d) = 5e-10 for d = 0.8) and the
+  oracle at 1e-13;
+* FP32 paths: relative L1 <= 1e-5 against the FP64 oracle.
+Every case is seeded; sizes span many blocks of the per-vertex kernels, end on
+a ragged tail, and include hubs split into several large-bin chunks.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import daic_gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def daic():
+    from paper_1710_05785_amd import daic as d
+
+    d.lib()
+    return d
+
+
+def pr_problem(daic, g, d, state="f64"):
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=d, state=state)
+    v0, dv1 = oracle.pagerank_init(g.n, d)
+    p.set_init(v0, dv1)
+    return p
+
+
+@pytest.fixture(scope="module")
+def pl10k():
+    return daic_gen.powerlaw(n=10000, seed=1)
+
+
+@pytest.fixture(scope="module")
+def pl10k_ref(pl10k):
+    v, _, _ = oracle.jacobi_sum(pl10k, oracle.G_DEG_SCALE, 0.8, np.full(pl10k.n, 0.2), eps=1e-13)
+    return v
+
+
+@pytest.mark.parametrize("sched,q", [("all", 1.0), ("sampled", 0.1), ("exact", 0.1),
+                                     ("sampled", 0.01), ("exact", 0.5)])
+def test_pagerank_f64_powerlaw10k(daic, pl10k, pl10k_ref, sched, q):
+    say("case pagerank f64 powerlaw10k", sched, q)
+    p = pr_problem(daic, pl10k, 0.8)
+    res = p.run(eps=1e-10, q=q, sched=sched, max_rounds=100000, seed=7)
+    assert res.converged
+    v = p.get()
+    err = np.abs(v - pl10k_ref).sum()
+    assert err <= 1e-9, err
+    assert err <= res.stats["final_residual"] / (1 - 0.8) + 1e-12
+    assert res.stats["final_residual"] <= 1e-10
+
+
+def test_pagerank_f64_timed_config_bound(daic, pl10k, pl10k_ref):
+    """The timed run stops at sum|dv| < 1e-9: error within r/(1-d)."""
+    say("case pagerank f64 stop 1e-9")
+    p = pr_problem(daic, pl10k, 0.8)
+    res = p.run(eps=1e-9, q=1.0, sched="all")
+    err = np.abs(p.get() - pl10k_ref).sum()
+    assert err <= res.stats["final_residual"] / 0.2 + 1e-12
+
+
+@pytest.mark.parametrize("state", ["f32_kahan", "f32"])
+@pytest.mark.parametrize("sched,q", [("all", 1.0), ("sampled", 0.1)])
+def test_pagerank_fp32_relative_l1(daic, pl10k, pl10k_ref, state, sched, q):
+    say("case pagerank", state, sched, q)
+    p = pr_problem(daic, pl10k, 0.8, state=state)
+    res = p.run(eps=1e-6, q=q, sched=sched, seed=3)
+    assert res.converged
+    v = p.get()
+    rel = np.abs(v - pl10k_ref).sum() / np.abs(pl10k_ref).sum()
+    assert rel <= 1e-5, rel
+
+
+def test_mass_conservation_partial_runs(daic):
+    """sum dv + sum (1 - s_j) v = sum dv1 after any number of rounds."""
+    say("case mass conservation")
+    g = daic_gen.rmat(14, 8, seed=11)
+    d = 0.8
+    deg = g.outdeg()
+    s = np.where(deg > 0, d, 0.0)
+    for sched, q in (("all", 1.0), ("sampled", 0.05), ("exact", 0.2)):
+        p = pr_problem(daic, g, d)
+        for rounds in (1, 2, 5):
+            p.run(eps=0.0, q=q, sched=sched, max_rounds=rounds, rounds_per_check=1, seed=5)
+            v, dv = p.get(with_dv=True)
+            lhs = dv.sum() + ((1 - s) * v).sum()
+            assert abs(lhs - 0.2 * g.n) <= 1e-12 * 0.2 * g.n, (sched, rounds, lhs)
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(12, 8, 21), (15, 16, 22)])
+def test_pagerank_rmat_f64_and_kahan(daic, scale, ef, seed):
+    say("case pagerank rmat", scale, ef)
+    g = daic_gen.rmat(scale, ef, seed=seed)
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.8, np.full(g.n, 0.2), eps=1e-13)
+    p = pr_problem(daic, g, 0.8)
+    assert p.run(eps=1e-10, q=1.0, sched="all").converged
+    assert np.abs(p.get() - ref).sum() <= 1e-9
+    pk = pr_problem(daic, g, 0.8, state="f32_kahan")
+    assert pk.run(eps=1e-6 * g.n / 1e4, q=1.0, sched="all").converged
+    assert np.abs(pk.get() - ref).sum() / ref.sum() <= 1e-5
+
+
+def sssp_case(g, wseed, source=0):
+    w = daic_gen.sssp_weights(g.m, seed=wseed)
+    return w, oracle.dijkstra(g, w, source)
+
+
+@pytest.mark.parametrize("scale", [10, 16])
+@pytest.mark.parametrize("sched,q", [("all", 1.0), ("sampled", 0.1), ("exact", 0.1)])
+def test_sssp_bit_exact(daic, scale, sched, q):
+    say("case sssp rmat", scale, sched, q)
+    g = daic_gen.rmat(scale, 16, seed=100 + scale)
+    w, ref = sssp_case(g, 3)
+    gg = daic.Graph(g.row_ptr, g.col, w)
+    for rep in range(3):
+        p = daic.Problem(gg, daic.MIN, daic.G_EDGE_ADD, state="u32")
+        v0, dv1 = oracle.sssp_init(g.n, 0)
+        p.set_init(v0, dv1)
+        res = p.run(q=q, sched=sched, seed=rep)
+        assert res.converged
+        np.testing.assert_array_equal(p.get(), ref)
+        assert res.stats["final_residual"] == 0
+
+
+def test_sssp_rmat20_full_config(daic):
+    """The single-source shortest-path workload at full size: RMAT scale 20,
+    edge factor 16, weights U{1..255}, source 0, q = 0.1 (sampled)."""
+    say("case sssp rmat20 full")
+    g = daic_gen.rmat(20, 16, seed=2)
+    w, ref = sssp_case(g, 3)
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+    v0, dv1 = oracle.sssp_init(g.n, 0)
+    p.set_init(v0, dv1)
+    res = p.run(q=0.1, sched="sampled", seed=1)
+    assert res.converged
+    np.testing.assert_array_equal(p.get(), ref)
+
+
+@pytest.mark.parametrize("symmetric", [False, True])
+@pytest.mark.parametrize("sched,q", [("all", 1.0), ("exact", 0.3)])
+def test_components_max_label_bit_exact(daic, symmetric, sched, q):
+    say("case cc", symmetric, sched, q)
+    g0 = daic_gen.rmat(13, 4, seed=31)
+    if symmetric:
+        src = np.repeat(np.arange(g0.n), g0.outdeg())
+        dst = g0.col.astype(np.int64)
+        g = daic_gen.from_edges(g0.n, np.concatenate([src, dst]), np.concatenate([dst, src]))
+    else:
+        g = g0
+    ref = oracle.maxlabel(g)
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.MAX, daic.G_COPY, state="i32")
+    v0, dv1 = oracle.cc_init(g.n)
+    p.set_init(v0, dv1)
+    assert p.run(q=q, sched=sched).converged
+    np.testing.assert_array_equal(p.get(), ref)
+
+
+def test_katz_src_scale(daic):
+    say("case katz")
+    g = daic_gen.rmat(12, 8, seed=41)
+    beta = 0.9 / max(1, int(g.outdeg().max()))
+    dv1 = np.zeros(g.n)
+    dv1[5] = 1.0
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_SRC_SCALE, beta, dv1, eps=1e-15)
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_SRC_SCALE, alpha=beta)
+    p.set_init(np.zeros(g.n), dv1)
+    assert p.run(eps=1e-13, q=1.0, sched="all").converged
+    assert np.abs(p.get() - ref).sum() <= 1e-11
+
+
+@pytest.mark.parametrize("state", ["f64", "f32_kahan"])
+def test_edge_scale_adsorption_weights(daic, state):
+    say("case edge scale", state)
+    g = daic_gen.rmat(12, 8, seed=51)
+    w = daic_gen.lognormal_f64(52, g.m, 0.4, 0.8)
+    deg = g.outdeg()
+    rs = np.bincount(np.repeat(np.arange(g.n), deg), weights=w, minlength=g.n)
+    rs = np.where(deg > 0, rs, 1.0)
+    a = 0.85 / rs
+    c = daic_gen.lognormal_f64(53, g.n, 0.0, 1.0)
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_EDGE_SCALE, 0.0, c, w=w, alpha_pv=a, eps=1e-13)
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.SUM, daic.G_EDGE_SCALE, alpha_pv=a,
+                     state=state)
+    p.set_init(np.zeros(g.n), c)
+    eps = 1e-11 if state == "f64" else 1e-3
+    assert p.run(eps=eps, q=1.0, sched="all").converged
+    rel = np.abs(p.get() - ref).sum() / np.abs(ref).sum()
+    assert rel <= (1e-12 if state == "f64" else 1e-5), rel
+
+
+def test_edge_cases(daic):
+    say("case edge cases")
+    # one vertex, no edges
+    g = daic_gen.from_edges(1, [], [])
+    p = pr_problem(daic, g, 0.8)
+    assert p.run(eps=0.0, q=1.0).converged
+    np.testing.assert_allclose(p.get(), [0.2])
+    # self-loop only: v = 0.2 / (1 - 0.8) = 1
+    g = daic_gen.from_edges(1, [0], [0])
+    p = pr_problem(daic, g, 0.8)
+    assert p.run(eps=1e-14, q=1.0).converged
+    np.testing.assert_allclose(p.get(), [1.0], atol=1e-13)
+    # edgeless ragged graph
+    g = daic_gen.from_edges(777, [], [])
+    p = pr_problem(daic, g, 0.8)
+    assert p.run(eps=0.0, q=0.01, sched="exact").converged
+    np.testing.assert_allclose(p.get(), 0.2)
+    # directed cycle of ragged length: v = 1 everywhere
+    n = 1000003 % 4099 + 300
+    g = daic_gen.from_edges(n, np.arange(n), (np.arange(n) + 1) % n)
+    p = pr_problem(daic, g, 0.8)
+    assert p.run(eps=1e-12, q=1.0).converged
+    np.testing.assert_allclose(p.get(), 1.0, atol=1e-12)
+    # a single hub with more edges than one large-bin chunk
+    n = 5000
+    src = np.zeros(n - 1, dtype=np.int64)
+    dst = np.arange(1, n)
+    g = daic_gen.from_edges(n, np.concatenate([src, dst]), np.concatenate([dst, np.zeros(n - 1)]))
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.8, np.full(n, 0.2), eps=1e-14)
+    for sched, q in (("all", 1.0), ("exact", 1e-4), ("sampled", 0.001)):
+        p = pr_problem(daic, g, 0.8)
+        assert p.run(eps=1e-12, q=q, sched=sched).converged
+        # the hub's value is a sum of ~5000 terms on both sides: FP64 rounding
+        # of that order, so the bound is relative
+        assert np.abs(p.get() - ref).sum() <= 1e-12 * ref.sum()
+
+
+def test_not_converged_status(daic):
+    say("case max rounds")
+    g = daic_gen.rmat(12, 8, seed=61)
+    p = pr_problem(daic, g, 0.8)
+    res = p.run(eps=1e-12, q=1.0, max_rounds=3, rounds_per_check=1)
+    assert res.status == daic.NOT_CONVERGED
+    assert res.stats["rounds"] == 3
+    # resume from the stopped state reaches the same fixed point
+    res2 = p.run(eps=1e-10, q=1.0)
+    assert res2.converged
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.8, np.full(g.n, 0.2), eps=1e-13)
+    assert np.abs(p.get() - ref).sum() <= 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Selection kernels against the oracle's rules
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1000, 70001])
+@pytest.mark.parametrize("q", [0.001, 0.1, 0.6])
+@pytest.mark.parametrize("state", ["f64", "f32", "u32"])
+def test_exact_topk_matches_oracle(daic, n, q, state):
+    say("case exact topk", n, q, state)
+    rng = np.random.default_rng(n + int(q * 1000))
+    g = daic_gen.from_edges(n, [], [])
+    if state == "u32":
+        w = np.ones(0, dtype=np.uint32)
+        gg = daic.Graph(g.row_ptr, g.col, w)
+        p = daic.Problem(gg, daic.MIN, daic.G_EDGE_ADD, state="u32")
+        v = rng.integers(0, 50, n).astype(np.uint32)
+        v[rng.random(n) < 0.1] = oracle.INF_U32
+        dv = rng.integers(0, 60, n).astype(np.uint32)
+        dv[rng.random(n) < 0.3] = oracle.INF_U32
+        p.set_init(v, dv)
+        pr = oracle.priority(oracle.OP_MIN, v, dv)
+    else:
+        p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8,
+                         state=state)
+        dv = rng.integers(0, 40, n) * 0.125  # many exact ties
+        dv[rng.random(n) < 0.2] = 0.0
+        dv *= np.where(rng.random(n) < 0.5, -1, 1)
+        p.set_init(np.zeros(n), dv)
+        pr = np.abs(dv)
+    sel, _ = p.select_frontier(q=q, sched="exact")
+    want = oracle.topk_exact(pr, q)
+    np.testing.assert_array_equal(np.nonzero(sel)[0], want)
+
+
+@pytest.mark.parametrize("round_no", [0, 3, 17])
+@pytest.mark.parametrize("q", [0.01, 0.1, 1.0])
+def test_sampled_threshold_matches_oracle(daic, round_no, q):
+    say("case sampled", round_no, q)
+    n = 50000
+    rng = np.random.default_rng(round_no)
+    g = daic_gen.from_edges(n, [], [])
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8,
+                     state="f32")
+    dv = rng.exponential(1.0, n).astype(np.float32).astype(np.float64)
+    dv[rng.random(n) < 0.4] = 0.0
+    p.set_init(np.zeros(n), dv)
+    sel, tau = p.select_frontier(q=q, sched="sampled", seed=1234, round_no=round_no, n_samples=4096)
+    pr = np.abs(dv).astype(np.float32)
+    tau_o = oracle.sampled_threshold(pr, q, 4096, 1234, round_no)
+    want = (pr >= tau_o) & (pr > 0)
+    np.testing.assert_array_equal(sel, want)
+    if q < 1.0:
+        assert np.float32(tau) == tau_o
+
+
+def test_device_graph_from_torch(daic):
+    import torch
+
+    say("case device graph")
+    g = daic_gen.rmat(12, 8, seed=71)
+    rp = torch.from_numpy(g.row_ptr.astype(np.int64)).cuda()
+    col = torch.from_numpy(g.col.astype(np.int32)).cuda()
+    stream = torch.cuda.current_stream()
+    gd = daic.Graph.from_device(rp, col, stream=stream)
+    p = daic.Problem(gd, daic.SUM, daic.G_DEG_SCALE, alpha=0.8)
+    p.set_init(*oracle.pagerank_init(g.n, 0.8))
+    assert p.run(eps=1e-10, stream=stream).converged
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.8, np.full(g.n, 0.2), eps=1e-13)
+    assert np.abs(p.get() - ref).sum() <= 1e-9
+    bad = col.clone()
+    bad[3] = g.n
+    with pytest.raises(daic.DaicError, match="out of range"):
+        daic.Graph.from_device(rp, bad, stream=stream)
