@@ -152,6 +152,12 @@ daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, doub
 /* v0, dv1: n host values each, typed double for FP states, uint32 for U32,
  * int32 for I32. The fourth condition v0 (+) dv1 = f(v0) is the caller's. */
 daic_status daic_problem_set_init(daic_problem* p, const void* v0, const void* dv1);
+/* The same from device arrays (borrowed only for the call) in the state's
+ * element type: double (F64), float (F32, F32_KAHAN; the compensation is
+ * cleared), uint32 (U32), int32 (I32). Enqueued on hip_stream; with a NULL
+ * stream the call returns after the copy. */
+daic_status daic_problem_set_init_device(daic_problem* p, const void* d_v0, const void* d_dv1,
+                                         void* hip_stream);
 /* Run rounds until the stop rule holds (DAIC_OK) or max_rounds (warning). */
 daic_status daic_run(daic_problem* p, const daic_run_opts* opts, daic_stats* stats);
 /* Copy the state out: v_out (n values; double for FP states, where F32_KAHAN
@@ -168,6 +174,22 @@ const char* daic_last_error(void);
  * a double. round selects the sample stream of TOPK_SAMPLED.              */
 daic_status daic_select_frontier(daic_problem* p, const daic_run_opts* opts, uint64_t round,
                                  uint8_t* sel_out, double* threshold_out);
+
+/* daic_profile runs like daic_run but launches every kernel on its own,
+ * bracketed by HIP events on the run's stream, one round at a time, and
+ * reports per kernel class: launches, summed duration and the algorithmic
+ * bytes those launches had to move (per-edge and per-vertex figures of the
+ * round's actual work). At most cap classes are written; *n_out receives
+ * the count. Slower than daic_run (one host sync per round).             */
+typedef struct {
+  char name[32];
+  uint64_t launches;
+  double total_ms;
+  double alg_bytes;
+  double edges;
+} daic_kernel_time;
+daic_status daic_profile(daic_problem* p, const daic_run_opts* opts, uint32_t cap,
+                         daic_kernel_time* out, uint32_t* n_out, daic_stats* stats);
 
 #ifdef __cplusplus
 }

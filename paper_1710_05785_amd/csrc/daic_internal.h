@@ -43,6 +43,10 @@ struct Ctl {
   uint64_t max_rounds;   // absolute round limit
   uint64_t activations;  // vertex updates performed
   uint64_t pushed;       // messages sent
+  uint64_t pushed_large; // messages sent from large-bin vertices
+  uint64_t round_act;    // the last round's activations, messages, large-bin messages
+  uint64_t round_pushed;
+  uint64_t round_pushed_large;
   uint64_t n_small;      // items in the small bin this round
   uint64_t n_large;      // items in the large bin this round
   uint32_t done;         // stop rule holds
@@ -54,7 +58,8 @@ struct Ctl {
   uint64_t k_rem;        // radix select: rank still to place
   uint64_t radix_prefix; // radix select: key bits fixed so far
   uint32_t radix_skip;   // radix select: nothing to do (all pending fit)
-  uint32_t pad;
+  uint32_t pull;         // the next round runs as a pull over in-edges (dense round)
+  uint32_t last_pull;    // the round just run was a dense round
   uint32_t hist[256];    // radix select histogram
 };
 
@@ -82,11 +87,36 @@ daic_status learned_prepare(daic_problem* p, const daic_sched_model* model, hipS
 daic_status learned_scores(daic_problem* p, const daic_sched_model* model, hipStream_t s,
                            const float** score);
 void learned_after_round(daic_problem* p, hipStream_t s);
+// Builds the in-edge form of g (no-op when built). Needs m < 2^32.
+daic_status pull_prepare(daic_graph* g, hipStream_t s);
+void pull_release(daic_graph* g);
 
+}  // namespace daic
+
+namespace daic {
+// In-edge (transposed) form of a graph for dense rounds, built on first use.
+// Sources are renumbered by out-degree (descending, ties by id) so that the
+// message bases of high-degree senders share cache lines.
+struct PullGraph {
+  bool ready = false;
+  uint32_t* perm = nullptr;     // perm[j] = rank of vertex j by out-degree
+  void* rowT = nullptr;         // in-edge offsets, RowT[n+1]
+  uint32_t* srcT = nullptr;     // perm[source] of each in-edge, sorted by (target, perm[source])
+  uint32_t* eidT = nullptr;     // original edge index of each in-edge (weighted graphs)
+  uint32_t* small_tgt = nullptr;  // targets with in-degree 1..kSmallMaxDeg
+  uint64_t n_small = 0;
+  uint32_t* large_tgt = nullptr;  // items (target, chunk) for larger in-degrees
+  uint32_t* large_chunk = nullptr;
+  uint32_t* large_nch = nullptr;  // number of chunks of the item's target
+  uint64_t n_large = 0;
+  uint64_t small_edges = 0;       // in-edges of the small targets
+  uint64_t large_edges = 0;
+};
 }  // namespace daic
 
 struct daic_graph {
   daic::GraphDev dev;
+  daic::PullGraph pull;
   void* own_row = nullptr;      // owned allocations (null when borrowed)
   void* own_col = nullptr;
   void* own_w = nullptr;

@@ -50,14 +50,27 @@ struct KArgs {
   uint32_t* blk_large;
   uint64_t* off_small;      // [blocks+1] prefix of blk_small
   uint64_t* off_large;      // [blocks+1] prefix of blk_large
-  uint64_t* blk_act;        // per-block activations / pushed edges
+  uint64_t* blk_act;        // per-block activations / pushed edges (all, large bin)
   uint64_t* blk_push;
+  uint64_t* blk_push_large;
   uint32_t* blk_ties;       // exact top-k: keys equal to tau per block
   uint64_t* off_ties;       // exclusive prefix of blk_ties
   double* part_r;           // residual partials per block
   uint64_t* part_n;         // pending-count partials per block
   uint8_t* sel_out;         // dry selection output [n]
   const float* score;       // learned scheduler: multiplier in (0,1) per vertex, or null
+  // dense rounds (pull over in-edges)
+  const uint32_t* perm;     // renumbering of sources by out-degree
+  const uint32_t* rowT;     // in-edge offsets [n+1]
+  const uint32_t* srcT;     // renumbered source of each in-edge
+  const void* wT;           // S[m] weights in in-edge order (EDGE_SCALE)
+  void* mu_pi;              // S[n] message base of every vertex, renumbered
+  const uint32_t* pt_small; // targets with in-degree 1..kSmallMaxDeg
+  uint64_t pn_small;
+  const uint32_t* pt_large; // (target, chunk, chunks of target) items
+  const uint32_t* pt_chunk;
+  const uint32_t* pt_nch;
+  uint64_t pn_large;
 };
 
 __device__ __forceinline__ uint32_t lane_id() {
@@ -267,8 +280,11 @@ __device__ __forceinline__ void push_edge(const KArgs& a, uint64_t e, typename T
 // A1: residual of the current state and the stop rule. Deterministic: block
 // partials are summed by the last block in a fixed order.
 // ---------------------------------------------------------------------------
+// Besides the residual, the last block picks the direction of the next round:
+// a dense round (pull over in-edges) when at least pull_min vertices are
+// expected to update (min(pending, k_sel)); k_sel = 0 disables dense rounds.
 template <int ST>
-__global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round) {
+__global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round, uint64_t k_sel, uint64_t pull_min) {
   using S = typename Tr<ST>::S;
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
@@ -317,6 +333,7 @@ __global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round) {
     bool done = Tr<ST>::sum ? (rr <= ctl->eps || nn == 0) : (nn == 0);
     ctl->done = done ? 1u : 0u;
     ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
+    ctl->pull = (k_sel != 0 && (nn < k_sel ? nn : k_sel) >= pull_min) ? 1u : 0u;
     ctl->ticket = 0;
   }
 }
@@ -522,7 +539,8 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
   S* small_mu = static_cast<S*>(a.small_mu);
   S* large_mu = static_cast<S*>(a.large_mu);
   const uint64_t large_base = DRY ? 0 : a.large_off[b];
-  uint64_t ties_seen = 0, n_small = 0, n_large = 0, act = 0, pushed = 0;
+  const bool pull = !DRY && ctl->pull != 0;
+  uint64_t ties_seen = 0, n_small = 0, n_large = 0, act = 0, pushed = 0, pushed_large = 0;
 
   for (uint64_t base = lo; base < hi; base += 256) {
     const uint64_t j = base + threadIdx.x;
@@ -557,6 +575,15 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
       deg = row_at<RowT>(a.row, j + 1) - beg;
       send = claim_fold<ST, G>(a, j, deg, vj, dj, mu) && deg > 0;
     }
+    if (pull) {  // dense round: every vertex publishes its message base (0 if silent)
+      if constexpr (Tr<ST>::sum) {
+        if (in) static_cast<S*>(a.mu_pi)[a.perm[j]] = send ? mu : (S)0;
+      }
+      act += sel ? 1 : 0;
+      pushed += send ? deg : 0;
+      pushed_large += (send && deg > kSmallMaxDeg) ? deg : 0;
+      continue;
+    }
     uint32_t cnt[2] = {(send && deg <= kSmallMaxDeg) ? 1u : 0u,
                        (send && deg > kSmallMaxDeg) ? (uint32_t)((deg + kChunk - 1) / kChunk) : 0u};
     uint32_t tot[2];
@@ -580,15 +607,18 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
     n_large += tot[1];
     act += sel ? 1 : 0;
     pushed += send ? deg : 0;
+    pushed_large += (send && deg > kSmallMaxDeg) ? deg : 0;
   }
   if constexpr (!DRY) {
     act = block_sum256(act);
     pushed = block_sum256(pushed);
+    pushed_large = block_sum256(pushed_large);
     if (threadIdx.x == 0) {
       a.blk_small[b] = (uint32_t)n_small;
       a.blk_large[b] = (uint32_t)n_large;
       a.blk_act[b] = act;
       a.blk_push[b] = pushed;
+      a.blk_push_large[b] = pushed_large;
     }
   }
 }
@@ -597,31 +627,40 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
 __global__ __launch_bounds__(1024) void k_bin_scan(KArgs a) {
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
+  if (threadIdx.x == 0) ctl->last_pull = ctl->pull;
   excl_prefix_1024(a.blk_small, a.off_small, a.blocks, &ctl->n_small);
   __syncthreads();
   excl_prefix_1024(a.blk_large, a.off_large, a.blocks, &ctl->n_large);
   __syncthreads();
-  uint64_t act = 0, push = 0;
+  uint64_t act = 0, push = 0, pl = 0;
   for (uint32_t i = threadIdx.x; i < a.blocks; i += 1024) {
     act += a.blk_act[i];
     push += a.blk_push[i];
+    pl += a.blk_push_large[i];
   }
   act = wave_sum(act);
   push = wave_sum(push);
-  __shared__ uint64_t s_a[16], s_p[16];
+  pl = wave_sum(pl);
+  __shared__ uint64_t s_a[16], s_p[16], s_l[16];
   if (lane_id() == 0) {
     s_a[threadIdx.x >> 6] = act;
     s_p[threadIdx.x >> 6] = push;
+    s_l[threadIdx.x >> 6] = pl;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint64_t ta = 0, tp = 0;
+    uint64_t ta = 0, tp = 0, tl = 0;
     for (int w = 0; w < 16; ++w) {
       ta += s_a[w];
       tp += s_p[w];
+      tl += s_l[w];
     }
     ctl->activations += ta;
     ctl->pushed += tp;
+    ctl->pushed_large += tl;
+    ctl->round_act = ta;
+    ctl->round_pushed = tp;
+    ctl->round_pushed_large = tl;
   }
 }
 
@@ -634,7 +673,7 @@ template <int ST, int G, typename RowT>
 __global__ __launch_bounds__(64) void k_push_small(KArgs a) {
   using S = typename Tr<ST>::S;
   Ctl* ctl = a.ctl;
-  if (ctl_halted(ctl)) return;
+  if (ctl_halted(ctl) || ctl->pull) return;
   const uint64_t total = ctl->n_small;
   __shared__ uint8_t owner[64 * kSmallMaxDeg];
   __shared__ uint32_t s_excl[64];
@@ -676,7 +715,7 @@ template <int ST, int G, typename RowT>
 __global__ __launch_bounds__(64) void k_push_large(KArgs a) {
   using S = typename Tr<ST>::S;
   Ctl* ctl = a.ctl;
-  if (ctl_halted(ctl)) return;
+  if (ctl_halted(ctl) || ctl->pull) return;
   const uint64_t total = ctl->n_large;
   const S* large_mu = static_cast<const S*>(a.large_mu);
   for (uint64_t i = blockIdx.x; i < total; i += gridDim.x) {
@@ -691,6 +730,97 @@ __global__ __launch_bounds__(64) void k_push_large(KArgs a) {
     uint64_t end = min(re, beg + kChunk);
     for (uint64_t e = beg + threadIdx.x; e < end; e += 64) push_edge<ST, G>(a, e, mu);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Dense rounds: the receive side of Eq. async done by the receiver. Every
+// target sums the message bases of its in-neighbours (0 for silent ones) and
+// adds the sum to dv. Sums are formed in FP64; a target is owned by one wave
+// unless its in-degree spans several chunks, whose partial sums are added
+// atomically.
+// ---------------------------------------------------------------------------
+template <int ST, int G>
+__device__ __forceinline__ double pull_msg(const KArgs& a, uint64_t p) {
+  using S = typename Tr<ST>::S;
+  double m = (double)static_cast<const S*>(a.mu_pi)[a.srcT[p]];
+  if constexpr (G == DAIC_G_EDGE_SCALE) m *= (double)static_cast<const S*>(a.wT)[p];
+  return m;
+}
+
+template <int ST, int G>
+__global__ __launch_bounds__(64) void k_pull_small(KArgs a) {
+  using S = typename Tr<ST>::S;
+  if constexpr (Tr<ST>::sum) {
+    Ctl* ctl = a.ctl;
+    if (ctl_halted(ctl) || !ctl->pull) return;
+    const uint64_t total = a.pn_small;
+    __shared__ uint8_t owner[64 * kSmallMaxDeg];
+    __shared__ double s_val[64 * kSmallMaxDeg];
+    __shared__ uint32_t s_excl[64];
+    __shared__ uint32_t s_beg[64];
+    const uint32_t lane = threadIdx.x;
+    S* dv = static_cast<S*>(a.dv);
+    for (uint64_t g = blockIdx.x; g * 64 < total; g += gridDim.x) {
+      const uint64_t i = g * 64 + lane;
+      uint32_t deg = 0, beg = 0, t = 0;
+      if (i < total) {
+        t = a.pt_small[i];
+        beg = a.rowT[t];
+        deg = a.rowT[t + 1] - beg;
+      }
+      const uint32_t incl = wave_incl_scan(deg);
+      const uint32_t excl = incl - deg;
+      const uint32_t E = __shfl(incl, 63, 64);
+      s_excl[lane] = excl;
+      s_beg[lane] = beg;
+      for (uint32_t k = 0; k < deg; ++k) owner[excl + k] = (uint8_t)lane;
+      __syncthreads();
+      for (uint32_t e = lane; e < E; e += 64) {
+        const uint32_t o = owner[e];
+        s_val[e] = pull_msg<ST, G>(a, (uint64_t)s_beg[o] + (e - s_excl[o]));
+      }
+      __syncthreads();
+      if (deg) {
+        double acc = 0.0;
+        for (uint32_t k = 0; k < deg; ++k) acc += s_val[excl + k];
+        dv[t] = (S)((double)dv[t] + acc);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int ST, int G>
+__global__ __launch_bounds__(64) void k_pull_large(KArgs a) {
+  using S = typename Tr<ST>::S;
+  if constexpr (Tr<ST>::sum) {
+    Ctl* ctl = a.ctl;
+    if (ctl_halted(ctl) || !ctl->pull) return;
+    S* dv = static_cast<S*>(a.dv);
+    for (uint64_t i = blockIdx.x; i < a.pn_large; i += gridDim.x) {
+      const uint32_t t = a.pt_large[i];
+      const uint32_t c = a.pt_chunk[i];
+      const uint32_t nch = a.pt_nch[i];
+      const uint64_t rb = a.rowT[t], re = a.rowT[t + 1];
+      const uint64_t beg = rb + (uint64_t)c * kChunk;
+      const uint64_t end = min(re, beg + kChunk);
+      double acc = 0.0;
+      for (uint64_t p = beg + threadIdx.x; p < end; p += 64) acc += pull_msg<ST, G>(a, p);
+      acc = wave_sum(acc);
+      if (threadIdx.x == 0) {
+        if (nch == 1) dv[t] = (S)((double)dv[t] + acc);
+        else unsafeAtomicAdd(&dv[t], (S)acc);
+      }
+    }
+  }
+}
+
+// Weights in in-edge order: wT[p] = w[eidT[p]].
+template <typename S>
+__global__ void k_gather_weights(const S* w, const uint32_t* eidT, uint64_t m, S* wT) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < m; i += st) wT[i] = w[eidT[i]];
 }
 
 // ---------------------------------------------------------------------------

@@ -90,9 +90,10 @@ struct GraphCacheKey {
   uint32_t K = 0;
   const void* stream = nullptr;
   const float* score = nullptr;
+  uint64_t k_sel = 0, pull_min = 0;
   bool operator==(const GraphCacheKey& o) const {
     return sched == o.sched && k == o.k && S == o.S && q == o.q && seed == o.seed && K == o.K &&
-           stream == o.stream && score == o.score;
+           stream == o.stream && score == o.score && k_sel == o.k_sel && pull_min == o.pull_min;
   }
 };
 
@@ -113,14 +114,52 @@ struct daic_problem {
   hipGraph_t graph = nullptr;
   GraphCacheKey key;
   std::vector<void*> allocs;
+  bool pull_ready = false;
+  uint64_t k_sel = 0;      // dense-round rule of the current run (see k_residual)
+  uint64_t pull_min = 0;
 };
 
 namespace daic {
 
+// Per-kernel timing with HIP events recorded on the launch stream.
+struct Prof {
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t ev() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      (void)hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~Prof() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+template <class F>
+static void launch(Prof* pr, const char* name, hipStream_t s, F&& f) {
+  if (!pr) {
+    f();
+    return;
+  }
+  hipEvent_t a = pr->ev(), b = pr->ev();
+  (void)hipEventRecord(a, s);
+  f();
+  (void)hipEventRecord(b, s);
+  pr->recs.push_back({name, a, b});
+}
+
 // Enqueue functions per instantiation.
 struct Ops {
   void (*residual)(daic_problem*, hipStream_t, int);
-  void (*round)(daic_problem*, const daic_run_opts*, hipStream_t, const float* score);
+  void (*round)(daic_problem*, const daic_run_opts*, hipStream_t, const float* score, Prof* pr);
   void (*select)(daic_problem*, const daic_run_opts*, hipStream_t, uint64_t round_override);
 };
 
@@ -131,48 +170,71 @@ struct Impl {
   using Key = typename Tr<ST>::Key;
 
   static void residual(daic_problem* p, hipStream_t s, int count_round) {
-    hipLaunchKernelGGL(k_residual<ST>, dim3(p->a.blocks), dim3(256), 0, s, p->a, count_round);
+    hipLaunchKernelGGL(k_residual<ST>, dim3(p->a.blocks), dim3(256), 0, s, p->a, count_round, p->k_sel,
+                       p->pull_min);
   }
 
   // Threshold of a round (A2) for the given rule.
   static void threshold(daic_problem* p, const daic_run_opts* o, hipStream_t s, const KArgs& a,
-                        uint64_t round_override) {
+                        uint64_t round_override, Prof* pr) {
     const uint64_t n = p->a.n;
     if (o->sched == DAIC_SCHED_ALL) {
-      hipLaunchKernelGGL(k_select_all, dim3(1), dim3(1), 0, s, a.ctl);
+      launch(pr, "select_all", s, [&] { hipLaunchKernelGGL(k_select_all, dim3(1), dim3(1), 0, s, a.ctl); });
     } else if (o->sched == DAIC_SCHED_TOPK_SAMPLED) {
       uint32_t S = o->n_samples ? o->n_samples : kMaxSamples;
       uint32_t rank = (uint32_t)std::max(1.0, std::ceil(o->priority_fraction * (double)S));
-      hipLaunchKernelGGL(k_sample<ST>, dim3(1), dim3(1024), 0, s, a, S, rank, o->seed, round_override);
+      launch(pr, "sample_threshold", s, [&] {
+        hipLaunchKernelGGL(k_sample<ST>, dim3(1), dim3(1024), 0, s, a, S, rank, o->seed, round_override);
+      });
     } else {  // exact top-k (also the learned rule, on the learned keys)
       uint64_t k = (uint64_t)std::ceil(o->priority_fraction * (double)n);
       if (k < 1) k = 1;
-      hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(1), 0, s, a.ctl, k);
       const int passes = (int)sizeof(Key);
       uint32_t hgrid = (uint32_t)std::min<uint64_t>(2048, (n + 255) / 256);
-      for (int pass = 0; pass < passes; ++pass) {
-        hipLaunchKernelGGL(k_radix_hist<ST>, dim3(hgrid), dim3(256), 0, s, a, pass);
-        hipLaunchKernelGGL(k_radix_pick<ST>, dim3(1), dim3(1), 0, s, a.ctl, pass);
-      }
-      hipLaunchKernelGGL(k_tie_count<ST>, dim3(a.blocks), dim3(256), 0, s, a);
-      hipLaunchKernelGGL(k_tie_scan, dim3(1), dim3(1024), 0, s, a);
+      launch(pr, "topk_radix", s, [&] {
+        hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(1), 0, s, a.ctl, k);
+        for (int pass = 0; pass < passes; ++pass) {
+          hipLaunchKernelGGL(k_radix_hist<ST>, dim3(hgrid), dim3(256), 0, s, a, pass);
+          hipLaunchKernelGGL(k_radix_pick<ST>, dim3(1), dim3(1), 0, s, a.ctl, pass);
+        }
+        hipLaunchKernelGGL(k_tie_count<ST>, dim3(a.blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_tie_scan, dim3(1), dim3(1024), 0, s, a);
+      });
     }
   }
 
-  static void round(daic_problem* p, const daic_run_opts* o, hipStream_t s, const float* score) {
+  static void round(daic_problem* p, const daic_run_opts* o, hipStream_t s, const float* score, Prof* pr) {
     KArgs a = p->a;
     a.score = score;
-    threshold(p, o, s, a, ~0ull);
-    hipLaunchKernelGGL((k_claim<ST, G, RowT, false>), dim3(a.blocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL((k_push_small<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
-    hipLaunchKernelGGL((k_push_large<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(k_residual<ST>, dim3(a.blocks), dim3(256), 0, s, a, 1);
+    threshold(p, o, s, a, ~0ull, pr);
+    launch(pr, "claim", s, [&] {
+      hipLaunchKernelGGL((k_claim<ST, G, RowT, false>), dim3(a.blocks), dim3(256), 0, s, a);
+    });
+    launch(pr, "bin_scan", s, [&] { hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a); });
+    launch(pr, "push_small", s, [&] {
+      hipLaunchKernelGGL((k_push_small<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
+    });
+    launch(pr, "push_large", s, [&] {
+      hipLaunchKernelGGL((k_push_large<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
+    });
+    if (p->pull_ready) {
+      launch(pr, "pull_small", s, [&] {
+        uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((a.pn_small + 63) / 64, 16384));
+        hipLaunchKernelGGL((k_pull_small<ST, G>), dim3(gs), dim3(64), 0, s, a);
+      });
+      launch(pr, "pull_large", s, [&] {
+        uint32_t gl = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(a.pn_large, 16384));
+        hipLaunchKernelGGL((k_pull_large<ST, G>), dim3(gl), dim3(64), 0, s, a);
+      });
+    }
+    launch(pr, "residual", s, [&] {
+      hipLaunchKernelGGL(k_residual<ST>, dim3(a.blocks), dim3(256), 0, s, a, 1, p->k_sel, p->pull_min);
+    });
   }
 
   static void select(daic_problem* p, const daic_run_opts* o, hipStream_t s, uint64_t round_override) {
     KArgs a = p->a;
-    threshold(p, o, s, a, round_override);
+    threshold(p, o, s, a, round_override, nullptr);
     hipLaunchKernelGGL((k_claim<ST, G, RowT, true>), dim3(a.blocks), dim3(256), 0, s, a);
   }
 
@@ -220,12 +282,18 @@ __global__ void k_init_ctl(Ctl* ctl, double eps, uint64_t max_rounds) {
   ctl->max_rounds = max_rounds;
   ctl->activations = 0;
   ctl->pushed = 0;
+  ctl->pushed_large = 0;
+  ctl->round_act = 0;
+  ctl->round_pushed = 0;
+  ctl->round_pushed_large = 0;
   ctl->done = 0;
   ctl->stop = 0;
   ctl->ticket = 0;
   ctl->sel_mode = 0;
   ctl->tau = 0;
   ctl->radix_skip = 1;
+  ctl->pull = 0;
+  ctl->last_pull = 0;
   for (int i = 0; i < 256; ++i) ctl->hist[i] = 0;
 }
 
@@ -408,6 +476,7 @@ void daic_graph_destroy(daic_graph* g) {
   dfree(g->own_w);
   dfree(g->row32);
   dfree(g->large_off);
+  pull_release(g);
   delete g;
 }
 
@@ -488,6 +557,7 @@ daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, doub
   GRAB(off_ties, uint64_t*, (nb + 1) * 8);
   GRAB(blk_act, uint64_t*, nb * 8);
   GRAB(blk_push, uint64_t*, nb * 8);
+  GRAB(blk_push_large, uint64_t*, nb * 8);
   GRAB(part_r, double*, nb * 8);
   GRAB(part_n, uint64_t*, nb * 8);
 #undef GRAB
@@ -604,6 +674,64 @@ static daic_status check_opts(const daic_problem* p, const daic_run_opts* o) {
   return DAIC_OK;
 }
 
+// Dense rounds (pull over in-edges) for sum problems: builds the in-edge form
+// on first use and sets the direction rule of this run. DAIC_NO_PULL=1 turns
+// them off; DAIC_PULL_DIV (default 32) sets the fraction n/div of updating
+// vertices from which a round runs dense.
+static daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStream_t s) {
+  p->k_sel = 0;
+  p->pull_min = 0;
+  const bool sum = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
+  const GraphDev& d = p->g->dev;
+  if (!sum || std::getenv("DAIC_NO_PULL") || !d.row32 || d.m > 0x7FFFFFFFull || d.n > 0x7FFFFFFFull)
+    return DAIC_OK;
+  if (!p->pull_ready) {
+    daic_graph* g = const_cast<daic_graph*>(p->g);
+    daic_status rc = pull_prepare(g, s);
+    if (rc) return rc;
+    const size_t S = state_size(p->st);
+    void* mu = nullptr;
+    DAIC_HIP(hipMalloc(&mu, std::max<uint64_t>(d.n, 1) * S));
+    p->allocs.push_back(mu);
+    DAIC_HIP(hipMemsetAsync(mu, 0, d.n * S, s));
+    KArgs& a = p->a;
+    a.mu_pi = mu;
+    if (p->gk == DAIC_G_EDGE_SCALE) {
+      void* wt = nullptr;
+      DAIC_HIP(hipMalloc(&wt, std::max<uint64_t>(d.m, 1) * S));
+      p->allocs.push_back(wt);
+      if (p->st == ST_F64)
+        hipLaunchKernelGGL(k_gather_weights<double>, dim3(grid_for(d.m)), dim3(256), 0, s,
+                           static_cast<const double*>(a.w), g->pull.eidT, d.m, static_cast<double*>(wt));
+      else
+        hipLaunchKernelGGL(k_gather_weights<float>, dim3(grid_for(d.m)), dim3(256), 0, s,
+                           static_cast<const float*>(a.w), g->pull.eidT, d.m, static_cast<float*>(wt));
+      a.wT = wt;
+    }
+    a.perm = g->pull.perm;
+    a.rowT = static_cast<const uint32_t*>(g->pull.rowT);
+    a.srcT = g->pull.srcT;
+    a.pt_small = g->pull.small_tgt;
+    a.pn_small = g->pull.n_small;
+    a.pt_large = g->pull.large_tgt;
+    a.pt_chunk = g->pull.large_chunk;
+    a.pt_nch = g->pull.large_nch;
+    a.pn_large = g->pull.n_large;
+    DAIC_HIP(hipStreamSynchronize(s));
+    p->pull_ready = true;
+    if (p->exec) {  // captured rounds predate the dense-round kernels
+      (void)hipGraphExecDestroy(p->exec);
+      p->exec = nullptr;
+    }
+  }
+  uint64_t div = 32;
+  if (const char* e = std::getenv("DAIC_PULL_DIV")) div = std::max<uint64_t>(1, std::strtoull(e, nullptr, 10));
+  const uint64_t n = d.n;
+  p->k_sel = o->sched == DAIC_SCHED_ALL ? n : std::max<uint64_t>(1, (uint64_t)std::ceil(o->priority_fraction * (double)n));
+  p->pull_min = std::max<uint64_t>(1, (n + div - 1) / div);
+  return DAIC_OK;
+}
+
 static double per_edge_bytes(const daic_problem* p) {
   const double S = (double)state_size(p->st);
   double b = 4.0 + 2.0 * S;  // col + RMW of dv_k
@@ -639,6 +767,8 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
     if (rc) return rc;
   }
 
+  rc = dense_rounds_setup(p, o, s);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, p->a.ctl, o->eps, max_rounds);
   ops.residual(p, s, 0);
   DAIC_HIP(hipEventRecord(p->ev0, s));
@@ -652,11 +782,13 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
   key.seed = o->seed;
   key.K = K;
   key.stream = s;
+  key.k_sel = p->k_sel;
+  key.pull_min = p->pull_min;
   if (use_graph && !(p->exec && p->key == key)) {
     if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
     if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
     DAIC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (uint32_t r = 0; r < K; ++r) ops.round(p, o, s, nullptr);
+    for (uint32_t r = 0; r < K; ++r) ops.round(p, o, s, nullptr, nullptr);
     hipGraph_t graph;
     DAIC_HIP(hipStreamEndCapture(s, &graph));
     p->graph = graph;
@@ -668,13 +800,13 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
       for (uint32_t r = 0; r < K; ++r) {
         rc = learned_scores(p, o->model, s, &score);
         if (rc) return rc;
-        ops.round(p, o, s, score);
+        ops.round(p, o, s, score, nullptr);
         learned_after_round(p, s);
       }
     } else if (use_graph) {
       DAIC_HIP(hipGraphLaunch(p->exec, s));
     } else {
-      for (uint32_t r = 0; r < K; ++r) ops.round(p, o, s, nullptr);
+      for (uint32_t r = 0; r < K; ++r) ops.round(p, o, s, nullptr, nullptr);
     }
     DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     DAIC_HIP(hipStreamSynchronize(s));
@@ -694,6 +826,115 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
     stats->gteps = ms > 0 ? (double)c.pushed / (ms * 1e-3) / 1e9 : 0.0;
     stats->alg_bytes = (double)c.pushed * per_edge_bytes(p) + (double)c.activations * per_vertex_bytes(p) +
                        (double)c.rounds * (double)n * (double)state_size(p->st) * 2.0;
+  }
+  return c.done ? DAIC_OK : DAIC_NOT_CONVERGED;
+}
+
+daic_status daic_problem_set_init_device(daic_problem* p, const void* d_v0, const void* d_dv1, void* hip_stream) {
+  if (!p || !d_v0 || !d_dv1) return fail(DAIC_E_INVALID, "null argument");
+  const uint64_t n = p->g->dev.n;
+  if (n == 0) return DAIC_OK;
+  hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : p->own_stream;
+  const size_t S = state_size(p->st);
+  DAIC_HIP(hipMemcpyAsync(p->a.v, d_v0, n * S, hipMemcpyDeviceToDevice, s));
+  DAIC_HIP(hipMemcpyAsync(p->a.dv, d_dv1, n * S, hipMemcpyDeviceToDevice, s));
+  if (p->a.c) hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(256), 0, s, p->a.c, 0.0f, n);
+  if (!hip_stream) DAIC_HIP(hipStreamSynchronize(s));
+  return DAIC_OK;
+}
+
+// Algorithmic bytes of one launch of a kernel class in the round just run.
+static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c) {
+  const double S = (double)state_size(p->st);
+  const double R = p->g->dev.row32 ? 4.0 : 8.0;
+  const double e = per_edge_bytes(p);
+  const double n = (double)p->g->dev.n;
+  const double small_edges = (double)(c.round_pushed - c.round_pushed_large);
+  if (!std::strcmp(name, "push_small"))
+    return small_edges * e + (double)c.n_small * (4.0 + S + 2.0 * R);
+  if (!std::strcmp(name, "push_large"))
+    return (double)c.round_pushed_large * e + (double)c.n_large * (8.0 + S + 2.0 * R);
+  if (!std::strcmp(name, "claim")) {
+    double kahan = p->st == ST_F32K ? 8.0 : 0.0;
+    double out = c.last_pull ? n * (4.0 + S) : (double)(c.n_small + c.n_large) * (4.0 + S);
+    return n * 2.0 * S + (double)c.round_act * (2.0 * R + 2.0 * S + kahan) + out;
+  }
+  if (!std::strcmp(name, "residual")) return n * S;
+  if (!std::strcmp(name, "pull_small") || !std::strcmp(name, "pull_large")) {
+    const PullGraph& P = p->g->pull;
+    const double per_in_edge = 4.0 + S + (p->gk == DAIC_G_EDGE_SCALE ? S : 0.0);
+    if (!std::strcmp(name, "pull_small"))
+      return (double)P.small_edges * per_in_edge + (double)P.n_small * (4.0 + 8.0 + 2.0 * S);
+    return (double)P.large_edges * per_in_edge + (double)P.n_large * (12.0 + 8.0 + 2.0 * S);
+  }
+  return 0.0;
+}
+
+daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, daic_kernel_time* out,
+                         uint32_t* n_out, daic_stats* stats) {
+  if (!p || !out || !n_out) return fail(DAIC_E_INVALID, "null argument");
+  daic_status rc = check_opts(p, o);
+  if (rc) return rc;
+  if (o->sched == DAIC_SCHED_LEARNED) return fail(DAIC_E_UNSUPPORTED, "profile takes the plain rules");
+  *n_out = 0;
+  const uint64_t n = p->g->dev.n;
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (n == 0) return DAIC_OK;
+  Ops ops;
+  if (!get_ops(p, &ops)) return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");
+  hipStream_t s = o->hip_stream ? static_cast<hipStream_t>(o->hip_stream) : p->own_stream;
+  const uint64_t max_rounds = o->max_rounds ? o->max_rounds : ~0ull;
+  rc = dense_rounds_setup(p, o, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, p->a.ctl, o->eps, max_rounds);
+  ops.residual(p, s, 0);
+  DAIC_HIP(hipStreamSynchronize(s));
+  std::vector<daic_kernel_time> acc;
+  auto slot = [&](const char* name) -> daic_kernel_time& {
+    for (auto& k : acc)
+      if (!std::strcmp(k.name, name)) return k;
+    daic_kernel_time k{};
+    std::snprintf(k.name, sizeof k.name, "%s", name);
+    acc.push_back(k);
+    return acc.back();
+  };
+  Prof prof;
+  double total_ms = 0.0;
+  for (;;) {
+    prof.recs.clear();
+    prof.used = 0;
+    ops.round(p, o, s, nullptr, &prof);
+    DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DAIC_HIP(hipStreamSynchronize(s));
+    const Ctl c = *p->h_ctl;
+    for (auto& r : prof.recs) {
+      float ms = 0.f;
+      DAIC_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      total_ms += ms;
+      // kernels of the other direction return at once: not counted as launches
+      const bool is_push = !std::strncmp(r.name, "push_", 5), is_pull = !std::strncmp(r.name, "pull_", 5);
+      if ((is_push && c.last_pull) || (is_pull && !c.last_pull)) continue;
+      daic_kernel_time& k = slot(r.name);
+      k.launches += 1;
+      k.total_ms += ms;
+      k.alg_bytes += kernel_bytes(p, r.name, c);
+      if (!std::strcmp(r.name, "push_small")) k.edges += (double)(c.round_pushed - c.round_pushed_large);
+      if (!std::strcmp(r.name, "push_large")) k.edges += (double)c.round_pushed_large;
+      if (!std::strcmp(r.name, "pull_small")) k.edges += (double)p->g->pull.small_edges;
+      if (!std::strcmp(r.name, "pull_large")) k.edges += (double)p->g->pull.large_edges;
+    }
+    if (c.done || c.stop) break;
+  }
+  const Ctl& c = *p->h_ctl;
+  for (uint32_t i = 0; i < acc.size() && i < cap; ++i) out[i] = acc[i];
+  *n_out = (uint32_t)std::min<size_t>(acc.size(), cap);
+  if (stats) {
+    stats->rounds = c.rounds;
+    stats->activations = c.activations;
+    stats->pushed_edges = c.pushed;
+    stats->final_residual = c.r;
+    stats->time_ms = total_ms;
+    stats->gteps = total_ms > 0 ? (double)c.pushed / (total_ms * 1e-3) / 1e9 : 0.0;
   }
   return c.done ? DAIC_OK : DAIC_NOT_CONVERGED;
 }

@@ -53,6 +53,12 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double),
+                ("edges", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -83,6 +89,10 @@ def lib():
         L.daic_problem_get.argtypes = [_vp, _vp, _vp]
         L.daic_problem_destroy.argtypes = [_vp]
         L.daic_problem_destroy.restype = None
+        L.daic_problem_set_init_device.argtypes = [_vp, _vp, _vp, _vp]
+        L.daic_profile.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint32,
+                                   ctypes.POINTER(KernelTime), ctypes.POINTER(ctypes.c_uint32),
+                                   ctypes.POINTER(Stats)]
         L.daic_select_frontier.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint64, _vp,
                                            ctypes.POINTER(ctypes.c_double)]
         _lib = L
@@ -206,6 +216,27 @@ class Problem:
         if v0.shape != (self.n,) or dv1.shape != (self.n,):
             raise ValueError("v0 and dv1 must have n entries")
         check(lib().daic_problem_set_init(self._h, _addr(v0), _addr(dv1)), "daic_problem_set_init")
+
+    def set_init_device(self, v0, dv1, stream=None):
+        """(v0, dv1) from device tensors in the state's element type."""
+        if v0.numel() != self.n or dv1.numel() != self.n:
+            raise ValueError("v0 and dv1 must have n entries")
+        check(lib().daic_problem_set_init_device(self._h, _addr(v0), _addr(dv1),
+                                                 _stream_handle(stream)),
+              "daic_problem_set_init_device")
+
+    def profile(self, **kw):
+        """Run with per-kernel event timing; returns (RunResult, [kernel dicts])."""
+        o = self.make_opts(**kw)
+        st = Stats()
+        arr = (KernelTime * 32)()
+        cnt = ctypes.c_uint32(0)
+        rc = check(lib().daic_profile(self._h, ctypes.byref(o), 32, arr, ctypes.byref(cnt),
+                                      ctypes.byref(st)), "daic_profile")
+        ks = [{"name": arr[i].name.decode(), "launches": arr[i].launches,
+               "total_ms": arr[i].total_ms, "alg_bytes": arr[i].alg_bytes,
+               "edges": arr[i].edges} for i in range(cnt.value)]
+        return RunResult(rc, st.as_dict()), ks
 
     @staticmethod
     def make_opts(eps=0.0, q=1.0, sched="all", max_rounds=0, rounds_per_check=8, n_samples=4096,

@@ -327,3 +327,40 @@ def test_device_graph_from_torch(daic):
     bad[3] = g.n
     with pytest.raises(daic.DaicError, match="out of range"):
         daic.Graph.from_device(rp, bad, stream=stream)
+
+
+@pytest.mark.parametrize("direction", ["push_only", "pull_when_dense", "pull_always"])
+@pytest.mark.parametrize("state,gk", [("f64", "deg"), ("f32_kahan", "deg"), ("f64", "edge")])
+def test_push_and_pull_rounds_agree(daic, monkeypatch, direction, state, gk):
+    """Dense rounds (receivers pull over in-edges) and push rounds reach the
+    same fixed point: both are legal update sequences of Eq. async."""
+    say("case direction", direction, state, gk)
+    monkeypatch.delenv("DAIC_NO_PULL", raising=False)
+    monkeypatch.delenv("DAIC_PULL_DIV", raising=False)
+    if direction == "push_only":
+        monkeypatch.setenv("DAIC_NO_PULL", "1")
+    elif direction == "pull_always":
+        monkeypatch.setenv("DAIC_PULL_DIV", "1000000000")
+    g = daic_gen.rmat(13, 16, seed=81)
+    if gk == "deg":
+        ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.8, np.full(g.n, 0.2), eps=1e-13)
+        p = pr_problem(daic, g, 0.8, state=state)
+    else:
+        w = daic_gen.lognormal_f64(82, g.m, 0.4, 0.8)
+        deg = g.outdeg()
+        rs = np.bincount(np.repeat(np.arange(g.n), deg), weights=w, minlength=g.n)
+        a = 0.8 / np.where(deg > 0, rs, 1.0)
+        ref, _, _ = oracle.jacobi_sum(g, oracle.G_EDGE_SCALE, 0.0, np.full(g.n, 0.2), w=w,
+                                      alpha_pv=a, eps=1e-13)
+        p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.SUM, daic.G_EDGE_SCALE,
+                         alpha_pv=a, state=state)
+        p.set_init(np.zeros(g.n), np.full(g.n, 0.2))
+    for sched, q in (("all", 1.0), ("sampled", 0.2), ("exact", 0.05)):
+        p.set_init(np.zeros(g.n), np.full(g.n, 0.2))
+        eps = 1e-10 if state == "f64" else 1e-5
+        assert p.run(eps=eps, q=q, sched=sched, seed=2).converged
+        err = np.abs(p.get() - ref).sum()
+        if state == "f64":
+            assert err <= 1e-9, (sched, err)
+        else:
+            assert err / ref.sum() <= 1e-5, (sched, err)
