@@ -145,9 +145,10 @@ def main():
     run_kw = dict(eps=args.eps, q=1.0, sched="all", rounds_per_check=args.rounds_per_check)
 
     if args.calib_copy:
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
         del a, b
 

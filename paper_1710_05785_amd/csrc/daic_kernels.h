@@ -747,49 +747,35 @@ __device__ __forceinline__ double pull_msg(const KArgs& a, uint64_t p) {
   return m;
 }
 
+// Small targets (in-degree 1..kSmallMaxDeg), one per thread; the static list
+// is ordered by in-degree class so that the lanes of a wave loop about equally.
 template <int ST, int G>
-__global__ __launch_bounds__(64) void k_pull_small(KArgs a) {
+__global__ __launch_bounds__(256) void k_pull_small(KArgs a) {
   using S = typename Tr<ST>::S;
   if constexpr (Tr<ST>::sum) {
     Ctl* ctl = a.ctl;
     if (ctl_halted(ctl) || !ctl->pull) return;
-    const uint64_t total = a.pn_small;
-    __shared__ uint8_t owner[64 * kSmallMaxDeg];
-    __shared__ double s_val[64 * kSmallMaxDeg];
-    __shared__ uint32_t s_excl[64];
-    __shared__ uint32_t s_beg[64];
-    const uint32_t lane = threadIdx.x;
     S* dv = static_cast<S*>(a.dv);
-    for (uint64_t g = blockIdx.x; g * 64 < total; g += gridDim.x) {
-      const uint64_t i = g * 64 + lane;
-      uint32_t deg = 0, beg = 0, t = 0;
-      if (i < total) {
-        t = a.pt_small[i];
-        beg = a.rowT[t];
-        deg = a.rowT[t + 1] - beg;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.pn_small; i += stride) {
+      const uint32_t t = a.pt_small[i];
+      const uint32_t beg = a.rowT[t], end = a.rowT[t + 1];
+      double acc = 0.0;
+      uint32_t p = beg;
+      for (; p + 3 < end; p += 4) {
+        double m0 = pull_msg<ST, G>(a, p), m1 = pull_msg<ST, G>(a, p + 1);
+        double m2 = pull_msg<ST, G>(a, p + 2), m3 = pull_msg<ST, G>(a, p + 3);
+        acc += (m0 + m1) + (m2 + m3);
       }
-      const uint32_t incl = wave_incl_scan(deg);
-      const uint32_t excl = incl - deg;
-      const uint32_t E = __shfl(incl, 63, 64);
-      s_excl[lane] = excl;
-      s_beg[lane] = beg;
-      for (uint32_t k = 0; k < deg; ++k) owner[excl + k] = (uint8_t)lane;
-      __syncthreads();
-      for (uint32_t e = lane; e < E; e += 64) {
-        const uint32_t o = owner[e];
-        s_val[e] = pull_msg<ST, G>(a, (uint64_t)s_beg[o] + (e - s_excl[o]));
-      }
-      __syncthreads();
-      if (deg) {
-        double acc = 0.0;
-        for (uint32_t k = 0; k < deg; ++k) acc += s_val[excl + k];
-        dv[t] = (S)((double)dv[t] + acc);
-      }
-      __syncthreads();
+      for (; p < end; ++p) acc += pull_msg<ST, G>(a, p);
+      dv[t] = (S)((double)dv[t] + acc);
     }
   }
 }
 
+// Larger targets: one wave per (target, chunk of kChunk in-edges) item. The
+// item records of 16 items are fetched at once (one per lane) and broadcast,
+// and four gathers are in flight per lane.
 template <int ST, int G>
 __global__ __launch_bounds__(64) void k_pull_large(KArgs a) {
   using S = typename Tr<ST>::S;
@@ -797,19 +783,36 @@ __global__ __launch_bounds__(64) void k_pull_large(KArgs a) {
     Ctl* ctl = a.ctl;
     if (ctl_halted(ctl) || !ctl->pull) return;
     S* dv = static_cast<S*>(a.dv);
-    for (uint64_t i = blockIdx.x; i < a.pn_large; i += gridDim.x) {
-      const uint32_t t = a.pt_large[i];
-      const uint32_t c = a.pt_chunk[i];
-      const uint32_t nch = a.pt_nch[i];
-      const uint64_t rb = a.rowT[t], re = a.rowT[t + 1];
-      const uint64_t beg = rb + (uint64_t)c * kChunk;
-      const uint64_t end = min(re, beg + kChunk);
-      double acc = 0.0;
-      for (uint64_t p = beg + threadIdx.x; p < end; p += 64) acc += pull_msg<ST, G>(a, p);
-      acc = wave_sum(acc);
-      if (threadIdx.x == 0) {
-        if (nch == 1) dv[t] = (S)((double)dv[t] + acc);
-        else unsafeAtomicAdd(&dv[t], (S)acc);
+    constexpr uint32_t kGroup = 16;
+    const uint32_t lane = threadIdx.x;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * kGroup; g0 < a.pn_large; g0 += (uint64_t)gridDim.x * kGroup) {
+      uint32_t t = 0, c = 0, nch = 0, rb = 0, re = 0;
+      if (lane < kGroup && g0 + lane < a.pn_large) {
+        t = a.pt_large[g0 + lane];
+        c = a.pt_chunk[g0 + lane];
+        nch = a.pt_nch[g0 + lane];
+        rb = a.rowT[t];
+        re = a.rowT[t + 1];
+      }
+      const uint32_t cnt = (uint32_t)min<uint64_t>(kGroup, a.pn_large - g0);
+      for (uint32_t k = 0; k < cnt; ++k) {
+        const uint32_t tk = __shfl(t, k, 64), ck = __shfl(c, k, 64), nk = __shfl(nch, k, 64);
+        const uint32_t bk = __shfl(rb, k, 64), ek = __shfl(re, k, 64);
+        const uint32_t beg = bk + ck * kChunk;
+        const uint32_t end = min(ek, beg + kChunk);
+        double acc = 0.0;
+        uint32_t p = beg + lane;
+        for (; p + 192 < end; p += 256) {
+          double m0 = pull_msg<ST, G>(a, p), m1 = pull_msg<ST, G>(a, p + 64);
+          double m2 = pull_msg<ST, G>(a, p + 128), m3 = pull_msg<ST, G>(a, p + 192);
+          acc += (m0 + m1) + (m2 + m3);
+        }
+        for (; p < end; p += 64) acc += pull_msg<ST, G>(a, p);
+        acc = wave_sum(acc);
+        if (lane == 0) {
+          if (nk == 1) dv[tk] = (S)((double)dv[tk] + acc);
+          else unsafeAtomicAdd(&dv[tk], (S)acc);
+        }
       }
     }
   }

@@ -219,11 +219,11 @@ struct Impl {
     });
     if (p->pull_ready) {
       launch(pr, "pull_small", s, [&] {
-        uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((a.pn_small + 63) / 64, 16384));
-        hipLaunchKernelGGL((k_pull_small<ST, G>), dim3(gs), dim3(64), 0, s, a);
+        uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((a.pn_small + 255) / 256, 8192));
+        hipLaunchKernelGGL((k_pull_small<ST, G>), dim3(gs), dim3(256), 0, s, a);
       });
       launch(pr, "pull_large", s, [&] {
-        uint32_t gl = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(a.pn_large, 16384));
+        uint32_t gl = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((a.pn_large + 15) / 16, 16384));
         hipLaunchKernelGGL((k_pull_large<ST, G>), dim3(gl), dim3(64), 0, s, a);
       });
     }
