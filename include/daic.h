@@ -175,6 +175,35 @@ const char* daic_last_error(void);
 daic_status daic_select_frontier(daic_problem* p, const daic_run_opts* opts, uint64_t round,
                                  uint8_t* sel_out, double* threshold_out);
 
+/* ---- Batched personalized PageRank --------------------------------------
+ * Many graphs of uneven size, each with up to 64 right-hand sides (the
+ * Rooted PageRank row of Table 1 read with damping: g(x) = alpha x / outdeg_j,
+ * dv1 = (1 - alpha) p for a personalization vector p). All graphs are solved
+ * together: every kernel of a round covers every graph, and K rounds are one
+ * hipGraph launch. Each instance (graph, right-hand side) has its own
+ * residual and stop flag; a run ends when every instance has residual <= eps.
+ * op must be DAIC_SUM with DAIC_G_DEG_SCALE; state DAIC_F32 or F32_KAHAN.
+ * The graphs are copied into one block-diagonal graph; they may be destroyed
+ * after the call.                                                           */
+daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs,
+                              const uint32_t* rhs_per_graph, daic_op op, daic_g gk, double alpha,
+                              daic_dtype state, daic_batch** out);
+/* v0, dv1: host arrays [n_g][rhs_g] (row-major, vertex-major) in double. */
+daic_status daic_batch_set_init(daic_batch* b, uint32_t graph, const double* v0, const double* dv1);
+/* Autotuner: times the dense-round kernels for each lanes-per-vertex and grid
+ * size on the current state (restored afterwards) and keeps the fastest;
+ * with DAIC_TUNE_CACHE set, results are cached in that file. desc receives a
+ * description of the choice (nullable). */
+daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len);
+/* Run every instance to residual <= eps (sched ALL, q = 1). inst_residual
+ * (nullable) receives the final residual of every instance, graph-major.
+ * stats->final_residual is the largest instance residual. */
+daic_status daic_batch_run(daic_batch* b, const daic_run_opts* opts, daic_stats* stats,
+                           double* inst_residual);
+/* v_out: [n_g][rhs_g] doubles (FP32 state; with Kahan, v - c). */
+daic_status daic_batch_get(const daic_batch* b, uint32_t graph, double* v_out);
+void daic_batch_destroy(daic_batch* b);
+
 /* daic_profile runs like daic_run but launches every kernel on its own,
  * bracketed by HIP events on the run's stream, one round at a time, and
  * reports per kernel class: launches, summed duration and the algorithmic

@@ -93,6 +93,15 @@ def lib():
         L.daic_profile.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint32,
                                    ctypes.POINTER(KernelTime), ctypes.POINTER(ctypes.c_uint32),
                                    ctypes.POINTER(Stats)]
+        L.daic_batch_create.argtypes = [ctypes.c_uint32, ctypes.POINTER(_vp), _vp, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                        ctypes.POINTER(_vp)]
+        L.daic_batch_set_init.argtypes = [_vp, ctypes.c_uint32, _vp, _vp]
+        L.daic_batch_tune.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
+        L.daic_batch_run.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.POINTER(Stats), _vp]
+        L.daic_batch_get.argtypes = [_vp, ctypes.c_uint32, _vp]
+        L.daic_batch_destroy.argtypes = [_vp]
+        L.daic_batch_destroy.restype = None
         L.daic_select_frontier.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint64, _vp,
                                            ctypes.POINTER(ctypes.c_double)]
         _lib = L
@@ -277,6 +286,62 @@ class Problem:
     def close(self):
         if getattr(self, "_h", None) is not None:
             lib().daic_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many graphs x many right-hand sides of personalized PageRank solved
+    together (daic_batch). rhs: one count (<= 64) or one per graph."""
+
+    def __init__(self, graphs, rhs, alpha: float, state="f32"):
+        self.graphs = list(graphs)
+        G = len(self.graphs)
+        self.rhs = [int(rhs)] * G if np.isscalar(rhs) else [int(r) for r in rhs]
+        self.n = [g.n for g in self.graphs]
+        handles = (_vp * G)(*[g.handle for g in self.graphs])
+        r = np.ascontiguousarray(self.rhs, dtype=np.uint32)
+        st = _STATE_NAMES[state] if isinstance(state, str) else state
+        h = _vp()
+        check(lib().daic_batch_create(G, handles, _addr(r), SUM, G_DEG_SCALE, float(alpha), st,
+                                      ctypes.byref(h)), "daic_batch_create")
+        self._h = h
+
+    def set_init(self, g: int, v0, dv1):
+        v0 = np.ascontiguousarray(v0, dtype=np.float64)
+        dv1 = np.ascontiguousarray(dv1, dtype=np.float64)
+        shape = (self.n[g], self.rhs[g])
+        if v0.shape != shape or dv1.shape != shape:
+            raise ValueError(f"expected arrays of shape {shape}")
+        check(lib().daic_batch_set_init(self._h, g, _addr(v0), _addr(dv1)), "daic_batch_set_init")
+
+    def tune(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        check(lib().daic_batch_tune(self._h, buf, 256), "daic_batch_tune")
+        return buf.value.decode()
+
+    def run(self, eps=1e-6, rounds_per_check=8, max_rounds=0, stream=None):
+        o = Problem.make_opts(eps=eps, q=1.0, sched="all", rounds_per_check=rounds_per_check,
+                              max_rounds=max_rounds, stream=stream)
+        st = Stats()
+        inst = np.zeros(sum(self.rhs), dtype=np.float64)
+        rc = check(lib().daic_batch_run(self._h, ctypes.byref(o), ctypes.byref(st), _addr(inst)),
+                   "daic_batch_run")
+        return RunResult(rc, st.as_dict()), inst
+
+    def get(self, g: int):
+        out = np.empty((self.n[g], self.rhs[g]), dtype=np.float64)
+        check(lib().daic_batch_get(self._h, g, _addr(out)), "daic_batch_get")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().daic_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):
