@@ -204,6 +204,31 @@ daic_status daic_batch_run(daic_batch* b, const daic_run_opts* opts, daic_stats*
 daic_status daic_batch_get(const daic_batch* b, uint32_t graph, double* v_out);
 void daic_batch_destroy(daic_batch* b);
 
+/* ---- Learned scheduler ----------------------------------------------------
+ * A 3 -> 64 -> 64 -> 1 network (ReLU, logit output) scoring pending vertices
+ * from the features [log2(priority), log2((1 + indeg) / (1 + outdeg)),
+ * min(rounds since the last update, 64) / 64], standardized by the model's
+ * feature mean and scale. Under DAIC_SCHED_LEARNED a round takes the top
+ * ceil(q n) vertices by priority x sigmoid(score); the exact top-k round is its
+ * fallback and the residual remains the stop rule. Not part of the paper: an
+ * addition that changes the update order only, which Theorems 1 and 3 allow.
+ * Parameters: 4481 FP32 values, [W1 (64x3), b1 (64), W2 (64x64), b2 (64),
+ * W3 (1x64), b3 (1)], row-major (output, input). The device keeps FP32
+ * master weights and BF16 copies for the MFMA kernels.                     */
+daic_status daic_sched_model_create(const float* params /* nullable: seeded init */, uint64_t seed,
+                                    daic_sched_model** out);
+daic_status daic_sched_model_get(const daic_sched_model* m, float* params /* 4481 */,
+                                 float* feat_mean /* 3, nullable */, float* feat_std /* 3, nullable */);
+daic_status daic_sched_model_set_features(daic_sched_model* m, const float* feat_mean,
+                                          const float* feat_std);
+void daic_sched_destroy(daic_sched_model* m);
+/* Forward (logits) and gradient of the mean BCE-with-logits loss on host
+ * inputs x [N][3] (already standardized) and labels y [N] in {0, 1}, on the
+ * BF16 MFMA kernels: for checking against a reference. grad: 4481 floats. */
+daic_status daic_mlp_forward(const daic_sched_model* m, const float* x, uint64_t N, float* logits);
+daic_status daic_mlp_grad(const daic_sched_model* m, const float* x, const float* y, uint64_t N,
+                          float* grad, double* loss /* nullable */);
+
 /* daic_profile runs like daic_run but launches every kernel on its own,
  * bracketed by HIP events on the run's stream, one round at a time, and
  * reports per kernel class: launches, summed duration and the algorithmic

@@ -327,7 +327,7 @@ __global__ __launch_bounds__(1024) void k_sample(KArgs a, uint32_t S_n, uint32_t
 }
 
 // Selection of every pending vertex (DAIC_SCHED_ALL).
-__global__ void k_select_all(Ctl* ctl) {
+static __global__ void k_select_all(Ctl* ctl) {
   ctl->sel_mode = 0;
   ctl->tau = 0;
 }
@@ -336,7 +336,7 @@ __global__ void k_select_all(Ctl* ctl) {
 // A2 (exact): radix select of the k-th largest key, 8 bits per pass, most
 // significant digit first. Ties at the k-th key go to the smaller ids.
 // ---------------------------------------------------------------------------
-__global__ void k_topk_init(Ctl* ctl, uint64_t k) {
+static __global__ void k_topk_init(Ctl* ctl, uint64_t k) {
   if (ctl_halted(ctl)) return;
   if (ctl->pending <= k) {
     ctl->sel_mode = 0;
@@ -448,7 +448,7 @@ __device__ __forceinline__ void excl_prefix_1024(const uint32_t* in, uint64_t* o
   }
 }
 
-__global__ __launch_bounds__(1024) void k_tie_scan(KArgs a) {
+static __global__ __launch_bounds__(1024) void k_tie_scan(KArgs a) {
   if (ctl_halted(a.ctl) || a.ctl->sel_mode != 2) return;
   excl_prefix_1024(a.blk_ties, a.off_ties, a.blocks, nullptr);
 }
@@ -562,7 +562,7 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
 }
 
 // Prefix of the bin counts and the round's work counters (one block).
-__global__ __launch_bounds__(1024) void k_bin_scan(KArgs a) {
+static __global__ __launch_bounds__(1024) void k_bin_scan(KArgs a) {
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
   if (threadIdx.x == 0) ctl->last_pull = ctl->pull;

@@ -102,6 +102,14 @@ def lib():
         L.daic_batch_get.argtypes = [_vp, ctypes.c_uint32, _vp]
         L.daic_batch_destroy.argtypes = [_vp]
         L.daic_batch_destroy.restype = None
+        L.daic_sched_model_create.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]
+        L.daic_sched_model_get.argtypes = [_vp, _vp, _vp, _vp]
+        L.daic_sched_model_set_features.argtypes = [_vp, _vp, _vp]
+        L.daic_sched_destroy.argtypes = [_vp]
+        L.daic_sched_destroy.restype = None
+        L.daic_mlp_forward.argtypes = [_vp, _vp, ctypes.c_uint64, _vp]
+        L.daic_mlp_grad.argtypes = [_vp, _vp, _vp, ctypes.c_uint64, _vp,
+                                    ctypes.POINTER(ctypes.c_double)]
         L.daic_select_frontier.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint64, _vp,
                                            ctypes.POINTER(ctypes.c_double)]
         _lib = L
@@ -342,6 +350,83 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None:
             lib().daic_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+N_PARAMS = 4481
+_PARAM_SHAPES = [("W1", (64, 3)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (1, 64)),
+                 ("b3", (1,))]
+
+
+def pack_params(p: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(p[k], dtype=np.float32).reshape(-1) for k, _ in _PARAM_SHAPES])
+
+
+def unpack_params(flat) -> dict:
+    out, o = {}, 0
+    for k, shp in _PARAM_SHAPES:
+        c = int(np.prod(shp))
+        out[k] = np.asarray(flat[o:o + c]).reshape(shp)
+        o += c
+    return out
+
+
+class SchedModel:
+    """The learned scheduler's network (daic_sched_model)."""
+
+    def __init__(self, params=None, seed=0, *, _handle=None):
+        if _handle is not None:
+            self._h = _handle
+            return
+        flat = None if params is None else np.ascontiguousarray(
+            pack_params(params) if isinstance(params, dict) else params, dtype=np.float32)
+        h = _vp()
+        check(lib().daic_sched_model_create(_addr(flat), seed, ctypes.byref(h)),
+              "daic_sched_model_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self):
+        flat = np.empty(N_PARAMS, dtype=np.float32)
+        mean = np.empty(3, dtype=np.float32)
+        std = np.empty(3, dtype=np.float32)
+        check(lib().daic_sched_model_get(self._h, _addr(flat), _addr(mean), _addr(std)),
+              "daic_sched_model_get")
+        return unpack_params(flat), mean, std
+
+    def set_features(self, mean, std):
+        mean = np.ascontiguousarray(mean, dtype=np.float32)
+        std = np.ascontiguousarray(std, dtype=np.float32)
+        check(lib().daic_sched_model_set_features(self._h, _addr(mean), _addr(std)),
+              "daic_sched_model_set_features")
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        out = np.empty(x.shape[0], dtype=np.float32)
+        check(lib().daic_mlp_forward(self._h, _addr(x), x.shape[0], _addr(out)), "daic_mlp_forward")
+        return out
+
+    def grad(self, x, y):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        g = np.empty(N_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double(0)
+        check(lib().daic_mlp_grad(self._h, _addr(x), _addr(y), x.shape[0], _addr(g),
+                                  ctypes.byref(loss)), "daic_mlp_grad")
+        return unpack_params(g), loss.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().daic_sched_destroy(self._h)
             self._h = None
 
     def __del__(self):
