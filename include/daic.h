@@ -229,6 +229,40 @@ daic_status daic_mlp_forward(const daic_sched_model* m, const float* x, uint64_t
 daic_status daic_mlp_grad(const daic_sched_model* m, const float* x, const float* y, uint64_t N,
                           float* grad, double* loss /* nullable */);
 
+/* Trace capture: runs exact top-k rounds (opts->sched = TOPK_EXACT) from the
+ * problem's current state to its stop rule (or max_rounds, at most 4096),
+ * sampling samples_per_round vertices per round with SplitMix64. A sampled
+ * vertex updated in round t becomes one training sample: its features at t
+ * and label 1, or 0 when the update was premature: within the next horizon
+ * rounds its priority reached half its priority at t (sum problems) or it
+ * became pending again (min/max problems). The problem ends converged.     */
+daic_status daic_trace_record(daic_problem* p, const daic_run_opts* opts, uint32_t samples_per_round,
+                              uint32_t horizon, daic_trace** out);
+/* Copies the samples out: x [n][3] raw features, y [n]; *n = sample count.
+ * x and y may be NULL to query n. */
+daic_status daic_trace_get(const daic_trace* tr, float* x, float* y, uint64_t* n);
+void daic_trace_destroy(daic_trace* tr);
+
+typedef struct {
+  uint32_t epochs;   /* passes over the samples (0 = 10)      */
+  uint32_t batch;    /* minibatch size (0 = 65536)            */
+  float lr;          /* Adam step size (0 = 1e-3)             */
+  uint64_t seed;     /* shuffle seed                          */
+} daic_train_opts;
+typedef struct {
+  uint64_t samples;
+  double positive_fraction;
+  double loss_first;  /* mean loss before training  */
+  double loss_final;  /* mean loss after training   */
+  double time_ms;     /* device time of the epochs  */
+  uint32_t epochs;
+} daic_train_stats;
+/* Trains m on the union of the traces on the device (BF16 MFMA gradients,
+ * FP32 Adam); sets the model's feature standardization from the samples. */
+daic_status daic_sched_train(const daic_trace* const* traces, uint32_t n_traces,
+                             const daic_train_opts* opts, daic_sched_model* m,
+                             daic_train_stats* stats);
+
 /* daic_profile runs like daic_run but launches every kernel on its own,
  * bracketed by HIP events on the run's stream, one round at a time, and
  * reports per kernel class: launches, summed duration and the algorithmic

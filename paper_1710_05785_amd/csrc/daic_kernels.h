@@ -60,6 +60,7 @@ struct KArgs {
   uint64_t* part_n;         // pending-count partials per block
   uint8_t* sel_out;         // dry selection output [n]
   const float* score;       // learned scheduler: multiplier in (0,1) per vertex, or null
+  uint32_t* last_upd;       // learned scheduler: round of each vertex's last update, or null
   // dense rounds (pull over in-edges)
   const uint32_t* perm;     // renumbering of sources by out-degree
   const uint32_t* rowT;     // in-edge offsets [n+1]
@@ -326,6 +327,28 @@ __global__ __launch_bounds__(1024) void k_sample(KArgs a, uint32_t S_n, uint32_t
   }
 }
 
+// Resets the control block at the start of a run.
+static __global__ void k_init_ctl(Ctl* ctl, double eps, uint64_t max_rounds) {
+  ctl->eps = eps;
+  ctl->rounds = 0;
+  ctl->max_rounds = max_rounds;
+  ctl->activations = 0;
+  ctl->pushed = 0;
+  ctl->pushed_large = 0;
+  ctl->round_act = 0;
+  ctl->round_pushed = 0;
+  ctl->round_pushed_large = 0;
+  ctl->done = 0;
+  ctl->stop = 0;
+  ctl->ticket = 0;
+  ctl->sel_mode = 0;
+  ctl->tau = 0;
+  ctl->radix_skip = 1;
+  ctl->pull = 0;
+  ctl->last_pull = 0;
+  for (int i = 0; i < 256; ++i) ctl->hist[i] = 0;
+}
+
 // Selection of every pending vertex (DAIC_SCHED_ALL).
 static __global__ void k_select_all(Ctl* ctl) {
   ctl->sel_mode = 0;
@@ -512,6 +535,7 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
       beg = row_at<RowT>(a.row, j);
       deg = row_at<RowT>(a.row, j + 1) - beg;
       send = claim_fold<ST, G>(a, j, deg, vj, dj, mu) && deg > 0;
+      if (a.last_upd) a.last_upd[j] = (uint32_t)ctl->rounds;
     }
     if (pull) {  // dense round: every vertex publishes its message base (0 if silent)
       if constexpr (Tr<ST>::sum) {

@@ -1,0 +1,109 @@
+// The problem object and the per-instantiation enqueue table, shared by the
+// runtime and the learned scheduler.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "daic_internal.h"
+#include "daic_kernels.h"
+
+// ---------------------------------------------------------------------------
+// Problem object.
+// ---------------------------------------------------------------------------
+struct GraphCacheKey {
+  int sched = -1;
+  uint64_t k = 0;
+  uint32_t S = 0;
+  double q = 0.0;
+  uint64_t seed = 0;
+  uint32_t K = 0;
+  const void* stream = nullptr;
+  const float* score = nullptr;
+  uint64_t k_sel = 0, pull_min = 0;
+  bool operator==(const GraphCacheKey& o) const {
+    return sched == o.sched && k == o.k && S == o.S && q == o.q && seed == o.seed && K == o.K &&
+           stream == o.stream && score == o.score && k_sel == o.k_sel && pull_min == o.pull_min;
+  }
+};
+
+struct daic_problem {
+  const daic_graph* g = nullptr;
+  daic_op op = DAIC_SUM;
+  daic_g gk = DAIC_G_SRC_SCALE;
+  daic_dtype state = DAIC_F64;
+  int st = daic::ST_F64;
+  double alpha = 0.0;
+  daic::KArgs a{};
+  void* alpha_pv = nullptr;
+  void* w_conv = nullptr;
+  daic::Ctl* h_ctl = nullptr;   // pinned mirror
+  hipStream_t own_stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  GraphCacheKey key;
+  std::vector<void*> allocs;
+  bool pull_ready = false;
+  uint64_t k_sel = 0;      // dense-round rule of the current run (see k_residual)
+  uint64_t pull_min = 0;
+  // learned scheduler state (allocated on first use)
+  bool learned_ready = false;
+  uint32_t* last_upd = nullptr;  // round of the last update of each vertex
+  uint32_t* indeg = nullptr;     // in-degree of each vertex
+  float* score = nullptr;        // selection multiplier of each vertex
+  uint64_t learned_fallbacks = 0;  // learned rounds that handed back to exact selection
+};
+
+namespace daic {
+
+// Per-kernel timing with HIP events recorded on the launch stream.
+struct Prof {
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t ev() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      (void)hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~Prof() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+template <class F>
+static void launch(Prof* pr, const char* name, hipStream_t s, F&& f) {
+  if (!pr) {
+    f();
+    return;
+  }
+  hipEvent_t a = pr->ev(), b = pr->ev();
+  (void)hipEventRecord(a, s);
+  f();
+  (void)hipEventRecord(b, s);
+  pr->recs.push_back({name, a, b});
+}
+
+// Enqueue functions per instantiation.
+struct Ops {
+  void (*residual)(daic_problem*, hipStream_t, int);
+  void (*round)(daic_problem*, const daic_run_opts*, hipStream_t, const float* score, Prof* pr);
+  void (*select)(daic_problem*, const daic_run_opts*, hipStream_t, uint64_t round_override);
+};
+
+// The enqueue table of a problem's (state, g, row width) instantiation.
+bool get_ops(const daic_problem* p, Ops* out);
+// Validation of run options, and the dense-round set-up of a run.
+daic_status check_opts(const daic_problem* p, const daic_run_opts* o);
+daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStream_t s);
+
+}  // namespace daic

@@ -14,6 +14,7 @@
 
 #include "daic_internal.h"
 #include "daic_kernels.h"
+#include "daic_problem.h"
 
 namespace daic {
 
@@ -78,90 +79,7 @@ static void dfree(void* p) {
 
 using namespace daic;
 
-// ---------------------------------------------------------------------------
-// Problem object.
-// ---------------------------------------------------------------------------
-struct GraphCacheKey {
-  int sched = -1;
-  uint64_t k = 0;
-  uint32_t S = 0;
-  double q = 0.0;
-  uint64_t seed = 0;
-  uint32_t K = 0;
-  const void* stream = nullptr;
-  const float* score = nullptr;
-  uint64_t k_sel = 0, pull_min = 0;
-  bool operator==(const GraphCacheKey& o) const {
-    return sched == o.sched && k == o.k && S == o.S && q == o.q && seed == o.seed && K == o.K &&
-           stream == o.stream && score == o.score && k_sel == o.k_sel && pull_min == o.pull_min;
-  }
-};
-
-struct daic_problem {
-  const daic_graph* g = nullptr;
-  daic_op op = DAIC_SUM;
-  daic_g gk = DAIC_G_SRC_SCALE;
-  daic_dtype state = DAIC_F64;
-  int st = ST_F64;
-  double alpha = 0.0;
-  KArgs a{};
-  void* alpha_pv = nullptr;
-  void* w_conv = nullptr;
-  Ctl* h_ctl = nullptr;   // pinned mirror
-  hipStream_t own_stream = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
-  GraphCacheKey key;
-  std::vector<void*> allocs;
-  bool pull_ready = false;
-  uint64_t k_sel = 0;      // dense-round rule of the current run (see k_residual)
-  uint64_t pull_min = 0;
-};
-
 namespace daic {
-
-// Per-kernel timing with HIP events recorded on the launch stream.
-struct Prof {
-  struct Rec {
-    const char* name;
-    hipEvent_t a, b;
-  };
-  std::vector<Rec> recs;
-  std::vector<hipEvent_t> pool;
-  size_t used = 0;
-  hipEvent_t ev() {
-    if (used == pool.size()) {
-      hipEvent_t e = nullptr;
-      (void)hipEventCreate(&e);
-      pool.push_back(e);
-    }
-    return pool[used++];
-  }
-  ~Prof() {
-    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-  }
-};
-
-template <class F>
-static void launch(Prof* pr, const char* name, hipStream_t s, F&& f) {
-  if (!pr) {
-    f();
-    return;
-  }
-  hipEvent_t a = pr->ev(), b = pr->ev();
-  (void)hipEventRecord(a, s);
-  f();
-  (void)hipEventRecord(b, s);
-  pr->recs.push_back({name, a, b});
-}
-
-// Enqueue functions per instantiation.
-struct Ops {
-  void (*residual)(daic_problem*, hipStream_t, int);
-  void (*round)(daic_problem*, const daic_run_opts*, hipStream_t, const float* score, Prof* pr);
-  void (*select)(daic_problem*, const daic_run_opts*, hipStream_t, uint64_t round_override);
-};
 
 static uint32_t push_grid() { return 256 * 16; }
 
@@ -248,7 +166,7 @@ static bool pick_row(const daic_problem* p, Ops* out) {
   return true;
 }
 
-static bool get_ops(const daic_problem* p, Ops* out) {
+bool get_ops(const daic_problem* p, Ops* out) {
   switch (p->st) {
     case ST_F64:
       if (p->gk == DAIC_G_SRC_SCALE) return pick_row<ST_F64, DAIC_G_SRC_SCALE>(p, out);
@@ -276,27 +194,6 @@ static bool get_ops(const daic_problem* p, Ops* out) {
 }
 
 // Set-up kernels that are not per instantiation.
-__global__ void k_init_ctl(Ctl* ctl, double eps, uint64_t max_rounds) {
-  ctl->eps = eps;
-  ctl->rounds = 0;
-  ctl->max_rounds = max_rounds;
-  ctl->activations = 0;
-  ctl->pushed = 0;
-  ctl->pushed_large = 0;
-  ctl->round_act = 0;
-  ctl->round_pushed = 0;
-  ctl->round_pushed_large = 0;
-  ctl->done = 0;
-  ctl->stop = 0;
-  ctl->ticket = 0;
-  ctl->sel_mode = 0;
-  ctl->tau = 0;
-  ctl->radix_skip = 1;
-  ctl->pull = 0;
-  ctl->last_pull = 0;
-  for (int i = 0; i < 256; ++i) ctl->hist[i] = 0;
-}
-
 __global__ void k_clear_done(Ctl* ctl) {
   ctl->done = 0;
   ctl->stop = 0;
@@ -374,6 +271,77 @@ static daic_status graph_finish(daic_graph* g, hipStream_t s) {
   if (st) return st;
   DAIC_HIP(hipMemcpyAsync(g->large_off, cap.data(), (nb + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
   DAIC_HIP(hipStreamSynchronize(s));
+  return DAIC_OK;
+}
+
+daic_status check_opts(const daic_problem* p, const daic_run_opts* o) {
+  if (!o) return fail(DAIC_E_INVALID, "opts is null");
+  if (!(o->priority_fraction > 0.0 && o->priority_fraction <= 1.0))
+    return fail(DAIC_E_INVALID, "priority_fraction must be in (0, 1]");
+  if (!(o->eps >= 0.0)) return fail(DAIC_E_INVALID, "eps must be >= 0");
+  if (o->sched < DAIC_SCHED_ALL || o->sched > DAIC_SCHED_LEARNED) return fail(DAIC_E_INVALID, "unknown sched");
+  if (o->sched == DAIC_SCHED_TOPK_SAMPLED && o->n_samples > kMaxSamples)
+    return fail(DAIC_E_INVALID, "n_samples must be <= %u", kMaxSamples);
+  if (o->sched == DAIC_SCHED_LEARNED && !o->model) return fail(DAIC_E_INVALID, "LEARNED needs a model");
+  (void)p;
+  return DAIC_OK;
+}
+
+// Dense rounds (pull over in-edges) for sum problems: builds the in-edge form
+// on first use and sets the direction rule of this run. DAIC_NO_PULL=1 turns
+// them off; DAIC_PULL_DIV (default 32) sets the fraction n/div of updating
+// vertices from which a round runs dense.
+daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStream_t s) {
+  p->k_sel = 0;
+  p->pull_min = 0;
+  const bool sum = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
+  const GraphDev& d = p->g->dev;
+  if (!sum || std::getenv("DAIC_NO_PULL") || !d.row32 || d.m > 0x7FFFFFFFull || d.n > 0x7FFFFFFFull)
+    return DAIC_OK;
+  if (!p->pull_ready) {
+    daic_graph* g = const_cast<daic_graph*>(p->g);
+    daic_status rc = pull_prepare(g, s);
+    if (rc) return rc;
+    const size_t S = state_size(p->st);
+    void* mu = nullptr;
+    DAIC_HIP(hipMalloc(&mu, std::max<uint64_t>(d.n, 1) * S));
+    p->allocs.push_back(mu);
+    DAIC_HIP(hipMemsetAsync(mu, 0, d.n * S, s));
+    KArgs& a = p->a;
+    a.mu_pi = mu;
+    if (p->gk == DAIC_G_EDGE_SCALE) {
+      void* wt = nullptr;
+      DAIC_HIP(hipMalloc(&wt, std::max<uint64_t>(d.m, 1) * S));
+      p->allocs.push_back(wt);
+      if (p->st == ST_F64)
+        hipLaunchKernelGGL(k_gather_weights<double>, dim3(grid_for(d.m)), dim3(256), 0, s,
+                           static_cast<const double*>(a.w), g->pull.eidT, d.m, static_cast<double*>(wt));
+      else
+        hipLaunchKernelGGL(k_gather_weights<float>, dim3(grid_for(d.m)), dim3(256), 0, s,
+                           static_cast<const float*>(a.w), g->pull.eidT, d.m, static_cast<float*>(wt));
+      a.wT = wt;
+    }
+    a.perm = g->pull.perm;
+    a.rowT = static_cast<const uint32_t*>(g->pull.rowT);
+    a.srcT = g->pull.srcT;
+    a.pt_small = g->pull.small_tgt;
+    a.pn_small = g->pull.n_small;
+    a.pt_large = g->pull.large_tgt;
+    a.pt_chunk = g->pull.large_chunk;
+    a.pt_nch = g->pull.large_nch;
+    a.pn_large = g->pull.n_large;
+    DAIC_HIP(hipStreamSynchronize(s));
+    p->pull_ready = true;
+    if (p->exec) {  // captured rounds predate the dense-round kernels
+      (void)hipGraphExecDestroy(p->exec);
+      p->exec = nullptr;
+    }
+  }
+  uint64_t div = 32;
+  if (const char* e = std::getenv("DAIC_PULL_DIV")) div = std::max<uint64_t>(1, std::strtoull(e, nullptr, 10));
+  const uint64_t n = d.n;
+  p->k_sel = o->sched == DAIC_SCHED_ALL ? n : std::max<uint64_t>(1, (uint64_t)std::ceil(o->priority_fraction * (double)n));
+  p->pull_min = std::max<uint64_t>(1, (n + div - 1) / div);
   return DAIC_OK;
 }
 
@@ -661,77 +629,6 @@ daic_status daic_problem_set_init(daic_problem* p, const void* v0, const void* d
   return DAIC_OK;
 }
 
-static daic_status check_opts(const daic_problem* p, const daic_run_opts* o) {
-  if (!o) return fail(DAIC_E_INVALID, "opts is null");
-  if (!(o->priority_fraction > 0.0 && o->priority_fraction <= 1.0))
-    return fail(DAIC_E_INVALID, "priority_fraction must be in (0, 1]");
-  if (!(o->eps >= 0.0)) return fail(DAIC_E_INVALID, "eps must be >= 0");
-  if (o->sched < DAIC_SCHED_ALL || o->sched > DAIC_SCHED_LEARNED) return fail(DAIC_E_INVALID, "unknown sched");
-  if (o->sched == DAIC_SCHED_TOPK_SAMPLED && o->n_samples > kMaxSamples)
-    return fail(DAIC_E_INVALID, "n_samples must be <= %u", kMaxSamples);
-  if (o->sched == DAIC_SCHED_LEARNED && !o->model) return fail(DAIC_E_INVALID, "LEARNED needs a model");
-  (void)p;
-  return DAIC_OK;
-}
-
-// Dense rounds (pull over in-edges) for sum problems: builds the in-edge form
-// on first use and sets the direction rule of this run. DAIC_NO_PULL=1 turns
-// them off; DAIC_PULL_DIV (default 32) sets the fraction n/div of updating
-// vertices from which a round runs dense.
-static daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStream_t s) {
-  p->k_sel = 0;
-  p->pull_min = 0;
-  const bool sum = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
-  const GraphDev& d = p->g->dev;
-  if (!sum || std::getenv("DAIC_NO_PULL") || !d.row32 || d.m > 0x7FFFFFFFull || d.n > 0x7FFFFFFFull)
-    return DAIC_OK;
-  if (!p->pull_ready) {
-    daic_graph* g = const_cast<daic_graph*>(p->g);
-    daic_status rc = pull_prepare(g, s);
-    if (rc) return rc;
-    const size_t S = state_size(p->st);
-    void* mu = nullptr;
-    DAIC_HIP(hipMalloc(&mu, std::max<uint64_t>(d.n, 1) * S));
-    p->allocs.push_back(mu);
-    DAIC_HIP(hipMemsetAsync(mu, 0, d.n * S, s));
-    KArgs& a = p->a;
-    a.mu_pi = mu;
-    if (p->gk == DAIC_G_EDGE_SCALE) {
-      void* wt = nullptr;
-      DAIC_HIP(hipMalloc(&wt, std::max<uint64_t>(d.m, 1) * S));
-      p->allocs.push_back(wt);
-      if (p->st == ST_F64)
-        hipLaunchKernelGGL(k_gather_weights<double>, dim3(grid_for(d.m)), dim3(256), 0, s,
-                           static_cast<const double*>(a.w), g->pull.eidT, d.m, static_cast<double*>(wt));
-      else
-        hipLaunchKernelGGL(k_gather_weights<float>, dim3(grid_for(d.m)), dim3(256), 0, s,
-                           static_cast<const float*>(a.w), g->pull.eidT, d.m, static_cast<float*>(wt));
-      a.wT = wt;
-    }
-    a.perm = g->pull.perm;
-    a.rowT = static_cast<const uint32_t*>(g->pull.rowT);
-    a.srcT = g->pull.srcT;
-    a.pt_small = g->pull.small_tgt;
-    a.pn_small = g->pull.n_small;
-    a.pt_large = g->pull.large_tgt;
-    a.pt_chunk = g->pull.large_chunk;
-    a.pt_nch = g->pull.large_nch;
-    a.pn_large = g->pull.n_large;
-    DAIC_HIP(hipStreamSynchronize(s));
-    p->pull_ready = true;
-    if (p->exec) {  // captured rounds predate the dense-round kernels
-      (void)hipGraphExecDestroy(p->exec);
-      p->exec = nullptr;
-    }
-  }
-  uint64_t div = 32;
-  if (const char* e = std::getenv("DAIC_PULL_DIV")) div = std::max<uint64_t>(1, std::strtoull(e, nullptr, 10));
-  const uint64_t n = d.n;
-  p->k_sel = o->sched == DAIC_SCHED_ALL ? n : std::max<uint64_t>(1, (uint64_t)std::ceil(o->priority_fraction * (double)n));
-  p->pull_min = std::max<uint64_t>(1, (n + div - 1) / div);
-  return DAIC_OK;
-}
-
 static double per_edge_bytes(const daic_problem* p) {
   const double S = (double)state_size(p->st);
   double b = 4.0 + 2.0 * S;  // col + RMW of dv_k
@@ -761,10 +658,10 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
   if (!get_ops(p, &ops)) return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");
   const uint32_t K = o->rounds_per_check ? o->rounds_per_check : 1;
   const uint64_t max_rounds = o->max_rounds ? o->max_rounds : ~0ull;
-  const float* score = nullptr;
   if (o->sched == DAIC_SCHED_LEARNED) {
     rc = learned_prepare(p, o->model, s);
     if (rc) return rc;
+    p->learned_fallbacks = 0;
   }
 
   rc = dense_rounds_setup(p, o, s);
@@ -795,15 +692,48 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
     DAIC_HIP(hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0));
     p->key = key;
   }
-  for (;;) {
-    if (o->sched == DAIC_SCHED_LEARNED) {
-      for (uint32_t r = 0; r < K; ++r) {
-        rc = learned_scores(p, o->model, s, &score);
+  if (o->sched == DAIC_SCHED_LEARNED) {
+    // Rounds ranked by priority x sigmoid(score). Exact top-k is the fallback:
+    // one exact round calibrates the residual drop per pushed edge, and a
+    // learned round that does worse than 0.8 x that figure hands the next
+    // kFallback rounds back to exact selection; every kWindow learned rounds
+    // are followed by a fresh calibration round. (Sum problems; min/max
+    // problems have no residual mass to compare and always use the network.)
+    constexpr uint32_t kFallback = 4, kWindow = 16;
+    const bool sum = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
+    uint32_t exact_left = sum ? 1 : 0, learned_run = 0;
+    double exact_eff = 0.0;
+    DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DAIC_HIP(hipStreamSynchronize(s));
+    while (!p->h_ctl->done && !p->h_ctl->stop) {
+      const double r0 = p->h_ctl->r;
+      const bool learned = exact_left == 0;
+      const float* sc = nullptr;
+      if (learned) {
+        rc = learned_scores(p, o->model, s, &sc);
         if (rc) return rc;
-        ops.round(p, o, s, score, nullptr);
-        learned_after_round(p, s);
       }
-    } else if (use_graph) {
+      ops.round(p, o, s, sc, nullptr);
+      DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+      DAIC_HIP(hipStreamSynchronize(s));
+      if (!sum) continue;
+      const double drop = (r0 - p->h_ctl->r) / std::max(r0, 1e-300);
+      const double eff = drop / std::max(1.0, (double)p->h_ctl->round_pushed);
+      if (!learned) {
+        exact_eff = eff;
+        --exact_left;
+        learned_run = 0;
+      } else if (eff < 0.8 * exact_eff) {
+        exact_left = kFallback;
+        ++p->learned_fallbacks;
+      } else if (++learned_run >= kWindow) {
+        exact_left = 1;
+      }
+    }
+  }
+  p->a.last_upd = nullptr;  // captured plain rounds do not track updates
+  for (; o->sched != DAIC_SCHED_LEARNED;) {
+    if (use_graph) {
       DAIC_HIP(hipGraphLaunch(p->exec, s));
     } else {
       for (uint32_t r = 0; r < K; ++r) ops.round(p, o, s, nullptr, nullptr);

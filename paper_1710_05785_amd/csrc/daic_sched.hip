@@ -22,6 +22,7 @@
 #include "daic_device.h"
 #include "daic_internal.h"
 #include "daic_kernels.h"
+#include "daic_problem.h"
 
 namespace daic {
 
@@ -551,14 +552,433 @@ daic_status daic_mlp_grad(const daic_sched_model* m, const float* x, const float
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Placeholder hooks of the round loop (replaced once inference is in place).
+// Inference on the problem state, trace capture and training.
 // ---------------------------------------------------------------------------
 namespace daic {
-daic_status learned_prepare(daic_problem*, const daic_sched_model*, hipStream_t) {
-  return fail(DAIC_E_UNSUPPORTED, "learned scheduler not available");
+
+struct FeatNorm {
+  float mean[3];
+  float inv_std[3];
+};
+
+__global__ void k_indeg(const uint32_t* col, uint64_t m, uint32_t* indeg) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < m; i += st) atomicAdd(&indeg[col[i]], 1u);
 }
-daic_status learned_scores(daic_problem*, const daic_sched_model*, hipStream_t, const float**) {
-  return fail(DAIC_E_UNSUPPORTED, "learned scheduler not available");
+
+// Raw features of vertex j: [log2 priority, log2((1 + indeg) / (1 + outdeg)),
+// min(rounds since the last update, 64) / 64]; false when j is not pending.
+template <int ST, typename RowT>
+__device__ __forceinline__ bool vertex_features(const KArgs& a, const uint32_t* indeg, const uint32_t* last_upd,
+                                                uint32_t round, uint64_t j, float (&f)[3], float& pr,
+                                                uint32_t& since) {
+  using S = typename Tr<ST>::S;
+  const S v = static_cast<const S*>(a.v)[j];
+  const S dv = static_cast<const S*>(a.dv)[j];
+  const auto k = prio_key<ST>(v, dv);
+  if (k == 0) return false;
+  float p;
+  if constexpr (Tr<ST>::sum) p = (float)fabs((double)dv);
+  else p = (float)k;
+  const uint64_t od = row_at<RowT>(a.row, j + 1) - row_at<RowT>(a.row, j);
+  since = round - last_upd[j];
+  f[0] = log2f(p + 1e-30f);
+  f[1] = log2f((1.0f + (float)indeg[j]) / (1.0f + (float)od));
+  f[2] = (float)min(since, 64u) * (1.0f / 64.0f);
+  pr = p;
+  return true;
 }
+
+// Selection multiplier of every vertex: sigmoid(network score) for pending
+// vertices, a very large value for pending vertices not updated for 64 rounds
+// (no vertex is starved), 0 otherwise. One wavefront per 16 vertices.
+template <int ST, typename RowT>
+__global__ __launch_bounds__(256) void k_score(KArgs a, MlpDev m, FeatNorm fn, const uint32_t* indeg,
+                                               const uint32_t* last_upd, float* score) {
+  if (ctl_halted(a.ctl)) return;
+  const uint32_t round = (uint32_t)a.ctl->rounds;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t waves = (uint64_t)gridDim.x * 4;
+  for (uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile * 16 < a.n; tile += waves) {
+    const uint64_t j = tile * 16 + (lane & 15);
+    float f[3] = {0.f, 0.f, 0.f}, pr = 0.f;
+    uint32_t since = 0;
+    bool pend = false;
+    if (lane < 16 && j < a.n) pend = vertex_features<ST, RowT>(a, indeg, last_upd, round, j, f, pr, since);
+    float x[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x[i] = pend ? (f[i] - fn.mean[i]) * fn.inv_std[i] : 0.f;
+    TileAct t;
+    tile_forward(m, x[0], x[1], x[2], t);
+    if (lane < 16 && j < a.n) {
+      float sc = 0.f;
+      if (pend) sc = since >= 64 ? 1099511627776.0f : 1.f / (1.f + __expf(-t.logit));
+      score[j] = sc;
+    }
+  }
+}
+
+// Trace capture: S sampled vertices per round.
+struct TraceDev {
+  uint32_t* vid;   // [R][S]
+  float* feat;     // [R][S][3]
+  float* p0;       // [R][S] priority when sampled (0: not pending)
+  float* maxp;     // [R][S] largest priority over the following rounds
+  uint8_t* sel;    // [R][S] updated in the sampled round
+};
+
+template <int ST, typename RowT>
+__global__ void k_trace_sample(KArgs a, const uint32_t* indeg, const uint32_t* last_upd, TraceDev td,
+                               uint64_t seed, uint32_t S, uint32_t slot) {
+  const uint32_t round = (uint32_t)a.ctl->rounds;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < S; i += gridDim.x * blockDim.x) {
+    const uint64_t j = splitmix64_at(seed, (uint64_t)slot * S + i) % a.n;
+    float f[3] = {0.f, 0.f, 0.f}, pr = 0.f;
+    uint32_t since = 0;
+    const bool pend = vertex_features<ST, RowT>(a, indeg, last_upd, round, j, f, pr, since);
+    const uint64_t o = (uint64_t)slot * S + i;
+    td.vid[o] = (uint32_t)j;
+    td.feat[o * 3] = f[0];
+    td.feat[o * 3 + 1] = f[1];
+    td.feat[o * 3 + 2] = f[2];
+    td.p0[o] = pend ? pr : 0.f;
+    td.maxp[o] = 0.f;
+    td.sel[o] = 0;
+  }
+}
+
+// After round `slot`: which samples were updated in it.
+__global__ void k_trace_selected(const uint32_t* last_upd, TraceDev td, uint32_t S, uint32_t slot) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < S; i += gridDim.x * blockDim.x) {
+    const uint64_t o = (uint64_t)slot * S + i;
+    td.sel[o] = (td.p0[o] > 0.f && last_upd[td.vid[o]] == slot) ? 1 : 0;
+  }
+}
+
+// Before a round: fold the current priority into the window maximum of the
+// samples of slots [first, last).
+template <int ST>
+__global__ void k_trace_window(KArgs a, TraceDev td, uint64_t first, uint64_t last) {
+  using S = typename Tr<ST>::S;
+  for (uint64_t o = first + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < last;
+       o += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = td.vid[o];
+    const S v = static_cast<const S*>(a.v)[j];
+    const S dv = static_cast<const S*>(a.dv)[j];
+    const auto k = prio_key<ST>(v, dv);
+    float p;
+    if constexpr (Tr<ST>::sum) p = (float)fabs((double)dv);
+    else p = (float)k;
+    if (k == 0) p = 0.f;
+    td.maxp[o] = fmaxf(td.maxp[o], p);
+  }
+}
+
+template <int ST, typename RowT>
+struct LearnedImpl {
+  static void score(daic_problem* p, const daic_sched_model* m, const FeatNorm& fn, hipStream_t s) {
+    const uint64_t tiles = (p->a.n + 15) / 16;
+    const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((tiles + 3) / 4, 8192));
+    hipLaunchKernelGGL((k_score<ST, RowT>), dim3(blocks), dim3(256), 0, s, p->a, m->dev(), fn, p->indeg,
+                       p->last_upd, p->score);
+  }
+  static void sample(daic_problem* p, const TraceDev& td, uint64_t seed, uint32_t S, uint32_t slot, hipStream_t s) {
+    hipLaunchKernelGGL((k_trace_sample<ST, RowT>), dim3((S + 255) / 256), dim3(256), 0, s, p->a, p->indeg,
+                       p->last_upd, td, seed, S, slot);
+  }
+  static void window(daic_problem* p, const TraceDev& td, uint64_t first, uint64_t last, hipStream_t s) {
+    if (last <= first) return;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (last - first + 255) / 256);
+    hipLaunchKernelGGL(k_trace_window<ST>, dim3(blocks), dim3(256), 0, s, p->a, td, first, last);
+  }
+};
+
+struct LearnedOps {
+  void (*score)(daic_problem*, const daic_sched_model*, const FeatNorm&, hipStream_t);
+  void (*sample)(daic_problem*, const TraceDev&, uint64_t, uint32_t, uint32_t, hipStream_t);
+  void (*window)(daic_problem*, const TraceDev&, uint64_t, uint64_t, hipStream_t);
+};
+
+template <int ST>
+static LearnedOps lops_row(const daic_problem* p) {
+  if (p->g->dev.row32)
+    return LearnedOps{&LearnedImpl<ST, uint32_t>::score, &LearnedImpl<ST, uint32_t>::sample,
+                      &LearnedImpl<ST, uint32_t>::window};
+  return LearnedOps{&LearnedImpl<ST, uint64_t>::score, &LearnedImpl<ST, uint64_t>::sample,
+                    &LearnedImpl<ST, uint64_t>::window};
+}
+
+static LearnedOps learned_ops(const daic_problem* p) {
+  switch (p->st) {
+    case ST_F64: return lops_row<ST_F64>(p);
+    case ST_F32: return lops_row<ST_F32>(p);
+    case ST_F32K: return lops_row<ST_F32K>(p);
+    case ST_U32: return lops_row<ST_U32>(p);
+    default: return lops_row<ST_I32>(p);
+  }
+}
+
+static FeatNorm norm_of(const daic_sched_model* m) {
+  FeatNorm fn;
+  for (int i = 0; i < 3; ++i) {
+    fn.mean[i] = m->fmean[i];
+    fn.inv_std[i] = 1.0f / m->fstd[i];
+  }
+  return fn;
+}
+
+// Per-vertex arrays of the learned scheduler; the update rounds are reset.
+static daic_status learned_arrays(daic_problem* p, hipStream_t s) {
+  const uint64_t n = p->g->dev.n, m = p->g->dev.m;
+  if (!p->learned_ready) {
+    DAIC_HIP(hipMalloc(&p->last_upd, std::max<uint64_t>(n, 1) * 4));
+    p->allocs.push_back(p->last_upd);
+    DAIC_HIP(hipMalloc(&p->indeg, std::max<uint64_t>(n, 1) * 4));
+    p->allocs.push_back(p->indeg);
+    DAIC_HIP(hipMalloc(&p->score, std::max<uint64_t>(n, 1) * 4));
+    p->allocs.push_back(p->score);
+    DAIC_HIP(hipMemsetAsync(p->indeg, 0, n * 4, s));
+    if (m) {
+      const uint32_t blocks = (uint32_t)std::min<uint64_t>(8192, (m + 255) / 256);
+      hipLaunchKernelGGL(k_indeg, dim3(blocks), dim3(256), 0, s, p->g->dev.col, m, p->indeg);
+    }
+    p->learned_ready = true;
+  }
+  DAIC_HIP(hipMemsetAsync(p->last_upd, 0, n * 4, s));
+  p->a.last_upd = p->last_upd;
+  return DAIC_OK;
+}
+
+daic_status learned_prepare(daic_problem* p, const daic_sched_model* model, hipStream_t s) {
+  if (!model) return fail(DAIC_E_INVALID, "LEARNED needs a model");
+  return learned_arrays(p, s);
+}
+
+daic_status learned_scores(daic_problem* p, const daic_sched_model* model, hipStream_t s, const float** score) {
+  learned_ops(p).score(p, model, norm_of(model), s);
+  *score = p->score;
+  return DAIC_OK;
+}
+
 void learned_after_round(daic_problem*, hipStream_t) {}
+
 }  // namespace daic
+
+// Host-side trace: features and labels of the vertices updated in the traced
+// rounds, with the windows of H rounds that decide their labels.
+struct daic_trace {
+  std::vector<float> x;  // [N][3] raw features
+  std::vector<float> y;  // [N]
+  uint64_t rounds = 0;
+  uint64_t sampled = 0;
+  int kind = 0;          // 0 sum, 1 min, 2 max
+};
+
+extern "C" {
+
+// Runs exact top-k rounds (opts: sched TOPK_EXACT, q, eps, max_rounds) from
+// the problem's current state to the stop rule, sampling S vertices per round.
+// A vertex updated in round t is labelled 1 ("update now") unless within the
+// next H rounds its priority reaches half its priority at t (sum problems) or
+// it becomes pending again at all (min/max problems): then its update was
+// premature and the label is 0.
+daic_status daic_trace_record(daic_problem* p, const daic_run_opts* o, uint32_t samples_per_round,
+                              uint32_t horizon, daic_trace** out) {
+  if (!p || !o || !out) return fail(DAIC_E_INVALID, "null argument");
+  *out = nullptr;
+  daic_status rc = check_opts(p, o);
+  if (rc) return rc;
+  if (o->sched != DAIC_SCHED_TOPK_EXACT) return fail(DAIC_E_INVALID, "traces come from exact top-k runs");
+  if (samples_per_round == 0 || samples_per_round > (1u << 20) || horizon == 0 || horizon > 64)
+    return fail(DAIC_E_INVALID, "samples_per_round in 1..2^20 and horizon in 1..64");
+  const uint64_t n = p->g->dev.n;
+  std::unique_ptr<daic_trace> tr(new daic_trace());
+  tr->kind = p->op == DAIC_SUM ? 0 : (p->op == DAIC_MIN ? 1 : 2);
+  if (n == 0) {
+    *out = tr.release();
+    return DAIC_OK;
+  }
+  Ops ops;
+  if (!get_ops(p, &ops)) return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");
+  hipStream_t s = o->hip_stream ? static_cast<hipStream_t>(o->hip_stream) : p->own_stream;
+  rc = learned_arrays(p, s);
+  if (rc) return rc;
+  rc = dense_rounds_setup(p, o, s);
+  if (rc) return rc;
+  const uint32_t S = samples_per_round, H = horizon;
+  const uint64_t R = std::min<uint64_t>(o->max_rounds ? o->max_rounds : 4096, 4096);
+  TraceDev td{};
+  DAIC_HIP(hipMalloc(&td.vid, R * S * 4));
+  DAIC_HIP(hipMalloc(&td.feat, R * S * 12));
+  DAIC_HIP(hipMalloc(&td.p0, R * S * 4));
+  DAIC_HIP(hipMalloc(&td.maxp, R * S * 4));
+  DAIC_HIP(hipMalloc(&td.sel, R * S));
+  LearnedOps lo = learned_ops(p);
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, p->a.ctl, o->eps, R);
+  ops.residual(p, s, 0);
+  uint64_t t = 0;
+  hipError_t e = hipSuccess;
+  for (; t < R; ++t) {
+    e = hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess || p->h_ctl->done || p->h_ctl->stop) break;
+    const uint64_t first = t >= H ? (t - H) * S : 0;
+    lo.window(p, td, first, t * S, s);
+    lo.sample(p, td, o->seed ^ 0x7A3E5C91u, S, (uint32_t)t, s);
+    ops.round(p, o, s, nullptr, nullptr);
+    hipLaunchKernelGGL(k_trace_selected, dim3((S + 255) / 256), dim3(256), 0, s, p->last_upd, td, S, (uint32_t)t);
+  }
+  std::vector<float> feat, p0, maxp;
+  std::vector<uint8_t> sel;
+  if (e == hipSuccess) {
+    const uint64_t cnt = t * S;
+    feat.resize(cnt * 3);
+    p0.resize(cnt);
+    maxp.resize(cnt);
+    sel.resize(cnt);
+    if (cnt) {
+      e = hipMemcpy(feat.data(), td.feat, cnt * 12, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(p0.data(), td.p0, cnt * 4, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(maxp.data(), td.maxp, cnt * 4, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(sel.data(), td.sel, cnt, hipMemcpyDeviceToHost);
+    }
+  }
+  for (void* q : {(void*)td.vid, (void*)td.feat, (void*)td.p0, (void*)td.maxp, (void*)td.sel}) (void)hipFree(q);
+  p->a.last_upd = nullptr;
+  if (e != hipSuccess) return fail(DAIC_E_DEVICE, "trace: %s", hipGetErrorString(e));
+  // labels from complete windows only
+  const bool done = p->h_ctl->done != 0;
+  const uint64_t full = done ? t : (t > H ? t - H : 0);
+  for (uint64_t r = 0; r < full; ++r)
+    for (uint32_t i = 0; i < S; ++i) {
+      const uint64_t o2 = r * S + i;
+      ++tr->sampled;
+      if (!sel[o2]) continue;
+      const bool premature = tr->kind == 0 ? (maxp[o2] >= 0.5f * p0[o2]) : (maxp[o2] > 0.f);
+      tr->x.insert(tr->x.end(), &feat[o2 * 3], &feat[o2 * 3] + 3);
+      tr->y.push_back(premature ? 0.f : 1.f);
+    }
+  tr->rounds = t;
+  *out = tr.release();
+  return DAIC_OK;
+}
+
+daic_status daic_trace_get(const daic_trace* tr, float* x, float* y, uint64_t* n) {
+  if (!tr || !n) return fail(DAIC_E_INVALID, "null argument");
+  if (x) std::memcpy(x, tr->x.data(), tr->x.size() * 4);
+  if (y) std::memcpy(y, tr->y.data(), tr->y.size() * 4);
+  *n = tr->y.size();
+  return DAIC_OK;
+}
+
+void daic_trace_destroy(daic_trace* tr) { delete tr; }
+
+// Trains the model on the union of the traces: features standardized with
+// their mean and scale (kept in the model), minibatch Adam on the mean
+// BCE-with-logits loss, gradients from the BF16 MFMA kernels.
+daic_status daic_sched_train(const daic_trace* const* traces, uint32_t n_traces, const daic_train_opts* to,
+                             daic_sched_model* m, daic_train_stats* st) {
+  if (!traces || !to || !m) return fail(DAIC_E_INVALID, "null argument");
+  std::vector<float> x, y;
+  for (uint32_t i = 0; i < n_traces; ++i) {
+    if (!traces[i]) return fail(DAIC_E_INVALID, "trace %u is null", i);
+    x.insert(x.end(), traces[i]->x.begin(), traces[i]->x.end());
+    y.insert(y.end(), traces[i]->y.begin(), traces[i]->y.end());
+  }
+  const uint64_t N = y.size();
+  if (N == 0) return fail(DAIC_E_INVALID, "no samples in the traces");
+  // standardization
+  double mean[3] = {0, 0, 0}, var[3] = {0, 0, 0};
+  for (uint64_t i = 0; i < N; ++i)
+    for (int k = 0; k < 3; ++k) mean[k] += x[i * 3 + k];
+  for (int k = 0; k < 3; ++k) mean[k] /= (double)N;
+  for (uint64_t i = 0; i < N; ++i)
+    for (int k = 0; k < 3; ++k) var[k] += (x[i * 3 + k] - mean[k]) * (x[i * 3 + k] - mean[k]);
+  for (int k = 0; k < 3; ++k) {
+    m->fmean[k] = (float)mean[k];
+    m->fstd[k] = (float)std::max(1e-6, std::sqrt(var[k] / (double)N));
+  }
+  // shuffle with a seeded Fisher-Yates on SplitMix64 draws, then standardize
+  std::vector<uint64_t> perm(N);
+  for (uint64_t i = 0; i < N; ++i) perm[i] = i;
+  uint64_t state = to->seed;
+  for (uint64_t i = N - 1; i > 0; --i) {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    std::swap(perm[i], perm[z % (i + 1)]);
+  }
+  std::vector<float> xs(N * 3), ys(N);
+  double pos = 0;
+  for (uint64_t i = 0; i < N; ++i) {
+    const uint64_t s0 = perm[i];
+    for (int k = 0; k < 3; ++k) xs[i * 3 + k] = (float)((x[s0 * 3 + k] - mean[k]) / m->fstd[k]);
+    ys[i] = y[s0];
+    pos += y[s0];
+  }
+  const uint64_t B = std::max<uint64_t>(16, std::min<uint64_t>(to->batch ? to->batch : 65536, N));
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (B + 63) / 64);
+  float *dx = nullptr, *dy = nullptr, *dg = nullptr, *part = nullptr;
+  double *dl = nullptr, *pl = nullptr;
+  DAIC_HIP(hipMalloc(&dx, N * 12));
+  DAIC_HIP(hipMalloc(&dy, N * 4));
+  DAIC_HIP(hipMalloc(&dg, kNParams * 4));
+  DAIC_HIP(hipMalloc(&dl, 8));
+  DAIC_HIP(hipMalloc(&part, (size_t)blocks * 4 * kNParams * 4));
+  DAIC_HIP(hipMalloc(&pl, (size_t)blocks * 4 * 8));
+  DAIC_HIP(hipMemcpy(dx, xs.data(), N * 12, hipMemcpyHostToDevice));
+  DAIC_HIP(hipMemcpy(dy, ys.data(), N * 4, hipMemcpyHostToDevice));
+  hipStream_t s = nullptr;
+  hipEvent_t e0, e1;
+  DAIC_HIP(hipEventCreate(&e0));
+  DAIC_HIP(hipEventCreate(&e1));
+  auto full_loss = [&](double* out_loss) -> daic_status {
+    daic_status rc2 = model_grad(m, dx, dy, N, (double)N, dg, dl, part, pl, blocks, s);
+    if (rc2) return rc2;
+    double l = 0;
+    DAIC_HIP(hipMemcpy(&l, dl, 8, hipMemcpyDeviceToHost));
+    *out_loss = l / (double)N;
+    return DAIC_OK;
+  };
+  double loss0 = 0, loss1 = 0;
+  daic_status rc = full_loss(&loss0);
+  DAIC_HIP(hipEventRecord(e0, s));
+  const float lr = to->lr > 0 ? to->lr : 1e-3f;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const uint32_t epochs = to->epochs ? to->epochs : 10;
+  for (uint32_t ep = 0; ep < epochs && rc == DAIC_OK; ++ep) {
+    for (uint64_t off = 0; off < N && rc == DAIC_OK; off += B) {
+      const uint64_t nb = std::min<uint64_t>(B, N - off);
+      rc = model_grad(m, dx + off * 3, dy + off, nb, (double)nb, dg, nullptr, part, pl, blocks, s);
+      m->adam_t += 1;
+      const float bc1 = 1.f - std::pow(b1, (float)m->adam_t);
+      const float bc2 = 1.f - std::pow(b2, (float)m->adam_t);
+      hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, m->w, m->m1, m->m2, dg, lr, b1, b2,
+                         1e-8f, bc1, bc2);
+      if (rc == DAIC_OK) rc = model_pack(m, s);
+    }
+  }
+  DAIC_HIP(hipEventRecord(e1, s));
+  DAIC_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  DAIC_HIP(hipEventElapsedTime(&ms, e0, e1));
+  if (rc == DAIC_OK) rc = full_loss(&loss1);
+  for (void* q : {(void*)dx, (void*)dy, (void*)dg, (void*)dl, (void*)part, (void*)pl}) (void)hipFree(q);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (st) {
+    st->samples = N;
+    st->positive_fraction = pos / (double)N;
+    st->loss_first = loss0;
+    st->loss_final = loss1;
+    st->time_ms = ms;
+    st->epochs = epochs;
+  }
+  return DAIC_OK;
+}
+
+}  // extern "C"

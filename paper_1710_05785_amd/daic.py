@@ -53,6 +53,17 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+class TrainStats(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_uint64), ("positive_fraction", ctypes.c_double),
+                ("loss_first", ctypes.c_double), ("loss_final", ctypes.c_double),
+                ("time_ms", ctypes.c_double), ("epochs", ctypes.c_uint32)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
                 ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double),
@@ -110,6 +121,13 @@ def lib():
         L.daic_mlp_forward.argtypes = [_vp, _vp, ctypes.c_uint64, _vp]
         L.daic_mlp_grad.argtypes = [_vp, _vp, _vp, ctypes.c_uint64, _vp,
                                     ctypes.POINTER(ctypes.c_double)]
+        L.daic_trace_record.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint32,
+                                        ctypes.c_uint32, ctypes.POINTER(_vp)]
+        L.daic_trace_get.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.daic_trace_destroy.argtypes = [_vp]
+        L.daic_trace_destroy.restype = None
+        L.daic_sched_train.argtypes = [ctypes.POINTER(_vp), ctypes.c_uint32,
+                                       ctypes.POINTER(TrainOpts), _vp, ctypes.POINTER(TrainStats)]
         L.daic_select_frontier.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint64, _vp,
                                            ctypes.POINTER(ctypes.c_double)]
         _lib = L
@@ -434,3 +452,52 @@ class SchedModel:
             self.close()
         except Exception:
             pass
+
+
+class Trace:
+    """Training samples captured from an exact top-k run (daic_trace)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def record(cls, problem: "Problem", samples_per_round=4096, horizon=4, **run_kw):
+        run_kw.setdefault("sched", "exact")
+        o = Problem.make_opts(**run_kw)
+        h = _vp()
+        check(lib().daic_trace_record(problem._h, ctypes.byref(o), samples_per_round, horizon,
+                                      ctypes.byref(h)), "daic_trace_record")
+        return cls(h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def get(self):
+        n = ctypes.c_uint64(0)
+        check(lib().daic_trace_get(self._h, None, None, ctypes.byref(n)), "daic_trace_get")
+        x = np.empty((n.value, 3), dtype=np.float32)
+        y = np.empty(n.value, dtype=np.float32)
+        check(lib().daic_trace_get(self._h, _addr(x), _addr(y), ctypes.byref(n)), "daic_trace_get")
+        return x, y
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().daic_trace_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sched_train(traces, model: SchedModel, epochs=10, batch=65536, lr=1e-3, seed=0) -> dict:
+    """Train the scheduler network on the device from captured traces."""
+    arr = (_vp * len(traces))(*[t.handle for t in traces])
+    o = TrainOpts(epochs, batch, lr, seed)
+    st = TrainStats()
+    check(lib().daic_sched_train(arr, len(traces), ctypes.byref(o), model.handle, ctypes.byref(st)),
+          "daic_sched_train")
+    return {k: getattr(st, k) for k, _ in TrainStats._fields_}
