@@ -171,6 +171,92 @@ def batched_form(daic, torch, eps, rounds_per_check):
     }
 
 
+def learned_form(daic, torch, g24, eps, rounds_per_check):
+    """The learned-scheduler form: the network is trained on the device on
+    traces of exact top-10% runs of PageRank (d = 0.8, FP32 + Kahan) and SSSP
+    (weights U{1..255}, source 0) on 16 RMAT-20 graphs (edge factor 16, seeds
+    100..115); then RMAT-24 PageRank to residual eps and RMAT-24 SSSP (weights
+    seed 7) run with exact top-10% and with learned selection."""
+    import numpy as np
+
+    import daic_gen
+
+    d = 0.8
+    q = 0.1
+    out = {}
+    t0 = time.perf_counter()
+    pr_tr, ss_tr = [], []
+    for seed in range(100, 116):
+        g = daic_gen.rmat(20, 16, seed=seed)
+        G = daic.Graph(g.row_ptr, g.col)
+        p = daic.Problem(G, daic.SUM, daic.G_DEG_SCALE, alpha=d, state="f32_kahan")
+        p.set_init(np.zeros(g.n), np.full(g.n, 1 - d))
+        pr_tr.append(daic.Trace.record(p, samples_per_round=4096, horizon=4, q=q, eps=eps))
+        w = daic_gen.sssp_weights(g.m, seed=seed + 1000)
+        ps = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+        v0 = np.full(g.n, 0xFFFFFFFF, dtype=np.uint32)
+        dv1 = v0.copy()
+        dv1[0] = 0
+        ps.set_init(v0, dv1)
+        ss_tr.append(daic.Trace.record(ps, samples_per_round=4096, horizon=4, q=q))
+    t_trace = time.perf_counter() - t0
+    log(f"learned: traces in {t_trace:.1f}s")
+    models = {}
+    for name, trs in (("pagerank", pr_tr), ("sssp", ss_tr)):
+        m = daic.SchedModel(seed=8)
+        st = daic.sched_train(trs, m, epochs=8, batch=65536, lr=3e-3, seed=8)
+        models[name] = m
+        out[f"train_{name}"] = st
+    # evaluation on RMAT-24
+    G = daic.Graph(g24.row_ptr, g24.col)
+    res = {}
+    for sched in ("exact", "learned"):
+        p = daic.Problem(G, daic.SUM, daic.G_DEG_SCALE, alpha=d, state="f32_kahan")
+        p.set_init(np.zeros(g24.n), np.full(g24.n, 1 - d))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = p.run(eps=eps, q=q, sched=sched, model=models["pagerank"] if sched == "learned" else None)
+        torch.cuda.synchronize()
+        res[sched] = (time.perf_counter() - t, r, p.get())
+    (te, re_, ve), (tl, rl, vl) = res["exact"], res["learned"]
+    out["pagerank_rmat24"] = {
+        "exact": {"time_to_residual_ms": te * 1e3, "rounds": re_.stats["rounds"],
+                  "pushed_edges": re_.stats["pushed_edges"], "converged": re_.converged},
+        "learned": {"time_to_residual_ms": tl * 1e3, "rounds": rl.stats["rounds"],
+                    "pushed_edges": rl.stats["pushed_edges"], "converged": rl.converged},
+        "pushed_edges_ratio_learned_vs_exact": rl.stats["pushed_edges"] / re_.stats["pushed_edges"],
+        "time_ratio_learned_vs_exact": tl / te,
+        "rel_l1_learned_vs_exact": float(np.abs(vl - ve).sum() / np.abs(ve).sum()),
+    }
+    del res
+    w24 = daic_gen.sssp_weights(g24.m, seed=7)
+    Gw = daic.Graph(g24.row_ptr, g24.col, w24)
+    sres = {}
+    for sched in ("exact", "learned"):
+        p = daic.Problem(Gw, daic.MIN, daic.G_EDGE_ADD, state="u32")
+        v0 = np.full(g24.n, 0xFFFFFFFF, dtype=np.uint32)
+        dv1 = v0.copy()
+        dv1[0] = 0
+        p.set_init(v0, dv1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = p.run(q=q, sched=sched, model=models["sssp"] if sched == "learned" else None)
+        torch.cuda.synchronize()
+        sres[sched] = (time.perf_counter() - t, r, p.get())
+    (te, re_, ve), (tl, rl, vl) = sres["exact"], sres["learned"]
+    out["sssp_rmat24"] = {
+        "exact": {"time_ms": te * 1e3, "rounds": re_.stats["rounds"],
+                  "pushed_edges": re_.stats["pushed_edges"], "converged": re_.converged},
+        "learned": {"time_ms": tl * 1e3, "rounds": rl.stats["rounds"],
+                    "pushed_edges": rl.stats["pushed_edges"], "converged": rl.converged},
+        "pushed_edges_ratio_learned_vs_exact": rl.stats["pushed_edges"] / re_.stats["pushed_edges"],
+        "time_ratio_learned_vs_exact": tl / te,
+        "bit_identical_learned_vs_exact": bool(np.array_equal(vl, ve)),
+    }
+    out["trace_seconds"] = t_trace
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +406,8 @@ def main():
                                       "pushed_edges": rq.stats["pushed_edges"],
                                       "gteps": rq.stats["pushed_edges"] / wq / 1e9,
                                       "converged": rq.converged}
+        log("learned-scheduler form ...")
+        forms["learned_sched"] = learned_form(daic, torch, g, args.eps, args.rounds_per_check)
         log("batched form ...")
         forms["batched_ppr_64x64"] = batched_form(daic, torch, args.eps, args.rounds_per_check)
         out["forms"] = forms
