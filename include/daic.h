@@ -92,12 +92,16 @@ typedef enum {
  *   ALL          : every pending vertex (a synchronous DAIC round, Eq. sync)
  *   TOPK_EXACT   : the ceil(q n) largest priorities, ties to the smaller id
  *   TOPK_SAMPLED : threshold = ceil(q S)-th largest of S sampled priorities
- *   LEARNED      : top ceil(q n) by priority x sigmoid(network score)        */
+ *   LEARNED      : top ceil(q n) by priority x sigmoid(network score)
+ *   ROUND_ROBIN  : the pending vertices of the next block of ceil(q n)
+ *                  consecutive ids, blocks taken cyclically (static order,
+ *                  Sec. 5.1 round-robin scheduling)                          */
 typedef enum {
   DAIC_SCHED_ALL = 0,
   DAIC_SCHED_TOPK_EXACT = 1,
   DAIC_SCHED_TOPK_SAMPLED = 2,
-  DAIC_SCHED_LEARNED = 3
+  DAIC_SCHED_LEARNED = 3,
+  DAIC_SCHED_ROUND_ROBIN = 4
 } daic_sched;
 
 typedef struct daic_graph daic_graph;
@@ -262,6 +266,15 @@ typedef struct {
 daic_status daic_sched_train(const daic_trace* const* traces, uint32_t n_traces,
                              const daic_train_opts* opts, daic_sched_model* m,
                              daic_train_stats* stats);
+
+/* Progress trace for update-count studies (Sec. 6.4): runs like daic_run,
+ * one round at a time, and after every round records the cumulative number
+ * of vertex updates and the progress metric sum_j v_j (sum problems: in
+ * FP64; min problems: over finite values; max problems: over all values).
+ * At most max_points rounds are recorded; *points receives the count. */
+daic_status daic_run_progress(daic_problem* p, const daic_run_opts* opts, uint64_t max_points,
+                              uint64_t* updates, double* progress, uint64_t* points,
+                              daic_stats* stats);
 
 /* daic_profile runs like daic_run but launches every kernel on its own,
  * bracketed by HIP events on the run's stream, one round at a time, and

@@ -61,6 +61,7 @@ struct KArgs {
   uint8_t* sel_out;         // dry selection output [n]
   const float* score;       // learned scheduler: multiplier in (0,1) per vertex, or null
   uint32_t* last_upd;       // learned scheduler: round of each vertex's last update, or null
+  uint64_t rr_chunk;        // round-robin: ids per block
   // dense rounds (pull over in-edges)
   const uint32_t* perm;     // renumbering of sources by out-degree
   const uint32_t* rowT;     // in-edge offsets [n+1]
@@ -355,6 +356,13 @@ static __global__ void k_select_all(Ctl* ctl) {
   ctl->tau = 0;
 }
 
+// Round-robin: block (round mod nblocks) of `chunk` consecutive ids.
+static __global__ void k_select_rr(Ctl* ctl, uint64_t nblocks) {
+  if (ctl_halted(ctl)) return;
+  ctl->sel_mode = 3;
+  ctl->tau = ctl->rounds % nblocks;
+}
+
 // ---------------------------------------------------------------------------
 // A2 (exact): radix select of the k-th largest key, 8 bits per pass, most
 // significant digit first. Ties at the k-th key go to the smaller ids.
@@ -436,6 +444,26 @@ __global__ __launch_bounds__(256) void k_tie_count(KArgs a) {
   for (uint64_t j = lo + threadIdx.x; j < hi; j += 256) cnt += sel_key<ST>(a, j, v[j], dv[j]) == tau;
   cnt = block_sum256(cnt);
   if (threadIdx.x == 0) a.blk_ties[blockIdx.x] = cnt;
+}
+
+// Progress metric sum_j v_j of the current state (FP64; min problems skip
+// infinite values; Kahan states report v - c), accumulated into *out.
+template <int ST>
+__global__ __launch_bounds__(256) void k_progress(KArgs a, double* out) {
+  using S = typename Tr<ST>::S;
+  const S* v = static_cast<const S*>(a.v);
+  double s = 0.0;
+  for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < a.n; j += (uint64_t)gridDim.x * 256) {
+    if constexpr (ST == ST_U32) {
+      if (v[j] != kInfU32) s += (double)v[j];
+    } else if constexpr (ST == ST_F32K) {
+      s += (double)v[j] - (double)a.c[j];
+    } else {
+      s += (double)v[j];
+    }
+  }
+  s = block_sum256(s);
+  if (threadIdx.x == 0) atomicAdd(out, s);
 }
 
 // Exclusive prefix of per-block counts (one block of 1024 threads).
@@ -521,7 +549,8 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
     if (pend) {
       if (mode == 0) sel = true;
       else if (mode == 1) sel = key >= tau;
-      else sel = key > tau || (key == tau && tie_base + ties_seen + tie[0] < ties_left);
+      else if (mode == 2) sel = key > tau || (key == tau && tie_base + ties_seen + tie[0] < ties_left);
+      else sel = j / a.rr_chunk == tau;
     }
     ties_seen += tie_tot[0];
     if constexpr (DRY) {

@@ -105,5 +105,6 @@ bool get_ops(const daic_problem* p, Ops* out);
 // Validation of run options, and the dense-round set-up of a run.
 daic_status check_opts(const daic_problem* p, const daic_run_opts* o);
 daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStream_t s);
+void apply_run_opts(daic_problem* p, const daic_run_opts* o);
 
 }  // namespace daic

@@ -98,6 +98,9 @@ struct Impl {
     const uint64_t n = p->a.n;
     if (o->sched == DAIC_SCHED_ALL) {
       launch(pr, "select_all", s, [&] { hipLaunchKernelGGL(k_select_all, dim3(1), dim3(1), 0, s, a.ctl); });
+    } else if (o->sched == DAIC_SCHED_ROUND_ROBIN) {
+      const uint64_t nb = (n + a.rr_chunk - 1) / a.rr_chunk;
+      launch(pr, "select_rr", s, [&] { hipLaunchKernelGGL(k_select_rr, dim3(1), dim3(1), 0, s, a.ctl, nb); });
     } else if (o->sched == DAIC_SCHED_TOPK_SAMPLED) {
       uint32_t S = o->n_samples ? o->n_samples : kMaxSamples;
       uint32_t rank = (uint32_t)std::max(1.0, std::ceil(o->priority_fraction * (double)S));
@@ -279,7 +282,7 @@ daic_status check_opts(const daic_problem* p, const daic_run_opts* o) {
   if (!(o->priority_fraction > 0.0 && o->priority_fraction <= 1.0))
     return fail(DAIC_E_INVALID, "priority_fraction must be in (0, 1]");
   if (!(o->eps >= 0.0)) return fail(DAIC_E_INVALID, "eps must be >= 0");
-  if (o->sched < DAIC_SCHED_ALL || o->sched > DAIC_SCHED_LEARNED) return fail(DAIC_E_INVALID, "unknown sched");
+  if (o->sched < DAIC_SCHED_ALL || o->sched > DAIC_SCHED_ROUND_ROBIN) return fail(DAIC_E_INVALID, "unknown sched");
   if (o->sched == DAIC_SCHED_TOPK_SAMPLED && o->n_samples > kMaxSamples)
     return fail(DAIC_E_INVALID, "n_samples must be <= %u", kMaxSamples);
   if (o->sched == DAIC_SCHED_LEARNED && !o->model) return fail(DAIC_E_INVALID, "LEARNED needs a model");
@@ -291,6 +294,12 @@ daic_status check_opts(const daic_problem* p, const daic_run_opts* o) {
 // on first use and sets the direction rule of this run. DAIC_NO_PULL=1 turns
 // them off; DAIC_PULL_DIV (default 32) sets the fraction n/div of updating
 // vertices from which a round runs dense.
+// Per-run kernel arguments that depend on the options.
+void apply_run_opts(daic_problem* p, const daic_run_opts* o) {
+  const uint64_t n = p->g->dev.n;
+  p->a.rr_chunk = std::max<uint64_t>(1, (uint64_t)std::ceil(o->priority_fraction * (double)n));
+}
+
 daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStream_t s) {
   p->k_sel = 0;
   p->pull_min = 0;
@@ -650,6 +659,7 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
   if (!p) return fail(DAIC_E_INVALID, "problem is null");
   daic_status rc = check_opts(p, o);
   if (rc) return rc;
+  apply_run_opts(p, o);
   const uint64_t n = p->g->dev.n;
   hipStream_t s = o->hip_stream ? static_cast<hipStream_t>(o->hip_stream) : p->own_stream;
   if (stats) std::memset(stats, 0, sizeof *stats);
@@ -805,6 +815,7 @@ daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, 
   if (!p || !out || !n_out) return fail(DAIC_E_INVALID, "null argument");
   daic_status rc = check_opts(p, o);
   if (rc) return rc;
+  apply_run_opts(p, o);
   if (o->sched == DAIC_SCHED_LEARNED) return fail(DAIC_E_UNSUPPORTED, "profile takes the plain rules");
   *n_out = 0;
   const uint64_t n = p->g->dev.n;
@@ -869,11 +880,72 @@ daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, 
   return c.done ? DAIC_OK : DAIC_NOT_CONVERGED;
 }
 
+daic_status daic_run_progress(daic_problem* p, const daic_run_opts* o, uint64_t max_points, uint64_t* updates,
+                              double* progress, uint64_t* points, daic_stats* stats) {
+  if (!p || !points || (max_points && (!updates || !progress))) return fail(DAIC_E_INVALID, "null argument");
+  daic_status rc = check_opts(p, o);
+  if (rc) return rc;
+  if (o->sched == DAIC_SCHED_LEARNED) return fail(DAIC_E_UNSUPPORTED, "progress traces take the plain rules");
+  apply_run_opts(p, o);
+  *points = 0;
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  const uint64_t n = p->g->dev.n;
+  if (n == 0) return DAIC_OK;
+  Ops ops;
+  if (!get_ops(p, &ops)) return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");
+  hipStream_t s = o->hip_stream ? static_cast<hipStream_t>(o->hip_stream) : p->own_stream;
+  const uint64_t max_rounds = o->max_rounds ? o->max_rounds : ~0ull;
+  rc = dense_rounds_setup(p, o, s);
+  if (rc) return rc;
+  double* dsum = nullptr;
+  DAIC_HIP(hipMalloc(&dsum, sizeof(double)));
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, p->a.ctl, o->eps, max_rounds);
+  ops.residual(p, s, 0);
+  const uint32_t pg = (uint32_t)std::min<uint64_t>(2048, (n + 255) / 256);
+  double sum = 0.0;
+  hipError_t e = hipSuccess;
+  for (;;) {
+    e = hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess || p->h_ctl->done || p->h_ctl->stop) break;
+    ops.round(p, o, s, nullptr, nullptr);
+    if (*points < max_points) {
+      e = hipMemsetAsync(dsum, 0, sizeof(double), s);
+      if (e != hipSuccess) break;
+      switch (p->st) {
+        case ST_F64: hipLaunchKernelGGL(k_progress<ST_F64>, dim3(pg), dim3(256), 0, s, p->a, dsum); break;
+        case ST_F32: hipLaunchKernelGGL(k_progress<ST_F32>, dim3(pg), dim3(256), 0, s, p->a, dsum); break;
+        case ST_F32K: hipLaunchKernelGGL(k_progress<ST_F32K>, dim3(pg), dim3(256), 0, s, p->a, dsum); break;
+        case ST_U32: hipLaunchKernelGGL(k_progress<ST_U32>, dim3(pg), dim3(256), 0, s, p->a, dsum); break;
+        default: hipLaunchKernelGGL(k_progress<ST_I32>, dim3(pg), dim3(256), 0, s, p->a, dsum); break;
+      }
+      e = hipMemcpyAsync(&sum, dsum, sizeof(double), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) break;
+      updates[*points] = p->h_ctl->activations;
+      progress[*points] = sum;
+      ++*points;
+    }
+  }
+  (void)hipFree(dsum);
+  if (e != hipSuccess) return fail(DAIC_E_DEVICE, "progress: %s", hipGetErrorString(e));
+  const Ctl& c = *p->h_ctl;
+  if (stats) {
+    stats->rounds = c.rounds;
+    stats->activations = c.activations;
+    stats->pushed_edges = c.pushed;
+    stats->final_residual = c.r;
+  }
+  return c.done ? DAIC_OK : DAIC_NOT_CONVERGED;
+}
+
 daic_status daic_select_frontier(daic_problem* p, const daic_run_opts* o, uint64_t round, uint8_t* sel_out,
                                  double* threshold_out) {
   if (!p || !sel_out) return fail(DAIC_E_INVALID, "null argument");
   daic_status rc = check_opts(p, o);
   if (rc) return rc;
+  apply_run_opts(p, o);
   if (o->sched == DAIC_SCHED_LEARNED) return fail(DAIC_E_UNSUPPORTED, "select_frontier takes the plain rules");
   const uint64_t n = p->g->dev.n;
   if (n == 0) return DAIC_OK;

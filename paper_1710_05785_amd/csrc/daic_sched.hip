@@ -790,6 +790,7 @@ daic_status daic_trace_record(daic_problem* p, const daic_run_opts* o, uint32_t 
   daic_status rc = check_opts(p, o);
   if (rc) return rc;
   if (o->sched != DAIC_SCHED_TOPK_EXACT) return fail(DAIC_E_INVALID, "traces come from exact top-k runs");
+  apply_run_opts(p, o);
   if (samples_per_round == 0 || samples_per_round > (1u << 20) || horizon == 0 || horizon > 64)
     return fail(DAIC_E_INVALID, "samples_per_round in 1..2^20 and horizon in 1..64");
   const uint64_t n = p->g->dev.n;

@@ -22,11 +22,11 @@ OK, NOT_CONVERGED = 0, 1
 SUM, MIN, MAX = 0, 1, 2
 G_SRC_SCALE, G_EDGE_SCALE, G_EDGE_ADD, G_COPY, G_DEG_SCALE = 0, 1, 2, 3, 4
 F64, F32, F32_KAHAN, U32, I32, NONE = 0, 1, 2, 3, 4, 5
-SCHED_ALL, SCHED_TOPK_EXACT, SCHED_TOPK_SAMPLED, SCHED_LEARNED = 0, 1, 2, 3
+SCHED_ALL, SCHED_TOPK_EXACT, SCHED_TOPK_SAMPLED, SCHED_LEARNED, SCHED_ROUND_ROBIN = 0, 1, 2, 3, 4
 INF_U32 = 0xFFFFFFFF
 
 _SCHED_NAMES = {"all": SCHED_ALL, "exact": SCHED_TOPK_EXACT, "sampled": SCHED_TOPK_SAMPLED,
-                "learned": SCHED_LEARNED}
+                "learned": SCHED_LEARNED, "round_robin": SCHED_ROUND_ROBIN}
 _STATE_NAMES = {"f64": F64, "f32": F32, "f32_kahan": F32_KAHAN, "u32": U32, "i32": I32}
 
 _vp = ctypes.c_void_p
@@ -128,6 +128,8 @@ def lib():
         L.daic_trace_destroy.restype = None
         L.daic_sched_train.argtypes = [ctypes.POINTER(_vp), ctypes.c_uint32,
                                        ctypes.POINTER(TrainOpts), _vp, ctypes.POINTER(TrainStats)]
+        L.daic_run_progress.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint64, _vp, _vp,
+                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(Stats)]
         L.daic_select_frontier.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint64, _vp,
                                            ctypes.POINTER(ctypes.c_double)]
         _lib = L
@@ -300,6 +302,18 @@ class Problem:
         dv = np.empty(self.n, dtype=dt) if with_dv else None
         check(lib().daic_problem_get(self._h, _addr(v), _addr(dv)), "daic_problem_get")
         return (v, dv) if with_dv else v
+
+    def run_progress(self, max_points=100000, **kw):
+        """Run one round at a time; returns (RunResult, updates[], progress[])."""
+        o = self.make_opts(**kw)
+        st = Stats()
+        up = np.zeros(max_points, dtype=np.uint64)
+        pr = np.zeros(max_points, dtype=np.float64)
+        pts = ctypes.c_uint64(0)
+        rc = check(lib().daic_run_progress(self._h, ctypes.byref(o), max_points, _addr(up), _addr(pr),
+                                           ctypes.byref(pts), ctypes.byref(st)), "daic_run_progress")
+        k = pts.value
+        return RunResult(rc, st.as_dict()), up[:k], pr[:k]
 
     def select_frontier(self, round_no=0, **kw):
         o = self.make_opts(**kw)

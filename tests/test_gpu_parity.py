@@ -364,3 +364,132 @@ def test_push_and_pull_rounds_agree(daic, monkeypatch, direction, state, gk):
             assert err <= 1e-9, (sched, err)
         else:
             assert err / ref.sum() <= 1e-5, (sched, err)
+
+
+# ---------------------------------------------------------------------------
+# Round-robin scheduling and progress traces (Sec. 5.1, Sec. 6.4)
+# ---------------------------------------------------------------------------
+
+def test_round_robin_selection_block(daic):
+    say("case rr selection")
+    n = 1000
+    g = daic_gen.from_edges(n, [], [])
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8)
+    dv = np.where(np.arange(n) % 3 == 0, 0.0, 1.0)
+    p.set_init(np.zeros(n), dv)
+    sel, _ = p.select_frontier(q=0.1, sched="round_robin")
+    # round 0 takes block 0 = ids 0..99, pending ones only
+    want = (np.arange(n) < 100) & (dv != 0)
+    np.testing.assert_array_equal(sel, want)
+
+
+def test_round_robin_reaches_the_fixed_point(daic, pl10k, pl10k_ref):
+    say("case rr pagerank")
+    p = pr_problem(daic, pl10k, 0.8)
+    res = p.run(eps=1e-10, q=0.1, sched="round_robin")
+    assert res.converged
+    assert np.abs(p.get() - pl10k_ref).sum() <= 1e-9
+    g = daic_gen.rmat(12, 16, seed=5)
+    w, ref = sssp_case(g, 3)
+    ps = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+    ps.set_init(*oracle.sssp_init(g.n, 0))
+    assert ps.run(q=0.05, sched="round_robin").converged
+    np.testing.assert_array_equal(ps.get(), ref)
+
+
+def test_progress_trace_is_monotone(daic):
+    """sum_j v_j grows monotonically for PageRank and falls for SSSP (Sec. 6.4);
+    the last point equals the fixed point's total."""
+    say("case progress")
+    g = daic_gen.rmat(13, 16, seed=9)
+    p = pr_problem(daic, g, 0.8)
+    res, up, pr = p.run_progress(eps=1e-9, q=0.2, sched="exact")
+    assert res.converged and len(pr) == res.stats["rounds"]
+    assert np.all(np.diff(pr) >= -1e-9) and np.all(np.diff(up.astype(np.int64)) > 0)
+    assert abs(pr[-1] - p.get().sum()) <= 1e-9 * pr[-1]
+    w, ref = sssp_case(g, 4)
+    ps = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+    ps.set_init(*oracle.sssp_init(g.n, 0))
+    res, up, pr = ps.run_progress(q=0.2, sched="round_robin")
+    assert res.converged
+    finite = ref != oracle.INF_U32
+    assert pr[-1] == ref[finite].astype(np.float64).sum()
+
+
+# ---------------------------------------------------------------------------
+# Further rows of the algorithm table (Table 1) through the same kernels
+# ---------------------------------------------------------------------------
+
+def test_jacobi_linear_solver(daic):
+    """Jacobi method (Sec. 4.2.2): g_{i,j}(x) = -A_ji / A_jj x, dv1_j = b_j / A_jj,
+    on a diagonally dominant sparse system; signed coefficients."""
+    say("case jacobi")
+    from scipy.sparse import random as sprandom
+
+    n = 3000
+    rng = np.random.default_rng(3)
+    A = sprandom(n, n, density=8.0 / n, random_state=4, format="csr")
+    A.data = rng.uniform(-1, 1, A.data.size)
+    A.setdiag(0)
+    A.eliminate_zeros()
+    rowabs = np.asarray(abs(A).sum(axis=1)).ravel()
+    diag = 2.0 * rowabs + 1.0
+    b = rng.normal(0, 1, n)
+    Ad = A.toarray() + np.diag(diag)
+    want = np.linalg.solve(Ad, b)
+    # edge i -> j carries -A_ji / A_jj: the transpose's rows are the senders
+    AT = A.T.tocsr()
+    AT.sort_indices()
+    src = np.repeat(np.arange(n), np.diff(AT.indptr))
+    dst = AT.indices
+    w = -AT.data / diag[dst]
+    order = np.lexsort((dst, src))
+    g = daic_gen.from_edges(n, src[order], dst[order])
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col, w[order].astype(np.float64)), daic.SUM,
+                     daic.G_EDGE_SCALE, alpha=1.0, state="f64")
+    p.set_init(np.zeros(n), b / diag)
+    assert p.run(eps=1e-12, q=1.0, sched="all").converged
+    np.testing.assert_allclose(p.get(), want, rtol=0, atol=1e-10)
+
+
+def test_hits_authority(daic):
+    """HITS authority (Table 1): g(x) = d A(i,j) x with A = W^T W built first."""
+    say("case hits")
+    from scipy.sparse import csr_matrix
+
+    g0 = daic_gen.rmat(10, 4, seed=12)
+    n = g0.n
+    src = np.repeat(np.arange(n), g0.outdeg())
+    W = csr_matrix((np.ones(g0.m), (src, g0.col.astype(np.int64))), shape=(n, n))
+    W.data[:] = 1.0
+    A = (W.T @ W).tocsr()
+    A.sort_indices()
+    d = 0.5 / max(1.0, float(abs(A).sum(axis=1).max()))
+    src = np.repeat(np.arange(n), np.diff(A.indptr))
+    g = daic_gen.from_edges(n, src, A.indices)
+    w = A.data.astype(np.float64)
+    want = np.linalg.solve(np.eye(n) - d * A.toarray().T, np.ones(n))
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.SUM, daic.G_EDGE_SCALE, alpha=d)
+    p.set_init(np.zeros(n), np.ones(n))
+    assert p.run(eps=1e-12).converged
+    np.testing.assert_allclose(p.get(), want, rtol=1e-10)
+
+
+def test_checkpoint_resume_through_files(daic, tmp_path):
+    """A round boundary is a consistent cut: (v, dv) saved to a file and loaded
+    into a fresh problem reaches the same fixed point (cf. Sec. 5.1 fault
+    tolerance; no in-flight messages exist between rounds)."""
+    say("case checkpoint")
+    g = daic_gen.rmat(13, 16, seed=21)
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.8, np.full(g.n, 0.2), eps=1e-13)
+    p = pr_problem(daic, g, 0.8)
+    res = p.run(eps=1e-12, q=0.3, sched="exact", max_rounds=5, rounds_per_check=1)
+    assert res.status == daic.NOT_CONVERGED
+    v, dv = p.get(with_dv=True)
+    np.savez(tmp_path / "ckpt.npz", v=v, dv=dv)
+    del p
+    ck = np.load(tmp_path / "ckpt.npz")
+    q = pr_problem(daic, g, 0.8)
+    q.set_init(ck["v"], ck["dv"])
+    assert q.run(eps=1e-10, q=1.0).converged
+    assert np.abs(q.get() - ref).sum() <= 1e-9
