@@ -52,7 +52,7 @@ def host_info():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("daic_kernels.h", "daic_runtime.hip"):
+    for f in ("daic_kernels.h", "daic_device.h", "daic_runtime.hip", "daic_pull.hip"):
         with open(os.path.join(ROOT, "paper_1710_05785_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -257,6 +257,68 @@ def learned_form(daic, torch, g24, eps, rounds_per_check):
     return out
 
 
+def ablation(daic, torch):
+    """Synchronous vs round-robin vs priority scheduling on one GPU (the
+    paper's update-count comparison, Sec. 6.4): progress metric against the
+    number of vertex updates, and time to the stop rule."""
+    import numpy as np
+
+    import daic_gen
+
+    out = {}
+    cases = []
+    g22 = daic_gen.rmat(22, 16, seed=4)
+    cases.append(("pagerank_rmat22_f32k", g22, None))
+    g20 = daic_gen.rmat(20, 16, seed=2)
+    cases.append(("sssp_rmat20_u32", g20, daic_gen.sssp_weights(g20.m, seed=3)))
+    for name, g, w in cases:
+        res = {}
+        for sched, q in (("all", 1.0), ("round_robin", 0.1), ("exact", 0.1), ("sampled", 0.1)):
+            if w is None:
+                p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8,
+                                 state="f32_kahan")
+                p.set_init(np.zeros(g.n), np.full(g.n, 0.2))
+                kw = dict(eps=1e-6)
+            else:
+                p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+                v0 = np.full(g.n, 0xFFFFFFFF, dtype=np.uint32)
+                dv1 = v0.copy()
+                dv1[0] = 0
+                p.set_init(v0, dv1)
+                kw = {}
+            r, up, pr = p.run_progress(q=q, sched=sched, seed=1, **kw)
+            # time of the same run without the per-round trace
+            if w is None:
+                p.set_init(np.zeros(g.n), np.full(g.n, 0.2))
+            else:
+                p.set_init(v0, dv1)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r2 = p.run(q=q, sched=sched, seed=1, **kw)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+            final = pr[-1]
+            first = pr[0]
+            def updates_to(frac):
+                target = first + frac * (final - first)
+                idx = np.nonzero((pr >= target) if final >= first else (pr <= target))[0]
+                return int(up[idx[0]]) if idx.size else None
+            step = max(1, len(pr) // 24)
+            res[f"{sched}_q{q}"] = {
+                "rounds": r.stats["rounds"], "updates": r.stats["activations"],
+                "pushed_edges": r.stats["pushed_edges"], "time_ms": wall * 1e3,
+                "converged": r2.converged,
+                "updates_to_99pct_progress": updates_to(0.99),
+                "updates_to_99.99pct_progress": updates_to(0.9999),
+                "curve_updates": [int(x) for x in up[::step]],
+                "curve_progress": [float(x) for x in pr[::step]],
+            }
+            log(f"ablation {name} {sched} q={q}: rounds {r.stats['rounds']} updates "
+                f"{r.stats['activations']} time {wall * 1e3:.1f} ms")
+        out[name] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +332,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP64 and sampled forms")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--ablation", action="store_true",
+                    help="only run the sync / round-robin / priority comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -289,6 +353,9 @@ def main():
 
     torch.cuda.set_device(0)
     daic.lib()
+    if args.ablation:
+        print(json.dumps({"ablation": ablation(daic, torch), "host": host_info()}), flush=True)
+        return
     d = 0.8
     t = time.perf_counter()
     g = daic_gen.rmat(args.scale, args.edgefactor, seed=args.seed)
