@@ -738,8 +738,8 @@ __device__ __forceinline__ double pull_msg(const KArgs& a, uint64_t p) {
   return m;
 }
 
-// Small targets (in-degree 1..kSmallMaxDeg), one per thread; the static list
-// is ordered by in-degree class so that the lanes of a wave loop about equally.
+// Small targets (in-degree 1..kSmallMaxDeg), one per thread, in id order, so
+// that offsets, in-edge lists and deltas are read by consecutive lanes.
 template <int ST, int G>
 __global__ __launch_bounds__(256) void k_pull_small(KArgs a) {
   using S = typename Tr<ST>::S;

@@ -160,16 +160,13 @@ daic_status pull_prepare(daic_graph* g, hipStream_t s) {
   v0 = v1 = nullptr;
   tmp = nullptr;
   std::vector<uint32_t> st, lt, lc, ln;
-  // small targets grouped by in-degree class {1}, {2}, {3,4}, {5..8}, ... ,
-  // ids ascending inside a class
-  std::vector<std::vector<uint32_t>> cls(8);
+  // small targets in id order: their offsets, in-edge lists and deltas are
+  // then read and written by consecutive lanes
   for (uint64_t t = 0; t < n; ++t) {
     uint32_t deg = rt[t + 1] - rt[t];
     if (deg == 0) continue;
     if (deg <= kSmallMaxDeg) {
-      uint32_t c = 0;
-      while ((1u << c) < deg) ++c;
-      cls[c].push_back((uint32_t)t);
+      st.push_back((uint32_t)t);
       P.small_edges += deg;
     } else {
       P.large_edges += deg;
@@ -181,7 +178,6 @@ daic_status pull_prepare(daic_graph* g, hipStream_t s) {
       }
     }
   }
-  for (auto& c : cls) st.insert(st.end(), c.begin(), c.end());
   P.n_small = st.size();
   P.n_large = lt.size();
   PCHK(hipMalloc(&P.small_tgt, std::max<size_t>(st.size(), 1) * 4));
