@@ -4,11 +4,15 @@
 //
 // The graphs are joined into one block-diagonal graph; the state is
 // [vertex][64 right-hand sides] in FP32, so one message is a contiguous
-// 256-byte vector. A round is three kernels over every graph at once (claim,
-// propagate, residual); propagation pulls over in-edges when dense and pushes
-// with atomics when sparse. Every instance (graph, right-hand side) has its
-// own residual and stop flag. Lanes per vertex and grid sizes come from an
-// autotuner that times the dense-round kernels on the device.
+// 256-byte vector. While few vertices are pending, a round is three kernels
+// (claim, push with atomics, residual). Once the pending set is dense, one
+// claim publishes the message bases and every later round is a fused pass
+// over graph-aligned vertex ranges: pull the previous round's messages over
+// in-edges (high in-degree targets are summed beforehand by a chunked
+// kernel), take the residual, claim and publish the next messages into a
+// second buffer. Every instance (graph, right-hand side) has its own residual
+// and finish state. Lanes per vertex and grid sizes come from an autotuner
+// that times the kernels on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,13 +32,21 @@ namespace daic {
 constexpr int kR = 64;                 // right-hand sides per vertex (padded)
 constexpr uint32_t kBChunk = 1024;     // in-edges per pull item
 constexpr uint32_t kPushChunk = 256;   // out-edges per push item
-constexpr uint32_t kResChunk = 8192;   // vertices per residual item
+constexpr uint32_t kResChunk = 4096;   // at most this many vertices per residual item
+constexpr uint32_t kItemWork = 32768;  // and about this much work (in-edges + kVertexWork per vertex)
+constexpr uint32_t kVertexWork = 4;
+constexpr uint32_t kHubDeg = 64;       // default in-degree above which a target is a hub
 
+// Round modes: 0 = sparse round (claim, push, residual); 1 = the claim that
+// starts the dense phase (publishes message bases, delivers nothing);
+// 2 = fused dense round (deliver the previous round's messages by pulling,
+// then claim and publish, with the residual in the same pass).
 struct BCtl {
-  uint32_t done;          // every instance finished
+  uint32_t done;          // every instance finished and nothing in flight
   uint32_t stop;          // round limit reached
-  uint32_t pull;          // next round is dense
+  uint32_t mode;          // mode of the next round
   uint32_t ticket;
+  uint32_t prev_all_done; // every instance was finished after the previous round
   uint64_t rounds;
   uint64_t max_rounds;
   uint64_t pending;       // vertices with a pending right-hand side
@@ -52,7 +64,8 @@ struct BArgs {
   float* v;                   // [N][64]
   float* dv;
   float* c;                   // Kahan term, or null
-  float* mu;                  // [N][64]: renumbered (dense) or by vertex (sparse)
+  float* mu;                  // [N][64]: by vertex (sparse) / renumbered, even rounds (dense)
+  float* mu2;                 // [N][64]: renumbered, odd rounds (dense)
   uint8_t* active;            // [N] vertex sent this round (sparse rounds)
   uint8_t* done;              // [G][64] instance finished
   double alpha;
@@ -60,10 +73,6 @@ struct BArgs {
   const uint32_t* perm;
   const uint32_t* rowT;
   const uint32_t* srcT;
-  const uint32_t* pt;         // pull items (target, chunk, nchunks)
-  const uint32_t* pc;
-  const uint32_t* pn;
-  uint64_t n_pull;
   // sparse rounds
   const uint32_t* sv;         // push items (vertex, chunk)
   const uint32_t* sc;
@@ -79,11 +88,32 @@ struct BArgs {
   uint64_t* part_p;           // [n_res] union pending
   uint64_t* part_a;           // [claim blocks] activations
   uint64_t* part_m;           // [claim blocks] messages
+  uint64_t* part_fa;          // [n_res] activations / messages of fused rounds
+  uint64_t* part_fm;
   double* inst_r;             // [G][64] residual per instance
-  uint64_t pull_min;          // dense round when union pending >= pull_min
+  uint64_t pull_min;          // dense phase when union pending >= pull_min
+  // per graph: item tickets and the sums of its retired items
+  uint32_t* g_ticket;
+  uint32_t* g_flag;
+  uint64_t* g_pend;
+  uint64_t* g_act;
+  uint64_t* g_msg;
+  // fused dense rounds: in-edges of hub targets (in-degree > hub_deg) are
+  // summed by a chunked kernel before the fused pass
+  uint32_t hub_deg;
+  const uint32_t* ht;         // hub items (target, chunk)
+  const uint32_t* hc;
+  uint64_t n_hub;
+  const uint32_t* item_order; // block -> residual item of the fused pass (~0u: none)
+  const uint32_t* vord;       // [N] vertices of each item by pulled in-degree, descending
+  uint32_t n_fused_blocks;
 };
 
 __device__ __forceinline__ bool bhalted(const BCtl* c) { return (c->done | c->stop) != 0; }
+
+
+// Message-base buffer written by the claims of round t (dense phase).
+__device__ __forceinline__ float* mu_of_round(const BArgs& a, uint64_t t) { return (t & 1) ? a.mu2 : a.mu; }
 
 template <int W>
 struct VecF;
@@ -118,8 +148,9 @@ __global__ __launch_bounds__(256) void k_bclaim(BArgs a) {
   constexpr int W = kR / LPV;
   constexpr int VPB = 256 / LPV;
   BCtl* ctl = a.ctl;
-  if (bhalted(ctl)) return;
-  const bool pull = ctl->pull != 0;
+  if (bhalted(ctl) || ctl->mode == 2) return;
+  const bool pull = ctl->mode == 1;
+  float* mu_dense = mu_of_round(a, ctl->rounds);
   const uint32_t sub = threadIdx.x / LPV;
   const uint32_t r0 = (threadIdx.x % LPV) * W;
   uint64_t act = 0, msg = 0;
@@ -178,7 +209,7 @@ __global__ __launch_bounds__(256) void k_bclaim(BArgs a) {
     act += nclaim;
     msg += (uint64_t)nclaim * deg;
     if (pull) {
-      vstore<W>(a.mu + (uint64_t)a.perm[j] * kR + r0, mu);
+      vstore<W>(mu_dense + (uint64_t)a.perm[j] * kR + r0, mu);
     } else {
       // a vertex is active when any of its lanes sends; every lane of the
       // vertex writes its part of the message base
@@ -197,63 +228,13 @@ __global__ __launch_bounds__(256) void k_bclaim(BArgs a) {
   }
 }
 
-// Dense round: every target adds the message bases of its in-neighbours.
-template <int LPV>
-__global__ __launch_bounds__(256) void k_bpull(BArgs a) {
-  constexpr int W = kR / LPV;
-  constexpr int IPB = 256 / LPV;  // items per block at a time
-  BCtl* ctl = a.ctl;
-  if (bhalted(ctl) || !ctl->pull) return;
-  const uint32_t sub = threadIdx.x / LPV;
-  const uint32_t r0 = (threadIdx.x % LPV) * W;
-  for (uint64_t base = (uint64_t)blockIdx.x * IPB; base < a.n_pull; base += (uint64_t)gridDim.x * IPB) {
-    const uint64_t i = base + sub;
-    if (i >= a.n_pull) continue;
-    const uint32_t t = a.pt[i], ch = a.pc[i], nch = a.pn[i];
-    const uint32_t beg = a.rowT[t] + ch * kBChunk;
-    const uint32_t end = min(a.rowT[t + 1], beg + kBChunk);
-    float acc[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) acc[k] = 0.0f;
-    uint32_t p = beg;
-    for (; p + 3 < end; p += 4) {
-      const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
-      float x0[W], x1[W], x2[W], x3[W];
-      vload<W>(a.mu + (uint64_t)s0 * kR + r0, x0);
-      vload<W>(a.mu + (uint64_t)s1 * kR + r0, x1);
-      vload<W>(a.mu + (uint64_t)s2 * kR + r0, x2);
-      vload<W>(a.mu + (uint64_t)s3 * kR + r0, x3);
-#pragma unroll
-      for (int k = 0; k < W; ++k) acc[k] += (x0[k] + x1[k]) + (x2[k] + x3[k]);
-    }
-    for (; p < end; ++p) {
-      float x[W];
-      vload<W>(a.mu + (uint64_t)a.srcT[p] * kR + r0, x);
-#pragma unroll
-      for (int k = 0; k < W; ++k) acc[k] += x[k];
-    }
-    float* dst = a.dv + (uint64_t)t * kR + r0;
-    if (nch == 1) {
-      float d[W];
-      vload<W>(dst, d);
-#pragma unroll
-      for (int k = 0; k < W; ++k) d[k] += acc[k];
-      vstore<W>(dst, d);
-    } else {
-#pragma unroll
-      for (int k = 0; k < W; ++k)
-        if (acc[k] != 0.0f) unsafeAtomicAdd(dst + k, acc[k]);
-    }
-  }
-}
-
 // Sparse round: active vertices push their 64-wide message to every out-edge.
 template <int LPV>
 __global__ __launch_bounds__(256) void k_bpush(BArgs a) {
   constexpr int W = kR / LPV;
   constexpr int IPB = 256 / LPV;
   BCtl* ctl = a.ctl;
-  if (bhalted(ctl) || ctl->pull) return;
+  if (bhalted(ctl) || ctl->mode != 0) return;
   const uint32_t sub = threadIdx.x / LPV;
   const uint32_t r0 = (threadIdx.x % LPV) * W;
   for (uint64_t base = (uint64_t)blockIdx.x * IPB; base < a.n_push; base += (uint64_t)gridDim.x * IPB) {
@@ -274,15 +255,129 @@ __global__ __launch_bounds__(256) void k_bpush(BArgs a) {
   }
 }
 
-// Residual per instance (FP64 sums of |dv| per graph and right-hand side),
-// union pending count, stop flags and the direction of the next round. One
-// block per residual item; the last block reduces in a fixed order.
+// Retirement of a residual item. The block that retires the last item of a
+// graph sums the graph's per-item partials in a fixed order and moves the
+// finish state of its 64 instances; the block that retires the last graph
+// updates the control block. kind 0: sparse round or initial check (all
+// messages delivered); kind 1: fused dense round (the residual is that of the
+// previous round's end state, whose last messages are still in flight);
+// kind 2: final delivery after a stop in the dense phase.
+// Finish states per instance: 0 running, 1 finished with messages in flight,
+// 2 finished and delivered.
+__device__ void retire_item(const BArgs& a, uint32_t g, int kind, int count_round) {
+  __shared__ uint32_t s_flag;
+  __shared__ double s_r[4][kR];
+  BCtl* ctl = a.ctl;
+  __threadfence();  // this block's partials are visible before its ticket
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t nit = a.g_first_item[g + 1] - a.g_first_item[g];
+    s_flag = atomicAdd(&a.g_ticket[g], 1u) == nit - 1;
+  }
+  __syncthreads();
+  if (!s_flag) return;
+  __threadfence();
+  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  const uint32_t k0 = a.g_first_item[g], k1 = a.g_first_item[g + 1];
+  double r = 0.0;
+  for (uint32_t k = k0 + wave; k < k1; k += 4)
+    r += __hip_atomic_load(&a.part_r[(uint64_t)k * kR + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  s_r[wave][lane] = r;
+  uint64_t pend = 0, act = 0, msg = 0;
+  for (uint32_t k = k0 + threadIdx.x; k < k1; k += 256) {
+    pend += __hip_atomic_load(&a.part_p[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    act += __hip_atomic_load(&a.part_fa[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    msg += __hip_atomic_load(&a.part_fm[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  pend = block_sum256(pend);
+  act = block_sum256(act);
+  msg = block_sum256(msg);
+  if (wave == 0) {
+    const uint32_t q = g * kR + lane;
+    const double sr = ((s_r[0][lane] + s_r[1][lane]) + s_r[2][lane]) + s_r[3][lane];
+    const uint8_t st = a.done[q];
+    uint8_t ns = st;
+    bool flag;
+    if (kind == 0) {
+      a.inst_r[q] = sr;
+      if (st == 0 && sr <= ctl->eps) ns = 2;
+      flag = ns == 2;
+    } else if (kind == 1) {
+      if (st != 2) a.inst_r[q] = sr;
+      if (st == 1) ns = 2;
+      else if (st == 0 && sr <= ctl->eps) ns = 1;
+      flag = st != 0;  // nothing was claimed for this instance in this round
+    } else {
+      if (st != 2) a.inst_r[q] = sr;
+      if (st == 1 || (st == 0 && sr <= ctl->eps)) ns = 2;
+      flag = ns == 2;
+    }
+    a.done[q] = ns;
+    const bool all = __ballot(!flag) == 0;
+    if (lane == 0) {
+      a.g_flag[g] = all ? 1u : 0u;
+      a.g_pend[g] = pend;
+      a.g_act[g] = act;
+      a.g_msg[g] = msg;
+      a.g_ticket[g] = 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_flag = atomicAdd(&ctl->ticket, 1u) == a.G - 1;
+  }
+  __syncthreads();
+  if (!s_flag) return;
+  __threadfence();
+  uint64_t pp = 0, aa = 0, mm = 0;
+  uint32_t all = 1;
+  for (uint32_t h = threadIdx.x; h < a.G; h += 256) {
+    pp += __hip_atomic_load(&a.g_pend[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    aa += __hip_atomic_load(&a.g_act[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    mm += __hip_atomic_load(&a.g_msg[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    all &= __hip_atomic_load(&a.g_flag[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  pp = block_sum256(pp);
+  aa = block_sum256(aa);
+  mm = block_sum256(mm);
+  all = block_sum256(all);
+  if (threadIdx.x == 0) {
+    ctl->ticket = 0;
+    if (kind == 2) {
+      ctl->mode = 0;
+      return;
+    }
+    const bool done = all == 256;
+    ctl->rounds += (uint64_t)count_round;
+    ctl->activations += aa;
+    ctl->messages += mm;
+    ctl->done = done ? 1u : 0u;
+    ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
+    if (kind == 0) {
+      ctl->pending = pp;
+      ctl->mode = (!done && pp >= a.pull_min) ? 1u : 0u;
+    }
+  }
+}
+
+// Residual of a sparse round (or of the state at the start of a run): FP64
+// sums of |dv| per instance and the union pending count, one block per
+// residual item. After the claim that opens the dense phase it only counts
+// the round and switches to fused rounds.
 __global__ __launch_bounds__(256) void k_bresidual(BArgs a, int count_round) {
   BCtl* ctl = a.ctl;
-  if (bhalted(ctl)) return;
+  if (bhalted(ctl) || ctl->mode == 2) return;
+  if (ctl->mode == 1) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctl->rounds += (uint64_t)count_round;
+      ctl->mode = 2;
+      ctl->stop = ctl->rounds >= ctl->max_rounds ? 1u : 0u;
+    }
+    return;
+  }
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-  __shared__ double s_r[4][kR];
-  __shared__ uint32_t s_last;
+  __shared__ double s_w[4][kR];
   double r = 0.0;
   uint64_t pend = 0;
   const uint32_t it = blockIdx.x;
@@ -291,50 +386,228 @@ __global__ __launch_bounds__(256) void k_bresidual(BArgs a, int count_round) {
     r += fabs((double)x);
     pend += __ballot(x != 0.0f) != 0 ? 1 : 0;
   }
-  s_r[wave][lane] = r;
+  s_w[wave][lane] = r;
   pend = (lane == 0) ? pend : 0;
   pend = block_sum256(pend);
-  __syncthreads();
   if (threadIdx.x < kR)
     a.part_r[(uint64_t)it * kR + threadIdx.x] =
-        s_r[0][threadIdx.x] + s_r[1][threadIdx.x] + s_r[2][threadIdx.x] + s_r[3][threadIdx.x];
+        ((s_w[0][threadIdx.x] + s_w[1][threadIdx.x]) + s_w[2][threadIdx.x]) + s_w[3][threadIdx.x];
   if (threadIdx.x == 0) {
     a.part_p[it] = pend;
-    __threadfence();
-    s_last = atomicAdd(&ctl->ticket, 1u) == a.n_res - 1;
+    a.part_fa[it] = 0;
+    a.part_fm[it] = 0;
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  // per instance: sum the items of its graph in order
-  uint32_t all_done = 1;
-  for (uint32_t q = threadIdx.x; q < a.G * kR; q += 256) {
-    const uint32_t g = q / kR, rr = q % kR;
-    double s = 0.0;
-    for (uint32_t k = a.g_first_item[g]; k < a.g_first_item[g + 1]; ++k)
-      s += __hip_atomic_load(&a.part_r[(uint64_t)k * kR + rr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a.inst_r[q] = s;
-    if (!a.done[q] && s <= ctl->eps) a.done[q] = 1;
-    all_done &= a.done[q];
-  }
-  uint64_t pp = 0;
-  for (uint32_t k = threadIdx.x; k < a.n_res; k += 256)
-    pp += __hip_atomic_load(&a.part_p[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  pp = block_sum256(pp);
-  all_done = block_sum256(all_done);
-  if (threadIdx.x == 0) {
-    ctl->rounds += (uint64_t)count_round;
-    ctl->pending = pp;
-    const bool done = all_done == 256;
-    ctl->done = done ? 1u : 0u;
-    ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
-    ctl->pull = pp >= a.pull_min ? 1u : 0u;
-    ctl->ticket = 0;
+  retire_item(a, a.rg[it], 0, count_round);
+}
+
+// Dense phase, hub targets (in-degree > hub_deg): one item per (target, chunk
+// of kBChunk in-edges) adds the previous round's message bases into dv, for
+// the instances whose messages are not yet all delivered; atomics where a
+// target has several chunks.
+template <int LPV>
+__global__ __launch_bounds__(256) void k_bhub(BArgs a, int final_pass) {
+  constexpr int W = kR / LPV;
+  constexpr int IPB = 256 / LPV;
+  BCtl* ctl = a.ctl;
+  if (!final_pass && (bhalted(ctl) || ctl->mode != 2)) return;
+  const float* mu_in = mu_of_round(a, ctl->rounds - 1);
+  const uint32_t sub = threadIdx.x / LPV;
+  const uint32_t r0 = (threadIdx.x % LPV) * W;
+  for (uint64_t base = (uint64_t)blockIdx.x * IPB; base < a.n_hub; base += (uint64_t)gridDim.x * IPB) {
+    const uint64_t i = base + sub;
+    if (i >= a.n_hub) continue;
+    const uint32_t t = a.ht[i];
+    const uint8_t* st = a.done + (uint64_t)a.gid[t] * kR + r0;
+    bool live[W], any = false;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      live[k] = st[k] != 2;
+      any |= live[k];
+    }
+    if (!any) continue;
+    const uint32_t beg = a.rowT[t] + a.hc[i] * kBChunk;
+    const uint32_t end = min(a.rowT[t + 1], beg + kBChunk);
+    float acc[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) acc[k] = 0.0f;
+    uint32_t p = beg;
+    for (; p + 3 < end; p += 4) {
+      const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
+      float x0[W], x1[W], x2[W], x3[W];
+      vload<W>(mu_in + (uint64_t)s0 * kR + r0, x0);
+      vload<W>(mu_in + (uint64_t)s1 * kR + r0, x1);
+      vload<W>(mu_in + (uint64_t)s2 * kR + r0, x2);
+      vload<W>(mu_in + (uint64_t)s3 * kR + r0, x3);
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc[k] += (x0[k] + x1[k]) + (x2[k] + x3[k]);
+    }
+    for (; p < end; ++p) {
+      float x[W];
+      vload<W>(mu_in + (uint64_t)a.srcT[p] * kR + r0, x);
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc[k] += x[k];
+    }
+    float* dst = a.dv + (uint64_t)t * kR + r0;
+    if (a.rowT[t + 1] - a.rowT[t] <= kBChunk) {
+      float d[W];
+      vload<W>(dst, d);
+#pragma unroll
+      for (int k = 0; k < W; ++k)
+        if (live[k]) d[k] += acc[k];
+      vstore<W>(dst, d);
+    } else {
+#pragma unroll
+      for (int k = 0; k < W; ++k)
+        if (live[k] && acc[k] != 0.0f) unsafeAtomicAdd(dst + k, acc[k]);
+    }
   }
 }
 
+// Fused dense round, one block per residual item (a vertex range inside one
+// graph), LPV lanes per vertex. Per vertex and running instance: deliver the
+// previous round's messages by pulling over in-edges (hubs: take dv, filled
+// by k_bhub), add |d| to the item's residual, then claim: fold d into v and
+// publish alpha d / outdeg as this round's message base (renumbered order,
+// ping-pong buffer). Instances finished at the previous check get their last
+// messages delivered into dv; instances delivered earlier are skipped.
+// final_pass: delivery only, after a stop in the dense phase.
+template <int LPV, bool KAHAN>
+__global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
+  constexpr int W = kR / LPV;
+  constexpr int VPB = 256 / LPV;
+  __shared__ double s_part[VPB][kR];
+  BCtl* ctl = a.ctl;
+  if (!final_pass && (bhalted(ctl) || ctl->mode != 2)) return;
+  const uint32_t it = a.item_order[blockIdx.x];
+  if (it == ~0u) return;
+  const uint32_t g = a.rg[it];
+  const uint64_t t = ctl->rounds;
+  const float* mu_in = mu_of_round(a, t - 1);
+  float* mu_out = mu_of_round(a, t);
+  const uint32_t sub = threadIdx.x / LPV;
+  const uint32_t r0 = (threadIdx.x % LPV) * W;
+  uint8_t st[W];
+  bool run_any = false, one_any = false;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    st[k] = a.done[(uint64_t)g * kR + r0 + k];
+    if (final_pass && st[k] == 0) st[k] = 1;  // deliver only
+    run_any |= st[k] == 0;
+    one_any |= st[k] == 1;
+  }
+  const bool mine = run_any || one_any;
+  double racc[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) racc[k] = 0.0;
+  uint64_t act = 0, msg = 0;
+  if (__syncthreads_or(mine)) {
+    for (uint64_t x = a.rlo[it] + sub; x < a.rhi[it]; x += VPB) {
+      if (!mine) continue;
+      const uint64_t j = a.vord[x];
+      const uint32_t b0 = a.rowT[j], b1 = a.rowT[j + 1];
+      const bool hub = b1 - b0 > a.hub_deg;
+      float* dvp = a.dv + j * kR + r0;
+      float old[W], d[W], vv[W], cc[W];
+      // the state is loaded before the gathers so that its latency overlaps
+      // theirs (in dense rounds nearly every running lane claims)
+      if (run_any) {
+        vload<W>(a.v + j * kR + r0, vv);
+        if constexpr (KAHAN) vload<W>(a.c + j * kR + r0, cc);
+      }
+      if (hub || one_any) {
+        vload<W>(dvp, old);
+      } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k) old[k] = 0.0f;
+      }
+      if (hub) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) d[k] = old[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k) d[k] = 0.0f;
+        uint32_t p = b0;
+        for (; p + 3 < b1; p += 4) {
+          const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
+          float x0[W], x1[W], x2[W], x3[W];
+          vload<W>(mu_in + (uint64_t)s0 * kR + r0, x0);
+          vload<W>(mu_in + (uint64_t)s1 * kR + r0, x1);
+          vload<W>(mu_in + (uint64_t)s2 * kR + r0, x2);
+          vload<W>(mu_in + (uint64_t)s3 * kR + r0, x3);
+#pragma unroll
+          for (int k = 0; k < W; ++k) d[k] += (x0[k] + x1[k]) + (x2[k] + x3[k]);
+        }
+        for (; p < b1; ++p) {
+          float xs[W];
+          vload<W>(mu_in + (uint64_t)a.srcT[p] * kR + r0, xs);
+#pragma unroll
+          for (int k = 0; k < W; ++k) d[k] += xs[k];
+        }
+      }
+      bool cl[W], claim_any = false;
+      uint32_t nclaim = 0;
+      float nd[W];
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        if (st[k] != 2) racc[k] += fabs((double)d[k]);
+        cl[k] = st[k] == 0 && d[k] != 0.0f;
+        claim_any |= cl[k];
+        nclaim += cl[k] ? 1u : 0u;
+        nd[k] = st[k] == 2 ? old[k] : (st[k] == 1 ? d[k] : 0.0f);
+      }
+      if (hub || one_any) vstore<W>(dvp, nd);
+      if (claim_any) {
+        if constexpr (KAHAN) {
+#pragma clang fp contract(off)
+#pragma unroll
+          for (int k = 0; k < W; ++k) {
+            if (cl[k]) {
+              const float y = d[k] - cc[k];
+              const float s = vv[k] + y;
+              cc[k] = (s - vv[k]) - y;
+              vv[k] = s;
+            }
+          }
+          vstore<W>(a.c + j * kR + r0, cc);
+        } else {
+#pragma unroll
+          for (int k = 0; k < W; ++k)
+            if (cl[k]) vv[k] += d[k];
+        }
+        vstore<W>(a.v + j * kR + r0, vv);
+      }
+      if (run_any) {
+        const uint32_t deg = a.row[j + 1] - a.row[j];
+        const double coef = deg ? a.alpha / (double)deg : 0.0;
+        float mu[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) mu[k] = cl[k] ? (float)(coef * (double)d[k]) : 0.0f;
+        vstore<W>(mu_out + (uint64_t)a.perm[j] * kR + r0, mu);
+        act += nclaim;
+        msg += (uint64_t)nclaim * deg;
+      }
+    }
+  }
+  // per-lane residual of the item: sum over the block's vertex groups in order
+#pragma unroll
+  for (int k = 0; k < W; ++k) s_part[sub][r0 + k] = racc[k];
+  act = block_sum256(act);
+  msg = block_sum256(msg);
+  if (threadIdx.x < kR) {
+    double sr = 0.0;
+    for (int u = 0; u < VPB; ++u) sr += s_part[u][threadIdx.x];
+    a.part_r[(uint64_t)it * kR + threadIdx.x] = sr;
+  }
+  if (threadIdx.x == 0) {
+    a.part_p[it] = 0;
+    a.part_fa[it] = act;
+    a.part_fm[it] = msg;
+  }
+  retire_item(a, g, final_pass ? 2 : 1, 1);
+}
+
 __global__ void k_bstats(BArgs a, uint32_t nblocks) {
-  if (bhalted(a.ctl)) return;
+  if (bhalted(a.ctl) || a.ctl->mode == 2) return;
   uint64_t s = 0, m = 0;
   for (uint32_t i = threadIdx.x; i < nblocks; i += 256) {
     s += a.part_a[i];
@@ -351,7 +624,8 @@ __global__ void k_bstats(BArgs a, uint32_t nblocks) {
 __global__ void k_binit(BCtl* ctl, double eps, uint64_t max_rounds) {
   ctl->done = 0;
   ctl->stop = 0;
-  ctl->pull = 0;
+  ctl->mode = 0;
+  ctl->prev_all_done = 0;
   ctl->ticket = 0;
   ctl->rounds = 0;
   ctl->max_rounds = max_rounds;
@@ -391,8 +665,8 @@ static uint32_t bgrid(uint64_t count, uint32_t block = 256) {
 using namespace daic;
 
 struct BTune {
-  int lpv_claim = 16, lpv_pull = 16, lpv_push = 16;
-  uint32_t grid_claim = 4096, grid_pull = 8192, grid_push = 8192;
+  int lpv_claim = 16, lpv_fused = 16, lpv_push = 16;
+  uint32_t grid_claim = 4096, grid_hub = 2048, grid_push = 8192;
 };
 
 struct daic_batch {
@@ -435,12 +709,22 @@ static void enqueue_claim(daic_batch* b, hipStream_t s) {
   hipLaunchKernelGGL(k_bstats, dim3(1), dim3(256), 0, s, b->a, b->tune.grid_claim);
 }
 
-static void enqueue_pull(daic_batch* b, hipStream_t s) {
-  const int l = b->tune.lpv_pull;
-  const uint32_t g = b->tune.grid_pull;
-  if (l == 16) hipLaunchKernelGGL(k_bpull<16>, dim3(g), dim3(256), 0, s, b->a);
-  else if (l == 32) hipLaunchKernelGGL(k_bpull<32>, dim3(g), dim3(256), 0, s, b->a);
-  else hipLaunchKernelGGL(k_bpull<64>, dim3(g), dim3(256), 0, s, b->a);
+template <int LPV>
+static void launch_dense(daic_batch* b, hipStream_t s, int final_pass) {
+  if (b->a.n_hub) hipLaunchKernelGGL(k_bhub<LPV>, dim3(b->tune.grid_hub), dim3(256), 0, s, b->a, final_pass);
+  if (b->kahan)
+    hipLaunchKernelGGL((k_bfused<LPV, true>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
+  else
+    hipLaunchKernelGGL((k_bfused<LPV, false>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
+}
+
+// Dense-phase round (hub sums, then the fused pass); both kernels return at
+// once outside the dense phase.
+static void enqueue_dense(daic_batch* b, hipStream_t s, int final_pass) {
+  const int l = b->tune.lpv_fused;
+  if (l == 16) launch_dense<16>(b, s, final_pass);
+  else if (l == 32) launch_dense<32>(b, s, final_pass);
+  else launch_dense<64>(b, s, final_pass);
 }
 
 static void enqueue_push(daic_batch* b, hipStream_t s) {
@@ -450,10 +734,12 @@ static void enqueue_push(daic_batch* b, hipStream_t s) {
   else hipLaunchKernelGGL(k_bpush<64>, dim3(g), dim3(256), 0, s, b->a);
 }
 
+// One round in whichever mode the control block holds: sparse (claim, push,
+// residual), the claim that opens the dense phase, or a fused dense round.
 static void enqueue_round(daic_batch* b, hipStream_t s) {
   enqueue_claim(b, s);
-  enqueue_pull(b, s);
   enqueue_push(b, s);
+  enqueue_dense(b, s, 0);
   hipLaunchKernelGGL(k_bresidual, dim3(b->a.n_res), dim3(256), 0, s, b->a, 1);
 }
 
@@ -568,40 +854,39 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
   BGRAB(dv, float*, SV);
   if (b->kahan) BGRAB(c, float*, SV);
   BGRAB(mu, float*, SV);
+  BGRAB(mu2, float*, SV);
   BGRAB(active, uint8_t*, N);
   BGRAB(done, uint8_t*, (size_t)n_graphs * kR);
   BGRAB(inst_r, double*, (size_t)n_graphs * kR * 8);
-  // pull items: every target with in-edges, chunks of kBChunk, ordered by
-  // in-degree class so that the targets of a block loop about equally
+  std::vector<uint32_t> rt(N + 1);
   {
-    std::vector<uint32_t> rt(N + 1);
+    // hub items: targets with in-degree > hub_deg, chunks of kBChunk
+    // in-edges, longest first
+    a.hub_deg = kHubDeg;
+    if (const char* e = std::getenv("DAIC_HUB_DEG")) a.hub_deg = (uint32_t)std::max(1L, std::atol(e));
     DAIC_HIP(hipMemcpy(rt.data(), ug->pull.rowT, (N + 1) * 4, hipMemcpyDeviceToHost));
-    std::vector<std::vector<uint32_t>> cls(12);
-    for (uint64_t t = 0; t < N; ++t) {
-      uint32_t deg = rt[t + 1] - rt[t];
-      if (!deg) continue;
-      uint32_t c = 0;
-      while (c < 11 && (1u << c) < deg) ++c;
-      cls[c].push_back((uint32_t)t);
-    }
-    std::vector<uint32_t> pt, pc, pn;
-    for (auto& cl : cls)
-      for (uint32_t t : cl) {
-        uint32_t deg = rt[t + 1] - rt[t];
-        uint32_t nch = (deg + kBChunk - 1) / kBChunk;
-        for (uint32_t c = 0; c < nch; ++c) {
-          pt.push_back(t);
-          pc.push_back(c);
-          pn.push_back(nch);
-        }
+    std::vector<uint32_t> ht, hc;
+    {
+      std::vector<std::pair<uint32_t, uint64_t>> items;  // (length, target << 32 | chunk)
+      for (uint64_t t = 0; t < N; ++t) {
+        const uint32_t deg = rt[t + 1] - rt[t];
+        if (deg <= a.hub_deg) continue;
+        for (uint32_t c = 0; c * kBChunk < deg; ++c)
+          items.push_back({std::min(kBChunk, deg - c * kBChunk), (t << 32) | c});
       }
-    a.n_pull = pt.size();
-    BGRAB(pt, const uint32_t*, pt.size() * 4);
-    BGRAB(pc, const uint32_t*, pc.size() * 4);
-    BGRAB(pn, const uint32_t*, pn.size() * 4);
-    DAIC_HIP(hipMemcpy((void*)a.pt, pt.data(), pt.size() * 4, hipMemcpyHostToDevice));
-    DAIC_HIP(hipMemcpy((void*)a.pc, pc.data(), pc.size() * 4, hipMemcpyHostToDevice));
-    DAIC_HIP(hipMemcpy((void*)a.pn, pn.data(), pn.size() * 4, hipMemcpyHostToDevice));
+      std::stable_sort(items.begin(), items.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+      for (auto& it : items) {
+        ht.push_back((uint32_t)(it.second >> 32));
+        hc.push_back((uint32_t)it.second);
+      }
+    }
+    a.n_hub = ht.size();
+    BGRAB(ht, const uint32_t*, ht.size() * 4);
+    BGRAB(hc, const uint32_t*, hc.size() * 4);
+    if (!ht.empty()) {
+      DAIC_HIP(hipMemcpy((void*)a.ht, ht.data(), ht.size() * 4, hipMemcpyHostToDevice));
+      DAIC_HIP(hipMemcpy((void*)a.hc, hc.data(), hc.size() * 4, hipMemcpyHostToDevice));
+    }
     // push items: every vertex with out-edges, chunks of kPushChunk
     std::vector<uint32_t> ro(N + 1);
     DAIC_HIP(hipMemcpy(ro.data(), urow, (N + 1) * 4, hipMemcpyDeviceToHost));
@@ -618,24 +903,49 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
     BGRAB(sc, const uint32_t*, sc.size() * 4);
     DAIC_HIP(hipMemcpy((void*)a.sv, sv.data(), sv.size() * 4, hipMemcpyHostToDevice));
     DAIC_HIP(hipMemcpy((void*)a.sc, sc.data(), sc.size() * 4, hipMemcpyHostToDevice));
-    // residual items: chunks of kResChunk vertices inside each graph
+    // residual items: vertex ranges inside each graph, closed at kResChunk
+    // vertices or kItemWork work (in-edges pulled in the fused pass plus a
+    // per-vertex share for the claim), whichever comes first, so that the
+    // in-edge-heavy low ids of an RMAT graph do not form one long item
     std::vector<uint32_t> rg, gfi;
-    std::vector<uint64_t> rlo, rhi;
+    std::vector<uint64_t> rlo, rhi, rw;
     for (uint32_t g = 0; g < n_graphs; ++g) {
       gfi.push_back((uint32_t)rg.size());
-      for (uint64_t lo = b->voff[g]; lo < b->voff[g + 1]; lo += kResChunk) {
-        rg.push_back(g);
-        rlo.push_back(lo);
-        rhi.push_back(std::min<uint64_t>(b->voff[g + 1], lo + kResChunk));
+      uint64_t lo = b->voff[g], w = 0;
+      for (uint64_t j = b->voff[g]; j < b->voff[g + 1]; ++j) {
+        const uint32_t deg = rt[j + 1] - rt[j];
+        w += (deg > a.hub_deg ? 0 : deg) + kVertexWork;
+        if (j + 1 - lo >= kResChunk || w >= kItemWork || j + 1 == b->voff[g + 1]) {
+          rg.push_back(g);
+          rlo.push_back(lo);
+          rhi.push_back(j + 1);
+          rw.push_back(w);
+          lo = j + 1;
+          w = 0;
+        }
       }
       if (b->voff[g] == b->voff[g + 1]) {  // empty graph: one empty item keeps the layout simple
         rg.push_back(g);
         rlo.push_back(b->voff[g]);
         rhi.push_back(b->voff[g]);
+        rw.push_back(0);
       }
     }
     gfi.push_back((uint32_t)rg.size());
     a.n_res = (uint32_t)rg.size();
+    // fused-pass visiting order inside each item: by pulled in-degree,
+    // descending, so that the vertices a wave takes together loop about
+    // equally long over their in-edges
+    {
+      std::vector<uint32_t> vord(N);
+      for (uint64_t j = 0; j < N; ++j) vord[j] = (uint32_t)j;
+      auto pulled = [&](uint32_t j) { const uint32_t d = rt[j + 1] - rt[j]; return d > a.hub_deg ? 0u : d; };
+      for (size_t k = 0; k < rlo.size(); ++k)
+        std::stable_sort(vord.begin() + rlo[k], vord.begin() + rhi[k],
+                         [&](uint32_t x, uint32_t y) { return pulled(x) > pulled(y); });
+      BGRAB(vord, const uint32_t*, std::max<size_t>(N, 1) * 4);
+      if (N) DAIC_HIP(hipMemcpy((void*)a.vord, vord.data(), N * 4, hipMemcpyHostToDevice));
+    }
     BGRAB(rg, const uint32_t*, rg.size() * 4);
     BGRAB(rlo, const uint64_t*, rlo.size() * 8);
     BGRAB(rhi, const uint64_t*, rhi.size() * 8);
@@ -646,7 +956,42 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
     DAIC_HIP(hipMemcpy((void*)a.g_first_item, gfi.data(), gfi.size() * 4, hipMemcpyHostToDevice));
     BGRAB(part_r, double*, (size_t)a.n_res * kR * 8);
     BGRAB(part_p, uint64_t*, (size_t)a.n_res * 8);
+    BGRAB(part_fa, uint64_t*, (size_t)a.n_res * 8);
+    BGRAB(part_fm, uint64_t*, (size_t)a.n_res * 8);
+    // Fused-pass block order. Workgroups go to the 8 XCDs round-robin by
+    // block index and each XCD has its own L2, so every graph is given to one
+    // XCD (largest graphs first, to the least loaded XCD by in-edges) and its
+    // items take that XCD's block slots.
+    constexpr uint32_t kXcd = 8;
+    std::vector<uint64_t> gw(n_graphs, 0);
+    for (uint32_t g = 0; g < n_graphs; ++g) gw[g] = rt[b->voff[g + 1]] - rt[b->voff[g]] + (b->voff[g + 1] - b->voff[g]);
+    std::vector<uint32_t> gorder(n_graphs);
+    for (uint32_t g = 0; g < n_graphs; ++g) gorder[g] = g;
+    std::stable_sort(gorder.begin(), gorder.end(), [&](uint32_t x, uint32_t y) { return gw[x] > gw[y]; });
+    std::vector<std::vector<uint32_t>> bins(kXcd);
+    std::vector<uint64_t> load(kXcd, 0);
+    for (uint32_t g : gorder) {
+      const uint32_t x = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[x] += gw[g];
+      for (uint32_t k = gfi[g]; k < gfi[g + 1]; ++k) bins[x].push_back(k);
+    }
+    // heaviest items first within each XCD, so that the long ones start early
+    for (auto& bn : bins)
+      std::stable_sort(bn.begin(), bn.end(), [&](uint32_t x, uint32_t y) { return rw[x] > rw[y]; });
+    size_t longest = 0;
+    for (auto& bn : bins) longest = std::max(longest, bn.size());
+    std::vector<uint32_t> order(longest * kXcd, ~0u);
+    for (uint32_t x = 0; x < kXcd; ++x)
+      for (size_t i = 0; i < bins[x].size(); ++i) order[i * kXcd + x] = bins[x][i];
+    a.n_fused_blocks = (uint32_t)order.size();
+    BGRAB(item_order, const uint32_t*, order.size() * 4);
+    DAIC_HIP(hipMemcpy((void*)a.item_order, order.data(), order.size() * 4, hipMemcpyHostToDevice));
   }
+  BGRAB(g_ticket, uint32_t*, (size_t)n_graphs * 4);
+  BGRAB(g_flag, uint32_t*, (size_t)n_graphs * 4);
+  BGRAB(g_pend, uint64_t*, (size_t)n_graphs * 8);
+  BGRAB(g_act, uint64_t*, (size_t)n_graphs * 8);
+  BGRAB(g_msg, uint64_t*, (size_t)n_graphs * 8);
   BGRAB(part_a, uint64_t*, 8192 * 8);
   BGRAB(part_m, uint64_t*, 8192 * 8);
 #undef BGRAB
@@ -658,7 +1003,9 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
   DAIC_HIP(hipMemsetAsync(a.dv, 0, SV, s));
   if (a.c) DAIC_HIP(hipMemsetAsync(a.c, 0, SV, s));
   DAIC_HIP(hipMemsetAsync(a.mu, 0, SV, s));
+  DAIC_HIP(hipMemsetAsync(a.mu2, 0, SV, s));
   DAIC_HIP(hipMemsetAsync(a.active, 0, N, s));
+  DAIC_HIP(hipMemsetAsync(a.g_ticket, 0, (size_t)n_graphs * 4, s));
   DAIC_HIP(hipMemsetAsync(a.done, 0, (size_t)n_graphs * kR, s));
   hipLaunchKernelGGL(k_binit, dim3(1), dim3(1), 0, s, a.ctl, 0.0, ~0ull);
   DAIC_HIP(hipHostMalloc((void**)&b->h_ctl, sizeof(BCtl), hipHostMallocDefault));
@@ -692,16 +1039,17 @@ daic_status daic_batch_set_init(daic_batch* b, uint32_t graph, const double* v0,
   return DAIC_OK;
 }
 
-// Autotuner: times the dense-round kernels (claim and pull) for each lanes-per-
-// vertex and grid size on the current state, which it saves and restores, and
-// keeps the fastest. With DAIC_TUNE_CACHE set, choices are read from and
-// appended to that file, keyed by the union graph's shape.
+// Autotuner: times the claim kernel (sparse rounds and the claim that opens
+// the dense phase) and the dense round (hub sums and fused pass) for each
+// lanes-per-vertex and grid size on the current state, which it saves and
+// restores, and keeps the fastest. With DAIC_TUNE_CACHE set, choices are read
+// from and appended to that file, keyed by the union graph's shape.
 daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len) {
   if (!b) return fail(DAIC_E_INVALID, "null batch");
   hipStream_t s = b->stream;
   BArgs& a = b->a;
   char key[160];
-  std::snprintf(key, sizeof key, "batch N=%llu M=%llu G=%u kahan=%d", (unsigned long long)a.N,
+  std::snprintf(key, sizeof key, "batch-fused N=%llu M=%llu G=%u kahan=%d", (unsigned long long)a.N,
                 (unsigned long long)b->ug->dev.m, b->G, (int)b->kahan);
   const char* cache = std::getenv("DAIC_TUNE_CACHE");
   if (cache) {
@@ -710,8 +1058,8 @@ daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len) {
       while (std::fgets(line, sizeof line, f)) {
         if (std::strncmp(line, key, std::strlen(key)) != 0) continue;
         BTune t;
-        if (std::sscanf(line + std::strlen(key), " : %d %d %d %u %u %u", &t.lpv_claim, &t.lpv_pull, &t.lpv_push,
-                        &t.grid_claim, &t.grid_pull, &t.grid_push) == 6) {
+        if (std::sscanf(line + std::strlen(key), " : %d %d %d %u %u %u", &t.lpv_claim, &t.lpv_fused, &t.lpv_push,
+                        &t.grid_claim, &t.grid_hub, &t.grid_push) == 6) {
           b->tune = t;
           b->tuned = true;
         }
@@ -721,23 +1069,38 @@ daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len) {
   }
   if (!b->tuned) {
     const size_t SV = a.N * (size_t)kR * 4;
+    const size_t SD = (size_t)b->G * kR;
     float *sv = nullptr, *sd = nullptr, *sc = nullptr;
     DAIC_HIP(hipMalloc(&sv, SV));
     DAIC_HIP(hipMalloc(&sd, SV));
     if (a.c) DAIC_HIP(hipMalloc(&sc, SV));
+    std::vector<uint8_t> done_save(SD);
     DAIC_HIP(hipMemcpyAsync(sv, a.v, SV, hipMemcpyDeviceToDevice, s));
     DAIC_HIP(hipMemcpyAsync(sd, a.dv, SV, hipMemcpyDeviceToDevice, s));
     if (sc) DAIC_HIP(hipMemcpyAsync(sc, a.c, SV, hipMemcpyDeviceToDevice, s));
-    auto restore = [&]() -> hipError_t {
+    DAIC_HIP(hipMemcpyAsync(done_save.data(), a.done, SD, hipMemcpyDeviceToHost, s));
+    DAIC_HIP(hipStreamSynchronize(s));
+    // control blocks for the timed kernels: the opening claim (mode 1,
+    // round 0) and a fused round (mode 2, round 1, reading the bases the
+    // claim published); every instance running
+    BCtl c_claim{}, c_dense{};
+    c_claim.max_rounds = c_dense.max_rounds = ~0ull;
+    c_claim.mode = 1;
+    c_dense.mode = 2;
+    c_dense.rounds = 1;
+    auto restore = [&](const BCtl* c) -> hipError_t {
       hipError_t e = hipMemcpyAsync(a.v, sv, SV, hipMemcpyDeviceToDevice, s);
       if (e == hipSuccess) e = hipMemcpyAsync(a.dv, sd, SV, hipMemcpyDeviceToDevice, s);
       if (e == hipSuccess && sc) e = hipMemcpyAsync(a.c, sc, SV, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = hipMemsetAsync(a.done, 0, SD, s);
+      if (e == hipSuccess && c) e = hipMemcpyAsync(a.ctl, c, sizeof(BCtl), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
       return e;
     };
-    auto time_it = [&](auto&& enqueue) -> float {
+    auto time_it = [&](const BCtl* c, auto&& enqueue) -> float {
       float best = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
-        (void)restore();
+        (void)restore(c);
         (void)hipEventRecord(b->ev0, s);
         enqueue();
         (void)hipEventRecord(b->ev1, s);
@@ -748,39 +1111,34 @@ daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len) {
       }
       return best;
     };
-    // the tuning rounds run as dense rounds on unfinished instances
-    hipLaunchKernelGGL(k_binit, dim3(1), dim3(1), 0, s, a.ctl, 0.0, ~0ull);
-    BCtl hc{};
-    hc.max_rounds = ~0ull;
-    hc.pull = 1;
-    DAIC_HIP(hipMemcpyAsync(a.ctl, &hc, sizeof hc, hipMemcpyHostToDevice, s));
-    std::vector<uint8_t> done_save((size_t)b->G * kR);
-    DAIC_HIP(hipMemcpyAsync(done_save.data(), a.done, done_save.size(), hipMemcpyDeviceToHost, s));
-    DAIC_HIP(hipStreamSynchronize(s));
-    DAIC_HIP(hipMemsetAsync(a.done, 0, done_save.size(), s));
     const int lpvs[3] = {16, 32, 64};
     const uint32_t grids[3] = {2048, 4096, 8192};
     BTune best = b->tune;
-    float best_claim = 1e30f, best_pull = 1e30f;
+    float best_claim = 1e30f, best_dense = 1e30f;
     for (int l : lpvs)
       for (uint32_t g : grids) {
         b->tune.lpv_claim = l;
         b->tune.grid_claim = g;
-        float t = time_it([&] { enqueue_claim(b, s); });
+        float t = time_it(&c_claim, [&] { enqueue_claim(b, s); });
         if (t < best_claim) { best_claim = t; best.lpv_claim = l; best.grid_claim = g; }
       }
+    // the dense round reads the bases published by the chosen claim
     b->tune.lpv_claim = best.lpv_claim;
     b->tune.grid_claim = best.grid_claim;
+    (void)restore(&c_claim);
+    enqueue_claim(b, s);
+    DAIC_HIP(hipStreamSynchronize(s));
     for (int l : lpvs)
-      for (uint32_t g : grids) {
-        b->tune.lpv_pull = l;
-        b->tune.grid_pull = g;
-        float t = time_it([&] { enqueue_pull(b, s); });
-        if (t < best_pull) { best_pull = t; best.lpv_pull = l; best.grid_pull = g; }
+      for (uint32_t g : {1024u, 4096u}) {
+        b->tune.lpv_fused = l;
+        b->tune.grid_hub = g;
+        float t = time_it(&c_dense, [&] { enqueue_dense(b, s, 0); });
+        if (t < best_dense) { best_dense = t; best.lpv_fused = l; best.grid_hub = g; }
       }
     b->tune = best;
-    DAIC_HIP(restore());
-    DAIC_HIP(hipMemcpyAsync(a.done, done_save.data(), done_save.size(), hipMemcpyHostToDevice, s));
+    DAIC_HIP(restore(nullptr));
+    DAIC_HIP(hipMemcpy(a.done, done_save.data(), SD, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_binit, dim3(1), dim3(1), 0, s, a.ctl, 0.0, ~0ull);
     DAIC_HIP(hipStreamSynchronize(s));
     (void)hipFree(sv);
     (void)hipFree(sd);
@@ -788,8 +1146,8 @@ daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len) {
     b->tuned = true;
     if (cache) {
       if (FILE* f = std::fopen(cache, "a")) {
-        std::fprintf(f, "%s : %d %d %d %u %u %u\n", key, best.lpv_claim, best.lpv_pull, best.lpv_push,
-                     best.grid_claim, best.grid_pull, best.grid_push);
+        std::fprintf(f, "%s : %d %d %d %u %u %u\n", key, best.lpv_claim, best.lpv_fused, best.lpv_push,
+                     best.grid_claim, best.grid_hub, best.grid_push);
         std::fclose(f);
       }
     }
@@ -799,8 +1157,9 @@ daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len) {
     }
   }
   if (desc && desc_len) {
-    std::snprintf(desc, desc_len, "claim lanes/vertex %d grid %u; pull lanes/vertex %d grid %u; push lanes/vertex %d grid %u",
-                  b->tune.lpv_claim, b->tune.grid_claim, b->tune.lpv_pull, b->tune.grid_pull, b->tune.lpv_push,
+    std::snprintf(desc, desc_len,
+                  "claim lanes/vertex %d grid %u; dense round lanes/vertex %d hub grid %u; push lanes/vertex %d grid %u",
+                  b->tune.lpv_claim, b->tune.grid_claim, b->tune.lpv_fused, b->tune.grid_hub, b->tune.lpv_push,
                   b->tune.grid_push);
   }
   return DAIC_OK;
@@ -841,6 +1200,12 @@ daic_status daic_batch_run(daic_batch* b, const daic_run_opts* o, daic_stats* st
     DAIC_HIP(hipMemcpyAsync(b->h_ctl, a.ctl, sizeof(BCtl), hipMemcpyDeviceToHost, s));
     DAIC_HIP(hipStreamSynchronize(s));
     if (b->h_ctl->done || b->h_ctl->stop) break;
+  }
+  if (!b->h_ctl->done && b->h_ctl->mode == 2) {
+    // stopped in the dense phase: deliver the last round's messages
+    enqueue_dense(b, s, 1);
+    DAIC_HIP(hipMemcpyAsync(b->h_ctl, a.ctl, sizeof(BCtl), hipMemcpyDeviceToHost, s));
+    DAIC_HIP(hipStreamSynchronize(s));
   }
   DAIC_HIP(hipEventRecord(b->ev1, s));
   DAIC_HIP(hipEventSynchronize(b->ev1));

@@ -108,3 +108,55 @@ def test_batched_max_rounds_and_resume(daic):
     assert res.converged and np.all(inst <= 1e-8)
     ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1[:, 3], eps=1e-14)
     assert np.abs(b.get(0)[:, 3] - ref).sum() <= 1e-5 * ref.sum()
+
+
+def hub_graph(n=5000):
+    """A ring plus three hub targets: every vertex points at 0 and 1 and every
+    even vertex at 2, so in-degrees span one to five 1024-edge chunks."""
+    i = np.arange(n)
+    src = np.concatenate([i, i[i != 0], i[i != 1], i[(i % 2 == 0) & (i != 2)]])
+    dst = np.concatenate([(i + 1) % n, np.zeros(n - 1, np.int64), np.ones(n - 1, np.int64),
+                          np.full(((i % 2 == 0) & (i != 2)).sum(), 2)])
+    return daic_gen.from_edges(n, src, dst)
+
+
+@pytest.mark.parametrize("state", ["f32", "f32_kahan"])
+def test_batched_hub_targets_match_oracle(daic, state):
+    """Dense rounds with hub targets (in-degree above 1024, summed in chunks
+    with atomics before the fused pass) next to an RMAT graph."""
+    say("case batch hubs", state)
+    d = 0.85
+    gs = [hub_graph(), daic_gen.rmat(11, 8, seed=3)]
+    b = daic.Batch([daic.Graph(g.row_ptr, g.col) for g in gs], 64, alpha=d, state=state)
+    inits = [ppr_inputs(g, 9, 64 * i, 64, d) for i, g in enumerate(gs)]
+    for i, g in enumerate(gs):
+        b.set_init(i, np.zeros((g.n, 64)), inits[i])
+    res, inst = b.run(eps=1e-7, rounds_per_check=8)
+    assert res.converged and np.all(inst <= 1e-7)
+    for i, g in enumerate(gs):
+        v = b.get(i)
+        for r in (0, 13, 63):
+            ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, inits[i][:, r], eps=1e-14)
+            assert np.abs(v[:, r] - ref).sum() <= 1e-5 * np.abs(ref).sum(), (i, r)
+
+
+def test_batched_stop_in_dense_phase_delivers(daic):
+    """Runs stopped by max_rounds in the dense phase (messages of the last
+    claim still in flight) deliver them before returning: later runs resume
+    from a consistent state and reach the oracle's fixed point."""
+    say("case batch stop dense")
+    d = 0.85
+    g = daic_gen.rmat(12, 8, seed=41)
+    b = daic.Batch([daic.Graph(g.row_ptr, g.col)], 64, alpha=d)
+    dv1 = ppr_inputs(g, 4, 0, 64, d)
+    b.set_init(0, np.zeros((g.n, 64)), dv1)
+    for k in (2, 5):
+        res, inst = b.run(eps=1e-9, rounds_per_check=1, max_rounds=k)
+        assert res.status == daic.NOT_CONVERGED and res.stats["rounds"] == k
+        assert np.all(np.isfinite(inst)) and np.all(inst > 0)
+    res, inst = b.run(eps=1e-9, rounds_per_check=16)
+    assert res.converged and np.all(inst <= 1e-9)
+    v = b.get(0)
+    for r in (0, 31, 63):
+        ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1[:, r], eps=1e-14)
+        assert np.abs(v[:, r] - ref).sum() <= 1e-5 * ref.sum()
