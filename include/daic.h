@@ -194,14 +194,18 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
                               daic_dtype state, daic_batch** out);
 /* v0, dv1: host arrays [n_g][rhs_g] (row-major, vertex-major) in double. */
 daic_status daic_batch_set_init(daic_batch* b, uint32_t graph, const double* v0, const double* dv1);
-/* Autotuner: times the dense-round kernels for each lanes-per-vertex and grid
- * size on the current state (restored afterwards) and keeps the fastest;
- * with DAIC_TUNE_CACHE set, results are cached in that file. desc receives a
+/* Autotuner: times the claim kernel and the dense round (hub sums and fused
+ * pass) for each lanes-per-vertex and grid size on the current state
+ * (restored afterwards, finish flags included) and keeps the fastest; with
+ * DAIC_TUNE_CACHE set, results are cached in that file. desc receives a
  * description of the choice (nullable). */
 daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len);
 /* Run every instance to residual <= eps (sched ALL, q = 1). inst_residual
  * (nullable) receives the final residual of every instance, graph-major.
- * stats->final_residual is the largest instance residual. */
+ * stats->final_residual is the largest instance residual. Instances are
+ * updated until the check after the round in which their residual fell to
+ * eps, so they may end below eps; a run stopped by max_rounds returns
+ * DAIC_NOT_CONVERGED with every message delivered (a later run resumes). */
 daic_status daic_batch_run(daic_batch* b, const daic_run_opts* opts, daic_stats* stats,
                            double* inst_residual);
 /* v_out: [n_g][rhs_g] doubles (FP32 state; with Kahan, v - c). */
