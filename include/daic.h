@@ -95,13 +95,26 @@ typedef enum {
  *   LEARNED      : top ceil(q n) by priority x sigmoid(network score)
  *   ROUND_ROBIN  : the pending vertices of the next block of ceil(q n)
  *                  consecutive ids, blocks taken cyclically (static order,
- *                  Sec. 5.1 round-robin scheduling)                          */
+ *                  Sec. 5.1 round-robin scheduling)
+ *   SWEEP        : round-robin over blocks of ceil(q n) vertices taken in
+ *                  out-degree order (highest first), every pending vertex of
+ *                  the block updated, each block receiving by a pull over
+ *                  its in-edges the latest message of every in-neighbour, so
+ *                  that blocks later in a sweep already see the updates made
+ *                  earlier in it (an asynchronous activation order, Eq. async;
+ *                  q = 1 is the synchronous round). Sum problems on graphs with
+ *                  n, m < 2^31. A round is one block; the stop rule is checked
+ *                  after whole sweeps, on an upper bound of the residual (exact
+ *                  for non-negative messages); the run ends by delivering the
+ *                  messages still in flight, so the final state and residual
+ *                  are the ordinary (v, dv) ones.                            */
 typedef enum {
   DAIC_SCHED_ALL = 0,
   DAIC_SCHED_TOPK_EXACT = 1,
   DAIC_SCHED_TOPK_SAMPLED = 2,
   DAIC_SCHED_LEARNED = 3,
-  DAIC_SCHED_ROUND_ROBIN = 4
+  DAIC_SCHED_ROUND_ROBIN = 4,
+  DAIC_SCHED_SWEEP = 5
 } daic_sched;
 
 typedef struct daic_graph daic_graph;

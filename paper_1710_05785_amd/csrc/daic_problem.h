@@ -9,6 +9,10 @@
 #include "daic_internal.h"
 #include "daic_kernels.h"
 
+namespace daic {
+struct SweepState;  // per-problem state of SWEEP scheduling (built on first use)
+}
+
 // ---------------------------------------------------------------------------
 // Problem object.
 // ---------------------------------------------------------------------------
@@ -54,6 +58,7 @@ struct daic_problem {
   uint32_t* indeg = nullptr;     // in-degree of each vertex
   float* score = nullptr;        // selection multiplier of each vertex
   uint64_t learned_fallbacks = 0;  // learned rounds that handed back to exact selection
+  daic::SweepState* sweep = nullptr;
 };
 
 namespace daic {
@@ -106,5 +111,8 @@ bool get_ops(const daic_problem* p, Ops* out);
 daic_status check_opts(const daic_problem* p, const daic_run_opts* o);
 daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStream_t s);
 void apply_run_opts(daic_problem* p, const daic_run_opts* o);
+// SWEEP scheduling: the run loop, and the release of its per-problem state.
+daic_status sweep_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats, hipStream_t s);
+void sweep_release(daic_problem* p);
 
 }  // namespace daic

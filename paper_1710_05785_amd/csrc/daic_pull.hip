@@ -29,14 +29,16 @@ __global__ void k_perm_from_sorted(const uint64_t* sorted, uint64_t n, uint32_t*
   for (uint64_t r = i; r < n; r += st) perm[(uint32_t)sorted[r]] = (uint32_t)r;
 }
 
-// One thread per source row: key = (target << 32) | perm[source], value = edge.
-__global__ void k_edge_keys(const uint32_t* row, const uint32_t* col, const uint32_t* perm, uint64_t n,
-                            uint64_t* keys, uint32_t* vals) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t st = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t j = i; j < n; j += st) {
+// One wave per source row (lanes stride its out-edges, so hub rows do not
+// serialize on one thread): key = (target << 32) | perm[source], value = edge.
+__global__ __launch_bounds__(256) void k_edge_keys(const uint32_t* row, const uint32_t* col, const uint32_t* perm,
+                                                   uint64_t n, uint64_t* keys, uint32_t* vals) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t j = wave; j < n; j += nwaves) {
     const uint64_t pj = perm[j];
-    for (uint32_t e = row[j]; e < row[j + 1]; ++e) {
+    for (uint32_t e = row[j] + lane; e < row[j + 1]; e += 64) {
       keys[e] = ((uint64_t)col[e] << 32) | pj;
       vals[e] = e;
     }
@@ -131,7 +133,8 @@ daic_status pull_prepare(daic_graph* g, hipStream_t s) {
   }
   // 2. in-edges sorted by (target, renumbered source), carrying the edge index
   if (m > 0) {
-    hipLaunchKernelGGL(k_edge_keys, dim3(grid(n)), dim3(256), 0, s, row, d.col, P.perm, n, k0, v0);
+    hipLaunchKernelGGL(k_edge_keys, dim3(std::max<uint64_t>(1, std::min<uint64_t>((n + 3) / 4, 8192))), dim3(256), 0,
+                       s, row, d.col, P.perm, n, k0, v0);
     hipcub::DoubleBuffer<uint64_t> kb(k0, k1);
     hipcub::DoubleBuffer<uint32_t> vb(v0, v1);
     int end_bit = 32;

@@ -282,7 +282,7 @@ daic_status check_opts(const daic_problem* p, const daic_run_opts* o) {
   if (!(o->priority_fraction > 0.0 && o->priority_fraction <= 1.0))
     return fail(DAIC_E_INVALID, "priority_fraction must be in (0, 1]");
   if (!(o->eps >= 0.0)) return fail(DAIC_E_INVALID, "eps must be >= 0");
-  if (o->sched < DAIC_SCHED_ALL || o->sched > DAIC_SCHED_ROUND_ROBIN) return fail(DAIC_E_INVALID, "unknown sched");
+  if (o->sched < DAIC_SCHED_ALL || o->sched > DAIC_SCHED_SWEEP) return fail(DAIC_E_INVALID, "unknown sched");
   if (o->sched == DAIC_SCHED_TOPK_SAMPLED && o->n_samples > kMaxSamples)
     return fail(DAIC_E_INVALID, "n_samples must be <= %u", kMaxSamples);
   if (o->sched == DAIC_SCHED_LEARNED && !o->model) return fail(DAIC_E_INVALID, "LEARNED needs a model");
@@ -664,6 +664,7 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
   hipStream_t s = o->hip_stream ? static_cast<hipStream_t>(o->hip_stream) : p->own_stream;
   if (stats) std::memset(stats, 0, sizeof *stats);
   if (n == 0) return DAIC_OK;
+  if (o->sched == DAIC_SCHED_SWEEP) return sweep_run(p, o, stats, s);
   Ops ops;
   if (!get_ops(p, &ops)) return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");
   const uint32_t K = o->rounds_per_check ? o->rounds_per_check : 1;
@@ -815,6 +816,7 @@ daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, 
   if (!p || !out || !n_out) return fail(DAIC_E_INVALID, "null argument");
   daic_status rc = check_opts(p, o);
   if (rc) return rc;
+  if (o->sched == DAIC_SCHED_SWEEP) return fail(DAIC_E_UNSUPPORTED, "daic_profile takes the per-round rules, not SWEEP");
   apply_run_opts(p, o);
   if (o->sched == DAIC_SCHED_LEARNED) return fail(DAIC_E_UNSUPPORTED, "profile takes the plain rules");
   *n_out = 0;
@@ -885,6 +887,7 @@ daic_status daic_run_progress(daic_problem* p, const daic_run_opts* o, uint64_t 
   if (!p || !points || (max_points && (!updates || !progress))) return fail(DAIC_E_INVALID, "null argument");
   daic_status rc = check_opts(p, o);
   if (rc) return rc;
+  if (o->sched == DAIC_SCHED_SWEEP) return fail(DAIC_E_UNSUPPORTED, "daic_run_progress takes the per-round rules, not SWEEP");
   if (o->sched == DAIC_SCHED_LEARNED) return fail(DAIC_E_UNSUPPORTED, "progress traces take the plain rules");
   apply_run_opts(p, o);
   *points = 0;
@@ -945,6 +948,7 @@ daic_status daic_select_frontier(daic_problem* p, const daic_run_opts* o, uint64
   if (!p || !sel_out) return fail(DAIC_E_INVALID, "null argument");
   daic_status rc = check_opts(p, o);
   if (rc) return rc;
+  if (o->sched == DAIC_SCHED_SWEEP) return fail(DAIC_E_UNSUPPORTED, "daic_select_frontier takes the per-round rules, not SWEEP");
   apply_run_opts(p, o);
   if (o->sched == DAIC_SCHED_LEARNED) return fail(DAIC_E_UNSUPPORTED, "select_frontier takes the plain rules");
   const uint64_t n = p->g->dev.n;
@@ -1006,6 +1010,7 @@ daic_status daic_problem_get(const daic_problem* p, void* v_out, void* dv_out) {
 
 void daic_problem_destroy(daic_problem* p) {
   if (!p) return;
+  sweep_release(p);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   for (void* q : p->allocs) dfree(q);

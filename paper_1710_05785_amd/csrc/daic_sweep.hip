@@ -1,0 +1,644 @@
+// Sweep scheduling for sum problems: round-robin over blocks of ceil(q n)
+// consecutive vertex ids. A round handles one block: each vertex of the block
+// receives, by a pull over its in-edges, the newest message base of every
+// in-neighbour, then folds the sum into its state and publishes its own
+// message base. Blocks later in a sweep therefore see the updates made
+// earlier in it, an asynchronous activation order (Eq. async) that Theorem 1
+// allows; with a single block (q = 1) it is the synchronous round.
+//
+// Numbering. Message bases are stored by a sweep numbering of the sources:
+// block-major (block c owns numbers [c B, c B + |block c|)) and, inside a
+// block, by out-degree descending, so that a source's block follows from its
+// number and the hot senders of a block share cache lines.
+//
+// Exactly-once delivery. Message bases live in two slots per vertex, chosen
+// by the parity of the sweep that published them. When block c of sweep k
+// runs, an in-neighbour numbered s < c B has published in sweep k (slot
+// k mod 2) and its previous base was consumed by this target in sweep k - 1;
+// an in-neighbour at s >= c B (this block included) last published in sweep
+// k - 1 (slot (k - 1) mod 2), after this target's pull of sweep k - 1. Either
+// way the target reads exactly the one base it has not consumed. Every
+// vertex of the block writes its slot each sweep (0 when silent), so a slot
+// never holds a base older than the previous sweep.
+//
+// Residual. After a whole sweep the messages not yet consumed are those of
+// every source s to its out-neighbours in blocks up to its own, so
+// sum_s |mu_s| * sum_{t in out(s), block(t) <= block(s)} |w_st| bounds the
+// pending L1 mass (with equality for non-negative messages, e.g. PageRank);
+// the sweep stops when that bound is <= eps. A final pass delivers the
+// messages still in flight into dv, after which the exact residual is taken.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "daic_device.h"
+#include "daic_problem.h"
+
+namespace daic {
+
+struct SweepArgs {
+  Ctl* ctl;
+  uint64_t n;
+  uint64_t B;                 // positions per block
+  uint32_t P;                 // blocks per sweep
+  const uint32_t* row;        // out-edge offsets [n+1]
+  const uint32_t* rowT;       // in-edge offsets [n+1]
+  const uint32_t* srcT;       // sweep number of the source of each in-edge
+  const uint32_t* perm;       // sweep number of each vertex
+  const void* wT;             // S[m] weights in in-edge order (EDGE_SCALE)
+  void* v;
+  void* dv;
+  float* c;                   // Kahan term or null
+  const void* alpha_pv;
+  double alpha;
+  void* mu2;                  // S[2n]: slot 0 then slot 1, by position
+  const uint32_t* voff;       // [P+1]: block c owns ids [voff[c], voff[c+1])
+  const uint32_t* lt;         // items (target, chunk, chunks of target) of targets with
+  const uint32_t* lc;         // in-degree > kSmallMaxDeg, grouped by the target's block
+  const uint32_t* ln;
+  const uint32_t* loff;       // [P+1]
+  uint64_t n_items;
+  const double* coef_le;      // [n] by position: sum of |w| to out-neighbours in blocks <= own
+  double* part_r;             // residual partials per grid block
+  uint64_t* part_n;
+  uint64_t* part_a;           // claim partials per grid block: activations, messages
+  uint64_t* part_m;
+  uint32_t claim_blocks;      // grid of k_sweep_claim
+};
+
+struct SweepState {
+  uint64_t B = 0;
+  uint32_t P = 0;
+  uint64_t max_block_items = 0;  // largest item count of one block
+  uint64_t max_block_verts = 0;
+  std::vector<void*> allocs;
+  SweepArgs a{};
+};
+
+namespace {
+
+constexpr uint32_t kResGrid = 2048;
+
+template <int ST, int G>
+__device__ __forceinline__ double sweep_msg(const SweepArgs& a, const typename Tr<ST>::S* mu2, uint32_t p,
+                                            uint32_t src, uint64_t lo, uint64_t cur, uint64_t prev) {
+  using S = typename Tr<ST>::S;
+  double m = (double)mu2[(src < lo ? cur : prev) + src];
+  if constexpr (G == DAIC_G_EDGE_SCALE) m *= (double)static_cast<const S*>(a.wT)[p];
+  return m;
+}
+
+// Block c, targets with more than kSmallMaxDeg in-edges: one wave per item
+// (target, chunk of kChunk in-edges; a block's items longest first) adds its
+// part of the pull into dv.
+template <int ST, int G>
+__global__ __launch_bounds__(256) void k_sweep_large(SweepArgs a, uint32_t c) {
+  using S = typename Tr<ST>::S;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  const uint64_t k = ctl->rounds / a.P;
+  const uint64_t cur = (k & 1) * a.n, prev = ((k + 1) & 1) * a.n, lo = (uint64_t)c * a.B;
+  const S* mu2 = static_cast<const S*>(a.mu2);
+  S* dv = static_cast<S*>(a.dv);
+  const uint64_t ib = a.loff[c], ie = a.loff[c + 1];
+  const uint32_t lane = lane_id();
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t i = ib + wave; i < ie; i += nwaves) {
+    const uint32_t t = a.lt[i], nch = a.ln[i];
+    const uint32_t beg = a.rowT[t] + a.lc[i] * kChunk;
+    const uint32_t end = min(a.rowT[t + 1], beg + kChunk);
+    double acc = 0.0;
+    uint32_t p = beg + lane;
+    for (; p + 192 < end; p += 256) {
+      const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 64], s2 = a.srcT[p + 128], s3 = a.srcT[p + 192];
+      const double m0 = sweep_msg<ST, G>(a, mu2, p, s0, lo, cur, prev);
+      const double m1 = sweep_msg<ST, G>(a, mu2, p + 64, s1, lo, cur, prev);
+      const double m2 = sweep_msg<ST, G>(a, mu2, p + 128, s2, lo, cur, prev);
+      const double m3 = sweep_msg<ST, G>(a, mu2, p + 192, s3, lo, cur, prev);
+      acc += (m0 + m1) + (m2 + m3);
+    }
+    for (; p < end; p += 64) acc += sweep_msg<ST, G>(a, mu2, p, a.srcT[p], lo, cur, prev);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      if (nch == 1) dv[t] = (S)((double)dv[t] + acc);
+      else unsafeAtomicAdd(&dv[t], (S)acc);
+    }
+  }
+}
+
+// Block c, every vertex: pull (targets with at most kSmallMaxDeg in-edges;
+// the others were summed into dv by k_sweep_large), fold, publish.
+template <int ST, int G>
+__global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
+  using S = typename Tr<ST>::S;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  const uint64_t k = ctl->rounds / a.P;
+  const uint64_t cur = (k & 1) * a.n, prev = ((k + 1) & 1) * a.n, lo = (uint64_t)c * a.B;
+  S* mu2 = static_cast<S*>(a.mu2);
+  S* v = static_cast<S*>(a.v);
+  S* dv = static_cast<S*>(a.dv);
+  const uint64_t vb = a.voff[c], ve = a.voff[c + 1];
+  uint64_t act = 0, pushed = 0;
+  for (uint64_t i = vb + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ve;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = (uint32_t)i;
+    const uint32_t b0 = a.rowT[j], b1 = a.rowT[j + 1];
+    const S d_old = dv[j];
+    S d = d_old;
+    // the state is loaded before the pull so that its latency overlaps the
+    // gathers' (in dense sweeps nearly every vertex updates)
+    const S vj = v[j];
+    float cj = 0.0f;
+    if constexpr (Tr<ST>::kahan) cj = a.c[j];
+    if (b1 - b0 <= kSmallMaxDeg) {
+      double acc = 0.0;
+      uint32_t p = b0;
+      for (; p + 3 < b1; p += 4) {
+        const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
+        const double m0 = sweep_msg<ST, G>(a, mu2, p, s0, lo, cur, prev);
+        const double m1 = sweep_msg<ST, G>(a, mu2, p + 1, s1, lo, cur, prev);
+        const double m2 = sweep_msg<ST, G>(a, mu2, p + 2, s2, lo, cur, prev);
+        const double m3 = sweep_msg<ST, G>(a, mu2, p + 3, s3, lo, cur, prev);
+        acc += (m0 + m1) + (m2 + m3);
+      }
+      for (; p < b1; ++p) acc += sweep_msg<ST, G>(a, mu2, p, a.srcT[p], lo, cur, prev);
+      d = (S)((double)d_old + acc);
+    }
+    S mu = (S)0;
+    if (d != (S)0) {
+      const uint32_t deg = a.row[j + 1] - a.row[j];
+      if (d_old != (S)0) dv[j] = (S)0;
+      if constexpr (Tr<ST>::kahan) {
+        // compensated fold (Kahan 1965), as in the round kernels
+#pragma clang fp contract(off)
+        const float y = d - cj;
+        const float t = vj + y;
+        a.c[j] = (t - vj) - y;
+        v[j] = t;
+      } else {
+        v[j] = vj + d;
+      }
+      double coef;
+      if constexpr (G == DAIC_G_DEG_SCALE) {
+        coef = deg ? a.alpha / (double)deg : 0.0;
+      } else {
+        coef = a.alpha_pv ? (double)static_cast<const S*>(a.alpha_pv)[j] : a.alpha;
+      }
+      mu = (S)(coef * (double)d);
+      act += 1;
+      pushed += deg;
+    }
+    mu2[cur + a.perm[j]] = mu;
+  }
+  act = block_sum256(act);
+  pushed = block_sum256(pushed);
+  if (threadIdx.x == 0) {
+    a.part_a[blockIdx.x] = act;
+    a.part_m[blockIdx.x] = pushed;
+  }
+}
+
+// After each round: add the claim's per-block counts to the totals; when the
+// round does not end a sweep, count it and apply the round limit (the sweep's
+// last round is counted by k_sweep_residual).
+__global__ __launch_bounds__(256) void k_sweep_step(SweepArgs a, int sweep_end) {
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  uint64_t act = 0, msg = 0;
+  for (uint32_t i = threadIdx.x; i < a.claim_blocks; i += 256) {
+    act += a.part_a[i];
+    msg += a.part_m[i];
+  }
+  act = block_sum256(act);
+  msg = block_sum256(msg);
+  if (threadIdx.x == 0) {
+    ctl->activations += act;
+    ctl->pushed += msg;
+    if (!sweep_end) {
+      ctl->rounds += 1;
+      ctl->stop = ctl->rounds >= ctl->max_rounds ? 1u : 0u;
+    }
+  }
+}
+
+// End of a sweep: the bound on the pending mass, the stop rule and the round
+// count. Fixed-order reduction of per-block FP64 partials.
+template <int ST>
+__global__ __launch_bounds__(256) void k_sweep_residual(SweepArgs a) {
+  using S = typename Tr<ST>::S;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  const uint64_t k = ctl->rounds / a.P;
+  const S* mu = static_cast<const S*>(a.mu2) + (k & 1) * a.n;
+  double r = 0.0;
+  uint64_t cnt = 0;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.n; s += (uint64_t)gridDim.x * blockDim.x) {
+    const double m = fabs((double)mu[s]);
+    r += m * a.coef_le[s];
+    cnt += m > 0.0 ? 1 : 0;
+  }
+  r = block_sum256(r);
+  cnt = block_sum256(cnt);
+  __shared__ uint32_t s_last;
+  if (threadIdx.x == 0) {
+    a.part_r[blockIdx.x] = r;
+    a.part_n[blockIdx.x] = cnt;
+    __threadfence();
+    s_last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double rr = 0.0;
+  uint64_t nn = 0;
+  for (uint32_t i = threadIdx.x; i < gridDim.x; i += 256) {
+    rr += __hip_atomic_load(&a.part_r[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    nn += __hip_atomic_load(&a.part_n[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  rr = block_sum256(rr);
+  nn = block_sum256(nn);
+  if (threadIdx.x == 0) {
+    ctl->r = rr;
+    ctl->pending = nn;
+    ctl->rounds += 1;
+    const bool done = rr <= ctl->eps;
+    ctl->done = done ? 1u : 0u;
+    ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
+    ctl->ticket = 0;
+  }
+}
+
+// Delivery of the messages still in flight after R rounds, R = k P + cl + 1
+// (blocks 0..cl of sweep k done). A source at position s last published in
+// sweep k if s < L = (cl + 1) B, else in sweep k - 1. A target of block bt
+// last pulled in sweep k if bt <= cl, else in sweep k - 1; a base is
+// unconsumed when it was published at or after the target's pull in
+// (sweep, block) order, equal blocks included.
+template <int ST, int G>
+__device__ __forceinline__ double sweep_pending(const SweepArgs& a, const typename Tr<ST>::S* mu2, uint32_t t,
+                                                uint32_t end, uint32_t step, uint32_t first) {
+  const uint64_t R = a.ctl->rounds;
+  const uint64_t k = (R - 1) / a.P, cl = (R - 1) % a.P;
+  const uint64_t L = min<uint64_t>(a.n, (cl + 1) * a.B);
+  const uint64_t cur = (k & 1) * a.n, prev = ((k + 1) & 1) * a.n;
+  const uint64_t bt = a.perm[t] / a.B, T0 = bt * a.B;
+  double acc = 0.0;
+  for (uint32_t p = first; p < end; p += step) {
+    const uint32_t s = a.srcT[p];
+    bool take;
+    uint64_t off;
+    if (bt <= cl) {
+      take = s >= T0 && s < L;
+      off = cur;
+    } else {
+      take = s < L || s >= T0;
+      off = s < L ? cur : prev;
+    }
+    if (take) {
+      double m = (double)mu2[off + s];
+      if constexpr (G == DAIC_G_EDGE_SCALE) m *= (double)static_cast<const typename Tr<ST>::S*>(a.wT)[p];
+      acc += m;
+    }
+  }
+  return acc;
+}
+
+template <int ST, int G>
+__global__ __launch_bounds__(256) void k_sweep_deliver_small(SweepArgs a) {
+  using S = typename Tr<ST>::S;
+  if (a.ctl->rounds == 0) return;
+  const S* mu2 = static_cast<const S*>(a.mu2);
+  S* dv = static_cast<S*>(a.dv);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t t = (uint32_t)i;
+    const uint32_t b0 = a.rowT[t], b1 = a.rowT[t + 1];
+    if (b1 == b0 || b1 - b0 > kSmallMaxDeg) continue;
+    const double acc = sweep_pending<ST, G>(a, mu2, t, b1, 1, b0);
+    if (acc != 0.0) dv[t] = (S)((double)dv[t] + acc);
+  }
+}
+
+template <int ST, int G>
+__global__ __launch_bounds__(256) void k_sweep_deliver_large(SweepArgs a) {
+  using S = typename Tr<ST>::S;
+  if (a.ctl->rounds == 0) return;
+  const S* mu2 = static_cast<const S*>(a.mu2);
+  S* dv = static_cast<S*>(a.dv);
+  const uint32_t lane = lane_id();
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t i = wave; i < a.n_items; i += nwaves) {
+    const uint32_t t = a.lt[i];
+    const uint32_t beg = a.rowT[t] + a.lc[i] * kChunk;
+    const uint32_t end = min(a.rowT[t + 1], beg + kChunk);
+    double acc = sweep_pending<ST, G>(a, mu2, t, end, 64, beg + lane);
+    acc = wave_sum(acc);
+    if (lane == 0 && acc != 0.0) unsafeAtomicAdd(&dv[t], (S)acc);
+  }
+}
+
+// coef_le[perm[j]] = sum over out-edges (j, t) with block(t) <= block(j) of
+// |w_jt| (1 per edge when unweighted); one wave per source vertex.
+template <typename S, bool W>
+__global__ __launch_bounds__(256) void k_sweep_coef(const uint32_t* row, const uint32_t* col, const S* w,
+                                                    const uint32_t* perm, uint64_t n, uint64_t B, double* coef_le) {
+  const uint32_t lane = lane_id();
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t j = wave; j < n; j += nwaves) {
+    const uint64_t bj = perm[j] / B;
+    double acc = 0.0;
+    for (uint32_t e = row[j] + lane; e < row[j + 1]; e += 64) {
+      if ((uint64_t)perm[col[e]] / B <= bj) acc += W ? fabs((double)w[e]) : 1.0;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) coef_le[perm[j]] = acc;
+  }
+}
+
+// srcT_sweep[p] = psw[inv[srcT[p]]]: from dense-round numbers to sweep numbers.
+__global__ void k_sweep_renumber(const uint32_t* srcT, const uint32_t* inv, const uint32_t* psw, uint64_t m,
+                                 uint32_t* out) {
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (uint64_t)gridDim.x * blockDim.x)
+    out[p] = psw[inv[srcT[p]]];
+}
+
+__global__ void k_sweep_reopen(Ctl* ctl) {
+  ctl->done = 0;
+  ctl->stop = 0;
+}
+
+uint32_t sgrid(uint64_t count, uint32_t per = 256, uint32_t cap = 8192) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((count + per - 1) / per, cap));
+}
+
+// Enqueue table per (state, g).
+struct SweepOps {
+  void (*round)(const SweepState&, hipStream_t, uint32_t c);
+  void (*deliver)(const SweepState&, hipStream_t);
+};
+
+template <int ST, int G>
+struct SweepImpl {
+  static void round(const SweepState& w, hipStream_t s, uint32_t c) {
+    const SweepArgs& a = w.a;
+    if (w.max_block_items)
+      hipLaunchKernelGGL((k_sweep_large<ST, G>), dim3(sgrid(w.max_block_items, 4)), dim3(256), 0, s, a, c);
+    hipLaunchKernelGGL((k_sweep_claim<ST, G>), dim3(a.claim_blocks), dim3(256), 0, s, a, c);
+    const bool end = c + 1 == a.P;
+    hipLaunchKernelGGL(k_sweep_step, dim3(1), dim3(256), 0, s, a, end ? 1 : 0);
+    if (end) hipLaunchKernelGGL(k_sweep_residual<ST>, dim3(sgrid(a.n, 256, kResGrid)), dim3(256), 0, s, a);
+  }
+  static void deliver(const SweepState& w, hipStream_t s) {
+    const SweepArgs& a = w.a;
+    hipLaunchKernelGGL((k_sweep_deliver_small<ST, G>), dim3(sgrid(a.n)), dim3(256), 0, s, a);
+    if (a.n_items)
+      hipLaunchKernelGGL((k_sweep_deliver_large<ST, G>), dim3(sgrid(a.n_items, 4)), dim3(256), 0, s, a);
+  }
+};
+
+template <int ST>
+bool sweep_ops_st(int gk, SweepOps* o) {
+  switch (gk) {
+    case DAIC_G_SRC_SCALE: *o = {SweepImpl<ST, DAIC_G_SRC_SCALE>::round, SweepImpl<ST, DAIC_G_SRC_SCALE>::deliver}; return true;
+    case DAIC_G_EDGE_SCALE: *o = {SweepImpl<ST, DAIC_G_EDGE_SCALE>::round, SweepImpl<ST, DAIC_G_EDGE_SCALE>::deliver}; return true;
+    case DAIC_G_DEG_SCALE: *o = {SweepImpl<ST, DAIC_G_DEG_SCALE>::round, SweepImpl<ST, DAIC_G_DEG_SCALE>::deliver}; return true;
+    default: return false;
+  }
+}
+
+bool sweep_ops(const daic_problem* p, SweepOps* o) {
+  switch (p->st) {
+    case ST_F64: return sweep_ops_st<ST_F64>(p->gk, o);
+    case ST_F32: return sweep_ops_st<ST_F32>(p->gk, o);
+    case ST_F32K: return sweep_ops_st<ST_F32K>(p->gk, o);
+    default: return false;
+  }
+}
+
+size_t sweep_state_size(int st) { return st == ST_F64 ? 8 : 4; }
+
+// Per-problem set-up for block size B: the sweep numbering (host, from the
+// dense-round renumbering), the in-edge sources in that numbering, the items
+// of the large targets grouped by block, the residual coefficients and the
+// two message slots.
+daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
+  SweepState*& w = p->sweep;
+  if (w && w->B == B) return DAIC_OK;
+  sweep_release(p);
+  w = new SweepState();
+  const GraphDev& d = p->g->dev;
+  const PullGraph& PG = p->g->pull;
+  const uint64_t n = d.n;
+  const uint32_t P = (uint32_t)((n + B - 1) / B);
+  w->B = B;
+  w->P = P;
+  auto grab = [&](void** q, size_t bytes) -> daic_status {
+    void* m = nullptr;
+    hipError_t e = hipMalloc(&m, bytes ? bytes : 1);
+    if (e != hipSuccess) return fail(DAIC_E_OOM, "sweep set-up: hipMalloc of %zu bytes failed", bytes);
+    w->allocs.push_back(m);
+    *q = m;
+    return DAIC_OK;
+  };
+  // sweep numbering: block-major, out-degree order (the dense-round
+  // renumbering) inside a block
+  std::vector<uint32_t> perm(n), inv(n), rt(n + 1), psw(n);
+  DAIC_HIP(hipMemcpy(perm.data(), PG.perm, n * 4, hipMemcpyDeviceToHost));
+  DAIC_HIP(hipMemcpy(rt.data(), PG.rowT, (n + 1) * 4, hipMemcpyDeviceToHost));
+  for (uint64_t j = 0; j < n; ++j) inv[perm[j]] = (uint32_t)j;
+  std::vector<uint32_t> voff(P + 1, 0);
+  for (uint32_t c = 0; c <= P; ++c) voff[c] = (uint32_t)std::min<uint64_t>(n, (uint64_t)c * B);
+  {
+    std::vector<uint32_t> fill(voff.begin(), voff.end() - 1);
+    for (uint64_t q = 0; q < n; ++q) {
+      const uint32_t j = inv[q];
+      psw[j] = fill[j / B]++;
+    }
+  }
+  std::vector<uint32_t> lt, lc, ln, loff(P + 1, 0);
+  for (uint32_t c = 0; c < P; ++c) {
+    std::vector<std::pair<uint32_t, uint64_t>> items;  // (edges, target << 32 | chunk)
+    for (uint32_t t = voff[c]; t < voff[c + 1]; ++t) {
+      const uint32_t deg = rt[t + 1] - rt[t];
+      if (deg <= kSmallMaxDeg) continue;
+      for (uint32_t ch = 0; ch * kChunk < deg; ++ch)
+        items.push_back({std::min(kChunk, deg - ch * kChunk), ((uint64_t)t << 32) | ch});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (auto& it : items) {
+      const uint32_t t = (uint32_t)(it.second >> 32);
+      const uint32_t deg = rt[t + 1] - rt[t];
+      lt.push_back(t);
+      lc.push_back((uint32_t)it.second);
+      ln.push_back((deg + kChunk - 1) / kChunk);
+    }
+    loff[c + 1] = (uint32_t)lt.size();
+    w->max_block_items = std::max<uint64_t>(w->max_block_items, loff[c + 1] - loff[c]);
+    w->max_block_verts = std::max<uint64_t>(w->max_block_verts, voff[c + 1] - voff[c]);
+  }
+  SweepArgs& a = w->a;
+  void* q = nullptr;
+  daic_status rc;
+#define SGRAB(field, type, bytes)            \
+  do {                                       \
+    if ((rc = grab(&q, (bytes)))) return rc; \
+    a.field = (type)q;                       \
+  } while (0)
+  const size_t S = sweep_state_size(p->st);
+  SGRAB(mu2, void*, 2 * n * S);
+  SGRAB(voff, const uint32_t*, (P + 1) * 4);
+  SGRAB(lt, const uint32_t*, lt.size() * 4);
+  SGRAB(lc, const uint32_t*, lc.size() * 4);
+  SGRAB(ln, const uint32_t*, ln.size() * 4);
+  SGRAB(loff, const uint32_t*, (P + 1) * 4);
+  SGRAB(coef_le, const double*, n * 8);
+  SGRAB(perm, const uint32_t*, n * 4);
+  SGRAB(srcT, const uint32_t*, std::max<uint64_t>(d.m, 1) * 4);
+  SGRAB(part_r, double*, kResGrid * 8);
+  SGRAB(part_n, uint64_t*, kResGrid * 8);
+  a.claim_blocks = sgrid(w->max_block_verts, 256, 4096);
+  SGRAB(part_a, uint64_t*, a.claim_blocks * 8);
+  SGRAB(part_m, uint64_t*, a.claim_blocks * 8);
+#undef SGRAB
+  DAIC_HIP(hipMemcpy((void*)a.voff, voff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
+  if (!lt.empty()) {
+    DAIC_HIP(hipMemcpy((void*)a.lt, lt.data(), lt.size() * 4, hipMemcpyHostToDevice));
+    DAIC_HIP(hipMemcpy((void*)a.lc, lc.data(), lc.size() * 4, hipMemcpyHostToDevice));
+    DAIC_HIP(hipMemcpy((void*)a.ln, ln.data(), ln.size() * 4, hipMemcpyHostToDevice));
+  }
+  DAIC_HIP(hipMemcpy((void*)a.loff, loff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
+  a.n_items = lt.size();
+  a.ctl = p->a.ctl;
+  a.n = n;
+  a.B = B;
+  a.P = P;
+  a.row = static_cast<const uint32_t*>(d.row);
+  a.rowT = static_cast<const uint32_t*>(PG.rowT);
+  DAIC_HIP(hipMemcpy((void*)a.perm, psw.data(), n * 4, hipMemcpyHostToDevice));
+  {
+    // sweep numbers of the in-edge sources, in the in-edge order of the
+    // dense rounds (so edge weights in in-edge order stay aligned)
+    uint32_t* d_inv = nullptr;
+    DAIC_HIP(hipMalloc(&d_inv, n * 4));
+    hipError_t e = hipMemcpy(d_inv, inv.data(), n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && d.m)
+      hipLaunchKernelGGL(k_sweep_renumber, dim3(sgrid(d.m)), dim3(256), 0, s, PG.srcT, d_inv, a.perm, d.m,
+                         const_cast<uint32_t*>(a.srcT));
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_inv);
+    if (e != hipSuccess) return fail(DAIC_E_DEVICE, "sweep set-up: %s", hipGetErrorString(e));
+  }
+  a.wT = p->a.wT;
+  a.v = p->a.v;
+  a.dv = p->a.dv;
+  a.c = p->a.c;
+  a.alpha_pv = p->a.alpha_pv;
+  a.alpha = p->a.alpha;
+  const uint32_t* row = static_cast<const uint32_t*>(d.row);
+  double* cl = const_cast<double*>(a.coef_le);
+  if (p->gk == DAIC_G_EDGE_SCALE) {
+    if (p->st == ST_F64)
+      hipLaunchKernelGGL((k_sweep_coef<double, true>), dim3(sgrid(n, 4)), dim3(256), 0, s, row, d.col,
+                         static_cast<const double*>(p->a.w), a.perm, n, B, cl);
+    else
+      hipLaunchKernelGGL((k_sweep_coef<float, true>), dim3(sgrid(n, 4)), dim3(256), 0, s, row, d.col,
+                         static_cast<const float*>(p->a.w), a.perm, n, B, cl);
+  } else {
+    hipLaunchKernelGGL((k_sweep_coef<float, false>), dim3(sgrid(n, 4)), dim3(256), 0, s, row, d.col,
+                       (const float*)nullptr, a.perm, n, B, cl);
+  }
+  DAIC_HIP(hipStreamSynchronize(s));
+  return DAIC_OK;
+}
+
+}  // namespace
+
+void sweep_release(daic_problem* p) {
+  if (!p->sweep) return;
+  for (void* q : p->sweep->allocs)
+    if (q) (void)hipFree(q);
+  delete p->sweep;
+  p->sweep = nullptr;
+}
+
+daic_status sweep_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats, hipStream_t s) {
+  const bool sum = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
+  if (!sum) return fail(DAIC_E_UNSUPPORTED, "SWEEP scheduling takes sum problems");
+  const uint64_t n = p->g->dev.n;
+  daic_status rc = dense_rounds_setup(p, o, s);
+  if (rc) return rc;
+  if (!p->pull_ready) return fail(DAIC_E_UNSUPPORTED, "SWEEP scheduling needs n, m < 2^31 (and DAIC_NO_PULL unset)");
+  Ops ops;
+  SweepOps sw;
+  if (!get_ops(p, &ops) || !sweep_ops(p, &sw)) return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");
+  const uint64_t B = std::max<uint64_t>(1, std::min<uint64_t>(n, (uint64_t)std::ceil(o->priority_fraction * (double)n)));
+  rc = sweep_setup(p, B, s);
+  if (rc) return rc;
+  const SweepState& w = *p->sweep;
+  const uint32_t P = w.P;
+  // rounds captured per launch: whole sweeps, at least rounds_per_check rounds
+  const uint32_t want = o->rounds_per_check ? o->rounds_per_check : 1;
+  const uint32_t K = P * std::max<uint32_t>(1, (want + P - 1) / P);
+  const uint64_t max_rounds = o->max_rounds ? o->max_rounds : ~0ull;
+
+  DAIC_HIP(hipMemsetAsync(w.a.mu2, 0, 2 * n * sweep_state_size(p->st), s));
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, p->a.ctl, o->eps, max_rounds);
+  ops.residual(p, s, 0);
+  DAIC_HIP(hipEventRecord(p->ev0, s));
+  const bool use_graph = std::getenv("DAIC_NO_GRAPH") == nullptr;
+  GraphCacheKey key;
+  key.sched = DAIC_SCHED_SWEEP;
+  key.k = B;
+  key.q = o->priority_fraction;
+  key.K = K;
+  key.stream = s;
+  if (use_graph && !(p->exec && p->key == key)) {
+    if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    DAIC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (uint32_t r = 0; r < K; ++r) sw.round(w, s, r % P);
+    hipGraph_t graph;
+    DAIC_HIP(hipStreamEndCapture(s, &graph));
+    p->graph = graph;
+    DAIC_HIP(hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0));
+    p->key = key;
+  }
+  for (;;) {
+    DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DAIC_HIP(hipStreamSynchronize(s));
+    if (p->h_ctl->done || p->h_ctl->stop) break;
+    if (use_graph) {
+      DAIC_HIP(hipGraphLaunch(p->exec, s));
+    } else {
+      for (uint32_t r = 0; r < K; ++r) sw.round(w, s, r % P);
+    }
+  }
+  // deliver the messages in flight, then the exact residual of (v, dv)
+  sw.deliver(w, s);
+  hipLaunchKernelGGL(k_sweep_reopen, dim3(1), dim3(1), 0, s, p->a.ctl);
+  ops.residual(p, s, 0);
+  DAIC_HIP(hipEventRecord(p->ev1, s));
+  DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  DAIC_HIP(hipStreamSynchronize(s));
+  float ms = 0.f;
+  DAIC_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+  const Ctl& c = *p->h_ctl;
+  if (stats) {
+    stats->rounds = c.rounds;
+    stats->activations = c.activations;
+    stats->pushed_edges = c.pushed;
+    stats->final_residual = c.r;
+    stats->time_ms = ms;
+    stats->gteps = ms > 0 ? (double)c.pushed / (ms * 1e-3) / 1e9 : 0.0;
+    stats->alg_bytes = 0.0;
+  }
+  return c.done ? DAIC_OK : DAIC_NOT_CONVERGED;
+}
+
+}  // namespace daic

@@ -22,11 +22,11 @@ OK, NOT_CONVERGED = 0, 1
 SUM, MIN, MAX = 0, 1, 2
 G_SRC_SCALE, G_EDGE_SCALE, G_EDGE_ADD, G_COPY, G_DEG_SCALE = 0, 1, 2, 3, 4
 F64, F32, F32_KAHAN, U32, I32, NONE = 0, 1, 2, 3, 4, 5
-SCHED_ALL, SCHED_TOPK_EXACT, SCHED_TOPK_SAMPLED, SCHED_LEARNED, SCHED_ROUND_ROBIN = 0, 1, 2, 3, 4
+SCHED_ALL, SCHED_TOPK_EXACT, SCHED_TOPK_SAMPLED, SCHED_LEARNED, SCHED_ROUND_ROBIN, SCHED_SWEEP = 0, 1, 2, 3, 4, 5
 INF_U32 = 0xFFFFFFFF
 
 _SCHED_NAMES = {"all": SCHED_ALL, "exact": SCHED_TOPK_EXACT, "sampled": SCHED_TOPK_SAMPLED,
-                "learned": SCHED_LEARNED, "round_robin": SCHED_ROUND_ROBIN}
+                "learned": SCHED_LEARNED, "round_robin": SCHED_ROUND_ROBIN, "sweep": SCHED_SWEEP}
 _STATE_NAMES = {"f64": F64, "f32": F32, "f32_kahan": F32_KAHAN, "u32": U32, "i32": I32}
 
 _vp = ctypes.c_void_p
