@@ -14,6 +14,8 @@ Contents
 * ``sync_daic_sum``  -- synchronous DAIC, Eq. sync (C, one thread).
 * ``async_run``      -- asynchronous DAIC, Eq. async, with priority (Sec. 3.4)
   or round-robin (Sec. 5.1) scheduling, for sum, min and max (C, one thread).
+* ``sweep_blocks``   -- asynchronous DAIC in blocks of B consecutive ids taken
+  round-robin, each block updated together (numpy).
 * ``dijkstra``       -- SSSP distances, the min problem's textbook answer.
 * ``maxlabel``       -- max-id reachability, the max problem's answer.
 * ``priority``       -- |v (+) dv - v| per vertex (Sec. 3.4 and Table 1 rows).
@@ -166,6 +168,46 @@ def async_run(g, op, gkind, v0, dv1, alpha=0.0, alpha_pv=None, w=None, sched=SCH
                         *args, ctypes.byref(r), _ptr(trace, _f64p) if trace_len else None,
                         trace_len, trace_every)
     return dict(v=v, dv=dv, updates=int(upd), residual=float(r.value), trace=trace)
+
+
+def sweep_blocks(g, gkind, alpha, v0, dv1, B, rounds, w=None, alpha_pv=None):
+    """Asynchronous DAIC (Eq. async) under round-robin scheduling over blocks
+    of B consecutive ids (Sec. 5.1): round r updates block r mod P, P =
+    ceil(n / B). Updating a block takes every delta of the block at once
+    (delta_j = dv_j, dv_j = 0, v_j += delta_j), then sends g_jk(delta_j) along
+    every out-edge of the block into dv_k, so that later blocks see these
+    messages in the same sweep and the block itself in the next one. g is
+    alpha x / outdeg_j (DEG_SCALE), alpha_j x (SRC_SCALE) or alpha_j w_jk x
+    (EDGE_SCALE), alpha_j = alpha_pv[j] when given. FP64; returns (v, dv).
+    B = n is the synchronous round (Eq. sync); B = 1 updates one vertex at a
+    time in id order."""
+    n = g.n
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    col = np.asarray(g.col, dtype=np.int64)
+    deg = np.diff(rp)
+    v = np.array(v0, dtype=np.float64, copy=True)
+    dv = np.array(dv1, dtype=np.float64, copy=True)
+    if gkind == G_DEG_SCALE:
+        coef = np.where(deg > 0, alpha / np.maximum(deg, 1), 0.0)
+    else:
+        coef = np.full(n, float(alpha)) if alpha_pv is None else np.asarray(alpha_pv, dtype=np.float64)
+    wv = None if w is None else np.asarray(w, dtype=np.float64)
+    P = max(1, -(-n // B)) if n else 1
+    for r in range(rounds):
+        if n == 0:
+            break
+        c = r % P
+        lo, hi = c * B, min(n, (c + 1) * B)
+        delta = dv[lo:hi].copy()
+        dv[lo:hi] = 0.0
+        v[lo:hi] += delta
+        e0, e1 = rp[lo], rp[hi]
+        src = np.repeat(np.arange(lo, hi), deg[lo:hi])
+        msg = coef[src] * delta[src - lo]
+        if gkind == G_EDGE_SCALE:
+            msg = msg * wv[e0:e1]
+        np.add.at(dv, col[e0:e1], msg)
+    return v, dv
 
 
 def dijkstra(g, w, source):

@@ -247,3 +247,42 @@ def test_sweep_rejects_min_problems(daic):
     p.set_init(*oracle.sssp_init(g.n, 0))
     with pytest.raises(daic.DaicError):
         p.run(q=0.5, sched="sweep")
+
+
+@pytest.mark.parametrize("q", [1.0, 0.3, 0.05])
+def test_sweep_trajectory_matches_block_oracle(daic, q):
+    """Round by round, the GPU state (messages in flight delivered) equals the
+    oracle's block-sequential DAIC with the same blocks: checks the order of
+    updates and that every message is delivered exactly once."""
+    say("case sweep trajectory", q)
+    g = daic_gen.rmat(12, 16, seed=71)
+    d = 0.8
+    v0, dv1 = oracle.pagerank_init(g.n, d)
+    B = max(1, int(np.ceil(q * g.n)))
+    P = -(-g.n // B)
+    for rounds in sorted({1, 2, P, P + 1, 3 * P + 2}):
+        p = pr_problem(daic, g)
+        p.run(eps=0.0, q=q, sched="sweep", max_rounds=rounds, rounds_per_check=1)
+        v, dv = p.get(with_dv=True)
+        vo, dvo = oracle.sweep_blocks(g, oracle.G_DEG_SCALE, d, v0, dv1, B, rounds)
+        np.testing.assert_allclose(v, vo, rtol=1e-11, atol=1e-13)
+        np.testing.assert_allclose(dv, dvo, rtol=1e-11, atol=1e-13)
+
+
+def test_sweep_trajectory_edge_scale(daic):
+    say("case sweep trajectory edge scale")
+    g = daic_gen.rmat(11, 8, seed=72)
+    w = daic_gen.lognormal_f64(73, g.m, 0.4, 0.8)
+    deg = g.outdeg()
+    rs = np.bincount(np.repeat(np.arange(g.n), deg), weights=w, minlength=g.n)
+    a = 0.85 / np.where(deg > 0, rs, 1.0)
+    c = daic_gen.lognormal_f64(74, g.n, 0.0, 1.0)
+    B = 300
+    for rounds in (3, 8, 21):
+        p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.SUM, daic.G_EDGE_SCALE, alpha_pv=a, state="f64")
+        p.set_init(np.zeros(g.n), c)
+        p.run(eps=0.0, q=B / g.n, sched="sweep", max_rounds=rounds, rounds_per_check=1)
+        v, dv = p.get(with_dv=True)
+        vo, dvo = oracle.sweep_blocks(g, oracle.G_EDGE_SCALE, 0.0, np.zeros(g.n), c, B, rounds, w=w, alpha_pv=a)
+        np.testing.assert_allclose(v, vo, rtol=1e-11, atol=1e-13)
+        np.testing.assert_allclose(dv, dvo, rtol=1e-11, atol=1e-13)

@@ -261,6 +261,69 @@ def test_theorem2_async_closer_than_sync_per_vertex():
         assert np.all(np.abs(want - ra["v"]) <= np.abs(want - vs) + 1e-12)
 
 
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_sweep_blocks_whole_graph_is_the_synchronous_round(k):
+    """Blocks of n ids: one round is one synchronous DAIC round (Eq. sync)."""
+    g = random_graph(150, 900, 41)
+    d = 0.8
+    v0, dv1 = oracle.pagerank_init(g.n, d)
+    vs, dvs, _, _ = oracle.sync_daic_sum(g, oracle.G_DEG_SCALE, d, v0, dv1, eps=0.0, max_rounds=k)
+    vb, dvb = oracle.sweep_blocks(g, oracle.G_DEG_SCALE, d, v0, dv1, g.n, k)
+    np.testing.assert_allclose(vb, vs, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(dvb, dvs, rtol=1e-13, atol=1e-15)
+    # weighted form with per-source coefficients
+    rng = np.random.default_rng(4)
+    w = rng.uniform(0.1, 1.0, g.m)
+    a = rng.uniform(0.1, 0.5, g.n) / np.maximum(1, g.outdeg())
+    c = rng.uniform(0, 1, g.n)
+    vs, dvs, _, _ = oracle.sync_daic_sum(g, oracle.G_EDGE_SCALE, 0.0, np.zeros(g.n), c, w=w, alpha_pv=a,
+                                         eps=0.0, max_rounds=k)
+    vb, dvb = oracle.sweep_blocks(g, oracle.G_EDGE_SCALE, 0.0, np.zeros(g.n), c, g.n, k, w=w, alpha_pv=a)
+    np.testing.assert_allclose(vb, vs, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(dvb, dvs, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("k", [1, 2, 6])
+def test_sweep_blocks_of_one_is_the_id_order_sequence(k):
+    """Blocks of one id: k n rounds are k passes of the one-vertex-at-a-time
+    update sequence in id order (the C oracle's sweep schedule)."""
+    g = daic_gen.powerlaw(n=300, seed=22)
+    d = 0.8
+    v0, dv1 = oracle.pagerank_init(g.n, d)
+    ra = oracle.async_run(g, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dv1, alpha=d,
+                          sched=oracle.SCHED_SWEEP, eps=0.0, max_updates=k * g.n)
+    vb, dvb = oracle.sweep_blocks(g, oracle.G_DEG_SCALE, d, v0, dv1, 1, k * g.n)
+    np.testing.assert_allclose(vb, ra["v"], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(dvb, ra["dv"], rtol=1e-13, atol=1e-15)
+    beta = 0.5 / max(1, int(g.outdeg().max()))
+    ra = oracle.async_run(g, oracle.OP_SUM, oracle.G_SRC_SCALE, np.zeros(g.n), dv1, alpha=beta,
+                          sched=oracle.SCHED_SWEEP, eps=0.0, max_updates=k * g.n)
+    vb, dvb = oracle.sweep_blocks(g, oracle.G_SRC_SCALE, beta, np.zeros(g.n), dv1, 1, k * g.n)
+    np.testing.assert_allclose(vb, ra["v"], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(dvb, ra["dv"], rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("B", [1, 7, 33])
+def test_sweep_blocks_invariants_and_fixed_point(B):
+    """Any number of block rounds keeps the state identities of Eq. async
+    (mass; v + dv = c + M^T v) and the rounds reach the dense solve."""
+    g = random_graph(120, 700, 9)
+    d = 0.8
+    n = g.n
+    deg = g.outdeg()
+    v0, dv1 = oracle.pagerank_init(n, d)
+    s = np.where(deg > 0, d, 0.0)
+    src = np.repeat(np.arange(n), deg)
+    for rounds in (1, 5, 40):
+        v, dv = oracle.sweep_blocks(g, oracle.G_DEG_SCALE, d, v0, dv1, B, rounds)
+        assert abs(dv.sum() + ((1 - s) * v).sum() - dv1.sum()) <= 1e-12 * dv1.sum()
+        mtv = np.bincount(g.col.astype(np.int64), weights=d * v[src] / deg[src], minlength=n)
+        np.testing.assert_allclose(v + dv, dv1 + mtv, rtol=1e-12, atol=1e-13)
+    P = -(-n // B)
+    v, dv = oracle.sweep_blocks(g, oracle.G_DEG_SCALE, d, v0, dv1, B, 200 * P)
+    np.testing.assert_allclose(v, dense_pagerank(g, d), rtol=1e-10, atol=1e-12)
+
+
 @pytest.mark.parametrize("seed", [31, 32, 33])
 def test_theorem4_priority_ahead_of_round_robin_in_l1(seed):
     """After the same number of updates, priority scheduling is at least as
