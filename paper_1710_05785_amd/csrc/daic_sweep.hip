@@ -61,6 +61,8 @@ struct SweepArgs {
   const uint32_t* ln;
   const uint32_t* loff;       // [P+1]
   uint64_t n_items;
+  const uint32_t* sm;         // targets with 1..kSmallMaxDeg in-edges, grouped by block, ids ascending
+  const uint32_t* soff;       // [P+1]
   const double* coef_le;      // [n] by position: sum of |w| to out-neighbours in blocks <= own
   double* part_r;             // residual partials per grid block
   uint64_t* part_n;
@@ -74,6 +76,7 @@ struct SweepState {
   uint32_t P = 0;
   uint64_t max_block_items = 0;  // largest item count of one block
   uint64_t max_block_verts = 0;
+  uint64_t max_block_small = 0;
   std::vector<void*> allocs;
   SweepArgs a{};
 };
@@ -130,15 +133,47 @@ __global__ __launch_bounds__(256) void k_sweep_large(SweepArgs a, uint32_t c) {
   }
 }
 
-// Block c, every vertex: pull (targets with at most kSmallMaxDeg in-edges;
-// the others were summed into dv by k_sweep_large), fold, publish.
+// Block c, targets with 1..kSmallMaxDeg in-edges: one thread per target (ids
+// ascending, so offsets, lists and deltas are read by consecutive lanes) adds
+// its pull into dv.
+template <int ST, int G>
+__global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a, uint32_t c) {
+  using S = typename Tr<ST>::S;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  const uint64_t k = ctl->rounds / a.P;
+  const uint64_t cur = (k & 1) * a.n, prev = ((k + 1) & 1) * a.n, lo = (uint64_t)c * a.B;
+  const S* mu2 = static_cast<const S*>(a.mu2);
+  S* dv = static_cast<S*>(a.dv);
+  const uint64_t ib = a.soff[c], ie = a.soff[c + 1];
+  for (uint64_t i = ib + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ie;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t t = a.sm[i];
+    const uint32_t b0 = a.rowT[t], b1 = a.rowT[t + 1];
+    double acc = 0.0;
+    uint32_t p = b0;
+    for (; p + 3 < b1; p += 4) {
+      const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
+      const double m0 = sweep_msg<ST, G>(a, mu2, p, s0, lo, cur, prev);
+      const double m1 = sweep_msg<ST, G>(a, mu2, p + 1, s1, lo, cur, prev);
+      const double m2 = sweep_msg<ST, G>(a, mu2, p + 2, s2, lo, cur, prev);
+      const double m3 = sweep_msg<ST, G>(a, mu2, p + 3, s3, lo, cur, prev);
+      acc += (m0 + m1) + (m2 + m3);
+    }
+    for (; p < b1; ++p) acc += sweep_msg<ST, G>(a, mu2, p, a.srcT[p], lo, cur, prev);
+    dv[t] = (S)((double)dv[t] + acc);
+  }
+}
+
+// Block c, every vertex: fold the received sum (dv, filled by k_sweep_small
+// and k_sweep_large) into the state and publish the message base.
 template <int ST, int G>
 __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
   using S = typename Tr<ST>::S;
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
   const uint64_t k = ctl->rounds / a.P;
-  const uint64_t cur = (k & 1) * a.n, prev = ((k + 1) & 1) * a.n, lo = (uint64_t)c * a.B;
+  const uint64_t cur = (k & 1) * a.n;
   S* mu2 = static_cast<S*>(a.mu2);
   S* v = static_cast<S*>(a.v);
   S* dv = static_cast<S*>(a.dv);
@@ -147,35 +182,16 @@ __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
   for (uint64_t i = vb + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ve;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t j = (uint32_t)i;
-    const uint32_t b0 = a.rowT[j], b1 = a.rowT[j + 1];
-    const S d_old = dv[j];
-    S d = d_old;
-    // the state is loaded before the pull so that its latency overlaps the
-    // gathers' (in dense sweeps nearly every vertex updates)
-    const S vj = v[j];
-    float cj = 0.0f;
-    if constexpr (Tr<ST>::kahan) cj = a.c[j];
-    if (b1 - b0 <= kSmallMaxDeg) {
-      double acc = 0.0;
-      uint32_t p = b0;
-      for (; p + 3 < b1; p += 4) {
-        const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
-        const double m0 = sweep_msg<ST, G>(a, mu2, p, s0, lo, cur, prev);
-        const double m1 = sweep_msg<ST, G>(a, mu2, p + 1, s1, lo, cur, prev);
-        const double m2 = sweep_msg<ST, G>(a, mu2, p + 2, s2, lo, cur, prev);
-        const double m3 = sweep_msg<ST, G>(a, mu2, p + 3, s3, lo, cur, prev);
-        acc += (m0 + m1) + (m2 + m3);
-      }
-      for (; p < b1; ++p) acc += sweep_msg<ST, G>(a, mu2, p, a.srcT[p], lo, cur, prev);
-      d = (S)((double)d_old + acc);
-    }
+    const S d = dv[j];
     S mu = (S)0;
     if (d != (S)0) {
       const uint32_t deg = a.row[j + 1] - a.row[j];
-      if (d_old != (S)0) dv[j] = (S)0;
+      dv[j] = (S)0;
+      const S vj = v[j];
       if constexpr (Tr<ST>::kahan) {
         // compensated fold (Kahan 1965), as in the round kernels
 #pragma clang fp contract(off)
+        const float cj = a.c[j];
         const float y = d - cj;
         const float t = vj + y;
         a.c[j] = (t - vj) - y;
@@ -387,6 +403,8 @@ template <int ST, int G>
 struct SweepImpl {
   static void round(const SweepState& w, hipStream_t s, uint32_t c) {
     const SweepArgs& a = w.a;
+    if (w.max_block_small)
+      hipLaunchKernelGGL((k_sweep_small<ST, G>), dim3(sgrid(w.max_block_small)), dim3(256), 0, s, a, c);
     if (w.max_block_items)
       hipLaunchKernelGGL((k_sweep_large<ST, G>), dim3(sgrid(w.max_block_items, 4)), dim3(256), 0, s, a, c);
     hipLaunchKernelGGL((k_sweep_claim<ST, G>), dim3(a.claim_blocks), dim3(256), 0, s, a, c);
@@ -461,8 +479,14 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
       psw[j] = fill[j / B]++;
     }
   }
-  std::vector<uint32_t> lt, lc, ln, loff(P + 1, 0);
+  std::vector<uint32_t> lt, lc, ln, loff(P + 1, 0), sm, soff(P + 1, 0);
   for (uint32_t c = 0; c < P; ++c) {
+    for (uint32_t t = voff[c]; t < voff[c + 1]; ++t) {
+      const uint32_t deg = rt[t + 1] - rt[t];
+      if (deg >= 1 && deg <= kSmallMaxDeg) sm.push_back(t);
+    }
+    soff[c + 1] = (uint32_t)sm.size();
+    w->max_block_small = std::max<uint64_t>(w->max_block_small, soff[c + 1] - soff[c]);
     std::vector<std::pair<uint32_t, uint64_t>> items;  // (edges, target << 32 | chunk)
     for (uint32_t t = voff[c]; t < voff[c + 1]; ++t) {
       const uint32_t deg = rt[t + 1] - rt[t];
@@ -497,6 +521,8 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
   SGRAB(lc, const uint32_t*, lc.size() * 4);
   SGRAB(ln, const uint32_t*, ln.size() * 4);
   SGRAB(loff, const uint32_t*, (P + 1) * 4);
+  SGRAB(sm, const uint32_t*, sm.size() * 4);
+  SGRAB(soff, const uint32_t*, (P + 1) * 4);
   SGRAB(coef_le, const double*, n * 8);
   SGRAB(perm, const uint32_t*, n * 4);
   SGRAB(srcT, const uint32_t*, std::max<uint64_t>(d.m, 1) * 4);
@@ -513,6 +539,8 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
     DAIC_HIP(hipMemcpy((void*)a.ln, ln.data(), ln.size() * 4, hipMemcpyHostToDevice));
   }
   DAIC_HIP(hipMemcpy((void*)a.loff, loff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
+  if (!sm.empty()) DAIC_HIP(hipMemcpy((void*)a.sm, sm.data(), sm.size() * 4, hipMemcpyHostToDevice));
+  DAIC_HIP(hipMemcpy((void*)a.soff, soff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
   a.n_items = lt.size();
   a.ctl = p->a.ctl;
   a.n = n;
