@@ -105,7 +105,8 @@ struct BArgs {
   const uint32_t* hc;
   uint64_t n_hub;
   const uint32_t* item_order; // block -> residual item of the fused pass (~0u: none)
-  const uint32_t* vord;       // [N] vertices of each item by pulled in-degree, descending
+  const uint32_t* vord;       // [N] vertices of each item by pulled in-degree, descending, isolated last
+  const uint64_t* rha;        // [n_res] end of the item's vertices that have any edge
   uint32_t n_fused_blocks;
 };
 
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
   for (int k = 0; k < W; ++k) racc[k] = 0.0;
   uint64_t act = 0, msg = 0;
   if (__syncthreads_or(mine)) {
-    for (uint64_t x = a.rlo[it] + sub; x < a.rhi[it]; x += VPB) {
+    for (uint64_t x = a.rlo[it] + sub; x < a.rha[it]; x += VPB) {
       if (!mine) continue;
       const uint64_t j = a.vord[x];
       const uint32_t b0 = a.rowT[j], b1 = a.rowT[j + 1];
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
         float mu[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) mu[k] = cl[k] ? (float)(coef * (double)d[k]) : 0.0f;
-        vstore<W>(mu_out + (uint64_t)a.perm[j] * kR + r0, mu);
+        if (deg) vstore<W>(mu_out + (uint64_t)a.perm[j] * kR + r0, mu);  // no reader otherwise
         act += nclaim;
         msg += (uint64_t)nclaim * deg;
       }
@@ -935,16 +936,30 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
     a.n_res = (uint32_t)rg.size();
     // fused-pass visiting order inside each item: by pulled in-degree,
     // descending, so that the vertices a wave takes together loop about
-    // equally long over their in-edges
+    // equally long over their in-edges; vertices without any edge last and
+    // left out of the fused pass (they neither receive nor send once their
+    // initial delta is claimed, which the claim kernel of the first dense
+    // or sparse round does)
     {
       std::vector<uint32_t> vord(N);
+      std::vector<uint64_t> rha(rlo.size());
       for (uint64_t j = 0; j < N; ++j) vord[j] = (uint32_t)j;
+      auto isolated = [&](uint32_t j) { return rt[j + 1] == rt[j] && ro[j + 1] == ro[j]; };
       auto pulled = [&](uint32_t j) { const uint32_t d = rt[j + 1] - rt[j]; return d > a.hub_deg ? 0u : d; };
-      for (size_t k = 0; k < rlo.size(); ++k)
-        std::stable_sort(vord.begin() + rlo[k], vord.begin() + rhi[k],
-                         [&](uint32_t x, uint32_t y) { return pulled(x) > pulled(y); });
+      for (size_t k = 0; k < rlo.size(); ++k) {
+        std::stable_sort(vord.begin() + rlo[k], vord.begin() + rhi[k], [&](uint32_t x, uint32_t y) {
+          const bool ix = isolated(x), iy = isolated(y);
+          if (ix != iy) return iy;
+          return pulled(x) > pulled(y);
+        });
+        uint64_t e = rlo[k];
+        while (e < rhi[k] && !isolated(vord[e])) ++e;
+        rha[k] = e;
+      }
       BGRAB(vord, const uint32_t*, std::max<size_t>(N, 1) * 4);
       if (N) DAIC_HIP(hipMemcpy((void*)a.vord, vord.data(), N * 4, hipMemcpyHostToDevice));
+      BGRAB(rha, const uint64_t*, std::max<size_t>(rha.size(), 1) * 8);
+      if (!rha.empty()) DAIC_HIP(hipMemcpy((void*)a.rha, rha.data(), rha.size() * 8, hipMemcpyHostToDevice));
     }
     BGRAB(rg, const uint32_t*, rg.size() * 4);
     BGRAB(rlo, const uint64_t*, rlo.size() * 8);

@@ -111,6 +111,7 @@ struct PullGraph {
   uint64_t n_large = 0;
   uint64_t small_edges = 0;       // in-edges of the small targets
   uint64_t large_edges = 0;
+  uint64_t n_src = 0;             // vertices with out-edges: renumbered positions [0, n_src)
 };
 }  // namespace daic
 

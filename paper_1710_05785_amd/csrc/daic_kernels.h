@@ -74,6 +74,7 @@ struct KArgs {
   const uint32_t* pt_chunk;
   const uint32_t* pt_nch;
   uint64_t pn_large;
+  uint64_t n_src;           // vertices with out-edges (renumbered positions below n_src)
 };
 
 __device__ __forceinline__ bool ctl_halted(const Ctl* ctl) {
@@ -566,9 +567,12 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
       send = claim_fold<ST, G>(a, j, deg, vj, dj, mu) && deg > 0;
       if (a.last_upd) a.last_upd[j] = (uint32_t)ctl->rounds;
     }
-    if (pull) {  // dense round: every vertex publishes its message base (0 if silent)
+    if (pull) {  // dense round: every sender publishes its message base (0 if silent)
       if constexpr (Tr<ST>::sum) {
-        if (in) static_cast<S*>(a.mu_pi)[a.perm[j]] = send ? mu : (S)0;
+        if (in) {
+          const uint32_t pj = a.perm[j];
+          if (pj < a.n_src) static_cast<S*>(a.mu_pi)[pj] = send ? mu : (S)0;  // no reader otherwise
+        }
       }
       act += sel ? 1 : 0;
       pushed += send ? deg : 0;

@@ -183,6 +183,15 @@ daic_status pull_prepare(daic_graph* g, hipStream_t s) {
   }
   P.n_small = st.size();
   P.n_large = lt.size();
+  {
+    // sources are renumbered by out-degree, descending: those with out-edges first
+    const uint32_t* rowp = static_cast<const uint32_t*>(d.row);
+    std::vector<uint32_t> ro(n + 1);
+    PCHK(hipMemcpy(ro.data(), rowp, (n + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    uint64_t ns = 0;
+    for (uint64_t j = 0; j < n; ++j) ns += ro[j + 1] > ro[j] ? 1 : 0;
+    P.n_src = ns;
+  }
   PCHK(hipMalloc(&P.small_tgt, std::max<size_t>(st.size(), 1) * 4));
   PCHK(hipMalloc(&P.large_tgt, std::max<size_t>(lt.size(), 1) * 4));
   PCHK(hipMalloc(&P.large_chunk, std::max<size_t>(lt.size(), 1) * 4));

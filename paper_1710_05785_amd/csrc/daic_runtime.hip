@@ -339,6 +339,7 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
     a.pt_chunk = g->pull.large_chunk;
     a.pt_nch = g->pull.large_nch;
     a.pn_large = g->pull.n_large;
+    a.n_src = g->pull.n_src;
     DAIC_HIP(hipStreamSynchronize(s));
     p->pull_ready = true;
     if (p->exec) {  // captured rounds predate the dense-round kernels

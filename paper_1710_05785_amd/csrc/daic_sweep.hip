@@ -63,6 +63,8 @@ struct SweepArgs {
   uint64_t n_items;
   const uint32_t* sm;         // targets with 1..kSmallMaxDeg in-edges, grouped by block, ids ascending
   const uint32_t* soff;       // [P+1]
+  const uint32_t* rv;         // vertices with in-edges, grouped by block, ids ascending
+  const uint32_t* roff;       // [P+1]
   const double* coef_le;      // [n] by position: sum of |w| to out-neighbours in blocks <= own
   double* part_r;             // residual partials per grid block
   uint64_t* part_n;
@@ -165,8 +167,11 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a, uint32_t c) {
   }
 }
 
-// Block c, every vertex: fold the received sum (dv, filled by k_sweep_small
-// and k_sweep_large) into the state and publish the message base.
+// Block c: fold the received sum (dv, filled by k_sweep_small and
+// k_sweep_large) into the state and publish the message base. Vertices
+// without in-edges receive nothing, so after their claim of the first sweep
+// and the clearing of both slots (sweeps 1 and 2) they are skipped; vertices
+// without out-edges have no reader and publish nothing.
 template <int ST, int G>
 __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
   using S = typename Tr<ST>::S;
@@ -177,15 +182,16 @@ __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
   S* mu2 = static_cast<S*>(a.mu2);
   S* v = static_cast<S*>(a.v);
   S* dv = static_cast<S*>(a.dv);
-  const uint64_t vb = a.voff[c], ve = a.voff[c + 1];
+  const bool all = k < 3;
+  const uint64_t vb = all ? a.voff[c] : a.roff[c], ve = all ? a.voff[c + 1] : a.roff[c + 1];
   uint64_t act = 0, pushed = 0;
   for (uint64_t i = vb + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ve;
        i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t j = (uint32_t)i;
+    const uint32_t j = all ? (uint32_t)i : a.rv[i];
     const S d = dv[j];
+    const uint32_t deg = a.row[j + 1] - a.row[j];
     S mu = (S)0;
     if (d != (S)0) {
-      const uint32_t deg = a.row[j + 1] - a.row[j];
       dv[j] = (S)0;
       const S vj = v[j];
       if constexpr (Tr<ST>::kahan) {
@@ -209,7 +215,7 @@ __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
       act += 1;
       pushed += deg;
     }
-    mu2[cur + a.perm[j]] = mu;
+    if (deg) mu2[cur + a.perm[j]] = mu;
   }
   act = block_sum256(act);
   pushed = block_sum256(pushed);
@@ -479,13 +485,15 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
       psw[j] = fill[j / B]++;
     }
   }
-  std::vector<uint32_t> lt, lc, ln, loff(P + 1, 0), sm, soff(P + 1, 0);
+  std::vector<uint32_t> lt, lc, ln, loff(P + 1, 0), sm, soff(P + 1, 0), rv, roff(P + 1, 0);
   for (uint32_t c = 0; c < P; ++c) {
     for (uint32_t t = voff[c]; t < voff[c + 1]; ++t) {
       const uint32_t deg = rt[t + 1] - rt[t];
       if (deg >= 1 && deg <= kSmallMaxDeg) sm.push_back(t);
+      if (deg >= 1) rv.push_back(t);
     }
     soff[c + 1] = (uint32_t)sm.size();
+    roff[c + 1] = (uint32_t)rv.size();
     w->max_block_small = std::max<uint64_t>(w->max_block_small, soff[c + 1] - soff[c]);
     std::vector<std::pair<uint32_t, uint64_t>> items;  // (edges, target << 32 | chunk)
     for (uint32_t t = voff[c]; t < voff[c + 1]; ++t) {
@@ -523,6 +531,8 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
   SGRAB(loff, const uint32_t*, (P + 1) * 4);
   SGRAB(sm, const uint32_t*, sm.size() * 4);
   SGRAB(soff, const uint32_t*, (P + 1) * 4);
+  SGRAB(rv, const uint32_t*, rv.size() * 4);
+  SGRAB(roff, const uint32_t*, (P + 1) * 4);
   SGRAB(coef_le, const double*, n * 8);
   SGRAB(perm, const uint32_t*, n * 4);
   SGRAB(srcT, const uint32_t*, std::max<uint64_t>(d.m, 1) * 4);
@@ -541,6 +551,8 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
   DAIC_HIP(hipMemcpy((void*)a.loff, loff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
   if (!sm.empty()) DAIC_HIP(hipMemcpy((void*)a.sm, sm.data(), sm.size() * 4, hipMemcpyHostToDevice));
   DAIC_HIP(hipMemcpy((void*)a.soff, soff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
+  if (!rv.empty()) DAIC_HIP(hipMemcpy((void*)a.rv, rv.data(), rv.size() * 4, hipMemcpyHostToDevice));
+  DAIC_HIP(hipMemcpy((void*)a.roff, roff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
   a.n_items = lt.size();
   a.ctl = p->a.ctl;
   a.n = n;
