@@ -315,8 +315,50 @@ def ablation(daic, torch):
             }
             log(f"ablation {name} {sched} q={q}: rounds {r.stats['rounds']} updates "
                 f"{r.stats['activations']} time {wall * 1e3:.1f} ms")
+        if w is None:
+            res["sweep_q0.125"] = sweep_ablation(daic, torch, g)
         out[name] = res
     return out
+
+
+def sweep_ablation(daic, torch, g, blocks=8):
+    """The sweep schedule (round-robin over id blocks, each block pulling the
+    newest messages) on the ablation's PageRank case: time to the stop rule in
+    one run, and the progress curve from one-sweep runs (each run ends with
+    every message delivered, so consecutive runs continue the same sequence)."""
+    import numpy as np
+
+    q = 1.0 / blocks
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8, state="f32_kahan")
+    p.set_init(np.zeros(g.n), np.full(g.n, 0.2))
+    p.run(eps=1e-6, q=q, sched="sweep")  # set-up and capture
+    p.set_init(np.zeros(g.n), np.full(g.n, 0.2))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = p.run(eps=1e-6, q=q, sched="sweep")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    p.set_init(np.zeros(g.n), np.full(g.n, 0.2))
+    up, pr = [0], [float(np.full(g.n, 0.0).sum())]
+    total = 0
+    for _ in range(10000):
+        rs = p.run(eps=1e-6, q=q, sched="sweep", max_rounds=blocks, rounds_per_check=blocks)
+        total += rs.stats["activations"]
+        up.append(total)
+        pr.append(float(p.get().sum()))
+        if rs.converged:
+            break
+    up, pr = np.array(up), np.array(pr)
+    final, first = pr[-1], pr[0]
+    def updates_to(frac):
+        idx = np.nonzero(pr >= first + frac * (final - first))[0]
+        return int(up[idx[0]]) if idx.size else None
+    log(f"ablation sweep {blocks} blocks: rounds {r.stats['rounds']} updates {r.stats['activations']} "
+        f"time {wall * 1e3:.1f} ms")
+    return {"rounds": r.stats["rounds"], "sweeps": r.stats["rounds"] / blocks, "updates": r.stats["activations"],
+            "pushed_edges": r.stats["pushed_edges"], "time_ms": wall * 1e3, "converged": r.converged,
+            "updates_to_99pct_progress": updates_to(0.99), "updates_to_99.99pct_progress": updates_to(0.9999),
+            "curve_updates": [int(x) for x in up], "curve_progress": [float(x) for x in pr]}
 
 
 def main():
@@ -473,6 +515,24 @@ def main():
                                       "pushed_edges": rq.stats["pushed_edges"],
                                       "gteps": rq.stats["pushed_edges"] / wq / 1e9,
                                       "converged": rq.converged}
+        # sweep scheduling: round-robin over 8 id blocks, each block pulling the
+        # newest messages of its in-neighbours (asynchronous order)
+        blocks = 8
+        P.set_init_device(v0, dv1)
+        P.run(eps=args.eps, q=1.0 / blocks, sched="sweep", rounds_per_check=args.rounds_per_check)
+        P.set_init_device(v0, dv1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rs = P.run(eps=args.eps, q=1.0 / blocks, sched="sweep", rounds_per_check=args.rounds_per_check)
+        torch.cuda.synchronize()
+        ws = time.perf_counter() - t
+        vs = P.get()
+        forms[f"sweep_{blocks}_blocks"] = {
+            "time_to_residual_ms": ws * 1e3, "rounds": rs.stats["rounds"], "sweeps": rs.stats["rounds"] / blocks,
+            "pushed_edges": rs.stats["pushed_edges"], "gteps": rs.stats["pushed_edges"] / ws / 1e9,
+            "converged": rs.converged, "final_residual": rs.stats["final_residual"],
+            "rel_l1_vs_all_pending": float(np.abs(vs - v32).sum() / np.abs(v32).sum()),
+            "time_ratio_vs_all_pending": ws * 1e3 / out["time_to_residual_ms"]}
         log("learned-scheduler form ...")
         forms["learned_sched"] = learned_form(daic, torch, g, args.eps, args.rounds_per_check)
         log("batched form ...")
