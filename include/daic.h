@@ -59,7 +59,8 @@ typedef enum {
 } daic_status;
 
 /* The accumulation operator (+) (Sec. 3.1, third condition) and its identity
- * 0: 0 for SUM, 0xFFFFFFFF (infinity) for MIN, -1 for MAX. */
+ * 0: 0 for SUM, infinity for MIN (0xFFFFFFFF in U32 state, +inf in F64
+ * state), -1 for MAX. */
 typedef enum { DAIC_SUM = 0, DAIC_MIN = 1, DAIC_MAX = 2 } daic_op;
 
 /* The per-edge function g_{j,k} (Table 1). a_j is alpha_per_vertex[j] when
@@ -67,7 +68,7 @@ typedef enum { DAIC_SUM = 0, DAIC_MIN = 1, DAIC_MAX = 2 } daic_op;
  *   SRC_SCALE : g(x) = a_j * x               Katz (beta), HITS-like rows
  *   DEG_SCALE : g(x) = alpha * x / outdeg_j  PageRank (d / |N(j)|, sender degree)
  *   EDGE_SCALE: g(x) = a_j * w_jk * x        Adsorption, weighted linear sums
- *   EDGE_ADD  : g(x) = x + w_jk (saturating) SSSP
+ *   EDGE_ADD  : g(x) = x + w_jk              SSSP (U32: saturating at infinity)
  *   COPY      : g(x) = x                     connected components            */
 typedef enum {
   DAIC_G_SRC_SCALE = 0,
@@ -161,6 +162,9 @@ void daic_graph_destroy(daic_graph* g);
  * Allowed combinations (second and third conditions):
  *   SUM x {SRC_SCALE, DEG_SCALE, EDGE_SCALE} x {F64, F32, F32_KAHAN}
  *   MIN x EDGE_ADD x U32 (weights U32)      MAX x COPY x I32
+ *   MIN x EDGE_ADD x F64 (real weights, Sec. 6.1.2's log-normal SSSP; the
+ *     weights, of any stored type, must be >= 0 and not NaN, else
+ *     DAIC_E_INVALID)
  * alpha_per_vertex: NULL or n doubles (SRC_SCALE and EDGE_SCALE only).
  * The new problem holds v = 0 and dv = 0 (identity); call set_init.       */
 daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, double alpha_scalar,

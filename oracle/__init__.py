@@ -17,6 +17,7 @@ Contents
 * ``sweep_blocks``   -- asynchronous DAIC in blocks of B consecutive ids taken
   round-robin, each block updated together (numpy).
 * ``dijkstra``       -- SSSP distances, the min problem's textbook answer.
+* ``dijkstra_f64``   -- the same for real non-negative weights (Python heap).
 * ``maxlabel``       -- max-id reachability, the max problem's answer.
 * ``priority``       -- |v (+) dv - v| per vertex (Sec. 3.4 and Table 1 rows).
 * ``sampled_threshold`` / ``topk_exact`` -- the two selection rules of a round.
@@ -220,6 +221,34 @@ def dijkstra(g, w, source):
     if rc != 0:
         raise OverflowError("a shortest distance does not fit in 32 bits")
     return out
+
+
+def dijkstra_f64(g, w, source):
+    """SSSP distances with real non-negative weights (FP64, +inf =
+    unreachable) by Dijkstra's algorithm with a binary heap; the distance of
+    a vertex is d(u) + w(u, v) of its best settled predecessor, added once."""
+    import heapq
+
+    n = g.n
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    col = np.asarray(g.col, dtype=np.int64)
+    w = np.asarray(w, dtype=np.float64)
+    dist = np.full(n, np.inf)
+    done = np.zeros(n, dtype=bool)
+    dist[source] = 0.0
+    heap = [(0.0, int(source))]
+    while heap:
+        du, u = heapq.heappop(heap)
+        if done[u] or du > dist[u]:
+            continue
+        done[u] = True
+        for e in range(rp[u], rp[u + 1]):
+            k = col[e]
+            nd = du + w[e]
+            if nd < dist[k]:
+                dist[k] = nd
+                heapq.heappush(heap, (nd, int(k)))
+    return dist
 
 
 def maxlabel(g):

@@ -64,7 +64,7 @@ struct Ctl {
 };
 
 // Compile-time identity of a (op, g, state, row) instantiation.
-enum StateKind { ST_F64 = 0, ST_F32 = 1, ST_F32K = 2, ST_U32 = 3, ST_I32 = 4 };
+enum StateKind { ST_F64 = 0, ST_F32 = 1, ST_F32K = 2, ST_U32 = 3, ST_I32 = 4, ST_F64MIN = 5 };
 
 struct GraphDev {
   uint64_t n = 0, m = 0;

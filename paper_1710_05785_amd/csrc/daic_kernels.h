@@ -26,6 +26,8 @@ template <> struct Tr<ST_F32> { using S = float;    using Key = uint32_t; static
 template <> struct Tr<ST_F32K>{ using S = float;    using Key = uint32_t; static constexpr bool sum = true;  static constexpr bool kahan = true;  };
 template <> struct Tr<ST_U32> { using S = uint32_t; using Key = uint32_t; static constexpr bool sum = false; static constexpr bool kahan = false; };
 template <> struct Tr<ST_I32> { using S = int32_t;  using Key = uint32_t; static constexpr bool sum = false; static constexpr bool kahan = false; };
+// min over non-negative doubles (SSSP with real weights); +inf = unreached
+template <> struct Tr<ST_F64MIN> { using S = double; using Key = uint64_t; static constexpr bool sum = false; static constexpr bool kahan = false; };
 
 // Kernel arguments (passed by value).
 struct KArgs {
@@ -104,9 +106,28 @@ __device__ __forceinline__ typename Tr<ST>::Key prio_key(typename Tr<ST>::S v, t
   } else if constexpr (ST == ST_U32) {
     if (v == kInfU32) return dv < kInfU32 ? kInfU32 : 0u;
     return v - (dv < v ? dv : v);
+  } else if constexpr (ST == ST_F64MIN) {
+    // d - min(d, dd) >= 0, whose IEEE bits order like the value; a first
+    // reach (d = inf, dd finite) takes the bits of +inf, above every finite
+    if (isinf(v)) return isinf(dv) ? 0ull : 0x7FF0000000000000ull;
+    return (uint64_t)__double_as_longlong(v - (dv < v ? dv : v));
   } else {
     int64_t mx = (int64_t)(dv > v ? dv : v);
     return (uint32_t)(mx - (int64_t)v);
+  }
+}
+
+// The priority as a float (features and the learned selection key); a first
+// reach of a min problem counts as 2^32, as for the integer state.
+template <int ST>
+__device__ __forceinline__ float prio_value(typename Tr<ST>::S v, typename Tr<ST>::S dv) {
+  if constexpr (Tr<ST>::sum) {
+    return (float)fabs((double)dv);
+  } else if constexpr (ST == ST_F64MIN) {
+    if (isinf(v)) return isinf(dv) ? 0.0f : 4294967296.0f;
+    return (float)(v - (dv < v ? dv : v));
+  } else {
+    return (float)prio_key<ST>(v, dv);
   }
 }
 
@@ -118,10 +139,7 @@ __device__ __forceinline__ typename Tr<ST>::Key sel_key(const KArgs& a, uint64_t
   using Key = typename Tr<ST>::Key;
   Key k = prio_key<ST>(v, dv);
   if (a.score != nullptr && k != 0) {
-    float p;
-    if constexpr (ST == ST_F64) p = (float)fabs(dv);
-    else if constexpr (ST == ST_F32 || ST == ST_F32K) p = fabsf(dv);
-    else p = (float)k;
+    const float p = prio_value<ST>(v, dv);
     float s = p * a.score[j];
     uint32_t b = __float_as_uint(s);
     return (Key)(b == 0 ? 1u : b);  // a pending vertex keeps a positive key
@@ -184,6 +202,14 @@ __device__ __forceinline__ bool claim_fold(const KArgs& a, uint64_t j, uint64_t 
       return true;
     }
     return false;
+  } else if constexpr (ST == ST_F64MIN) {
+    dv[j] = __builtin_huge_val();
+    if (delta < v_old) {
+      v[j] = delta;
+      mu = delta;
+      return true;
+    }
+    return false;
   } else {
     dv[j] = -1;
     if (delta > v_old) {
@@ -211,6 +237,13 @@ __device__ __forceinline__ void push_edge(const KArgs& a, uint64_t e, typename T
     uint32_t m = s >= kInfU32 ? kInfU32 : (uint32_t)s;
     const uint32_t* v = static_cast<const uint32_t*>(a.v);
     if (m < v[k] && m < dv[k]) atomicMin(&dv[k], m);
+  } else if constexpr (ST == ST_F64MIN) {
+    // non-negative doubles order like their bit patterns, so the minimum is
+    // an unsigned 64-bit atomic min on the bits
+    const double m = mu + static_cast<const double*>(a.w)[e];
+    const double* v = static_cast<const double*>(a.v);
+    if (m < v[k] && m < dv[k])
+      atomicMin(reinterpret_cast<unsigned long long*>(&dv[k]), (unsigned long long)__double_as_longlong(m));
   } else {
     const int32_t* v = static_cast<const int32_t*>(a.v);
     if (mu > v[k] && mu > dv[k]) atomicMax(&dv[k], mu);
@@ -457,6 +490,8 @@ __global__ __launch_bounds__(256) void k_progress(KArgs a, double* out) {
   for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < a.n; j += (uint64_t)gridDim.x * 256) {
     if constexpr (ST == ST_U32) {
       if (v[j] != kInfU32) s += (double)v[j];
+    } else if constexpr (ST == ST_F64MIN) {
+      if (!isinf(v[j])) s += v[j];
     } else if constexpr (ST == ST_F32K) {
       s += (double)v[j] - (double)a.c[j];
     } else {

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <string>
 #include <vector>
@@ -41,7 +42,8 @@ daic_status fail(daic_status s, const char* fmt, ...) {
 
 static size_t state_size(int st) {
   switch (st) {
-    case ST_F64: return 8;
+    case ST_F64:
+    case ST_F64MIN: return 8;
     case ST_F32:
     case ST_F32K: return 4;
     default: return 4;
@@ -189,6 +191,9 @@ bool get_ops(const daic_problem* p, Ops* out) {
     case ST_U32:
       if (p->gk == DAIC_G_EDGE_ADD) return pick_row<ST_U32, DAIC_G_EDGE_ADD>(p, out);
       return false;
+    case ST_F64MIN:
+      if (p->gk == DAIC_G_EDGE_ADD) return pick_row<ST_F64MIN, DAIC_G_EDGE_ADD>(p, out);
+      return false;
     case ST_I32:
       if (p->gk == DAIC_G_COPY) return pick_row<ST_I32, DAIC_G_COPY>(p, out);
       return false;
@@ -197,6 +202,11 @@ bool get_ops(const daic_problem* p, Ops* out) {
 }
 
 // Set-up kernels that are not per instantiation.
+__global__ void k_check_nonneg(const double* w, uint64_t m, uint32_t* bad) {
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+    if (!(w[e] >= 0.0)) *bad = 1u;  // negative or NaN
+}
+
 __global__ void k_clear_done(Ctl* ctl) {
   ctl->done = 0;
   ctl->stop = 0;
@@ -476,9 +486,15 @@ daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, doub
       return fail(DAIC_E_INVALID, "DEG_SCALE takes a scalar alpha only");
   } else if (op == DAIC_MIN) {
     if (gk != DAIC_G_EDGE_ADD) return fail(DAIC_E_UNSUPPORTED, "min takes EDGE_ADD");
-    if (state != DAIC_U32) return fail(DAIC_E_UNSUPPORTED, "min takes U32 state");
-    if (!g->dev.w || g->dev.w_type != DAIC_U32) return fail(DAIC_E_INVALID, "EDGE_ADD needs U32 edge weights");
-    st = ST_U32;
+    if (state == DAIC_U32) {
+      if (!g->dev.w || g->dev.w_type != DAIC_U32) return fail(DAIC_E_INVALID, "EDGE_ADD with U32 state needs U32 edge weights");
+      st = ST_U32;
+    } else if (state == DAIC_F64) {
+      if (!g->dev.w) return fail(DAIC_E_INVALID, "EDGE_ADD needs edge weights");
+      st = ST_F64MIN;
+    } else {
+      return fail(DAIC_E_UNSUPPORTED, "min takes U32 or F64 state");
+    }
   } else if (op == DAIC_MAX) {
     if (gk != DAIC_G_COPY) return fail(DAIC_E_UNSUPPORTED, "max takes COPY");
     if (state != DAIC_I32) return fail(DAIC_E_UNSUPPORTED, "max takes I32 state");
@@ -568,6 +584,35 @@ daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, doub
       }
       a.w = p->w_conv;
     }
+  } else if (gk == DAIC_G_EDGE_ADD && st == ST_F64MIN) {
+    // real weights as doubles, which must be non-negative and not NaN (the
+    // atomic min compares bit patterns, and shortest paths need w >= 0)
+    if (d.w_type == DAIC_F64) {
+      a.w = d.w;
+    } else {
+      rc = grab(&p->w_conv, m * 8);
+      if (rc) { daic_problem_destroy(p.release()); return rc; }
+      const uint32_t gr = grid_for(m);
+      if (d.w_type == DAIC_F32) hipLaunchKernelGGL((k_convert<float, double>), dim3(gr), dim3(256), 0, s, (const float*)d.w, (double*)p->w_conv, m);
+      else hipLaunchKernelGGL((k_convert<uint32_t, double>), dim3(gr), dim3(256), 0, s, (const uint32_t*)d.w, (double*)p->w_conv, m);
+      a.w = p->w_conv;
+    }
+    uint32_t* bad = nullptr;
+    DAIC_HIP(hipMalloc(&bad, 4));
+    hipError_t e = hipMemset(bad, 0, 4);
+    if (e == hipSuccess && m)
+      hipLaunchKernelGGL(k_check_nonneg, dim3(grid_for(m)), dim3(256), 0, s, (const double*)a.w, m, bad);
+    uint32_t h_bad = 0;
+    if (e == hipSuccess) e = hipMemcpy(&h_bad, bad, 4, hipMemcpyDeviceToHost);
+    (void)hipFree(bad);
+    if (e != hipSuccess) {
+      daic_problem_destroy(p.release());
+      return fail(DAIC_E_DEVICE, "weight check: %s", hipGetErrorString(e));
+    }
+    if (h_bad) {
+      daic_problem_destroy(p.release());
+      return fail(DAIC_E_INVALID, "EDGE_ADD with F64 state needs non-negative weights (no NaN)");
+    }
   } else if (gk == DAIC_G_EDGE_ADD) {
     a.w = d.w;
   }
@@ -595,6 +640,10 @@ daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, doub
   } else if (st == ST_U32) {
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(gr), dim3(256), 0, s, (uint32_t*)a.v, kInfU32, n);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(gr), dim3(256), 0, s, (uint32_t*)a.dv, kInfU32, n);
+  } else if (st == ST_F64MIN) {
+    const double inf = std::numeric_limits<double>::infinity();
+    hipLaunchKernelGGL(k_fill<double>, dim3(gr), dim3(256), 0, s, (double*)a.v, inf, n);
+    hipLaunchKernelGGL(k_fill<double>, dim3(gr), dim3(256), 0, s, (double*)a.dv, inf, n);
   } else {
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(gr), dim3(256), 0, s, (int32_t*)a.v, -1, n);
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(gr), dim3(256), 0, s, (int32_t*)a.dv, -1, n);
@@ -618,7 +667,7 @@ daic_status daic_problem_set_init(daic_problem* p, const void* v0, const void* d
   if (!p || !v0 || !dv1) return fail(DAIC_E_INVALID, "null argument");
   const uint64_t n = p->g->dev.n;
   if (n == 0) return DAIC_OK;
-  if (p->st == ST_F64 || p->st == ST_U32 || p->st == ST_I32) {
+  if (p->st == ST_F64 || p->st == ST_U32 || p->st == ST_I32 || p->st == ST_F64MIN) {
     size_t S = state_size(p->st);
     DAIC_HIP(hipMemcpy(p->a.v, v0, n * S, hipMemcpyHostToDevice));
     DAIC_HIP(hipMemcpy(p->a.dv, dv1, n * S, hipMemcpyHostToDevice));
@@ -643,7 +692,7 @@ static double per_edge_bytes(const daic_problem* p) {
   const double S = (double)state_size(p->st);
   double b = 4.0 + 2.0 * S;  // col + RMW of dv_k
   if (p->gk == DAIC_G_EDGE_SCALE) b += S;
-  if (p->gk == DAIC_G_EDGE_ADD) b += 4.0;
+  if (p->gk == DAIC_G_EDGE_ADD) b += p->st == ST_F64MIN ? 8.0 : 4.0;
   return b;
 }
 
@@ -921,6 +970,7 @@ daic_status daic_run_progress(daic_problem* p, const daic_run_opts* o, uint64_t 
         case ST_F32: hipLaunchKernelGGL(k_progress<ST_F32>, dim3(pg), dim3(256), 0, s, p->a, dsum); break;
         case ST_F32K: hipLaunchKernelGGL(k_progress<ST_F32K>, dim3(pg), dim3(256), 0, s, p->a, dsum); break;
         case ST_U32: hipLaunchKernelGGL(k_progress<ST_U32>, dim3(pg), dim3(256), 0, s, p->a, dsum); break;
+        case ST_F64MIN: hipLaunchKernelGGL(k_progress<ST_F64MIN>, dim3(pg), dim3(256), 0, s, p->a, dsum); break;
         default: hipLaunchKernelGGL(k_progress<ST_I32>, dim3(pg), dim3(256), 0, s, p->a, dsum); break;
       }
       e = hipMemcpyAsync(&sum, dsum, sizeof(double), hipMemcpyDeviceToHost, s);
@@ -990,7 +1040,7 @@ daic_status daic_problem_get(const daic_problem* p, void* v_out, void* dv_out) {
   const uint64_t n = p->g->dev.n;
   if (n == 0) return DAIC_OK;
   DAIC_HIP(hipDeviceSynchronize());
-  if (p->st == ST_F64 || p->st == ST_U32 || p->st == ST_I32) {
+  if (p->st == ST_F64 || p->st == ST_U32 || p->st == ST_I32 || p->st == ST_F64MIN) {
     size_t S = state_size(p->st);
     DAIC_HIP(hipMemcpy(v_out, p->a.v, n * S, hipMemcpyDeviceToHost));
     if (dv_out) DAIC_HIP(hipMemcpy(dv_out, p->a.dv, n * S, hipMemcpyDeviceToHost));

@@ -578,9 +578,7 @@ __device__ __forceinline__ bool vertex_features(const KArgs& a, const uint32_t* 
   const S dv = static_cast<const S*>(a.dv)[j];
   const auto k = prio_key<ST>(v, dv);
   if (k == 0) return false;
-  float p;
-  if constexpr (Tr<ST>::sum) p = (float)fabs((double)dv);
-  else p = (float)k;
+  const float p = prio_value<ST>(v, dv);
   const uint64_t od = row_at<RowT>(a.row, j + 1) - row_at<RowT>(a.row, j);
   since = round - last_upd[j];
   f[0] = log2f(p + 1e-30f);
@@ -667,9 +665,7 @@ __global__ void k_trace_window(KArgs a, TraceDev td, uint64_t first, uint64_t la
     const S v = static_cast<const S*>(a.v)[j];
     const S dv = static_cast<const S*>(a.dv)[j];
     const auto k = prio_key<ST>(v, dv);
-    float p;
-    if constexpr (Tr<ST>::sum) p = (float)fabs((double)dv);
-    else p = (float)k;
+    float p = prio_value<ST>(v, dv);
     if (k == 0) p = 0.f;
     td.maxp[o] = fmaxf(td.maxp[o], p);
   }
@@ -715,6 +711,7 @@ static LearnedOps learned_ops(const daic_problem* p) {
     case ST_F32: return lops_row<ST_F32>(p);
     case ST_F32K: return lops_row<ST_F32K>(p);
     case ST_U32: return lops_row<ST_U32>(p);
+    case ST_F64MIN: return lops_row<ST_F64MIN>(p);
     default: return lops_row<ST_I32>(p);
   }
 }

@@ -151,6 +151,52 @@ def test_sssp_rmat20_full_config(daic):
     np.testing.assert_array_equal(p.get(), ref)
 
 
+def sssp_f64_problem(daic, g, w, source=0):
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="f64")
+    v0 = np.full(g.n, np.inf)
+    dv1 = np.full(g.n, np.inf)
+    dv1[source] = 0.0
+    p.set_init(v0, dv1)
+    return p
+
+
+@pytest.mark.parametrize("graph", ["rmat16", "paper_lognormal"])
+@pytest.mark.parametrize("sched,q", [("all", 1.0), ("sampled", 0.1), ("exact", 0.1)])
+def test_sssp_f64_lognormal_weights_bit_exact(daic, graph, sched, q):
+    """SSSP with the paper's real log-normal(0, 1) edge weights (Sec. 6.1) in
+    FP64: min over d(u) + w(u, v) is exact in the sense that every path sum
+    is formed once, left to right, so the fixed point equals the heap
+    Dijkstra's distances bit for bit."""
+    say("case sssp f64", graph, sched, q)
+    if graph == "rmat16":
+        g = daic_gen.rmat(16, 16, seed=81)
+    else:
+        g = daic_gen.paper_lognormal(20000, seed=82)
+    w = daic_gen.lognormal_f64(83, g.m, 0.0, 1.0)
+    ref = oracle.dijkstra_f64(g, w, 0)
+    for _ in range(2):
+        p = sssp_f64_problem(daic, g, w)
+        res = p.run(q=q, sched=sched, seed=3)
+        assert res.converged
+        got = p.get()
+        np.testing.assert_array_equal(got, ref)
+    # weights stored as float32 are widened to double first
+    w32 = w.astype(np.float32)
+    p = sssp_f64_problem(daic, g, w32)
+    assert p.run(q=1.0, sched="all").converged
+    np.testing.assert_array_equal(p.get(), oracle.dijkstra_f64(g, w32.astype(np.float64), 0))
+
+
+def test_sssp_f64_rejects_negative_or_nan_weights(daic):
+    say("case sssp f64 invalid weights")
+    g = daic_gen.rmat(8, 4, seed=2)
+    for bad in (-1.0, np.nan):
+        w = np.ones(g.m)
+        w[g.m // 2] = bad
+        with pytest.raises(daic.DaicError):
+            daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="f64")
+
+
 @pytest.mark.parametrize("symmetric", [False, True])
 @pytest.mark.parametrize("sched,q", [("all", 1.0), ("exact", 0.3)])
 def test_components_max_label_bit_exact(daic, symmetric, sched, q):

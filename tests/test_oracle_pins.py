@@ -415,6 +415,53 @@ def test_async_min_matches_dijkstra_on_rmat():
         assert r["residual"] == 0
 
 
+@pytest.mark.parametrize("seed", [5, 6, 7])
+def test_dijkstra_f64_vs_bellman_ford_and_scipy(seed):
+    """Real log-normal weights (the paper's SSSP data, Sec. 6.1): the heap
+    Dijkstra equals Bellman-Ford relaxation to a fixed point, and scipy's
+    Dijkstra on the graph with duplicate edges reduced to the lightest."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra as sp_dijkstra
+
+    g = random_graph(200, 1500, seed)
+    w = daic_gen.lognormal_f64(seed, g.m, 0.0, 1.0)
+    got = oracle.dijkstra_f64(g, w, 0)
+    # Bellman-Ford: relax every edge until nothing changes
+    src = np.repeat(np.arange(g.n), g.outdeg())
+    col = g.col.astype(np.int64)
+    bf = np.full(g.n, np.inf)
+    bf[0] = 0.0
+    for _ in range(g.n):
+        cand = bf[src] + w
+        new = bf.copy()
+        np.minimum.at(new, col, cand)
+        if np.array_equal(new, bf):
+            break
+        bf = new
+    np.testing.assert_array_equal(got, bf)
+    best = {}
+    for s_, t_, w_ in zip(src, col, w):
+        if s_ == t_:
+            continue  # a self-loop never shortens a path
+        if (s_, t_) not in best or w_ < best[(s_, t_)]:
+            best[(s_, t_)] = w_
+    keys = np.array(list(best.keys()), dtype=np.int64).reshape(-1, 2)
+    M = csr_matrix((np.array(list(best.values())), (keys[:, 0], keys[:, 1])), shape=(g.n, g.n))
+    ref = sp_dijkstra(M, directed=True, indices=0)
+    np.testing.assert_allclose(got, ref, rtol=1e-15, atol=0)
+    assert np.array_equal(np.isinf(got), np.isinf(ref))
+
+
+def test_dijkstra_f64_integer_weights_match_u32_oracle():
+    g = daic_gen.rmat(10, 8, seed=3)
+    w = daic_gen.sssp_weights(g.m, seed=4)
+    got = oracle.dijkstra_f64(g, w.astype(np.float64), 0)
+    ref = oracle.dijkstra(g, w, 0)
+    reach = ref != 0xFFFFFFFF
+    np.testing.assert_array_equal(got[reach], ref[reach].astype(np.float64))
+    assert np.all(np.isinf(got[~reach]))
+
+
 def test_sssp_path_graph_prefix_sums():
     n = 50
     g = daic_gen.from_edges(n, np.arange(n - 1), np.arange(1, n))
