@@ -203,7 +203,11 @@ daic_status daic_select_frontier(daic_problem* p, const daic_run_opts* opts, uin
  * together: every kernel of a round covers every graph, and K rounds are one
  * hipGraph launch. Each instance (graph, right-hand side) has its own
  * residual and stop flag; a run ends when every instance has residual <= eps.
- * op must be DAIC_SUM with DAIC_G_DEG_SCALE; state DAIC_F32 or F32_KAHAN.
+ * op must be DAIC_SUM with DAIC_G_DEG_SCALE, or with DAIC_G_EDGE_SCALE
+ * (g(x) = alpha w_jk x; every graph with edges must carry weights; e.g.
+ * multi-label Adsorption with one label per right-hand side and the
+ * receiver's continuation probability folded into w); state DAIC_F32 or
+ * F32_KAHAN.
  * The graphs are copied into one block-diagonal graph; they may be destroyed
  * after the call.                                                           */
 daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs,

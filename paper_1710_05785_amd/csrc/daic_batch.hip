@@ -66,6 +66,8 @@ struct BArgs {
   float* c;                   // Kahan term, or null
   float* mu;                  // [N][64]: by vertex (sparse) / renumbered, even rounds (dense)
   float* mu2;                 // [N][64]: renumbered, odd rounds (dense)
+  const float* w;             // EDGE_SCALE: weight of each out-edge, or null (DEG_SCALE)
+  const float* wT;            // the same in in-edge order
   uint8_t* active;            // [N] vertex sent this round (sparse rounds)
   uint8_t* done;              // [G][64] instance finished
   double alpha;
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(256) void k_bclaim(BArgs a) {
     if (j >= a.N) continue;
     const uint32_t g = a.gid[j];
     const uint32_t deg = a.row[j + 1] - a.row[j];
-    const double coef = deg ? a.alpha / (double)deg : 0.0;
+    const double coef = a.w ? a.alpha : (deg ? a.alpha / (double)deg : 0.0);
     float d[W], mu[W];
     bool cl[W];
     vload<W>(a.dv + j * kR + r0, d);
@@ -249,9 +251,10 @@ __global__ __launch_bounds__(256) void k_bpush(BArgs a) {
     vload<W>(a.mu + (uint64_t)j * kR + r0, mu);
     for (uint32_t e = beg; e < end; ++e) {
       float* dst = a.dv + (uint64_t)a.col[e] * kR + r0;
+      const float we = a.w ? a.w[e] : 1.0f;
 #pragma unroll
       for (int k = 0; k < W; ++k)
-        if (mu[k] != 0.0f) unsafeAtomicAdd(dst + k, mu[k]);
+        if (mu[k] != 0.0f) unsafeAtomicAdd(dst + k, a.w ? mu[k] * we : mu[k]);
     }
   }
 }
@@ -405,7 +408,38 @@ __global__ __launch_bounds__(256) void k_bresidual(BArgs a, int count_round) {
 // of kBChunk in-edges) adds the previous round's message bases into dv, for
 // the instances whose messages are not yet all delivered; atomics where a
 // target has several chunks.
-template <int LPV>
+// Sum over in-edges [beg, end) of the message-base vectors (times the edge
+// weight under EDGE_SCALE), four gathers in flight per lane.
+template <int W, bool WGT>
+__device__ __forceinline__ void bgather(const BArgs& a, const float* mu_in, uint32_t beg, uint32_t end, uint32_t r0,
+                                        float (&acc)[W]) {
+  uint32_t p = beg;
+  for (; p + 3 < end; p += 4) {
+    const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
+    float x0[W], x1[W], x2[W], x3[W];
+    vload<W>(mu_in + (uint64_t)s0 * kR + r0, x0);
+    vload<W>(mu_in + (uint64_t)s1 * kR + r0, x1);
+    vload<W>(mu_in + (uint64_t)s2 * kR + r0, x2);
+    vload<W>(mu_in + (uint64_t)s3 * kR + r0, x3);
+    if constexpr (WGT) {
+      const float w0 = a.wT[p], w1 = a.wT[p + 1], w2 = a.wT[p + 2], w3 = a.wT[p + 3];
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc[k] += (x0[k] * w0 + x1[k] * w1) + (x2[k] * w2 + x3[k] * w3);
+    } else {
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc[k] += (x0[k] + x1[k]) + (x2[k] + x3[k]);
+    }
+  }
+  for (; p < end; ++p) {
+    float x[W];
+    vload<W>(mu_in + (uint64_t)a.srcT[p] * kR + r0, x);
+    const float wp = WGT ? a.wT[p] : 1.0f;
+#pragma unroll
+    for (int k = 0; k < W; ++k) acc[k] += WGT ? x[k] * wp : x[k];
+  }
+}
+
+template <int LPV, bool WGT>
 __global__ __launch_bounds__(256) void k_bhub(BArgs a, int final_pass) {
   constexpr int W = kR / LPV;
   constexpr int IPB = 256 / LPV;
@@ -431,23 +465,7 @@ __global__ __launch_bounds__(256) void k_bhub(BArgs a, int final_pass) {
     float acc[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) acc[k] = 0.0f;
-    uint32_t p = beg;
-    for (; p + 3 < end; p += 4) {
-      const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
-      float x0[W], x1[W], x2[W], x3[W];
-      vload<W>(mu_in + (uint64_t)s0 * kR + r0, x0);
-      vload<W>(mu_in + (uint64_t)s1 * kR + r0, x1);
-      vload<W>(mu_in + (uint64_t)s2 * kR + r0, x2);
-      vload<W>(mu_in + (uint64_t)s3 * kR + r0, x3);
-#pragma unroll
-      for (int k = 0; k < W; ++k) acc[k] += (x0[k] + x1[k]) + (x2[k] + x3[k]);
-    }
-    for (; p < end; ++p) {
-      float x[W];
-      vload<W>(mu_in + (uint64_t)a.srcT[p] * kR + r0, x);
-#pragma unroll
-      for (int k = 0; k < W; ++k) acc[k] += x[k];
-    }
+    bgather<W, WGT>(a, mu_in, beg, end, r0, acc);
     float* dst = a.dv + (uint64_t)t * kR + r0;
     if (a.rowT[t + 1] - a.rowT[t] <= kBChunk) {
       float d[W];
@@ -472,7 +490,7 @@ __global__ __launch_bounds__(256) void k_bhub(BArgs a, int final_pass) {
 // ping-pong buffer). Instances finished at the previous check get their last
 // messages delivered into dv; instances delivered earlier are skipped.
 // final_pass: delivery only, after a stop in the dense phase.
-template <int LPV, bool KAHAN>
+template <int LPV, bool KAHAN, bool WGT>
 __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
   constexpr int W = kR / LPV;
   constexpr int VPB = 256 / LPV;
@@ -527,23 +545,7 @@ __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
       } else {
 #pragma unroll
         for (int k = 0; k < W; ++k) d[k] = 0.0f;
-        uint32_t p = b0;
-        for (; p + 3 < b1; p += 4) {
-          const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
-          float x0[W], x1[W], x2[W], x3[W];
-          vload<W>(mu_in + (uint64_t)s0 * kR + r0, x0);
-          vload<W>(mu_in + (uint64_t)s1 * kR + r0, x1);
-          vload<W>(mu_in + (uint64_t)s2 * kR + r0, x2);
-          vload<W>(mu_in + (uint64_t)s3 * kR + r0, x3);
-#pragma unroll
-          for (int k = 0; k < W; ++k) d[k] += (x0[k] + x1[k]) + (x2[k] + x3[k]);
-        }
-        for (; p < b1; ++p) {
-          float xs[W];
-          vload<W>(mu_in + (uint64_t)a.srcT[p] * kR + r0, xs);
-#pragma unroll
-          for (int k = 0; k < W; ++k) d[k] += xs[k];
-        }
+        bgather<W, WGT>(a, mu_in, b0, b1, r0, d);
       }
       bool cl[W], claim_any = false;
       uint32_t nclaim = 0;
@@ -579,7 +581,7 @@ __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
       }
       if (run_any) {
         const uint32_t deg = a.row[j + 1] - a.row[j];
-        const double coef = deg ? a.alpha / (double)deg : 0.0;
+        const double coef = WGT ? a.alpha : (deg ? a.alpha / (double)deg : 0.0);
         float mu[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) mu[k] = cl[k] ? (float)(coef * (double)d[k]) : 0.0f;
@@ -656,6 +658,21 @@ __global__ void k_union_cols(const uint32_t* col, uint64_t m, uint64_t voff, uin
 
 __global__ void k_set_last(uint32_t* p, uint64_t idx, uint32_t val) { p[idx] = val; }
 
+// Union edge weights (as float) of graph g at its edge offset.
+template <typename T>
+__global__ void k_union_weights(const T* w, uint64_t m, uint64_t eoff, float* uw) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = i; e < m; e += st) uw[eoff + e] = (float)w[e];
+}
+
+// Weights in in-edge order: wT[p] = w[eidT[p]].
+__global__ void k_bgather_weights(const float* w, const uint32_t* eidT, uint64_t m, float* wT) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t p = i; p < m; p += st) wT[p] = w[eidT[p]];
+}
+
 static uint32_t bgrid(uint64_t count, uint32_t block = 256) {
   uint64_t g = (count + block - 1) / block;
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, 8192));
@@ -710,13 +727,19 @@ static void enqueue_claim(daic_batch* b, hipStream_t s) {
   hipLaunchKernelGGL(k_bstats, dim3(1), dim3(256), 0, s, b->a, b->tune.grid_claim);
 }
 
+template <int LPV, bool WGT>
+static void launch_dense_w(daic_batch* b, hipStream_t s, int final_pass) {
+  if (b->a.n_hub) hipLaunchKernelGGL((k_bhub<LPV, WGT>), dim3(b->tune.grid_hub), dim3(256), 0, s, b->a, final_pass);
+  if (b->kahan)
+    hipLaunchKernelGGL((k_bfused<LPV, true, WGT>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
+  else
+    hipLaunchKernelGGL((k_bfused<LPV, false, WGT>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
+}
+
 template <int LPV>
 static void launch_dense(daic_batch* b, hipStream_t s, int final_pass) {
-  if (b->a.n_hub) hipLaunchKernelGGL(k_bhub<LPV>, dim3(b->tune.grid_hub), dim3(256), 0, s, b->a, final_pass);
-  if (b->kahan)
-    hipLaunchKernelGGL((k_bfused<LPV, true>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
-  else
-    hipLaunchKernelGGL((k_bfused<LPV, false>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
+  if (b->a.w) launch_dense_w<LPV, true>(b, s, final_pass);
+  else launch_dense_w<LPV, false>(b, s, final_pass);
 }
 
 // Dense-phase round (hub sums, then the fused pass); both kernels return at
@@ -767,8 +790,9 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
   if (!out) return fail(DAIC_E_INVALID, "out is null");
   *out = nullptr;
   if (n_graphs == 0 || !graphs || !rhs_per_graph) return fail(DAIC_E_INVALID, "no graphs");
-  if (op != DAIC_SUM || gk != DAIC_G_DEG_SCALE)
-    return fail(DAIC_E_UNSUPPORTED, "batched runs take SUM with DEG_SCALE (personalized PageRank)");
+  if (op != DAIC_SUM || (gk != DAIC_G_DEG_SCALE && gk != DAIC_G_EDGE_SCALE))
+    return fail(DAIC_E_UNSUPPORTED,
+                "batched runs take SUM with DEG_SCALE (personalized PageRank) or EDGE_SCALE (weighted, e.g. Adsorption)");
   if (state != DAIC_F32 && state != DAIC_F32_KAHAN)
     return fail(DAIC_E_UNSUPPORTED, "batched runs take F32 or F32_KAHAN state");
   if (!std::isfinite(alpha)) return fail(DAIC_E_INVALID, "alpha must be finite");
@@ -778,6 +802,8 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
     if (rhs_per_graph[g] == 0 || rhs_per_graph[g] > (uint32_t)kR)
       return fail(DAIC_E_INVALID, "right-hand sides per graph must be in 1..%d", kR);
     if (!graphs[g]->dev.row32) return fail(DAIC_E_UNSUPPORTED, "graph %u has m >= 2^32", g);
+    if (gk == DAIC_G_EDGE_SCALE && graphs[g]->dev.m && !graphs[g]->dev.w)
+      return fail(DAIC_E_INVALID, "EDGE_SCALE needs edge weights (graph %u has none)", g);
     N += graphs[g]->dev.n;
     M += graphs[g]->dev.m;
   }
@@ -810,6 +836,11 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
   ucol = (uint32_t*)ptr;
   if ((rc = grab(&ptr, N * 4))) { daic_batch_destroy(b.release()); return rc; }
   gid = (uint32_t*)ptr;
+  float* uw = nullptr;
+  if (gk == DAIC_G_EDGE_SCALE) {
+    if ((rc = grab(&ptr, M * 4))) { daic_batch_destroy(b.release()); return rc; }
+    uw = (float*)ptr;
+  }
   uint64_t voff = 0, eoff = 0;
   for (uint32_t g = 0; g < n_graphs; ++g) {
     const GraphDev& d = graphs[g]->dev;
@@ -818,6 +849,14 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
     if (d.n) hipLaunchKernelGGL(k_union_rows, dim3(bgrid(d.n)), dim3(256), 0, s, static_cast<const uint32_t*>(d.row),
                                 d.n, voff, eoff, g, urow, gid);
     if (d.m) hipLaunchKernelGGL(k_union_cols, dim3(bgrid(d.m)), dim3(256), 0, s, d.col, d.m, voff, eoff, ucol);
+    if (uw && d.m) {
+      if (d.w_type == DAIC_F64)
+        hipLaunchKernelGGL(k_union_weights<double>, dim3(bgrid(d.m)), dim3(256), 0, s, (const double*)d.w, d.m, eoff, uw);
+      else if (d.w_type == DAIC_F32)
+        hipLaunchKernelGGL(k_union_weights<float>, dim3(bgrid(d.m)), dim3(256), 0, s, (const float*)d.w, d.m, eoff, uw);
+      else
+        hipLaunchKernelGGL(k_union_weights<uint32_t>, dim3(bgrid(d.m)), dim3(256), 0, s, (const uint32_t*)d.w, d.m, eoff, uw);
+    }
     voff += d.n;
     eoff += d.m;
   }
@@ -1013,6 +1052,13 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
   a.perm = ug->pull.perm;
   a.rowT = static_cast<const uint32_t*>(ug->pull.rowT);
   a.srcT = ug->pull.srcT;
+  if (uw) {
+    if ((rc = grab(&ptr, M * 4))) { daic_batch_destroy(b.release()); return rc; }
+    float* uwT = (float*)ptr;
+    if (M) hipLaunchKernelGGL(k_bgather_weights, dim3(bgrid(M)), dim3(256), 0, s, uw, ug->pull.eidT, M, uwT);
+    a.w = uw;
+    a.wT = uwT;
+  }
   a.pull_min = std::max<uint64_t>(1, N / 32);
   DAIC_HIP(hipMemsetAsync(a.v, 0, SV, s));
   DAIC_HIP(hipMemsetAsync(a.dv, 0, SV, s));
@@ -1064,8 +1110,8 @@ daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len) {
   hipStream_t s = b->stream;
   BArgs& a = b->a;
   char key[160];
-  std::snprintf(key, sizeof key, "batch-fused N=%llu M=%llu G=%u kahan=%d", (unsigned long long)a.N,
-                (unsigned long long)b->ug->dev.m, b->G, (int)b->kahan);
+  std::snprintf(key, sizeof key, "batch-fused N=%llu M=%llu G=%u kahan=%d weighted=%d", (unsigned long long)a.N,
+                (unsigned long long)b->ug->dev.m, b->G, (int)b->kahan, a.w ? 1 : 0);
   const char* cache = std::getenv("DAIC_TUNE_CACHE");
   if (cache) {
     if (FILE* f = std::fopen(cache, "r")) {

@@ -336,10 +336,12 @@ class Problem:
 
 
 class Batch:
-    """Many graphs x many right-hand sides of personalized PageRank solved
-    together (daic_batch). rhs: one count (<= 64) or one per graph."""
+    """Many graphs x many right-hand sides solved together (daic_batch):
+    personalized PageRank (g=G_DEG_SCALE) or weighted sums such as
+    multi-label Adsorption (g=G_EDGE_SCALE, graphs with weights). rhs: one
+    count (<= 64) or one per graph."""
 
-    def __init__(self, graphs, rhs, alpha: float, state="f32"):
+    def __init__(self, graphs, rhs, alpha: float, state="f32", g=None):
         self.graphs = list(graphs)
         G = len(self.graphs)
         self.rhs = [int(rhs)] * G if np.isscalar(rhs) else [int(r) for r in rhs]
@@ -348,7 +350,8 @@ class Batch:
         r = np.ascontiguousarray(self.rhs, dtype=np.uint32)
         st = _STATE_NAMES[state] if isinstance(state, str) else state
         h = _vp()
-        check(lib().daic_batch_create(G, handles, _addr(r), SUM, G_DEG_SCALE, float(alpha), st,
+        gk = G_DEG_SCALE if g is None else g
+        check(lib().daic_batch_create(G, handles, _addr(r), SUM, gk, float(alpha), st,
                                       ctypes.byref(h)), "daic_batch_create")
         self._h = h
 

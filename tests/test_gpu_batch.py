@@ -160,3 +160,67 @@ def test_batched_stop_in_dense_phase_delivers(daic):
     for r in (0, 31, 63):
         ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1[:, r], eps=1e-14)
         assert np.abs(v[:, r] - ref).sum() <= 1e-5 * ref.sum()
+
+
+def adsorption_case(g, seed):
+    """Adsorption (Table 1): A column-normalized from log-normal(0.4, 0.8)
+    weights (the sum of a vertex's in-edge weights is 1), p_cont ~ U[0.5, 0.9]
+    per vertex, p_inj = 1 - p_cont; g_{i,j}(x) = p_cont_j A(i,j) x is folded
+    into one weight per edge (receiver's coefficient, reading 4)."""
+    raw = daic_gen.lognormal_f64(seed, g.m, 0.4, 0.8)
+    col = g.col.astype(np.int64)
+    insum = np.bincount(col, weights=raw, minlength=g.n)
+    A = raw / np.where(insum[col] > 0, insum[col], 1.0)
+    rng = np.random.default_rng(seed)
+    p_cont = rng.uniform(0.5, 0.9, g.n)
+    return A * p_cont[col], 1.0 - p_cont
+
+
+@pytest.mark.parametrize("state", ["f32", "f32_kahan"])
+def test_batched_multilabel_adsorption_matches_oracle(daic, state):
+    """Multi-label Adsorption through the batched path: one label per
+    right-hand side (64 labels), dv1_{j,l} = p_inj_j I_{j,l}; every label of
+    every graph against the oracle's FP64 traditional iteration."""
+    say("case batch adsorption", state)
+    gs = [daic_gen.rmat(11, 8, seed=301), daic_gen.paper_lognormal(3000, seed=302),
+          daic_gen.from_edges(40, [], []), daic_gen.rmat(9, 16, seed=303)]
+    labels = 64
+    ws, inits = [], []
+    dgs = []
+    for i, g in enumerate(gs):
+        if g.m:
+            w, p_inj = adsorption_case(g, 310 + i)
+            dgs.append(daic.Graph(g.row_ptr, g.col, w))
+        else:
+            w, p_inj = None, np.full(g.n, 0.3)
+            dgs.append(daic.Graph(g.row_ptr, g.col))
+        ws.append(w)
+        seeds = ppr_inputs(g, 320 + i, 64 * i, labels, 0.0, max_k=8) if g.m else None
+        dv1 = np.zeros((g.n, labels))
+        if seeds is not None:
+            dv1 = (seeds > 0) * p_inj[:, None]
+        else:
+            dv1[np.arange(labels) % g.n, np.arange(labels)] = p_inj[0]
+        inits.append(dv1)
+    b = daic.Batch(dgs, labels, alpha=1.0, state=state, g=daic.G_EDGE_SCALE)
+    for i, g in enumerate(gs):
+        b.set_init(i, np.zeros((g.n, labels)), inits[i])
+    say("tuned:", b.tune())
+    res, inst = b.run(eps=1e-7, rounds_per_check=4)
+    assert res.converged and np.all(inst <= 1e-7)
+    for i, g in enumerate(gs):
+        v = b.get(i)
+        for l in range(0, labels, 7):
+            if g.m:
+                ref, _, _ = oracle.jacobi_sum(g, oracle.G_EDGE_SCALE, 1.0, inits[i][:, l], w=ws[i], eps=1e-14)
+            else:
+                ref = inits[i][:, l]
+            den = max(np.abs(ref).sum(), 1e-300)
+            assert np.abs(v[:, l] - ref).sum() / den <= 1e-5, (i, l)
+
+
+def test_batched_edge_scale_needs_weights(daic):
+    say("case batch edge scale without weights")
+    g = daic_gen.rmat(8, 4, seed=5)
+    with pytest.raises(daic.DaicError):
+        daic.Batch([daic.Graph(g.row_ptr, g.col)], 8, alpha=1.0, g=daic.G_EDGE_SCALE)
