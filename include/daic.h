@@ -221,7 +221,10 @@ daic_status daic_batch_set_init(daic_batch* b, uint32_t graph, const double* v0,
  * DAIC_TUNE_CACHE set, results are cached in that file. desc receives a
  * description of the choice (nullable). */
 daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len);
-/* Run every instance to residual <= eps (sched ALL, q = 1). inst_residual
+/* Run every instance to residual <= eps: sched ALL (q = 1; synchronous dense
+ * rounds) or SWEEP (dense rounds take blocks of ceil(q n_g) vertices of
+ * every graph in turn, each pulling the newest message of every
+ * in-neighbour; one round is one block). inst_residual
  * (nullable) receives the final residual of every instance, graph-major.
  * stats->final_residual is the largest instance residual. Instances are
  * updated until the check after the round in which their residual fell to

@@ -35,18 +35,30 @@ constexpr uint32_t kPushChunk = 256;   // out-edges per push item
 constexpr uint32_t kResChunk = 4096;   // at most this many vertices per residual item
 constexpr uint32_t kItemWork = 32768;  // and about this much work (in-edges + kVertexWork per vertex)
 constexpr uint32_t kVertexWork = 4;
+// sweep rounds run one block (a fraction of the items) per launch, so their
+// items are smaller: the longest item bounds each launch
+constexpr uint32_t kSwResChunk = 1024;
+constexpr uint32_t kSwItemWork = 8192;
+constexpr uint32_t kSwHubChunk = 256;
 constexpr uint32_t kHubDeg = 64;       // default in-degree above which a target is a hub
 
 // Round modes: 0 = sparse round (claim, push, residual); 1 = the claim that
 // starts the dense phase (publishes message bases, delivers nothing);
 // 2 = fused dense round (deliver the previous round's messages by pulling,
-// then claim and publish, with the residual in the same pass).
+// then claim and publish, with the residual in the same pass); 3 = sweep
+// round (the fused pass over one block of every graph, pulling the newest
+// message of every in-neighbour; see k_bfused).
 struct BCtl {
   uint32_t done;          // every instance finished and nothing in flight
   uint32_t stop;          // round limit reached
   uint32_t mode;          // mode of the next round
   uint32_t ticket;
   uint32_t prev_all_done; // every instance was finished after the previous round
+  uint32_t dense_mode;    // mode the dense phase starts in: 1 (synchronous) or 3 (sweep)
+  uint32_t sw_c;          // sweep rounds: block of the current round
+  uint32_t sw_started;    // a sweep round has run since the dense phase began
+  uint64_t sw_k;          // sweep rounds: sweep of the current round
+  uint64_t base;          // round at which the sweep phase began
   uint64_t rounds;
   uint64_t max_rounds;
   uint64_t pending;       // vertices with a pending right-hand side
@@ -103,10 +115,20 @@ struct BArgs {
   // fused dense rounds: in-edges of hub targets (in-degree > hub_deg) are
   // summed by a chunked kernel before the fused pass
   uint32_t hub_deg;
+  uint32_t hub_chunk;         // in-edges per hub item
   const uint32_t* ht;         // hub items (target, chunk)
   const uint32_t* hc;
   uint64_t n_hub;
   const uint32_t* item_order; // block -> residual item of the fused pass (~0u: none)
+  // sweep rounds (the sweep copy of these arguments also points the item,
+  // hub-item, source-numbering and partial fields at the sweep's own arrays)
+  uint32_t sw_P;              // blocks per graph
+  const uint64_t* sw_bstart;  // [P+1] first sweep number of each block
+  const uint32_t* sw_items;   // items of each block (XCD-interleaved, ~0u padding)
+  const uint32_t* sw_ioff;    // [P+1]
+  const uint32_t* sw_hoff;    // [P+1] hub items of each block
+  const double* sw_coef;      // [N] sum of |w| (1 per edge when unweighted) to out-neighbours in blocks <= own
+  const uint32_t* sw_blk;     // [N] block of each vertex
   const uint32_t* vord;       // [N] vertices of each item by pulled in-degree, descending, isolated last
   const uint64_t* rha;        // [n_res] end of the item's vertices that have any edge
   uint32_t n_fused_blocks;
@@ -151,7 +173,7 @@ __global__ __launch_bounds__(256) void k_bclaim(BArgs a) {
   constexpr int W = kR / LPV;
   constexpr int VPB = 256 / LPV;
   BCtl* ctl = a.ctl;
-  if (bhalted(ctl) || ctl->mode == 2) return;
+  if (bhalted(ctl) || ctl->mode >= 2) return;
   const bool pull = ctl->mode == 1;
   float* mu_dense = mu_of_round(a, ctl->rounds);
   const uint32_t sub = threadIdx.x / LPV;
@@ -304,7 +326,7 @@ __device__ void retire_item(const BArgs& a, uint32_t g, int kind, int count_roun
     bool flag;
     if (kind == 0) {
       a.inst_r[q] = sr;
-      if (st == 0 && sr <= ctl->eps) ns = 2;
+      if (st == 1 || (st == 0 && sr <= ctl->eps)) ns = 2;  // state 1: delivered since
       flag = ns == 2;
     } else if (kind == 1) {
       if (st != 2) a.inst_r[q] = sr;
@@ -360,7 +382,9 @@ __device__ void retire_item(const BArgs& a, uint32_t g, int kind, int count_roun
     ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
     if (kind == 0) {
       ctl->pending = pp;
-      ctl->mode = (!done && pp >= a.pull_min) ? 1u : 0u;
+      ctl->mode = (!done && pp >= a.pull_min) ? ctl->dense_mode : 0u;
+      ctl->base = ctl->rounds;
+      ctl->sw_started = 0;
     }
   }
 }
@@ -371,7 +395,7 @@ __device__ void retire_item(const BArgs& a, uint32_t g, int kind, int count_roun
 // the round and switches to fused rounds.
 __global__ __launch_bounds__(256) void k_bresidual(BArgs a, int count_round) {
   BCtl* ctl = a.ctl;
-  if (bhalted(ctl) || ctl->mode == 2) return;
+  if (bhalted(ctl) || ctl->mode >= 2) return;
   if (ctl->mode == 1) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       ctl->rounds += (uint64_t)count_round;
@@ -439,18 +463,88 @@ __device__ __forceinline__ void bgather(const BArgs& a, const float* mu_in, uint
   }
 }
 
-template <int LPV, bool WGT>
+// Sweep rounds: the same sum, each source read from the slot of the sweep
+// that last published it: this sweep's (cur) when its sweep number is below
+// lo (an earlier block), else the previous sweep's (prev), which does not
+// exist in the first sweep (prev_ok false: those terms are 0).
+template <int W, bool WGT>
+__device__ __forceinline__ void bgather_sweep(const BArgs& a, const float* cur, const float* prev, uint32_t lo,
+                                              bool prev_ok, uint32_t beg, uint32_t end, uint32_t r0,
+                                              float (&acc)[W]) {
+  uint32_t p = beg;
+  for (; p + 3 < end; p += 4) {
+    const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
+    const bool n0 = s0 < lo, n1 = s1 < lo, n2 = s2 < lo, n3 = s3 < lo;
+    float x0[W], x1[W], x2[W], x3[W];
+    vload<W>((n0 ? cur : prev) + (uint64_t)s0 * kR + r0, x0);
+    vload<W>((n1 ? cur : prev) + (uint64_t)s1 * kR + r0, x1);
+    vload<W>((n2 ? cur : prev) + (uint64_t)s2 * kR + r0, x2);
+    vload<W>((n3 ? cur : prev) + (uint64_t)s3 * kR + r0, x3);
+    const bool o0 = n0 || prev_ok, o1 = n1 || prev_ok, o2 = n2 || prev_ok, o3 = n3 || prev_ok;
+    const float w0 = WGT ? a.wT[p] : 1.0f, w1 = WGT ? a.wT[p + 1] : 1.0f;
+    const float w2 = WGT ? a.wT[p + 2] : 1.0f, w3 = WGT ? a.wT[p + 3] : 1.0f;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+      acc[k] += ((o0 ? x0[k] * w0 : 0.0f) + (o1 ? x1[k] * w1 : 0.0f)) +
+                ((o2 ? x2[k] * w2 : 0.0f) + (o3 ? x3[k] * w3 : 0.0f));
+  }
+  for (; p < end; ++p) {
+    const uint32_t sp = a.srcT[p];
+    const bool np = sp < lo;
+    float x[W];
+    vload<W>((np ? cur : prev) + (uint64_t)sp * kR + r0, x);
+    const bool op = np || prev_ok;
+    const float wp = WGT ? a.wT[p] : 1.0f;
+#pragma unroll
+    for (int k = 0; k < W; ++k) acc[k] += op ? x[k] * wp : 0.0f;
+  }
+}
+
+// Sweep rounds: block c of sweep k runs as round base + k P + c; the block
+// and sweep are set here, before the round's kernels, and the round limit
+// is applied.
+__global__ void k_bstep(BArgs a) {
+  BCtl* ctl = a.ctl;
+  if (bhalted(ctl) || ctl->mode != 3) return;
+  if (ctl->rounds >= ctl->max_rounds) {
+    ctl->stop = 1;
+    return;
+  }
+  const uint64_t r = ctl->rounds - ctl->base;
+  ctl->sw_c = (uint32_t)(r % a.sw_P);
+  ctl->sw_k = r / a.sw_P;
+  ctl->sw_started = 1;
+  ctl->rounds += 1;
+}
+
+template <int LPV, bool WGT, bool SWEEP>
 __global__ __launch_bounds__(256) void k_bhub(BArgs a, int final_pass) {
   constexpr int W = kR / LPV;
   constexpr int IPB = 256 / LPV;
   BCtl* ctl = a.ctl;
-  if (!final_pass && (bhalted(ctl) || ctl->mode != 2)) return;
-  const float* mu_in = mu_of_round(a, ctl->rounds - 1);
+  const float *mu_in, *mu_prev = nullptr;
+  uint64_t i0 = 0, i1 = a.n_hub;
+  uint32_t lo = 0;
+  bool prev_ok = true;
+  if constexpr (SWEEP) {
+    if (bhalted(ctl) || ctl->mode != 3) return;
+    const uint32_t c = ctl->sw_c;
+    const uint64_t k = ctl->sw_k;
+    i0 = a.sw_hoff[c];
+    i1 = a.sw_hoff[c + 1];
+    mu_in = (k & 1) ? a.mu2 : a.mu;
+    mu_prev = (k & 1) ? a.mu : a.mu2;
+    lo = (uint32_t)a.sw_bstart[c];
+    prev_ok = k > 0;
+  } else {
+    if (!final_pass && (bhalted(ctl) || ctl->mode != 2)) return;
+    mu_in = mu_of_round(a, ctl->rounds - 1);
+  }
   const uint32_t sub = threadIdx.x / LPV;
   const uint32_t r0 = (threadIdx.x % LPV) * W;
-  for (uint64_t base = (uint64_t)blockIdx.x * IPB; base < a.n_hub; base += (uint64_t)gridDim.x * IPB) {
+  for (uint64_t base = i0 + (uint64_t)blockIdx.x * IPB; base < i1; base += (uint64_t)gridDim.x * IPB) {
     const uint64_t i = base + sub;
-    if (i >= a.n_hub) continue;
+    if (i >= i1) continue;
     const uint32_t t = a.ht[i];
     const uint8_t* st = a.done + (uint64_t)a.gid[t] * kR + r0;
     bool live[W], any = false;
@@ -460,14 +554,15 @@ __global__ __launch_bounds__(256) void k_bhub(BArgs a, int final_pass) {
       any |= live[k];
     }
     if (!any) continue;
-    const uint32_t beg = a.rowT[t] + a.hc[i] * kBChunk;
-    const uint32_t end = min(a.rowT[t + 1], beg + kBChunk);
+    const uint32_t beg = a.rowT[t] + a.hc[i] * a.hub_chunk;
+    const uint32_t end = min(a.rowT[t + 1], beg + a.hub_chunk);
     float acc[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) acc[k] = 0.0f;
-    bgather<W, WGT>(a, mu_in, beg, end, r0, acc);
+    if constexpr (SWEEP) bgather_sweep<W, WGT>(a, mu_in, mu_prev, lo, prev_ok, beg, end, r0, acc);
+    else bgather<W, WGT>(a, mu_in, beg, end, r0, acc);
     float* dst = a.dv + (uint64_t)t * kR + r0;
-    if (a.rowT[t + 1] - a.rowT[t] <= kBChunk) {
+    if (a.rowT[t + 1] - a.rowT[t] <= a.hub_chunk) {
       float d[W];
       vload<W>(dst, d);
 #pragma unroll
@@ -490,19 +585,42 @@ __global__ __launch_bounds__(256) void k_bhub(BArgs a, int final_pass) {
 // ping-pong buffer). Instances finished at the previous check get their last
 // messages delivered into dv; instances delivered earlier are skipped.
 // final_pass: delivery only, after a stop in the dense phase.
-template <int LPV, bool KAHAN, bool WGT>
+template <int LPV, bool KAHAN, bool WGT, bool SWEEP>
 __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
   constexpr int W = kR / LPV;
   constexpr int VPB = 256 / LPV;
   __shared__ double s_part[VPB][kR];
   BCtl* ctl = a.ctl;
-  if (!final_pass && (bhalted(ctl) || ctl->mode != 2)) return;
-  const uint32_t it = a.item_order[blockIdx.x];
-  if (it == ~0u) return;
+  uint32_t it;
+  const float *mu_in, *mu_prev = nullptr;
+  float* mu_out;
+  uint32_t lo = 0;
+  bool prev_ok = true, first = false;
+  if constexpr (SWEEP) {
+    // block c of sweep k: earlier blocks published in this sweep (mu_out's
+    // slot), later blocks and this one in the previous sweep (mu_prev)
+    if (bhalted(ctl) || ctl->mode != 3) return;
+    const uint32_t c = ctl->sw_c;
+    const uint64_t k = ctl->sw_k;
+    const uint32_t ib = a.sw_ioff[c], ie = a.sw_ioff[c + 1];
+    if (blockIdx.x >= ie - ib) return;
+    it = a.sw_items[ib + blockIdx.x];
+    if (it == ~0u) return;
+    mu_out = (k & 1) ? a.mu2 : a.mu;
+    mu_in = mu_out;
+    mu_prev = (k & 1) ? a.mu : a.mu2;
+    lo = (uint32_t)a.sw_bstart[c];
+    prev_ok = k > 0;
+    first = k == 0;  // the deltas left by the sparse rounds are still in dv
+  } else {
+    if (!final_pass && (bhalted(ctl) || ctl->mode != 2)) return;
+    it = a.item_order[blockIdx.x];
+    if (it == ~0u) return;
+    const uint64_t t = ctl->rounds;
+    mu_in = mu_of_round(a, t - 1);
+    mu_out = mu_of_round(a, t);
+  }
   const uint32_t g = a.rg[it];
-  const uint64_t t = ctl->rounds;
-  const float* mu_in = mu_of_round(a, t - 1);
-  float* mu_out = mu_of_round(a, t);
   const uint32_t sub = threadIdx.x / LPV;
   const uint32_t r0 = (threadIdx.x % LPV) * W;
   uint8_t st[W];
@@ -520,7 +638,11 @@ __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
   for (int k = 0; k < W; ++k) racc[k] = 0.0;
   uint64_t act = 0, msg = 0;
   if (__syncthreads_or(mine)) {
-    for (uint64_t x = a.rlo[it] + sub; x < a.rha[it]; x += VPB) {
+    // vertices without edges only matter in the first sweep, which folds in
+    // the deltas the sparse rounds left (the synchronous phase's opening
+    // claim does that for them)
+    const uint64_t xend = first ? a.rhi[it] : a.rha[it];
+    for (uint64_t x = a.rlo[it] + sub; x < xend; x += VPB) {
       if (!mine) continue;
       const uint64_t j = a.vord[x];
       const uint32_t b0 = a.rowT[j], b1 = a.rowT[j + 1];
@@ -533,7 +655,7 @@ __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
         vload<W>(a.v + j * kR + r0, vv);
         if constexpr (KAHAN) vload<W>(a.c + j * kR + r0, cc);
       }
-      if (hub || one_any) {
+      if (hub || one_any || first) {
         vload<W>(dvp, old);
       } else {
 #pragma unroll
@@ -544,15 +666,18 @@ __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
         for (int k = 0; k < W; ++k) d[k] = old[k];
       } else {
 #pragma unroll
-        for (int k = 0; k < W; ++k) d[k] = 0.0f;
-        bgather<W, WGT>(a, mu_in, b0, b1, r0, d);
+        for (int k = 0; k < W; ++k) d[k] = first ? old[k] : 0.0f;
+        if constexpr (SWEEP) bgather_sweep<W, WGT>(a, mu_in, mu_prev, lo, prev_ok, b0, b1, r0, d);
+        else bgather<W, WGT>(a, mu_in, b0, b1, r0, d);
       }
       bool cl[W], claim_any = false;
       uint32_t nclaim = 0;
       float nd[W];
 #pragma unroll
       for (int k = 0; k < W; ++k) {
-        if (st[k] != 2) racc[k] += fabs((double)d[k]);
+        // sweep rounds count a running lane's residual from what it sends
+        // below (its messages not yet consumed at the end of the sweep)
+        if (SWEEP ? st[k] == 1 : st[k] != 2) racc[k] += fabs((double)d[k]);
         cl[k] = st[k] == 0 && d[k] != 0.0f;
         claim_any |= cl[k];
         nclaim += cl[k] ? 1u : 0u;
@@ -579,13 +704,21 @@ __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
         }
         vstore<W>(a.v + j * kR + r0, vv);
       }
-      if (run_any) {
+      // (sweep rounds: finished instances publish zeros, which the blocks
+      // after this one read in the same sweep)
+      if (run_any || (SWEEP && one_any)) {
         const uint32_t deg = a.row[j + 1] - a.row[j];
         const double coef = WGT ? a.alpha : (deg ? a.alpha / (double)deg : 0.0);
         float mu[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) mu[k] = cl[k] ? (float)(coef * (double)d[k]) : 0.0f;
         if (deg) vstore<W>(mu_out + (uint64_t)a.perm[j] * kR + r0, mu);  // no reader otherwise
+        if constexpr (SWEEP) {
+          const double cf = a.sw_coef[j];
+#pragma unroll
+          for (int k = 0; k < W; ++k)
+            if (st[k] == 0) racc[k] += fabs((double)mu[k]) * cf;
+        }
         act += nclaim;
         msg += (uint64_t)nclaim * deg;
       }
@@ -606,11 +739,151 @@ __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
     a.part_fa[it] = act;
     a.part_fm[it] = msg;
   }
-  retire_item(a, g, final_pass ? 2 : 1, 1);
+  retire_item(a, g, final_pass ? 2 : 1, SWEEP ? 0 : 1);
+}
+
+// Sweep rounds stopped by the round limit: deliver the messages still in
+// flight into dv. After round base + k P + cl, a source numbered s last
+// published in sweep k if s < L (blocks up to cl), else in sweep k - 1; a
+// target of block bt last pulled in sweep k if bt <= cl, else in sweep
+// k - 1; a message is in flight when published at or after the target's
+// pull ((sweep, block) order, equal blocks included). Targets with in-degree
+// above hub_deg are handled by k_bdeliver_hub (their dv is always current).
+template <int LPV, bool WGT>
+__global__ __launch_bounds__(256) void k_bdeliver(BArgs a) {
+  constexpr int W = kR / LPV;
+  constexpr int VPB = 256 / LPV;
+  const BCtl* ctl = a.ctl;
+  const uint64_t k = ctl->sw_k;
+  const uint32_t cl = ctl->sw_c;
+  const uint32_t L = (uint32_t)a.sw_bstart[cl + 1];
+  const float* cur = (k & 1) ? a.mu2 : a.mu;
+  const float* prev = (k & 1) ? a.mu : a.mu2;
+  const uint32_t sub = threadIdx.x / LPV;
+  const uint32_t r0 = (threadIdx.x % LPV) * W;
+  for (uint64_t base = (uint64_t)blockIdx.x * VPB; base < a.N; base += (uint64_t)gridDim.x * VPB) {
+    const uint64_t j = base + sub;
+    if (j >= a.N) continue;
+    const uint32_t b0 = a.rowT[j], b1 = a.rowT[j + 1];
+    if (b1 - b0 > a.hub_deg) continue;
+    const uint32_t bt = a.sw_blk[j];
+    const uint32_t T0 = (uint32_t)a.sw_bstart[bt];
+    const bool processed = bt <= cl;
+    uint8_t st[W];
+    bool live = false;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      st[q] = a.done[(uint64_t)a.gid[j] * kR + r0 + q];
+      live |= st[q] != 2;
+    }
+    if (!live) continue;
+    float acc[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[q] = 0.0f;
+    for (uint32_t p = b0; p < b1; ++p) {
+      const uint32_t sp = a.srcT[p];
+      const float* src = nullptr;
+      if (processed) {
+        if (sp >= T0 && sp < L) src = cur;
+      } else {
+        if (sp < L) src = cur;
+        else if (sp >= T0 && k > 0) src = prev;
+      }
+      if (!src) continue;
+      float x[W];
+      vload<W>(src + (uint64_t)sp * kR + r0, x);
+      const float wp = WGT ? a.wT[p] : 1.0f;
+#pragma unroll
+      for (int q = 0; q < W; ++q) acc[q] += x[q] * wp;
+    }
+    float* dvp = a.dv + j * kR + r0;
+    float old[W], nd[W];
+    vload<W>(dvp, old);
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      // what dv holds for the lane: the sparse rounds' deltas (first sweep,
+      // block not reached), the delivered sum (finished lanes of processed
+      // blocks), else nothing (a running lane's dv is not kept current)
+      const bool keep = (k == 0 && !processed) || (st[q] == 1 && processed);
+      nd[q] = st[q] == 2 ? old[q] : (keep ? old[q] : 0.0f) + acc[q];
+    }
+    vstore<W>(dvp, nd);
+  }
+}
+
+template <int LPV, bool WGT>
+__global__ __launch_bounds__(256) void k_bdeliver_hub(BArgs a) {
+  constexpr int W = kR / LPV;
+  constexpr int IPB = 256 / LPV;
+  const BCtl* ctl = a.ctl;
+  const uint64_t k = ctl->sw_k;
+  const uint32_t cl = ctl->sw_c;
+  const uint32_t L = (uint32_t)a.sw_bstart[cl + 1];
+  const float* cur = (k & 1) ? a.mu2 : a.mu;
+  const float* prev = (k & 1) ? a.mu : a.mu2;
+  const uint32_t sub = threadIdx.x / LPV;
+  const uint32_t r0 = (threadIdx.x % LPV) * W;
+  for (uint64_t base = (uint64_t)blockIdx.x * IPB; base < a.n_hub; base += (uint64_t)gridDim.x * IPB) {
+    const uint64_t i = base + sub;
+    if (i >= a.n_hub) continue;
+    const uint32_t t = a.ht[i];
+    const uint32_t bt = a.sw_blk[t];
+    const uint32_t T0 = (uint32_t)a.sw_bstart[bt];
+    const bool processed = bt <= cl;
+    const uint8_t* stp = a.done + (uint64_t)a.gid[t] * kR + r0;
+    bool live[W], any = false;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      live[q] = stp[q] != 2;
+      any |= live[q];
+    }
+    if (!any) continue;
+    const uint32_t beg = a.rowT[t] + a.hc[i] * a.hub_chunk;
+    const uint32_t end = min(a.rowT[t + 1], beg + a.hub_chunk);
+    float acc[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[q] = 0.0f;
+    for (uint32_t p = beg; p < end; ++p) {
+      const uint32_t sp = a.srcT[p];
+      const float* src = nullptr;
+      if (processed) {
+        if (sp >= T0 && sp < L) src = cur;
+      } else {
+        if (sp < L) src = cur;
+        else if (sp >= T0 && k > 0) src = prev;
+      }
+      if (!src) continue;
+      float x[W];
+      vload<W>(src + (uint64_t)sp * kR + r0, x);
+      const float wp = WGT ? a.wT[p] : 1.0f;
+#pragma unroll
+      for (int q = 0; q < W; ++q) acc[q] += x[q] * wp;
+    }
+    float* dst = a.dv + (uint64_t)t * kR + r0;
+#pragma unroll
+    for (int q = 0; q < W; ++q)
+      if (live[q] && acc[q] != 0.0f) unsafeAtomicAdd(dst + q, acc[q]);
+  }
+}
+
+// After a delivery: back to a sparse state whose residual pass (count 0)
+// takes every delivered instance to finished.
+__global__ void k_bto_sparse(BCtl* ctl) {
+  ctl->mode = 0;
+  ctl->stop = 0;
+  ctl->ticket = 0;
+}
+
+// Item tickets of every graph and the graph ticket back to 0. A run stopped
+// between sweep rounds leaves some graphs' items of the interrupted sweep
+// counted; every run and every delivery starts from here.
+__global__ void k_breset_tickets(BArgs a) {
+  for (uint32_t g = threadIdx.x; g < a.G; g += blockDim.x) a.g_ticket[g] = 0;
+  if (threadIdx.x == 0) a.ctl->ticket = 0;
 }
 
 __global__ void k_bstats(BArgs a, uint32_t nblocks) {
-  if (bhalted(a.ctl) || a.ctl->mode == 2) return;
+  if (bhalted(a.ctl) || a.ctl->mode >= 2) return;
   uint64_t s = 0, m = 0;
   for (uint32_t i = threadIdx.x; i < nblocks; i += 256) {
     s += a.part_a[i];
@@ -624,11 +897,16 @@ __global__ void k_bstats(BArgs a, uint32_t nblocks) {
   }
 }
 
-__global__ void k_binit(BCtl* ctl, double eps, uint64_t max_rounds) {
+__global__ void k_binit(BCtl* ctl, double eps, uint64_t max_rounds, uint32_t dense_mode) {
   ctl->done = 0;
   ctl->stop = 0;
   ctl->mode = 0;
   ctl->prev_all_done = 0;
+  ctl->dense_mode = dense_mode;
+  ctl->sw_c = 0;
+  ctl->sw_started = 0;
+  ctl->sw_k = 0;
+  ctl->base = 0;
   ctl->ticket = 0;
   ctl->rounds = 0;
   ctl->max_rounds = max_rounds;
@@ -666,6 +944,32 @@ __global__ void k_union_weights(const T* w, uint64_t m, uint64_t eoff, float* uw
   for (uint64_t e = i; e < m; e += st) uw[eoff + e] = (float)w[e];
 }
 
+// Sweep numbers of the in-edge sources: out[p] = psw[inv[srcT[p]]].
+__global__ void k_brenumber(const uint32_t* srcT, const uint32_t* inv, const uint32_t* psw, uint64_t m,
+                            uint32_t* out) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t st = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t p = i; p < m; p += st) out[p] = psw[inv[srcT[p]]];
+}
+
+// coef[j] = sum over out-edges (j, t) with blk[t] <= blk[j] of |w| (1 when
+// unweighted): the multiplier of j's message base in the pending mass left
+// at the end of a sweep. One wave per vertex.
+__global__ __launch_bounds__(256) void k_bsweep_coef(const uint32_t* row, const uint32_t* col, const float* w,
+                                                     const uint32_t* blk, uint64_t n, double* coef) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t j = wave; j < n; j += nwaves) {
+    const uint32_t bj = blk[j];
+    double acc = 0.0;
+    for (uint32_t e = row[j] + lane; e < row[j + 1]; e += 64)
+      if (blk[col[e]] <= bj) acc += w ? fabs((double)w[e]) : 1.0;
+    acc = wave_sum(acc);
+    if (lane == 0) coef[j] = acc;
+  }
+}
+
 // Weights in in-edge order: wT[p] = w[eidT[p]].
 __global__ void k_bgather_weights(const float* w, const uint32_t* eidT, uint64_t m, float* wT) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -701,9 +1005,18 @@ struct daic_batch {
   hipGraph_t graph = nullptr;
   uint32_t exec_K = 0;
   const void* exec_stream = nullptr;
+  uint32_t exec_dense = 0, exec_P = 0;
+  hipGraphExec_t exec_sw = nullptr;   // sweep rounds only
+  hipGraph_t graph_sw = nullptr;
   BTune tune;
   bool tuned = false;
   std::vector<void*> allocs;
+  // sweep rounds (built for a block count P on first use)
+  BArgs as{};
+  uint32_t sw_P = 0;
+  uint32_t sw_grid = 0;               // fused-pass blocks per sweep round
+  std::vector<void*> sw_allocs;
+  std::vector<uint32_t> xcd_of;       // XCD slot given to each graph
 };
 
 namespace daic {
@@ -729,11 +1042,45 @@ static void enqueue_claim(daic_batch* b, hipStream_t s) {
 
 template <int LPV, bool WGT>
 static void launch_dense_w(daic_batch* b, hipStream_t s, int final_pass) {
-  if (b->a.n_hub) hipLaunchKernelGGL((k_bhub<LPV, WGT>), dim3(b->tune.grid_hub), dim3(256), 0, s, b->a, final_pass);
+  if (b->a.n_hub)
+    hipLaunchKernelGGL((k_bhub<LPV, WGT, false>), dim3(b->tune.grid_hub), dim3(256), 0, s, b->a, final_pass);
   if (b->kahan)
-    hipLaunchKernelGGL((k_bfused<LPV, true, WGT>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
+    hipLaunchKernelGGL((k_bfused<LPV, true, WGT, false>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
   else
-    hipLaunchKernelGGL((k_bfused<LPV, false, WGT>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
+    hipLaunchKernelGGL((k_bfused<LPV, false, WGT, false>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
+}
+
+// One sweep round (block and sweep from the control block): step, hub sums
+// of the block's hub targets, fused pass over the block's items.
+template <int LPV, bool WGT>
+static void launch_sweep_w(daic_batch* b, hipStream_t s) {
+  const BArgs& as = b->as;
+  hipLaunchKernelGGL(k_bstep, dim3(1), dim3(1), 0, s, as);
+  if (as.n_hub) hipLaunchKernelGGL((k_bhub<LPV, WGT, true>), dim3(b->tune.grid_hub), dim3(256), 0, s, as, 0);
+  if (b->kahan)
+    hipLaunchKernelGGL((k_bfused<LPV, true, WGT, true>), dim3(b->sw_grid), dim3(256), 0, s, as, 0);
+  else
+    hipLaunchKernelGGL((k_bfused<LPV, false, WGT, true>), dim3(b->sw_grid), dim3(256), 0, s, as, 0);
+}
+
+static void enqueue_sweep(daic_batch* b, hipStream_t s) {
+  const int l = b->tune.lpv_fused;
+  const bool w = b->a.w != nullptr;
+  if (l == 16) w ? launch_sweep_w<16, true>(b, s) : launch_sweep_w<16, false>(b, s);
+  else if (l == 32) w ? launch_sweep_w<32, true>(b, s) : launch_sweep_w<32, false>(b, s);
+  else w ? launch_sweep_w<64, true>(b, s) : launch_sweep_w<64, false>(b, s);
+}
+
+// Delivery of the messages in flight when sweep rounds stop at the round
+// limit, then the residual of the delivered state.
+template <bool WGT>
+static void launch_sweep_deliver_w(daic_batch* b, hipStream_t s) {
+  const BArgs& as = b->as;
+  hipLaunchKernelGGL((k_bdeliver<16, WGT>), dim3(bgrid(as.N, 16)), dim3(256), 0, s, as);
+  if (as.n_hub) hipLaunchKernelGGL((k_bdeliver_hub<16, WGT>), dim3(bgrid(as.n_hub, 16)), dim3(256), 0, s, as);
+  hipLaunchKernelGGL(k_bto_sparse, dim3(1), dim3(1), 0, s, as.ctl);
+  hipLaunchKernelGGL(k_breset_tickets, dim3(1), dim3(256), 0, s, b->a);
+  hipLaunchKernelGGL(k_bresidual, dim3(b->a.n_res), dim3(256), 0, s, b->a, 0);
 }
 
 template <int LPV>
@@ -760,6 +1107,193 @@ static void enqueue_push(daic_batch* b, hipStream_t s) {
 
 // One round in whichever mode the control block holds: sparse (claim, push,
 // residual), the claim that opens the dense phase, or a fused dense round.
+// Sweep set-up for P blocks per graph: graph g's block c is its vertices
+// [c B_g, (c+1) B_g), B_g = ceil(n_g / P). The sweep numbering is
+// block-major over the union (out-degree order, the dense rounds'
+// renumbering, inside a block), so that a source's block follows from its
+// number; residual items never cross a block; each block gets its items in
+// XCD-interleaved order and its hub items longest first.
+static daic_status batch_sweep_setup(daic_batch* b, uint32_t P, hipStream_t s) {
+  if (b->sw_P == P) return DAIC_OK;
+  for (void* q : b->sw_allocs)
+    if (q) (void)hipFree(q);
+  b->sw_allocs.clear();
+  b->sw_P = 0;
+  const BArgs& a = b->a;
+  const uint64_t N = a.N, M = b->ug->dev.m;
+  const uint32_t G = b->G;
+  auto grab = [&](void** q, size_t bytes) -> daic_status {
+    void* m = nullptr;
+    hipError_t e = hipMalloc(&m, bytes ? bytes : 1);
+    if (e != hipSuccess) return fail(DAIC_E_OOM, "sweep set-up: hipMalloc of %zu bytes failed", bytes);
+    b->sw_allocs.push_back(m);
+    *q = m;
+    return DAIC_OK;
+  };
+  std::vector<uint32_t> perm(N), inv(N), rt(N + 1), ro(N + 1), blk(N), psw(N);
+  DAIC_HIP(hipMemcpy(perm.data(), b->ug->pull.perm, N * 4, hipMemcpyDeviceToHost));
+  DAIC_HIP(hipMemcpy(rt.data(), b->ug->pull.rowT, (N + 1) * 4, hipMemcpyDeviceToHost));
+  DAIC_HIP(hipMemcpy(ro.data(), a.row, (N + 1) * 4, hipMemcpyDeviceToHost));
+  for (uint64_t j = 0; j < N; ++j) inv[perm[j]] = (uint32_t)j;
+  std::vector<uint64_t> Bg(G);
+  for (uint32_t g = 0; g < G; ++g) {
+    const uint64_t n = b->voff[g + 1] - b->voff[g];
+    Bg[g] = std::max<uint64_t>(1, (n + P - 1) / P);
+    for (uint64_t v = b->voff[g]; v < b->voff[g + 1]; ++v) blk[v] = (uint32_t)((v - b->voff[g]) / Bg[g]);
+  }
+  std::vector<uint64_t> bstart(P + 1, 0);
+  for (uint64_t j = 0; j < N; ++j) ++bstart[blk[j] + 1];
+  for (uint32_t c = 0; c < P; ++c) bstart[c + 1] += bstart[c];
+  {
+    std::vector<uint64_t> fill(bstart.begin(), bstart.end() - 1);
+    for (uint64_t q = 0; q < N; ++q) {
+      const uint32_t j = inv[q];
+      psw[j] = (uint32_t)fill[blk[j]]++;
+    }
+  }
+  // items: (graph, block) segments split at kResChunk vertices or kItemWork work
+  std::vector<uint32_t> rg, gfi, iblk;
+  std::vector<uint64_t> rlo, rhi, rw;
+  for (uint32_t g = 0; g < G; ++g) {
+    gfi.push_back((uint32_t)rg.size());
+    for (uint32_t c = 0; c < P; ++c) {
+      const uint64_t seg_lo = b->voff[g] + c * Bg[g];
+      const uint64_t seg_hi = std::min<uint64_t>(b->voff[g + 1], seg_lo + Bg[g]);
+      if (seg_lo >= seg_hi) continue;
+      uint64_t lo = seg_lo, w = 0;
+      for (uint64_t j = seg_lo; j < seg_hi; ++j) {
+        const uint32_t deg = rt[j + 1] - rt[j];
+        w += (deg > a.hub_deg ? 0 : deg) + kVertexWork;
+        if (j + 1 - lo >= kSwResChunk || w >= kSwItemWork || j + 1 == seg_hi) {
+          rg.push_back(g);
+          rlo.push_back(lo);
+          rhi.push_back(j + 1);
+          rw.push_back(w);
+          iblk.push_back(c);
+          lo = j + 1;
+          w = 0;
+        }
+      }
+    }
+    if (b->voff[g] == b->voff[g + 1]) {  // empty graph: one empty item in block 0
+      rg.push_back(g);
+      rlo.push_back(b->voff[g]);
+      rhi.push_back(b->voff[g]);
+      rw.push_back(0);
+      iblk.push_back(0);
+    }
+  }
+  gfi.push_back((uint32_t)rg.size());
+  const size_t nres = rg.size();
+  std::vector<uint32_t> vord(N);
+  std::vector<uint64_t> rha(nres);
+  for (uint64_t j = 0; j < N; ++j) vord[j] = (uint32_t)j;
+  auto isolated = [&](uint32_t j) { return rt[j + 1] == rt[j] && ro[j + 1] == ro[j]; };
+  auto pulled = [&](uint32_t j) { const uint32_t d = rt[j + 1] - rt[j]; return d > a.hub_deg ? 0u : d; };
+  for (size_t k = 0; k < nres; ++k) {
+    std::stable_sort(vord.begin() + rlo[k], vord.begin() + rhi[k], [&](uint32_t x, uint32_t y) {
+      const bool ix = isolated(x), iy = isolated(y);
+      if (ix != iy) return iy;
+      return pulled(x) > pulled(y);
+    });
+    uint64_t e = rlo[k];
+    while (e < rhi[k] && !isolated(vord[e])) ++e;
+    rha[k] = e;
+  }
+  // per block: items in XCD-interleaved order (each graph keeps its XCD)
+  constexpr uint32_t kXcd = 8;
+  std::vector<uint32_t> items, ioff(P + 1, 0);
+  uint32_t grid = 1;
+  for (uint32_t c = 0; c < P; ++c) {
+    std::vector<std::vector<uint32_t>> bins(kXcd);
+    for (size_t k = 0; k < nres; ++k)
+      if (iblk[k] == c) bins[b->xcd_of[rg[k]] % kXcd].push_back((uint32_t)k);
+    for (auto& bn : bins)
+      std::stable_sort(bn.begin(), bn.end(), [&](uint32_t x, uint32_t y) { return rw[x] > rw[y]; });
+    size_t longest = 0;
+    for (auto& bn : bins) longest = std::max(longest, bn.size());
+    std::vector<uint32_t> order(longest * kXcd, ~0u);
+    for (uint32_t x = 0; x < kXcd; ++x)
+      for (size_t i = 0; i < bins[x].size(); ++i) order[i * kXcd + x] = bins[x][i];
+    items.insert(items.end(), order.begin(), order.end());
+    ioff[c + 1] = (uint32_t)items.size();
+    grid = std::max<uint32_t>(grid, (uint32_t)order.size());
+  }
+  // hub items grouped by block, longest first
+  std::vector<uint32_t> ht, hc, hoff(P + 1, 0);
+  {
+    std::vector<std::vector<std::pair<uint32_t, uint64_t>>> per(P);
+    for (uint64_t t = 0; t < N; ++t) {
+      const uint32_t deg = rt[t + 1] - rt[t];
+      if (deg <= a.hub_deg) continue;
+      for (uint32_t c = 0; c * kSwHubChunk < deg; ++c)
+        per[blk[t]].push_back({std::min(kSwHubChunk, deg - c * kSwHubChunk), (t << 32) | c});
+    }
+    for (uint32_t c = 0; c < P; ++c) {
+      std::stable_sort(per[c].begin(), per[c].end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+      for (auto& it : per[c]) {
+        ht.push_back((uint32_t)(it.second >> 32));
+        hc.push_back((uint32_t)it.second);
+      }
+      hoff[c + 1] = (uint32_t)ht.size();
+    }
+  }
+  BArgs as = a;
+  void* q = nullptr;
+  daic_status rc;
+#define SWGRAB(field, type, bytes, src)                                                    \
+  do {                                                                                     \
+    if ((rc = grab(&q, (bytes)))) return rc;                                               \
+    as.field = (type)q;                                                                    \
+    if ((bytes) && (src)) DAIC_HIP(hipMemcpy(q, (src), (bytes), hipMemcpyHostToDevice));   \
+  } while (0)
+  SWGRAB(perm, const uint32_t*, N * 4, psw.data());
+  SWGRAB(sw_blk, const uint32_t*, N * 4, blk.data());
+  SWGRAB(sw_bstart, const uint64_t*, (P + 1) * 8, bstart.data());
+  SWGRAB(sw_items, const uint32_t*, items.size() * 4, items.data());
+  SWGRAB(sw_ioff, const uint32_t*, (P + 1) * 4, ioff.data());
+  SWGRAB(sw_hoff, const uint32_t*, (P + 1) * 4, hoff.data());
+  SWGRAB(ht, const uint32_t*, ht.size() * 4, ht.data());
+  SWGRAB(hc, const uint32_t*, hc.size() * 4, hc.data());
+  SWGRAB(rg, const uint32_t*, nres * 4, rg.data());
+  SWGRAB(rlo, const uint64_t*, nres * 8, rlo.data());
+  SWGRAB(rhi, const uint64_t*, nres * 8, rhi.data());
+  SWGRAB(rha, const uint64_t*, nres * 8, rha.data());
+  SWGRAB(g_first_item, const uint32_t*, gfi.size() * 4, gfi.data());
+  SWGRAB(vord, const uint32_t*, N * 4, vord.data());
+  SWGRAB(part_r, double*, nres * kR * 8, (const void*)nullptr);
+  SWGRAB(part_p, uint64_t*, nres * 8, (const void*)nullptr);
+  SWGRAB(part_fa, uint64_t*, nres * 8, (const void*)nullptr);
+  SWGRAB(part_fm, uint64_t*, nres * 8, (const void*)nullptr);
+  SWGRAB(sw_coef, const double*, N * 8, (const void*)nullptr);
+  SWGRAB(srcT, const uint32_t*, M * 4, (const void*)nullptr);
+#undef SWGRAB
+  as.n_res = (uint32_t)nres;
+  as.n_hub = ht.size();
+  as.hub_chunk = kSwHubChunk;
+  as.sw_P = P;
+  {
+    uint32_t* d_inv = nullptr;
+    DAIC_HIP(hipMalloc(&d_inv, std::max<uint64_t>(N, 1) * 4));
+    hipError_t e = hipMemcpy(d_inv, inv.data(), N * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && M)
+      hipLaunchKernelGGL(k_brenumber, dim3(bgrid(M)), dim3(256), 0, s, a.srcT, d_inv, as.perm, M,
+                         const_cast<uint32_t*>(as.srcT));
+    if (e == hipSuccess && N)
+      hipLaunchKernelGGL(k_bsweep_coef, dim3(bgrid(N, 4)), dim3(256), 0, s, a.row, a.col, a.w, as.sw_blk, N,
+                         const_cast<double*>(as.sw_coef));
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_inv);
+    if (e != hipSuccess) return fail(DAIC_E_DEVICE, "sweep set-up: %s", hipGetErrorString(e));
+  }
+  b->as = as;
+  b->sw_grid = grid;
+  b->sw_P = P;
+  return DAIC_OK;
+}
+
+// A sparse or synchronous-dense round; sweep rounds are a graph of their own
+// (the host launches the one that matches the control block's mode).
 static void enqueue_round(daic_batch* b, hipStream_t s) {
   enqueue_claim(b, s);
   enqueue_push(b, s);
@@ -775,7 +1309,11 @@ void daic_batch_destroy(daic_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->exec_sw) (void)hipGraphExecDestroy(b->exec_sw);
+  if (b->graph_sw) (void)hipGraphDestroy(b->graph_sw);
   for (void* q : b->allocs)
+    if (q) (void)hipFree(q);
+  for (void* q : b->sw_allocs)
     if (q) (void)hipFree(q);
   if (b->ug) daic_graph_destroy(b->ug);
   if (b->h_ctl) (void)hipHostFree(b->h_ctl);
@@ -903,6 +1441,7 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
     // hub items: targets with in-degree > hub_deg, chunks of kBChunk
     // in-edges, longest first
     a.hub_deg = kHubDeg;
+    a.hub_chunk = kBChunk;
     if (const char* e = std::getenv("DAIC_HUB_DEG")) a.hub_deg = (uint32_t)std::max(1L, std::atol(e));
     DAIC_HIP(hipMemcpy(rt.data(), ug->pull.rowT, (N + 1) * 4, hipMemcpyDeviceToHost));
     std::vector<uint32_t> ht, hc;
@@ -1024,9 +1563,11 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
     std::stable_sort(gorder.begin(), gorder.end(), [&](uint32_t x, uint32_t y) { return gw[x] > gw[y]; });
     std::vector<std::vector<uint32_t>> bins(kXcd);
     std::vector<uint64_t> load(kXcd, 0);
+    b->xcd_of.assign(n_graphs, 0);
     for (uint32_t g : gorder) {
       const uint32_t x = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
       load[x] += gw[g];
+      b->xcd_of[g] = x;
       for (uint32_t k = gfi[g]; k < gfi[g + 1]; ++k) bins[x].push_back(k);
     }
     // heaviest items first within each XCD, so that the long ones start early
@@ -1068,7 +1609,7 @@ daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs
   DAIC_HIP(hipMemsetAsync(a.active, 0, N, s));
   DAIC_HIP(hipMemsetAsync(a.g_ticket, 0, (size_t)n_graphs * 4, s));
   DAIC_HIP(hipMemsetAsync(a.done, 0, (size_t)n_graphs * kR, s));
-  hipLaunchKernelGGL(k_binit, dim3(1), dim3(1), 0, s, a.ctl, 0.0, ~0ull);
+  hipLaunchKernelGGL(k_binit, dim3(1), dim3(1), 0, s, a.ctl, 0.0, ~0ull, 1u);
   DAIC_HIP(hipHostMalloc((void**)&b->h_ctl, sizeof(BCtl), hipHostMallocDefault));
   DAIC_HIP(hipEventCreate(&b->ev0));
   DAIC_HIP(hipEventCreate(&b->ev1));
@@ -1199,7 +1740,7 @@ daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len) {
     b->tune = best;
     DAIC_HIP(restore(nullptr));
     DAIC_HIP(hipMemcpy(a.done, done_save.data(), SD, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_binit, dim3(1), dim3(1), 0, s, a.ctl, 0.0, ~0ull);
+    hipLaunchKernelGGL(k_binit, dim3(1), dim3(1), 0, s, a.ctl, 0.0, ~0ull, 1u);
     DAIC_HIP(hipStreamSynchronize(s));
     (void)hipFree(sv);
     (void)hipFree(sd);
@@ -1228,43 +1769,93 @@ daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len) {
 
 daic_status daic_batch_run(daic_batch* b, const daic_run_opts* o, daic_stats* stats, double* inst_residual) {
   if (!b || !o) return fail(DAIC_E_INVALID, "null argument");
-  if (o->sched != DAIC_SCHED_ALL || o->priority_fraction != 1.0)
-    return fail(DAIC_E_UNSUPPORTED, "batched runs update every pending vertex (sched ALL, q = 1)");
+  const bool sweep = o->sched == DAIC_SCHED_SWEEP;
+  if (!sweep && (o->sched != DAIC_SCHED_ALL || o->priority_fraction != 1.0))
+    return fail(DAIC_E_UNSUPPORTED, "batched runs take sched ALL (q = 1) or SWEEP");
+  if (sweep && !(o->priority_fraction > 0.0 && o->priority_fraction <= 1.0))
+    return fail(DAIC_E_INVALID, "priority_fraction must be in (0, 1]");
   if (!(o->eps >= 0.0)) return fail(DAIC_E_INVALID, "eps must be >= 0");
   hipStream_t s = o->hip_stream ? static_cast<hipStream_t>(o->hip_stream) : b->stream;
   const uint32_t K = o->rounds_per_check ? o->rounds_per_check : 1;
   const uint64_t max_rounds = o->max_rounds ? o->max_rounds : ~0ull;
   if (stats) std::memset(stats, 0, sizeof *stats);
   BArgs& a = b->a;
-  hipLaunchKernelGGL(k_binit, dim3(1), dim3(1), 0, s, a.ctl, o->eps, max_rounds);
+  uint32_t P = 0;
+  if (sweep) {
+    // blocks per graph: ceil(1 / q), at most 1024
+    P = (uint32_t)std::min(1024.0, std::ceil(1.0 / o->priority_fraction - 1e-9));
+    P = std::max<uint32_t>(P, 1);
+    daic_status rc = batch_sweep_setup(b, P, s);
+    if (rc) return rc;
+  }
+  const uint32_t dense = sweep ? 3u : 1u;
+  hipLaunchKernelGGL(k_binit, dim3(1), dim3(1), 0, s, a.ctl, o->eps, max_rounds, dense);
+  hipLaunchKernelGGL(k_breset_tickets, dim3(1), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_bresidual, dim3(a.n_res), dim3(256), 0, s, a, 0);
   DAIC_HIP(hipEventRecord(b->ev0, s));
   const bool use_graph = std::getenv("DAIC_NO_GRAPH") == nullptr;
-  if (use_graph && !(b->exec && b->exec_K == K && b->exec_stream == s)) {
+  if (use_graph && !(b->exec && b->exec_K == K && b->exec_stream == s && b->exec_dense == dense &&
+                     b->exec_P == P)) {
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    if (b->exec_sw) { (void)hipGraphExecDestroy(b->exec_sw); b->exec_sw = nullptr; }
+    if (b->graph_sw) { (void)hipGraphDestroy(b->graph_sw); b->graph_sw = nullptr; }
     DAIC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     for (uint32_t r = 0; r < K; ++r) enqueue_round(b, s);
     hipGraph_t graph;
     DAIC_HIP(hipStreamEndCapture(s, &graph));
     b->graph = graph;
     DAIC_HIP(hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0));
+    if (sweep) {
+      DAIC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      for (uint32_t r = 0; r < K; ++r) enqueue_sweep(b, s);
+      DAIC_HIP(hipStreamEndCapture(s, &graph));
+      b->graph_sw = graph;
+      DAIC_HIP(hipGraphInstantiate(&b->exec_sw, graph, nullptr, nullptr, 0));
+    }
     b->exec_K = K;
     b->exec_stream = s;
+    b->exec_dense = dense;
+    b->exec_P = P;
   }
+  uint64_t seen_rounds = ~0ull;
+  DAIC_HIP(hipMemcpyAsync(b->h_ctl, a.ctl, sizeof(BCtl), hipMemcpyDeviceToHost, s));
+  DAIC_HIP(hipStreamSynchronize(s));
   for (;;) {
+    const bool sweep_now = sweep && b->h_ctl->mode == 3;
     if (use_graph) {
-      DAIC_HIP(hipGraphLaunch(b->exec, s));
+      DAIC_HIP(hipGraphLaunch(sweep_now ? b->exec_sw : b->exec, s));
     } else {
-      for (uint32_t r = 0; r < K; ++r) enqueue_round(b, s);
+      for (uint32_t r = 0; r < K; ++r) {
+        if (sweep_now) enqueue_sweep(b, s);
+        else enqueue_round(b, s);
+      }
     }
     DAIC_HIP(hipMemcpyAsync(b->h_ctl, a.ctl, sizeof(BCtl), hipMemcpyDeviceToHost, s));
     DAIC_HIP(hipStreamSynchronize(s));
     if (b->h_ctl->done || b->h_ctl->stop) break;
+    // every round advances the count; a launch of K rounds that did not
+    // means the control block is inconsistent: fail instead of spinning
+    if (b->h_ctl->rounds == seen_rounds)
+      return fail(DAIC_E_DEVICE, "batched run made no progress (round %llu)", (unsigned long long)seen_rounds);
+    seen_rounds = b->h_ctl->rounds;
   }
   if (!b->h_ctl->done && b->h_ctl->mode == 2) {
     // stopped in the dense phase: deliver the last round's messages
     enqueue_dense(b, s, 1);
+    DAIC_HIP(hipMemcpyAsync(b->h_ctl, a.ctl, sizeof(BCtl), hipMemcpyDeviceToHost, s));
+    DAIC_HIP(hipStreamSynchronize(s));
+  }
+  if (!b->h_ctl->done && b->h_ctl->mode == 3) {
+    // stopped in the sweep phase: deliver the messages in flight, then the
+    // residual of the delivered state (which may finish instances)
+    if (b->h_ctl->sw_started) {
+      if (a.w) launch_sweep_deliver_w<true>(b, s);
+      else launch_sweep_deliver_w<false>(b, s);
+    } else {
+      hipLaunchKernelGGL(k_bto_sparse, dim3(1), dim3(1), 0, s, a.ctl);
+      hipLaunchKernelGGL(k_bresidual, dim3(a.n_res), dim3(256), 0, s, a, 0);
+    }
     DAIC_HIP(hipMemcpyAsync(b->h_ctl, a.ctl, sizeof(BCtl), hipMemcpyDeviceToHost, s));
     DAIC_HIP(hipStreamSynchronize(s));
   }

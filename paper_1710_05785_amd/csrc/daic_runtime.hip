@@ -793,6 +793,7 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
     }
   }
   p->a.last_upd = nullptr;  // captured plain rounds do not track updates
+  uint64_t seen_rounds = ~0ull;
   for (; o->sched != DAIC_SCHED_LEARNED;) {
     if (use_graph) {
       DAIC_HIP(hipGraphLaunch(p->exec, s));
@@ -802,6 +803,11 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
     DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     DAIC_HIP(hipStreamSynchronize(s));
     if (p->h_ctl->done || p->h_ctl->stop) break;
+    // every round advances the count; a launch that did not means the
+    // control block is inconsistent: fail instead of spinning
+    if (p->h_ctl->rounds == seen_rounds)
+      return fail(DAIC_E_DEVICE, "run made no progress (round %llu)", (unsigned long long)seen_rounds);
+    seen_rounds = p->h_ctl->rounds;
   }
   DAIC_HIP(hipEventRecord(p->ev1, s));
   DAIC_HIP(hipEventSynchronize(p->ev1));

@@ -649,10 +649,15 @@ daic_status sweep_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats
     DAIC_HIP(hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0));
     p->key = key;
   }
+  uint64_t seen_rounds = ~0ull;
   for (;;) {
     DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     DAIC_HIP(hipStreamSynchronize(s));
     if (p->h_ctl->done || p->h_ctl->stop) break;
+    // every launch advances the round count; fail instead of spinning if not
+    if (p->h_ctl->rounds == seen_rounds)
+      return fail(DAIC_E_DEVICE, "sweep run made no progress (round %llu)", (unsigned long long)seen_rounds);
+    seen_rounds = p->h_ctl->rounds;
     if (use_graph) {
       DAIC_HIP(hipGraphLaunch(p->exec, s));
     } else {

@@ -368,8 +368,10 @@ class Batch:
         check(lib().daic_batch_tune(self._h, buf, 256), "daic_batch_tune")
         return buf.value.decode()
 
-    def run(self, eps=1e-6, rounds_per_check=8, max_rounds=0, stream=None):
-        o = Problem.make_opts(eps=eps, q=1.0, sched="all", rounds_per_check=rounds_per_check,
+    def run(self, eps=1e-6, rounds_per_check=8, max_rounds=0, stream=None, sched="all", q=1.0):
+        """sched "all" (synchronous dense rounds) or "sweep" (blocks of
+        ceil(q n_g) vertices of every graph in turn, asynchronous order)."""
+        o = Problem.make_opts(eps=eps, q=q, sched=sched, rounds_per_check=rounds_per_check,
                               max_rounds=max_rounds, stream=stream)
         st = Stats()
         inst = np.zeros(sum(self.rhs), dtype=np.float64)

@@ -224,3 +224,104 @@ def test_batched_edge_scale_needs_weights(daic):
     g = daic_gen.rmat(8, 4, seed=5)
     with pytest.raises(daic.DaicError):
         daic.Batch([daic.Graph(g.row_ptr, g.col)], 8, alpha=1.0, g=daic.G_EDGE_SCALE)
+
+
+def ppr_batch(daic, gs, rhs, d, state, seed0=6):
+    dgs = [daic.Graph(g.row_ptr, g.col) for g in gs]
+    b = daic.Batch(dgs, rhs, alpha=d, state=state)
+    inits = []
+    for i, g in enumerate(gs):
+        if g.m == 0:
+            dv1 = np.zeros((g.n, rhs))
+            dv1[np.arange(rhs) % g.n, np.arange(rhs)] = 1 - d
+        else:
+            dv1 = ppr_inputs(g, seed0, i * 64, rhs, d)
+        inits.append(dv1)
+        b.set_init(i, np.zeros((g.n, rhs)), dv1)
+    return b, inits
+
+
+def check_ppr(b, gs, inits, d, rhs, every=1, tol=1e-5):
+    for i, g in enumerate(gs):
+        v = b.get(i)
+        for r in range(0, rhs, every):
+            ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, inits[i][:, r], eps=1e-14)
+            den = max(np.abs(ref).sum(), 1e-300)
+            assert np.abs(v[:, r] - ref).sum() / den <= tol, (i, r)
+
+
+@pytest.mark.parametrize("state", ["f32", "f32_kahan"])
+@pytest.mark.parametrize("rhs,q", [(64, 0.125), (5, 0.3), (64, 1.0)])
+def test_batched_sweep_matches_oracle(daic, state, rhs, q):
+    """Sweep rounds over the batch (blocks of ceil(q n_g) vertices of every
+    graph in turn, each pulling the newest messages): every instance at the
+    oracle's fixed point and at residual <= eps."""
+    say("case batch sweep", state, rhs, q)
+    d = 0.85
+    gs = [daic_gen.rmat(s, 8, seed=1000 + i) for i, s in enumerate([7, 10, 9, 12, 8, 11])]
+    gs.append(daic_gen.from_edges(37, [], []))
+    gs.append(daic_gen.from_edges(5, [0, 1, 2, 3, 4], [1, 2, 3, 4, 0]))
+    gs.append(hub_graph(3000))
+    b, inits = ppr_batch(daic, gs, rhs, d, state)
+    res, inst = b.run(eps=1e-7, rounds_per_check=4, sched="sweep", q=q)
+    assert res.converged and np.all(inst <= 1e-7)
+    check_ppr(b, gs, inits, d, rhs)
+
+
+def test_batched_sweep_needs_fewer_passes(daic):
+    say("case batch sweep passes")
+    d = 0.85
+    gs = [daic_gen.rmat(s, 8, seed=2000 + s) for s in (12, 13)]
+    b, inits = ppr_batch(daic, gs, 64, d, "f32")
+    ra, _ = b.run(eps=1e-7, rounds_per_check=4)
+    b2, _ = ppr_batch(daic, gs, 64, d, "f32")
+    rs, _ = b2.run(eps=1e-7, rounds_per_check=4, sched="sweep", q=0.125)
+    assert ra.converged and rs.converged
+    say("synchronous rounds", ra.stats["rounds"], "sweep rounds", rs.stats["rounds"],
+        "messages", ra.stats["pushed_edges"], rs.stats["pushed_edges"])
+    assert rs.stats["rounds"] / 8 <= 0.8 * ra.stats["rounds"]
+    assert rs.stats["pushed_edges"] < ra.stats["pushed_edges"]
+
+
+def test_batched_sweep_stop_and_resume(daic):
+    """Runs stopped by max_rounds inside a sweep deliver the messages in
+    flight; resuming (sweep or synchronous) reaches the fixed point."""
+    say("case batch sweep stop")
+    d = 0.85
+    gs = [daic_gen.rmat(12, 8, seed=41), hub_graph(2000), daic_gen.rmat(9, 16, seed=42)]
+    for stops in ((3,), (5, 11), (9, 2, 17)):
+        b, inits = ppr_batch(daic, gs, 64, d, "f32")
+        for k in stops:
+            res, inst = b.run(eps=1e-7, rounds_per_check=1, max_rounds=k, sched="sweep", q=0.2)
+            assert res.status == daic.NOT_CONVERGED
+            assert np.all(np.isfinite(inst))
+        res, inst = b.run(eps=1e-7, rounds_per_check=4, sched="sweep", q=0.2)
+        assert res.converged and np.all(inst <= 1e-7)
+        check_ppr(b, gs, inits, d, 64, every=9)
+    b, inits = ppr_batch(daic, gs, 64, d, "f32")
+    b.run(eps=1e-7, rounds_per_check=1, max_rounds=6, sched="sweep", q=0.25)
+    res, inst = b.run(eps=1e-7)
+    assert res.converged
+    check_ppr(b, gs, inits, d, 64, every=9)
+
+
+def test_batched_sweep_adsorption(daic):
+    say("case batch sweep adsorption")
+    gs = [daic_gen.rmat(11, 8, seed=301), daic_gen.paper_lognormal(3000, seed=302)]
+    labels = 64
+    dgs, ws, inits = [], [], []
+    for i, g in enumerate(gs):
+        w, p_inj = adsorption_case(g, 310 + i)
+        dgs.append(daic.Graph(g.row_ptr, g.col, w))
+        ws.append(w)
+        inits.append((ppr_inputs(g, 320 + i, 64 * i, labels, 0.0, max_k=8) > 0) * p_inj[:, None])
+    b = daic.Batch(dgs, labels, alpha=1.0, state="f32_kahan", g=daic.G_EDGE_SCALE)
+    for i, g in enumerate(gs):
+        b.set_init(i, np.zeros((g.n, labels)), inits[i])
+    res, inst = b.run(eps=1e-7, rounds_per_check=4, sched="sweep", q=0.125)
+    assert res.converged and np.all(inst <= 1e-7)
+    for i, g in enumerate(gs):
+        v = b.get(i)
+        for l in range(0, labels, 9):
+            ref, _, _ = oracle.jacobi_sum(g, oracle.G_EDGE_SCALE, 1.0, inits[i][:, l], w=ws[i], eps=1e-14)
+            assert np.abs(v[:, l] - ref).sum() / max(np.abs(ref).sum(), 1e-300) <= 1e-5, (i, l)
