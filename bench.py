@@ -143,6 +143,15 @@ def batched_form(daic, torch, eps, rounds_per_check):
     res, inst = b.run(eps=eps, rounds_per_check=rounds_per_check)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
+    # the same instances in round-robin sweeps of 8 id blocks per graph
+    reset()
+    b.run(eps=eps, rounds_per_check=rounds_per_check, sched="sweep", q=0.125)  # warm-up (capture)
+    reset()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res_sw, inst_sw = b.run(eps=eps, rounds_per_check=rounds_per_check, sched="sweep", q=0.125)
+    torch.cuda.synchronize()
+    wall_sw = time.perf_counter() - t
     # single-instance solves on a sample: one right-hand side of every 4th graph
     sample = list(range(0, len(gs), 4))
     single_ms = []
@@ -168,6 +177,11 @@ def batched_form(daic, torch, eps, rounds_per_check):
         "sequential_sample": (f"{len(sample)} single-instance solves (right-hand side 0 of graphs "
                               f"{sample}), mean x {len(gs) * rhs} instances"),
         "speedup_vs_sequential": est_seq_ms / (wall * 1e3),
+        "sweep_8_blocks": {
+            "time_to_residual_ms": wall_sw * 1e3, "rounds": res_sw.stats["rounds"],
+            "converged": res_sw.converged, "max_instance_residual": float(inst_sw.max()),
+            "messages": res_sw.stats["pushed_edges"],
+        },
     }
 
 
