@@ -29,6 +29,8 @@ constexpr int kScanBlock = 256;       // threads per block of the per-vertex ker
 constexpr int kMaxScanBlocks = 2048;  // blocks of the per-vertex kernels (upper bound)
 constexpr uint32_t kSmallMaxDeg = 32; // out-degree bound of the small bin
 constexpr uint32_t kChunk = 1024;     // edges per item of the large bin
+constexpr uint32_t kStreamEdges = 2048; // in-edges per block of the streamed pull
+constexpr uint32_t kStreamRows = 1024;  // targets per block of the streamed pull
 constexpr uint32_t kMaxSamples = 4096;
 constexpr uint32_t kInfU32 = 0xFFFFFFFFu;
 
@@ -90,6 +92,13 @@ void learned_after_round(daic_problem* p, hipStream_t s);
 // Builds the in-edge form of g (no-op when built). Needs m < 2^32.
 daic_status pull_prepare(daic_graph* g, hipStream_t s);
 void pull_release(daic_graph* g);
+// Edge blocks of the streamed pull over targets [t_begin, t_end) of the
+// in-edge offsets rt: whole targets in id order while a block holds at most
+// kStreamEdges in-edges and kStreamRows targets; a target with more in-edges
+// is cut into pieces of kStreamEdges. Appends (first target, first in-edge,
+// targets covered) per block; targets without in-edges start no block.
+void stream_blocks(const uint32_t* rt, uint64_t t_begin, uint64_t t_end, std::vector<uint32_t>& bt,
+                   std::vector<uint32_t>& be, std::vector<uint32_t>& bn);
 
 }  // namespace daic
 
@@ -103,15 +112,12 @@ struct PullGraph {
   void* rowT = nullptr;         // in-edge offsets, RowT[n+1]
   uint32_t* srcT = nullptr;     // perm[source] of each in-edge, sorted by (target, perm[source])
   uint32_t* eidT = nullptr;     // original edge index of each in-edge (weighted graphs)
-  uint32_t* small_tgt = nullptr;  // targets with in-degree 1..kSmallMaxDeg
-  uint64_t n_small = 0;
-  uint32_t* large_tgt = nullptr;  // items (target, chunk) for larger in-degrees
-  uint32_t* large_chunk = nullptr;
-  uint32_t* large_nch = nullptr;  // number of chunks of the item's target
-  uint64_t n_large = 0;
-  uint64_t small_edges = 0;       // in-edges of the small targets
-  uint64_t large_edges = 0;
+  uint64_t n_targets = 0;         // targets with in-edges
   uint64_t n_src = 0;             // vertices with out-edges: renumbered positions [0, n_src)
+  uint32_t* sb_t = nullptr;       // edge blocks of the streamed pull (first target,
+  uint32_t* sb_e = nullptr;       //   first in-edge with a closing entry m,
+  uint32_t* sb_n = nullptr;       //   targets covered)
+  uint64_t sb_count = 0;
 };
 }  // namespace daic
 

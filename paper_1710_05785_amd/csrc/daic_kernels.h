@@ -12,6 +12,8 @@
 // later round and never lost (the receive/update split of Eq. async).
 #pragma once
 
+#include <type_traits>
+
 #include "daic_device.h"
 #include "daic_internal.h"
 
@@ -70,13 +72,11 @@ struct KArgs {
   const uint32_t* srcT;     // renumbered source of each in-edge
   const void* wT;           // S[m] weights in in-edge order (EDGE_SCALE)
   void* mu_pi;              // S[n] message base of every vertex, renumbered
-  const uint32_t* pt_small; // targets with in-degree 1..kSmallMaxDeg
-  uint64_t pn_small;
-  const uint32_t* pt_large; // (target, chunk, chunks of target) items
-  const uint32_t* pt_chunk;
-  const uint32_t* pt_nch;
-  uint64_t pn_large;
   uint64_t n_src;           // vertices with out-edges (renumbered positions below n_src)
+  const uint32_t* sb_t;     // edge blocks of the streamed pull: first target,
+  const uint32_t* sb_e;     //   first in-edge (one extra entry: m),
+  const uint32_t* sb_n;     //   number of targets covered
+  uint64_t sb_count;
 };
 
 __device__ __forceinline__ bool ctl_halted(const Ctl* ctl) {
@@ -765,85 +765,115 @@ __global__ __launch_bounds__(64) void k_push_large(KArgs a) {
 // ---------------------------------------------------------------------------
 // Dense rounds: the receive side of Eq. async done by the receiver. Every
 // target sums the message bases of its in-neighbours (0 for silent ones) and
-// adds the sum to dv. Sums are formed in FP64; a target is owned by one wave
-// unless its in-degree spans several chunks, whose partial sums are added
-// atomically.
+// adds the sum to dv. Sums are formed in FP64.
 // ---------------------------------------------------------------------------
-template <int ST, int G>
-__device__ __forceinline__ double pull_msg(const KArgs& a, uint64_t p) {
-  using S = typename Tr<ST>::S;
-  double m = (double)static_cast<const S*>(a.mu_pi)[a.srcT[p]];
-  if constexpr (G == DAIC_G_EDGE_SCALE) m *= (double)static_cast<const S*>(a.wT)[p];
-  return m;
-}
-
-// Small targets (in-degree 1..kSmallMaxDeg), one per thread, in id order, so
-// that offsets, in-edge lists and deltas are read by consecutive lanes.
-template <int ST, int G>
-__global__ __launch_bounds__(256) void k_pull_small(KArgs a) {
-  using S = typename Tr<ST>::S;
-  if constexpr (Tr<ST>::sum) {
-    Ctl* ctl = a.ctl;
-    if (ctl_halted(ctl) || !ctl->pull) return;
-    S* dv = static_cast<S*>(a.dv);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.pn_small; i += stride) {
-      const uint32_t t = a.pt_small[i];
-      const uint32_t beg = a.rowT[t], end = a.rowT[t + 1];
-      double acc = 0.0;
-      uint32_t p = beg;
-      for (; p + 3 < end; p += 4) {
-        double m0 = pull_msg<ST, G>(a, p), m1 = pull_msg<ST, G>(a, p + 1);
-        double m2 = pull_msg<ST, G>(a, p + 2), m3 = pull_msg<ST, G>(a, p + 3);
-        acc += (m0 + m1) + (m2 + m3);
-      }
-      for (; p < end; ++p) acc += pull_msg<ST, G>(a, p);
-      dv[t] = (S)((double)dv[t] + acc);
-    }
+// Streamed pull: the in-edges are cut into blocks of at most kStreamEdges
+// consecutive in-edges covering whole targets (a target with more in-edges
+// is cut into pieces of its own). A workgroup of 256 threads reads a block's
+// sources with consecutive lanes, gathers the messages into LDS, then every
+// thread sums its run of kStreamEdges/256 consecutive values per target it
+// meets, adding into per-target LDS accumulators (FP64). Targets wholly
+// inside the block are written once; pieces of a cut target add atomically.
+// msg(source, in-edge) returns the message carried by an in-edge.
+template <typename S, typename V, typename Msg>
+__device__ __forceinline__ void stream_block(const uint32_t* rowT, const uint32_t* srcT, S* dv, uint32_t t0,
+                                             uint32_t nr, uint32_t e0, uint32_t e1, V* vals, double* acc,
+                                             uint32_t* off, const Msg& msg) {
+  constexpr uint32_t PER = kStreamEdges / 256, ROFF = (kStreamRows + 256) / 256, RDV = kStreamRows / 256;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t ne = e1 - e0;
+  // every independent load first, at clamped indices (no branch around
+  // them, so they are in flight together): row offsets, sources, and dv of
+  // this thread's targets (only this workgroup writes a whole target's dv)
+  uint32_t ro[ROFF], src[PER];
+  S dvp[RDV];
+#pragma unroll
+  for (uint32_t k = 0; k < ROFF; ++k) ro[k] = rowT[t0 + min(tid + 256 * k, nr)];
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) src[j] = srcT[e0 + min(tid + 256 * j, ne - 1)];
+#pragma unroll
+  for (uint32_t k = 0; k < RDV; ++k) dvp[k] = dv[t0 + min(tid + 256 * k, nr - 1)];
+  V val[PER];
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) val[j] = msg(src[j], e0 + min(tid + 256 * j, ne - 1));
+  // row offsets relative to the block, clipped to [0, ne]
+#pragma unroll
+  for (uint32_t k = 0; k < ROFF; ++k) {
+    const uint32_t i = tid + 256 * k;
+    if (i <= nr) off[i] = ro[k] <= e0 ? 0u : min(ro[k] - e0, ne);
+    if (i < nr) acc[i] = 0.0;
   }
+  // lanes past the block's end store 0
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) vals[tid + 256 * j] = tid + 256 * j < ne ? val[j] : (V)0;
+  __syncthreads();
+  // this thread's run [q0, q1) of the block's values
+  const uint32_t q0 = min(tid * PER, ne), q1 = min(q0 + PER, ne);
+  if (q0 < q1) {
+    uint32_t lo = 0, hi = nr - 1;  // last row i with off[i] <= q0
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= q0) lo = mid;
+      else hi = mid - 1;
+    }
+    uint32_t i = lo, next = off[i + 1];
+    double sum = 0.0;
+    for (uint32_t q = q0; q < q1; ++q) {
+      while (q >= next) {  // row i ends before q
+        if (sum != 0.0) atomicAdd(&acc[i], sum);
+        sum = 0.0;
+        ++i;
+        next = off[i + 1];
+      }
+      sum += (double)vals[q];
+    }
+    atomicAdd(&acc[i], sum);
+  }
+  __syncthreads();
+  // several targets: all whole; one target: whole or a piece
+  const bool piece = nr == 1 && (rowT[t0] != e0 || rowT[t0 + 1] != e1);
+#pragma unroll
+  for (uint32_t k = 0; k < RDV; ++k) {
+    const uint32_t i = tid + 256 * k;
+    if (i >= nr || off[i + 1] == off[i]) continue;  // beyond the block, or no in-edges
+    const uint32_t t = t0 + i;
+    if (!piece) dv[t] = (S)((double)dvp[k] + acc[i]);
+    else unsafeAtomicAdd(&dv[t], (S)acc[i]);
+  }
+  __syncthreads();
 }
 
-// Larger targets: one wave per (target, chunk of kChunk in-edges) item. The
-// item records of 16 items are fetched at once (one per lane) and broadcast,
-// and four gathers are in flight per lane.
+// Dense round by streamed blocks (Eq. sync over the in-edges): message of an
+// in-edge = the source's base (times the edge weight for EDGE_SCALE).
 template <int ST, int G>
-__global__ __launch_bounds__(64) void k_pull_large(KArgs a) {
+__global__ __launch_bounds__(256) void k_pull_stream(KArgs a) {
   using S = typename Tr<ST>::S;
   if constexpr (Tr<ST>::sum) {
     Ctl* ctl = a.ctl;
+    uint64_t b = blockIdx.x;
+    if (b >= a.sb_count) return;
+    // the first block's descriptors are read together with the control block
+    uint32_t t0 = a.sb_t[b], nr = a.sb_n[b], e0 = a.sb_e[b], e1 = a.sb_e[b + 1];
     if (ctl_halted(ctl) || !ctl->pull) return;
-    S* dv = static_cast<S*>(a.dv);
-    constexpr uint32_t kGroup = 16;
-    const uint32_t lane = threadIdx.x;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * kGroup; g0 < a.pn_large; g0 += (uint64_t)gridDim.x * kGroup) {
-      uint32_t t = 0, c = 0, nch = 0, rb = 0, re = 0;
-      if (lane < kGroup && g0 + lane < a.pn_large) {
-        t = a.pt_large[g0 + lane];
-        c = a.pt_chunk[g0 + lane];
-        nch = a.pt_nch[g0 + lane];
-        rb = a.rowT[t];
-        re = a.rowT[t + 1];
-      }
-      const uint32_t cnt = (uint32_t)min<uint64_t>(kGroup, a.pn_large - g0);
-      for (uint32_t k = 0; k < cnt; ++k) {
-        const uint32_t tk = __shfl(t, k, 64), ck = __shfl(c, k, 64), nk = __shfl(nch, k, 64);
-        const uint32_t bk = __shfl(rb, k, 64), ek = __shfl(re, k, 64);
-        const uint32_t beg = bk + ck * kChunk;
-        const uint32_t end = min(ek, beg + kChunk);
-        double acc = 0.0;
-        uint32_t p = beg + lane;
-        for (; p + 192 < end; p += 256) {
-          double m0 = pull_msg<ST, G>(a, p), m1 = pull_msg<ST, G>(a, p + 64);
-          double m2 = pull_msg<ST, G>(a, p + 128), m3 = pull_msg<ST, G>(a, p + 192);
-          acc += (m0 + m1) + (m2 + m3);
-        }
-        for (; p < end; p += 64) acc += pull_msg<ST, G>(a, p);
-        acc = wave_sum(acc);
-        if (lane == 0) {
-          if (nk == 1) dv[tk] = (S)((double)dv[tk] + acc);
-          else unsafeAtomicAdd(&dv[tk], (S)acc);
-        }
-      }
+    using V = typename std::conditional<G == DAIC_G_EDGE_SCALE, double, S>::type;
+    __shared__ V vals[kStreamEdges];
+    __shared__ double acc[kStreamRows];
+    __shared__ uint32_t off[kStreamRows + 1];
+    const S* mu = static_cast<const S*>(a.mu_pi);
+    const S* wT = static_cast<const S*>(a.wT);
+    auto msg = [&](uint32_t src, uint32_t p) -> V {
+      V m = (V)mu[src];
+      if constexpr (G == DAIC_G_EDGE_SCALE) m *= (V)wT[p];
+      return m;
+    };
+    for (;;) {
+      stream_block<S, V>(a.rowT, a.srcT, static_cast<S*>(a.dv), t0, nr, e0, e1, vals, acc, off, msg);
+      b += gridDim.x;
+      if (b >= a.sb_count) break;
+      t0 = a.sb_t[b];
+      nr = a.sb_n[b];
+      e0 = a.sb_e[b];
+      e1 = a.sb_e[b + 1];
     }
   }
 }

@@ -50,6 +50,7 @@ struct daic_problem {
   GraphCacheKey key;
   std::vector<void*> allocs;
   bool pull_ready = false;
+  uint64_t stream_grid = 16384;  // workgroups of k_pull_stream
   uint64_t k_sel = 0;      // dense-round rule of the current run (see k_residual)
   uint64_t pull_min = 0;
   // learned scheduler state (allocated on first use)

@@ -1,6 +1,7 @@
 // Set-up of the in-edge form used by dense rounds: a renumbering of the
 // sources by out-degree and the transposed CSR sorted by (target, renumbered
-// source), built on the device with radix sorts, plus the static target bins.
+// source), built on the device with radix sorts, plus the edge blocks of the
+// streamed pull.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -71,10 +72,35 @@ uint32_t grid(uint64_t count) {
 
 }  // namespace
 
+void stream_blocks(const uint32_t* rt, uint64_t t_begin, uint64_t t_end, std::vector<uint32_t>& bt,
+                   std::vector<uint32_t>& be, std::vector<uint32_t>& bn) {
+  for (uint64_t t = t_begin; t < t_end;) {
+    const uint64_t deg = rt[t + 1] - rt[t];
+    if (deg == 0) {
+      ++t;
+      continue;
+    }
+    if (deg > kStreamEdges) {
+      for (uint64_t o = 0; o < deg; o += kStreamEdges) {
+        bt.push_back((uint32_t)t);
+        be.push_back((uint32_t)(rt[t] + o));
+        bn.push_back(1);
+      }
+      ++t;
+      continue;
+    }
+    uint64_t t1 = t + 1;
+    while (t1 < t_end && t1 - t < kStreamRows && (uint64_t)rt[t1 + 1] - rt[t] <= kStreamEdges) ++t1;
+    bt.push_back((uint32_t)t);
+    be.push_back(rt[t]);
+    bn.push_back((uint32_t)(t1 - t));
+    t = t1;
+  }
+}
+
 void pull_release(daic_graph* g) {
   PullGraph& p = g->pull;
-  for (void* q : {(void*)p.perm, p.rowT, (void*)p.srcT, (void*)p.eidT, (void*)p.small_tgt, (void*)p.large_tgt,
-                  (void*)p.large_chunk, (void*)p.large_nch})
+  for (void* q : {(void*)p.perm, p.rowT, (void*)p.srcT, (void*)p.eidT, (void*)p.sb_t, (void*)p.sb_e, (void*)p.sb_n})
     if (q) (void)hipFree(q);
   p = PullGraph();
 }
@@ -154,7 +180,7 @@ daic_status pull_prepare(daic_graph* g, hipStream_t s) {
   } else {
     hipLaunchKernelGGL(k_split_sorted, dim3(1), dim3(256), 0, s, k0, 0, n, P.srcT, static_cast<uint32_t*>(P.rowT));
   }
-  // 3. static target bins by in-degree (built on the host from the offsets)
+  // 3. edge blocks of the streamed pull (built on the host from the offsets)
   std::vector<uint32_t> rt(n + 1);
   PCHK(hipMemcpyAsync(rt.data(), P.rowT, (n + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   PCHK(hipStreamSynchronize(s));
@@ -162,27 +188,11 @@ daic_status pull_prepare(daic_graph* g, hipStream_t s) {
   k0 = k1 = nullptr;
   v0 = v1 = nullptr;
   tmp = nullptr;
-  std::vector<uint32_t> st, lt, lc, ln;
-  // small targets in id order: their offsets, in-edge lists and deltas are
-  // then read and written by consecutive lanes
-  for (uint64_t t = 0; t < n; ++t) {
-    uint32_t deg = rt[t + 1] - rt[t];
-    if (deg == 0) continue;
-    if (deg <= kSmallMaxDeg) {
-      st.push_back((uint32_t)t);
-      P.small_edges += deg;
-    } else {
-      P.large_edges += deg;
-      uint32_t nch = (deg + kChunk - 1) / kChunk;
-      for (uint32_t c = 0; c < nch; ++c) {
-        lt.push_back((uint32_t)t);
-        lc.push_back(c);
-        ln.push_back(nch);
-      }
-    }
-  }
-  P.n_small = st.size();
-  P.n_large = lt.size();
+  for (uint64_t t = 0; t < n; ++t) P.n_targets += rt[t + 1] > rt[t] ? 1 : 0;
+  std::vector<uint32_t> bt, be, bn;
+  stream_blocks(rt.data(), 0, n, bt, be, bn);
+  be.push_back((uint32_t)m);
+  P.sb_count = bt.size();
   {
     // sources are renumbered by out-degree, descending: those with out-edges first
     const uint32_t* rowp = static_cast<const uint32_t*>(d.row);
@@ -192,16 +202,14 @@ daic_status pull_prepare(daic_graph* g, hipStream_t s) {
     for (uint64_t j = 0; j < n; ++j) ns += ro[j + 1] > ro[j] ? 1 : 0;
     P.n_src = ns;
   }
-  PCHK(hipMalloc(&P.small_tgt, std::max<size_t>(st.size(), 1) * 4));
-  PCHK(hipMalloc(&P.large_tgt, std::max<size_t>(lt.size(), 1) * 4));
-  PCHK(hipMalloc(&P.large_chunk, std::max<size_t>(lt.size(), 1) * 4));
-  PCHK(hipMalloc(&P.large_nch, std::max<size_t>(lt.size(), 1) * 4));
-  if (!st.empty()) PCHK(hipMemcpy(P.small_tgt, st.data(), st.size() * 4, hipMemcpyHostToDevice));
-  if (!lt.empty()) {
-    PCHK(hipMemcpy(P.large_tgt, lt.data(), lt.size() * 4, hipMemcpyHostToDevice));
-    PCHK(hipMemcpy(P.large_chunk, lc.data(), lc.size() * 4, hipMemcpyHostToDevice));
-    PCHK(hipMemcpy(P.large_nch, ln.data(), ln.size() * 4, hipMemcpyHostToDevice));
+  PCHK(hipMalloc(&P.sb_t, std::max<size_t>(bt.size(), 1) * 4));
+  PCHK(hipMalloc(&P.sb_e, be.size() * 4));
+  PCHK(hipMalloc(&P.sb_n, std::max<size_t>(bn.size(), 1) * 4));
+  if (!bt.empty()) {
+    PCHK(hipMemcpy(P.sb_t, bt.data(), bt.size() * 4, hipMemcpyHostToDevice));
+    PCHK(hipMemcpy(P.sb_n, bn.data(), bn.size() * 4, hipMemcpyHostToDevice));
   }
+  PCHK(hipMemcpy(P.sb_e, be.data(), be.size() * 4, hipMemcpyHostToDevice));
 #undef PCHK
   P.ready = true;
   (void)rc;

@@ -141,13 +141,9 @@ struct Impl {
       hipLaunchKernelGGL((k_push_large<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
     });
     if (p->pull_ready) {
-      launch(pr, "pull_small", s, [&] {
-        uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((a.pn_small + 255) / 256, 8192));
-        hipLaunchKernelGGL((k_pull_small<ST, G>), dim3(gs), dim3(256), 0, s, a);
-      });
-      launch(pr, "pull_large", s, [&] {
-        uint32_t gl = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((a.pn_large + 15) / 16, 16384));
-        hipLaunchKernelGGL((k_pull_large<ST, G>), dim3(gl), dim3(64), 0, s, a);
+      launch(pr, "pull_stream", s, [&] {
+        uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(a.sb_count, p->stream_grid));
+        hipLaunchKernelGGL((k_pull_stream<ST, G>), dim3(gs), dim3(256), 0, s, a);
       });
     }
     launch(pr, "residual", s, [&] {
@@ -343,13 +339,11 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
     a.perm = g->pull.perm;
     a.rowT = static_cast<const uint32_t*>(g->pull.rowT);
     a.srcT = g->pull.srcT;
-    a.pt_small = g->pull.small_tgt;
-    a.pn_small = g->pull.n_small;
-    a.pt_large = g->pull.large_tgt;
-    a.pt_chunk = g->pull.large_chunk;
-    a.pt_nch = g->pull.large_nch;
-    a.pn_large = g->pull.n_large;
     a.n_src = g->pull.n_src;
+    a.sb_t = g->pull.sb_t;
+    a.sb_e = g->pull.sb_e;
+    a.sb_n = g->pull.sb_n;
+    a.sb_count = g->pull.sb_count;
     DAIC_HIP(hipStreamSynchronize(s));
     p->pull_ready = true;
     if (p->exec) {  // captured rounds predate the dense-round kernels
@@ -857,12 +851,12 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
     return n * 2.0 * S + (double)c.round_act * (2.0 * R + 2.0 * S + kahan) + out;
   }
   if (!std::strcmp(name, "residual")) return n * S;
-  if (!std::strcmp(name, "pull_small") || !std::strcmp(name, "pull_large")) {
+  if (!std::strcmp(name, "pull_stream")) {
+    // per in-edge: source 4 + message base S (+ weight S); per edge block 12;
+    // per target with in-edges: offsets 2R + dv read and write 2S
     const PullGraph& P = p->g->pull;
     const double per_in_edge = 4.0 + S + (p->gk == DAIC_G_EDGE_SCALE ? S : 0.0);
-    if (!std::strcmp(name, "pull_small"))
-      return (double)P.small_edges * per_in_edge + (double)P.n_small * (4.0 + 8.0 + 2.0 * S);
-    return (double)P.large_edges * per_in_edge + (double)P.n_large * (12.0 + 8.0 + 2.0 * S);
+    return (double)p->g->dev.m * per_in_edge + (double)P.sb_count * 12.0 + (double)P.n_targets * (2.0 * R + 2.0 * S);
   }
   return 0.0;
 }
@@ -919,8 +913,7 @@ daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, 
       k.alg_bytes += kernel_bytes(p, r.name, c);
       if (!std::strcmp(r.name, "push_small")) k.edges += (double)(c.round_pushed - c.round_pushed_large);
       if (!std::strcmp(r.name, "push_large")) k.edges += (double)c.round_pushed_large;
-      if (!std::strcmp(r.name, "pull_small")) k.edges += (double)p->g->pull.small_edges;
-      if (!std::strcmp(r.name, "pull_large")) k.edges += (double)p->g->pull.large_edges;
+      if (!std::strcmp(r.name, "pull_stream")) k.edges += (double)p->g->dev.m;
     }
     if (c.done || c.stop) break;
   }

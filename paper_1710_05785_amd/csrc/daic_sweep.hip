@@ -31,6 +31,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -56,13 +57,9 @@ struct SweepArgs {
   double alpha;
   void* mu2;                  // S[2n]: slot 0 then slot 1, by position
   const uint32_t* voff;       // [P+1]: block c owns ids [voff[c], voff[c+1])
-  const uint32_t* lt;         // items (target, chunk, chunks of target) of targets with
-  const uint32_t* lc;         // in-degree > kSmallMaxDeg, grouped by the target's block
-  const uint32_t* ln;
-  const uint32_t* loff;       // [P+1]
-  uint64_t n_items;
-  const uint32_t* sm;         // targets with 1..kSmallMaxDeg in-edges, grouped by block, ids ascending
-  const uint32_t* soff;       // [P+1]
+  const uint32_t* sb_t;       // edge blocks of the streamed pull, cut at block boundaries:
+  const uint32_t* sb_e;       //   first target, first in-edge (closing entry m),
+  const uint32_t* sb_n;       //   targets covered
   const uint32_t* rv;         // vertices with in-edges, grouped by block, ids ascending
   const uint32_t* roff;       // [P+1]
   const double* coef_le;      // [n] by position: sum of |w| to out-neighbours in blocks <= own
@@ -76,9 +73,9 @@ struct SweepArgs {
 struct SweepState {
   uint64_t B = 0;
   uint32_t P = 0;
-  uint64_t max_block_items = 0;  // largest item count of one block
   uint64_t max_block_verts = 0;
-  uint64_t max_block_small = 0;
+  std::vector<uint32_t> block_sb_off;  // [P+1]: edge blocks of block c
+  uint64_t sb_total = 0;           // edge blocks of all blocks
   std::vector<void*> allocs;
   SweepArgs a{};
 };
@@ -87,91 +84,47 @@ namespace {
 
 constexpr uint32_t kResGrid = 2048;
 
+// Block c: streamed pull of the block's targets. An in-edge from a source
+// at position s reads the base published in this sweep when s lies in an
+// earlier block (s < c B), else the base of the previous sweep.
 template <int ST, int G>
-__device__ __forceinline__ double sweep_msg(const SweepArgs& a, const typename Tr<ST>::S* mu2, uint32_t p,
-                                            uint32_t src, uint64_t lo, uint64_t cur, uint64_t prev) {
-  using S = typename Tr<ST>::S;
-  double m = (double)mu2[(src < lo ? cur : prev) + src];
-  if constexpr (G == DAIC_G_EDGE_SCALE) m *= (double)static_cast<const S*>(a.wT)[p];
-  return m;
-}
-
-// Block c, targets with more than kSmallMaxDeg in-edges: one wave per item
-// (target, chunk of kChunk in-edges; a block's items longest first) adds its
-// part of the pull into dv.
-template <int ST, int G>
-__global__ __launch_bounds__(256) void k_sweep_large(SweepArgs a, uint32_t c) {
+__global__ __launch_bounds__(256) void k_sweep_stream(SweepArgs a, uint32_t c, uint32_t b_begin, uint32_t b_end) {
   using S = typename Tr<ST>::S;
   Ctl* ctl = a.ctl;
+  uint64_t b = b_begin + blockIdx.x;
+  if (b >= b_end) return;
+  // the first edge block's descriptors are read together with the control block
+  uint32_t t0 = a.sb_t[b], nr = a.sb_n[b], e0 = a.sb_e[b], e1 = a.sb_e[b + 1];
   if (ctl_halted(ctl)) return;
+  using V = typename std::conditional<G == DAIC_G_EDGE_SCALE, double, S>::type;
+  __shared__ V vals[kStreamEdges];
+  __shared__ double acc[kStreamRows];
+  __shared__ uint32_t off[kStreamRows + 1];
   const uint64_t k = ctl->rounds / a.P;
   const uint64_t cur = (k & 1) * a.n, prev = ((k + 1) & 1) * a.n, lo = (uint64_t)c * a.B;
   const S* mu2 = static_cast<const S*>(a.mu2);
-  S* dv = static_cast<S*>(a.dv);
-  const uint64_t ib = a.loff[c], ie = a.loff[c + 1];
-  const uint32_t lane = lane_id();
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t i = ib + wave; i < ie; i += nwaves) {
-    const uint32_t t = a.lt[i], nch = a.ln[i];
-    const uint32_t beg = a.rowT[t] + a.lc[i] * kChunk;
-    const uint32_t end = min(a.rowT[t + 1], beg + kChunk);
-    double acc = 0.0;
-    uint32_t p = beg + lane;
-    for (; p + 192 < end; p += 256) {
-      const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 64], s2 = a.srcT[p + 128], s3 = a.srcT[p + 192];
-      const double m0 = sweep_msg<ST, G>(a, mu2, p, s0, lo, cur, prev);
-      const double m1 = sweep_msg<ST, G>(a, mu2, p + 64, s1, lo, cur, prev);
-      const double m2 = sweep_msg<ST, G>(a, mu2, p + 128, s2, lo, cur, prev);
-      const double m3 = sweep_msg<ST, G>(a, mu2, p + 192, s3, lo, cur, prev);
-      acc += (m0 + m1) + (m2 + m3);
-    }
-    for (; p < end; p += 64) acc += sweep_msg<ST, G>(a, mu2, p, a.srcT[p], lo, cur, prev);
-    acc = wave_sum(acc);
-    if (lane == 0) {
-      if (nch == 1) dv[t] = (S)((double)dv[t] + acc);
-      else unsafeAtomicAdd(&dv[t], (S)acc);
-    }
+  const S* wT = static_cast<const S*>(a.wT);
+  auto msg = [&](uint32_t src, uint32_t p) -> V {
+    V m = (V)mu2[(src < lo ? cur : prev) + src];
+    if constexpr (G == DAIC_G_EDGE_SCALE) m *= (V)wT[p];
+    return m;
+  };
+  for (;;) {
+    stream_block<S, V>(a.rowT, a.srcT, static_cast<S*>(a.dv), t0, nr, e0, e1, vals, acc, off, msg);
+    b += gridDim.x;
+    if (b >= b_end) break;
+    t0 = a.sb_t[b];
+    nr = a.sb_n[b];
+    e0 = a.sb_e[b];
+    e1 = a.sb_e[b + 1];
   }
 }
 
-// Block c, targets with 1..kSmallMaxDeg in-edges: one thread per target (ids
-// ascending, so offsets, lists and deltas are read by consecutive lanes) adds
-// its pull into dv.
-template <int ST, int G>
-__global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a, uint32_t c) {
-  using S = typename Tr<ST>::S;
-  Ctl* ctl = a.ctl;
-  if (ctl_halted(ctl)) return;
-  const uint64_t k = ctl->rounds / a.P;
-  const uint64_t cur = (k & 1) * a.n, prev = ((k + 1) & 1) * a.n, lo = (uint64_t)c * a.B;
-  const S* mu2 = static_cast<const S*>(a.mu2);
-  S* dv = static_cast<S*>(a.dv);
-  const uint64_t ib = a.soff[c], ie = a.soff[c + 1];
-  for (uint64_t i = ib + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ie;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t t = a.sm[i];
-    const uint32_t b0 = a.rowT[t], b1 = a.rowT[t + 1];
-    double acc = 0.0;
-    uint32_t p = b0;
-    for (; p + 3 < b1; p += 4) {
-      const uint32_t s0 = a.srcT[p], s1 = a.srcT[p + 1], s2 = a.srcT[p + 2], s3 = a.srcT[p + 3];
-      const double m0 = sweep_msg<ST, G>(a, mu2, p, s0, lo, cur, prev);
-      const double m1 = sweep_msg<ST, G>(a, mu2, p + 1, s1, lo, cur, prev);
-      const double m2 = sweep_msg<ST, G>(a, mu2, p + 2, s2, lo, cur, prev);
-      const double m3 = sweep_msg<ST, G>(a, mu2, p + 3, s3, lo, cur, prev);
-      acc += (m0 + m1) + (m2 + m3);
-    }
-    for (; p < b1; ++p) acc += sweep_msg<ST, G>(a, mu2, p, a.srcT[p], lo, cur, prev);
-    dv[t] = (S)((double)dv[t] + acc);
-  }
-}
-
-// Block c: fold the received sum (dv, filled by k_sweep_small and
-// k_sweep_large) into the state and publish the message base. Vertices
-// without in-edges receive nothing, so after their claim of the first sweep
-// and the clearing of both slots (sweeps 1 and 2) they are skipped; vertices
-// without out-edges have no reader and publish nothing.
+// Block c: fold the received sum (dv, filled by k_sweep_stream) into the
+// state and publish the message base. Vertices without in-edges receive
+// nothing, so after their claim of the first sweep and the clearing of both
+// slots (sweeps 1 and 2) they are skipped; vertices without out-edges have
+// no reader and publish nothing.
 template <int ST, int G>
 __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
   using S = typename Tr<ST>::S;
@@ -301,66 +254,41 @@ __global__ __launch_bounds__(256) void k_sweep_residual(SweepArgs a) {
 // last pulled in sweep k if bt <= cl, else in sweep k - 1; a base is
 // unconsumed when it was published at or after the target's pull in
 // (sweep, block) order, equal blocks included.
+// Every edge block (of all blocks) pulls the messages still in flight
+// towards its targets, which share one block bt.
 template <int ST, int G>
-__device__ __forceinline__ double sweep_pending(const SweepArgs& a, const typename Tr<ST>::S* mu2, uint32_t t,
-                                                uint32_t end, uint32_t step, uint32_t first) {
+__global__ __launch_bounds__(256) void k_sweep_deliver_stream(SweepArgs a, uint64_t nb) {
+  using S = typename Tr<ST>::S;
   const uint64_t R = a.ctl->rounds;
+  if (R == 0) return;
+  using V = typename std::conditional<G == DAIC_G_EDGE_SCALE, double, S>::type;
+  __shared__ V vals[kStreamEdges];
+  __shared__ double acc[kStreamRows];
+  __shared__ uint32_t off[kStreamRows + 1];
   const uint64_t k = (R - 1) / a.P, cl = (R - 1) % a.P;
   const uint64_t L = min<uint64_t>(a.n, (cl + 1) * a.B);
   const uint64_t cur = (k & 1) * a.n, prev = ((k + 1) & 1) * a.n;
-  const uint64_t bt = a.perm[t] / a.B, T0 = bt * a.B;
-  double acc = 0.0;
-  for (uint32_t p = first; p < end; p += step) {
-    const uint32_t s = a.srcT[p];
-    bool take;
-    uint64_t off;
-    if (bt <= cl) {
-      take = s >= T0 && s < L;
-      off = cur;
-    } else {
-      take = s < L || s >= T0;
-      off = s < L ? cur : prev;
-    }
-    if (take) {
-      double m = (double)mu2[off + s];
-      if constexpr (G == DAIC_G_EDGE_SCALE) m *= (double)static_cast<const typename Tr<ST>::S*>(a.wT)[p];
-      acc += m;
-    }
-  }
-  return acc;
-}
-
-template <int ST, int G>
-__global__ __launch_bounds__(256) void k_sweep_deliver_small(SweepArgs a) {
-  using S = typename Tr<ST>::S;
-  if (a.ctl->rounds == 0) return;
   const S* mu2 = static_cast<const S*>(a.mu2);
-  S* dv = static_cast<S*>(a.dv);
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t t = (uint32_t)i;
-    const uint32_t b0 = a.rowT[t], b1 = a.rowT[t + 1];
-    if (b1 == b0 || b1 - b0 > kSmallMaxDeg) continue;
-    const double acc = sweep_pending<ST, G>(a, mu2, t, b1, 1, b0);
-    if (acc != 0.0) dv[t] = (S)((double)dv[t] + acc);
-  }
-}
-
-template <int ST, int G>
-__global__ __launch_bounds__(256) void k_sweep_deliver_large(SweepArgs a) {
-  using S = typename Tr<ST>::S;
-  if (a.ctl->rounds == 0) return;
-  const S* mu2 = static_cast<const S*>(a.mu2);
-  S* dv = static_cast<S*>(a.dv);
-  const uint32_t lane = lane_id();
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t i = wave; i < a.n_items; i += nwaves) {
-    const uint32_t t = a.lt[i];
-    const uint32_t beg = a.rowT[t] + a.lc[i] * kChunk;
-    const uint32_t end = min(a.rowT[t + 1], beg + kChunk);
-    double acc = sweep_pending<ST, G>(a, mu2, t, end, 64, beg + lane);
-    acc = wave_sum(acc);
-    if (lane == 0 && acc != 0.0) unsafeAtomicAdd(&dv[t], (S)acc);
+  const S* wT = static_cast<const S*>(a.wT);
+  for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const uint32_t t0 = a.sb_t[b];
+    const uint64_t bt = t0 / a.B, T0 = bt * a.B;
+    auto msg = [&](uint32_t src, uint32_t p) -> V {
+      bool take;
+      uint64_t o;
+      if (bt <= cl) {
+        take = src >= T0 && src < L;
+        o = cur;
+      } else {
+        take = src < L || src >= T0;
+        o = src < L ? cur : prev;
+      }
+      V m = take ? (V)mu2[o + src] : (V)0;
+      if constexpr (G == DAIC_G_EDGE_SCALE) m *= (V)wT[p];
+      return m;
+    };
+    stream_block<S, V>(a.rowT, a.srcT, static_cast<S*>(a.dv), t0, a.sb_n[b], a.sb_e[b], a.sb_e[b + 1], vals, acc,
+                       off, msg);
   }
 }
 
@@ -409,10 +337,10 @@ template <int ST, int G>
 struct SweepImpl {
   static void round(const SweepState& w, hipStream_t s, uint32_t c) {
     const SweepArgs& a = w.a;
-    if (w.max_block_small)
-      hipLaunchKernelGGL((k_sweep_small<ST, G>), dim3(sgrid(w.max_block_small)), dim3(256), 0, s, a, c);
-    if (w.max_block_items)
-      hipLaunchKernelGGL((k_sweep_large<ST, G>), dim3(sgrid(w.max_block_items, 4)), dim3(256), 0, s, a, c);
+    // one workgroup per edge block of block c, at most 16384
+    const uint32_t bb = w.block_sb_off[c], be = w.block_sb_off[c + 1];
+    if (be > bb)
+      hipLaunchKernelGGL((k_sweep_stream<ST, G>), dim3(sgrid(be - bb, 1, 16384)), dim3(256), 0, s, a, c, bb, be);
     hipLaunchKernelGGL((k_sweep_claim<ST, G>), dim3(a.claim_blocks), dim3(256), 0, s, a, c);
     const bool end = c + 1 == a.P;
     hipLaunchKernelGGL(k_sweep_step, dim3(1), dim3(256), 0, s, a, end ? 1 : 0);
@@ -420,9 +348,9 @@ struct SweepImpl {
   }
   static void deliver(const SweepState& w, hipStream_t s) {
     const SweepArgs& a = w.a;
-    hipLaunchKernelGGL((k_sweep_deliver_small<ST, G>), dim3(sgrid(a.n)), dim3(256), 0, s, a);
-    if (a.n_items)
-      hipLaunchKernelGGL((k_sweep_deliver_large<ST, G>), dim3(sgrid(a.n_items, 4)), dim3(256), 0, s, a);
+    if (w.sb_total)
+      hipLaunchKernelGGL((k_sweep_deliver_stream<ST, G>), dim3(sgrid(w.sb_total, 1, 16384)), dim3(256), 0, s, a,
+                         w.sb_total);
   }
 };
 
@@ -485,33 +413,14 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
       psw[j] = fill[j / B]++;
     }
   }
-  std::vector<uint32_t> lt, lc, ln, loff(P + 1, 0), sm, soff(P + 1, 0), rv, roff(P + 1, 0);
+  std::vector<uint32_t> rv, roff(P + 1, 0);
+  std::vector<uint32_t> sbt, sbe, sbn, sboff(P + 1, 0);
   for (uint32_t c = 0; c < P; ++c) {
-    for (uint32_t t = voff[c]; t < voff[c + 1]; ++t) {
-      const uint32_t deg = rt[t + 1] - rt[t];
-      if (deg >= 1 && deg <= kSmallMaxDeg) sm.push_back(t);
-      if (deg >= 1) rv.push_back(t);
-    }
-    soff[c + 1] = (uint32_t)sm.size();
+    for (uint32_t t = voff[c]; t < voff[c + 1]; ++t)
+      if (rt[t + 1] > rt[t]) rv.push_back(t);
     roff[c + 1] = (uint32_t)rv.size();
-    w->max_block_small = std::max<uint64_t>(w->max_block_small, soff[c + 1] - soff[c]);
-    std::vector<std::pair<uint32_t, uint64_t>> items;  // (edges, target << 32 | chunk)
-    for (uint32_t t = voff[c]; t < voff[c + 1]; ++t) {
-      const uint32_t deg = rt[t + 1] - rt[t];
-      if (deg <= kSmallMaxDeg) continue;
-      for (uint32_t ch = 0; ch * kChunk < deg; ++ch)
-        items.push_back({std::min(kChunk, deg - ch * kChunk), ((uint64_t)t << 32) | ch});
-    }
-    std::stable_sort(items.begin(), items.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
-    for (auto& it : items) {
-      const uint32_t t = (uint32_t)(it.second >> 32);
-      const uint32_t deg = rt[t + 1] - rt[t];
-      lt.push_back(t);
-      lc.push_back((uint32_t)it.second);
-      ln.push_back((deg + kChunk - 1) / kChunk);
-    }
-    loff[c + 1] = (uint32_t)lt.size();
-    w->max_block_items = std::max<uint64_t>(w->max_block_items, loff[c + 1] - loff[c]);
+    stream_blocks(rt.data(), voff[c], voff[c + 1], sbt, sbe, sbn);
+    sboff[c + 1] = (uint32_t)sbt.size();
     w->max_block_verts = std::max<uint64_t>(w->max_block_verts, voff[c + 1] - voff[c]);
   }
   SweepArgs& a = w->a;
@@ -525,12 +434,12 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
   const size_t S = sweep_state_size(p->st);
   SGRAB(mu2, void*, 2 * n * S);
   SGRAB(voff, const uint32_t*, (P + 1) * 4);
-  SGRAB(lt, const uint32_t*, lt.size() * 4);
-  SGRAB(lc, const uint32_t*, lc.size() * 4);
-  SGRAB(ln, const uint32_t*, ln.size() * 4);
-  SGRAB(loff, const uint32_t*, (P + 1) * 4);
-  SGRAB(sm, const uint32_t*, sm.size() * 4);
-  SGRAB(soff, const uint32_t*, (P + 1) * 4);
+  sbe.push_back((uint32_t)d.m);
+  w->sb_total = sbt.size();
+  w->block_sb_off = sboff;
+  SGRAB(sb_t, const uint32_t*, sbt.size() * 4);
+  SGRAB(sb_e, const uint32_t*, sbe.size() * 4);
+  SGRAB(sb_n, const uint32_t*, sbn.size() * 4);
   SGRAB(rv, const uint32_t*, rv.size() * 4);
   SGRAB(roff, const uint32_t*, (P + 1) * 4);
   SGRAB(coef_le, const double*, n * 8);
@@ -543,17 +452,13 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
   SGRAB(part_m, uint64_t*, a.claim_blocks * 8);
 #undef SGRAB
   DAIC_HIP(hipMemcpy((void*)a.voff, voff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
-  if (!lt.empty()) {
-    DAIC_HIP(hipMemcpy((void*)a.lt, lt.data(), lt.size() * 4, hipMemcpyHostToDevice));
-    DAIC_HIP(hipMemcpy((void*)a.lc, lc.data(), lc.size() * 4, hipMemcpyHostToDevice));
-    DAIC_HIP(hipMemcpy((void*)a.ln, ln.data(), ln.size() * 4, hipMemcpyHostToDevice));
+  if (!sbt.empty()) {
+    DAIC_HIP(hipMemcpy((void*)a.sb_t, sbt.data(), sbt.size() * 4, hipMemcpyHostToDevice));
+    DAIC_HIP(hipMemcpy((void*)a.sb_n, sbn.data(), sbn.size() * 4, hipMemcpyHostToDevice));
   }
-  DAIC_HIP(hipMemcpy((void*)a.loff, loff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
-  if (!sm.empty()) DAIC_HIP(hipMemcpy((void*)a.sm, sm.data(), sm.size() * 4, hipMemcpyHostToDevice));
-  DAIC_HIP(hipMemcpy((void*)a.soff, soff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
+  DAIC_HIP(hipMemcpy((void*)a.sb_e, sbe.data(), sbe.size() * 4, hipMemcpyHostToDevice));
   if (!rv.empty()) DAIC_HIP(hipMemcpy((void*)a.rv, rv.data(), rv.size() * 4, hipMemcpyHostToDevice));
   DAIC_HIP(hipMemcpy((void*)a.roff, roff.data(), (P + 1) * 4, hipMemcpyHostToDevice));
-  a.n_items = lt.size();
   a.ctl = p->a.ctl;
   a.n = n;
   a.B = B;
