@@ -258,6 +258,12 @@ void daic_sched_destroy(daic_sched_model* m);
  * inputs x [N][3] (already standardized) and labels y [N] in {0, 1}, on the
  * BF16 MFMA kernels: for checking against a reference. grad: 4481 floats. */
 daic_status daic_mlp_forward(const daic_sched_model* m, const float* x, uint64_t N, float* logits);
+/* The scoring kernel of a learned round, exposed for unit tests: on the
+ * problem's current state at round 0 (every vertex last updated at round 0),
+ * writes each vertex's selection multiplier to score_out (n host floats):
+ * sigmoid(logit) of its standardized features for pending vertices, 0 for
+ * the others. The problem's state is not changed.                          */
+daic_status daic_sched_score(daic_problem* p, const daic_sched_model* m, float* score_out);
 daic_status daic_mlp_grad(const daic_sched_model* m, const float* x, const float* y, uint64_t N,
                           float* grad, double* loss /* nullable */);
 

@@ -15,6 +15,10 @@ HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in ordinary VGPRs: the network kernels apply ReLU and BF16
+    # conversion to every output, which would otherwise copy each one out of
+    # the accumulation registers first
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

@@ -588,32 +588,137 @@ __device__ __forceinline__ bool vertex_features(const KArgs& a, const uint32_t* 
   return true;
 }
 
+// The network held in registers for the whole scoring kernel: this lane's
+// A-operand fragments and the biases of the hidden units whose outputs it
+// holds. Layers 2 and 3 use the 16x16x32 BF16 MFMA: in step s (s = 0, 1)
+// lane (q, r) supplies 8 products over the hidden units 32 s + 4 q + i and
+// 32 s + 16 + 4 q + i (i = 0..3), which are exactly the units of the two
+// layer outputs (tiles 2 s and 2 s + 1) the lane already holds; A and B use
+// the same assignment, so the sum covers every unit once.
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+typedef short i16x8v __attribute__((ext_vector_type(8)));
+struct MlpRegs {
+  bf16x4 w1[4];      // layer 1, output tile mt: W1 row 16 mt + r, inputs 0..3 (lanes q = 0)
+  i16x8v w2[4][2];   // layer 2, output tile ot, step s: W2 row 16 ot + r at the units above
+  i16x8v w3[2];      // layer 3, step s: W3 at the units above (lanes r = 0)
+  f32x4 b1[4], b2[4];
+  float b3;
+};
+
+__device__ __forceinline__ uint32_t mlp_unit(int s, uint32_t q, int j) {
+  return 32 * s + (j < 4 ? 4 * q + j : 16 + 4 * q + (j - 4));
+}
+
+__device__ __forceinline__ void mlp_regs(const MlpDev& m, MlpRegs& R) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t q = lane >> 4, r = lane & 15;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      R.w1[t][i] = q == 0 ? (short)m.W1b[(16 * t + r) * 4 + i] : (short)0;
+      R.b1[t][i] = m.b1[16 * t + 4 * q + i];
+      R.b2[t][i] = m.b2[16 * t + 4 * q + i];
+    }
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) R.w2[t][st][j] = (short)m.W2b[(16 * t + r) * kH + mlp_unit(st, q, j)];
+  }
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) R.w3[st][j] = r == 0 ? (short)m.W3b[mlp_unit(st, q, j)] : (short)0;
+  R.b3 = m.b3[0];
+}
+
+__device__ __forceinline__ f32x4 mfma32(i16x8v a, i16x8v b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8v, a), __builtin_bit_cast(bf16x8v, b), c,
+                                                 0, 0, 0);
+}
+
+// BF16 of max(z, 0) for the four elements of an MFMA output: a packed
+// round-to-nearest-even conversion of each pair, then the ReLU as a packed
+// 16-bit integer max with 0 on the BF16 bits (a negative BF16 is a negative
+// int16, a non-negative one keeps its order), which equals rounding max(z, 0).
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef short i16x2v __attribute__((ext_vector_type(2)));
+typedef short i16x4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf16x4 relu_bf16(f32x4 z) {
+  const f32x2v z01 = {z[0], z[1]}, z23 = {z[2], z[3]};
+  const i16x2v zero = {0, 0};
+  const i16x2v lo = __builtin_elementwise_max(__builtin_bit_cast(i16x2v, __builtin_convertvector(z01, bf16x2v)), zero);
+  const i16x2v hi = __builtin_elementwise_max(__builtin_bit_cast(i16x2v, __builtin_convertvector(z23, bf16x2v)), zero);
+  return __builtin_bit_cast(bf16x4, __builtin_shufflevector(lo, hi, 0, 1, 2, 3));
+}
+
+// Logit of the 16 samples of one tile (lane r of q = 0 ends with sample r's;
+// bx: the tile's B operand of layer 1, sample r's inputs in lane r, q = 0).
+__device__ __forceinline__ float tile_logit(const MlpRegs& R, bf16x4 bx) {
+  bf16x4 h1[4], h2[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) h1[mt] = relu_bf16(mfma16(R.w1[mt], bx, R.b1[mt]));
+  const i16x8v g0 = __builtin_shufflevector(__builtin_bit_cast(i16x4v, h1[0]), __builtin_bit_cast(i16x4v, h1[1]),
+                                            0, 1, 2, 3, 4, 5, 6, 7);
+  const i16x8v g1 = __builtin_shufflevector(__builtin_bit_cast(i16x4v, h1[2]), __builtin_bit_cast(i16x4v, h1[3]),
+                                            0, 1, 2, 3, 4, 5, 6, 7);
+#pragma unroll
+  for (int ot = 0; ot < 4; ++ot) h2[ot] = relu_bf16(mfma32(R.w2[ot][1], g1, mfma32(R.w2[ot][0], g0, R.b2[ot])));
+  const i16x8v k0 = __builtin_shufflevector(__builtin_bit_cast(i16x4v, h2[0]), __builtin_bit_cast(i16x4v, h2[1]),
+                                            0, 1, 2, 3, 4, 5, 6, 7);
+  const i16x8v k1 = __builtin_shufflevector(__builtin_bit_cast(i16x4v, h2[2]), __builtin_bit_cast(i16x4v, h2[3]),
+                                            0, 1, 2, 3, 4, 5, 6, 7);
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  const f32x4 z = mfma32(R.w3[1], k1, mfma32(R.w3[0], k0, zero));
+  return z[0] + R.b3;
+}
+
 // Selection multiplier of every vertex: sigmoid(network score) for pending
 // vertices, a very large value for pending vertices not updated for 64 rounds
-// (no vertex is starved), 0 otherwise. One wavefront per 16 vertices.
+// (no vertex is starved), 0 otherwise. A wavefront takes 64 vertices at a
+// time (one per lane for the feature loads) and runs them as four 16-sample
+// MFMA tiles with the network in registers; 64 vertices without a pending
+// one are skipped.
 template <int ST, typename RowT>
 __global__ __launch_bounds__(256) void k_score(KArgs a, MlpDev m, FeatNorm fn, const uint32_t* indeg,
                                                const uint32_t* last_upd, float* score) {
   if (ctl_halted(a.ctl)) return;
   const uint32_t round = (uint32_t)a.ctl->rounds;
-  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
   const uint64_t waves = (uint64_t)gridDim.x * 4;
-  for (uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile * 16 < a.n; tile += waves) {
-    const uint64_t j = tile * 16 + (lane & 15);
+  MlpRegs R;
+  mlp_regs(m, R);
+  for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c * 64 < a.n; c += waves) {
+    const uint64_t j = c * 64 + lane;
     float f[3] = {0.f, 0.f, 0.f}, pr = 0.f;
     uint32_t since = 0;
     bool pend = false;
-    if (lane < 16 && j < a.n) pend = vertex_features<ST, RowT>(a, indeg, last_upd, round, j, f, pr, since);
+    if (j < a.n) pend = vertex_features<ST, RowT>(a, indeg, last_upd, round, j, f, pr, since);
     float x[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) x[i] = pend ? (f[i] - fn.mean[i]) * fn.inv_std[i] : 0.f;
-    TileAct t;
-    tile_forward(m, x[0], x[1], x[2], t);
-    if (lane < 16 && j < a.n) {
-      float sc = 0.f;
-      if (pend) sc = since >= 64 ? 1099511627776.0f : 1.f / (1.f + __expf(-t.logit));
-      score[j] = sc;
+    float logit = 0.f;
+    if (__ballot(pend) != 0) {  // wave-uniform; the four tiles are independent chains
+      float lt[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float y0 = __shfl(x[0], 16 * t + r, 64), y1 = __shfl(x[1], 16 * t + r, 64);
+        const float y2 = __shfl(x[2], 16 * t + r, 64);
+        bf16x4 bx;
+        bx[0] = q == 0 ? __builtin_bit_cast(short, (__bf16)y0) : (short)0;
+        bx[1] = q == 0 ? __builtin_bit_cast(short, (__bf16)y1) : (short)0;
+        bx[2] = q == 0 ? __builtin_bit_cast(short, (__bf16)y2) : (short)0;
+        bx[3] = 0;
+        lt[t] = tile_logit(R, bx);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float v = __shfl(lt[t], r, 64);  // sample r of tile t, from lane r
+        if (q == (uint32_t)t) logit = v;
+      }
     }
+    if (j < a.n) score[j] = pend ? (since >= 64 ? 1099511627776.0f : 1.f / (1.f + __expf(-logit))) : 0.f;
   }
 }
 
@@ -773,6 +878,21 @@ struct daic_trace {
 };
 
 extern "C" {
+
+daic_status daic_sched_score(daic_problem* p, const daic_sched_model* model, float* score_out) {
+  if (!p || !model || !score_out) return fail(DAIC_E_INVALID, "null argument");
+  const uint64_t n = p->g->dev.n;
+  if (n == 0) return DAIC_OK;
+  hipStream_t s = p->own_stream;
+  daic_status rc = learned_arrays(p, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, p->a.ctl, 0.0, ~0ull);
+  learned_ops(p).score(p, model, norm_of(model), s);
+  hipError_t e = hipMemcpyAsync(score_out, p->score, n * sizeof(float), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(DAIC_E_DEVICE, "sched_score: %s", hipGetErrorString(e));
+  return DAIC_OK;
+}
 
 // Runs exact top-k rounds (opts: sched TOPK_EXACT, q, eps, max_rounds) from
 // the problem's current state to the stop rule, sampling S vertices per round.

@@ -119,6 +119,7 @@ def lib():
         L.daic_sched_destroy.argtypes = [_vp]
         L.daic_sched_destroy.restype = None
         L.daic_mlp_forward.argtypes = [_vp, _vp, ctypes.c_uint64, _vp]
+        L.daic_sched_score.argtypes = [_vp, _vp, _vp]
         L.daic_mlp_grad.argtypes = [_vp, _vp, _vp, ctypes.c_uint64, _vp,
                                     ctypes.POINTER(ctypes.c_double)]
         L.daic_trace_record.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint32,
@@ -253,6 +254,13 @@ class Problem:
         if v0.shape != (self.n,) or dv1.shape != (self.n,):
             raise ValueError("v0 and dv1 must have n entries")
         check(lib().daic_problem_set_init(self._h, _addr(v0), _addr(dv1)), "daic_problem_set_init")
+
+    def sched_score(self, model):
+        """Selection multiplier of every vertex under the learned rule at
+        round 0 (test hook of the scoring kernel)."""
+        out = np.empty(self.n, dtype=np.float32)
+        check(lib().daic_sched_score(self._h, model.handle, _addr(out)), "daic_sched_score")
+        return out
 
     def set_init_device(self, v0, dv1, stream=None):
         """(v0, dv1) from device tensors in the state's element type."""

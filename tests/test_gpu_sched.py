@@ -61,6 +61,52 @@ def test_mlp_forward_matches_oracle(daic, n):
     assert rel(got, want) <= 2e-2, rel(got, want)
 
 
+@pytest.mark.parametrize("case", ["powerlaw_5000", "rmat_14"])
+def test_score_kernel_matches_oracle(daic, case):
+    """The scoring kernel of learned rounds (features, standardization, BF16
+    network on MFMA, sigmoid) against the oracle network on the features
+    computed here from the same state: vertices without a pending delta
+    score exactly 0; the others' logits agree to the BF16 tolerance. Sizes
+    span many 64-vertex chunks with a ragged tail (5000)."""
+    import daic_gen
+
+    say("case score kernel", case)
+    g = daic_gen.powerlaw(5000, seed=31) if case == "powerlaw_5000" else daic_gen.rmat(14, 8, seed=32)
+    n = g.n
+    rng = np.random.default_rng(33)
+    dv1 = (rng.uniform(0.5, 1.0, n) * 10.0 ** rng.uniform(-6, 0, n)).astype(np.float32)
+    dv1[rng.uniform(size=n) < 0.25] = 0.0  # not pending
+    v0 = rng.uniform(0, 1, n).astype(np.float32)
+    P = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.85,
+                     state="f32_kahan")
+    P.set_init(v0.astype(np.float64), dv1.astype(np.float64))
+    m0 = daic.SchedModel(seed=34)
+    p, _, _ = m0.params()
+    p["b1"] = rng.normal(0, 0.3, 64).astype(np.float32)
+    p["b2"] = rng.normal(0, 0.3, 64).astype(np.float32)
+    p["b3"] = rng.normal(0, 0.3, 1).astype(np.float32)
+    m = daic.SchedModel(params=p)
+    mean = np.array([-8.0, 0.1, 0.2], dtype=np.float32)
+    std = np.array([5.0, 1.5, 0.5], dtype=np.float32)
+    m.set_features(mean, std)
+    got = P.sched_score(m)
+    # features in FP32 as the kernel forms them (round 0: no rounds since the last update)
+    outdeg = np.diff(g.row_ptr).astype(np.float32)
+    indeg = np.bincount(g.col, minlength=n).astype(np.float32)
+    pend = dv1 != 0
+    f = np.zeros((n, 3), dtype=np.float32)
+    f[:, 0] = np.log2(np.abs(dv1) + np.float32(1e-30))
+    f[:, 1] = np.log2((np.float32(1) + indeg) / (np.float32(1) + outdeg))
+    x = (f - mean) * (np.float32(1) / std)
+    want_logit, _ = oracle.mlp_forward(ref_params(p), bf16_round(x[pend]))
+    assert np.all(got[~pend] == 0.0)
+    s = got[pend].astype(np.float64)
+    ok = (s > 1e-4) & (s < 1 - 1e-4)
+    assert ok.mean() > 0.9
+    got_logit = np.log(s[ok] / (1 - s[ok]))
+    assert rel(got_logit, want_logit[ok]) <= 2e-2, rel(got_logit, want_logit[ok])
+
+
 def test_mfma_lane_layout_single_units(daic):
     """Each hidden unit and input feature in isolation: catches a transposed
     or misplaced operand in the MFMA lane layout (exact up to BF16 rounding)."""
