@@ -179,7 +179,12 @@ daic_status daic_problem_set_init(daic_problem* p, const void* v0, const void* d
  * stream the call returns after the copy. */
 daic_status daic_problem_set_init_device(daic_problem* p, const void* d_v0, const void* d_dv1,
                                          void* hip_stream);
-/* Run rounds until the stop rule holds (DAIC_OK) or max_rounds (warning). */
+/* Run rounds until the stop rule holds (DAIC_OK) or max_rounds (warning).
+ * Sum problems run a round as a pull over in-edges when at least n/32
+ * vertices update (env DAIC_PULL_DIV sets 32, DAIC_NO_PULL=1 always pushes);
+ * under DAIC_SCHED_ALL such rounds fuse the next round's claim into the pull
+ * (DAIC_NO_FUSE=1 keeps them apart). Every form ends in the same state after
+ * the same rounds (up to FP32 summation order). */
 daic_status daic_run(daic_problem* p, const daic_run_opts* opts, daic_stats* stats);
 /* Copy the state out: v_out (n values; double for FP states, where F32_KAHAN
  * reports v - c in FP64), dv_out nullable (same type). */

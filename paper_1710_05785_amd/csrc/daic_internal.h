@@ -62,6 +62,7 @@ struct Ctl {
   uint32_t radix_skip;   // radix select: nothing to do (all pending fit)
   uint32_t pull;         // the next round runs as a pull over in-edges (dense round)
   uint32_t last_pull;    // the round just run was a dense round
+  uint64_t fuse_base;    // fused dense rounds: round count when buffer A was last published
   uint32_t hist[256];    // radix select histogram
 };
 
@@ -96,9 +97,11 @@ void pull_release(daic_graph* g);
 // in-edge offsets rt: whole targets in id order while a block holds at most
 // kStreamEdges in-edges and kStreamRows targets; a target with more in-edges
 // is cut into pieces of kStreamEdges. Appends (first target, first in-edge,
-// targets covered) per block; targets without in-edges start no block.
+// targets covered) per block. Targets without in-edges start no block unless
+// cover_all (then every target of the range is in exactly one block, and a
+// block may have no in-edges).
 void stream_blocks(const uint32_t* rt, uint64_t t_begin, uint64_t t_end, std::vector<uint32_t>& bt,
-                   std::vector<uint32_t>& be, std::vector<uint32_t>& bn);
+                   std::vector<uint32_t>& be, std::vector<uint32_t>& bn, bool cover_all);
 
 }  // namespace daic
 
@@ -118,6 +121,11 @@ struct PullGraph {
   uint32_t* sb_e = nullptr;       //   first in-edge with a closing entry m,
   uint32_t* sb_n = nullptr;       //   targets covered)
   uint64_t sb_count = 0;
+  uint32_t* sb_g = nullptr;       // group of a piece of a cut target, else 0xFFFFFFFF
+  uint32_t* g_np = nullptr;       // pieces of each group
+  uint32_t* g_first = nullptr;    // first block of each group
+  uint64_t n_groups = 0;
+  uint64_t n_pieces = 0;          // blocks that are pieces of cut targets
 };
 }  // namespace daic
 

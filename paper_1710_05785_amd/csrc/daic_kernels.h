@@ -77,6 +77,19 @@ struct KArgs {
   const uint32_t* sb_e;     //   first in-edge (one extra entry: m),
   const uint32_t* sb_n;     //   number of targets covered
   uint64_t sb_count;
+  // fused dense rounds
+  void* mu_pi2;             // S[n] second message-base buffer (rounds alternate A, B)
+  const uint32_t* sb_g;     // group of a piece of a cut target, else 0xFFFFFFFF
+  const uint32_t* g_np;     // pieces per group
+  const uint32_t* g_first;  // first block of each group
+  uint64_t n_groups;
+  double* sb_part;          // partial sum of each piece (per block)
+  double* fpart_r;          // per-workgroup partials of k_pull_fused: |new delta|,
+  uint64_t* fpart_a;        //   vertex updates,
+  uint64_t* fpart_p;        //   messages
+  double* gpart_r;          // the same per block of k_fused_finish
+  uint64_t* gpart_a;
+  uint64_t* gpart_p;
 };
 
 __device__ __forceinline__ bool ctl_halted(const Ctl* ctl) {
@@ -381,7 +394,14 @@ static __global__ void k_init_ctl(Ctl* ctl, double eps, uint64_t max_rounds) {
   ctl->radix_skip = 1;
   ctl->pull = 0;
   ctl->last_pull = 0;
+  ctl->fuse_base = 0;
   for (int i = 0; i < 256; ++i) ctl->hist[i] = 0;
+}
+
+// The stop flags are recomputed by the next residual.
+static __global__ void k_clear_done(Ctl* ctl) {
+  ctl->done = 0;
+  ctl->stop = 0;
 }
 
 // Selection of every pending vertex (DAIC_SCHED_ALL).
@@ -775,37 +795,39 @@ __global__ __launch_bounds__(64) void k_push_large(KArgs a) {
 // meets, adding into per-target LDS accumulators (FP64). Targets wholly
 // inside the block are written once; pieces of a cut target add atomically.
 // msg(source, in-edge) returns the message carried by an in-edge.
-template <typename S, typename V, typename Msg>
-__device__ __forceinline__ void stream_block(const uint32_t* rowT, const uint32_t* srcT, S* dv, uint32_t t0,
-                                             uint32_t nr, uint32_t e0, uint32_t e1, V* vals, double* acc,
-                                             uint32_t* off, const Msg& msg) {
-  constexpr uint32_t PER = kStreamEdges / 256, ROFF = (kStreamRows + 256) / 256, RDV = kStreamRows / 256;
+// Gathers one block's messages and sums them per target. On return (after a
+// barrier) acc[i] holds the FP64 sum of target t0 + i and off[0..nr] the
+// block-relative in-edge offsets, clipped to [0, ne]. A block may have no
+// in-edges (then every sum is 0).
+template <typename V, typename Msg>
+__device__ __forceinline__ void stream_sums(const uint32_t* rowT, const uint32_t* srcT, uint32_t t0, uint32_t nr,
+                                            uint32_t e0, uint32_t e1, V* vals, double* acc, uint32_t* off,
+                                            const Msg& msg) {
+  constexpr uint32_t PER = kStreamEdges / 256, ROFF = (kStreamRows + 256) / 256;
   const uint32_t tid = threadIdx.x;
   const uint32_t ne = e1 - e0;
   // every independent load first, at clamped indices (no branch around
-  // them, so they are in flight together): row offsets, sources, and dv of
-  // this thread's targets (only this workgroup writes a whole target's dv)
-  uint32_t ro[ROFF], src[PER];
-  S dvp[RDV];
+  // them, so they are in flight together): row offsets and sources
+  uint32_t ro[ROFF];
 #pragma unroll
   for (uint32_t k = 0; k < ROFF; ++k) ro[k] = rowT[t0 + min(tid + 256 * k, nr)];
+  if (ne > 0) {  // uniform over the workgroup
+    uint32_t src[PER];
 #pragma unroll
-  for (uint32_t j = 0; j < PER; ++j) src[j] = srcT[e0 + min(tid + 256 * j, ne - 1)];
+    for (uint32_t j = 0; j < PER; ++j) src[j] = srcT[e0 + min(tid + 256 * j, ne - 1)];
+    V val[PER];
 #pragma unroll
-  for (uint32_t k = 0; k < RDV; ++k) dvp[k] = dv[t0 + min(tid + 256 * k, nr - 1)];
-  V val[PER];
+    for (uint32_t j = 0; j < PER; ++j) val[j] = msg(src[j], e0 + min(tid + 256 * j, ne - 1));
+    // lanes past the block's end store 0
 #pragma unroll
-  for (uint32_t j = 0; j < PER; ++j) val[j] = msg(src[j], e0 + min(tid + 256 * j, ne - 1));
-  // row offsets relative to the block, clipped to [0, ne]
+    for (uint32_t j = 0; j < PER; ++j) vals[tid + 256 * j] = tid + 256 * j < ne ? val[j] : (V)0;
+  }
 #pragma unroll
   for (uint32_t k = 0; k < ROFF; ++k) {
     const uint32_t i = tid + 256 * k;
     if (i <= nr) off[i] = ro[k] <= e0 ? 0u : min(ro[k] - e0, ne);
     if (i < nr) acc[i] = 0.0;
   }
-  // lanes past the block's end store 0
-#pragma unroll
-  for (uint32_t j = 0; j < PER; ++j) vals[tid + 256 * j] = tid + 256 * j < ne ? val[j] : (V)0;
   __syncthreads();
   // this thread's run [q0, q1) of the block's values
   const uint32_t q0 = min(tid * PER, ne), q1 = min(q0 + PER, ne);
@@ -830,6 +852,20 @@ __device__ __forceinline__ void stream_block(const uint32_t* rowT, const uint32_
     atomicAdd(&acc[i], sum);
   }
   __syncthreads();
+}
+
+template <typename S, typename V, typename Msg>
+__device__ __forceinline__ void stream_block(const uint32_t* rowT, const uint32_t* srcT, S* dv, uint32_t t0,
+                                             uint32_t nr, uint32_t e0, uint32_t e1, V* vals, double* acc,
+                                             uint32_t* off, const Msg& msg) {
+  constexpr uint32_t RDV = kStreamRows / 256;
+  const uint32_t tid = threadIdx.x;
+  // dv of this thread's targets, read early (only this workgroup writes a
+  // whole target's dv)
+  S dvp[RDV];
+#pragma unroll
+  for (uint32_t k = 0; k < RDV; ++k) dvp[k] = dv[t0 + min(tid + 256 * k, nr - 1)];
+  stream_sums<V>(rowT, srcT, t0, nr, e0, e1, vals, acc, off, msg);
   // several targets: all whole; one target: whole or a piece
   const bool piece = nr == 1 && (rowT[t0] != e0 || rowT[t0 + 1] != e1);
 #pragma unroll
@@ -877,6 +913,202 @@ __global__ __launch_bounds__(256) void k_pull_stream(KArgs a) {
     }
   }
 }
+
+// Fused dense round (sum problems, every pending vertex updated each round).
+// Round r of Eq. sync claims the deltas left by round r - 1 (folds them into
+// v and sends their messages) and pulls those messages into new deltas. Here
+// one kernel does round r's pull and, for each target right after its sum
+// is known, the claim work that does not change round r's messages: it folds
+// the target's previous delta into v and publishes the message base of its
+// new delta into the other buffer (A and B alternate by round), to be pulled
+// by round r + 1. After the round, (v, dv) is exactly the state after round
+// r, and the bases in flight are those round r + 1 would send. The kernel
+// only stores (no atomics, no fences): a piece of a cut target stores its
+// partial sum, every workgroup stores its partial residual and counters, and
+// k_fused_finish completes the cut targets and the round's totals.
+template <int ST, int G>
+struct FusedTarget {
+  using S = typename Tr<ST>::S;
+  // target t: fold its previous delta d_old into v (Kahan when the state
+  // has the compensation term: the claim of Eq. sync), keep the new delta
+  // d_new in dv and publish its message base into mu_out
+  static __device__ __forceinline__ void finish(const KArgs& a, S* mu_out, uint32_t t, S d_old, S d_new, S vt,
+                                                float ct, uint32_t deg, uint32_t pt, double& r_part, uint64_t& act,
+                                                uint64_t& pushed) {
+    S* v = static_cast<S*>(a.v);
+    if (d_old != (S)0) {
+      if constexpr (Tr<ST>::kahan) {
+#pragma clang fp contract(off)
+        const float y = d_old - ct;
+        const float tt = vt + y;
+        a.c[t] = (tt - vt) - y;
+        v[t] = tt;
+      } else {
+        v[t] = vt + d_old;
+      }
+      act += 1;
+      pushed += deg;
+    }
+    if (d_new != d_old) static_cast<S*>(a.dv)[t] = d_new;
+    r_part += fabs((double)d_new);
+    if (pt < a.n_src) {
+      double coef;
+      if constexpr (G == DAIC_G_DEG_SCALE) coef = a.alpha / (double)max(deg, 1u);
+      else coef = a.alpha_pv ? (double)static_cast<const S*>(a.alpha_pv)[t] : a.alpha;
+      mu_out[pt] = (d_new != (S)0 && deg > 0) ? (S)(coef * (double)d_new) : (S)0;
+    }
+  }
+};
+
+template <int ST, int G>
+__global__ __launch_bounds__(256) void k_pull_fused(KArgs a) {
+  using S = typename Tr<ST>::S;
+  if constexpr (Tr<ST>::sum) {
+    constexpr uint32_t RDV = kStreamRows / 256;
+    Ctl* ctl = a.ctl;
+    uint64_t b = blockIdx.x;  // the grid never exceeds the block count
+    uint32_t t0 = a.sb_t[b], nr = a.sb_n[b], e0 = a.sb_e[b], e1 = a.sb_e[b + 1], grp = a.sb_g[b];
+    if (ctl_halted(ctl)) return;
+    using V = typename std::conditional<G == DAIC_G_EDGE_SCALE, double, S>::type;
+    __shared__ V vals[kStreamEdges];
+    __shared__ double acc[kStreamRows];
+    __shared__ uint32_t off[kStreamRows + 1];
+    const uint32_t tid = threadIdx.x;
+    const bool odd = ((ctl->rounds - ctl->fuse_base) & 1) != 0;
+    const S* mu_in = static_cast<const S*>(odd ? a.mu_pi2 : a.mu_pi);
+    S* mu_out = static_cast<S*>(odd ? a.mu_pi : a.mu_pi2);
+    const S* wT = static_cast<const S*>(a.wT);
+    const uint32_t* row = static_cast<const uint32_t*>(a.row);
+    const S* dv = static_cast<const S*>(a.dv);
+    const S* v = static_cast<const S*>(a.v);
+    auto msg = [&](uint32_t src, uint32_t p) -> V {
+      V m = (V)mu_in[src];
+      if constexpr (G == DAIC_G_EDGE_SCALE) m *= (V)wT[p];
+      return m;
+    };
+    double r_part = 0.0;
+    uint64_t act = 0, pushed = 0;
+    for (;;) {
+      S dvp[RDV], vp[RDV];
+      float cp[RDV];
+      uint32_t dg[RDV], pp[RDV];
+      if (grp == 0xFFFFFFFFu) {  // uniform: whole targets; their operands are read early
+#pragma unroll
+        for (uint32_t k = 0; k < RDV; ++k) {
+          const uint32_t t = t0 + min(tid + 256 * k, nr - 1);
+          dvp[k] = dv[t];
+          vp[k] = v[t];
+          cp[k] = Tr<ST>::kahan ? a.c[t] : 0.f;
+          dg[k] = row[t + 1] - row[t];
+          pp[k] = a.perm[t];
+        }
+      }
+      stream_sums<V>(a.rowT, a.srcT, t0, nr, e0, e1, vals, acc, off, msg);
+      if (grp == 0xFFFFFFFFu) {
+#pragma unroll
+        for (uint32_t k = 0; k < RDV; ++k) {
+          const uint32_t i = tid + 256 * k;
+          if (i < nr)
+            FusedTarget<ST, G>::finish(a, mu_out, t0 + i, dvp[k], (S)acc[i], vp[k], cp[k], dg[k], pp[k], r_part,
+                                       act, pushed);
+        }
+      } else if (tid == 0) {
+        a.sb_part[b] = acc[0];  // a piece of a cut target
+      }
+      __syncthreads();
+      b += gridDim.x;
+      if (b >= a.sb_count) break;
+      t0 = a.sb_t[b];
+      nr = a.sb_n[b];
+      e0 = a.sb_e[b];
+      e1 = a.sb_e[b + 1];
+      grp = a.sb_g[b];
+    }
+    r_part = block_sum256(r_part);
+    act = block_sum256(act);
+    pushed = block_sum256(pushed);
+    if (tid == 0) {
+      a.fpart_r[blockIdx.x] = r_part;
+      a.fpart_a[blockIdx.x] = act;
+      a.fpart_p[blockIdx.x] = pushed;
+    }
+  }
+}
+
+// After k_pull_fused (nf of its workgroups): one thread per cut target sums
+// the target's pieces in order and finishes it, and the blocks add up the
+// partials of k_pull_fused; the last block to finish adds the per-block
+// partials in a fixed order and updates the control block (residual,
+// counters, round count, stop rule).
+template <int ST, int G>
+__global__ __launch_bounds__(256) void k_fused_finish(KArgs a, uint32_t nf) {
+  using S = typename Tr<ST>::S;
+  if constexpr (Tr<ST>::sum) {
+    Ctl* ctl = a.ctl;
+    if (ctl_halted(ctl)) return;
+    __shared__ uint32_t s_last;
+    const uint32_t tid = threadIdx.x;
+    const bool odd = ((ctl->rounds - ctl->fuse_base) & 1) != 0;
+    S* mu_out = static_cast<S*>(odd ? a.mu_pi : a.mu_pi2);
+    const uint32_t* row = static_cast<const uint32_t*>(a.row);
+    double r_part = 0.0;
+    uint64_t act = 0, pushed = 0;
+    // the partials of k_pull_fused, spread over this grid (written by the
+    // previous kernel)
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + tid; i < nf; i += (uint64_t)gridDim.x * 256) {
+      r_part += a.fpart_r[i];
+      act += a.fpart_a[i];
+      pushed += a.fpart_p[i];
+    }
+    const uint64_t g = (uint64_t)blockIdx.x * 256 + tid;
+    if (g < a.n_groups) {
+      const uint32_t b0 = a.g_first[g], np = a.g_np[g];
+      double sum = 0.0;
+      for (uint32_t k = 0; k < np; ++k) sum += a.sb_part[b0 + k];
+      const uint32_t t = a.sb_t[b0];
+      FusedTarget<ST, G>::finish(a, mu_out, t, static_cast<const S*>(a.dv)[t], (S)sum, static_cast<const S*>(a.v)[t],
+                                 Tr<ST>::kahan ? a.c[t] : 0.f, row[t + 1] - row[t], a.perm[t], r_part, act, pushed);
+    }
+    r_part = block_sum256(r_part);
+    act = block_sum256(act);
+    pushed = block_sum256(pushed);
+    if (tid == 0) {
+      a.gpart_r[blockIdx.x] = r_part;
+      a.gpart_a[blockIdx.x] = act;
+      a.gpart_p[blockIdx.x] = pushed;
+      __threadfence();
+      s_last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double rr = 0.0;
+    uint64_t aa = 0, ps = 0;
+    for (uint32_t i = tid; i < gridDim.x; i += 256) {
+      rr += __hip_atomic_load(&a.gpart_r[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      aa += __hip_atomic_load(&a.gpart_a[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ps += __hip_atomic_load(&a.gpart_p[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    rr = block_sum256(rr);
+    aa = block_sum256(aa);
+    ps = block_sum256(ps);
+    if (tid == 0) {
+      ctl->r = rr;
+      ctl->rounds += 1;
+      ctl->activations += aa;
+      ctl->pushed += ps;
+      ctl->round_act = aa;
+      ctl->round_pushed = ps;
+      const bool done = rr <= ctl->eps;
+      ctl->done = done ? 1u : 0u;
+      ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
+      ctl->ticket = 0;
+    }
+  }
+}
+
+// Start of fused dense rounds: the bases just published went to buffer A.
+static __global__ void k_fuse_begin(Ctl* ctl) { ctl->fuse_base = ctl->rounds; }
 
 // Weights in in-edge order: wT[p] = w[eidT[p]].
 template <typename S>

@@ -47,6 +47,10 @@ struct daic_problem {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  hipGraphExec_t exec_fused = nullptr;  // K fused dense rounds
+  hipGraph_t graph_fused = nullptr;
+  uint32_t fused_K = 0;
+  hipStream_t fused_stream = nullptr;
   GraphCacheKey key;
   std::vector<void*> allocs;
   bool pull_ready = false;
@@ -104,6 +108,10 @@ struct Ops {
   void (*residual)(daic_problem*, hipStream_t, int);
   void (*round)(daic_problem*, const daic_run_opts*, hipStream_t, const float* score, Prof* pr);
   void (*select)(daic_problem*, const daic_run_opts*, hipStream_t, uint64_t round_override);
+  // fused dense rounds (sum problems with the in-edge form): the claim that
+  // publishes buffer A, and one fused round
+  void (*fuse_prime)(daic_problem*, const daic_run_opts*, hipStream_t, Prof* pr);
+  void (*fused_round)(daic_problem*, hipStream_t, Prof* pr);
 };
 
 // The enqueue table of a problem's (state, g, row width) instantiation.

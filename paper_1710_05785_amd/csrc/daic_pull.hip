@@ -73,10 +73,10 @@ uint32_t grid(uint64_t count) {
 }  // namespace
 
 void stream_blocks(const uint32_t* rt, uint64_t t_begin, uint64_t t_end, std::vector<uint32_t>& bt,
-                   std::vector<uint32_t>& be, std::vector<uint32_t>& bn) {
+                   std::vector<uint32_t>& be, std::vector<uint32_t>& bn, bool cover_all) {
   for (uint64_t t = t_begin; t < t_end;) {
     const uint64_t deg = rt[t + 1] - rt[t];
-    if (deg == 0) {
+    if (deg == 0 && !cover_all) {
       ++t;
       continue;
     }
@@ -100,7 +100,8 @@ void stream_blocks(const uint32_t* rt, uint64_t t_begin, uint64_t t_end, std::ve
 
 void pull_release(daic_graph* g) {
   PullGraph& p = g->pull;
-  for (void* q : {(void*)p.perm, p.rowT, (void*)p.srcT, (void*)p.eidT, (void*)p.sb_t, (void*)p.sb_e, (void*)p.sb_n})
+  for (void* q : {(void*)p.perm, p.rowT, (void*)p.srcT, (void*)p.eidT, (void*)p.sb_t, (void*)p.sb_e, (void*)p.sb_n,
+                  (void*)p.sb_g, (void*)p.g_np, (void*)p.g_first})
     if (q) (void)hipFree(q);
   p = PullGraph();
 }
@@ -189,10 +190,26 @@ daic_status pull_prepare(daic_graph* g, hipStream_t s) {
   v0 = v1 = nullptr;
   tmp = nullptr;
   for (uint64_t t = 0; t < n; ++t) P.n_targets += rt[t + 1] > rt[t] ? 1 : 0;
+  // every target is in one block (the fused dense round claims through them)
   std::vector<uint32_t> bt, be, bn;
-  stream_blocks(rt.data(), 0, n, bt, be, bn);
+  stream_blocks(rt.data(), 0, n, bt, be, bn, true);
   be.push_back((uint32_t)m);
   P.sb_count = bt.size();
+  // pieces of one cut target form a group; the last piece of a round to
+  // finish claims the target
+  std::vector<uint32_t> bg(bt.size(), 0xFFFFFFFFu), gnp, gfirst;
+  for (size_t b = 0; b < bt.size();) {
+    size_t e = b + 1;
+    while (e < bt.size() && bn[b] == 1 && bn[e] == 1 && bt[e] == bt[b]) ++e;
+    if (e - b > 1) {
+      for (size_t k = b; k < e; ++k) bg[k] = (uint32_t)gnp.size();
+      gnp.push_back((uint32_t)(e - b));
+      gfirst.push_back((uint32_t)b);
+      P.n_pieces += e - b;
+    }
+    b = e;
+  }
+  P.n_groups = gnp.size();
   {
     // sources are renumbered by out-degree, descending: those with out-edges first
     const uint32_t* rowp = static_cast<const uint32_t*>(d.row);
@@ -202,6 +219,12 @@ daic_status pull_prepare(daic_graph* g, hipStream_t s) {
     for (uint64_t j = 0; j < n; ++j) ns += ro[j + 1] > ro[j] ? 1 : 0;
     P.n_src = ns;
   }
+  PCHK(hipMalloc(&P.sb_g, std::max<size_t>(bg.size(), 1) * 4));
+  PCHK(hipMalloc(&P.g_np, std::max<size_t>(gnp.size(), 1) * 4));
+  if (!bg.empty()) PCHK(hipMemcpy(P.sb_g, bg.data(), bg.size() * 4, hipMemcpyHostToDevice));
+  if (!gnp.empty()) PCHK(hipMemcpy(P.g_np, gnp.data(), gnp.size() * 4, hipMemcpyHostToDevice));
+  PCHK(hipMalloc(&P.g_first, std::max<size_t>(gfirst.size(), 1) * 4));
+  if (!gfirst.empty()) PCHK(hipMemcpy(P.g_first, gfirst.data(), gfirst.size() * 4, hipMemcpyHostToDevice));
   PCHK(hipMalloc(&P.sb_t, std::max<size_t>(bt.size(), 1) * 4));
   PCHK(hipMalloc(&P.sb_e, be.size() * 4));
   PCHK(hipMalloc(&P.sb_n, std::max<size_t>(bn.size(), 1) * 4));

@@ -157,7 +157,39 @@ struct Impl {
     hipLaunchKernelGGL((k_claim<ST, G, RowT, true>), dim3(a.blocks), dim3(256), 0, s, a);
   }
 
-  static Ops ops() { return Ops{&residual, &round, &select}; }
+  static uint32_t fused_grid(const daic_problem* p) {
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->a.sb_count, p->stream_grid));
+  }
+  // one thread per cut target and at least one per partial of k_pull_fused
+  static uint32_t finish_grid(const daic_problem* p) {
+    return (uint32_t)std::max<uint64_t>((p->a.n_groups + 255) / 256, (fused_grid(p) + 255) / 256);
+  }
+
+  static void fuse_prime(daic_problem* p, const daic_run_opts* o, hipStream_t s, Prof* pr) {
+    if constexpr (Tr<ST>::sum) {
+      KArgs a = p->a;
+      threshold(p, o, s, a, ~0ull, pr);
+      launch(pr, "claim", s, [&] {
+        hipLaunchKernelGGL((k_claim<ST, G, RowT, false>), dim3(a.blocks), dim3(256), 0, s, a);
+      });
+      launch(pr, "bin_scan", s, [&] { hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a); });
+      hipLaunchKernelGGL(k_fuse_begin, dim3(1), dim3(1), 0, s, a.ctl);
+    }
+  }
+
+  static void fused_round(daic_problem* p, hipStream_t s, Prof* pr) {
+    if constexpr (Tr<ST>::sum) {
+      const uint32_t nf = fused_grid(p);
+      launch(pr, "pull_fused", s, [&] {
+        hipLaunchKernelGGL((k_pull_fused<ST, G>), dim3(nf), dim3(256), 0, s, p->a);
+      });
+      launch(pr, "fused_finish", s, [&] {
+        hipLaunchKernelGGL((k_fused_finish<ST, G>), dim3(finish_grid(p)), dim3(256), 0, s, p->a, nf);
+      });
+    }
+  }
+
+  static Ops ops() { return Ops{&residual, &round, &select, &fuse_prime, &fused_round}; }
 };
 
 template <int ST, int G>
@@ -201,11 +233,6 @@ bool get_ops(const daic_problem* p, Ops* out) {
 __global__ void k_check_nonneg(const double* w, uint64_t m, uint32_t* bad) {
   for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
     if (!(w[e] >= 0.0)) *bad = 1u;  // negative or NaN
-}
-
-__global__ void k_clear_done(Ctl* ctl) {
-  ctl->done = 0;
-  ctl->stop = 0;
 }
 
 template <typename From, typename To>
@@ -344,6 +371,37 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
     a.sb_e = g->pull.sb_e;
     a.sb_n = g->pull.sb_n;
     a.sb_count = g->pull.sb_count;
+    // fused dense rounds: the second base buffer, the piece tickets and the
+    // per-workgroup partials
+    {
+      void* mu2 = nullptr;
+      DAIC_HIP(hipMalloc(&mu2, std::max<uint64_t>(d.n, 1) * S));
+      p->allocs.push_back(mu2);
+      DAIC_HIP(hipMemsetAsync(mu2, 0, d.n * S, s));
+      a.mu_pi2 = mu2;
+      a.sb_g = g->pull.sb_g;
+      a.g_np = g->pull.g_np;
+      a.g_first = g->pull.g_first;
+      a.n_groups = g->pull.n_groups;
+      auto grab8 = [&](void** q, uint64_t count) -> daic_status {
+        DAIC_HIP(hipMalloc(q, std::max<uint64_t>(count, 1) * 8));
+        p->allocs.push_back(*q);
+        return DAIC_OK;
+      };
+      const uint64_t nf = std::max<uint64_t>(p->stream_grid, 1);
+      const uint64_t nfin = std::max<uint64_t>((g->pull.n_groups + 255) / 256, (nf + 255) / 256);
+      void *sp, *fr, *fa, *fp, *gr, *ga, *gp;
+      if ((rc = grab8(&sp, g->pull.sb_count)) || (rc = grab8(&fr, nf)) || (rc = grab8(&fa, nf)) ||
+          (rc = grab8(&fp, nf)) || (rc = grab8(&gr, nfin)) || (rc = grab8(&ga, nfin)) || (rc = grab8(&gp, nfin)))
+        return rc;
+      a.sb_part = static_cast<double*>(sp);
+      a.fpart_r = static_cast<double*>(fr);
+      a.fpart_a = static_cast<uint64_t*>(fa);
+      a.fpart_p = static_cast<uint64_t*>(fp);
+      a.gpart_r = static_cast<double*>(gr);
+      a.gpart_a = static_cast<uint64_t*>(ga);
+      a.gpart_p = static_cast<uint64_t*>(gp);
+    }
     DAIC_HIP(hipStreamSynchronize(s));
     p->pull_ready = true;
     if (p->exec) {  // captured rounds predate the dense-round kernels
@@ -787,9 +845,40 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
     }
   }
   p->a.last_upd = nullptr;  // captured plain rounds do not track updates
+  // Fused dense rounds (every pending vertex, sum problems, in-edge form):
+  // entered when a dense round is next and at least two rounds remain.
+  const bool sum_state = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
+  const bool fuse = use_graph && o->sched == DAIC_SCHED_ALL && sum_state && p->pull_ready &&
+                    std::getenv("DAIC_NO_FUSE") == nullptr;
+  bool fused = false;
+  if (fuse) {
+    DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    DAIC_HIP(hipStreamSynchronize(s));
+  }
   uint64_t seen_rounds = ~0ull;
   for (; o->sched != DAIC_SCHED_LEARNED;) {
-    if (use_graph) {
+    if (fuse && !fused) {
+      const Ctl& c = *p->h_ctl;
+      if (!c.done && !c.stop && c.pull && c.rounds < max_rounds) {
+        ops.fuse_prime(p, o, s, nullptr);
+        if (!(p->exec_fused && p->fused_K == K && p->fused_stream == s)) {
+          if (p->exec_fused) { (void)hipGraphExecDestroy(p->exec_fused); p->exec_fused = nullptr; }
+          if (p->graph_fused) { (void)hipGraphDestroy(p->graph_fused); p->graph_fused = nullptr; }
+          DAIC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          for (uint32_t r = 0; r < K; ++r) ops.fused_round(p, s, nullptr);
+          hipGraph_t graph;
+          DAIC_HIP(hipStreamEndCapture(s, &graph));
+          p->graph_fused = graph;
+          DAIC_HIP(hipGraphInstantiate(&p->exec_fused, graph, nullptr, nullptr, 0));
+          p->fused_K = K;
+          p->fused_stream = s;
+        }
+        fused = true;
+      }
+    }
+    if (fused) {
+      DAIC_HIP(hipGraphLaunch(p->exec_fused, s));
+    } else if (use_graph) {
       DAIC_HIP(hipGraphLaunch(p->exec, s));
     } else {
       for (uint32_t r = 0; r < K; ++r) ops.round(p, o, s, nullptr, nullptr);
@@ -858,6 +947,26 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
     const double per_in_edge = 4.0 + S + (p->gk == DAIC_G_EDGE_SCALE ? S : 0.0);
     return (double)p->g->dev.m * per_in_edge + (double)P.sb_count * 12.0 + (double)P.n_targets * (2.0 * R + 2.0 * S);
   }
+  if (!std::strcmp(name, "fused_finish")) {
+    // the pieces' partial sums 8 each, the claim of every cut target (as in
+    // pull_fused) and the per-workgroup partials of pull_fused (3 x 8 each)
+    const PullGraph& P = p->g->pull;
+    const double kahan = p->st == ST_F32K ? 8.0 : 0.0;
+    const uint64_t pieces = P.n_pieces;
+    const double nf = (double)std::max<uint64_t>(1, std::min<uint64_t>(P.sb_count, p->stream_grid));
+    return (double)pieces * 8.0 + (double)P.n_groups * (4.0 + 4.0 + 4.0 * S + kahan + 2.0 * R + 4.0 + S) + nf * 24.0;
+  }
+  if (!std::strcmp(name, "pull_fused")) {
+    // the pull as above (descriptor 16 per block, in-edge offsets 2R per
+    // target) and the claim of every vertex: dv read and write 2S, v read
+    // and write 2S (+ Kahan term 8), out-edge offsets 2R, renumbering 4,
+    // base written S
+    const PullGraph& P = p->g->pull;
+    const double per_in_edge = 4.0 + S + (p->gk == DAIC_G_EDGE_SCALE ? S : 0.0);
+    const double kahan = p->st == ST_F32K ? 8.0 : 0.0;
+    return (double)p->g->dev.m * per_in_edge + (double)P.sb_count * 16.0 +
+           n * (2.0 * R + 2.0 * S + 2.0 * S + kahan + 2.0 * R + 4.0 + S);
+  }
   return 0.0;
 }
 
@@ -893,10 +1002,25 @@ daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, 
   };
   Prof prof;
   double total_ms = 0.0;
+  // the same round forms as daic_run, fused dense rounds included
+  const bool sum_state = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
+  const bool fuse = o->sched == DAIC_SCHED_ALL && sum_state && p->pull_ready &&
+                    std::getenv("DAIC_NO_FUSE") == nullptr && std::getenv("DAIC_NO_GRAPH") == nullptr;
+  bool fused = false;
+  DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  DAIC_HIP(hipStreamSynchronize(s));
   for (;;) {
     prof.recs.clear();
     prof.used = 0;
-    ops.round(p, o, s, nullptr, &prof);
+    if (fuse && !fused) {
+      const Ctl& c0 = *p->h_ctl;
+      if (!c0.done && !c0.stop && c0.pull && c0.rounds < max_rounds) {
+        ops.fuse_prime(p, o, s, &prof);
+        fused = true;
+      }
+    }
+    if (fused) ops.fused_round(p, s, &prof);
+    else ops.round(p, o, s, nullptr, &prof);
     DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     DAIC_HIP(hipStreamSynchronize(s));
     const Ctl c = *p->h_ctl;
@@ -913,7 +1037,7 @@ daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, 
       k.alg_bytes += kernel_bytes(p, r.name, c);
       if (!std::strcmp(r.name, "push_small")) k.edges += (double)(c.round_pushed - c.round_pushed_large);
       if (!std::strcmp(r.name, "push_large")) k.edges += (double)c.round_pushed_large;
-      if (!std::strcmp(r.name, "pull_stream")) k.edges += (double)p->g->dev.m;
+      if (!std::strcmp(r.name, "pull_stream") || !std::strcmp(r.name, "pull_fused")) k.edges += (double)p->g->dev.m;
     }
     if (c.done || c.stop) break;
   }
@@ -1063,6 +1187,8 @@ void daic_problem_destroy(daic_problem* p) {
   sweep_release(p);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->exec_fused) (void)hipGraphExecDestroy(p->exec_fused);
+  if (p->graph_fused) (void)hipGraphDestroy(p->graph_fused);
   for (void* q : p->allocs) dfree(q);
   if (p->h_ctl) (void)hipHostFree(p->h_ctl);
   if (p->own_stream) (void)hipStreamDestroy(p->own_stream);

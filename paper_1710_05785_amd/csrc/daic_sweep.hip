@@ -419,7 +419,7 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
     for (uint32_t t = voff[c]; t < voff[c + 1]; ++t)
       if (rt[t + 1] > rt[t]) rv.push_back(t);
     roff[c + 1] = (uint32_t)rv.size();
-    stream_blocks(rt.data(), voff[c], voff[c + 1], sbt, sbe, sbn);
+    stream_blocks(rt.data(), voff[c], voff[c + 1], sbt, sbe, sbn, false);
     sboff[c + 1] = (uint32_t)sbt.size();
     w->max_block_verts = std::max<uint64_t>(w->max_block_verts, voff[c + 1] - voff[c]);
   }

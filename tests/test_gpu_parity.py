@@ -115,6 +115,54 @@ def test_pagerank_rmat_f64_and_kahan(daic, scale, ef, seed):
     assert np.abs(pk.get() - ref).sum() / ref.sum() <= 1e-5
 
 
+@pytest.mark.parametrize("state,gk", [("f32_kahan", "deg"), ("f64", "deg"), ("f32", "edge")])
+def test_fused_dense_rounds_match_plain_rounds(daic, monkeypatch, state, gk):
+    """Dense rounds with every pending vertex run as one fused kernel per
+    round (pull, then the claim work of the next round). They must give the
+    plain rounds' state after the same number of rounds, with the same work
+    counters: to convergence and when stopped by the round limit. RMAT-16
+    with edge factor 16 has targets with more than 2,048 in-edges, which the
+    fused round finishes through per-group tickets."""
+    say("case fused vs plain", state, gk)
+    g = daic_gen.rmat(16, 16, seed=41)
+    indeg = np.bincount(g.col, minlength=g.n)
+    assert indeg.max() > 2048
+    rng = np.random.default_rng(42)
+    w = rng.uniform(0.1, 1.0, g.m).astype(np.float32) if gk == "edge" else None
+    if w is not None:  # column-stochastic-like scaling: sum of weights per source <= 1
+        outdeg = np.diff(g.row_ptr).astype(np.float64)
+        src = np.repeat(np.arange(g.n), np.diff(g.row_ptr).astype(np.int64))
+        w = (w / np.maximum(outdeg[src], 1.0)).astype(np.float32)
+
+    def make():
+        G = daic.Graph(g.row_ptr, g.col, w)
+        P = daic.Problem(G, daic.SUM, daic.G_EDGE_SCALE if w is not None else daic.G_DEG_SCALE,
+                         alpha=0.85, state=state)
+        P.set_init(np.zeros(g.n), np.full(g.n, 0.15))
+        return P
+
+    for max_rounds in (7, 0):
+        kw = dict(eps=1e-9 if state == "f64" else 1e-5, q=1.0, sched="all", rounds_per_check=4,
+                  max_rounds=max_rounds)
+        monkeypatch.setenv("DAIC_NO_FUSE", "1")
+        a = make()
+        ra = a.run(**kw)
+        va, dva = a.get(with_dv=True)
+        monkeypatch.delenv("DAIC_NO_FUSE")
+        b = make()
+        rb = b.run(**kw)
+        vb, dvb = b.get(with_dv=True)
+        assert rb.stats["rounds"] == ra.stats["rounds"], (max_rounds, rb.stats, ra.stats)
+        if max_rounds:
+            assert rb.stats["rounds"] == max_rounds and not rb.converged
+        assert rb.stats["activations"] == ra.stats["activations"]
+        assert rb.stats["pushed_edges"] == ra.stats["pushed_edges"]
+        tol = 1e-12 if state == "f64" else 2e-6
+        assert np.abs(vb - va).sum() <= tol * np.abs(va).sum()
+        assert np.abs(dvb - dva).sum() <= tol * max(np.abs(va).sum(), 1.0)
+        assert abs(rb.stats["final_residual"] - ra.stats["final_residual"]) <= tol * np.abs(va).sum()
+
+
 def sssp_case(g, wseed, source=0):
     w = daic_gen.sssp_weights(g.m, seed=wseed)
     return w, oracle.dijkstra(g, w, source)
