@@ -290,19 +290,12 @@ __global__ __launch_bounds__(256) void k_bpush(BArgs a) {
 // kind 2: final delivery after a stop in the dense phase.
 // Finish states per instance: 0 running, 1 finished with messages in flight,
 // 2 finished and delivered.
-__device__ void retire_item(const BArgs& a, uint32_t g, int kind, int count_round) {
+// Graph g once all its items of the pass are done: sum its items' partials,
+// move its instances' finish states, and take the ticket of the graphs.
+__device__ void retire_graph(const BArgs& a, uint32_t g, int kind, int count_round) {
   __shared__ uint32_t s_flag;
   __shared__ double s_r[4][kR];
   BCtl* ctl = a.ctl;
-  __threadfence();  // this block's partials are visible before its ticket
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t nit = a.g_first_item[g + 1] - a.g_first_item[g];
-    s_flag = atomicAdd(&a.g_ticket[g], 1u) == nit - 1;
-  }
-  __syncthreads();
-  if (!s_flag) return;
-  __threadfence();
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
   const uint32_t k0 = a.g_first_item[g], k1 = a.g_first_item[g + 1];
   double r = 0.0;
@@ -387,6 +380,38 @@ __device__ void retire_item(const BArgs& a, uint32_t g, int kind, int count_roun
       ctl->sw_started = 0;
     }
   }
+}
+
+__device__ void retire_item(const BArgs& a, uint32_t g, int kind, int count_round) {
+  __shared__ uint32_t s_last;
+  __threadfence();  // this block's partials are visible before its ticket
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t nit = a.g_first_item[g + 1] - a.g_first_item[g];
+    s_last = atomicAdd(&a.g_ticket[g], 1u) == nit - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  retire_graph(a, g, kind, count_round);
+}
+
+// Retirement of the fused dense pass, after it (its kernel only stores
+// partials: a fence per item in a kernel that keeps dirtying L2 would write
+// the L2 back each time): one block per graph.
+__global__ __launch_bounds__(256) void k_bretire_dense(BArgs a, int final_pass) {
+  BCtl* ctl = a.ctl;
+  if (!final_pass && (bhalted(ctl) || ctl->mode != 2)) return;  // as k_bfused
+  retire_graph(a, blockIdx.x, final_pass ? 2 : 1, 1);
+}
+
+// Retirement of a sweep: every graph's items have all run once the last
+// block of the sweep has (graphs without vertices in the last blocks
+// included), so after that block's pass one block per graph retires it.
+__global__ __launch_bounds__(256) void k_bretire_sweep(BArgs a) {
+  BCtl* ctl = a.ctl;
+  if (bhalted(ctl) || ctl->mode != 3 || ctl->sw_c != a.sw_P - 1) return;  // as k_bfused, at the sweep's end
+  retire_graph(a, blockIdx.x, 1, 0);
 }
 
 // Residual of a sparse round (or of the state at the start of a run): FP64
@@ -739,7 +764,7 @@ __global__ __launch_bounds__(256) void k_bfused(BArgs a, int final_pass) {
     a.part_fa[it] = act;
     a.part_fm[it] = msg;
   }
-  retire_item(a, g, final_pass ? 2 : 1, SWEEP ? 0 : 1);
+  // retired after the kernel: k_bretire_dense, k_bretire_sweep
 }
 
 // Sweep rounds stopped by the round limit: deliver the messages still in
@@ -1048,6 +1073,7 @@ static void launch_dense_w(daic_batch* b, hipStream_t s, int final_pass) {
     hipLaunchKernelGGL((k_bfused<LPV, true, WGT, false>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
   else
     hipLaunchKernelGGL((k_bfused<LPV, false, WGT, false>), dim3(b->a.n_fused_blocks), dim3(256), 0, s, b->a, final_pass);
+  hipLaunchKernelGGL(k_bretire_dense, dim3(b->a.G), dim3(256), 0, s, b->a, final_pass);
 }
 
 // One sweep round (block and sweep from the control block): step, hub sums
@@ -1061,6 +1087,7 @@ static void launch_sweep_w(daic_batch* b, hipStream_t s) {
     hipLaunchKernelGGL((k_bfused<LPV, true, WGT, true>), dim3(b->sw_grid), dim3(256), 0, s, as, 0);
   else
     hipLaunchKernelGGL((k_bfused<LPV, false, WGT, true>), dim3(b->sw_grid), dim3(256), 0, s, as, 0);
+  hipLaunchKernelGGL(k_bretire_sweep, dim3(as.G), dim3(256), 0, s, as);
 }
 
 static void enqueue_sweep(daic_batch* b, hipStream_t s) {
