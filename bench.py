@@ -185,6 +185,28 @@ def batched_form(daic, torch, eps, rounds_per_check):
     }
 
 
+def sweep_form(daic, torch, g, d, eps, rounds_per_check, P=None, v0=None, dv1=None):
+    """The sweep schedule on the plain workload: 8 id blocks in turn, each
+    pulling the newest messages of its in-neighbours; warmed up, then timed."""
+    blocks = 8
+    if P is None:
+        P = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=d, state="f32_kahan")
+        v0 = torch.zeros(g.n, dtype=torch.float32, device="cuda")
+        dv1 = torch.full((g.n,), 1.0 - d, dtype=torch.float32, device="cuda")
+    kw = dict(eps=eps, q=1.0 / blocks, sched="sweep", rounds_per_check=rounds_per_check)
+    P.set_init_device(v0, dv1)
+    P.run(**kw)
+    P.set_init_device(v0, dv1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rs = P.run(**kw)
+    torch.cuda.synchronize()
+    ws = time.perf_counter() - t
+    return {"time_to_residual_ms": ws * 1e3, "rounds": rs.stats["rounds"], "sweeps": rs.stats["rounds"] / blocks,
+            "pushed_edges": rs.stats["pushed_edges"], "gteps": rs.stats["pushed_edges"] / ws / 1e9,
+            "converged": rs.converged, "final_residual": rs.stats["final_residual"], "_v": P.get()}
+
+
 def learned_form(daic, torch, g24, eps, rounds_per_check):
     """The learned-scheduler form: the network is trained on the device on
     traces of exact top-10% runs of PageRank (d = 0.8, FP32 + Kahan) and SSSP
@@ -394,7 +416,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP64 and sampled forms")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--form", choices=("learned", "batched"),
+    ap.add_argument("--form", choices=("learned", "batched", "sweep"),
                     help="run only this form and print it (for profiling its kernels)")
     ap.add_argument("--ablation", action="store_true",
                     help="only run the sync / round-robin / priority comparison")
@@ -431,6 +453,11 @@ def main():
     if args.form == "learned":
         print(json.dumps({"learned_sched": learned_form(daic, torch, g, args.eps, args.rounds_per_check)}),
               flush=True)
+        return
+    if args.form == "sweep":
+        sw = sweep_form(daic, torch, g, d, args.eps, args.rounds_per_check)
+        sw.pop("_v")
+        print(json.dumps({"sweep_8_blocks": sw}), flush=True)
         return
     G = daic.Graph(g.row_ptr, g.col)
     P = daic.Problem(G, daic.SUM, daic.G_DEG_SCALE, alpha=d, state="f32_kahan")
@@ -551,22 +578,11 @@ def main():
                                       "converged": rq.converged}
         # sweep scheduling: round-robin over 8 id blocks, each block pulling the
         # newest messages of its in-neighbours (asynchronous order)
-        blocks = 8
-        P.set_init_device(v0, dv1)
-        P.run(eps=args.eps, q=1.0 / blocks, sched="sweep", rounds_per_check=args.rounds_per_check)
-        P.set_init_device(v0, dv1)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        rs = P.run(eps=args.eps, q=1.0 / blocks, sched="sweep", rounds_per_check=args.rounds_per_check)
-        torch.cuda.synchronize()
-        ws = time.perf_counter() - t
-        vs = P.get()
-        forms[f"sweep_{blocks}_blocks"] = {
-            "time_to_residual_ms": ws * 1e3, "rounds": rs.stats["rounds"], "sweeps": rs.stats["rounds"] / blocks,
-            "pushed_edges": rs.stats["pushed_edges"], "gteps": rs.stats["pushed_edges"] / ws / 1e9,
-            "converged": rs.converged, "final_residual": rs.stats["final_residual"],
-            "rel_l1_vs_all_pending": float(np.abs(vs - v32).sum() / np.abs(v32).sum()),
-            "time_ratio_vs_all_pending": ws * 1e3 / out["time_to_residual_ms"]}
+        sw = sweep_form(daic, torch, g, d, args.eps, args.rounds_per_check, P=P, v0=v0, dv1=dv1)
+        vs = sw.pop("_v")
+        sw["rel_l1_vs_all_pending"] = float(np.abs(vs - v32).sum() / np.abs(v32).sum())
+        sw["time_ratio_vs_all_pending"] = sw["time_to_residual_ms"] / out["time_to_residual_ms"]
+        forms["sweep_8_blocks"] = sw
         log("learned-scheduler form ...")
         forms["learned_sched"] = learned_form(daic, torch, g, args.eps, args.rounds_per_check)
         log("batched form ...")
