@@ -282,14 +282,26 @@ __global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round, uint
   const S* dv = static_cast<const S*>(a.dv);
   double r = 0.0;
   uint64_t cnt = 0;
-  for (uint64_t j = lo + threadIdx.x; j < hi; j += 256) {
-    S dj = dv[j];
-    if constexpr (Tr<ST>::sum) {
-      double x = fabs((double)dj);
-      r += x;
-      cnt += x > 0.0;
-    } else {
-      cnt += prio_key<ST>(v[j], dj) != 0;
+  // four vertices per step, their loads in flight together (a thread walks
+  // many vertices; one load at a time would leave the kernel latency-bound)
+  for (uint64_t j0 = lo + threadIdx.x; j0 < hi; j0 += 1024) {
+    S dj[4], vj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t j = min(j0 + 256 * u, hi - 1);
+      dj[u] = dv[j];
+      if constexpr (!Tr<ST>::sum) vj[u] = v[j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (j0 + 256 * u >= hi) break;
+      if constexpr (Tr<ST>::sum) {
+        double x = fabs((double)dj[u]);
+        r += x;
+        cnt += x > 0.0;
+      } else {
+        cnt += prio_key<ST>(vj[u], dj[u]) != 0;
+      }
     }
   }
   r = block_sum256(r);
@@ -307,9 +319,21 @@ __global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round, uint
   __threadfence();
   double rr = 0.0;
   uint64_t nn = 0;
-  for (uint32_t i = threadIdx.x; i < a.blocks; i += 256) {
-    rr += __hip_atomic_load(&a.part_r[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    nn += __hip_atomic_load(&a.part_n[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t i0 = threadIdx.x; i0 < a.blocks; i0 += 1024) {
+    double pr[4];
+    uint64_t pn[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t i = min(i0 + 256 * u, a.blocks - 1);
+      pr[u] = __hip_atomic_load(&a.part_r[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      pn[u] = __hip_atomic_load(&a.part_n[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + 256 * u >= a.blocks) break;
+      rr += pr[u];
+      nn += pn[u];
+    }
   }
   rr = block_sum256(rr);
   nn = block_sum256(nn);

@@ -212,10 +212,24 @@ __global__ __launch_bounds__(256) void k_sweep_residual(SweepArgs a) {
   const S* mu = static_cast<const S*>(a.mu2) + (k & 1) * a.n;
   double r = 0.0;
   uint64_t cnt = 0;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.n; s += (uint64_t)gridDim.x * blockDim.x) {
-    const double m = fabs((double)mu[s]);
-    r += m * a.coef_le[s];
-    cnt += m > 0.0 ? 1 : 0;
+  // four positions per step, their loads in flight together
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s0 < a.n; s0 += 4 * stride) {
+    S mv[4];
+    double cf[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t s = min(s0 + stride * u, a.n - 1);
+      mv[u] = mu[s];
+      cf[u] = a.coef_le[s];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (s0 + stride * u >= a.n) break;
+      const double m = fabs((double)mv[u]);
+      r += m * cf[u];
+      cnt += m > 0.0 ? 1 : 0;
+    }
   }
   r = block_sum256(r);
   cnt = block_sum256(cnt);
