@@ -163,6 +163,36 @@ def test_fused_dense_rounds_match_plain_rounds(daic, monkeypatch, state, gk):
         assert abs(rb.stats["final_residual"] - ra.stats["final_residual"]) <= tol * np.abs(va).sum()
 
 
+def test_profile_matches_run_and_accounts_the_pull(daic, monkeypatch):
+    """daic_profile (the source of the benchmark's roofline) runs the same
+    rounds as daic_run, to the same state, and reports every dense round's
+    pull over all m in-edges: the fused kernel under all-pending scheduling,
+    the streamed pull with the claim and residual kernels otherwise."""
+    say("case profile accounting")
+    g = daic_gen.rmat(14, 8, seed=51)
+    for fuse in (True, False):
+        if fuse:
+            monkeypatch.delenv("DAIC_NO_FUSE", raising=False)
+        else:
+            monkeypatch.setenv("DAIC_NO_FUSE", "1")
+        a = pr_problem(daic, g, 0.85, state="f32_kahan")
+        ra = a.run(eps=1e-6, q=1.0, sched="all")
+        b = pr_problem(daic, g, 0.85, state="f32_kahan")
+        rb, ks = b.profile(eps=1e-6, q=1.0, sched="all")
+        assert ra.converged and rb.converged
+        assert rb.stats["rounds"] == ra.stats["rounds"]
+        assert rb.stats["pushed_edges"] == ra.stats["pushed_edges"]
+        va, vb = a.get(), b.get()
+        assert np.abs(va - vb).sum() <= 2e-6 * np.abs(va).sum()
+        names = {k["name"]: k for k in ks}
+        pull = names["pull_fused" if fuse else "pull_stream"]
+        assert pull["launches"] == rb.stats["rounds"]
+        assert pull["edges"] == pull["launches"] * g.m
+        assert pull["alg_bytes"] >= pull["edges"] * 8 and pull["total_ms"] > 0
+        if not fuse:
+            assert {"claim", "residual"} <= set(names)
+
+
 def sssp_case(g, wseed, source=0):
     w = daic_gen.sssp_weights(g.m, seed=wseed)
     return w, oracle.dijkstra(g, w, source)
