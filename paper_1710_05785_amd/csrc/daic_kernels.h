@@ -611,7 +611,79 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
   const bool pull = !DRY && ctl->pull != 0;
   uint64_t ties_seen = 0, n_small = 0, n_large = 0, act = 0, pushed = 0, pushed_large = 0;
 
-  for (uint64_t base = lo; base < hi; base += 256) {
+  // Dense rounds without tie counting (sum problems): no bins and no block
+  // scans, so a thread takes four vertices per step with every load of the
+  // four in flight together (the general loop below waits on each vertex).
+  bool fast = false;
+  if constexpr (!DRY && Tr<ST>::sum) {
+    fast = pull && mode != 2;
+    if (fast) {
+      S* vw = static_cast<S*>(a.v);
+      S* dw = static_cast<S*>(a.dv);
+      S* mu_pi = static_cast<S*>(a.mu_pi);
+      for (uint64_t base = lo; base < hi; base += 1024) {
+        S vj[4], dj[4];
+        float sc[4], cj[4];
+        uint64_t r0[4], r1[4];
+        uint32_t pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint64_t j = min(base + threadIdx.x + 256 * u, hi - 1);
+          vj[u] = v[j];
+          dj[u] = dv[j];
+          sc[u] = a.score ? a.score[j] : 1.f;
+          cj[u] = Tr<ST>::kahan ? a.c[j] : 0.f;
+          r0[u] = row_at<RowT>(a.row, j);
+          r1[u] = row_at<RowT>(a.row, j + 1);
+          pj[u] = a.perm[j];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint64_t j = base + threadIdx.x + 256 * u;
+          if (j >= hi) break;
+          Key key = prio_key<ST>(vj[u], dj[u]);
+          if (a.score != nullptr && key != 0) {  // as sel_key
+            const uint32_t bits = __float_as_uint(prio_value<ST>(vj[u], dj[u]) * sc[u]);
+            key = (Key)(bits == 0 ? 1u : bits);
+          }
+          bool sel = false;
+          if (key != 0) {
+            if (mode == 0) sel = true;
+            else if (mode == 1) sel = key >= tau;
+            else sel = j / a.rr_chunk == tau;
+          }
+          const uint64_t deg = r1[u] - r0[u];
+          bool send = false;
+          S mu{};
+          if (sel) {  // claim_fold with the operands read above
+            const S delta = dj[u];
+            dw[j] = (S)0;
+            if constexpr (Tr<ST>::kahan) {
+#pragma clang fp contract(off)
+              const float y = delta - cj[u];
+              const float t = vj[u] + y;
+              a.c[j] = (t - vj[u]) - y;
+              vw[j] = t;
+            } else {
+              vw[j] = vj[u] + delta;
+            }
+            double coef;
+            if constexpr (G == DAIC_G_DEG_SCALE) coef = a.alpha / (double)deg;
+            else coef = a.alpha_pv ? (double)static_cast<const S*>(a.alpha_pv)[j] : a.alpha;
+            mu = (S)(coef * (double)delta);
+            send = delta != (S)0 && deg > 0;
+            if (a.last_upd) a.last_upd[j] = (uint32_t)ctl->rounds;
+          }
+          if (pj[u] < a.n_src) mu_pi[pj[u]] = send ? mu : (S)0;  // no reader otherwise
+          act += sel ? 1 : 0;
+          pushed += send ? deg : 0;
+          pushed_large += (send && deg > kSmallMaxDeg) ? deg : 0;
+        }
+      }
+    }
+  }
+
+  for (uint64_t base = lo; base < hi && !fast; base += 256) {
     const uint64_t j = base + threadIdx.x;
     const bool in = j < hi;
     S vj{}, dj{};
