@@ -271,10 +271,12 @@ __device__ __forceinline__ void push_edge(const KArgs& a, uint64_t e, typename T
 // a dense round (pull over in-edges) when at least pull_min vertices are
 // expected to update (min(pending, k_sel)); k_sel = 0 disables dense rounds.
 template <int ST>
-__global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round, uint64_t k_sel, uint64_t pull_min) {
+__global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round, uint64_t k_sel, uint64_t pull_min,
+                                                  int skip_dense = 0) {
   using S = typename Tr<ST>::S;
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
+  if (skip_dense && ctl->last_pull) return;  // a dense round's residual comes from k_pull_finish
   const uint32_t b = blockIdx.x;
   const uint64_t lo = (uint64_t)b * a.per_block;
   const uint64_t hi = min(a.n, lo + a.per_block);
@@ -976,36 +978,134 @@ __device__ __forceinline__ void stream_block(const uint32_t* rowT, const uint32_
 }
 
 // Dense round by streamed blocks (Eq. sync over the in-edges): message of an
-// in-edge = the source's base (times the edge weight for EDGE_SCALE).
+// in-edge = the source's base (times the edge weight for EDGE_SCALE). Every
+// vertex is in one edge block, so each workgroup also stores the residual
+// partials (sum of |dv| and pending count) of the vertices it finished;
+// cut targets and the round's totals are left to k_pull_finish.
 template <int ST, int G>
 __global__ __launch_bounds__(256) void k_pull_stream(KArgs a) {
   using S = typename Tr<ST>::S;
   if constexpr (Tr<ST>::sum) {
+    constexpr uint32_t RDV = kStreamRows / 256;
     Ctl* ctl = a.ctl;
     uint64_t b = blockIdx.x;
-    if (b >= a.sb_count) return;
+    if (b >= a.sb_count) {  // only with an empty block table (grid of one)
+      if (threadIdx.x == 0) {
+        a.fpart_r[b] = 0.0;
+        a.fpart_a[b] = 0;
+      }
+      return;
+    }
     // the first block's descriptors are read together with the control block
-    uint32_t t0 = a.sb_t[b], nr = a.sb_n[b], e0 = a.sb_e[b], e1 = a.sb_e[b + 1];
+    uint32_t t0 = a.sb_t[b], nr = a.sb_n[b], e0 = a.sb_e[b], e1 = a.sb_e[b + 1], grp = a.sb_g[b];
     if (ctl_halted(ctl) || !ctl->pull) return;
     using V = typename std::conditional<G == DAIC_G_EDGE_SCALE, double, S>::type;
     __shared__ V vals[kStreamEdges];
     __shared__ double acc[kStreamRows];
     __shared__ uint32_t off[kStreamRows + 1];
+    const uint32_t tid = threadIdx.x;
     const S* mu = static_cast<const S*>(a.mu_pi);
     const S* wT = static_cast<const S*>(a.wT);
+    S* dv = static_cast<S*>(a.dv);
     auto msg = [&](uint32_t src, uint32_t p) -> V {
       V m = (V)mu[src];
       if constexpr (G == DAIC_G_EDGE_SCALE) m *= (V)wT[p];
       return m;
     };
+    double r_part = 0.0;
+    uint64_t pend = 0;
     for (;;) {
-      stream_block<S, V>(a.rowT, a.srcT, static_cast<S*>(a.dv), t0, nr, e0, e1, vals, acc, off, msg);
+      S dvp[RDV];
+#pragma unroll
+      for (uint32_t q = 0; q < RDV; ++q) dvp[q] = dv[t0 + min(tid + 256 * q, nr - 1)];
+      stream_sums<V>(a.rowT, a.srcT, t0, nr, e0, e1, vals, acc, off, msg);
+      if (grp == 0xFFFFFFFFu) {  // whole targets
+#pragma unroll
+        for (uint32_t q = 0; q < RDV; ++q) {
+          const uint32_t i = tid + 256 * q;
+          if (i >= nr) continue;
+          S d = dvp[q];
+          if (off[i + 1] != off[i]) {  // in-edges
+            d = (S)((double)dvp[q] + acc[i]);
+            dv[t0 + i] = d;
+          }
+          r_part += fabs((double)d);
+          pend += d != (S)0 ? 1 : 0;
+        }
+      } else if (tid == 0) {  // a piece of a cut target
+        unsafeAtomicAdd(&dv[t0], (S)acc[0]);
+      }
+      __syncthreads();
       b += gridDim.x;
       if (b >= a.sb_count) break;
       t0 = a.sb_t[b];
       nr = a.sb_n[b];
       e0 = a.sb_e[b];
       e1 = a.sb_e[b + 1];
+      grp = a.sb_g[b];
+    }
+    r_part = block_sum256(r_part);
+    pend = block_sum256(pend);
+    if (tid == 0) {
+      a.fpart_r[blockIdx.x] = r_part;
+      a.fpart_a[blockIdx.x] = pend;
+    }
+  }
+}
+
+// After a dense round's k_pull_stream (nf workgroups): the residual of the
+// round's end state as k_residual computes it (sum of |dv| in FP64, pending
+// count, round count, stop rule, direction of the next round), from the
+// pull's partials and the cut targets' final dv; the last block to finish
+// adds the per-block partials in a fixed order.
+template <int ST>
+__global__ __launch_bounds__(256) void k_pull_finish(KArgs a, uint32_t nf, uint64_t k_sel, uint64_t pull_min) {
+  using S = typename Tr<ST>::S;
+  if constexpr (Tr<ST>::sum) {
+    Ctl* ctl = a.ctl;
+    if (ctl_halted(ctl) || !ctl->last_pull) return;
+    __shared__ uint32_t s_last;
+    const uint32_t tid = threadIdx.x;
+    double r = 0.0;
+    uint64_t cnt = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + tid; i < nf; i += (uint64_t)gridDim.x * 256) {
+      r += a.fpart_r[i];  // written by the previous kernel
+      cnt += a.fpart_a[i];
+    }
+    const uint64_t g = (uint64_t)blockIdx.x * 256 + tid;
+    if (g < a.n_groups) {
+      const double x = fabs((double)static_cast<const S*>(a.dv)[a.sb_t[a.g_first[g]]]);
+      r += x;
+      cnt += x > 0.0 ? 1 : 0;
+    }
+    r = block_sum256(r);
+    cnt = block_sum256(cnt);
+    if (tid == 0) {
+      a.gpart_r[blockIdx.x] = r;
+      a.gpart_a[blockIdx.x] = cnt;
+      __threadfence();
+      s_last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double rr = 0.0;
+    uint64_t nn = 0;
+    for (uint32_t i = tid; i < gridDim.x; i += 256) {
+      rr += __hip_atomic_load(&a.gpart_r[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      nn += __hip_atomic_load(&a.gpart_a[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    rr = block_sum256(rr);
+    nn = block_sum256(nn);
+    if (tid == 0) {
+      ctl->r = rr;
+      ctl->pending = nn;
+      ctl->rounds += 1;
+      const bool done = rr <= ctl->eps || nn == 0;
+      ctl->done = done ? 1u : 0u;
+      ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
+      ctl->pull = (k_sel != 0 && (nn < k_sel ? nn : k_sel) >= pull_min) ? 1u : 0u;
+      ctl->ticket = 0;
     }
   }
 }

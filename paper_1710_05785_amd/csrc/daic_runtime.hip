@@ -141,13 +141,17 @@ struct Impl {
       hipLaunchKernelGGL((k_push_large<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
     });
     if (p->pull_ready) {
+      const uint32_t nf = fused_grid(p);
       launch(pr, "pull_stream", s, [&] {
-        uint32_t gs = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(a.sb_count, p->stream_grid));
-        hipLaunchKernelGGL((k_pull_stream<ST, G>), dim3(gs), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_pull_stream<ST, G>), dim3(nf), dim3(256), 0, s, a);
+      });
+      launch(pr, "pull_finish", s, [&] {
+        hipLaunchKernelGGL(k_pull_finish<ST>, dim3(finish_grid(p)), dim3(256), 0, s, a, nf, p->k_sel, p->pull_min);
       });
     }
     launch(pr, "residual", s, [&] {
-      hipLaunchKernelGGL(k_residual<ST>, dim3(a.blocks), dim3(256), 0, s, a, 1, p->k_sel, p->pull_min);
+      hipLaunchKernelGGL(k_residual<ST>, dim3(a.blocks), dim3(256), 0, s, a, 1, p->k_sel, p->pull_min,
+                         p->pull_ready ? 1 : 0);
     });
   }
 
@@ -941,11 +945,21 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
   }
   if (!std::strcmp(name, "residual")) return n * S;
   if (!std::strcmp(name, "pull_stream")) {
-    // per in-edge: source 4 + message base S (+ weight S); per edge block 12;
-    // per target with in-edges: offsets 2R + dv read and write 2S
+    // per in-edge: source 4 + message base S (+ weight S); per edge block 16;
+    // dv read of every vertex S; per target with in-edges: offsets 2R + dv
+    // written S; per workgroup the two residual partials 16
     const PullGraph& P = p->g->pull;
     const double per_in_edge = 4.0 + S + (p->gk == DAIC_G_EDGE_SCALE ? S : 0.0);
-    return (double)p->g->dev.m * per_in_edge + (double)P.sb_count * 12.0 + (double)P.n_targets * (2.0 * R + 2.0 * S);
+    const double nf = (double)std::max<uint64_t>(1, std::min<uint64_t>(P.sb_count, p->stream_grid));
+    return (double)p->g->dev.m * per_in_edge + (double)P.sb_count * 16.0 + n * S +
+           (double)P.n_targets * (2.0 * R + S) + nf * 16.0;
+  }
+  if (!std::strcmp(name, "pull_finish")) {
+    // the partials of pull_stream 16 each and the final dv of every cut
+    // target (block number 4, target 4, dv S)
+    const PullGraph& P = p->g->pull;
+    const double nf = (double)std::max<uint64_t>(1, std::min<uint64_t>(P.sb_count, p->stream_grid));
+    return nf * 16.0 + (double)P.n_groups * (8.0 + S);
   }
   if (!std::strcmp(name, "fused_finish")) {
     // the pieces' partial sums 8 each, the claim of every cut target (as in
@@ -1028,9 +1042,11 @@ daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, 
       float ms = 0.f;
       DAIC_HIP(hipEventElapsedTime(&ms, r.a, r.b));
       total_ms += ms;
-      // kernels of the other direction return at once: not counted as launches
+      // kernels of the other direction return at once: not counted as
+      // launches (after a dense round, k_pull_finish takes the residual's part)
       const bool is_push = !std::strncmp(r.name, "push_", 5), is_pull = !std::strncmp(r.name, "pull_", 5);
-      if ((is_push && c.last_pull) || (is_pull && !c.last_pull)) continue;
+      const bool is_res = !std::strcmp(r.name, "residual");
+      if ((is_push && c.last_pull) || (is_pull && !c.last_pull) || (is_res && c.last_pull)) continue;
       daic_kernel_time& k = slot(r.name);
       k.launches += 1;
       k.total_ms += ms;

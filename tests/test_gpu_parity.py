@@ -167,7 +167,8 @@ def test_profile_matches_run_and_accounts_the_pull(daic, monkeypatch):
     """daic_profile (the source of the benchmark's roofline) runs the same
     rounds as daic_run, to the same state, and reports every dense round's
     pull over all m in-edges: the fused kernel under all-pending scheduling,
-    the streamed pull with the claim and residual kernels otherwise."""
+    the streamed pull with the claim and the pull's finishing kernel (which
+    takes the residual's place after a dense round) otherwise."""
     say("case profile accounting")
     g = daic_gen.rmat(14, 8, seed=51)
     for fuse in (True, False):
@@ -190,7 +191,10 @@ def test_profile_matches_run_and_accounts_the_pull(daic, monkeypatch):
         assert pull["edges"] == pull["launches"] * g.m
         assert pull["alg_bytes"] >= pull["edges"] * 8 and pull["total_ms"] > 0
         if not fuse:
-            assert {"claim", "residual"} <= set(names)
+            assert {"claim", "pull_finish"} <= set(names)
+            assert names["pull_finish"]["launches"] == pull["launches"]
+            # a residual launch is counted only after a sparse round
+            assert names.get("residual", {"launches": 0})["launches"] == rb.stats["rounds"] - pull["launches"]
 
 
 def sssp_case(g, wseed, source=0):
