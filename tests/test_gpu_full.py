@@ -8,6 +8,11 @@ benchmark runs them (captured groups of rounds, the default launch shapes).
   the same problem within its residual bound r / (1 - d) of that result, and
   its delta mass conserved (sum dv + sum (1 - s_j) v_j = sum dv1, s_j = d for
   a vertex with out-edges, 0 otherwise).
+* The learned scheduler as the benchmark trains it (traces of exact top-10 %
+  runs of PageRank and SSSP on 16 RMAT-20 graphs, 8 epochs on the device),
+  then run with learned selection (q = 0.1) on RMAT-24: PageRank against the
+  same FP64 oracle result (relative L1 <= 1e-5), SSSP (weights U{1..255},
+  seed 7, source 0) bit-exact against the oracle's Dijkstra.
 * Batched personalized PageRank, 64 RMAT graphs of scale U{12..20} with edge
   factor 8, 64 right-hand sides each (4,096 instances, d = 0.85, FP32 + Kahan,
   residual 1e-6 per instance): one instance per graph, each against the
@@ -38,11 +43,29 @@ def daic():
     return d
 
 
+@pytest.fixture(scope="module")
+def g24():
+    say("generate rmat24")
+    return daic_gen.rmat(24, 16, seed=4)
+
+
+@pytest.fixture(scope="module")
+def pr24_ref(g24):
+    """The oracle's FP64 iteration of PageRank d = 0.8 on RMAT-24 to a sweep
+    difference of 1e-9, and its distance bound to the fixed point."""
+    say("oracle pagerank rmat24")
+    d = 0.8
+    _, dv1 = oracle.pagerank_init(g24.n, d)
+    ref, _, last = oracle.jacobi_sum(g24, oracle.G_DEG_SCALE, d, dv1, eps=1e-9)
+    assert last <= 1e-9
+    return ref, last * d / (1 - d)
+
+
 @pytest.mark.timeout(900)
-def test_pagerank_rmat24_full_config(daic):
-    say("case pagerank rmat24 full: generate")
+def test_pagerank_rmat24_full_config(daic, g24, pr24_ref):
+    say("case pagerank rmat24 full")
     d, eps = 0.8, 1e-6
-    g = daic_gen.rmat(24, 16, seed=4)
+    g = g24
     G = daic.Graph(g.row_ptr, g.col)
     v0, dv1 = oracle.pagerank_init(g.n, d)
     results = {}
@@ -55,11 +78,9 @@ def test_pagerank_rmat24_full_config(daic):
             assert res.converged and res.stats["final_residual"] <= eps
         results[state] = (p.get(with_dv=True), res.stats["final_residual"])
         del p
-    say("case pagerank rmat24 full: oracle")
-    ref, sweeps, last = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1, eps=1e-9)
-    assert last <= 1e-9
-    # the oracle's own distance to the fixed point: at most last * d / (1 - d)
-    ref_err = last * d / (1 - d)
+    # ref_err: the oracle's own distance to the fixed point (last sweep
+    # difference x d / (1 - d))
+    ref, ref_err = pr24_ref
     (v32, _), _ = results["f32_kahan"]
     rel = np.abs(v32.astype(np.float64) - ref).sum() / np.abs(ref).sum()
     say("  FP32 + Kahan relative L1", rel)
@@ -72,6 +93,51 @@ def test_pagerank_rmat24_full_config(daic):
     s = np.where(np.diff(g.row_ptr) > 0, d, 0.0)
     lhs = dv64.sum() + ((1 - s) * v64).sum()
     assert abs(lhs - dv1.sum()) <= 1e-11 * dv1.sum(), (lhs, dv1.sum())
+
+
+@pytest.mark.timeout(900)
+def test_learned_scheduler_full_config(daic, g24, pr24_ref):
+    d, q, eps = 0.8, 0.1, 1e-6
+    say("case learned full: traces")
+    pr_tr, ss_tr = [], []
+    for seed in range(100, 116):
+        g = daic_gen.rmat(20, 16, seed=seed)
+        p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=d,
+                         state="f32_kahan")
+        p.set_init(np.zeros(g.n), np.full(g.n, 1 - d))
+        pr_tr.append(daic.Trace.record(p, samples_per_round=4096, horizon=4, q=q, eps=eps))
+        w = daic_gen.sssp_weights(g.m, seed=seed + 1000)
+        ps = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+        ps.set_init(*oracle.sssp_init(g.n, 0))
+        ss_tr.append(daic.Trace.record(ps, samples_per_round=4096, horizon=4, q=q))
+    say("case learned full: training")
+    models = {}
+    for name, trs in (("pagerank", pr_tr), ("sssp", ss_tr)):
+        m = daic.SchedModel(seed=8)
+        daic.sched_train(trs, m, epochs=8, batch=65536, lr=3e-3, seed=8)
+        models[name] = m
+    say("case learned full: pagerank rmat24")
+    g = g24
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=d, state="f32_kahan")
+    for _ in range(2):  # the second run replays the captured rounds
+        p.set_init(np.zeros(g.n), np.full(g.n, 1 - d))
+        res = p.run(eps=eps, q=q, sched="learned", model=models["pagerank"])
+        assert res.converged and res.stats["final_residual"] <= eps
+    ref, _ = pr24_ref
+    rel = np.abs(p.get().astype(np.float64) - ref).sum() / np.abs(ref).sum()
+    say("  learned PageRank relative L1", rel)
+    assert rel <= 1e-5, rel
+    del p
+    say("case learned full: sssp rmat24")
+    w = daic_gen.sssp_weights(g.m, seed=7)
+    ps = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+    for _ in range(2):
+        ps.set_init(*oracle.sssp_init(g.n, 0))
+        res = ps.run(q=q, sched="learned", model=models["sssp"])
+        assert res.converged
+    got = ps.get()
+    say("case learned full: oracle dijkstra")
+    np.testing.assert_array_equal(got, oracle.dijkstra(g, w, 0))
 
 
 @pytest.mark.timeout(900)
