@@ -63,7 +63,6 @@ struct Ctl {
   uint32_t pull;         // the next round runs as a pull over in-edges (dense round)
   uint32_t last_pull;    // the round just run was a dense round
   uint64_t fuse_base;    // fused dense rounds: round count when buffer A was last published
-  uint32_t hist[256];    // radix select histogram
 };
 
 // Compile-time identity of a (op, g, state, row) instantiation.

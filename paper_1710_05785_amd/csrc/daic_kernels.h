@@ -59,6 +59,7 @@ struct KArgs {
   uint64_t* blk_push;
   uint64_t* blk_push_large;
   uint32_t* blk_ties;       // exact top-k: keys equal to tau per block
+  uint32_t* rhist;          // exact top-k: radix histogram (kRadixBins counters)
   uint64_t* off_ties;       // exclusive prefix of blk_ties
   double* part_r;           // residual partials per block
   uint64_t* part_n;         // pending-count partials per block
@@ -421,7 +422,6 @@ static __global__ void k_init_ctl(Ctl* ctl, double eps, uint64_t max_rounds) {
   ctl->pull = 0;
   ctl->last_pull = 0;
   ctl->fuse_base = 0;
-  for (int i = 0; i < 256; ++i) ctl->hist[i] = 0;
 }
 
 // The stop flags are recomputed by the next residual.
@@ -444,11 +444,31 @@ static __global__ void k_select_rr(Ctl* ctl, uint64_t nblocks) {
 }
 
 // ---------------------------------------------------------------------------
-// A2 (exact): radix select of the k-th largest key, 8 bits per pass, most
-// significant digit first. Ties at the k-th key go to the smaller ids.
+// A2 (exact): radix select of the k-th largest key, kRadixBits bits per pass,
+// most significant digit first. Ties at the k-th key go to the smaller ids;
+// when every key equal to the k-th one fits in the k, the round selects
+// key >= tau and needs no tie ranks.
 // ---------------------------------------------------------------------------
-static __global__ void k_topk_init(Ctl* ctl, uint64_t k) {
-  if (ctl_halted(ctl)) return;
+constexpr int kRadixBits = 11;
+constexpr uint32_t kRadixBins = 1u << kRadixBits;
+
+template <typename Key>
+constexpr int radix_passes() {
+  return ((int)sizeof(Key) * 8 + kRadixBits - 1) / kRadixBits;
+}
+
+// Bits [shift, shift + width) form the digit of a pass; the bits above are
+// fixed by the passes before it.
+__device__ __forceinline__ void radix_digit(int key_bits, int pass, int& shift, int& width) {
+  const int top = key_bits - kRadixBits * pass;
+  shift = top > kRadixBits ? top - kRadixBits : 0;
+  width = top - shift;
+}
+
+// One block of 256 threads: clears the histogram and starts the select.
+static __global__ __launch_bounds__(256) void k_topk_init(Ctl* ctl, uint32_t* rhist, uint64_t k) {
+  for (uint32_t i = threadIdx.x; i < kRadixBins; i += 256) rhist[i] = 0;
+  if (threadIdx.x != 0 || ctl_halted(ctl)) return;
   if (ctl->pending <= k) {
     ctl->sel_mode = 0;
     ctl->radix_skip = 1;
@@ -458,55 +478,102 @@ static __global__ void k_topk_init(Ctl* ctl, uint64_t k) {
     ctl->k_rem = k;
     ctl->radix_prefix = 0;
   }
-  for (int i = 0; i < 256; ++i) ctl->hist[i] = 0;
 }
 
+// One pass: every workgroup counts the digits of the keys that match the
+// prefix in LDS and adds its counts into the global histogram; the last
+// workgroup to finish picks the digit that holds the k_rem-th largest key
+// (bins scanned from the top, 8 per thread), fixes it in the prefix and
+// clears the histogram for the next pass.
 template <int ST>
-__global__ __launch_bounds__(256) void k_radix_hist(KArgs a, int pass) {
+__global__ __launch_bounds__(256) void k_radix_pass(KArgs a, int pass) {
   using S = typename Tr<ST>::S;
   using Key = typename Tr<ST>::Key;
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl) || ctl->radix_skip) return;
   constexpr int kBits = sizeof(Key) * 8;
-  const int shift = kBits - 8 * (pass + 1);
-  const Key hi_mask = pass == 0 ? (Key)0 : (Key)(~(Key)0 << (shift + 8));
+  int shift, width;
+  radix_digit(kBits, pass, shift, width);
+  const Key hi_mask = pass == 0 ? (Key)0 : (Key)(~(Key)0 << (shift + width));
   const Key prefix = (Key)ctl->radix_prefix;
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  const uint32_t nbins = 1u << width, dmask = nbins - 1;
+  const uint32_t tid = threadIdx.x;
+  __shared__ uint32_t h[kRadixBins];
+  __shared__ uint32_t s_last, s_found;
+  for (uint32_t i = tid; i < nbins; i += 256) h[i] = 0;
   __syncthreads();
   const S* v = static_cast<const S*>(a.v);
   const S* dv = static_cast<const S*>(a.dv);
-  const uint64_t stride = (uint64_t)gridDim.x * 256;
-  for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < a.n; j += stride) {
-    Key k = sel_key<ST>(a, j, v[j], dv[j]);
-    if (k != 0 && (k & hi_mask) == prefix) atomicAdd(&h[(k >> shift) & 255], 1u);
+  const uint64_t stride = (uint64_t)gridDim.x * 1024;
+  // four keys per step, their loads in flight together
+  for (uint64_t j0 = (uint64_t)blockIdx.x * 1024 + tid; j0 < a.n; j0 += stride) {
+    Key k[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t j = min(j0 + 256 * u, a.n - 1);
+      k[u] = sel_key<ST>(a, j, v[j], dv[j]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j0 + 256 * u < a.n && k[u] != 0 && (k[u] & hi_mask) == prefix)
+        atomicAdd(&h[(uint32_t)(k[u] >> shift) & dmask], 1u);
   }
   __syncthreads();
-  uint32_t c = h[threadIdx.x];
-  if (c) atomicAdd(&ctl->hist[threadIdx.x], c);
-}
-
-template <int ST>
-__global__ void k_radix_pick(Ctl* ctl, int pass) {
-  using Key = typename Tr<ST>::Key;
-  if (ctl_halted(ctl) || ctl->radix_skip) return;
-  constexpr int kBits = sizeof(Key) * 8;
-  const int shift = kBits - 8 * (pass + 1);
-  uint64_t k = ctl->k_rem;
-  uint64_t cum = 0;
-  int d = 255;
-  for (; d > 0; --d) {
-    uint64_t c = ctl->hist[d];
-    if (cum + c >= k) break;
-    cum += c;
+  // the first wave adds the counts, so its own fence orders them all before
+  // the ticket (one fence per workgroup)
+  if (tid < 64) {
+    for (uint32_t i = tid; i < nbins; i += 64) {
+      const uint32_t c = h[i];
+      if (c) atomicAdd(&a.rhist[i], c);
+    }
+    if (tid == 0) {
+      __threadfence();
+      s_last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
+    }
   }
-  ctl->k_rem = k - cum;
-  ctl->radix_prefix |= (uint64_t)d << shift;
-  for (int i = 0; i < 256; ++i) ctl->hist[i] = 0;
-  if (shift == 0) {
-    ctl->tau = ctl->radix_prefix;
-    ctl->ties_left = ctl->k_rem;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // bins from the top: thread t holds bins nbins-1-8t-q, q = 0..7
+  uint32_t c[8];
+  uint32_t sum[1] = {0};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t r = tid * 8 + q;
+    c[q] = r < nbins ? __hip_atomic_load(&a.rhist[nbins - 1 - r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    sum[0] += c[q];
   }
+  uint32_t tot[1];
+  const uint32_t mine = sum[0];
+  block_excl_scan<1>(sum, tot);  // sum[0] = keys in the bins above this thread's
+  if (tid == 0) s_found = 0;
+  __syncthreads();
+  const uint64_t k = ctl->k_rem;
+  if ((uint64_t)sum[0] < k && k <= (uint64_t)sum[0] + mine) {
+    uint64_t cum = sum[0];
+    int q = 0;
+    for (; q < 7; ++q) {
+      if (cum + c[q] >= k) break;
+      cum += c[q];
+    }
+    const uint64_t d = nbins - 1 - (tid * 8 + q);
+    const uint64_t rem = k - cum;
+    ctl->k_rem = rem;
+    ctl->radix_prefix |= d << shift;
+    if (shift == 0) {
+      ctl->tau = ctl->radix_prefix;
+      ctl->ties_left = rem;
+      ctl->sel_mode = c[q] == rem ? 1u : 2u;  // all equal keys fit: no tie ranks
+    }
+    s_found = 1;
+  }
+  __syncthreads();
+  if (tid == 0 && !s_found) {  // fewer keys than k (not reached: pending > k)
+    ctl->sel_mode = 0;
+    ctl->radix_skip = 1;
+  }
+  for (uint32_t i = tid; i < nbins; i += 256) a.rhist[i] = 0;
+  if (tid == 0) ctl->ticket = 0;
 }
 
 template <int ST>

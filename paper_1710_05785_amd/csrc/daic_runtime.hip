@@ -112,14 +112,12 @@ struct Impl {
     } else {  // exact top-k (also the learned rule, on the learned keys)
       uint64_t k = (uint64_t)std::ceil(o->priority_fraction * (double)n);
       if (k < 1) k = 1;
-      const int passes = (int)sizeof(Key);
-      uint32_t hgrid = (uint32_t)std::min<uint64_t>(2048, (n + 255) / 256);
+      const int passes = radix_passes<Key>();
+      uint32_t hgrid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, (n + 1023) / 1024));
       launch(pr, "topk_radix", s, [&] {
-        hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(1), 0, s, a.ctl, k);
-        for (int pass = 0; pass < passes; ++pass) {
-          hipLaunchKernelGGL(k_radix_hist<ST>, dim3(hgrid), dim3(256), 0, s, a, pass);
-          hipLaunchKernelGGL(k_radix_pick<ST>, dim3(1), dim3(1), 0, s, a.ctl, pass);
-        }
+        hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, s, a.ctl, a.rhist, k);
+        for (int pass = 0; pass < passes; ++pass)
+          hipLaunchKernelGGL(k_radix_pass<ST>, dim3(hgrid), dim3(256), 0, s, a, pass);
         hipLaunchKernelGGL(k_tie_count<ST>, dim3(a.blocks), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_tie_scan, dim3(1), dim3(1024), 0, s, a);
       });
@@ -602,6 +600,7 @@ daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, doub
   GRAB(blk_small, uint32_t*, nb * 4);
   GRAB(blk_large, uint32_t*, nb * 4);
   GRAB(blk_ties, uint32_t*, nb * 4);
+  GRAB(rhist, uint32_t*, kRadixBins * 4);
   GRAB(off_small, uint64_t*, (nb + 1) * 8);
   GRAB(off_large, uint64_t*, (nb + 1) * 8);
   GRAB(off_ties, uint64_t*, (nb + 1) * 8);
