@@ -355,50 +355,74 @@ __global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round, uint
 // ---------------------------------------------------------------------------
 // A2 (sampled): threshold = the rank-th largest of S sampled keys; a
 // threshold of 0 (no positive sample) selects every pending vertex.
+// Grid of ceil(S / 64) workgroups: each loads all S sampled keys into LDS;
+// its four waves rank the same 64 samples against a quarter of the keys each
+// (keys above, keys equal), and the rank-th largest is the sample with
+// above < rank <= above + equal. Threads holding equal keys store the same
+// threshold.
 // ---------------------------------------------------------------------------
 template <int ST>
-__global__ __launch_bounds__(1024) void k_sample(KArgs a, uint32_t S_n, uint32_t rank, uint64_t seed,
-                                                 uint64_t round_override) {
+__global__ __launch_bounds__(256) void k_sample(KArgs a, uint32_t S_n, uint32_t rank, uint64_t seed,
+                                                uint64_t round_override) {
   using S = typename Tr<ST>::S;
   using Key = typename Tr<ST>::Key;
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
   __shared__ Key keys[kMaxSamples];
+  __shared__ uint32_t s_above[4][64], s_equal[4][64];
   const uint64_t round = round_override != ~0ull ? round_override : ctl->rounds;
   const S* v = static_cast<const S*>(a.v);
   const S* dv = static_cast<const S*>(a.dv);
-  uint32_t P = 1;
-  while (P < S_n) P <<= 1;
-  for (uint32_t i = threadIdx.x; i < P; i += 1024) {
-    Key k = 0;
-    if (i < S_n) {
-      uint64_t j = splitmix64_at(seed, round * (uint64_t)S_n + i) % a.n;
-      k = sel_key<ST>(a, j, v[j], dv[j]);
-    }
-    keys[i] = k;
+  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t PER = kMaxSamples / 256;
+  uint64_t jj[PER];
+#pragma unroll
+  for (uint32_t q = 0; q < PER; ++q) {
+    const uint32_t i = tid + 256 * q;
+    jj[q] = i < S_n ? splitmix64_at(seed, round * (uint64_t)S_n + i) % a.n : 0;
+  }
+  S vv[PER], dd[PER];
+#pragma unroll
+  for (uint32_t q = 0; q < PER; ++q) {
+    vv[q] = v[jj[q]];
+    dd[q] = dv[jj[q]];
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < PER; ++q) {
+    const uint32_t i = tid + 256 * q;
+    if (i < S_n) keys[i] = sel_key<ST>(a, jj[q], vv[q], dd[q]);
   }
   __syncthreads();
-  // bitonic sort, descending
-  for (uint32_t size = 2; size <= P; size <<= 1) {
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t i = threadIdx.x; i < P; i += 1024) {
-        uint32_t pr = i ^ stride;
-        if (pr > i) {
-          bool desc = (i & size) == 0;
-          Key x = keys[i], y = keys[pr];
-          if (desc ? (x < y) : (x > y)) {
-            keys[i] = y;
-            keys[pr] = x;
-          }
-        }
-      }
-      __syncthreads();
+  const uint32_t lane = tid & 63, wave = tid >> 6;
+  const uint32_t mine_i = min(blockIdx.x * 64 + lane, S_n - 1);
+  const Key mine = keys[mine_i];
+  // this wave's quarter of the keys; every lane reads the same key (broadcast)
+  const uint32_t quarter = (S_n + 3) / 4;
+  const uint32_t i0 = min(S_n, wave * quarter), i1 = min(S_n, i0 + quarter);
+  uint32_t above = 0, equal = 0, i = i0;
+  for (; i + 8 <= i1; i += 8) {
+    Key k[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) k[u] = keys[i + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      above += k[u] > mine ? 1u : 0u;
+      equal += k[u] == mine ? 1u : 0u;
     }
   }
-  if (threadIdx.x == 0) {
-    Key tau = keys[rank - 1];
-    ctl->sel_mode = tau == 0 ? 0u : 1u;
-    ctl->tau = (uint64_t)tau;
+  for (; i < i1; ++i) {
+    above += keys[i] > mine ? 1u : 0u;
+    equal += keys[i] == mine ? 1u : 0u;
+  }
+  s_above[wave][lane] = above;
+  s_equal[wave][lane] = equal;
+  __syncthreads();
+  if (wave != 0 || blockIdx.x * 64 + lane >= S_n) return;
+  above = s_above[0][lane] + s_above[1][lane] + s_above[2][lane] + s_above[3][lane];
+  equal = s_equal[0][lane] + s_equal[1][lane] + s_equal[2][lane] + s_equal[3][lane];
+  if (above < rank && rank <= above + equal) {
+    ctl->sel_mode = mine == 0 ? 0u : 1u;
+    ctl->tau = (uint64_t)mine;
   }
 }
 

@@ -107,7 +107,7 @@ struct Impl {
       uint32_t S = o->n_samples ? o->n_samples : kMaxSamples;
       uint32_t rank = (uint32_t)std::max(1.0, std::ceil(o->priority_fraction * (double)S));
       launch(pr, "sample_threshold", s, [&] {
-        hipLaunchKernelGGL(k_sample<ST>, dim3(1), dim3(1024), 0, s, a, S, rank, o->seed, round_override);
+        hipLaunchKernelGGL(k_sample<ST>, dim3((S + 63) / 64), dim3(256), 0, s, a, S, rank, o->seed, round_override);
       });
     } else {  // exact top-k (also the learned rule, on the learned keys)
       uint64_t k = (uint64_t)std::ceil(o->priority_fraction * (double)n);
