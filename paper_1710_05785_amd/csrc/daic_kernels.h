@@ -420,9 +420,9 @@ __global__ __launch_bounds__(256) void k_sample(KArgs a, uint32_t S_n, uint32_t 
   if (wave != 0 || blockIdx.x * 64 + lane >= S_n) return;
   above = s_above[0][lane] + s_above[1][lane] + s_above[2][lane] + s_above[3][lane];
   equal = s_equal[0][lane] + s_equal[1][lane] + s_equal[2][lane] + s_equal[3][lane];
-  if (above < rank && rank <= above + equal) {
-    ctl->sel_mode = mine == 0 ? 0u : 1u;
-    ctl->tau = (uint64_t)mine;
+  if (above < rank && rank <= above + equal) {  // every such thread stores the same values
+    __hip_atomic_store(&ctl->sel_mode, mine == 0 ? 0u : 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->tau, (uint64_t)mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

@@ -416,6 +416,40 @@ def test_exact_topk_matches_oracle(daic, n, q, state):
     np.testing.assert_array_equal(np.nonzero(sel)[0], want)
 
 
+@pytest.mark.parametrize("case", ["distinct", "ties_fit", "ties_cut"])
+@pytest.mark.parametrize("state", ["f64", "f32"])
+def test_exact_topk_tie_forms(daic, case, state):
+    """The k-th key alone (distinct keys), its equal keys all inside the k
+    (the round takes key >= tau without tie ranks), or cut by the k (ties go
+    to the smaller ids), for 64- and 32-bit keys."""
+    say("case exact topk ties", case, state)
+    n = 100003
+    rng = np.random.default_rng(7)
+    zero = rng.random(n) < 0.05
+    if case == "distinct":
+        dv = rng.permutation(n).astype(np.float64) + 1.0
+        q = 0.05
+    else:
+        # 4,000 keys above 10, 1,000 keys equal to 10, the other pending ones below
+        dv = rng.uniform(0.5, 9.5, n)
+        hi = rng.choice(n, 5000, replace=False)
+        dv[hi[:4000]] = rng.uniform(11.0, 20.0, 4000)
+        dv[hi[4000:]] = 10.0
+        zero[hi] = False
+        q = 5000 / n if case == "ties_fit" else 4500 / n
+    dv[zero] = 0.0
+    if state == "f32":
+        dv = dv.astype(np.float32).astype(np.float64)
+    g = daic_gen.from_edges(n, [], [])
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8, state=state)
+    p.set_init(np.zeros(n), dv)
+    sel, _ = p.select_frontier(q=q, sched="exact")
+    want = oracle.topk_exact(np.abs(dv), q)
+    if case != "distinct":
+        assert len(want) == int(np.ceil(q * n)) and (np.abs(dv)[want] >= 10.0).all()
+    np.testing.assert_array_equal(np.nonzero(sel)[0], want)
+
+
 @pytest.mark.parametrize("round_no", [0, 3, 17])
 @pytest.mark.parametrize("q", [0.01, 0.1, 1.0])
 def test_sampled_threshold_matches_oracle(daic, round_no, q):
@@ -435,6 +469,27 @@ def test_sampled_threshold_matches_oracle(daic, round_no, q):
     np.testing.assert_array_equal(sel, want)
     if q < 1.0:
         assert np.float32(tau) == tau_o
+
+
+@pytest.mark.parametrize("n_samples", [1, 1000, 4096])
+@pytest.mark.parametrize("q", [0.01, 0.37])
+def test_sampled_threshold_with_ties_matches_oracle(daic, n_samples, q):
+    """Sample counts that leave a ragged last workgroup of the ranking
+    kernel, and integer priorities, so the threshold sample has many equal
+    keys; q * S below 1 takes the largest sample."""
+    say("case sampled ties", n_samples, q)
+    n = 30011
+    rng = np.random.default_rng(n_samples)
+    g = daic_gen.from_edges(n, [], [])
+    p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8, state="f64")
+    dv = rng.integers(0, 12, n).astype(np.float64)
+    p.set_init(np.zeros(n), dv)
+    for round_no in (0, 5):
+        sel, tau = p.select_frontier(q=q, sched="sampled", seed=99, round_no=round_no, n_samples=n_samples)
+        tau_o = oracle.sampled_threshold(dv, q, n_samples, 99, round_no)
+        np.testing.assert_array_equal(sel, (dv >= tau_o) & (dv > 0))
+        if tau != 0:  # 0: the sample at the rank was not pending, every pending vertex is taken
+            assert tau == tau_o
 
 
 def test_device_graph_from_torch(daic):
