@@ -161,6 +161,21 @@ __device__ __forceinline__ typename Tr<ST>::Key sel_key(const KArgs& a, uint64_t
   return k;
 }
 
+// sel_key with the vertex's multiplier already loaded (sc, read only when
+// the learned scheduler's scores are present), so that the loads of several
+// vertices can be issued before any key is formed.
+template <int ST>
+__device__ __forceinline__ typename Tr<ST>::Key sel_key_loaded(const KArgs& a, typename Tr<ST>::S v,
+                                                                typename Tr<ST>::S dv, float sc) {
+  using Key = typename Tr<ST>::Key;
+  Key k = prio_key<ST>(v, dv);
+  if (a.score != nullptr && k != 0) {
+    const uint32_t b = __float_as_uint(prio_value<ST>(v, dv) * sc);
+    return (Key)(b == 0 ? 1u : b);
+  }
+  return k;
+}
+
 template <typename RowT>
 __device__ __forceinline__ uint64_t row_at(const void* row, uint64_t j) {
   return (uint64_t)static_cast<const RowT*>(row)[j];
@@ -382,15 +397,17 @@ __global__ __launch_bounds__(256) void k_sample(KArgs a, uint32_t S_n, uint32_t 
     jj[q] = i < S_n ? splitmix64_at(seed, round * (uint64_t)S_n + i) % a.n : 0;
   }
   S vv[PER], dd[PER];
+  float sc[PER];
 #pragma unroll
   for (uint32_t q = 0; q < PER; ++q) {
     vv[q] = v[jj[q]];
     dd[q] = dv[jj[q]];
+    sc[q] = a.score != nullptr ? a.score[jj[q]] : 1.f;
   }
 #pragma unroll
   for (uint32_t q = 0; q < PER; ++q) {
     const uint32_t i = tid + 256 * q;
-    if (i < S_n) keys[i] = sel_key<ST>(a, jj[q], vv[q], dd[q]);
+    if (i < S_n) keys[i] = sel_key_loaded<ST>(a, vv[q], dd[q], sc[q]);
   }
   __syncthreads();
   const uint32_t lane = tid & 63, wave = tid >> 6;
@@ -528,17 +545,24 @@ __global__ __launch_bounds__(256) void k_radix_pass(KArgs a, int pass) {
   __syncthreads();
   const S* v = static_cast<const S*>(a.v);
   const S* dv = static_cast<const S*>(a.dv);
-  const uint64_t stride = (uint64_t)gridDim.x * 1024;
-  // four keys per step, their loads in flight together
-  for (uint64_t j0 = (uint64_t)blockIdx.x * 1024 + tid; j0 < a.n; j0 += stride) {
-    Key k[4];
+  constexpr int U = 8;
+  const uint64_t stride = (uint64_t)gridDim.x * 256 * U;
+  // U keys per step, their loads in flight together
+  for (uint64_t j0 = (uint64_t)blockIdx.x * 256 * U + tid; j0 < a.n; j0 += stride) {
+    S vv[U], dd[U];
+    float sc[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const uint64_t j = min(j0 + 256 * u, a.n - 1);
-      k[u] = sel_key<ST>(a, j, v[j], dv[j]);
+      vv[u] = v[j];
+      dd[u] = dv[j];
+      sc[u] = a.score != nullptr ? a.score[j] : 1.f;
     }
+    Key k[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u) k[u] = sel_key_loaded<ST>(a, vv[u], dd[u], sc[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
       if (j0 + 256 * u < a.n && k[u] != 0 && (k[u] & hi_mask) == prefix)
         atomicAdd(&h[(uint32_t)(k[u] >> shift) & dmask], 1u);
   }
@@ -612,7 +636,21 @@ __global__ __launch_bounds__(256) void k_tie_count(KArgs a) {
   const S* v = static_cast<const S*>(a.v);
   const S* dv = static_cast<const S*>(a.dv);
   uint32_t cnt = 0;
-  for (uint64_t j = lo + threadIdx.x; j < hi; j += 256) cnt += sel_key<ST>(a, j, v[j], dv[j]) == tau;
+  // four vertices per step, their loads in flight together
+  for (uint64_t j0 = lo + threadIdx.x; j0 < hi; j0 += 1024) {
+    S vv[4], dd[4];
+    float sc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t j = min(j0 + 256 * u, hi - 1);
+      vv[u] = v[j];
+      dd[u] = dv[j];
+      sc[u] = a.score != nullptr ? a.score[j] : 1.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      cnt += (j0 + 256 * u < hi && sel_key_loaded<ST>(a, vv[u], dd[u], sc[u]) == tau) ? 1u : 0u;
+  }
   cnt = block_sum256(cnt);
   if (threadIdx.x == 0) a.blk_ties[blockIdx.x] = cnt;
 }
