@@ -280,15 +280,13 @@ __device__ __forceinline__ void push_edge(const KArgs& a, uint64_t e, typename T
 }
 
 // ---------------------------------------------------------------------------
-// A1: residual of the current state and the stop rule. Deterministic: block
-// partials are summed by the last block in a fixed order.
+// A1: residual of the current state and the stop rule. Deterministic: every
+// block of k_residual stores its partials, and k_residual_final (one block)
+// sums them in a fixed order. (A last-block ticket would make all blocks
+// increment one counter at the same time; those atomics serialize.)
 // ---------------------------------------------------------------------------
-// Besides the residual, the last block picks the direction of the next round:
-// a dense round (pull over in-edges) when at least pull_min vertices are
-// expected to update (min(pending, k_sel)); k_sel = 0 disables dense rounds.
 template <int ST>
-__global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round, uint64_t k_sel, uint64_t pull_min,
-                                                  int skip_dense = 0) {
+__global__ __launch_bounds__(256) void k_residual(KArgs a, int skip_dense = 0) {
   using S = typename Tr<ST>::S;
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
@@ -324,17 +322,22 @@ __global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round, uint
   }
   r = block_sum256(r);
   cnt = block_sum256(cnt);
-  __shared__ uint32_t s_last;
   if (threadIdx.x == 0) {
     a.part_r[b] = r;
     a.part_n[b] = cnt;
-    __threadfence();
-    uint32_t t = atomicAdd(&ctl->ticket, 1u);
-    s_last = (t == a.blocks - 1);
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
+
+// Besides the residual, k_residual_final picks the direction of the next
+// round: a dense round (pull over in-edges) when at least pull_min vertices
+// are expected to update (min(pending, k_sel)); k_sel = 0 disables dense
+// rounds. One block; it returns in the cases where k_residual returned.
+template <int ST>
+__global__ __launch_bounds__(256) void k_residual_final(KArgs a, int count_round, uint64_t k_sel,
+                                                        uint64_t pull_min, int skip_dense = 0) {
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  if (skip_dense && ctl->last_pull) return;
   double rr = 0.0;
   uint64_t nn = 0;
   for (uint32_t i0 = threadIdx.x; i0 < a.blocks; i0 += 1024) {
@@ -343,8 +346,8 @@ __global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round, uint
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint32_t i = min(i0 + 256 * u, a.blocks - 1);
-      pr[u] = __hip_atomic_load(&a.part_r[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      pn[u] = __hip_atomic_load(&a.part_n[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      pr[u] = a.part_r[i];
+      pn[u] = a.part_n[i];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -363,7 +366,6 @@ __global__ __launch_bounds__(256) void k_residual(KArgs a, int count_round, uint
     ctl->done = done ? 1u : 0u;
     ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
     ctl->pull = (k_sel != 0 && (nn < k_sel ? nn : k_sel) >= pull_min) ? 1u : 0u;
-    ctl->ticket = 0;
   }
 }
 
@@ -492,6 +494,9 @@ static __global__ void k_select_rr(Ctl* ctl, uint64_t nblocks) {
 // ---------------------------------------------------------------------------
 constexpr int kRadixBits = 11;
 constexpr uint32_t kRadixBins = 1u << kRadixBits;
+// copies of the global histogram: workgroup b adds into copy b mod
+// kRadixCopies, so each counter takes a fraction of the atomics
+constexpr uint32_t kRadixCopies = 8;
 
 template <typename Key>
 constexpr int radix_passes() {
@@ -506,9 +511,9 @@ __device__ __forceinline__ void radix_digit(int key_bits, int pass, int& shift, 
   width = top - shift;
 }
 
-// One block of 256 threads: clears the histogram and starts the select.
+// One block of 256 threads: clears the histograms and starts the select.
 static __global__ __launch_bounds__(256) void k_topk_init(Ctl* ctl, uint32_t* rhist, uint64_t k) {
-  for (uint32_t i = threadIdx.x; i < kRadixBins; i += 256) rhist[i] = 0;
+  for (uint32_t i = threadIdx.x; i < kRadixBins * kRadixCopies; i += 256) rhist[i] = 0;
   if (threadIdx.x != 0 || ctl_halted(ctl)) return;
   if (ctl->pending <= k) {
     ctl->sel_mode = 0;
@@ -522,10 +527,8 @@ static __global__ __launch_bounds__(256) void k_topk_init(Ctl* ctl, uint32_t* rh
 }
 
 // One pass: every workgroup counts the digits of the keys that match the
-// prefix in LDS and adds its counts into the global histogram; the last
-// workgroup to finish picks the digit that holds the k_rem-th largest key
-// (bins scanned from the top, 8 per thread), fixes it in the prefix and
-// clears the histogram for the next pass.
+// prefix in LDS and adds its counts into its copy of the global histogram;
+// k_radix_pick then picks the digit.
 template <int ST>
 __global__ __launch_bounds__(256) void k_radix_pass(KArgs a, int pass) {
   using S = typename Tr<ST>::S;
@@ -540,7 +543,6 @@ __global__ __launch_bounds__(256) void k_radix_pass(KArgs a, int pass) {
   const uint32_t nbins = 1u << width, dmask = nbins - 1;
   const uint32_t tid = threadIdx.x;
   __shared__ uint32_t h[kRadixBins];
-  __shared__ uint32_t s_last, s_found;
   for (uint32_t i = tid; i < nbins; i += 256) h[i] = 0;
   __syncthreads();
   const S* v = static_cast<const S*>(a.v);
@@ -567,28 +569,41 @@ __global__ __launch_bounds__(256) void k_radix_pass(KArgs a, int pass) {
         atomicAdd(&h[(uint32_t)(k[u] >> shift) & dmask], 1u);
   }
   __syncthreads();
-  // the first wave adds the counts, so its own fence orders them all before
-  // the ticket (one fence per workgroup)
-  if (tid < 64) {
-    for (uint32_t i = tid; i < nbins; i += 64) {
-      const uint32_t c = h[i];
-      if (c) atomicAdd(&a.rhist[i], c);
-    }
-    if (tid == 0) {
-      __threadfence();
-      s_last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
-    }
+  uint32_t* hist = a.rhist + (blockIdx.x % kRadixCopies) * kRadixBins;
+  for (uint32_t i = tid; i < nbins; i += 256) {
+    const uint32_t c = h[i];
+    if (c) atomicAdd(&hist[i], c);
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
+
+// After a pass (one block of 256 threads): the digit that holds the
+// k_rem-th largest key, from the sum of the histogram copies (bins scanned
+// from the top, 8 per thread); it is fixed in the prefix and the copies are
+// cleared for the next pass.
+template <int ST>
+__global__ __launch_bounds__(256) void k_radix_pick(KArgs a, int pass) {
+  using Key = typename Tr<ST>::Key;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl) || ctl->radix_skip) return;
+  constexpr int kBits = sizeof(Key) * 8;
+  int shift, width;
+  radix_digit(kBits, pass, shift, width);
+  const uint32_t nbins = 1u << width;
+  const uint32_t tid = threadIdx.x;
+  __shared__ uint32_t s_found;
   // bins from the top: thread t holds bins nbins-1-8t-q, q = 0..7
   uint32_t c[8];
   uint32_t sum[1] = {0};
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const uint32_t r = tid * 8 + q;
-    c[q] = r < nbins ? __hip_atomic_load(&a.rhist[nbins - 1 - r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    uint32_t x[kRadixCopies];
+#pragma unroll
+    for (uint32_t cp = 0; cp < kRadixCopies; ++cp)
+      x[cp] = r < nbins ? a.rhist[cp * kRadixBins + nbins - 1 - r] : 0u;
+    c[q] = 0;
+#pragma unroll
+    for (uint32_t cp = 0; cp < kRadixCopies; ++cp) c[q] += x[cp];
     sum[0] += c[q];
   }
   uint32_t tot[1];
@@ -620,8 +635,9 @@ __global__ __launch_bounds__(256) void k_radix_pass(KArgs a, int pass) {
     ctl->sel_mode = 0;
     ctl->radix_skip = 1;
   }
-  for (uint32_t i = tid; i < nbins; i += 256) a.rhist[i] = 0;
-  if (tid == 0) ctl->ticket = 0;
+  for (uint32_t i = tid; i < nbins; i += 256)
+#pragma unroll
+    for (uint32_t cp = 0; cp < kRadixCopies; ++cp) a.rhist[cp * kRadixBins + i] = 0;
 }
 
 template <int ST>

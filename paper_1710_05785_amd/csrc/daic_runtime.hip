@@ -90,8 +90,8 @@ struct Impl {
   using Key = typename Tr<ST>::Key;
 
   static void residual(daic_problem* p, hipStream_t s, int count_round) {
-    hipLaunchKernelGGL(k_residual<ST>, dim3(p->a.blocks), dim3(256), 0, s, p->a, count_round, p->k_sel,
-                       p->pull_min);
+    hipLaunchKernelGGL(k_residual<ST>, dim3(p->a.blocks), dim3(256), 0, s, p->a, 0);
+    hipLaunchKernelGGL(k_residual_final<ST>, dim3(1), dim3(256), 0, s, p->a, count_round, p->k_sel, p->pull_min, 0);
   }
 
   // Threshold of a round (A2) for the given rule.
@@ -116,8 +116,10 @@ struct Impl {
       uint32_t hgrid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, (n + 1023) / 1024));
       launch(pr, "topk_radix", s, [&] {
         hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, s, a.ctl, a.rhist, k);
-        for (int pass = 0; pass < passes; ++pass)
+        for (int pass = 0; pass < passes; ++pass) {
           hipLaunchKernelGGL(k_radix_pass<ST>, dim3(hgrid), dim3(256), 0, s, a, pass);
+          hipLaunchKernelGGL(k_radix_pick<ST>, dim3(1), dim3(256), 0, s, a, pass);
+        }
         hipLaunchKernelGGL(k_tie_count<ST>, dim3(a.blocks), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_tie_scan, dim3(1), dim3(1024), 0, s, a);
       });
@@ -148,8 +150,9 @@ struct Impl {
       });
     }
     launch(pr, "residual", s, [&] {
-      hipLaunchKernelGGL(k_residual<ST>, dim3(a.blocks), dim3(256), 0, s, a, 1, p->k_sel, p->pull_min,
-                         p->pull_ready ? 1 : 0);
+      const int skip = p->pull_ready ? 1 : 0;
+      hipLaunchKernelGGL(k_residual<ST>, dim3(a.blocks), dim3(256), 0, s, a, skip);
+      hipLaunchKernelGGL(k_residual_final<ST>, dim3(1), dim3(256), 0, s, a, 1, p->k_sel, p->pull_min, skip);
     });
   }
 
@@ -600,7 +603,7 @@ daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, doub
   GRAB(blk_small, uint32_t*, nb * 4);
   GRAB(blk_large, uint32_t*, nb * 4);
   GRAB(blk_ties, uint32_t*, nb * 4);
-  GRAB(rhist, uint32_t*, kRadixBins * 4);
+  GRAB(rhist, uint32_t*, kRadixBins * kRadixCopies * 4);
   GRAB(off_small, uint64_t*, (nb + 1) * 8);
   GRAB(off_large, uint64_t*, (nb + 1) * 8);
   GRAB(off_ties, uint64_t*, (nb + 1) * 8);

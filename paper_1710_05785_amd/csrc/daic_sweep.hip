@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
 
 // After each round: add the claim's per-block counts to the totals; when the
 // round does not end a sweep, count it and apply the round limit (the sweep's
-// last round is counted by k_sweep_residual).
+// last round is counted by k_sweep_residual_final).
 __global__ __launch_bounds__(256) void k_sweep_step(SweepArgs a, int sweep_end) {
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
@@ -201,8 +201,8 @@ __global__ __launch_bounds__(256) void k_sweep_step(SweepArgs a, int sweep_end) 
   }
 }
 
-// End of a sweep: the bound on the pending mass, the stop rule and the round
-// count. Fixed-order reduction of per-block FP64 partials.
+// End of a sweep: per-workgroup partials of the bound on the pending mass
+// (k_sweep_residual_final adds them in a fixed order).
 template <int ST>
 __global__ __launch_bounds__(256) void k_sweep_residual(SweepArgs a) {
   using S = typename Tr<ST>::S;
@@ -233,21 +233,22 @@ __global__ __launch_bounds__(256) void k_sweep_residual(SweepArgs a) {
   }
   r = block_sum256(r);
   cnt = block_sum256(cnt);
-  __shared__ uint32_t s_last;
   if (threadIdx.x == 0) {
     a.part_r[blockIdx.x] = r;
     a.part_n[blockIdx.x] = cnt;
-    __threadfence();
-    s_last = atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1;
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
+
+// One block after k_sweep_residual (nparts workgroups): their partials
+// summed in a fixed order, the stop rule and the round count.
+__global__ __launch_bounds__(256) void k_sweep_residual_final(SweepArgs a, uint32_t nparts) {
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
   double rr = 0.0;
   uint64_t nn = 0;
-  for (uint32_t i = threadIdx.x; i < gridDim.x; i += 256) {
-    rr += __hip_atomic_load(&a.part_r[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    nn += __hip_atomic_load(&a.part_n[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t i = threadIdx.x; i < nparts; i += 256) {
+    rr += a.part_r[i];
+    nn += a.part_n[i];
   }
   rr = block_sum256(rr);
   nn = block_sum256(nn);
@@ -258,7 +259,6 @@ __global__ __launch_bounds__(256) void k_sweep_residual(SweepArgs a) {
     const bool done = rr <= ctl->eps;
     ctl->done = done ? 1u : 0u;
     ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
-    ctl->ticket = 0;
   }
 }
 
@@ -358,7 +358,11 @@ struct SweepImpl {
     hipLaunchKernelGGL((k_sweep_claim<ST, G>), dim3(a.claim_blocks), dim3(256), 0, s, a, c);
     const bool end = c + 1 == a.P;
     hipLaunchKernelGGL(k_sweep_step, dim3(1), dim3(256), 0, s, a, end ? 1 : 0);
-    if (end) hipLaunchKernelGGL(k_sweep_residual<ST>, dim3(sgrid(a.n, 256, kResGrid)), dim3(256), 0, s, a);
+    if (end) {
+      const uint32_t g = sgrid(a.n, 256, kResGrid);
+      hipLaunchKernelGGL(k_sweep_residual<ST>, dim3(g), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(k_sweep_residual_final, dim3(1), dim3(256), 0, s, a, g);
+    }
   }
   static void deliver(const SweepState& w, hipStream_t s) {
     const SweepArgs& a = w.a;
