@@ -1404,8 +1404,18 @@ __global__ __launch_bounds__(256) void k_fused_finish(KArgs a, uint32_t nf) {
     const uint64_t g = (uint64_t)blockIdx.x * 256 + tid;
     if (g < a.n_groups) {
       const uint32_t b0 = a.g_first[g], np = a.g_np[g];
+      // the pieces' partials in order, 32 loads in flight at a time (a hub
+      // has hundreds of pieces; one load per step would make its thread the
+      // kernel's critical path)
       double sum = 0.0;
-      for (uint32_t k = 0; k < np; ++k) sum += a.sb_part[b0 + k];
+      for (uint32_t k0 = 0; k0 < np; k0 += 32) {
+        double x[32];
+#pragma unroll
+        for (uint32_t u = 0; u < 32; ++u) x[u] = a.sb_part[b0 + min(k0 + u, np - 1)];
+#pragma unroll
+        for (uint32_t u = 0; u < 32; ++u)
+          if (k0 + u < np) sum += x[u];
+      }
       const uint32_t t = a.sb_t[b0];
       FusedTarget<ST, G>::finish(a, mu_out, t, static_cast<const S*>(a.dv)[t], (S)sum, static_cast<const S*>(a.v)[t],
                                  Tr<ST>::kahan ? a.c[t] : 0.f, row[t + 1] - row[t], a.perm[t], r_part, act, pushed);
