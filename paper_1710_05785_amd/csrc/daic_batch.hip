@@ -434,10 +434,19 @@ __global__ __launch_bounds__(256) void k_bresidual(BArgs a, int count_round) {
   double r = 0.0;
   uint64_t pend = 0;
   const uint32_t it = blockIdx.x;
-  for (uint64_t j = a.rlo[it] + wave; j < a.rhi[it]; j += 4) {
-    float x = a.dv[j * kR + lane];
-    r += fabs((double)x);
-    pend += __ballot(x != 0.0f) != 0 ? 1 : 0;
+  // rows j, j + 4, j + 8, j + 12 of this wave per step, their loads in
+  // flight together (the same summation order as one row per step)
+  const uint64_t rlo = a.rlo[it], rhi = a.rhi[it];
+  for (uint64_t j0 = rlo + wave; j0 < rhi; j0 += 16) {
+    float x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = a.dv[min(j0 + 4 * u, rhi - 1) * kR + lane];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (j0 + 4 * u >= rhi) break;  // uniform over the wave
+      r += fabs((double)x[u]);
+      pend += __ballot(x[u] != 0.0f) != 0 ? 1 : 0;
+    }
   }
   s_w[wave][lane] = r;
   pend = (lane == 0) ? pend : 0;
