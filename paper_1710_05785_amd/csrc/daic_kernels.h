@@ -920,11 +920,17 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
 static __global__ __launch_bounds__(1024) void k_bin_scan(KArgs a) {
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
-  if (threadIdx.x == 0) ctl->last_pull = ctl->pull;
-  excl_prefix_1024(a.blk_small, a.off_small, a.blocks, &ctl->n_small);
-  __syncthreads();
-  excl_prefix_1024(a.blk_large, a.off_large, a.blocks, &ctl->n_large);
-  __syncthreads();
+  const uint32_t pull = ctl->pull;
+  if (threadIdx.x == 0) ctl->last_pull = pull;
+  if (!pull) {  // the bins feed the push kernels only
+    excl_prefix_1024(a.blk_small, a.off_small, a.blocks, &ctl->n_small);
+    __syncthreads();
+    excl_prefix_1024(a.blk_large, a.off_large, a.blocks, &ctl->n_large);
+    __syncthreads();
+  } else if (threadIdx.x == 0) {
+    ctl->n_small = 0;
+    ctl->n_large = 0;
+  }
   uint64_t act = 0, push = 0, pl = 0;
   for (uint32_t i = threadIdx.x; i < a.blocks; i += 1024) {
     act += a.blk_act[i];
