@@ -561,6 +561,9 @@ def main():
             "bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "alg_bytes_per_launch": per_launch, "avg_launch_ms": dom["avg_ms"],
+            # the counted bytes per launch over the same live launch time: how
+            # close the kernel's actual memory traffic runs to the HBM peak
+            "traffic_GBs": (traffic / (dom["avg_ms"] * 1e-3) / 1e9) if traffic else None,
         }
         out["kernels"] = [{k2: (round(v, 6) if isinstance(v, float) else v) for k2, v in k.items()}
                           for k in sorted(ks, key=lambda k: -k["total_ms"])]
