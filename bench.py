@@ -206,6 +206,44 @@ def priority_form(torch, P, v0, dv1, eps, rounds_per_check, q=0.1):
     return out
 
 
+def sssp_form(daic, torch, rounds_per_check):
+    """The single-source shortest-path workload (push rounds, integer min):
+    RMAT-20, edge factor 16 (seed 2), weights U{1..255} (seed 3), source 0,
+    sampled top-10 % and all-pending scheduling, each warmed up and timed; the
+    per-kernel profile of the sampled run with the push kernels' algorithmic
+    GB/s."""
+    import numpy as np
+
+    import daic_gen
+
+    g = daic_gen.rmat(20, 16, seed=2)
+    w = daic_gen.sssp_weights(g.m, seed=3)
+    P = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+    v0 = np.full(g.n, 0xFFFFFFFF, dtype=np.uint32)
+    dv1 = v0.copy()
+    dv1[0] = 0
+    out = {"workload": "SSSP RMAT-20 (n=1048576, m=16777216), weights U{1..255}, source 0, uint32"}
+    for name, kw in (("sampled_q0.1", dict(q=0.1, sched="sampled", seed=1)), ("all", dict(q=1.0, sched="all"))):
+        run_kw = dict(rounds_per_check=rounds_per_check, **kw)
+        P.set_init(v0, dv1)
+        P.run(**run_kw)  # warm-up
+        P.set_init(v0, dv1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = P.run(**run_kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        out[name] = {"time_ms": wall * 1e3, "rounds": r.stats["rounds"], "pushed_edges": r.stats["pushed_edges"],
+                     "gteps": r.stats["pushed_edges"] / wall / 1e9, "converged": r.converged}
+    P.set_init(v0, dv1)
+    _, ks = P.profile(q=0.1, sched="sampled", seed=1, rounds_per_check=rounds_per_check)
+    out["kernels_sampled_q0.1"] = [
+        {"name": k["name"], "launches": k["launches"], "avg_ms": k["total_ms"] / max(1, k["launches"]),
+         "achieved_GBs": (k["alg_bytes"] / (k["total_ms"] * 1e-3) / 1e9) if k["total_ms"] > 0 else 0.0}
+        for k in sorted(ks, key=lambda k: -k["total_ms"])]
+    return out
+
+
 def sweep_form(daic, torch, g, d, eps, rounds_per_check, P=None, v0=None, dv1=None):
     """The sweep schedule on the plain workload: 8 id blocks in turn, each
     pulling the newest messages of its in-neighbours; warmed up, then timed."""
@@ -437,7 +475,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP64 and sampled forms")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--form", choices=("learned", "batched", "sweep", "priority"),
+    ap.add_argument("--form", choices=("learned", "batched", "sweep", "priority", "sssp"),
                     help="run only this form and print it (for profiling its kernels)")
     ap.add_argument("--ablation", action="store_true",
                     help="only run the sync / round-robin / priority comparison")
@@ -466,6 +504,9 @@ def main():
     if args.form == "batched":
         print(json.dumps({"batched_ppr_64x64": batched_form(daic, torch, args.eps, args.rounds_per_check)}),
               flush=True)
+        return
+    if args.form == "sssp":
+        print(json.dumps({"sssp_rmat20": sssp_form(daic, torch, args.rounds_per_check)}), flush=True)
         return
     d = 0.8
     t = time.perf_counter()
@@ -601,6 +642,8 @@ def main():
         forms["learned_sched"] = learned_form(daic, torch, g, args.eps, args.rounds_per_check)
         log("batched form ...")
         forms["batched_ppr_64x64"] = batched_form(daic, torch, args.eps, args.rounds_per_check)
+        log("sssp form ...")
+        forms["sssp_rmat20"] = sssp_form(daic, torch, args.rounds_per_check)
         out["forms"] = forms
 
     if not args.no_cpu_baseline:
