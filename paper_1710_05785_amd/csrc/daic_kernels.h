@@ -59,7 +59,8 @@ struct KArgs {
   uint64_t* blk_push;
   uint64_t* blk_push_large;
   uint32_t* blk_ties;       // exact top-k: keys equal to tau per block
-  uint32_t* rhist;          // exact top-k: radix histogram (kRadixBins counters)
+  uint32_t* rhist;          // exact top-k: radix histogram (kRadixCopies x kRadixBins counters)
+  uint64_t* skeys;          // sampled threshold: the round's sampled keys (kMaxSamples)
   uint64_t* off_ties;       // exclusive prefix of blk_ties
   double* part_r;           // residual partials per block
   uint64_t* part_n;         // pending-count partials per block
@@ -372,45 +373,41 @@ __global__ __launch_bounds__(256) void k_residual_final(KArgs a, int count_round
 // ---------------------------------------------------------------------------
 // A2 (sampled): threshold = the rank-th largest of S sampled keys; a
 // threshold of 0 (no positive sample) selects every pending vertex.
-// Grid of ceil(S / 64) workgroups: each loads all S sampled keys into LDS;
-// its four waves rank the same 64 samples against a quarter of the keys each
-// (keys above, keys equal), and the rank-th largest is the sample with
-// above < rank <= above + equal. Threads holding equal keys store the same
+// k_sample_keys draws the S sampled keys (one thread each); k_sample then
+// ranks them: ceil(S / 64) workgroups, each loading all S keys into LDS,
+// whose four waves rank the same 64 samples against a quarter of the keys
+// each (keys above, keys equal). The rank-th largest is the sample with
+// above < rank <= above + equal; threads holding equal keys store the same
 // threshold.
 // ---------------------------------------------------------------------------
 template <int ST>
-__global__ __launch_bounds__(256) void k_sample(KArgs a, uint32_t S_n, uint32_t rank, uint64_t seed,
-                                                uint64_t round_override) {
+__global__ __launch_bounds__(256) void k_sample_keys(KArgs a, uint32_t S_n, uint64_t seed, uint64_t round_override) {
   using S = typename Tr<ST>::S;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= S_n) return;
+  const uint64_t round = round_override != ~0ull ? round_override : ctl->rounds;
+  const uint64_t j = splitmix64_at(seed, round * (uint64_t)S_n + i) % a.n;
+  const float sc = a.score != nullptr ? a.score[j] : 1.f;
+  a.skeys[i] = (uint64_t)sel_key_loaded<ST>(a, static_cast<const S*>(a.v)[j], static_cast<const S*>(a.dv)[j], sc);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_sample(KArgs a, uint32_t S_n, uint32_t rank) {
   using Key = typename Tr<ST>::Key;
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
   __shared__ Key keys[kMaxSamples];
   __shared__ uint32_t s_above[4][64], s_equal[4][64];
-  const uint64_t round = round_override != ~0ull ? round_override : ctl->rounds;
-  const S* v = static_cast<const S*>(a.v);
-  const S* dv = static_cast<const S*>(a.dv);
   const uint32_t tid = threadIdx.x;
   constexpr uint32_t PER = kMaxSamples / 256;
-  uint64_t jj[PER];
+  Key kk[PER];
 #pragma unroll
-  for (uint32_t q = 0; q < PER; ++q) {
-    const uint32_t i = tid + 256 * q;
-    jj[q] = i < S_n ? splitmix64_at(seed, round * (uint64_t)S_n + i) % a.n : 0;
-  }
-  S vv[PER], dd[PER];
-  float sc[PER];
+  for (uint32_t q = 0; q < PER; ++q) kk[q] = (Key)a.skeys[min(tid + 256 * q, S_n - 1)];
 #pragma unroll
-  for (uint32_t q = 0; q < PER; ++q) {
-    vv[q] = v[jj[q]];
-    dd[q] = dv[jj[q]];
-    sc[q] = a.score != nullptr ? a.score[jj[q]] : 1.f;
-  }
-#pragma unroll
-  for (uint32_t q = 0; q < PER; ++q) {
-    const uint32_t i = tid + 256 * q;
-    if (i < S_n) keys[i] = sel_key_loaded<ST>(a, vv[q], dd[q], sc[q]);
-  }
+  for (uint32_t q = 0; q < PER; ++q)
+    if (tid + 256 * q < S_n) keys[tid + 256 * q] = kk[q];
   __syncthreads();
   const uint32_t lane = tid & 63, wave = tid >> 6;
   const uint32_t mine_i = min(blockIdx.x * 64 + lane, S_n - 1);

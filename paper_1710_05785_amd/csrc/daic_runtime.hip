@@ -107,7 +107,8 @@ struct Impl {
       uint32_t S = o->n_samples ? o->n_samples : kMaxSamples;
       uint32_t rank = (uint32_t)std::max(1.0, std::ceil(o->priority_fraction * (double)S));
       launch(pr, "sample_threshold", s, [&] {
-        hipLaunchKernelGGL(k_sample<ST>, dim3((S + 63) / 64), dim3(256), 0, s, a, S, rank, o->seed, round_override);
+        hipLaunchKernelGGL(k_sample_keys<ST>, dim3((S + 255) / 256), dim3(256), 0, s, a, S, o->seed, round_override);
+        hipLaunchKernelGGL(k_sample<ST>, dim3((S + 63) / 64), dim3(256), 0, s, a, S, rank);
       });
     } else {  // exact top-k (also the learned rule, on the learned keys)
       uint64_t k = (uint64_t)std::ceil(o->priority_fraction * (double)n);
@@ -604,6 +605,7 @@ daic_status daic_problem_create(const daic_graph* g, daic_op op, daic_g gk, doub
   GRAB(blk_large, uint32_t*, nb * 4);
   GRAB(blk_ties, uint32_t*, nb * 4);
   GRAB(rhist, uint32_t*, kRadixBins * kRadixCopies * 4);
+  GRAB(skeys, uint64_t*, kMaxSamples * 8);
   GRAB(off_small, uint64_t*, (nb + 1) * 8);
   GRAB(off_large, uint64_t*, (nb + 1) * 8);
   GRAB(off_ties, uint64_t*, (nb + 1) * 8);
