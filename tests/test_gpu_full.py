@@ -14,10 +14,10 @@ benchmark runs them (captured groups of rounds, the default launch shapes).
   same FP64 oracle result (relative L1 <= 1e-5), SSSP (weights U{1..255},
   seed 7, source 0) bit-exact against the oracle's Dijkstra.
 * Batched personalized PageRank, 64 RMAT graphs of scale U{12..20} with edge
-  factor 8, 64 right-hand sides each (4,096 instances, d = 0.85, FP32 + Kahan,
-  residual 1e-6 per instance): one instance per graph, each against the
-  oracle's FP64 iteration with the same personalization vector (relative
-  L1 <= 1e-5).
+  factor 8, 64 right-hand sides each (4,096 instances, d = 0.85, FP32 deltas
+  with the Kahan-compensated or the plain FP32 state, residual 1e-6 per
+  instance): one instance per graph, each against the oracle's FP64
+  iteration with the same personalization vector (relative L1 <= 1e-5).
 """
 import sys
 
@@ -141,13 +141,14 @@ def test_learned_scheduler_full_config(daic, g24, pr24_ref):
 
 
 @pytest.mark.timeout(900)
-def test_batched_ppr_full_config_sampled_instances(daic):
-    say("case batched ppr full: generate")
+@pytest.mark.parametrize("state", ["f32_kahan", "f32"])
+def test_batched_ppr_full_config_sampled_instances(daic, state):
+    say("case batched ppr full: generate", state)
     d, rhs, eps = 0.85, 64, 1e-6
     scales = daic_gen.batch_scales()
     gs = [daic_gen.rmat(int(s), 8, seed=1000 + i) for i, s in enumerate(scales)]
     assert len(gs) == 64
-    b = daic.Batch([daic.Graph(g.row_ptr, g.col) for g in gs], rhs, alpha=d, state="f32_kahan")
+    b = daic.Batch([daic.Graph(g.row_ptr, g.col) for g in gs], rhs, alpha=d, state=state)
     inits = []
     for i, g in enumerate(gs):
         counts, seeds = daic_gen.ppr_seeds(g, 6, i * rhs, rhs, 32)
