@@ -99,7 +99,7 @@ def test_pagerank_matches_dense_solve(seed):
         assert np.abs(v - want).sum() <= 1e-12 * g.n
 
 
-def test_pagerank_north_star_normalization():
+def test_pagerank_normalized_linear_system():
     """(I - d W^T) x = (1-d)/n 1 is the paper's solution divided by n."""
     g = daic_gen.powerlaw(n=300, seed=11)
     d = 0.8
