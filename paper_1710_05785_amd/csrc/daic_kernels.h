@@ -1,12 +1,18 @@
 // Device code of one DAIC round on gfx950 (64-lane wavefronts).
 //
 // A round (Eq. async of the paper applied to a selected set, Sec. 3.2/3.4):
-//   A2 k_sample / k_radix_* : threshold of the priority keys (sampled or exact)
+//   A2 k_sample_keys + k_sample, or k_radix_pass + k_radix_pick per digit
+//                           : threshold of the priority keys (sampled or exact)
 //   A3+A4 k_claim           : select, claim dv_j, fold v_j (+)= delta, compute
 //                             the message base mu_j, compact into degree bins
+//                             (sparse rounds) or publish mu_j (dense rounds)
 //   k_bin_scan              : prefix of the per-block bin counts
 //   A5 k_push_small/large   : atomic (+) of g(mu_j) into dv_k for every out-edge
-//   A1 k_residual           : residual of the new state and the stop rule
+//      k_pull_stream        : dense rounds: every target sums its in-neighbours'
+//                             bases (then k_pull_finish: residual and stop rule)
+//   A1 k_residual + k_residual_final : residual of the new state and the stop rule
+// Fused dense rounds (every pending vertex, sum problems): k_pull_fused +
+// k_fused_finish per round after one priming claim.
 // The claim happens in a kernel of its own, before any push of the round, so
 // every message of the round lands in dv after the claim: it is folded in a
 // later round and never lost (the receive/update split of Eq. async).
