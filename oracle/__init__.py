@@ -22,6 +22,11 @@ Contents
 * ``priority``       -- |v (+) dv - v| per vertex (Sec. 3.4 and Table 1 rows).
 * ``sampled_threshold`` / ``topk_exact`` -- the two selection rules of a round.
 * ``mlp_*``          -- FP64 forward/backward of the scheduler network.
+* ``adam_step``      -- one Adam update (Kingma and Ba 2015) in FP64.
+* ``trace_exact_topk`` -- rounds of exact top-k scheduling on an integer
+  (min or max) problem with the learned scheduler's training samples: the
+  features of sampled vertices and the label "not pending again within H
+  rounds" (numpy).
 
 Parity status: every function here is pinned by tests under ``tests/`` except
 the ones listed as "parity unpinned" in their docstrings.
@@ -385,3 +390,147 @@ def mlp_backward(params, cache, logits, y):
     g["W1"] = dz1.T @ x
     g["b1"] = dz1.sum(0)
     return g
+
+
+def adam_step(w, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba 2015) in FP64 with bias correction:
+    m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
+    w <- w - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+    t counts steps from 1. Returns (w, m, v) as new arrays."""
+    w = np.asarray(w, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    return w - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# Sample stream of traced rounds: SplitMix64 seeded with (seed XOR this value),
+# a stream apart from the one of the sampled selection rule.
+TRACE_SEED_XOR = 0x7A3E5C91
+
+
+def _prio_f32(op, v, dv):
+    """The priority as an FP32 number, as the learned features take it: the
+    integer priority of ``priority`` rounded to FP32 (a first reach of a min
+    problem counts as 0xFFFFFFFF, which rounds to 2^32)."""
+    return priority(op, v, dv).astype(np.float32)
+
+
+def trace_exact_topk(g, op, v0, dv1, q, samples_per_round, horizon, seed, w=None,
+                     max_rounds=4096):
+    """Rounds of exact top-k priority scheduling on an integer problem (op =
+    OP_MIN with g(x) = x + w_jk saturating at 0xFFFFFFFF, uint32 state; or
+    OP_MAX with g(x) = x, int32 state), recording the learned scheduler's
+    training samples. Sec. 3.5 (priority scheduling), Eq. async (update);
+    the trace rule itself is not in the paper.
+
+    Round t (t = 0, 1, ...) runs while some vertex is pending and t <
+    max_rounds:
+      1. S = samples_per_round vertices are drawn: sample i is output
+         t S + i of SplitMix64(seed XOR TRACE_SEED_XOR), mod n. For each its
+         features at the start of the round are taken:
+         [log2(p + 1e-30), log2((1 + indeg) / (1 + outdeg)),
+          min(rounds since its last update, 64) / 64] in FP32, where p is the
+         priority and a vertex never updated counts as updated in round -1.
+      2. The round selects the k = ceil(q n) largest priorities among the
+         pending vertices (ties to the smaller id; all pending when fewer),
+         claims every selected delta (dv_j becomes the identity, v_j takes the
+         delta when it improves v_j), then sends g_jk(delta) along every
+         out-edge of each improved vertex, combined into dv_k with (+).
+    A sample counts when its vertex was pending and selected in its round. Its
+    label is 0 ("premature") when the vertex is pending at the start of any of
+    the next `horizon` rounds (the state after the last round standing for
+    every later start), else 1. Labels are given for every sampled round when
+    the run ends with nothing pending, otherwise for rounds t < T - horizon.
+
+    Returns dict(x [N,3] float32, y [N] float32, vid, round, value (the value
+    the update stored in v), rounds T, v, dv)."""
+    n = g.n
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    col = np.asarray(g.col, dtype=np.int64)
+    outdeg = np.diff(rp)
+    indeg = np.bincount(col, minlength=n)
+    S, H = int(samples_per_round), int(horizon)
+    if op == OP_MIN:
+        v = np.array(v0, dtype=np.uint32, copy=True)
+        dv = np.array(dv1, dtype=np.uint32, copy=True)
+        wu = np.asarray(w, dtype=np.uint64)
+    elif op == OP_MAX:
+        v = np.array(v0, dtype=np.int32, copy=True)
+        dv = np.array(dv1, dtype=np.int32, copy=True)
+    else:
+        raise ValueError("trace_exact_topk takes the integer problems (min, max)")
+    last = np.full(n, -1, dtype=np.int64)           # round of the last update, -1 = none
+    k = int(np.ceil(q * n))
+    f1 = np.log2((np.float32(1) + indeg.astype(np.float32)) /
+                 (np.float32(1) + outdeg.astype(np.float32))).astype(np.float32)
+    rec = []                                        # per round: vid, feat, p0, sel, value
+    pend_hist = []                                  # pending mask at the start of each round
+    t = 0
+    while t < max_rounds:
+        p = priority(op, v, dv)
+        pending = p > 0
+        if not pending.any():
+            break
+        pend_hist.append(pending.copy())
+        # 1. samples and their features
+        c = np.uint64(t) * np.uint64(S) + np.arange(S, dtype=np.uint64)
+        vid = (splitmix64(seed ^ TRACE_SEED_XOR, c) % np.uint64(n)).astype(np.int64)
+        pf = _prio_f32(op, v, dv)[vid]
+        since = t - last[vid]
+        feat = np.stack([np.log2(pf + np.float32(1e-30)), f1[vid],
+                         (np.minimum(since, 64).astype(np.float32) * np.float32(1.0 / 64.0))],
+                        axis=1).astype(np.float32)
+        # 2. the round: select, claim, send
+        sel = topk_exact(p, q) if pending.sum() > k else np.flatnonzero(pending)
+        delta = dv[sel].copy()
+        if op == OP_MIN:
+            dv[sel] = INF_U32
+            improves = delta < v[sel]
+        else:
+            dv[sel] = -1
+            improves = delta > v[sel]
+        v[sel[improves]] = delta[improves]
+        last[sel] = t
+        senders = sel[improves]
+        for j, d in zip(senders, delta[improves]):
+            e0, e1 = rp[j], rp[j + 1]
+            if op == OP_MIN:
+                if int(d) == INF_U32:
+                    continue
+                msg = np.minimum(np.uint64(d) + wu[e0:e1], np.uint64(INF_U32)).astype(np.uint32)
+                np.minimum.at(dv, col[e0:e1], msg)
+            else:
+                np.maximum.at(dv, col[e0:e1], np.int32(d))
+        chosen = np.zeros(n, dtype=bool)
+        chosen[sel] = True
+        rec.append((vid, feat, pending[vid], chosen[vid], v[vid].copy()))
+        t += 1
+    T = t
+    final_pending = priority(op, v, dv) > 0
+    done = not final_pending.any()
+    full = T if done else max(T - H, 0)
+    xs, ys, vids, rounds, vals = [], [], [], [], []
+    for r in range(full):
+        vid, feat, p0, chosen, val = rec[r]
+        for i in range(S):
+            if not (p0[i] and chosen[i]):
+                continue
+            j = vid[i]
+            again = False
+            for s in range(r + 1, r + H + 1):
+                mask = pend_hist[s] if s < T else final_pending
+                if mask[j]:
+                    again = True
+                    break
+            xs.append(feat[i])
+            ys.append(0.0 if again else 1.0)
+            vids.append(j)
+            rounds.append(r)
+            vals.append(val[i])
+    x = np.array(xs, dtype=np.float32).reshape(-1, 3)
+    return dict(x=x, y=np.array(ys, dtype=np.float32), vid=np.array(vids, dtype=np.int64),
+                round=np.array(rounds, dtype=np.int64), value=np.array(vals), rounds=T, v=v,
+                dv=dv)

@@ -581,6 +581,22 @@ def test_sampled_threshold_properties():
     assert oracle.sampled_threshold(p2, 0.01, 64, 1, 0) == 1.0
 
 
+def test_golden_sampled_threshold_rank():
+    """The rank rule of the sampled threshold, by hand: ceil(q S)-th largest,
+    ranked from 1 (floor, or a rank counted from 0, fail one of the cases)."""
+    gd = read_golden("sampled_threshold_10.txt")
+    n, S, seed = int(gd["n"][0]), int(gd["S"][0]), int(gd["seed"][0])
+    p = np.array(list(map(float, gd["prio"])))
+    for t in (0, 1):
+        np.testing.assert_array_equal(oracle.sample_indices(n, S, seed, t),
+                                      list(map(int, gd[f"ids_round{t}"])))
+    for key, vals in gd.items():
+        if key.startswith("tau_round"):
+            t = int(key[len("tau_round")])
+            q = float(key.split("_q")[1])
+            assert oracle.sampled_threshold(p, q, S, seed, t) == float(vals[0]), key
+
+
 # ---------------------------------------------------------------------------
 # Scheduler network
 # ---------------------------------------------------------------------------
@@ -623,3 +639,98 @@ def test_generators_are_deterministic_and_shaped():
     for j in range(pl.n):  # no self-loop, no duplicate per source
         row = pl.col[pl.row_ptr[j]:pl.row_ptr[j + 1]]
         assert j not in row and len(set(row.tolist())) == len(row)
+
+
+def test_golden_adam_steps():
+    """Adam by hand: a constant gradient moves w by exactly -lr g / (|g| + eps)
+    per step (bias-corrected moments equal g and g^2); a sign flip gives
+    w2 = -0.1 (18/19) / (1 + eps). A dropped bias correction, a swapped beta
+    or a missing square fails one of them."""
+    gd = read_golden("adam_steps.txt")
+    w, m, v = np.array([float(gd["const_w0"][0])]), np.zeros(1), np.zeros(1)
+    g = np.array([float(gd["const_g"][0])])
+    for t in range(1, int(gd["const_steps"][0]) + 1):
+        w, m, v = oracle.adam_step(w, g, m, v, t, float(gd["const_lr"][0]))
+    np.testing.assert_allclose(w, float(gd["const_w"][0]), rtol=0, atol=1e-15)
+    lr = float(gd["flip_lr"][0])
+    w, m, v = oracle.adam_step(np.zeros(1), np.ones(1), np.zeros(1), np.zeros(1), 1, lr)
+    np.testing.assert_allclose(w, float(gd["flip_w1"][0]), rtol=0, atol=1e-15)
+    w, m, v = oracle.adam_step(w, -np.ones(1), m, v, 2, lr)
+    np.testing.assert_allclose(w, float(gd["flip_w2"][0]), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Trace rule of the learned scheduler (exact top-k rounds, integer problems)
+# ---------------------------------------------------------------------------
+
+def _golden_trace():
+    gd = {}
+    ups = []
+    with open(os.path.join(GOLDEN, "trace_sssp_4node.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            key, *vals = line.split()
+            if key == "update":
+                ups.append(vals)
+            else:
+                gd[key] = vals
+    return gd, ups
+
+
+@pytest.mark.parametrize("H", [1, 4])
+def test_golden_trace_sssp_4node(H):
+    """Features and labels of every sampled update against the hand-worked
+    4-vertex run; the emitted samples are exactly the sampled vertices that
+    were selected in their round (once per draw)."""
+    gd, ups = _golden_trace()
+    n = int(gd["n"][0])
+    e = list(map(int, gd["edges"]))
+    g = daic_gen.from_edges(n, e[0::3], e[1::3])
+    order = np.lexsort((e[1::3], e[0::3]))  # the CSR keeps edges sorted by source
+    w = np.array(e[2::3], dtype=np.uint32)[order]
+    np.testing.assert_array_equal(g.col, np.array(e[1::3])[order])
+    v0, dv1 = oracle.sssp_init(n, int(gd["source"][0]))
+    S, seed = 16, 5
+    r = oracle.trace_exact_topk(g, oracle.OP_MIN, v0, dv1, float(gd["q"][0]), S, H, seed, w=w)
+    assert r["rounds"] == int(gd["rounds"][0])
+    np.testing.assert_array_equal(r["v"], list(map(int, gd["dist"])))
+    want = {(int(u[0]), int(u[1])): u for u in ups}
+    expect_count = 0
+    for t in range(r["rounds"]):
+        ids = oracle.sample_indices(n, S, seed ^ oracle.TRACE_SEED_XOR, t)
+        expect_count += sum(1 for j in ids if (t, int(j)) in want)
+    assert len(r["y"]) == expect_count
+    for i in range(len(r["y"])):
+        u = want[(int(r["round"][i]), int(r["vid"][i]))]
+        np.testing.assert_allclose(r["x"][i], np.array(u[2:5], dtype=np.float64), rtol=1e-6,
+                                   atol=1e-7)
+        assert r["y"][i] == float(u[5] if H == 4 else u[6])
+        assert r["value"][i] == int(u[7])
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_trace_labels_match_final_values(seed):
+    """With a horizon past the run's end, an update is labelled 1 exactly when
+    the value it stored is the vertex's final value: Dijkstra distances (min)
+    and max-label reachability (max), both computed independently. A label
+    window off by one round, or a stale pending test, breaks this."""
+    rng = np.random.default_rng(seed)
+    n = 60
+    src, dst = rng.integers(0, n, 240), rng.integers(0, n, 240)
+    g = daic_gen.from_edges(n, src, dst)
+    w = rng.integers(1, 30, g.m).astype(np.uint32)
+    v0, dv1 = oracle.sssp_init(n, 0)
+    r = oracle.trace_exact_topk(g, oracle.OP_MIN, v0, dv1, 0.3, 64, 64, seed, w=w)
+    assert r["rounds"] < 64
+    dist = oracle.dijkstra(g, w, 0)
+    np.testing.assert_array_equal(r["v"], dist)
+    assert len(r["y"]) > 20
+    np.testing.assert_array_equal(r["y"], (r["value"] == dist[r["vid"]]).astype(np.float32))
+    v0, dv1 = oracle.cc_init(n)
+    r = oracle.trace_exact_topk(g, oracle.OP_MAX, v0, dv1, 0.3, 64, 64, seed)
+    assert r["rounds"] < 64
+    lab = oracle.maxlabel(g)
+    np.testing.assert_array_equal(r["v"], lab)
+    np.testing.assert_array_equal(r["y"], (r["value"] == lab[r["vid"]]).astype(np.float32))
