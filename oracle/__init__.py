@@ -355,14 +355,19 @@ def sampled_threshold(p, q, n_samples, seed, round_no):
 # Scheduler network: 3 -> 64 -> 64 -> 1, ReLU, BCE-with-logits, FP64.
 # ---------------------------------------------------------------------------
 
-def mlp_forward(params, x):
+def mlp_forward(params, x, rnd=None):
     """Returns (logits[N], cache). params = dict(W1[64,3], b1[64], W2[64,64],
-    b2[64], W3[1,64], b3[1]); x = [N, 3]."""
+    b2[64], W3[1,64], b3[1]); x = [N, 3]. rnd (optional) is applied to the
+    hidden activations after each ReLU: a kernel that rounds them to a
+    narrower type (BF16 between MFMA layers) is compared with this function
+    given that rounding, so that both take their ReLU decisions on the same
+    values; rnd = None is the plain FP64 network."""
+    r = (lambda a: a) if rnd is None else rnd
     x = np.asarray(x, dtype=np.float64)
     z1 = x @ params["W1"].T + params["b1"]
-    h1 = np.maximum(z1, 0.0)
+    h1 = r(np.maximum(z1, 0.0))
     z2 = h1 @ params["W2"].T + params["b2"]
-    h2 = np.maximum(z2, 0.0)
+    h2 = r(np.maximum(z2, 0.0))
     z3 = h2 @ params["W3"].T + params["b3"]
     return z3[:, 0], (x, z1, h1, z2, h2)
 
@@ -374,8 +379,13 @@ def bce_with_logits(logits, y):
     return float(np.mean(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
 
 
-def mlp_backward(params, cache, logits, y):
-    """Gradients of the mean BCE-with-logits loss w.r.t. every parameter."""
+def mlp_backward(params, cache, logits, y, rnd=None):
+    """Gradients of the mean BCE-with-logits loss w.r.t. every parameter.
+    rnd (optional) is applied to the back-propagated deltas where they enter
+    a product (dZ2 before dH1 = dZ2 W2 and dW2 = dZ2^T H1; dZ1 before
+    dW1 = dZ1^T X), as a kernel with BF16 product operands does; the bias
+    gradients take the unrounded deltas."""
+    r = (lambda a: a) if rnd is None else rnd
     x, z1, h1, z2, h2 = cache
     n = x.shape[0]
     y = np.asarray(y, dtype=np.float64)
@@ -383,12 +393,13 @@ def mlp_backward(params, cache, logits, y):
     g = {"W3": dz3.T @ h2, "b3": dz3.sum(0)}
     dh2 = dz3 @ params["W3"]
     dz2 = dh2 * (z2 > 0)
-    g["W2"] = dz2.T @ h1
     g["b2"] = dz2.sum(0)
-    dh1 = dz2 @ params["W2"]
+    rdz2 = r(dz2)
+    g["W2"] = rdz2.T @ h1
+    dh1 = rdz2 @ params["W2"]
     dz1 = dh1 * (z1 > 0)
-    g["W1"] = dz1.T @ x
     g["b1"] = dz1.sum(0)
+    g["W1"] = r(dz1).T @ x
     return g
 
 

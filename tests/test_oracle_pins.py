@@ -734,3 +734,42 @@ def test_trace_labels_match_final_values(seed):
     lab = oracle.maxlabel(g)
     np.testing.assert_array_equal(r["v"], lab)
     np.testing.assert_array_equal(r["y"], (r["value"] == lab[r["vid"]]).astype(np.float32))
+
+
+def test_mlp_rounding_hook():
+    """The optional rounding of activations and deltas: with values that the
+    rounding keeps (small integers and halves in BF16) it changes nothing;
+    with BF16 rounding of random values it moves the logits by at most a few
+    BF16 units of the absolute-value network (three rounding points)."""
+    def bf16(a):
+        a = np.asarray(a, dtype=np.float32)
+        u = a.view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+        return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+    rng = np.random.default_rng(4)
+    P = {"W1": rng.integers(-2, 3, (64, 3)).astype(float), "b1": rng.integers(-1, 2, 64) * 0.5,
+         "W2": rng.integers(-1, 2, (64, 64)) * (rng.random((64, 64)) < 0.1),
+         "b2": rng.integers(-1, 2, 64) * 0.5,
+         "W3": rng.integers(-1, 2, (1, 64)).astype(float), "b3": np.array([0.5])}
+    x = rng.integers(-1, 2, (40, 3)).astype(float)
+    y = (rng.random(40) < 0.5).astype(float)
+    P["W2"] = P["W2"].astype(float)
+    z0, c0 = oracle.mlp_forward(P, x)
+    z1, c1 = oracle.mlp_forward(P, x, rnd=bf16)
+    assert np.abs(c0[4]).max() < 128 and np.any(c0[4] > 0)  # every activation exact in BF16
+    np.testing.assert_array_equal(z0, z1)
+    # logits are integers and halves here; the gradient's deltas are not, so
+    # compare only the forward and the layer-3 terms that see no rounded delta
+    g0 = oracle.mlp_backward(P, c0, z0, y)
+    g1 = oracle.mlp_backward(P, c1, z1, y, rnd=bf16)
+    for k in ("W3", "b3", "b2"):
+        np.testing.assert_array_equal(g0[k], g1[k])
+    Q = {k: rng.normal(0, 0.5, v.shape) for k, v in P.items()}
+    xr = rng.normal(0, 1, (200, 3))
+    za, _ = oracle.mlp_forward(Q, xr)
+    zb, _ = oracle.mlp_forward(Q, xr, rnd=bf16)
+    A = {k: np.abs(v) for k, v in Q.items()}
+    zabs, _ = oracle.mlp_forward(A, np.abs(xr))
+    assert np.all(np.abs(za - zb) <= 2.0 ** -7 * zabs)
+    assert np.any(za != zb)
