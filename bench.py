@@ -391,7 +391,7 @@ def learned_form(daic, torch, g24, eps, rounds_per_check):
 
 def ablation(daic, torch):
     """Synchronous vs round-robin vs priority scheduling on one GPU (the
-    paper's update-count comparison, Sec. 6.4): progress metric against the
+    paper's update-count comparison, Sec. 6.3): progress metric against the
     number of vertex updates, and time to the stop rule."""
     import numpy as np
 

@@ -11,7 +11,7 @@
  *     distributive over (+) (second condition), and initial values that meet
  *     the fourth condition v^0 (+) dv^1 = f(v^0).
  *   - One round applies the asynchronous update of Eq. async (Sec. 3.2) to the
- *     vertices chosen by priority |v_j (+) dv_j - v_j| (Sec. 3.4):
+ *     vertices chosen by priority |v_j (+) dv_j - v_j| (Sec. 3.5):
  *        delta = dv_j;  dv_j = 0;  v_j = v_j (+) delta;
  *        for every out-edge (j,k): dv_k = dv_k (+) g_{j,k}(delta)   [skip if = 0]
  *     The chosen set is the top portion q of the state table (Sec. 5.1,
@@ -89,7 +89,7 @@ typedef enum {
   DAIC_NONE = 5
 } daic_dtype;
 
-/* Selection rule of a round (Sec. 3.4 priority scheduling, Sec. 5.1 queue).
+/* Selection rule of a round (Sec. 3.5 priority scheduling, Sec. 5.1 queue).
  *   ALL          : every pending vertex (a synchronous DAIC round, Eq. sync)
  *   TOPK_EXACT   : the ceil(q n) largest priorities, ties to the smaller id
  *   TOPK_SAMPLED : threshold = ceil(q S)-th largest of S sampled priorities
@@ -97,9 +97,9 @@ typedef enum {
  *   ROUND_ROBIN  : the pending vertices of the next block of ceil(q n)
  *                  consecutive ids, blocks taken cyclically (static order,
  *                  Sec. 5.1 round-robin scheduling)
- *   SWEEP        : round-robin over blocks of ceil(q n) vertices taken in
- *                  out-degree order (highest first), every pending vertex of
- *                  the block updated, each block receiving by a pull over
+ *   SWEEP        : round-robin over blocks of ceil(q n) consecutive ids
+ *                  (block c holds ids [c B, (c + 1) B)), every pending vertex
+ *                  of the block updated, each block receiving by a pull over
  *                  its in-edges the latest message of every in-neighbour, so
  *                  that blocks later in a sweep already see the updates made
  *                  earlier in it (an asynchronous activation order, Eq. async;
@@ -191,6 +191,40 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* opts, daic_stats* sta
 daic_status daic_problem_get(const daic_problem* p, void* v_out, void* dv_out);
 void daic_problem_destroy(daic_problem* p);
 
+/* ---- Fourth condition (Sec. 3.1) -----------------------------------------
+ * The initial values must satisfy v0_j (+) dv1_j = f(v0)_j, with f the
+ * update function of Eq. decompose: f(v)_j = (+)_{i->j} g_{i,j}(v_i) (+) c_j.
+ * The library is given (g, (+), v0, dv1) but not c, so the check needs it:
+ * daic_problem_set_const copies c (n host values: double for FP states,
+ * uint32 for U32, int32 for I32). daic_problem_check_init then checks the
+ * problem's current state on the device (the identity also holds at every
+ * state a run leaves, since all messages are then delivered): exact for
+ * min/max problems; for sum problems |lhs - rhs| <= tol x (|c_j| + sum of
+ * |g_ij(v_i)| + |v_j| + |dv_j|), tol 0 meaning 1e-12 (F64) or 1e-5 (FP32
+ * states). It returns DAIC_E_INVALID when some vertex fails (count in
+ * *mismatches, nullable; first vertex in daic_last_error) and also when no
+ * constant was given. With the environment variable DAIC_CHECK_INIT set,
+ * daic_run performs this check on its starting state first and returns its
+ * failure without running. The check allocates device scratch per call (a
+ * debug path).                                                              */
+daic_status daic_problem_set_const(daic_problem* p, const void* c);
+daic_status daic_problem_check_init(daic_problem* p, double tol, uint64_t* mismatches);
+
+/* ---- Checkpoint / resume (the snapshots of the state table of Sec. 5.1) ---
+ * daic_problem_save writes the problem's state (v, dv and, for F32_KAHAN,
+ * the compensation term, all bit-exact) into buf; with buf NULL it writes
+ * the size needed to *len, and with *len too small it fails (DAIC_E_INVALID,
+ * size needed in *len). Layout, little-endian: "DAICPRB1", uint32 version 1,
+ * uint32 state type, uint64 n, uint64 m, uint32 op, uint32 g kind, double
+ * alpha, uint64 payload bytes, then v[n], dv[n] in the device element type
+ * (8 bytes for F64 states, 4 otherwise) and c[n] (FP32, F32_KAHAN only).
+ * daic_problem_load restores such a buffer into a problem of the same kind
+ * (op, g, state type, alpha, n, m; anything else is DAIC_E_INVALID). A state
+ * saved after daic_run (which returns with every message delivered, also at
+ * max_rounds) resumes the same computation: the next daic_run continues it. */
+daic_status daic_problem_save(const daic_problem* p, void* buf, size_t* len);
+daic_status daic_problem_load(daic_problem* p, const void* buf, size_t len);
+
 const char* daic_last_error(void);
 
 /* ---- Device-side round pieces, exposed for unit tests --------------------
@@ -239,6 +273,23 @@ daic_status daic_batch_run(daic_batch* b, const daic_run_opts* opts, daic_stats*
                            double* inst_residual);
 /* v_out: [n_g][rhs_g] doubles (FP32 state; with Kahan, v - c). */
 daic_status daic_batch_get(const daic_batch* b, uint32_t graph, double* v_out);
+/* The state of one graph's instances, each output nullable: v_out and dv_out
+ * [n_g][rhs_g] doubles, done_out [rhs_g] finish states (0 running, 1
+ * finished with its last messages in flight, 2 finished and delivered). */
+daic_status daic_batch_get_state(const daic_batch* b, uint32_t graph, double* v_out, double* dv_out,
+                                 uint8_t* done_out);
+/* Snapshot of the whole batch for checkpoint and resume, bit-exact, with the
+ * size protocol of daic_problem_save. Layout, little-endian: "DAICBAT1",
+ * uint32 version 1, uint32 G, uint64 N (union vertices), uint32 Kahan flag,
+ * uint32 weighted flag, double alpha, uint64 payload bytes; per graph uint64
+ * n_g, uint32 rhs_g, uint32 0; then v, dv and (Kahan) c as [N][64] FP32 and
+ * the finish states [G][64] uint8. daic_batch_load restores it into a batch
+ * built from graphs of the same sizes with the same right-hand-side counts,
+ * state type, weights flag and alpha. A batch run stopped by max_rounds ends
+ * with every message delivered, so a saved state resumes with
+ * daic_batch_run. */
+daic_status daic_batch_save(const daic_batch* b, void* buf, size_t* len);
+daic_status daic_batch_load(daic_batch* b, const void* buf, size_t len);
 void daic_batch_destroy(daic_batch* b);
 
 /* ---- Learned scheduler ----------------------------------------------------
@@ -264,7 +315,8 @@ void daic_sched_destroy(daic_sched_model* m);
  * BF16 MFMA kernels: for checking against a reference. grad: 4481 floats. */
 daic_status daic_mlp_forward(const daic_sched_model* m, const float* x, uint64_t N, float* logits);
 /* The scoring kernel of a learned round, exposed for unit tests: on the
- * problem's current state at round 0 (every vertex last updated at round 0),
+ * problem's current state at round 0 with no vertex updated yet (so every
+ * vertex is one round past its last update, counted at round -1),
  * writes each vertex's selection multiplier to score_out (n host floats):
  * sigmoid(logit) of its standardized features for pending vertices, 0 for
  * the others. The problem's state is not changed.                          */
@@ -272,18 +324,32 @@ daic_status daic_sched_score(daic_problem* p, const daic_sched_model* m, float* 
 daic_status daic_mlp_grad(const daic_sched_model* m, const float* x, const float* y, uint64_t N,
                           float* grad, double* loss /* nullable */);
 
-/* Trace capture: runs exact top-k rounds (opts->sched = TOPK_EXACT) from the
- * problem's current state to its stop rule (or max_rounds, at most 4096),
- * sampling samples_per_round vertices per round with SplitMix64. A sampled
- * vertex updated in round t becomes one training sample: its features at t
- * and label 1, or 0 when the update was premature: within the next horizon
- * rounds its priority reached half its priority at t (sum problems) or it
- * became pending again (min/max problems). The problem ends converged.     */
+/* Trace capture: runs exact top-k rounds (opts->sched = TOPK_EXACT, the
+ * priority scheduling of Sec. 3.5) from the problem's current state to its
+ * stop rule (or max_rounds, at most 4096). In round t, S = samples_per_round
+ * vertices are drawn before the round (sample i is output t S + i of
+ * SplitMix64 seeded with opts->seed XOR 0x7A3E5C91, mod n) with their raw
+ * features at that moment; a vertex never updated counts as last updated in
+ * round -1. A sampled vertex that was pending and is updated by round t
+ * becomes one training sample (once per draw): its features and label 1, or
+ * 0 when the update was premature: at the start of one of the next `horizon`
+ * rounds (the state after the last round standing for every later start) its
+ * priority reached half its priority at t (sum problems) or it was pending
+ * again (min/max problems). Samples of the last `horizon` rounds are dropped
+ * unless the run ended converged. Samples are ordered by round, then draw.
+ * The problem ends converged (or at max_rounds). samples_per_round in
+ * 1..2^20, horizon in 1..64.                                                  */
 daic_status daic_trace_record(daic_problem* p, const daic_run_opts* opts, uint32_t samples_per_round,
                               uint32_t horizon, daic_trace** out);
 /* Copies the samples out: x [n][3] raw features, y [n]; *n = sample count.
  * x and y may be NULL to query n. */
 daic_status daic_trace_get(const daic_trace* tr, float* x, float* y, uint64_t* n);
+/* Vertex and round of each sample of a recorded trace (n of each; NULL to
+ * query n; a trace made by daic_trace_create has none: *n = 0). */
+daic_status daic_trace_samples(const daic_trace* tr, uint32_t* vid, uint32_t* round, uint64_t* n);
+/* A trace from caller samples: x [n][3] raw features (finite), y [n] labels in
+ * {0, 1}; both copied. For training on samples gathered elsewhere. */
+daic_status daic_trace_create(const float* x, const float* y, uint64_t n, daic_trace** out);
 void daic_trace_destroy(daic_trace* tr);
 
 typedef struct {
@@ -301,12 +367,32 @@ typedef struct {
   uint32_t epochs;
 } daic_train_stats;
 /* Trains m on the union of the traces on the device (BF16 MFMA gradients,
- * FP32 Adam); sets the model's feature standardization from the samples. */
+ * FP32 Adam); sets the model's feature standardization from the samples
+ * (mean and population standard deviation in FP64, kept as FP32, scale at
+ * least 1e-6), shuffles them with a seeded Fisher-Yates and takes minibatch
+ * steps as daic_sched_step does. */
 daic_status daic_sched_train(const daic_trace* const* traces, uint32_t n_traces,
                              const daic_train_opts* opts, daic_sched_model* m,
                              daic_train_stats* stats);
+/* One training step of m on host samples x [N][3] (already standardized) and
+ * labels y [N]: the gradient of the mean BCE-with-logits loss on the BF16
+ * MFMA kernels, then one Adam step (Kingma and Ba 2015; beta1 0.9, beta2
+ * 0.999, eps 1e-8, bias-corrected, FP32 moments and master weights; the step
+ * count is kept in the model). grad_out (nullable, 4481 floats) receives the
+ * gradient applied, loss (nullable) the mean loss before the step. Exposed
+ * for checking the trainer against a reference. */
+daic_status daic_sched_step(daic_sched_model* m, const float* x, const float* y, uint64_t N, float lr,
+                            float* grad_out, double* loss);
+/* Serialization of a model: FP32 master weights, both Adam moments, the Adam
+ * step count and the feature standardization, in a versioned little-endian
+ * buffer ("DAICSCH1", version 1, 53,820 bytes). daic_sched_save with buf NULL
+ * writes the size to *len; with *len too small it fails (DAIC_E_INVALID) and
+ * writes the size needed. daic_sched_load checks the magic, version, size and
+ * that every value is finite (scales positive) and makes a new model. */
+daic_status daic_sched_save(const daic_sched_model* m, void* buf, size_t* len);
+daic_status daic_sched_load(const void* buf, size_t len, daic_sched_model** out);
 
-/* Progress trace for update-count studies (Sec. 6.4): runs like daic_run,
+/* Progress trace for update-count studies (Sec. 6.3): runs like daic_run,
  * one round at a time, and after every round records the cumulative number
  * of vertex updates and the progress metric sum_j v_j (sum problems: in
  * FP64; min problems: over finite values; max problems: over all values).

@@ -12,14 +12,14 @@ Contents
 * ``jacobi_sum``     -- traditional synchronous iteration (Eq. concurrent in the
   form of Eq. decompose), FP64 pull over in-edges (C, OpenMP).
 * ``sync_daic_sum``  -- synchronous DAIC, Eq. sync (C, one thread).
-* ``async_run``      -- asynchronous DAIC, Eq. async, with priority (Sec. 3.4)
+* ``async_run``      -- asynchronous DAIC, Eq. async, with priority (Sec. 3.5)
   or round-robin (Sec. 5.1) scheduling, for sum, min and max (C, one thread).
 * ``sweep_blocks``   -- asynchronous DAIC in blocks of B consecutive ids taken
   round-robin, each block updated together (numpy).
 * ``dijkstra``       -- SSSP distances, the min problem's textbook answer.
 * ``dijkstra_f64``   -- the same for real non-negative weights (Python heap).
 * ``maxlabel``       -- max-id reachability, the max problem's answer.
-* ``priority``       -- |v (+) dv - v| per vertex (Sec. 3.4 and Table 1 rows).
+* ``priority``       -- |v (+) dv - v| per vertex (Sec. 3.5 and Table 1 rows).
 * ``sampled_threshold`` / ``topk_exact`` -- the two selection rules of a round.
 * ``mlp_*``          -- FP64 forward/backward of the scheduler network.
 * ``adam_step``      -- one Adam update (Kingma and Ba 2015) in FP64.
@@ -287,7 +287,7 @@ def cc_init(n):
 
 
 def priority(op, v, dv):
-    """Scheduling priority |v (+) dv - v| (Sec. 3.4); SSSP form d - min(d, dd)
+    """Scheduling priority |v (+) dv - v| (Sec. 3.5); SSSP form d - min(d, dd)
     with inf - x taken as 0xFFFFFFFF (Sec. 4.2.1)."""
     if op == OP_SUM:
         return np.abs(np.asarray(dv, dtype=np.float64))

@@ -75,7 +75,7 @@ InEdges transpose_sum(uint64_t n, const uint64_t* row_ptr, const uint32_t* col, 
 }
 
 // Indexed binary max-heap over vertices keyed by (priority, -vid): the largest
-// priority first, ties to the smaller vertex id (Sec. 3.4, priority scheduling).
+// priority first, ties to the smaller vertex id (Sec. 3.5, priority scheduling).
 struct MaxHeap {
   std::vector<uint32_t> heap;   // vertex ids
   std::vector<int64_t> where;   // position in heap, -1 if absent
@@ -225,9 +225,9 @@ int64_t orc_sync_daic_sum(uint64_t n, const uint64_t* row_ptr, const uint32_t* c
 //   update of j:  delta = dv_j; dv_j = identity; v_j = v_j (+) delta;
 //                 for every out-edge (j,k): dv_k = dv_k (+) g_jk(delta),
 //                 a message equal to the identity being skipped.
-// The receive is applied at once (no transmission delay, Sec. 3.3).
+// The receive is applied at once (no transmission delay, Sec. 3.4).
 //   sched 0: priority scheduling, largest |v_j (+) dv_j - v_j| first, ties to
-//            the smaller id (Sec. 3.4; SSSP priority d_j - min(d_j, dd_j)).
+//            the smaller id (Sec. 3.5; SSSP priority d_j - min(d_j, dd_j)).
 //   sched 1: round-robin, sweeping ids 0..n-1 and updating each pending vertex
 //            (Sec. 5.1, scheduling within the update thread).
 //   sched 2: the synchronous update sequence of Sec. 3.4 (every vertex once per
@@ -240,7 +240,7 @@ int64_t orc_sync_daic_sum(uint64_t n, const uint64_t* row_ptr, const uint32_t* c
 // updates. Returns the number of updates performed; *residual receives the
 // final sum of |dv| (sum) or the number of pending vertices (min/max).
 // trace (nullable, length trace_len): progress metric sum_j v_j after update
-// number (i+1)*trace_every, for the update-count experiments (Sec. 6.4).
+// number (i+1)*trace_every, for the update-count experiments (Sec. 6.3).
 int64_t orc_async(uint64_t n, const uint64_t* row_ptr, const uint32_t* col, const double* w_f64,
                   const uint32_t* w_u32, int op, int gkind, double alpha, const double* alpha_pv,
                   int sched, double eps, int64_t max_updates, double* v_f64, double* dv_f64,

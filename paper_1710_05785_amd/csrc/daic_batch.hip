@@ -1939,4 +1939,132 @@ daic_status daic_batch_get(const daic_batch* b, uint32_t graph, double* v_out) {
   return DAIC_OK;
 }
 
+
+daic_status daic_batch_get_state(const daic_batch* b, uint32_t graph, double* v_out, double* dv_out,
+                                 uint8_t* done_out) {
+  if (!b) return fail(DAIC_E_INVALID, "null argument");
+  if (graph >= b->G) return fail(DAIC_E_INVALID, "graph index out of range");
+  const uint64_t n = b->n_of[graph], off = b->voff[graph];
+  const uint32_t R = b->rhs[graph];
+  DAIC_HIP(hipDeviceSynchronize());
+  if (v_out && n) {
+    daic_status rc = daic_batch_get(b, graph, v_out);
+    if (rc) return rc;
+  }
+  if (dv_out && n) {
+    std::vector<float> td(n * kR);
+    DAIC_HIP(hipMemcpy(td.data(), b->a.dv + off * kR, n * kR * 4, hipMemcpyDeviceToHost));
+    for (uint64_t j = 0; j < n; ++j)
+      for (uint32_t r = 0; r < R; ++r) dv_out[j * R + r] = (double)td[j * kR + r];
+  }
+  if (done_out) {
+    uint8_t st[kR];
+    DAIC_HIP(hipMemcpy(st, b->a.done + (size_t)graph * kR, kR, hipMemcpyDeviceToHost));
+    std::memcpy(done_out, st, R);
+  }
+  return DAIC_OK;
+}
+
+// Snapshot of a batch (every instance's v, dv, Kahan term and finish state)
+// for checkpoint and resume; layout in include/daic.h.
+static constexpr char kBatchMagic[8] = {'D', 'A', 'I', 'C', 'B', 'A', 'T', '1'};
+static constexpr uint32_t kBatchVersion = 1;
+
+static uint64_t batch_state_bytes(const daic_batch* b) {
+  const uint64_t N = b->a.N;
+  return 48 + 16 * (uint64_t)b->G + N * kR * 4 * (b->kahan ? 3 : 2) + (uint64_t)b->G * kR;
+}
+
+daic_status daic_batch_save(const daic_batch* b, void* buf, size_t* len) {
+  if (!b || !len) return fail(DAIC_E_INVALID, "null argument");
+  const uint64_t need = batch_state_bytes(b);
+  if (!buf) {
+    *len = need;
+    return DAIC_OK;
+  }
+  if (*len < need) {
+    const size_t have = *len;
+    *len = need;
+    return fail(DAIC_E_INVALID, "buffer of %zu bytes, %llu needed", have, (unsigned long long)need);
+  }
+  uint8_t* p = static_cast<uint8_t*>(buf);
+  const uint32_t ver = kBatchVersion, G = b->G, kah = b->kahan ? 1u : 0u, wgt = b->a.w ? 1u : 0u;
+  const uint64_t N = b->a.N, pay = need - 48 - 16 * (uint64_t)b->G;
+  std::memcpy(p, kBatchMagic, 8);
+  std::memcpy(p + 8, &ver, 4);
+  std::memcpy(p + 12, &G, 4);
+  std::memcpy(p + 16, &N, 8);
+  std::memcpy(p + 24, &kah, 4);
+  std::memcpy(p + 28, &wgt, 4);
+  std::memcpy(p + 32, &b->a.alpha, 8);
+  std::memcpy(p + 40, &pay, 8);
+  uint8_t* q = p + 48;
+  for (uint32_t g = 0; g < G; ++g) {
+    const uint64_t ng = b->n_of[g];
+    const uint32_t r = b->rhs[g], z = 0;
+    std::memcpy(q, &ng, 8);
+    std::memcpy(q + 8, &r, 4);
+    std::memcpy(q + 12, &z, 4);
+    q += 16;
+  }
+  DAIC_HIP(hipDeviceSynchronize());
+  const size_t V = (size_t)N * kR * 4;
+  if (N) {
+    DAIC_HIP(hipMemcpy(q, b->a.v, V, hipMemcpyDeviceToHost));
+    DAIC_HIP(hipMemcpy(q + V, b->a.dv, V, hipMemcpyDeviceToHost));
+    q += 2 * V;
+    if (b->kahan) {
+      DAIC_HIP(hipMemcpy(q, b->a.c, V, hipMemcpyDeviceToHost));
+      q += V;
+    }
+  }
+  DAIC_HIP(hipMemcpy(q, b->a.done, (size_t)G * kR, hipMemcpyDeviceToHost));
+  *len = need;
+  return DAIC_OK;
+}
+
+daic_status daic_batch_load(daic_batch* b, const void* buf, size_t len) {
+  if (!b || !buf) return fail(DAIC_E_INVALID, "null argument");
+  const uint8_t* p = static_cast<const uint8_t*>(buf);
+  if (len < 48 || std::memcmp(p, kBatchMagic, 8) != 0) return fail(DAIC_E_INVALID, "not a saved batch state");
+  uint32_t ver, G, kah, wgt;
+  uint64_t N, pay;
+  double alpha;
+  std::memcpy(&ver, p + 8, 4);
+  std::memcpy(&G, p + 12, 4);
+  std::memcpy(&N, p + 16, 8);
+  std::memcpy(&kah, p + 24, 4);
+  std::memcpy(&wgt, p + 28, 4);
+  std::memcpy(&alpha, p + 32, 8);
+  std::memcpy(&pay, p + 40, 8);
+  if (ver != kBatchVersion) return fail(DAIC_E_INVALID, "unsupported batch state version %u", ver);
+  if (G != b->G || N != b->a.N || kah != (b->kahan ? 1u : 0u) || wgt != (b->a.w ? 1u : 0u) ||
+      std::memcmp(&alpha, &b->a.alpha, 8) != 0)
+    return fail(DAIC_E_INVALID, "saved state belongs to another batch (graphs, state type, weights or alpha differ)");
+  if (len != batch_state_bytes(b) || pay != len - 48 - 16 * (uint64_t)G)
+    return fail(DAIC_E_INVALID, "batch state buffer has the wrong size");
+  const uint8_t* q = p + 48;
+  for (uint32_t g = 0; g < G; ++g) {
+    uint64_t ng;
+    uint32_t r;
+    std::memcpy(&ng, q, 8);
+    std::memcpy(&r, q + 8, 4);
+    if (ng != b->n_of[g] || r != b->rhs[g]) return fail(DAIC_E_INVALID, "graph %u differs from the saved batch", g);
+    q += 16;
+  }
+  DAIC_HIP(hipDeviceSynchronize());
+  const size_t V = (size_t)N * kR * 4;
+  if (N) {
+    DAIC_HIP(hipMemcpy(b->a.v, q, V, hipMemcpyHostToDevice));
+    DAIC_HIP(hipMemcpy(b->a.dv, q + V, V, hipMemcpyHostToDevice));
+    q += 2 * V;
+    if (b->kahan) {
+      DAIC_HIP(hipMemcpy(b->a.c, q, V, hipMemcpyHostToDevice));
+      q += V;
+    }
+  }
+  DAIC_HIP(hipMemcpy(b->a.done, q, (size_t)G * kR, hipMemcpyHostToDevice));
+  return DAIC_OK;
+}
+
 }  // extern "C"

@@ -72,7 +72,7 @@ struct KArgs {
   uint64_t* part_n;         // pending-count partials per block
   uint8_t* sel_out;         // dry selection output [n]
   const float* score;       // learned scheduler: multiplier in (0,1) per vertex, or null
-  uint32_t* last_upd;       // learned scheduler: round of each vertex's last update, or null
+  uint32_t* last_upd;       // learned scheduler: 1 + round of each vertex's last update (0: none), or null
   uint64_t rr_chunk;        // round-robin: ids per block
   // dense rounds (pull over in-edges)
   const uint32_t* perm;     // renumbering of sources by out-degree
@@ -115,7 +115,7 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
 
 // ---------------------------------------------------------------------------
 // Priority |v (+) dv - v| as an unsigned key whose integer order is the order
-// of the priority (Sec. 3.4; SSSP form d - min(d, dd) of Sec. 4.2.1 with
+// of the priority (Sec. 3.5; SSSP form d - min(d, dd) of Sec. 4.2.1 with
 // inf - x taken as 0xFFFFFFFF; CC form max(v, dv) - v). Key 0 = not pending.
 // ---------------------------------------------------------------------------
 template <int ST>
@@ -822,7 +822,7 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
             else coef = a.alpha_pv ? (double)static_cast<const S*>(a.alpha_pv)[j] : a.alpha;
             mu = (S)(coef * (double)delta);
             send = delta != (S)0 && deg > 0;
-            if (a.last_upd) a.last_upd[j] = (uint32_t)ctl->rounds;
+            if (a.last_upd) a.last_upd[j] = (uint32_t)ctl->rounds + 1u;
           }
           if (pj[u] < a.n_src) mu_pi[pj[u]] = send ? mu : (S)0;  // no reader otherwise
           act += sel ? 1 : 0;
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
       beg = row_at<RowT>(a.row, j);
       deg = row_at<RowT>(a.row, j + 1) - beg;
       send = claim_fold<ST, G>(a, j, deg, vj, dj, mu) && deg > 0;
-      if (a.last_upd) a.last_upd[j] = (uint32_t)ctl->rounds;
+      if (a.last_upd) a.last_upd[j] = (uint32_t)ctl->rounds + 1u;
     }
     if (pull) {  // dense round: every sender publishes its message base (0 if silent)
       if constexpr (Tr<ST>::sum) {

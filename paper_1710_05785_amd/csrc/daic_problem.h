@@ -59,11 +59,12 @@ struct daic_problem {
   uint64_t pull_min = 0;
   // learned scheduler state (allocated on first use)
   bool learned_ready = false;
-  uint32_t* last_upd = nullptr;  // round of the last update of each vertex
+  uint32_t* last_upd = nullptr;  // 1 + round of the last update of each vertex, 0 = never updated
   uint32_t* indeg = nullptr;     // in-degree of each vertex
   float* score = nullptr;        // selection multiplier of each vertex
   uint64_t learned_fallbacks = 0;  // learned rounds that handed back to exact selection
   daic::SweepState* sweep = nullptr;
+  void* cst = nullptr;           // constant c of the update function (fourth-condition check), or null
 };
 
 namespace daic {
@@ -120,6 +121,8 @@ bool get_ops(const daic_problem* p, Ops* out);
 daic_status check_opts(const daic_problem* p, const daic_run_opts* o);
 daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStream_t s);
 void apply_run_opts(daic_problem* p, const daic_run_opts* o);
+// Fourth condition of Sec. 3.1 on the current state (needs the constant c).
+daic_status check_init(daic_problem* p, double tol, uint64_t* mismatches, hipStream_t s);
 // SWEEP scheduling: the run loop, and the release of its per-problem state.
 daic_status sweep_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats, hipStream_t s);
 void sweep_release(daic_problem* p);

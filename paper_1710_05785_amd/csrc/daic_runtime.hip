@@ -774,6 +774,10 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
   hipStream_t s = o->hip_stream ? static_cast<hipStream_t>(o->hip_stream) : p->own_stream;
   if (stats) std::memset(stats, 0, sizeof *stats);
   if (n == 0) return DAIC_OK;
+  if (std::getenv("DAIC_CHECK_INIT")) {  // debug: the starting state must meet the fourth condition
+    rc = check_init(p, 0.0, nullptr, s);
+    if (rc) return rc;
+  }
   if (o->sched == DAIC_SCHED_SWEEP) return sweep_run(p, o, stats, s);
   Ops ops;
   if (!get_ops(p, &ops)) return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");

@@ -430,6 +430,27 @@ static daic_status model_grad(daic_sched_model* m, const float* dx, const float*
   return DAIC_OK;
 }
 
+constexpr float kAdamB1 = 0.9f, kAdamB2 = 0.999f, kAdamEps = 1e-8f;
+
+// One Adam step (Kingma and Ba 2015) with the gradient already in dgrad:
+// moments and FP32 master weights updated, then the BF16 copies refreshed.
+static daic_status adam_apply(daic_sched_model* m, const float* dgrad, float lr, hipStream_t s) {
+  m->adam_t += 1;
+  const float bc1 = 1.f - std::pow(kAdamB1, (float)m->adam_t);
+  const float bc2 = 1.f - std::pow(kAdamB2, (float)m->adam_t);
+  hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, m->w, m->m1, m->m2, dgrad, lr, kAdamB1,
+                     kAdamB2, kAdamEps, bc1, bc2);
+  DAIC_HIP(hipGetLastError());
+  return model_pack(m, s);
+}
+
+// Serialized model: magic, version, parameter count, Adam step count, the
+// feature standardization and the FP32 master weights with both Adam moments.
+constexpr char kModelMagic[8] = {'D', 'A', 'I', 'C', 'S', 'C', 'H', '1'};
+constexpr uint32_t kModelVersion = 1;
+constexpr size_t kModelHeader = 8 + 4 + 4 + 8 + 6 * 4;
+constexpr size_t kModelBytes = kModelHeader + 3 * (size_t)kNParams * 4;
+
 }  // namespace daic
 
 extern "C" {
@@ -569,6 +590,8 @@ __global__ void k_indeg(const uint32_t* col, uint64_t m, uint32_t* indeg) {
 
 // Raw features of vertex j: [log2 priority, log2((1 + indeg) / (1 + outdeg)),
 // min(rounds since the last update, 64) / 64]; false when j is not pending.
+// last_upd holds 1 + the round of the last update (0: never updated), so a
+// vertex never updated counts as updated in round -1.
 template <int ST, typename RowT>
 __device__ __forceinline__ bool vertex_features(const KArgs& a, const uint32_t* indeg, const uint32_t* last_upd,
                                                 uint32_t round, uint64_t j, float (&f)[3], float& pr,
@@ -580,7 +603,7 @@ __device__ __forceinline__ bool vertex_features(const KArgs& a, const uint32_t* 
   if (k == 0) return false;
   const float p = prio_value<ST>(v, dv);
   const uint64_t od = row_at<RowT>(a.row, j + 1) - row_at<RowT>(a.row, j);
-  since = round - last_upd[j];
+  since = round + 1u - last_upd[j];
   f[0] = log2f(p + 1e-30f);
   f[1] = log2f((1.0f + (float)indeg[j]) / (1.0f + (float)od));
   f[2] = (float)min(since, 64u) * (1.0f / 64.0f);
@@ -751,11 +774,12 @@ __global__ void k_trace_sample(KArgs a, const uint32_t* indeg, const uint32_t* l
   }
 }
 
-// After round `slot`: which samples were updated in it.
+// After round `slot`: which samples were updated in it (pending when sampled
+// and claimed by the round, which stored slot + 1).
 __global__ void k_trace_selected(const uint32_t* last_upd, TraceDev td, uint32_t S, uint32_t slot) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < S; i += gridDim.x * blockDim.x) {
     const uint64_t o = (uint64_t)slot * S + i;
-    td.sel[o] = (td.p0[o] > 0.f && last_upd[td.vid[o]] == slot) ? 1 : 0;
+    td.sel[o] = (td.p0[o] > 0.f && last_upd[td.vid[o]] == slot + 1u) ? 1 : 0;
   }
 }
 
@@ -872,6 +896,8 @@ void learned_after_round(daic_problem*, hipStream_t) {}
 struct daic_trace {
   std::vector<float> x;  // [N][3] raw features
   std::vector<float> y;  // [N]
+  std::vector<uint32_t> vid;    // [N] vertex of each sample (recorded traces)
+  std::vector<uint32_t> round;  // [N] round of each sample (recorded traces)
   uint64_t rounds = 0;
   uint64_t sampled = 0;
   int kind = 0;          // 0 sum, 1 min, 2 max
@@ -947,16 +973,21 @@ daic_status daic_trace_record(daic_problem* p, const daic_run_opts* o, uint32_t 
     ops.round(p, o, s, nullptr, nullptr);
     hipLaunchKernelGGL(k_trace_selected, dim3((S + 255) / 256), dim3(256), 0, s, p->last_upd, td, S, (uint32_t)t);
   }
+  // the state after the last round stands for the start of every later round
+  if (e == hipSuccess && t > 0) lo.window(p, td, t >= H ? (t - H) * S : 0, t * S, s);
   std::vector<float> feat, p0, maxp;
   std::vector<uint8_t> sel;
+  std::vector<uint32_t> vids;
   if (e == hipSuccess) {
     const uint64_t cnt = t * S;
     feat.resize(cnt * 3);
     p0.resize(cnt);
     maxp.resize(cnt);
     sel.resize(cnt);
+    vids.resize(cnt);
     if (cnt) {
       e = hipMemcpy(feat.data(), td.feat, cnt * 12, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(vids.data(), td.vid, cnt * 4, hipMemcpyDeviceToHost);
       if (e == hipSuccess) e = hipMemcpy(p0.data(), td.p0, cnt * 4, hipMemcpyDeviceToHost);
       if (e == hipSuccess) e = hipMemcpy(maxp.data(), td.maxp, cnt * 4, hipMemcpyDeviceToHost);
       if (e == hipSuccess) e = hipMemcpy(sel.data(), td.sel, cnt, hipMemcpyDeviceToHost);
@@ -976,6 +1007,8 @@ daic_status daic_trace_record(daic_problem* p, const daic_run_opts* o, uint32_t 
       const bool premature = tr->kind == 0 ? (maxp[o2] >= 0.5f * p0[o2]) : (maxp[o2] > 0.f);
       tr->x.insert(tr->x.end(), &feat[o2 * 3], &feat[o2 * 3] + 3);
       tr->y.push_back(premature ? 0.f : 1.f);
+      tr->vid.push_back(vids[o2]);
+      tr->round.push_back((uint32_t)r);
     }
   tr->rounds = t;
   *out = tr.release();
@@ -991,6 +1024,138 @@ daic_status daic_trace_get(const daic_trace* tr, float* x, float* y, uint64_t* n
 }
 
 void daic_trace_destroy(daic_trace* tr) { delete tr; }
+
+daic_status daic_trace_samples(const daic_trace* tr, uint32_t* vid, uint32_t* round, uint64_t* n) {
+  if (!tr || !n) return fail(DAIC_E_INVALID, "null argument");
+  *n = tr->vid.size();
+  if (vid) std::memcpy(vid, tr->vid.data(), tr->vid.size() * 4);
+  if (round) std::memcpy(round, tr->round.data(), tr->round.size() * 4);
+  return DAIC_OK;
+}
+
+daic_status daic_trace_create(const float* x, const float* y, uint64_t n, daic_trace** out) {
+  if (!out || (n && (!x || !y))) return fail(DAIC_E_INVALID, "null argument");
+  *out = nullptr;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (!(y[i] == 0.f || y[i] == 1.f)) return fail(DAIC_E_INVALID, "label %llu is not 0 or 1", (unsigned long long)i);
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(x[i * 3 + k])) return fail(DAIC_E_INVALID, "feature %llu is not finite", (unsigned long long)i);
+  }
+  std::unique_ptr<daic_trace> tr(new daic_trace());
+  tr->x.assign(x, x + n * 3);
+  tr->y.assign(y, y + n);
+  *out = tr.release();
+  return DAIC_OK;
+}
+
+daic_status daic_sched_step(daic_sched_model* m, const float* x, const float* y, uint64_t N, float lr,
+                            float* grad_out, double* loss) {
+  if (!m || (N && (!x || !y))) return fail(DAIC_E_INVALID, "null argument");
+  if (N == 0) return fail(DAIC_E_INVALID, "no samples");
+  if (!(lr > 0.f)) return fail(DAIC_E_INVALID, "lr must be positive");
+  float *dx = nullptr, *dy = nullptr, *dg = nullptr, *part = nullptr;
+  double *dl = nullptr, *pl = nullptr;
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (N + 63) / 64);
+  std::vector<void*> bufs;
+  auto grab = [&](void** q, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(q, bytes);
+    if (e == hipSuccess) bufs.push_back(*q);
+    return e;
+  };
+  hipError_t e = grab((void**)&dx, N * 12);
+  if (e == hipSuccess) e = grab((void**)&dy, N * 4);
+  if (e == hipSuccess) e = grab((void**)&dg, kNParams * 4);
+  if (e == hipSuccess) e = grab((void**)&dl, 8);
+  if (e == hipSuccess) e = grab((void**)&part, (size_t)blocks * 4 * kNParams * 4);
+  if (e == hipSuccess) e = grab((void**)&pl, (size_t)blocks * 4 * 8);
+  if (e == hipSuccess) e = hipMemcpy(dx, x, N * 12, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dy, y, N * 4, hipMemcpyHostToDevice);
+  daic_status rc = e == hipSuccess ? DAIC_OK : fail(DAIC_E_DEVICE, "sched_step: %s", hipGetErrorString(e));
+  if (rc == DAIC_OK) rc = model_grad(m, dx, dy, N, (double)N, dg, dl, part, pl, blocks, nullptr);
+  if (rc == DAIC_OK) rc = adam_apply(m, dg, lr, nullptr);
+  if (rc == DAIC_OK && grad_out) {
+    e = hipMemcpy(grad_out, dg, kNParams * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = fail(DAIC_E_DEVICE, "sched_step: %s", hipGetErrorString(e));
+  }
+  if (rc == DAIC_OK && loss) {
+    double l = 0;
+    e = hipMemcpy(&l, dl, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = fail(DAIC_E_DEVICE, "sched_step: %s", hipGetErrorString(e));
+    *loss = l / (double)N;
+  }
+  if (rc == DAIC_OK) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = fail(DAIC_E_DEVICE, "sched_step: %s", hipGetErrorString(e));
+  }
+  for (void* q : bufs) (void)hipFree(q);
+  return rc;
+}
+
+daic_status daic_sched_save(const daic_sched_model* m, void* buf, size_t* len) {
+  if (!m || !len) return fail(DAIC_E_INVALID, "null argument");
+  if (!buf) {
+    *len = kModelBytes;
+    return DAIC_OK;
+  }
+  if (*len < kModelBytes) {
+    const size_t have = *len;
+    *len = kModelBytes;
+    return fail(DAIC_E_INVALID, "buffer of %zu bytes, %zu needed", have, kModelBytes);
+  }
+  uint8_t* b = static_cast<uint8_t*>(buf);
+  const uint32_t ver = kModelVersion, np = (uint32_t)kNParams;
+  const uint64_t t = m->adam_t;
+  std::memcpy(b, kModelMagic, 8);
+  std::memcpy(b + 8, &ver, 4);
+  std::memcpy(b + 12, &np, 4);
+  std::memcpy(b + 16, &t, 8);
+  std::memcpy(b + 24, m->fmean, 12);
+  std::memcpy(b + 36, m->fstd, 12);
+  float* w = reinterpret_cast<float*>(b + kModelHeader);
+  DAIC_HIP(hipMemcpy(w, m->w, kNParams * 4, hipMemcpyDeviceToHost));
+  DAIC_HIP(hipMemcpy(w + kNParams, m->m1, kNParams * 4, hipMemcpyDeviceToHost));
+  DAIC_HIP(hipMemcpy(w + 2 * kNParams, m->m2, kNParams * 4, hipMemcpyDeviceToHost));
+  *len = kModelBytes;
+  return DAIC_OK;
+}
+
+daic_status daic_sched_load(const void* buf, size_t len, daic_sched_model** out) {
+  if (!buf || !out) return fail(DAIC_E_INVALID, "null argument");
+  *out = nullptr;
+  const uint8_t* b = static_cast<const uint8_t*>(buf);
+  if (len < kModelHeader || std::memcmp(b, kModelMagic, 8) != 0) return fail(DAIC_E_INVALID, "not a saved model");
+  uint32_t ver, np;
+  uint64_t t;
+  std::memcpy(&ver, b + 8, 4);
+  std::memcpy(&np, b + 12, 4);
+  std::memcpy(&t, b + 16, 8);
+  if (ver != kModelVersion || np != (uint32_t)kNParams) return fail(DAIC_E_INVALID, "unsupported model version or size");
+  if (len != kModelBytes) return fail(DAIC_E_INVALID, "model buffer of %zu bytes, %zu expected", len, kModelBytes);
+  float mean[3], sd[3];
+  std::memcpy(mean, b + 24, 12);
+  std::memcpy(sd, b + 36, 12);
+  std::vector<float> w(3 * (size_t)kNParams);
+  std::memcpy(w.data(), b + kModelHeader, w.size() * 4);
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(mean[k]) || !(sd[k] > 0.f) || !std::isfinite(sd[k]))
+      return fail(DAIC_E_INVALID, "bad feature standardization");
+  for (float x : w)
+    if (!std::isfinite(x)) return fail(DAIC_E_INVALID, "non-finite parameter");
+  daic_sched_model* m = nullptr;
+  daic_status rc = daic_sched_model_create(w.data(), 0, &m);
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(m->m1, w.data() + kNParams, kNParams * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->m2, w.data() + 2 * kNParams, kNParams * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    daic_sched_destroy(m);
+    return fail(DAIC_E_DEVICE, "sched_load: %s", hipGetErrorString(e));
+  }
+  std::memcpy(m->fmean, mean, 12);
+  std::memcpy(m->fstd, sd, 12);
+  m->adam_t = t;
+  *out = m;
+  return DAIC_OK;
+}
 
 // Trains the model on the union of the traces: features standardized with
 // their mean and scale (kept in the model), minibatch Adam on the mean
@@ -1065,18 +1230,12 @@ daic_status daic_sched_train(const daic_trace* const* traces, uint32_t n_traces,
   daic_status rc = full_loss(&loss0);
   DAIC_HIP(hipEventRecord(e0, s));
   const float lr = to->lr > 0 ? to->lr : 1e-3f;
-  const float b1 = 0.9f, b2 = 0.999f;
   const uint32_t epochs = to->epochs ? to->epochs : 10;
   for (uint32_t ep = 0; ep < epochs && rc == DAIC_OK; ++ep) {
     for (uint64_t off = 0; off < N && rc == DAIC_OK; off += B) {
       const uint64_t nb = std::min<uint64_t>(B, N - off);
       rc = model_grad(m, dx + off * 3, dy + off, nb, (double)nb, dg, nullptr, part, pl, blocks, s);
-      m->adam_t += 1;
-      const float bc1 = 1.f - std::pow(b1, (float)m->adam_t);
-      const float bc2 = 1.f - std::pow(b2, (float)m->adam_t);
-      hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, m->w, m->m1, m->m2, dg, lr, b1, b2,
-                         1e-8f, bc1, bc2);
-      if (rc == DAIC_OK) rc = model_pack(m, s);
+      if (rc == DAIC_OK) rc = adam_apply(m, dg, lr, s);
     }
   }
   DAIC_HIP(hipEventRecord(e1, s));

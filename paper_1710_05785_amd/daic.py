@@ -127,14 +127,40 @@ def lib():
         L.daic_trace_get.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)]
         L.daic_trace_destroy.argtypes = [_vp]
         L.daic_trace_destroy.restype = None
+        L.daic_trace_samples.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.daic_trace_create.argtypes = [_vp, _vp, ctypes.c_uint64, ctypes.POINTER(_vp)]
+        L.daic_sched_step.argtypes = [_vp, _vp, _vp, ctypes.c_uint64, ctypes.c_float, _vp,
+                                      ctypes.POINTER(ctypes.c_double)]
+        L.daic_sched_save.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.daic_sched_load.argtypes = [_vp, ctypes.c_size_t, ctypes.POINTER(_vp)]
         L.daic_sched_train.argtypes = [ctypes.POINTER(_vp), ctypes.c_uint32,
                                        ctypes.POINTER(TrainOpts), _vp, ctypes.POINTER(TrainStats)]
         L.daic_run_progress.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint64, _vp, _vp,
                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(Stats)]
         L.daic_select_frontier.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint64, _vp,
                                            ctypes.POINTER(ctypes.c_double)]
+        L.daic_problem_set_const.argtypes = [_vp, _vp]
+        L.daic_problem_check_init.argtypes = [_vp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
+        L.daic_problem_save.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.daic_problem_load.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.daic_batch_get_state.argtypes = [_vp, ctypes.c_uint32, _vp, _vp, _vp]
+        L.daic_batch_save.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.daic_batch_load.argtypes = [_vp, _vp, ctypes.c_size_t]
         _lib = L
     return _lib
+
+
+def _save(fn, h, what) -> bytes:
+    n = ctypes.c_size_t(0)
+    check(fn(h, None, ctypes.byref(n)), what)
+    buf = ctypes.create_string_buffer(n.value)
+    check(fn(h, buf, ctypes.byref(n)), what)
+    return buf.raw[:n.value]
+
+
+def _load(fn, h, data: bytes, what):
+    buf = ctypes.create_string_buffer(bytes(data), len(data))
+    check(fn(h, buf, len(data)), what)
 
 
 def check(rc: int, what: str) -> int:
@@ -323,6 +349,40 @@ class Problem:
         k = pts.value
         return RunResult(rc, st.as_dict()), up[:k], pr[:k]
 
+    def set_const(self, c):
+        """The constant c of the update function (Eq. decompose), for the
+        fourth-condition check."""
+        dt = np.float64 if self.state in (F64, F32, F32_KAHAN) else self._host_dtype()
+        c = np.ascontiguousarray(c, dtype=dt)
+        if c.shape != (self.n,):
+            raise ValueError("c must have n entries")
+        check(lib().daic_problem_set_const(self._h, _addr(c)), "daic_problem_set_const")
+
+    def check_init(self, tol=0.0):
+        """Checks v (+) dv = f(v) on the device; returns the mismatch count
+        (0), raising DaicError when some vertex fails."""
+        bad = ctypes.c_uint64(0)
+        rc = lib().daic_problem_check_init(self._h, float(tol), ctypes.byref(bad))
+        if rc < 0:
+            msg = lib().daic_last_error().decode(errors="replace")
+            raise DaicError(f"daic_problem_check_init failed ({rc}, {bad.value} mismatches): {msg}")
+        return bad.value
+
+    def save_state(self) -> bytes:
+        """The state snapshot of daic_problem_save."""
+        return _save(lib().daic_problem_save, self._h, "daic_problem_save")
+
+    def load_state(self, data: bytes):
+        _load(lib().daic_problem_load, self._h, data, "daic_problem_load")
+
+    def save(self, path):
+        with open(path, "wb") as f:
+            f.write(self.save_state())
+
+    def load(self, path):
+        with open(path, "rb") as f:
+            self.load_state(f.read())
+
     def select_frontier(self, round_no=0, **kw):
         o = self.make_opts(**kw)
         sel = np.zeros(self.n, dtype=np.uint8)
@@ -391,6 +451,29 @@ class Batch:
         out = np.empty((self.n[g], self.rhs[g]), dtype=np.float64)
         check(lib().daic_batch_get(self._h, g, _addr(out)), "daic_batch_get")
         return out
+
+    def get_state(self, g: int):
+        """(v, dv, finish states) of graph g's instances."""
+        v = np.empty((self.n[g], self.rhs[g]), dtype=np.float64)
+        dv = np.empty((self.n[g], self.rhs[g]), dtype=np.float64)
+        done = np.empty(self.rhs[g], dtype=np.uint8)
+        check(lib().daic_batch_get_state(self._h, g, _addr(v), _addr(dv), _addr(done)),
+              "daic_batch_get_state")
+        return v, dv, done
+
+    def save_state(self) -> bytes:
+        return _save(lib().daic_batch_save, self._h, "daic_batch_save")
+
+    def load_state(self, data: bytes):
+        _load(lib().daic_batch_load, self._h, data, "daic_batch_load")
+
+    def save(self, path):
+        with open(path, "wb") as f:
+            f.write(self.save_state())
+
+    def load(self, path):
+        with open(path, "rb") as f:
+            self.load_state(f.read())
 
     def close(self):
         if getattr(self, "_h", None) is not None:
@@ -469,6 +552,30 @@ class SchedModel:
                                   ctypes.byref(loss)), "daic_mlp_grad")
         return unpack_params(g), loss.value
 
+    def step(self, x, y, lr):
+        """One Adam step on standardized samples; returns (gradient dict, loss)."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        g = np.empty(N_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double(0)
+        check(lib().daic_sched_step(self._h, _addr(x), _addr(y), x.shape[0], float(lr), _addr(g),
+                                    ctypes.byref(loss)), "daic_sched_step")
+        return unpack_params(g), loss.value
+
+    def save(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        check(lib().daic_sched_save(self._h, None, ctypes.byref(n)), "daic_sched_save")
+        buf = ctypes.create_string_buffer(n.value)
+        check(lib().daic_sched_save(self._h, buf, ctypes.byref(n)), "daic_sched_save")
+        return buf.raw[:n.value]
+
+    @classmethod
+    def load(cls, data: bytes) -> "SchedModel":
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        h = _vp()
+        check(lib().daic_sched_load(buf, len(data), ctypes.byref(h)), "daic_sched_load")
+        return cls(_handle=h)
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             lib().daic_sched_destroy(self._h)
@@ -496,9 +603,29 @@ class Trace:
                                       ctypes.byref(h)), "daic_trace_record")
         return cls(h)
 
+    @classmethod
+    def from_samples(cls, x, y):
+        """A trace of caller samples (x [n, 3] raw features, y [n] in {0, 1})."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        h = _vp()
+        check(lib().daic_trace_create(_addr(x), _addr(y), y.shape[0], ctypes.byref(h)),
+              "daic_trace_create")
+        return cls(h)
+
     @property
     def handle(self):
         return self._h
+
+    def samples(self):
+        """(vertex, round) of every sample of a recorded trace."""
+        n = ctypes.c_uint64(0)
+        check(lib().daic_trace_samples(self._h, None, None, ctypes.byref(n)), "daic_trace_samples")
+        vid = np.empty(n.value, dtype=np.uint32)
+        rnd = np.empty(n.value, dtype=np.uint32)
+        check(lib().daic_trace_samples(self._h, _addr(vid), _addr(rnd), ctypes.byref(n)),
+              "daic_trace_samples")
+        return vid, rnd
 
     def get(self):
         n = ctypes.c_uint64(0)

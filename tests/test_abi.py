@@ -32,7 +32,11 @@ def L():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("daic_graph_create", "daic_problem_create", "daic_problem_set_init", "daic_run",
-                 "daic_problem_get", "daic_last_error"):
+                 "daic_problem_get", "daic_last_error", "daic_trace_record", "daic_sched_train",
+                 "daic_sched_save", "daic_sched_load", "daic_sched_step", "daic_trace_create",
+                 "daic_trace_samples", "daic_problem_set_const", "daic_problem_check_init",
+                 "daic_problem_save", "daic_problem_load", "daic_batch_get_state", "daic_batch_save",
+                 "daic_batch_load"):
         assert must in names
 
 

@@ -550,7 +550,7 @@ def test_push_and_pull_rounds_agree(daic, monkeypatch, direction, state, gk):
 
 
 # ---------------------------------------------------------------------------
-# Round-robin scheduling and progress traces (Sec. 5.1, Sec. 6.4)
+# Round-robin scheduling and progress traces (Sec. 5.1, Sec. 6.3)
 # ---------------------------------------------------------------------------
 
 def test_round_robin_selection_block(daic):
@@ -581,7 +581,7 @@ def test_round_robin_reaches_the_fixed_point(daic, pl10k, pl10k_ref):
 
 
 def test_progress_trace_is_monotone(daic):
-    """sum_j v_j grows monotonically for PageRank and falls for SSSP (Sec. 6.4);
+    """sum_j v_j grows monotonically for PageRank and falls for SSSP (Sec. 6.3);
     the last point equals the fixed point's total."""
     say("case progress")
     g = daic_gen.rmat(13, 16, seed=9)
@@ -676,3 +676,123 @@ def test_checkpoint_resume_through_files(daic, tmp_path):
     q.set_init(ck["v"], ck["dv"])
     assert q.run(eps=1e-10, q=1.0).converged
     assert np.abs(q.get() - ref).sum() <= 1e-9
+
+
+def test_library_checkpoint_resume(daic, tmp_path):
+    """Checkpoint through the library's own snapshot (daic_problem_save /
+    load, Sec. 5.1 snapshots of the state table): runs stopped by max_rounds
+    are written to files, every handle (graph included) is destroyed, the
+    problems are rebuilt from the CSR and the files, and the resumed runs
+    reach the oracle's fixed point. The snapshot is bit-exact: a reloaded
+    state saves to the same bytes."""
+    say("case library checkpoint")
+    g = daic_gen.rmat(13, 16, seed=23)
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.8, np.full(g.n, 0.2), eps=1e-13)
+    w = daic_gen.sssp_weights(g.m, seed=24)
+    dist = oracle.dijkstra(g, w, 0)
+    paths = {}
+    for kind in ("f32_kahan", "f64", "sssp"):
+        if kind == "sssp":
+            p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+            p.set_init(*oracle.sssp_init(g.n, 0))
+            res = p.run(q=0.1, sched="exact", max_rounds=3, rounds_per_check=1)
+        else:
+            p = pr_problem(daic, g, 0.8, state=kind)
+            res = p.run(eps=1e-10, q=0.3, sched="exact", max_rounds=6, rounds_per_check=1)
+        assert res.status == daic.NOT_CONVERGED
+        paths[kind] = tmp_path / f"{kind}.state"
+        p.save(paths[kind])
+        blob = p.save_state()
+        p.close()
+        del p
+        if kind == "sssp":
+            q = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+        else:
+            q = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8,
+                             state=kind)
+        q.load(paths[kind])
+        assert q.save_state() == blob
+        if kind == "sssp":
+            assert q.run(q=0.1, sched="sampled").converged
+            np.testing.assert_array_equal(q.get(), dist)
+        else:
+            assert q.run(eps=1e-10 if kind == "f64" else 1e-7, q=1.0).converged
+            err = np.abs(q.get() - ref).sum()
+            assert err <= (1e-9 if kind == "f64" else 1e-5 * ref.sum()), (kind, err)
+    # a snapshot of another kind of problem, or a damaged one, is refused
+    q = pr_problem(daic, g, 0.85)
+    with pytest.raises(daic.DaicError):
+        q.load(paths["f64"])
+    bad = bytearray(open(paths["f32_kahan"], "rb").read())
+    bad[3] ^= 0x20
+    q2 = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8, state="f32_kahan")
+    with pytest.raises(daic.DaicError):
+        q2.load_state(bytes(bad))
+    with pytest.raises(daic.DaicError):
+        q2.load_state(open(paths["f32_kahan"], "rb").read()[:-8])
+
+
+@pytest.mark.parametrize("kind", ["pagerank_f64", "pagerank_f32_kahan", "sssp", "cc", "katz"])
+def test_fourth_condition_check(daic, monkeypatch, kind):
+    """v0 (+) dv1 = f(v0) (fourth condition, Sec. 3.1) checked on the device:
+    the paper's initial values pass, a wrong delta at one vertex is caught
+    (DAIC_E_INVALID, one mismatch), with DAIC_CHECK_INIT set daic_run refuses
+    the wrong start without touching the state, and a converged state still
+    satisfies the identity."""
+    say("case fourth condition", kind)
+    g = daic_gen.rmat(11, 8, seed=31)
+    n = g.n
+    if kind.startswith("pagerank"):
+        state = kind.split("_", 1)[1]
+        p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8, state=state)
+        v0, dv1 = oracle.pagerank_init(n, 0.8)
+        c = np.full(n, 0.2)
+        wrong = dv1.copy()
+        wrong[77] = 0.25
+        run = dict(eps=1e-9, q=1.0)
+    elif kind == "katz":
+        # Katz from a nonzero start: v0 random, dv1 = f(v0) - v0 with c = e_s
+        beta = 0.9 / max(1, int(g.outdeg().max()))
+        p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_SRC_SCALE, alpha=beta, state="f64")
+        rng = np.random.default_rng(5)
+        v0 = rng.uniform(0, 1, n)
+        c = np.zeros(n)
+        c[3] = 1.0
+        fv = c.copy()
+        np.add.at(fv, g.col, beta * np.repeat(v0, g.outdeg()))
+        dv1 = fv - v0
+        wrong = dv1.copy()
+        wrong[1000] += 1e-6
+        run = dict(eps=1e-12, q=1.0)
+    elif kind == "sssp":
+        w = daic_gen.sssp_weights(g.m, seed=32)
+        p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.MIN, daic.G_EDGE_ADD, state="u32")
+        v0, dv1 = oracle.sssp_init(n, 0)
+        c = dv1.copy()
+        wrong = dv1.copy()
+        wrong[9] = 3
+        run = dict(q=0.1, sched="sampled")
+    else:
+        p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.MAX, daic.G_COPY, state="i32")
+        v0, dv1 = oracle.cc_init(n)
+        c = np.arange(n, dtype=np.int32)
+        wrong = dv1.copy()
+        wrong[5] = 4
+        run = dict(q=1.0)
+    with pytest.raises(daic.DaicError):
+        p.check_init()  # no constant given yet
+    p.set_const(c)
+    p.set_init(v0, wrong)
+    with pytest.raises(daic.DaicError, match="1 mismatches"):
+        p.check_init()
+    monkeypatch.setenv("DAIC_CHECK_INIT", "1")
+    with pytest.raises(daic.DaicError):
+        p.run(**run)
+    _, dv_after = p.get(with_dv=True)
+    expect = wrong.astype(np.float32) if kind == "pagerank_f32_kahan" else wrong
+    np.testing.assert_array_equal(dv_after, expect.astype(dv_after.dtype))
+    p.set_init(v0, dv1)
+    assert p.check_init() == 0
+    assert p.run(**run).converged
+    monkeypatch.delenv("DAIC_CHECK_INIT")
+    assert p.check_init(tol=1e-4 if kind == "pagerank_f32_kahan" else 0.0) == 0

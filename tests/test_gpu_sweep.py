@@ -1,5 +1,5 @@
-"""GPU parity of SWEEP scheduling (blocks of ceil(q n) vertices in out-degree
-order, each block pulling the newest message of every in-neighbour) against
+"""GPU parity of SWEEP scheduling (blocks of ceil(q n) consecutive vertex ids,
+each block pulling the newest message of every in-neighbour) against
 the CPU oracle, with the tolerances of the other parity tests: FP64 L1 <= 1e-9
 at residual 1e-10, FP32 relative L1 <= 1e-5. Runs stopped inside a sweep are
 checked through the invariants that any DAIC state with every message

@@ -125,7 +125,7 @@ def test_closed_forms_pagerank():
     empty = daic_gen.from_edges(5, [], [])
     v, _, _ = oracle.jacobi_sum(empty, oracle.G_DEG_SCALE, d, np.full(5, 1 - d))
     np.testing.assert_allclose(v, 1 - d, atol=0)
-    # no dangling vertex: total rank equals n (Sec. 6.4: sum R grows from 0.2 N to N)
+    # no dangling vertex: total rank equals n (Sec. 6.3: sum R grows from 0.2 N to N)
     g = random_graph(200, 1500, 7)
     deg = g.outdeg()
     if (deg == 0).any():  # add a self-loop to every dangling vertex
@@ -221,7 +221,7 @@ def test_mass_conservation_and_state_identity(updates, sched):
 
 
 def test_progress_is_monotone_and_bounded():
-    """sum_j v_j grows monotonically from 0.2 N towards its limit (Sec. 3.4, 6.4)."""
+    """sum_j v_j grows monotonically from 0.2 N towards its limit (Sec. 3.4, 6.3)."""
     g = daic_gen.powerlaw(n=400, seed=4)
     d = 0.8
     v0, dv1 = oracle.pagerank_init(g.n, d)
