@@ -199,8 +199,9 @@ void daic_problem_destroy(daic_problem* p);
  * uint32 for U32, int32 for I32). daic_problem_check_init then checks the
  * problem's current state on the device (the identity also holds at every
  * state a run leaves, since all messages are then delivered): exact for
- * min/max problems; for sum problems |lhs - rhs| <= tol x (|c_j| + sum of
- * |g_ij(v_i)| + |v_j| + |dv_j|), tol 0 meaning 1e-12 (F64) or 1e-5 (FP32
+ * min/max problems; for sum problems |lhs - rhs| <= tol x (s_j + mean_k s_k)
+ * with s_j = |c_j| + sum of |g_ij(v_i)| + |v_j| + |dv_j| (the mean is a floor
+ * for vertices whose terms cancel), tol 0 meaning 1e-12 (F64) or 1e-5 (FP32
  * states). It returns DAIC_E_INVALID when some vertex fails (count in
  * *mismatches, nullable; first vertex in daic_last_error) and also when no
  * constant was given. With the environment variable DAIC_CHECK_INIT set,

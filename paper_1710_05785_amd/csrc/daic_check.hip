@@ -29,7 +29,9 @@ struct CheckBuf {
   void* acc;           // sum: double; min U32: uint32; min F64: uint64 bits; max: int32
   double* absacc;      // sum problems: sum of |g(v_i)|
   const void* cst;     // c_j in the state's host element type on the device (double for FP states)
-  unsigned long long* bad;    // [0] mismatches, [1] smallest mismatching vertex
+  double* total;       // sum problems: sum over vertices of each vertex's magnitude scale
+  unsigned long long* bad;    // [0] mismatches, [1] smallest mismatching vertex,
+                              // [2] bits of the largest |lhs - rhs| / scale (sum problems)
 };
 
 // Every edge (j -> k) adds g_jk(v_j) into the accumulator of k.
@@ -74,6 +76,30 @@ __global__ __launch_bounds__(256) void k_check_push(KArgs a, CheckBuf cb) {
   }
 }
 
+// Magnitude scale of vertex k's identity: |c_k| + sum |g_ik(v_i)| + |v_k| + |dv_k|.
+template <int ST>
+__device__ __forceinline__ double check_scale(const KArgs& a, const CheckBuf& cb, uint64_t k) {
+  using S = typename Tr<ST>::S;
+  double vk = (double)static_cast<const S*>(a.v)[k];
+  if constexpr (Tr<ST>::kahan) vk -= (double)a.c[k];
+  return fabs(static_cast<const double*>(cb.cst)[k]) + cb.absacc[k] + fabs(vk) +
+         fabs((double)static_cast<const S*>(a.dv)[k]);
+}
+
+// Sum problems: the total of the vertices' scales (its mean sets an absolute
+// floor of the tolerance: where the terms of a vertex cancel, the rounding
+// left from earlier states is of the size of the state's typical values).
+template <int ST>
+__global__ __launch_bounds__(256) void k_check_total(KArgs a, CheckBuf cb) {
+  if constexpr (Tr<ST>::sum) {
+    double t = 0.0;
+    for (uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x; k < a.n; k += (uint64_t)gridDim.x * 256)
+      t += check_scale<ST>(a, cb, k);
+    t = block_sum256(t);
+    if (threadIdx.x == 0) atomicAdd(cb.total, t);
+  }
+}
+
 // Every vertex: v_k (+) dv_k against acc_k (+) c_k.
 template <int ST>
 __global__ __launch_bounds__(256) void k_check_compare(KArgs a, CheckBuf cb, double tol) {
@@ -88,8 +114,13 @@ __global__ __launch_bounds__(256) void k_check_compare(KArgs a, CheckBuf cb, dou
       const double ck = static_cast<const double*>(cb.cst)[k];
       const double lhs = vk + (double)dv[k];
       const double rhs = static_cast<const double*>(cb.acc)[k] + ck;
-      const double scale = fabs(ck) + cb.absacc[k] + fabs(vk) + fabs((double)dv[k]);
-      ok = fabs(lhs - rhs) <= tol * scale;
+      const double scale = check_scale<ST>(a, cb, k) + *cb.total / (double)a.n;
+      const double dev = fabs(lhs - rhs);
+      ok = dev <= tol * scale;
+      if (dev > 0.0) {
+        const double rel = scale > 0.0 ? dev / scale : 1.0;
+        atomicMax(&cb.bad[2], (unsigned long long)__double_as_longlong(rel));  // non-negative: bits order like values
+      }
     } else if constexpr (ST == ST_U32) {
       const uint32_t ck = static_cast<const uint32_t*>(cb.cst)[k];
       const uint32_t lhs = min(v[k], dv[k]);
@@ -121,6 +152,7 @@ __global__ void k_check_fill(T* p, T val, uint64_t count) {
 template <int ST, int G, typename RowT>
 static void check_launch(daic_problem* p, const CheckBuf& cb, double tol, uint32_t grid, hipStream_t s) {
   hipLaunchKernelGGL((k_check_push<ST, G, RowT>), dim3(grid), dim3(256), 0, s, p->a, cb);
+  hipLaunchKernelGGL(k_check_total<ST>, dim3(grid), dim3(256), 0, s, p->a, cb);
   hipLaunchKernelGGL(k_check_compare<ST>, dim3(grid), dim3(256), 0, s, p->a, cb, tol);
 }
 
@@ -174,7 +206,8 @@ daic_status check_init(daic_problem* p, double tol, uint64_t* mismatches, hipStr
   const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8192, (n + 255) / 256));
   hipError_t e = grab(&cb.acc, n * 8);
   if (e == hipSuccess && sum) e = grab((void**)&cb.absacc, n * 8);
-  if (e == hipSuccess) e = grab((void**)&cb.bad, 16);
+  if (e == hipSuccess) e = grab((void**)&cb.bad, 24);
+  if (e == hipSuccess) e = grab((void**)&cb.total, 8);
   if (e == hipSuccess) {
     if (sum) {
       hipLaunchKernelGGL(k_check_fill<double>, dim3(grid), dim3(256), 0, s, static_cast<double*>(cb.acc), 0.0, n);
@@ -192,18 +225,23 @@ daic_status check_init(daic_problem* p, double tol, uint64_t* mismatches, hipStr
     }
     hipLaunchKernelGGL(k_check_fill<unsigned long long>, dim3(1), dim3(256), 0, s, cb.bad, 0ull, 1);
     hipLaunchKernelGGL(k_check_fill<unsigned long long>, dim3(1), dim3(256), 0, s, cb.bad + 1, ~0ull, 1);
+    hipLaunchKernelGGL(k_check_fill<unsigned long long>, dim3(1), dim3(256), 0, s, cb.bad + 2, 0ull, 1);
+    hipLaunchKernelGGL(k_check_fill<double>, dim3(1), dim3(256), 0, s, cb.total, 0.0, 1);
     check_dispatch(p, cb, tol, grid, s);
     e = hipGetLastError();
   }
-  unsigned long long hb[2] = {0, 0};
-  if (e == hipSuccess) e = hipMemcpyAsync(hb, cb.bad, 16, hipMemcpyDeviceToHost, s);
+  unsigned long long hb[3] = {0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(hb, cb.bad, 24, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   for (void* q : bufs) (void)hipFree(q);
   if (e != hipSuccess) return fail(DAIC_E_DEVICE, "fourth-condition check: %s", hipGetErrorString(e));
   if (mismatches) *mismatches = hb[0];
+  double worst = 0.0;
+  std::memcpy(&worst, &hb[2], 8);
   if (hb[0])
-    return fail(DAIC_E_INVALID, "v (+) dv != f(v) at %llu vertices (first: %llu): the initial values break the "
-                "fourth condition", hb[0], hb[1]);
+    return fail(DAIC_E_INVALID, "v (+) dv != f(v) at %llu vertices (first: %llu; largest deviation %.3g of the "
+                "terms' magnitude, tolerance %.3g): the state breaks the fourth condition",
+                (unsigned long long)hb[0], (unsigned long long)hb[1], worst, tol);
   (void)fp_state;
   return DAIC_OK;
 }

@@ -1051,12 +1051,14 @@ __global__ __launch_bounds__(64) void k_push_large(KArgs a) {
 // barrier) acc[i] holds the FP64 sum of target t0 + i and off[0..nr] the
 // block-relative in-edge offsets, clipped to [0, ne]. A block may have no
 // in-edges (then every sum is 0).
+// tid is the thread's index in its group of 256 (a workgroup of 1024 runs
+// four groups on four blocks; every thread of the workgroup reaches both
+// barriers).
 template <typename V, typename Msg>
 __device__ __forceinline__ void stream_sums(const uint32_t* rowT, const uint32_t* srcT, uint32_t t0, uint32_t nr,
                                             uint32_t e0, uint32_t e1, V* vals, double* acc, uint32_t* off,
-                                            const Msg& msg) {
+                                            const Msg& msg, const uint32_t tid) {
   constexpr uint32_t PER = kStreamEdges / 256, ROFF = (kStreamRows + 256) / 256;
-  const uint32_t tid = threadIdx.x;
   const uint32_t ne = e1 - e0;
   // every independent load first, at clamped indices (no branch around
   // them, so they are in flight together): row offsets and sources
@@ -1117,7 +1119,7 @@ __device__ __forceinline__ void stream_block(const uint32_t* rowT, const uint32_
   S dvp[RDV];
 #pragma unroll
   for (uint32_t k = 0; k < RDV; ++k) dvp[k] = dv[t0 + min(tid + 256 * k, nr - 1)];
-  stream_sums<V>(rowT, srcT, t0, nr, e0, e1, vals, acc, off, msg);
+  stream_sums<V>(rowT, srcT, t0, nr, e0, e1, vals, acc, off, msg, threadIdx.x);
   // several targets: all whole; one target: whole or a piece
   const bool piece = nr == 1 && (rowT[t0] != e0 || rowT[t0 + 1] != e1);
 #pragma unroll
@@ -1172,7 +1174,7 @@ __global__ __launch_bounds__(256) void k_pull_stream(KArgs a) {
       S dvp[RDV];
 #pragma unroll
       for (uint32_t q = 0; q < RDV; ++q) dvp[q] = dv[t0 + min(tid + 256 * q, nr - 1)];
-      stream_sums<V>(a.rowT, a.srcT, t0, nr, e0, e1, vals, acc, off, msg);
+      stream_sums<V>(a.rowT, a.srcT, t0, nr, e0, e1, vals, acc, off, msg, threadIdx.x);
       if (grp == 0xFFFFFFFFu) {  // whole targets
 #pragma unroll
         for (uint32_t q = 0; q < RDV; ++q) {
@@ -1353,7 +1355,7 @@ __global__ __launch_bounds__(256) void k_pull_fused(KArgs a) {
           pp[k] = a.perm[t];
         }
       }
-      stream_sums<V>(a.rowT, a.srcT, t0, nr, e0, e1, vals, acc, off, msg);
+      stream_sums<V>(a.rowT, a.srcT, t0, nr, e0, e1, vals, acc, off, msg, threadIdx.x);
       if (grp == 0xFFFFFFFFu) {
 #pragma unroll
         for (uint32_t k = 0; k < RDV; ++k) {

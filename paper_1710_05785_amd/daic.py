@@ -655,3 +655,4 @@ def sched_train(traces, model: SchedModel, epochs=10, batch=65536, lr=1e-3, seed
     check(lib().daic_sched_train(arr, len(traces), ctypes.byref(o), model.handle, ctypes.byref(st)),
           "daic_sched_train")
     return {k: getattr(st, k) for k, _ in TrainStats._fields_}
+

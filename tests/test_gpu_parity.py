@@ -163,6 +163,31 @@ def test_fused_dense_rounds_match_plain_rounds(daic, monkeypatch, state, gk):
         assert abs(rb.stats["final_residual"] - ra.stats["final_residual"]) <= tol * np.abs(va).sum()
 
 
+@pytest.mark.parametrize("n,ef", [(5, 2), (300, 3), (3000, 6)])
+def test_fused_pull_small_graphs(daic, monkeypatch, n, ef):
+    """Fused dense rounds on graphs with fewer edge blocks than the grid
+    would take: the same rounds and state as unfused rounds."""
+    say("case fused small", n, ef)
+    rng = np.random.default_rng(n)
+    src, dst = rng.integers(0, n, n * ef), rng.integers(0, n, n * ef)
+    g = daic_gen.from_edges(n, src, dst)
+    out = []
+    for fuse in (False, True):
+        if fuse:
+            monkeypatch.delenv("DAIC_NO_FUSE", raising=False)
+        else:
+            monkeypatch.setenv("DAIC_NO_FUSE", "1")
+        p = pr_problem(daic, g, 0.85, state="f64")
+        r = p.run(eps=1e-12, q=1.0, sched="all", rounds_per_check=4)
+        assert r.converged
+        out.append((r.stats["rounds"], p.get()))
+    monkeypatch.delenv("DAIC_NO_FUSE", raising=False)
+    assert out[0][0] == out[1][0]
+    assert np.abs(out[0][1] - out[1][1]).sum() <= 1e-12 * np.abs(out[0][1]).sum()
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.85, np.full(n, 0.15), eps=1e-14)
+    assert np.abs(out[1][1] - ref).sum() <= 1e-9
+
+
 def test_profile_matches_run_and_accounts_the_pull(daic, monkeypatch):
     """daic_profile (the source of the benchmark's roofline) runs the same
     rounds as daic_run, to the same state, and reports every dense round's
@@ -795,4 +820,7 @@ def test_fourth_condition_check(daic, monkeypatch, kind):
     assert p.check_init() == 0
     assert p.run(**run).converged
     monkeypatch.delenv("DAIC_CHECK_INIT")
+    if kind == "katz":  # a start away from 0 with deltas of both signs
+        ref, _, _ = oracle.jacobi_sum(g, oracle.G_SRC_SCALE, beta, dv1, v0=v0, eps=1e-15)
+        assert np.abs(p.get() - ref).sum() <= 1e-9
     assert p.check_init(tol=1e-4 if kind == "pagerank_f32_kahan" else 0.0) == 0
