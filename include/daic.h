@@ -235,6 +235,27 @@ const char* daic_last_error(void);
  * a double. round selects the sample stream of TOPK_SAMPLED.              */
 daic_status daic_select_frontier(daic_problem* p, const daic_run_opts* opts, uint64_t round,
                                  uint8_t* sel_out, double* threshold_out);
+/* daic_select_frontier for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * selection (opts: sched ALL, TOPK_EXACT, TOPK_SAMPLED or ROUND_ROBIN,
+ * priority_fraction, n_samples <= 4096, seed; round picks the sample stream)
+ * on caller device arrays d_v, d_dv (n values of the state's device element
+ * type: double for F64, float for F32 and F32_KAHAN, uint32 for U32, int32
+ * for I32; op and state as daic_problem_create takes them), written to
+ * caller device arrays: d_sel_out (n bytes, 0/1) and d_threshold_out
+ * (nullable, one double: the threshold, 0 when every pending vertex is
+ * taken). Inputs are only read. It allocates nothing and does not
+ * synchronize: kernels are enqueued on opts->hip_stream (NULL = default
+ * stream) and the call returns. Its scratch (control block, radix
+ * histograms, sampled keys, per-block partials: under 160 KiB, the same for every
+ * n up to the maximum n < 2^32 - 1) is one fixed array per device that every
+ * call on that device shares and overwrites, so calls that overlap on one
+ * device (other streams, other threads) race and must be serialized by the
+ * caller. Errors (DAIC_E_INVALID, DAIC_E_UNSUPPORTED) are returned before
+ * anything is enqueued. */
+daic_status daic_select_frontier_noalloc(daic_op op, daic_dtype state, uint64_t n, const void* d_v,
+                                         const void* d_dv, const daic_run_opts* opts, uint64_t round,
+                                         uint8_t* d_sel_out, double* d_threshold_out);
 
 /* ---- Batched personalized PageRank --------------------------------------
  * Many graphs of uneven size, each with up to 64 right-hand sides (the

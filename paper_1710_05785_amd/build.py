@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdaic.so")
 SOURCES = ["daic_runtime.hip", "daic_pull.hip", "daic_batch.hip", "daic_sched.hip", "daic_sweep.hip",
-           "daic_check.hip", "daic_state.hip"]
+           "daic_check.hip", "daic_state.hip", "daic_noalloc.hip"]
 
 # Packed FP32 instructions are disabled for all device code; FP atomics map
 # to the hardware instructions (the target memory is coarse-grained).

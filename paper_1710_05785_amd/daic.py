@@ -656,3 +656,21 @@ def sched_train(traces, model: SchedModel, epochs=10, batch=65536, lr=1e-3, seed
           "daic_sched_train")
     return {k: getattr(st, k) for k, _ in TrainStats._fields_}
 
+
+def select_frontier_noalloc(op, state, v, dv, sel_out, tau_out=None, round_no=0, **kw):
+    """daic_select_frontier_noalloc on torch device tensors: the selection of
+    one round from (v, dv) written into sel_out (uint8, n) and tau_out
+    (float64, 1, optional); enqueued on kw["stream"] (default stream)."""
+    o = Problem.make_opts(**kw)
+    st = _STATE_NAMES[state] if isinstance(state, str) else state
+    L = lib()
+    if not hasattr(L.daic_select_frontier_noalloc, "_typed"):
+        L.daic_select_frontier_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _vp, _vp,
+                                                   ctypes.POINTER(RunOpts), ctypes.c_uint64, _vp, _vp]
+        L.daic_select_frontier_noalloc._typed = True
+    n = v.numel()
+    if dv.numel() != n or sel_out.numel() != n:
+        raise ValueError("v, dv and sel_out must have n entries")
+    check(L.daic_select_frontier_noalloc(op, st, n, _addr(v), _addr(dv), ctypes.byref(o), round_no,
+                                         _addr(sel_out), _addr(tau_out)),
+          "daic_select_frontier_noalloc")
