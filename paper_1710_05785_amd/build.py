@@ -8,13 +8,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdaic.so")
 SOURCES = ["daic_runtime.hip", "daic_pull.hip", "daic_batch.hip", "daic_sched.hip", "daic_sweep.hip",
-           "daic_check.hip", "daic_state.hip", "daic_noalloc.hip"]
+           "daic_check.hip", "daic_state.hip", "daic_noalloc.hip", "daic_tile.hip"]
 
 # Packed FP32 instructions are disabled for all device code; FP atomics map
 # to the hardware instructions (the target memory is coarse-grained).
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
-    "-munsafe-fp-atomics",
+    "-munsafe-fp-atomics", "-Wl,--no-undefined",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # MFMA results in ordinary VGPRs: the network kernels apply ReLU and BF16
     # conversion to every output, which would otherwise copy each one out of

@@ -70,4 +70,18 @@ __device__ __forceinline__ T block_sum256(T x) {
   return t;
 }
 
+// Sum over a block of NW waves (every thread must call it).
+template <int NW, typename T>
+__device__ __forceinline__ T block_sum_waves(T x) {
+  __shared__ T s_w[NW];
+  x = wave_sum(x);
+  if (lane_id() == 0) s_w[threadIdx.x >> 6] = x;
+  __syncthreads();
+  T t = s_w[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) t += s_w[w];
+  __syncthreads();
+  return t;
+}
+
 }  // namespace daic

@@ -128,9 +128,39 @@ struct PullGraph {
 };
 }  // namespace daic
 
+namespace daic {
+// Partition-tiled in-edge form of the fused dense round. Targets are cut into
+// partitions of kTileT consecutive ids. Inside a partition the in-edges are
+// sorted by (renumbered source, target), so the in-edges one source sends
+// into the partition are consecutive: such a run is a "pair" (source,
+// partition) whose message base is gathered once. A partition's in-edges are
+// cut into tiles of at most kTileE; a partition with one tile is summed and
+// finished by one workgroup, the tiles of a larger one store partial sums that
+// a finishing kernel adds in tile order.
+constexpr uint32_t kTileT = 8192;      // targets per partition (local ids fit 13 bits)
+constexpr uint32_t kTileE = 131072;    // in-edges per tile
+constexpr uint16_t kPairStart = 0x8000;  // flag of a pair's first in-edge in tloc
+struct TileGraph {
+  bool ready = false;
+  uint64_t n_part = 0, n_tiles = 0, n_pairs = 0, n_split = 0, n_slots = 0, n_seg = 0;
+  uint16_t* tloc = nullptr;        // [m] target - partition base, | kPairStart at a pair's first in-edge
+  uint32_t* psrc = nullptr;        // [n_pairs] renumbered source of each pair
+  uint32_t* segpair = nullptr;     // [n_seg] pair of the first in-edge of each 64-in-edge segment
+  uint32_t* eid = nullptr;         // [m] original edge index (weights in tile order)
+  uint32_t* tile_part = nullptr;   // [n_tiles] partition of each tile
+  uint32_t* tile_e = nullptr;      // [n_tiles + 1] first in-edge of each tile (tiles are contiguous)
+  uint32_t* tile_slot = nullptr;   // [n_tiles] partial-sum slot, or 0xFFFFFFFF (partition of one tile)
+  uint32_t* split_part = nullptr;  // [n_split] partitions of several tiles
+  uint32_t* split_slot = nullptr;  // [n_split + 1] their first slot (slots of one partition are consecutive)
+};
+daic_status tile_prepare(daic_graph* g, hipStream_t s);
+void tile_release(daic_graph* g);
+}  // namespace daic
+
 struct daic_graph {
   daic::GraphDev dev;
   daic::PullGraph pull;
+  daic::TileGraph tile;
   void* own_row = nullptr;      // owned allocations (null when borrowed)
   void* own_col = nullptr;
   void* own_w = nullptr;

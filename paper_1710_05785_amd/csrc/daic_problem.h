@@ -8,6 +8,7 @@
 
 #include "daic_internal.h"
 #include "daic_kernels.h"
+#include "daic_tile.h"
 
 namespace daic {
 struct SweepState;  // per-problem state of SWEEP scheduling (built on first use)
@@ -55,6 +56,18 @@ struct daic_problem {
   std::vector<void*> allocs;
   bool pull_ready = false;
   uint64_t stream_grid = 16384;  // workgroups of k_pull_stream
+  // tiled fused dense rounds (the graph's TileGraph plus per-problem buffers)
+  bool tile_ready = false;
+  double* tile_pbuf = nullptr;   // partial-sum slots of split partitions
+  void* tile_w = nullptr;        // weights in tile order (EDGE_SCALE)
+  double* tpart_r = nullptr;     // per-workgroup partials of k_tile_pull / k_tile_finish
+  uint64_t* tpart_a = nullptr;
+  uint64_t* tpart_p = nullptr;
+  double* spart_r = nullptr;
+  uint64_t* spart_a = nullptr;
+  uint64_t* spart_p = nullptr;
+  uint32_t tile_grid = 2048;     // workgroups of k_tile_pull (at most; two 64 KiB-LDS workgroups fit a CU)
+  uint32_t tfin_grid = 1024;     // workgroups of k_tile_finish (at most)
   uint64_t k_sel = 0;      // dense-round rule of the current run (see k_residual)
   uint64_t pull_min = 0;
   // learned scheduler state (allocated on first use)

@@ -183,8 +183,54 @@ struct Impl {
     }
   }
 
+  static TileArgs tile_args(const daic_problem* p) {
+    const TileGraph& T = p->g->tile;
+    TileArgs t{};
+    t.tloc = T.tloc;
+    t.psrc = T.psrc;
+    t.segpair = T.segpair;
+    t.wtile = p->tile_w;
+    t.tile_part = T.tile_part;
+    t.tile_e = T.tile_e;
+    t.tile_slot = T.tile_slot;
+    t.split_part = T.split_part;
+    t.split_slot = T.split_slot;
+    t.pbuf = p->tile_pbuf;
+    t.m = p->g->dev.m;
+    t.n_tiles = T.n_tiles;
+    t.n_split = T.n_split;
+    t.n_seg = T.n_seg;
+    t.tpart_r = p->tpart_r;
+    t.tpart_a = p->tpart_a;
+    t.tpart_p = p->tpart_p;
+    t.spart_r = p->spart_r;
+    t.spart_a = p->spart_a;
+    t.spart_p = p->spart_p;
+    return t;
+  }
+  static uint32_t tile_pull_grid(const daic_problem* p) {
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->g->tile.n_tiles, p->tile_grid));
+  }
+  static uint32_t tile_finish_grid(const daic_problem* p) {
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->g->tile.n_split * (kTileT / 256), p->tfin_grid));
+  }
+
   static void fused_round(daic_problem* p, hipStream_t s, Prof* pr) {
     if constexpr (Tr<ST>::sum) {
+      if (p->tile_ready) {
+        const TileArgs t = tile_args(p);
+        const uint32_t np = tile_pull_grid(p), nfin = tile_finish_grid(p);
+        launch(pr, "tile_pull", s, [&] {
+          hipLaunchKernelGGL((k_tile_pull<ST, G>), dim3(np), dim3(kTileThreads), 0, s, p->a, t);
+        });
+        launch(pr, "tile_finish", s, [&] {
+          hipLaunchKernelGGL((k_tile_finish<ST, G>), dim3(nfin), dim3(256), 0, s, p->a, t);
+        });
+        launch(pr, "tile_total", s, [&] {
+          hipLaunchKernelGGL(k_tile_total<ST>, dim3(1), dim3(256), 0, s, p->a, t, np, nfin);
+        });
+        return;
+      }
       const uint32_t nf = fused_grid(p);
       launch(pr, "pull_fused", s, [&] {
         hipLaunchKernelGGL((k_pull_fused<ST, G>), dim3(nf), dim3(256), 0, s, p->a);
@@ -415,6 +461,43 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
       p->exec = nullptr;
     }
   }
+  // the tiled form of fused dense rounds, built when they can run (every
+  // pending vertex per round); DAIC_NO_TILE=1 keeps the streamed form
+  if (!p->tile_ready && o->sched == DAIC_SCHED_ALL && !std::getenv("DAIC_NO_TILE") && !std::getenv("DAIC_NO_FUSE")) {
+    daic_graph* g = const_cast<daic_graph*>(p->g);
+    daic_status rc = tile_prepare(g, s);
+    if (rc) return rc;
+    const TileGraph& T = g->tile;
+    auto grab = [&](void** q, uint64_t bytes) -> daic_status {
+      DAIC_HIP(hipMalloc(q, std::max<uint64_t>(bytes, 8)));
+      p->allocs.push_back(*q);
+      return DAIC_OK;
+    };
+    if ((rc = grab((void**)&p->tile_pbuf, T.n_slots * (uint64_t)kTileT * 8)) ||
+        (rc = grab((void**)&p->tpart_r, (uint64_t)p->tile_grid * 8)) ||
+        (rc = grab((void**)&p->tpart_a, (uint64_t)p->tile_grid * 8)) ||
+        (rc = grab((void**)&p->tpart_p, (uint64_t)p->tile_grid * 8)) ||
+        (rc = grab((void**)&p->spart_r, (uint64_t)p->tfin_grid * 8)) ||
+        (rc = grab((void**)&p->spart_a, (uint64_t)p->tfin_grid * 8)) ||
+        (rc = grab((void**)&p->spart_p, (uint64_t)p->tfin_grid * 8)))
+      return rc;
+    if (p->gk == DAIC_G_EDGE_SCALE) {
+      const size_t S = state_size(p->st);
+      if ((rc = grab(&p->tile_w, d.m * S))) return rc;
+      if (p->st == ST_F64)
+        hipLaunchKernelGGL(k_gather_weights<double>, dim3(grid_for(d.m)), dim3(256), 0, s,
+                           static_cast<const double*>(p->a.w), T.eid, d.m, static_cast<double*>(p->tile_w));
+      else
+        hipLaunchKernelGGL(k_gather_weights<float>, dim3(grid_for(d.m)), dim3(256), 0, s,
+                           static_cast<const float*>(p->a.w), T.eid, d.m, static_cast<float*>(p->tile_w));
+    }
+    DAIC_HIP(hipStreamSynchronize(s));
+    p->tile_ready = true;
+    if (p->exec_fused) {  // captured fused rounds predate the tiled kernels
+      (void)hipGraphExecDestroy(p->exec_fused);
+      p->exec_fused = nullptr;
+    }
+  }
   uint64_t div = 32;
   if (const char* e = std::getenv("DAIC_PULL_DIV")) div = std::max<uint64_t>(1, std::strtoull(e, nullptr, 10));
   const uint64_t n = d.n;
@@ -523,6 +606,7 @@ void daic_graph_destroy(daic_graph* g) {
   dfree(g->row32);
   dfree(g->large_off);
   pull_release(g);
+  tile_release(g);
   delete g;
 }
 
@@ -978,6 +1062,25 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
     const double nf = (double)std::max<uint64_t>(1, std::min<uint64_t>(P.sb_count, p->stream_grid));
     return (double)pieces * 8.0 + (double)P.n_groups * (4.0 + 4.0 + 4.0 * S + kahan + 2.0 * R + 4.0 + S) + nf * 24.0;
   }
+  if (!std::strcmp(name, "tile_pull") || !std::strcmp(name, "tile_finish")) {
+    // tile_pull: per in-edge its local target 2 (+ weight S), per (source,
+    // partition) pair the source 4 and its base S, per 64 in-edges the
+    // segment's pair 4, per tile 12, and the finish of every target of the
+    // partitions of one tile as below; the tiles of split partitions store
+    // their partial sums 8 per target. tile_finish: the slots read back 8 per
+    // target and tile, and the finish of those targets. The finish of a
+    // target: dv read and write 2S, v read and write 2S (+ Kahan term 8),
+    // out-edge offsets 2R, renumbering 4, base written S.
+    const TileGraph& T = p->g->tile;
+    const double kahan = p->st == ST_F32K ? 8.0 : 0.0;
+    const double fin = 2.0 * S + 2.0 * S + kahan + 2.0 * R + 4.0 + S;
+    const double split_targets = (double)T.n_split * kTileT;  // upper bound (the last partition may be short)
+    const double slots = (double)T.n_slots * kTileT * 8.0;
+    if (name[5] == 'p')
+      return (double)p->g->dev.m * (2.0 + (p->gk == DAIC_G_EDGE_SCALE ? S : 0.0)) + (double)T.n_pairs * (4.0 + S) +
+             (double)T.n_seg * 4.0 + (double)T.n_tiles * 12.0 + std::max(0.0, n - split_targets) * fin + slots;
+    return slots + std::min(n, split_targets) * fin;
+  }
   if (!std::strcmp(name, "pull_fused")) {
     // the pull as above (descriptor 16 per block, in-edge offsets 2R per
     // target) and the claim of every vertex: dv read and write 2S, v read
@@ -1061,7 +1164,8 @@ daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, 
       k.alg_bytes += kernel_bytes(p, r.name, c);
       if (!std::strcmp(r.name, "push_small")) k.edges += (double)(c.round_pushed - c.round_pushed_large);
       if (!std::strcmp(r.name, "push_large")) k.edges += (double)c.round_pushed_large;
-      if (!std::strcmp(r.name, "pull_stream") || !std::strcmp(r.name, "pull_fused")) k.edges += (double)p->g->dev.m;
+      if (!std::strcmp(r.name, "pull_stream") || !std::strcmp(r.name, "pull_fused") || !std::strcmp(r.name, "tile_pull"))
+        k.edges += (double)p->g->dev.m;
     }
     if (c.done || c.stop) break;
   }

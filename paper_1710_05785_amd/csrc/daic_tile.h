@@ -1,0 +1,244 @@
+// Device code of the tiled fused dense round (layout in daic_internal.h).
+//
+// Round r of Eq. sync over every pending vertex, as k_pull_fused computes it
+// (pull of round r's message bases, then for every target the fold of its
+// previous delta into v, the new delta kept in dv and the base of the new
+// delta published for round r + 1), with the in-edges walked partition by
+// partition in source order:
+//   k_tile_pull  : a workgroup per tile. Each run of in-edges from one source
+//                  into the partition gathers that source's base once; every
+//                  in-edge adds it (times its weight) into an FP64 LDS
+//                  accumulator of its target. A partition of one tile is then
+//                  finished by the same workgroup; a tile of a larger one
+//                  stores its accumulators as a partial-sum slot.
+//   k_tile_finish: targets of partitions with several tiles: their slots added
+//                  in tile order (FP64), then finished.
+//   k_tile_total : the round's residual and counters from the per-workgroup
+//                  partials, in a fixed order, and the stop rule.
+// The kernels only store: no fences, tickets or global atomics.
+#pragma once
+
+#include "daic_device.h"
+#include "daic_internal.h"
+#include "daic_kernels.h"
+
+namespace daic {
+
+struct TileArgs {
+  const uint16_t* tloc;
+  const uint32_t* psrc;
+  const uint32_t* segpair;
+  const void* wtile;          // S[m] weights in tile order (EDGE_SCALE)
+  const uint32_t* tile_part;
+  const uint32_t* tile_e;
+  const uint32_t* tile_slot;
+  const uint32_t* split_part;
+  const uint32_t* split_slot;
+  double* pbuf;               // [n_slots][kTileT] partial sums of the tiles of split partitions
+  uint64_t m, n_tiles, n_split, n_seg;
+  double* tpart_r;            // per-workgroup partials of k_tile_pull: |new delta|,
+  uint64_t* tpart_a;          //   vertex updates,
+  uint64_t* tpart_p;          //   messages
+  double* spart_r;            // the same per workgroup of k_tile_finish
+  uint64_t* spart_a;
+  uint64_t* spart_p;
+};
+
+constexpr uint32_t kTileThreads = 512;
+constexpr uint32_t kTileWaves = kTileThreads / 64;
+constexpr uint32_t kTileU = 12;  // 64-in-edge segments a wave has in flight per step
+
+// Finishes targets [base + i] for i = tid, tid + 512, ... < count with new
+// deltas d(i), four targets per step with their operands loaded first.
+template <int ST, int G, typename D>
+__device__ __forceinline__ void tile_finish_targets(const KArgs& a, typename Tr<ST>::S* mu_out, uint64_t base,
+                                                    uint32_t count, uint32_t tid, uint32_t nthreads, const D& d,
+                                                    double& r_part, uint64_t& act, uint64_t& pushed) {
+  using S = typename Tr<ST>::S;
+  const S* dv = static_cast<const S*>(a.dv);
+  const S* v = static_cast<const S*>(a.v);
+  const uint32_t* row = static_cast<const uint32_t*>(a.row);
+  for (uint32_t i0 = tid; i0 < count; i0 += 4 * nthreads) {
+    S dvp[4], vp[4];
+    float cp[4];
+    uint32_t dg[4], pp[4];
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) {
+      const uint64_t t = base + min(i0 + u * nthreads, count - 1);
+      dvp[u] = dv[t];
+      vp[u] = v[t];
+      cp[u] = Tr<ST>::kahan ? a.c[t] : 0.f;
+      dg[u] = row[t + 1] - row[t];
+      pp[u] = a.perm[t];
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) {
+      const uint32_t i = i0 + u * nthreads;
+      if (i < count)
+        FusedTarget<ST, G>::finish(a, mu_out, (uint32_t)(base + i), dvp[u], (S)d(i), vp[u], cp[u], dg[u], pp[u], r_part,
+                                   act, pushed);
+    }
+  }
+}
+
+template <int ST, int G>
+__global__ __launch_bounds__(kTileThreads) void k_tile_pull(KArgs a, TileArgs t) {
+  using S = typename Tr<ST>::S;
+  if constexpr (Tr<ST>::sum) {
+    Ctl* ctl = a.ctl;
+    if (ctl_halted(ctl)) return;
+    __shared__ double acc[kTileT];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool odd = ((ctl->rounds - ctl->fuse_base) & 1) != 0;
+    const S* mu_in = static_cast<const S*>(odd ? a.mu_pi2 : a.mu_pi);
+    S* mu_out = static_cast<S*>(odd ? a.mu_pi : a.mu_pi2);
+    const S* wt = static_cast<const S*>(t.wtile);
+    // flags of segment positions 1..lane (position 0 belongs to the segment's pair)
+    const uint64_t upto = (lane == 63 ? ~0ull : ((2ull << lane) - 1)) & ~1ull;
+    double r_part = 0.0;
+    uint64_t act = 0, pushed = 0;
+    for (uint64_t tile = blockIdx.x; tile < t.n_tiles; tile += gridDim.x) {
+      const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
+      for (uint32_t i = tid; i < kTileT; i += kTileThreads) acc[i] = 0.0;
+      __syncthreads();
+      const uint64_t s0 = e0 >> 6, s1 = (e1 + 63) >> 6;  // 64-in-edge segments overlapping the tile
+      for (uint64_t sg = s0 + (uint64_t)wave * kTileU; sg < s1; sg += (uint64_t)kTileWaves * kTileU) {
+        uint32_t loc[kTileU], sp[kTileU];
+        uint64_t ec[kTileU];
+        bool in[kTileU];
+#pragma unroll
+        for (uint32_t u = 0; u < kTileU; ++u) {
+          const uint64_t seg = min(sg + u, t.n_seg - 1);
+          const uint64_t e = (sg + u) * 64 + lane;
+          in[u] = sg + u < s1 && e >= e0 && e < e1;
+          ec[u] = min(e, t.m - 1);
+          loc[u] = t.tloc[ec[u]];
+          sp[u] = t.segpair[seg];  // the same for the whole wave
+        }
+        uint32_t src[kTileU];
+#pragma unroll
+        for (uint32_t u = 0; u < kTileU; ++u) {
+          const uint64_t e = (sg + u) * 64 + lane;
+          const uint64_t flags = __ballot(e < t.m && (loc[u] & kPairStart) != 0);
+          const uint32_t pr = sp[u] + (uint32_t)__popcll(flags & upto);
+          src[u] = t.psrc[in[u] ? pr : sp[u]];
+        }
+        S mu[kTileU];
+        S w[kTileU];
+#pragma unroll
+        for (uint32_t u = 0; u < kTileU; ++u) {
+          mu[u] = mu_in[src[u]];
+          if constexpr (G == DAIC_G_EDGE_SCALE) w[u] = wt[ec[u]];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kTileU; ++u) {
+          double x = (double)mu[u];
+          if constexpr (G == DAIC_G_EDGE_SCALE) x *= (double)w[u];
+          if (in[u] && x != 0.0) atomicAdd(&acc[loc[u] & (kTileT - 1)], x);
+        }
+      }
+      __syncthreads();
+      const uint64_t base = (uint64_t)part * kTileT;
+      const uint32_t count = (uint32_t)min((uint64_t)kTileT, a.n - base);
+      if (slot == 0xFFFFFFFFu) {
+        tile_finish_targets<ST, G>(a, mu_out, base, count, tid, kTileThreads, [&](uint32_t i) { return acc[i]; },
+                                   r_part, act, pushed);
+      } else {
+        double* dst = t.pbuf + (uint64_t)slot * kTileT;
+        for (uint32_t i = tid; i < count; i += kTileThreads) dst[i] = acc[i];
+      }
+      __syncthreads();
+    }
+    r_part = block_sum_waves<kTileWaves>(r_part);
+    act = block_sum_waves<kTileWaves>(act);
+    pushed = block_sum_waves<kTileWaves>(pushed);
+    if (tid == 0) {
+      t.tpart_r[blockIdx.x] = r_part;
+      t.tpart_a[blockIdx.x] = act;
+      t.tpart_p[blockIdx.x] = pushed;
+    }
+  }
+}
+
+// Targets of split partitions: a work item is 256 consecutive targets of one
+// split partition; their slots are added in tile order, 16 loads in flight.
+template <int ST, int G>
+__global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
+  using S = typename Tr<ST>::S;
+  if constexpr (Tr<ST>::sum) {
+    Ctl* ctl = a.ctl;
+    if (ctl_halted(ctl)) return;
+    const bool odd = ((ctl->rounds - ctl->fuse_base) & 1) != 0;
+    S* mu_out = static_cast<S*>(odd ? a.mu_pi : a.mu_pi2);
+    const uint32_t tid = threadIdx.x;
+    constexpr uint32_t kChunks = kTileT / 256;
+    double r_part = 0.0;
+    uint64_t act = 0, pushed = 0;
+    for (uint64_t item = blockIdx.x; item < t.n_split * kChunks; item += gridDim.x) {
+      const uint64_t sp = item / kChunks;
+      const uint32_t chunk = (uint32_t)(item % kChunks);
+      const uint32_t part = t.split_part[sp], k0 = t.split_slot[sp], k1 = t.split_slot[sp + 1];
+      const uint64_t base = (uint64_t)part * kTileT + chunk * 256;
+      if (base >= a.n) continue;  // uniform
+      const uint32_t count = (uint32_t)min((uint64_t)256, a.n - base);
+      const uint32_t i = chunk * 256 + min(tid, count - 1);
+      double sum = 0.0;
+      for (uint32_t k = k0; k < k1; k += 16) {
+        double x[16];
+#pragma unroll
+        for (uint32_t u = 0; u < 16; ++u) x[u] = t.pbuf[(uint64_t)min(k + u, k1 - 1) * kTileT + i];
+#pragma unroll
+        for (uint32_t u = 0; u < 16; ++u)
+          if (k + u < k1) sum += x[u];
+      }
+      tile_finish_targets<ST, G>(a, mu_out, base, count, tid, 256, [&](uint32_t) { return sum; }, r_part, act, pushed);
+    }
+    r_part = block_sum256(r_part);
+    act = block_sum256(act);
+    pushed = block_sum256(pushed);
+    if (tid == 0) {
+      t.spart_r[blockIdx.x] = r_part;
+      t.spart_a[blockIdx.x] = act;
+      t.spart_p[blockIdx.x] = pushed;
+    }
+  }
+}
+
+// The round's totals (one block): partials of np k_tile_pull and nf
+// k_tile_finish workgroups in a fixed order; residual, counters, round count
+// and stop rule as k_fused_finish sets them.
+template <int ST>
+__global__ __launch_bounds__(256) void k_tile_total(KArgs a, TileArgs t, uint32_t np, uint32_t nf) {
+  if constexpr (Tr<ST>::sum) {
+    Ctl* ctl = a.ctl;
+    if (ctl_halted(ctl)) return;
+    double rr = 0.0;
+    uint64_t aa = 0, ps = 0;
+    for (uint32_t i = threadIdx.x; i < np; i += 256) {
+      rr += t.tpart_r[i];
+      aa += t.tpart_a[i];
+      ps += t.tpart_p[i];
+    }
+    for (uint32_t i = threadIdx.x; i < nf; i += 256) {
+      rr += t.spart_r[i];
+      aa += t.spart_a[i];
+      ps += t.spart_p[i];
+    }
+    rr = block_sum256(rr);
+    aa = block_sum256(aa);
+    ps = block_sum256(ps);
+    if (threadIdx.x == 0) {
+      ctl->r = rr;
+      ctl->rounds += 1;
+      ctl->activations += aa;
+      ctl->pushed += ps;
+      ctl->round_act = aa;
+      ctl->round_pushed = ps;
+      const bool done = rr <= ctl->eps;
+      ctl->done = done ? 1u : 0u;
+      ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
+    }
+  }
+}
+
+}  // namespace daic

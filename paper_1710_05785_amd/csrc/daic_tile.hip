@@ -1,0 +1,210 @@
+// Set-up of the partition-tiled in-edge form used by fused dense rounds
+// (layout in daic_internal.h): in-edges sorted by (partition of the target,
+// renumbered source, target) with a device radix sort, pair flags and pair
+// sources from a scan of the flags, and the tile table built on the host from
+// the partitions' in-edge counts.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <vector>
+
+#include "daic_internal.h"
+
+namespace daic {
+
+namespace {
+
+constexpr uint32_t kLocBits = 13;  // log2(kTileT)
+static_assert((1u << kLocBits) == kTileT, "partition width");
+
+uint32_t tgrid(uint64_t count) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((count + 255) / 256, 8192));
+}
+
+// One wave per source row: key = (partition << (sbits + 13)) | (rank << 13) | local target.
+__global__ __launch_bounds__(256) void k_tile_keys(const uint32_t* row, const uint32_t* col, const uint32_t* perm,
+                                                   uint64_t n, uint32_t sbits, uint64_t* keys, uint32_t* vals) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t j = wave; j < n; j += nwaves) {
+    const uint64_t rank = perm[j];
+    for (uint32_t e = row[j] + lane; e < row[j + 1]; e += 64) {
+      const uint64_t t = col[e];
+      keys[e] = ((t >> kLocBits) << (sbits + kLocBits)) | (rank << kLocBits) | (t & (kTileT - 1));
+      vals[e] = e;
+    }
+  }
+}
+
+// Pair flags (a new (partition, source) run starts), local targets and edge
+// indices in sorted order.
+__global__ void k_tile_flags(const uint64_t* keys, const uint32_t* vals, uint64_t m, uint32_t* flag, uint16_t* tloc,
+                             uint32_t* eid) {
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[p];
+    const bool start = p == 0 || (keys[p - 1] >> kLocBits) != (k >> kLocBits);
+    flag[p] = start ? 1u : 0u;
+    tloc[p] = (uint16_t)((k & (kTileT - 1)) | (start ? kPairStart : 0));
+    eid[p] = vals[p];
+  }
+}
+
+// Pair sources, the pair of each 64-in-edge segment's first in-edge, and the
+// first in-edge of every partition.
+__global__ void k_tile_pairs(const uint64_t* keys, const uint32_t* flag, const uint32_t* incl, uint64_t m,
+                             uint32_t sbits, uint64_t n_part, uint32_t* psrc, uint32_t* segpair, uint32_t* pstart) {
+  const uint64_t smask = (1ull << sbits) - 1;
+  const uint32_t pshift = sbits + kLocBits;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[p];
+    if (flag[p]) psrc[incl[p] - 1] = (uint32_t)((k >> kLocBits) & smask);
+    if ((p & 63) == 0) segpair[p >> 6] = incl[p] - 1;
+    const uint64_t part = k >> pshift;
+    const uint64_t prev = p == 0 ? 0 : (keys[p - 1] >> pshift) + 1;
+    for (uint64_t q = prev; q <= part; ++q) pstart[q] = (uint32_t)p;
+    if (p == m - 1)
+      for (uint64_t q = part + 1; q <= n_part; ++q) pstart[q] = (uint32_t)m;
+  }
+}
+
+}  // namespace
+
+void tile_release(daic_graph* g) {
+  TileGraph& t = g->tile;
+  for (void* q : {(void*)t.tloc, (void*)t.psrc, (void*)t.segpair, (void*)t.eid, (void*)t.tile_part, (void*)t.tile_e,
+                  (void*)t.tile_slot, (void*)t.split_part, (void*)t.split_slot})
+    if (q) (void)hipFree(q);
+  t = TileGraph();
+}
+
+daic_status tile_prepare(daic_graph* g, hipStream_t s) {
+  TileGraph& T = g->tile;
+  if (T.ready) return DAIC_OK;
+  if (!g->pull.ready) return fail(DAIC_E_INVALID, "tiled rounds need the renumbering of the in-edge form");
+  const GraphDev& d = g->dev;
+  const uint64_t n = d.n, m = d.m;
+  const uint32_t* row = static_cast<const uint32_t*>(d.row);
+  uint32_t sbits = 1;
+  while ((1ull << sbits) < n) ++sbits;
+  T.n_part = (n + kTileT - 1) / kTileT;
+  const uint32_t pbits_end = sbits + kLocBits + [&] {
+    uint32_t b = 1;
+    while ((1ull << b) < T.n_part + 1) ++b;
+    return b;
+  }();
+  uint64_t *k0 = nullptr, *k1 = nullptr;
+  uint32_t *v0 = nullptr, *v1 = nullptr, *flag = nullptr, *incl = nullptr;  // flag, incl: views of a key buffer
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  auto cleanup = [&]() {
+    for (void* q : {(void*)k0, (void*)k1, (void*)v0, (void*)v1, tmp})
+      if (q) (void)hipFree(q);
+  };
+#define TCHK(call)                                                                               \
+  do {                                                                                           \
+    hipError_t _e = (call);                                                                      \
+    if (_e != hipSuccess) {                                                                      \
+      cleanup();                                                                                 \
+      tile_release(g);                                                                           \
+      return fail(_e == hipErrorOutOfMemory ? DAIC_E_OOM : DAIC_E_DEVICE, "tiled-round set-up: %s: %s", #call, \
+                  hipGetErrorString(_e));                                                        \
+    }                                                                                            \
+  } while (0)
+  const uint64_t mm = std::max<uint64_t>(m, 1);
+  TCHK(hipMalloc(&T.tloc, mm * sizeof(uint16_t)));
+  TCHK(hipMalloc(&T.eid, mm * sizeof(uint32_t)));
+  T.n_seg = (m + 63) / 64;
+  TCHK(hipMalloc(&T.segpair, std::max<uint64_t>(T.n_seg, 1) * sizeof(uint32_t)));
+  std::vector<uint32_t> pstart(T.n_part + 1, 0);
+  if (m > 0) {
+    TCHK(hipMalloc(&k0, m * sizeof(uint64_t)));
+    TCHK(hipMalloc(&k1, m * sizeof(uint64_t)));
+    TCHK(hipMalloc(&v0, m * sizeof(uint32_t)));
+    TCHK(hipMalloc(&v1, m * sizeof(uint32_t)));
+    hipLaunchKernelGGL(k_tile_keys, dim3(std::max<uint64_t>(1, std::min<uint64_t>((n + 3) / 4, 8192))), dim3(256), 0,
+                       s, row, d.col, g->pull.perm, n, sbits, k0, v0);
+    hipcub::DoubleBuffer<uint64_t> kb(k0, k1);
+    hipcub::DoubleBuffer<uint32_t> vb(v0, v1);
+    size_t need = 0;
+    TCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kb, vb, (int)m, 0, (int)pbits_end, s));
+    TCHK(hipMalloc(&tmp, need));
+    tmp_bytes = need;
+    TCHK(hipcub::DeviceRadixSort::SortPairs(tmp, need, kb, vb, (int)m, 0, (int)pbits_end, s));
+    // the buffers not holding the sorted data take the flags and their scan
+    flag = kb.Current() == k0 ? reinterpret_cast<uint32_t*>(k1) : reinterpret_cast<uint32_t*>(k0);
+    incl = flag + m;  // the other half of the 8-byte-per-edge buffer
+    hipLaunchKernelGGL(k_tile_flags, dim3(tgrid(m)), dim3(256), 0, s, kb.Current(), vb.Current(), m, flag, T.tloc,
+                       T.eid);
+    size_t need2 = 0;
+    TCHK(hipcub::DeviceScan::InclusiveSum(nullptr, need2, flag, incl, (int)m, s));
+    if (need2 > tmp_bytes) {
+      (void)hipFree(tmp);
+      tmp = nullptr;
+      TCHK(hipMalloc(&tmp, need2));
+      tmp_bytes = need2;
+    }
+    TCHK(hipcub::DeviceScan::InclusiveSum(tmp, need2, flag, incl, (int)m, s));
+    uint32_t npairs = 0;
+    TCHK(hipMemcpyAsync(&npairs, incl + (m - 1), 4, hipMemcpyDeviceToHost, s));
+    TCHK(hipStreamSynchronize(s));
+    T.n_pairs = npairs;
+    TCHK(hipMalloc(&T.psrc, std::max<uint64_t>(npairs, 1) * sizeof(uint32_t)));
+    uint32_t* dpstart = v0 == vb.Current() ? v1 : v0;  // the free value buffer holds m entries
+    uint32_t* own_pstart = nullptr;
+    if (T.n_part + 1 > m) {
+      TCHK(hipMalloc(&own_pstart, (T.n_part + 1) * sizeof(uint32_t)));
+      dpstart = own_pstart;
+    }
+    hipLaunchKernelGGL(k_tile_pairs, dim3(tgrid(m)), dim3(256), 0, s, kb.Current(), flag, incl, m, sbits, T.n_part,
+                       T.psrc, T.segpair, dpstart);
+    hipError_t e = hipMemcpyAsync(pstart.data(), dpstart, (T.n_part + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (own_pstart) (void)hipFree(own_pstart);
+    TCHK(e);
+  } else {
+    TCHK(hipMalloc(&T.psrc, sizeof(uint32_t)));
+  }
+  cleanup();
+  k0 = k1 = nullptr;
+  v0 = v1 = nullptr;
+  tmp = nullptr;
+  // tiles: every partition has at least one (its targets are finished by
+  // it); a partition with more than kTileE in-edges gets consecutive slots
+  std::vector<uint32_t> tp, te, ts, sp, ss;
+  uint32_t slots = 0;
+  for (uint64_t p = 0; p < T.n_part; ++p) {
+    const uint64_t a = pstart[p], b = pstart[p + 1];
+    const uint64_t nt = std::max<uint64_t>(1, (b - a + kTileE - 1) / kTileE);
+    if (nt > 1) {
+      sp.push_back((uint32_t)p);
+      ss.push_back(slots);
+    }
+    for (uint64_t k = 0; k < nt; ++k) {
+      tp.push_back((uint32_t)p);
+      te.push_back((uint32_t)(a + k * kTileE));
+      ts.push_back(nt > 1 ? slots++ : 0xFFFFFFFFu);
+    }
+  }
+  te.push_back((uint32_t)m);
+  ss.push_back(slots);
+  T.n_tiles = tp.size();
+  T.n_split = sp.size();
+  T.n_slots = slots;
+  TCHK(hipMalloc(&T.tile_part, tp.size() * 4));
+  TCHK(hipMalloc(&T.tile_e, te.size() * 4));
+  TCHK(hipMalloc(&T.tile_slot, ts.size() * 4));
+  TCHK(hipMalloc(&T.split_part, std::max<size_t>(sp.size(), 1) * 4));
+  TCHK(hipMalloc(&T.split_slot, ss.size() * 4));
+  TCHK(hipMemcpy(T.tile_part, tp.data(), tp.size() * 4, hipMemcpyHostToDevice));
+  TCHK(hipMemcpy(T.tile_e, te.data(), te.size() * 4, hipMemcpyHostToDevice));
+  TCHK(hipMemcpy(T.tile_slot, ts.data(), ts.size() * 4, hipMemcpyHostToDevice));
+  if (!sp.empty()) TCHK(hipMemcpy(T.split_part, sp.data(), sp.size() * 4, hipMemcpyHostToDevice));
+  TCHK(hipMemcpy(T.split_slot, ss.data(), ss.size() * 4, hipMemcpyHostToDevice));
+#undef TCHK
+  T.ready = true;
+  return DAIC_OK;
+}
+
+}  // namespace daic

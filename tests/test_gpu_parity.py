@@ -115,15 +115,23 @@ def test_pagerank_rmat_f64_and_kahan(daic, scale, ef, seed):
     assert np.abs(pk.get() - ref).sum() / ref.sum() <= 1e-5
 
 
+@pytest.mark.parametrize("tiled", [True, False])
 @pytest.mark.parametrize("state,gk", [("f32_kahan", "deg"), ("f64", "deg"), ("f32", "edge")])
-def test_fused_dense_rounds_match_plain_rounds(daic, monkeypatch, state, gk):
+def test_fused_dense_rounds_match_plain_rounds(daic, monkeypatch, state, gk, tiled):
     """Dense rounds with every pending vertex run as one fused kernel per
     round (pull, then the claim work of the next round). They must give the
     plain rounds' state after the same number of rounds, with the same work
     counters: to convergence and when stopped by the round limit. RMAT-16
     with edge factor 16 has targets with more than 2,048 in-edges, which the
-    fused round finishes through per-group tickets."""
-    say("case fused vs plain", state, gk)
+    fused round finishes through per-group tickets. tiled: the fused round
+    walks partitions of 8,192 targets in source order (one gather per
+    source and partition); RMAT-16 has partitions cut into several tiles,
+    whose partial sums a finishing kernel adds."""
+    say("case fused vs plain", state, gk, "tiled", tiled)
+    if not tiled:
+        monkeypatch.setenv("DAIC_NO_TILE", "1")
+    else:
+        monkeypatch.delenv("DAIC_NO_TILE", raising=False)
     g = daic_gen.rmat(16, 16, seed=41)
     indeg = np.bincount(g.col, minlength=g.n)
     assert indeg.max() > 2048
@@ -211,10 +219,13 @@ def test_profile_matches_run_and_accounts_the_pull(daic, monkeypatch):
         va, vb = a.get(), b.get()
         assert np.abs(va - vb).sum() <= 2e-6 * np.abs(va).sum()
         names = {k["name"]: k for k in ks}
-        pull = names["pull_fused" if fuse else "pull_stream"]
+        pull = names[("tile_pull" if "tile_pull" in names else "pull_fused") if fuse else "pull_stream"]
         assert pull["launches"] == rb.stats["rounds"]
         assert pull["edges"] == pull["launches"] * g.m
-        assert pull["alg_bytes"] >= pull["edges"] * 8 and pull["total_ms"] > 0
+        # the streamed pull reads a source and a base per in-edge; the tiled
+        # one a 2-byte target per in-edge and a source and base per pair
+        per_edge = 2 if pull["name"] == "tile_pull" else 8
+        assert pull["alg_bytes"] >= pull["edges"] * per_edge and pull["total_ms"] > 0
         if not fuse:
             assert {"claim", "pull_finish"} <= set(names)
             assert names["pull_finish"]["launches"] == pull["launches"]
