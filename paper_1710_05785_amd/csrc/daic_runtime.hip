@@ -141,7 +141,19 @@ struct Impl {
     launch(pr, "push_large", s, [&] {
       hipLaunchKernelGGL((k_push_large<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
     });
-    if (p->pull_ready) {
+    if (p->pull_ready && p->tile_ready) {  // dense rounds through the tiled in-edges
+      const TileArgs t = tile_args(p);
+      const uint32_t np = tile_pull_grid(p), nfin = tile_finish_grid(p);
+      launch(pr, "pull_tile", s, [&] {
+        hipLaunchKernelGGL((k_tile_pull<ST, G, false>), dim3(np), dim3(kTileThreads), 0, s, a, t);
+      });
+      launch(pr, "pull_tile_finish", s, [&] {
+        hipLaunchKernelGGL((k_tile_finish<ST, G, false>), dim3(nfin), dim3(256), 0, s, a, t);
+      });
+      launch(pr, "pull_tile_total", s, [&] {
+        hipLaunchKernelGGL((k_tile_total<ST, false>), dim3(1), dim3(256), 0, s, a, t, np, nfin, p->k_sel, p->pull_min);
+      });
+    } else if (p->pull_ready) {
       const uint32_t nf = fused_grid(p);
       launch(pr, "pull_stream", s, [&] {
         hipLaunchKernelGGL((k_pull_stream<ST, G>), dim3(nf), dim3(256), 0, s, a);
@@ -221,13 +233,13 @@ struct Impl {
         const TileArgs t = tile_args(p);
         const uint32_t np = tile_pull_grid(p), nfin = tile_finish_grid(p);
         launch(pr, "tile_pull", s, [&] {
-          hipLaunchKernelGGL((k_tile_pull<ST, G>), dim3(np), dim3(kTileThreads), 0, s, p->a, t);
+          hipLaunchKernelGGL((k_tile_pull<ST, G, true>), dim3(np), dim3(kTileThreads), 0, s, p->a, t);
         });
         launch(pr, "tile_finish", s, [&] {
-          hipLaunchKernelGGL((k_tile_finish<ST, G>), dim3(nfin), dim3(256), 0, s, p->a, t);
+          hipLaunchKernelGGL((k_tile_finish<ST, G, true>), dim3(nfin), dim3(256), 0, s, p->a, t);
         });
         launch(pr, "tile_total", s, [&] {
-          hipLaunchKernelGGL(k_tile_total<ST>, dim3(1), dim3(256), 0, s, p->a, t, np, nfin);
+          hipLaunchKernelGGL((k_tile_total<ST, true>), dim3(1), dim3(256), 0, s, p->a, t, np, nfin, 0ull, 0ull);
         });
         return;
       }
@@ -461,9 +473,9 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
       p->exec = nullptr;
     }
   }
-  // the tiled form of fused dense rounds, built when they can run (every
-  // pending vertex per round); DAIC_NO_TILE=1 keeps the streamed form
-  if (!p->tile_ready && o->sched == DAIC_SCHED_ALL && !std::getenv("DAIC_NO_TILE") && !std::getenv("DAIC_NO_FUSE")) {
+  // the tiled in-edge form of dense rounds (fused and not); DAIC_NO_TILE=1
+  // keeps the streamed form
+  if (!p->tile_ready && !std::getenv("DAIC_NO_TILE")) {
     daic_graph* g = const_cast<daic_graph*>(p->g);
     daic_status rc = tile_prepare(g, s);
     if (rc) return rc;
@@ -1062,6 +1074,17 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
     const double nf = (double)std::max<uint64_t>(1, std::min<uint64_t>(P.sb_count, p->stream_grid));
     return (double)pieces * 8.0 + (double)P.n_groups * (4.0 + 4.0 + 4.0 * S + kahan + 2.0 * R + 4.0 + S) + nf * 24.0;
   }
+  if (!std::strcmp(name, "pull_tile") || !std::strcmp(name, "pull_tile_finish")) {
+    // as tile_pull / tile_finish below with a target's finish reduced to its
+    // dv read and written (2S): the claim of these rounds ran before
+    const TileGraph& T = p->g->tile;
+    const double split_targets = (double)T.n_split * kTileT;
+    const double slots = (double)T.n_slots * kTileT * 8.0;
+    if (!std::strcmp(name, "pull_tile"))
+      return (double)p->g->dev.m * (2.0 + (p->gk == DAIC_G_EDGE_SCALE ? S : 0.0)) + (double)T.n_pairs * (4.0 + S) +
+             (double)T.n_seg * 4.0 + (double)T.n_tiles * 12.0 + std::max(0.0, n - split_targets) * 2.0 * S + slots;
+    return slots + std::min(n, split_targets) * 2.0 * S;
+  }
   if (!std::strcmp(name, "tile_pull") || !std::strcmp(name, "tile_finish")) {
     // tile_pull: per in-edge its local target 2 (+ weight S), per (source,
     // partition) pair the source 4 and its base S, per 64 in-edges the
@@ -1164,7 +1187,8 @@ daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, 
       k.alg_bytes += kernel_bytes(p, r.name, c);
       if (!std::strcmp(r.name, "push_small")) k.edges += (double)(c.round_pushed - c.round_pushed_large);
       if (!std::strcmp(r.name, "push_large")) k.edges += (double)c.round_pushed_large;
-      if (!std::strcmp(r.name, "pull_stream") || !std::strcmp(r.name, "pull_fused") || !std::strcmp(r.name, "tile_pull"))
+      if (!std::strcmp(r.name, "pull_stream") || !std::strcmp(r.name, "pull_fused") || !std::strcmp(r.name, "tile_pull") ||
+          !std::strcmp(r.name, "pull_tile"))
         k.edges += (double)p->g->dev.m;
     }
     if (c.done || c.stop) break;

@@ -16,6 +16,12 @@
 //   k_tile_total : the round's residual and counters from the per-workgroup
 //                  partials, in a fixed order, and the stop rule.
 // The kernels only store: no fences, tickets or global atomics.
+//
+// The same kernels run the dense rounds of the other selection rules
+// (FUSED = false): the round's claim has already folded the selected deltas
+// and published their bases (0 for the others) into the first buffer, so a
+// target only adds its sum into dv; the totals then also set the pending
+// count and the direction of the next round, as k_pull_finish does.
 #pragma once
 
 #include "daic_device.h"
@@ -50,11 +56,33 @@ constexpr uint32_t kTileU = 12;  // 64-in-edge segments a wave has in flight per
 
 // Finishes targets [base + i] for i = tid, tid + 512, ... < count with new
 // deltas d(i), four targets per step with their operands loaded first.
-template <int ST, int G, typename D>
+template <int ST, int G, bool FUSED, typename D>
 __device__ __forceinline__ void tile_finish_targets(const KArgs& a, typename Tr<ST>::S* mu_out, uint64_t base,
                                                     uint32_t count, uint32_t tid, uint32_t nthreads, const D& d,
                                                     double& r_part, uint64_t& act, uint64_t& pushed) {
   using S = typename Tr<ST>::S;
+  if constexpr (!FUSED) {  // dv += sum; act counts the pending vertices of the new state
+    S* dvw = static_cast<S*>(a.dv);
+    for (uint32_t i0 = tid; i0 < count; i0 += 4 * nthreads) {
+      S dvp[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) dvp[u] = dvw[base + min(i0 + u * nthreads, count - 1)];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) {
+        const uint32_t i = i0 + u * nthreads;
+        if (i >= count) break;
+        const double x = d(i);
+        S nd = dvp[u];
+        if (x != 0.0) {
+          nd = (S)((double)dvp[u] + x);
+          dvw[base + i] = nd;
+        }
+        r_part += fabs((double)nd);
+        act += nd != (S)0 ? 1 : 0;
+      }
+    }
+    return;
+  }
   const S* dv = static_cast<const S*>(a.dv);
   const S* v = static_cast<const S*>(a.v);
   const uint32_t* row = static_cast<const uint32_t*>(a.row);
@@ -81,15 +109,15 @@ __device__ __forceinline__ void tile_finish_targets(const KArgs& a, typename Tr<
   }
 }
 
-template <int ST, int G>
+template <int ST, int G, bool FUSED>
 __global__ __launch_bounds__(kTileThreads) void k_tile_pull(KArgs a, TileArgs t) {
   using S = typename Tr<ST>::S;
   if constexpr (Tr<ST>::sum) {
     Ctl* ctl = a.ctl;
-    if (ctl_halted(ctl)) return;
+    if (ctl_halted(ctl) || (!FUSED && !ctl->last_pull)) return;
     __shared__ double acc[kTileT];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool odd = ((ctl->rounds - ctl->fuse_base) & 1) != 0;
+    const bool odd = FUSED && ((ctl->rounds - ctl->fuse_base) & 1) != 0;
     const S* mu_in = static_cast<const S*>(odd ? a.mu_pi2 : a.mu_pi);
     S* mu_out = static_cast<S*>(odd ? a.mu_pi : a.mu_pi2);
     const S* wt = static_cast<const S*>(t.wtile);
@@ -141,8 +169,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pull(KArgs a, TileArgs t)
       const uint64_t base = (uint64_t)part * kTileT;
       const uint32_t count = (uint32_t)min((uint64_t)kTileT, a.n - base);
       if (slot == 0xFFFFFFFFu) {
-        tile_finish_targets<ST, G>(a, mu_out, base, count, tid, kTileThreads, [&](uint32_t i) { return acc[i]; },
-                                   r_part, act, pushed);
+        tile_finish_targets<ST, G, FUSED>(a, mu_out, base, count, tid, kTileThreads,
+                                          [&](uint32_t i) { return acc[i]; }, r_part, act, pushed);
       } else {
         double* dst = t.pbuf + (uint64_t)slot * kTileT;
         for (uint32_t i = tid; i < count; i += kTileThreads) dst[i] = acc[i];
@@ -162,13 +190,13 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pull(KArgs a, TileArgs t)
 
 // Targets of split partitions: a work item is 256 consecutive targets of one
 // split partition; their slots are added in tile order, 16 loads in flight.
-template <int ST, int G>
+template <int ST, int G, bool FUSED>
 __global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
   using S = typename Tr<ST>::S;
   if constexpr (Tr<ST>::sum) {
     Ctl* ctl = a.ctl;
-    if (ctl_halted(ctl)) return;
-    const bool odd = ((ctl->rounds - ctl->fuse_base) & 1) != 0;
+    if (ctl_halted(ctl) || (!FUSED && !ctl->last_pull)) return;
+    const bool odd = FUSED && ((ctl->rounds - ctl->fuse_base) & 1) != 0;
     S* mu_out = static_cast<S*>(odd ? a.mu_pi : a.mu_pi2);
     const uint32_t tid = threadIdx.x;
     constexpr uint32_t kChunks = kTileT / 256;
@@ -191,7 +219,8 @@ __global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
         for (uint32_t u = 0; u < 16; ++u)
           if (k + u < k1) sum += x[u];
       }
-      tile_finish_targets<ST, G>(a, mu_out, base, count, tid, 256, [&](uint32_t) { return sum; }, r_part, act, pushed);
+      tile_finish_targets<ST, G, FUSED>(a, mu_out, base, count, tid, 256, [&](uint32_t) { return sum; }, r_part, act,
+                                        pushed);
     }
     r_part = block_sum256(r_part);
     act = block_sum256(act);
@@ -206,12 +235,14 @@ __global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
 
 // The round's totals (one block): partials of np k_tile_pull and nf
 // k_tile_finish workgroups in a fixed order; residual, counters, round count
-// and stop rule as k_fused_finish sets them.
-template <int ST>
-__global__ __launch_bounds__(256) void k_tile_total(KArgs a, TileArgs t, uint32_t np, uint32_t nf) {
+// and stop rule as k_fused_finish sets them (FUSED), or residual, pending
+// count, round count, stop rule and next direction as k_pull_finish does.
+template <int ST, bool FUSED>
+__global__ __launch_bounds__(256) void k_tile_total(KArgs a, TileArgs t, uint32_t np, uint32_t nf, uint64_t k_sel,
+                                                    uint64_t pull_min) {
   if constexpr (Tr<ST>::sum) {
     Ctl* ctl = a.ctl;
-    if (ctl_halted(ctl)) return;
+    if (ctl_halted(ctl) || (!FUSED && !ctl->last_pull)) return;
     double rr = 0.0;
     uint64_t aa = 0, ps = 0;
     for (uint32_t i = threadIdx.x; i < np; i += 256) {
@@ -230,13 +261,22 @@ __global__ __launch_bounds__(256) void k_tile_total(KArgs a, TileArgs t, uint32_
     if (threadIdx.x == 0) {
       ctl->r = rr;
       ctl->rounds += 1;
-      ctl->activations += aa;
-      ctl->pushed += ps;
-      ctl->round_act = aa;
-      ctl->round_pushed = ps;
-      const bool done = rr <= ctl->eps;
-      ctl->done = done ? 1u : 0u;
-      ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
+      if constexpr (FUSED) {
+        ctl->activations += aa;
+        ctl->pushed += ps;
+        ctl->round_act = aa;
+        ctl->round_pushed = ps;
+        const bool done = rr <= ctl->eps;
+        ctl->done = done ? 1u : 0u;
+        ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
+      } else {
+        const uint64_t nn = aa;  // pending vertices of the new state
+        ctl->pending = nn;
+        const bool done = rr <= ctl->eps || nn == 0;
+        ctl->done = done ? 1u : 0u;
+        ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
+        ctl->pull = (k_sel != 0 && (nn < k_sel ? nn : k_sel) >= pull_min) ? 1u : 0u;
+      }
     }
   }
 }

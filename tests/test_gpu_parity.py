@@ -171,6 +171,50 @@ def test_fused_dense_rounds_match_plain_rounds(daic, monkeypatch, state, gk, til
         assert abs(rb.stats["final_residual"] - ra.stats["final_residual"]) <= tol * np.abs(va).sum()
 
 
+@pytest.mark.parametrize("state,gk", [("f32_kahan", "deg"), ("f64", "deg"), ("f32", "edge")])
+def test_tiled_unfused_dense_rounds_match_streamed(daic, monkeypatch, state, gk):
+    """Dense rounds that are not fused (the claim folds and publishes, the
+    pull adds into dv) through the tiled in-edges against the streamed pull:
+    the same rounds, updates and messages, and the same state, to
+    convergence and when stopped by the round limit. RMAT-16 has split
+    partitions; the run also decides the direction of every next round from
+    the tiled pull's pending count."""
+    say("case tiled unfused", state, gk)
+    monkeypatch.setenv("DAIC_NO_FUSE", "1")
+    g = daic_gen.rmat(16, 16, seed=43)
+    rng = np.random.default_rng(44)
+    w = None
+    if gk == "edge":
+        outdeg = np.diff(g.row_ptr).astype(np.float64)
+        src = np.repeat(np.arange(g.n), np.diff(g.row_ptr).astype(np.int64))
+        w = (rng.uniform(0.1, 1.0, g.m) / np.maximum(outdeg[src], 1.0)).astype(np.float32)
+
+    def make():
+        P = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.SUM,
+                         daic.G_EDGE_SCALE if w is not None else daic.G_DEG_SCALE, alpha=0.85, state=state)
+        P.set_init(np.zeros(g.n), np.full(g.n, 0.15))
+        return P
+
+    for max_rounds in (9, 0):
+        kw = dict(eps=1e-9 if state == "f64" else 1e-5, q=1.0, sched="all", rounds_per_check=4,
+                  max_rounds=max_rounds)
+        out = []
+        for tiled in (False, True):
+            if tiled:
+                monkeypatch.delenv("DAIC_NO_TILE", raising=False)
+            else:
+                monkeypatch.setenv("DAIC_NO_TILE", "1")
+            P = make()
+            r = P.run(**kw)
+            out.append((r, *P.get(with_dv=True)))
+        (ra, va, dva), (rb, vb, dvb) = out
+        for key in ("rounds", "activations", "pushed_edges"):
+            assert rb.stats[key] == ra.stats[key], (key, max_rounds, ra.stats, rb.stats)
+        tol = 1e-12 if state == "f64" else 2e-6
+        assert np.abs(vb - va).sum() <= tol * np.abs(va).sum()
+        assert np.abs(dvb - dva).sum() <= tol * max(np.abs(va).sum(), 1.0)
+
+
 @pytest.mark.parametrize("n,ef", [(5, 2), (300, 3), (3000, 6)])
 def test_fused_pull_small_graphs(daic, monkeypatch, n, ef):
     """Fused dense rounds on graphs with fewer edge blocks than the grid
@@ -219,16 +263,20 @@ def test_profile_matches_run_and_accounts_the_pull(daic, monkeypatch):
         va, vb = a.get(), b.get()
         assert np.abs(va - vb).sum() <= 2e-6 * np.abs(va).sum()
         names = {k["name"]: k for k in ks}
-        pull = names[("tile_pull" if "tile_pull" in names else "pull_fused") if fuse else "pull_stream"]
+        if fuse:
+            pull = names["tile_pull" if "tile_pull" in names else "pull_fused"]
+        else:
+            pull = names["pull_tile" if "pull_tile" in names else "pull_stream"]
         assert pull["launches"] == rb.stats["rounds"]
         assert pull["edges"] == pull["launches"] * g.m
         # the streamed pull reads a source and a base per in-edge; the tiled
         # one a 2-byte target per in-edge and a source and base per pair
-        per_edge = 2 if pull["name"] == "tile_pull" else 8
+        per_edge = 2 if pull["name"] in ("tile_pull", "pull_tile") else 8
         assert pull["alg_bytes"] >= pull["edges"] * per_edge and pull["total_ms"] > 0
         if not fuse:
-            assert {"claim", "pull_finish"} <= set(names)
-            assert names["pull_finish"]["launches"] == pull["launches"]
+            fin = "pull_tile_total" if "pull_tile" in names else "pull_finish"
+            assert {"claim", fin} <= set(names)
+            assert names[fin]["launches"] == pull["launches"]
             # a residual launch is counted only after a sparse round
             assert names.get("residual", {"launches": 0})["launches"] == rb.stats["rounds"] - pull["launches"]
 
