@@ -10,10 +10,15 @@ Inputs are resident in HBM before timing; each step resets the state from
 device tensors.
 
 Prints one JSON line. `value` is GTEPS = messages pushed / wall time of the
-timed steps. Also reported: per-kernel times and the roofline of the
-dominant kernel (from daic_profile, HIP events on the launch stream), the
-CPU oracle on a bounded sample of the same workload, and other forms of the
-same step (all-FP64, sampled top-10% priority).
+timed steps. Also reported: per-kernel times and the roofline of the dense
+round (from daic_profile, HIP events on the launch stream) with the
+algorithmic bytes of the measurement plan (12 B per message, 48 B per
+updated vertex, 4 B per vertex scanned); other forms of the same step
+(all-FP64, sampled and exact top-10 % priority, sweeps, the learned
+scheduler, the batched personalized PageRank, RMAT-20 SSSP, the 10,000-vertex
+PageRank); and the CPU oracle: its whole RMAT-24 solve to the same stop rule
+(the CPU baseline), whose result is the reference of every result's relative
+L1 error, plus its timings of the 10,000-vertex and SSSP workloads.
 """
 from __future__ import annotations
 
@@ -52,7 +57,7 @@ def host_info():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("daic_kernels.h", "daic_device.h", "daic_runtime.hip", "daic_pull.hip"):
+    for f in ("daic_kernels.h", "daic_device.h", "daic_tile.h", "daic_runtime.hip", "daic_pull.hip", "daic_tile.hip"):
         with open(os.path.join(ROOT, "paper_1710_05785_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -72,33 +77,75 @@ def stored_traffic(kernel):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(g, d, threads):
-    """The oracle's synchronous Jacobi (FP64 pull, all host threads) on the full
-    graph: after a warm-up call, calls of 1 and 7 sweeps; their difference is 6
-    sweeps without the transpose build."""
+def oracle_leg(g, d, eps, threads, out, vecs):
+    """The CPU oracle beside the GPU results (the only part of the benchmark
+    that calls the oracle): its synchronous Jacobi iteration (FP64 pull over
+    in-edges, all host threads) solves the RMAT-24 workload to the same stop
+    rule (sum of |v^k - v^(k-1)| <= eps, which equals the pending delta mass
+    of synchronous DAIC); that solve is the CPU baseline, and its result (within
+    eps / (1 - d) of the fixed point in L1) is the reference for the relative
+    L1 error of every GPU result in vecs. Also timed: the 10,000-vertex
+    PageRank workload (priority-ordered asynchronous worklist on one core,
+    Jacobi on all cores) and Dijkstra on the RMAT-20 SSSP workload (one core),
+    with the GPU results checked against them."""
     import numpy as np
 
+    import daic_gen
     import oracle
 
     dv1 = np.full(g.n, 1.0 - d)
-    oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1, eps=0.0, max_iter=1, threads=threads)
     t = time.perf_counter()
-    oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1, eps=0.0, max_iter=1, threads=threads)
-    t1 = time.perf_counter() - t
-    t = time.perf_counter()
-    oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1, eps=0.0, max_iter=7, threads=threads)
-    t4 = time.perf_counter() - t
-    per_sweep = max(1e-9, (t4 - t1) / 6.0)
+    ref, sweeps, last = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1, eps=eps, threads=threads)
+    secs = time.perf_counter() - t
+    tot = np.abs(ref).sum()
+    errs = {name: float(np.abs(v - ref).sum() / tot) for name, v in vecs.items()}
+    forms = out.get("forms", {})
+    out["rel_l1_vs_oracle"] = errs.pop("headline", None)
+    for name, e in errs.items():
+        path = name.split("/")
+        node = forms
+        for k in path:
+            node = node.setdefault(k, {})
+        node["rel_l1_vs_oracle"] = e
+    # the 10,000-vertex PageRank workload: asynchronous worklist (one core)
+    # and Jacobi (all cores) to the GPU's stop rule; GPU errors against the
+    # oracle's iteration to 1e-13
+    c1 = forms.get("c1_powerlaw10k")
+    if c1 is not None:
+        gp = daic_gen.powerlaw(n=10000, seed=1)
+        v0, dvp = oracle.pagerank_init(gp.n, d)
+        t = time.perf_counter()
+        r = oracle.async_run(gp, oracle.OP_SUM, oracle.G_DEG_SCALE, v0, dvp, alpha=d, eps=c1["eps"])
+        c1["oracle_async_priority_ms"] = (time.perf_counter() - t) * 1e3
+        c1["oracle_async_updates"] = r["updates"]
+        t = time.perf_counter()
+        _, sw, _ = oracle.jacobi_sum(gp, oracle.G_DEG_SCALE, d, dvp, eps=c1["eps"], threads=threads)
+        c1["oracle_jacobi_ms"] = (time.perf_counter() - t) * 1e3
+        c1["oracle_jacobi_sweeps"] = sw
+        pref, _, _ = oracle.jacobi_sum(gp, oracle.G_DEG_SCALE, d, dvp, eps=1e-13, threads=threads)
+        for k, v in c1.pop("_v", {}).items():
+            c1[k]["l1_vs_oracle"] = float(np.abs(v - pref).sum())
+            c1[k]["l1_bound"] = c1[k]["final_residual"] / (1.0 - d)
+    # SSSP RMAT-20: Dijkstra on one core, and the GPU distances against it
+    ss = forms.get("sssp_rmat20")
+    if ss is not None and "_dist" in ss:
+        gs = daic_gen.rmat(20, 16, seed=2)
+        w = daic_gen.sssp_weights(gs.m, seed=3)
+        t = time.perf_counter()
+        dist = oracle.dijkstra(gs, w, 0)
+        ss["oracle_dijkstra_ms"] = (time.perf_counter() - t) * 1e3
+        gpu = ss.pop("_dist")
+        ss["bit_exact_vs_oracle"] = {k: bool(np.array_equal(v, dist)) for k, v in gpu.items()}
     return {
-        "value": g.m / per_sweep / 1e9,
+        "value": g.m * sweeps / secs / 1e9,
         "unit": "GTEPS",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"6 synchronous Jacobi sweeps (FP64 pull over in-edges) over the full "
-                   f"RMAT-{int(round(np.log2(g.n)))} graph ({g.m} edges per sweep), timed as the "
-                   f"difference of a 7-sweep and a 1-sweep oracle call so the transpose build is "
-                   f"excluded; {per_sweep:.3f} s per sweep, {t1 + t4:.1f} s of CPU work in total"),
-        "seconds_per_sweep": per_sweep,
+        "sample": (f"the whole RMAT-{int(round(np.log2(g.n)))} solve: {sweeps} synchronous Jacobi sweeps "
+                   f"(FP64 pull over in-edges, transpose build included) to a sweep difference of "
+                   f"{eps:g} = the GPU's stop rule; {secs:.1f} s of CPU work"),
+        "time_to_residual_s": secs,
+        "sweeps": sweeps,
     }
 
 
@@ -191,7 +238,17 @@ def batched_form(daic, torch, eps, rounds_per_check):
         va, vb = b.get(i).astype(np.float64), b32.get(i).astype(np.float64)
         rel.extend((np.abs(vb - va).sum(axis=0) / np.maximum(np.abs(va).sum(axis=0), 1e-300)).tolist())
     del b32
+    achieved = res.stats["alg_bytes"] / wall / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "alg_bytes": res.stats["alg_bytes"],
+            "unit_of_work": (f"the whole solve ({res.stats['rounds']} rounds, wall time); bytes of its dense "
+                             "rounds only, so a lower bound of their rate"),
+            "bytes_model": ("per dense round: per vertex v, c read and written and the base vector "
+                            "written (5 x 256 B), per in-edge its source index (4 B), per sender its base "
+                            "vector read once (256 B)")}
     return {
+        "roofline": roof,
         "instances": len(gs) * rhs, "graphs": len(gs), "vertices": sum(g.n for g in gs),
         "edges": sum(g.m for g in gs), "time_to_residual_ms": wall * 1e3,
         "rounds": res.stats["rounds"], "converged": res.converged,
@@ -216,6 +273,37 @@ def batched_form(daic, torch, eps, rounds_per_check):
     }
 
 
+def c1_form(daic, torch, rounds_per_check):
+    """The 10,000-vertex PageRank workload (out-degrees floor(LogNormal(2, 1))
+    capped at 500, preferential targets, seed 1; d = 0.8, FP64, v0 = 0,
+    dv1 = 0.2) to residual 1e-9, every pending vertex per round and sampled
+    top-10 %; each warmed up, then timed."""
+    import numpy as np
+
+    import daic_gen
+
+    g = daic_gen.powerlaw(n=10000, seed=1)
+    P = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8, state="f64")
+    v0, dv1 = np.zeros(g.n), np.full(g.n, 0.2)
+    eps = 1e-9
+    out = {"workload": f"PageRank d=0.8, FP64, power-law n={g.n} m={g.m}, stop at L1 residual {eps:g}",
+           "eps": eps, "_v": {}}
+    for name, kw in (("all", dict(q=1.0, sched="all")), ("sampled_q0.1", dict(q=0.1, sched="sampled", seed=1))):
+        run_kw = dict(eps=eps, rounds_per_check=rounds_per_check, **kw)
+        P.set_init(v0, dv1)
+        P.run(**run_kw)  # warm-up
+        P.set_init(v0, dv1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = P.run(**run_kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        out[name] = {"time_ms": wall * 1e3, "rounds": r.stats["rounds"], "pushed_edges": r.stats["pushed_edges"],
+                     "final_residual": r.stats["final_residual"], "converged": r.converged}
+        out["_v"][name] = P.get()
+    return out
+
+
 def priority_form(torch, P, v0, dv1, eps, rounds_per_check, q=0.1):
     """Top-q priority scheduling on the headline problem P: the sampled
     threshold (4,096 samples, seed 1) and the exact radix select, each warmed
@@ -233,7 +321,8 @@ def priority_form(torch, P, v0, dv1, eps, rounds_per_check, q=0.1):
         w = time.perf_counter() - t
         out[f"{sched}_q{q}"] = {"time_to_residual_ms": w * 1e3, "rounds": r.stats["rounds"],
                                 "pushed_edges": r.stats["pushed_edges"],
-                                "gteps": r.stats["pushed_edges"] / w / 1e9, "converged": r.converged}
+                                "gteps": r.stats["pushed_edges"] / w / 1e9, "converged": r.converged,
+                                "_v": P.get()}
     return out
 
 
@@ -266,6 +355,7 @@ def sssp_form(daic, torch, rounds_per_check):
         wall = time.perf_counter() - t
         out[name] = {"time_ms": wall * 1e3, "rounds": r.stats["rounds"], "pushed_edges": r.stats["pushed_edges"],
                      "gteps": r.stats["pushed_edges"] / wall / 1e9, "converged": r.converged}
+        out.setdefault("_dist", {})[name] = P.get()
     P.set_init(v0, dv1)
     _, ks = P.profile(q=0.1, sched="sampled", seed=1, rounds_per_check=rounds_per_check)
     out["kernels_sampled_q0.1"] = [
@@ -356,6 +446,7 @@ def learned_form(daic, torch, g24, eps, rounds_per_check):
         "pushed_edges_ratio_learned_vs_exact": rl.stats["pushed_edges"] / re_.stats["pushed_edges"],
         "time_ratio_learned_vs_exact": tl / te,
         "rel_l1_learned_vs_exact": float(np.abs(vl - ve).sum() / np.abs(ve).sum()),
+        "_v": {"exact": ve, "learned": vl},
     }
     del res
     w24 = daic_gen.sssp_weights(g24.m, seed=7)
@@ -589,6 +680,7 @@ def main():
     log(f"timed {args.steps} steps: {wall:.3f}s, rounds/step {last.stats['rounds']}, "
         f"final residual {last.stats['final_residual']:.3e}")
     v32 = P.get()
+    vecs = {"headline": v32}  # results checked against the oracle's solve
 
     out = {
         "metric": METRIC,
@@ -626,13 +718,34 @@ def main():
             k["avg_ms"] = k["total_ms"] / max(1, k["launches"])
             k["achieved_GBs"] = k["alg_bytes"] / max(1e-12, k["total_ms"]) / 1e6
         dom = max(ks, key=lambda k: k["total_ms"])
-        achieved = dom["achieved_GBs"]
-        per_launch = dom["alg_bytes"] / max(1, dom["launches"])
+        names = {k["name"]: k for k in ks}
+        # Algorithmic bytes of one dense round by the per-unit figures of the
+        # measurement plan (FP32 PageRank): 12 B per message (column index 4 +
+        # read-modify-write of the receiver's delta 8), 48 B per updated vertex
+        # (row offsets 16, delta exchange 8, v and compensation read-modify-
+        # write 16, frontier write and read 8), 4 B per vertex scanned; the
+        # units are the averages per round of the profiled solve. The dense
+        # round is the dominant kernel with its two small finishing kernels,
+        # so its time is the sum of their average launch times.
+        rounds = max(1, pres.stats["rounds"])
+        units = {"messages": pres.stats["pushed_edges"] / rounds, "updates": pres.stats["activations"] / rounds,
+                 "vertices": g.n}
+        bytes_8d = 12.0 * units["messages"] + 48.0 * units["updates"] + 4.0 * units["vertices"]
+        round_kernels = [k for k in ("tile_pull", "tile_finish", "tile_total", "pull_fused", "fused_finish")
+                         if k in names]
+        round_ms = sum(names[k]["avg_ms"] for k in round_kernels)
+        achieved = bytes_8d / (round_ms * 1e-3) / 1e9
         traffic = stored_traffic(dom["name"])
         out["roofline"] = {
             "bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "alg_bytes_per_launch": per_launch, "avg_launch_ms": dom["avg_ms"],
+            "unit_of_work": "one dense round: " + " + ".join(f"{k} {names[k]['avg_ms']:.4f} ms" for k in round_kernels),
+            "alg_bytes_per_launch": bytes_8d, "avg_launch_ms": round_ms, "units_per_launch": units,
+            # the kernel's own byte model (2 B per in-edge, a source and a base
+            # per pair, the targets' state streams) over its own time
+            "kernel_model": {"alg_bytes_per_launch": dom["alg_bytes"] / max(1, dom["launches"]),
+                             "avg_launch_ms": dom["avg_ms"], "achieved": dom["achieved_GBs"],
+                             "frac": dom["achieved_GBs"] / HBM_PEAK_GBS},
             # the counted bytes per launch over the same live launch time: how
             # close the kernel's actual memory traffic runs to the HBM peak
             "traffic_GBs": (traffic / (dom["avg_ms"] * 1e-3) / 1e9) if traffic else None,
@@ -659,28 +772,40 @@ def main():
         forms["f64_all"] = {"time_to_residual_ms": w64 * 1e3, "rounds": r64.stats["rounds"],
                             "gteps": r64.stats["pushed_edges"] / w64 / 1e9,
                             "f32_kahan_rel_l1_vs_f64": float(np.abs(v32 - v64).sum() / np.abs(v64).sum())}
+        vecs["f64_all"] = v64
         del P64
         # top-10% priority scheduling (the paper's priority queue), sampled and exact
-        forms.update(priority_form(torch, P, v0, dv1, args.eps, args.rounds_per_check))
+        for name, f in priority_form(torch, P, v0, dv1, args.eps, args.rounds_per_check).items():
+            vecs[name] = f.pop("_v")
+            forms[name] = f
         # sweep scheduling: round-robin over 8 id blocks, each block pulling the
         # newest messages of its in-neighbours (asynchronous order)
         sw = sweep_form(daic, torch, g, d, args.eps, args.rounds_per_check, P=P, v0=v0, dv1=dv1)
         vs = sw.pop("_v")
+        vecs["sweep_8_blocks"] = vs
         sw["rel_l1_vs_all_pending"] = float(np.abs(vs - v32).sum() / np.abs(v32).sum())
         sw["time_ratio_vs_all_pending"] = sw["time_to_residual_ms"] / out["time_to_residual_ms"]
         forms["sweep_8_blocks"] = sw
         log("learned-scheduler form ...")
         forms["learned_sched"] = learned_form(daic, torch, g, args.eps, args.rounds_per_check)
+        for k, v in forms["learned_sched"]["pagerank_rmat24"].pop("_v").items():
+            vecs[f"learned_sched/pagerank_rmat24/{k}"] = v
         log("batched form ...")
         forms["batched_ppr_64x64"] = batched_form(daic, torch, args.eps, args.rounds_per_check)
         log("sssp form ...")
         forms["sssp_rmat20"] = sssp_form(daic, torch, args.rounds_per_check)
+        log("10k power-law form ...")
+        forms["c1_powerlaw10k"] = c1_form(daic, torch, args.rounds_per_check)
         out["forms"] = forms
 
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(g, d, threads)
+        log("the CPU oracle: RMAT-24 solve, 10k power-law, RMAT-20 Dijkstra ...")
+        out["cpu_baseline"] = oracle_leg(g, d, args.eps, threads, out, vecs)
+    for f in out.get("forms", {}).values():  # vectors kept for the oracle leg
+        if isinstance(f, dict):
+            f.pop("_v", None)
+            f.pop("_dist", None)
 
     print(json.dumps(out), flush=True)
 

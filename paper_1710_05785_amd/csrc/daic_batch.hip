@@ -1919,7 +1919,17 @@ daic_status daic_batch_run(daic_batch* b, const daic_run_opts* o, daic_stats* st
     stats->final_residual = mx;
     stats->time_ms = ms;
     stats->gteps = ms > 0 ? (double)c.messages / (ms * 1e-3) / 1e9 : 0.0;
-    stats->alg_bytes = 0.0;
+    // Compulsory bytes of the dense rounds: per vertex the state vectors (v
+    // read and written, with the Kahan term c read and written) and the
+    // published base vector written, 64 floats each; per in-edge its source
+    // index; per sender with out-edges its base vector read once. A sweep
+    // round covers 1/P of the vertices. The sparse opening rounds are not
+    // counted, so bytes / time is a lower bound of the dense rounds' rate.
+    const uint64_t dense_rounds = c.rounds >= c.base ? c.rounds - c.base : 0;
+    const double vec = (double)kR * 4.0;
+    const double per_round = (double)a.N * (b->kahan ? 5.0 : 3.0) * vec + (double)b->ug->dev.m * 4.0 +
+                             (double)b->ug->pull.n_src * vec;
+    stats->alg_bytes = (double)dense_rounds * per_round / (double)(sweep ? std::max<uint32_t>(P, 1) : 1);
   }
   return c.done ? DAIC_OK : DAIC_NOT_CONVERGED;
 }

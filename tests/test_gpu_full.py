@@ -17,8 +17,10 @@ benchmark runs them (captured groups of rounds, the default launch shapes).
 * Batched personalized PageRank, 64 RMAT graphs of scale U{12..20} with edge
   factor 8, 64 right-hand sides each (4,096 instances, d = 0.85, FP32 deltas
   with the Kahan-compensated or the plain FP32 state, residual 1e-6 per
-  instance): one instance per graph, each against the oracle's FP64
-  iteration with the same personalization vector (relative L1 <= 1e-5).
+  instance): a seeded subset of 256 instances (four right-hand sides of
+  every graph), each against the oracle's FP64 iteration with the same
+  personalization vector (relative L1 <= 1e-5); every other instance is
+  held to its residual, which bounds its L1 error by r / (1 - d).
 """
 import sys
 
@@ -149,16 +151,25 @@ def test_learned_scheduler_full_config(daic, g24, pr24_ref):
     np.testing.assert_array_equal(got, oracle.dijkstra(g, w, 0))
 
 
-@pytest.mark.timeout(900)
-@pytest.mark.parametrize("state", ["f32_kahan", "f32"])
-def test_batched_ppr_full_config_sampled_instances(daic, state):
-    say("case batched ppr full: generate", state)
-    d, rhs, eps = 0.85, 64, 1e-6
+BATCH_D, BATCH_RHS = 0.85, 64
+
+
+def batch_instances(i):
+    """The four right-hand sides of graph i compared with the oracle."""
+    return [(7 * i + 3 + 16 * k) % BATCH_RHS for k in range(4)]
+
+
+@pytest.fixture(scope="module")
+def batch_case():
+    """The 64 graphs, their personalization vectors and the oracle's FP64
+    iteration for the 256 sampled instances (to a sweep difference of 1e-11,
+    bound 7e-11 against totals of 1)."""
+    say("case batched ppr full: generate and oracle")
+    d, rhs = BATCH_D, BATCH_RHS
     scales = daic_gen.batch_scales()
     gs = [daic_gen.rmat(int(s), 8, seed=1000 + i) for i, s in enumerate(scales)]
     assert len(gs) == 64
-    b = daic.Batch([daic.Graph(g.row_ptr, g.col) for g in gs], rhs, alpha=d, state=state)
-    inits = []
+    inits, refs = [], {}
     for i, g in enumerate(gs):
         counts, seeds = daic_gen.ppr_seeds(g, 6, i * rhs, rhs, 32)
         dv1 = np.zeros((g.n, rhs))
@@ -166,6 +177,18 @@ def test_batched_ppr_full_config_sampled_instances(daic, state):
             sd = seeds[r, : counts[r]]
             dv1[sd, r] = (1.0 - d) / len(sd)
         inits.append(dv1)
+        for r in batch_instances(i):
+            refs[(i, r)], _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, dv1[:, r], eps=1e-11)
+    return gs, inits, refs
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("state", ["f32_kahan", "f32"])
+def test_batched_ppr_full_config_sampled_instances(daic, batch_case, state):
+    say("case batched ppr full", state)
+    d, rhs, eps = BATCH_D, BATCH_RHS, 1e-6
+    gs, inits, refs = batch_case
+    b = daic.Batch([daic.Graph(g.row_ptr, g.col) for g in gs], rhs, alpha=d, state=state)
 
     def reset():
         for i, g in enumerate(gs):
@@ -177,10 +200,12 @@ def test_batched_ppr_full_config_sampled_instances(daic, state):
         reset()
         res, inst = b.run(eps=eps, rounds_per_check=16)
         assert res.converged and np.all(inst <= eps)
-    say("case batched ppr full: oracle")
+    worst = 0.0
     for i, g in enumerate(gs):
-        r = (7 * i + 3) % rhs
-        v = b.get(i)[:, r].astype(np.float64)
-        ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, d, inits[i][:, r], eps=1e-13)
-        rel = np.abs(v - ref).sum() / np.abs(ref).sum()
-        assert rel <= 1e-5, (i, r, rel)
+        vi = b.get(i)
+        for r in batch_instances(i):
+            ref = refs[(i, r)]
+            rel = np.abs(vi[:, r].astype(np.float64) - ref).sum() / np.abs(ref).sum()
+            worst = max(worst, rel)
+            assert rel <= 1e-5, (i, r, rel)
+    say("  256 instances, worst relative L1", worst)
