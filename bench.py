@@ -153,7 +153,8 @@ def batched_form(daic, torch, eps, rounds_per_check):
     """The batched personalized PageRank form: 64 RMAT graphs (scale U{12..20},
     edge factor 8, graph g seed 1000+g) x 64 right-hand sides (k ~ U{1..32}
     seeds), d = 0.85, FP32 state with Kahan term, every instance to residual
-    eps; against single-instance solves of the same instances on the GPU."""
+    eps in one launch of a captured graph of 128 rounds; against
+    single-instance solves of the same instances on the GPU."""
     import numpy as np
 
     import daic_gen
@@ -183,11 +184,12 @@ def batched_form(daic, torch, eps, rounds_per_check):
 
     reset()
     tuned = b.tune()
-    b.run(eps=eps, rounds_per_check=rounds_per_check)  # warm-up (graph capture)
+    # rounds_per_check 0: the whole solve is one launch of a captured graph
+    b.run(eps=eps, rounds_per_check=0)  # warm-up (graph capture)
     reset()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    res, inst = b.run(eps=eps, rounds_per_check=rounds_per_check)
+    res, inst = b.run(eps=eps, rounds_per_check=0)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     # the same instances in round-robin sweeps of 8 id blocks per graph
@@ -442,7 +444,9 @@ def learned_form(daic, torch, g24, eps, rounds_per_check):
         "exact": {"time_to_residual_ms": te * 1e3, "rounds": re_.stats["rounds"],
                   "pushed_edges": re_.stats["pushed_edges"], "converged": re_.converged},
         "learned": {"time_to_residual_ms": tl * 1e3, "rounds": rl.stats["rounds"],
-                    "pushed_edges": rl.stats["pushed_edges"], "converged": rl.converged},
+                    "pushed_edges": rl.stats["pushed_edges"], "converged": rl.converged,
+                    "exact_rounds": rl.stats["learned_exact_rounds"],
+                    "fallbacks": rl.stats["learned_fallbacks"]},
         "pushed_edges_ratio_learned_vs_exact": rl.stats["pushed_edges"] / re_.stats["pushed_edges"],
         "time_ratio_learned_vs_exact": tl / te,
         "rel_l1_learned_vs_exact": float(np.abs(vl - ve).sum() / np.abs(ve).sum()),
@@ -471,7 +475,9 @@ def learned_form(daic, torch, g24, eps, rounds_per_check):
         "exact": {"time_ms": te * 1e3, "rounds": re_.stats["rounds"],
                   "pushed_edges": re_.stats["pushed_edges"], "converged": re_.converged},
         "learned": {"time_ms": tl * 1e3, "rounds": rl.stats["rounds"],
-                    "pushed_edges": rl.stats["pushed_edges"], "converged": rl.converged},
+                    "pushed_edges": rl.stats["pushed_edges"], "converged": rl.converged,
+                    "exact_rounds": rl.stats["learned_exact_rounds"],
+                    "fallbacks": rl.stats["learned_fallbacks"]},
         "pushed_edges_ratio_learned_vs_exact": rl.stats["pushed_edges"] / re_.stats["pushed_edges"],
         "time_ratio_learned_vs_exact": tl / te,
         "bit_identical_learned_vs_exact": bool(np.array_equal(vl, ve)),
@@ -635,8 +641,9 @@ def main():
     g = daic_gen.rmat(args.scale, args.edgefactor, seed=args.seed)
     log(f"generated RMAT-{args.scale} n={g.n} m={g.m} in {time.perf_counter() - t:.1f}s")
     if args.form == "learned":
-        print(json.dumps({"learned_sched": learned_form(daic, torch, g, args.eps, args.rounds_per_check)}),
-              flush=True)
+        lf = learned_form(daic, torch, g, args.eps, args.rounds_per_check)
+        lf["pagerank_rmat24"].pop("_v")
+        print(json.dumps({"learned_sched": lf}), flush=True)
         return
     if args.form == "sweep":
         sw = sweep_form(daic, torch, g, d, args.eps, args.rounds_per_check)

@@ -144,6 +144,9 @@ typedef struct {
   double time_ms;             /* device time of the round loop                 */
   double gteps;               /* pushed_edges / time / 1e9                     */
   double alg_bytes;           /* algorithmic bytes moved by the round loop     */
+  uint64_t learned_exact_rounds; /* LEARNED: rounds taken by exact top-k       */
+  uint64_t learned_fallbacks; /* LEARNED: times the judge handed the next rounds
+                                 back to exact selection                       */
 } daic_stats;
 
 /* ---- Graphs --------------------------------------------------------------
@@ -290,7 +293,10 @@ daic_status daic_batch_tune(daic_batch* b, char* desc, size_t desc_len);
  * stats->final_residual is the largest instance residual. Instances are
  * updated until the check after the round in which their residual fell to
  * eps, so they may end below eps; a run stopped by max_rounds returns
- * DAIC_NOT_CONVERGED with every message delivered (a later run resumes). */
+ * DAIC_NOT_CONVERGED with every message delivered (a later run resumes).
+ * opts->rounds_per_check rounds are one graph launch between host checks;
+ * 0 means 128, so that a whole solve of up to 128 rounds is one launch
+ * (rounds after every instance finished return at once). */
 daic_status daic_batch_run(daic_batch* b, const daic_run_opts* opts, daic_stats* stats,
                            double* inst_residual);
 /* v_out: [n_g][rhs_g] doubles (FP32 state; with Kahan, v - c). */
@@ -322,6 +328,14 @@ void daic_batch_destroy(daic_batch* b);
  * ceil(q n) vertices by priority x sigmoid(score); the exact top-k round is its
  * fallback and the residual remains the stop rule. Not part of the paper: an
  * addition that changes the update order only, which Theorems 1 and 3 allow.
+ * The exact rounds and the judge: a learned run starts with one exact top-k
+ * round; each round's realized priority per message (the sum of
+ * |v (+) dv - v| over the vertices it updated, divided by the messages it
+ * sent, and for sum problems also by the residual at the round's start) is
+ * compared on the device with the last exact round's; a learned round below
+ * 0.8 x that figure hands the next 4 rounds back to exact selection, and
+ * every 16 learned rounds are followed by one exact round. Learned rounds are captured in graphs like the others
+ * (rounds_per_check rounds per launch).
  * Parameters: 4481 FP32 values, [W1 (64x3), b1 (64), W2 (64x64), b2 (64),
  * W3 (1x64), b3 (1)], row-major (output, input). The device keeps FP32
  * master weights and BF16 copies for the MFMA kernels.                     */

@@ -1812,7 +1812,11 @@ daic_status daic_batch_run(daic_batch* b, const daic_run_opts* o, daic_stats* st
     return fail(DAIC_E_INVALID, "priority_fraction must be in (0, 1]");
   if (!(o->eps >= 0.0)) return fail(DAIC_E_INVALID, "eps must be >= 0");
   hipStream_t s = o->hip_stream ? static_cast<hipStream_t>(o->hip_stream) : b->stream;
-  const uint32_t K = o->rounds_per_check ? o->rounds_per_check : 1;
+  // rounds_per_check 0: one launch of kBatchLaunchRounds captured rounds
+  // (rounds after every instance finished return at once), so a solve of up
+  // to that many rounds is a single graph launch
+  constexpr uint32_t kBatchLaunchRounds = 128;
+  const uint32_t K = o->rounds_per_check ? o->rounds_per_check : kBatchLaunchRounds;
   const uint64_t max_rounds = o->max_rounds ? o->max_rounds : ~0ull;
   if (stats) std::memset(stats, 0, sizeof *stats);
   BArgs& a = b->a;

@@ -63,6 +63,17 @@ struct Ctl {
   uint32_t pull;         // the next round runs as a pull over in-edges (dense round)
   uint32_t last_pull;    // the round just run was a dense round
   uint64_t fuse_base;    // fused dense rounds: round count when buffer A was last published
+  // learned scheduling, decided on the device each round
+  uint32_t use_score;    // this round ranks by priority x network multiplier (else exact top-k)
+  uint32_t l_exact_left; // exact rounds still to run before the network is used again
+  uint32_t l_run;        // learned rounds since the last exact round
+  uint32_t l_pad;
+  double l_r0;           // residual at the start of the round
+  uint64_t l_rounds0;    // round count at the start of the round
+  double l_gain;         // priority realized by the round's updates (sum over the selected vertices)
+  double l_exact_eff;    // the judge's figure for the last exact round
+  uint64_t l_fallbacks;  // learned rounds that handed the next rounds back to exact selection
+  uint64_t l_exact_rounds;  // rounds of a learned run taken by exact selection
 };
 
 // Compile-time identity of a (op, g, state, row) instantiation.
@@ -86,9 +97,12 @@ struct Partition {
 
 // Learned scheduler hooks (defined with the scheduler network).
 daic_status learned_prepare(daic_problem* p, const daic_sched_model* model, hipStream_t s);
-daic_status learned_scores(daic_problem* p, const daic_sched_model* model, hipStream_t s,
-                           const float** score);
-void learned_after_round(daic_problem* p, hipStream_t s);
+// The multiplier array of learned rounds, and the enqueue of the scoring
+// kernel (which returns at once in an exact round of a learned run).
+daic_status learned_scores_array(daic_problem* p, const daic_sched_model* model, const float** score);
+void learned_scores_enqueue(daic_problem* p, const daic_sched_model* model, hipStream_t s);
+// Bumped whenever the network's parameters or feature scales change.
+uint64_t learned_model_version(const daic_sched_model* model);
 // Builds the in-edge form of g (no-op when built). Needs m < 2^32.
 daic_status pull_prepare(daic_graph* g, hipStream_t s);
 void pull_release(daic_graph* g);

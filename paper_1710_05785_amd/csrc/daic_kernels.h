@@ -388,6 +388,7 @@ __global__ __launch_bounds__(256) void k_residual_final(KArgs a, int count_round
 // ---------------------------------------------------------------------------
 template <int ST>
 __global__ __launch_bounds__(256) void k_sample_keys(KArgs a, uint32_t S_n, uint64_t seed, uint64_t round_override) {
+  if (a.score != nullptr && !a.ctl->use_score) a.score = nullptr;  // an exact round of a learned run
   using S = typename Tr<ST>::S;
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
@@ -468,6 +469,55 @@ static __global__ void k_init_ctl(Ctl* ctl, double eps, uint64_t max_rounds) {
   ctl->pull = 0;
   ctl->last_pull = 0;
   ctl->fuse_base = 0;
+  ctl->use_score = 1;
+  ctl->l_exact_left = 1;  // a learned run starts with one exact round (the judge's calibration)
+  ctl->l_run = 0;
+  ctl->l_r0 = 0.0;
+  ctl->l_rounds0 = 0;
+  ctl->l_gain = 0.0;
+  ctl->l_exact_eff = 0.0;
+  ctl->l_fallbacks = 0;
+  ctl->l_exact_rounds = 0;
+}
+
+// Learned scheduling, before a round: remember the residual and decide
+// whether the round ranks by the network (exact top-k while exact rounds
+// are owed).
+static __global__ void k_learned_pre(Ctl* ctl) {
+  if (ctl_halted(ctl)) return;
+  ctl->l_r0 = ctl->r;
+  ctl->l_rounds0 = ctl->rounds;
+  ctl->use_score = ctl->l_exact_left == 0 ? 1u : 0u;
+}
+
+// After the round: the judge's figure, the priority its updates realized
+// (sum over the selected vertices of |v (+) dv - v|) per message, as a
+// fraction of the residual at the round's start for sum problems (where the
+// residual is that same priority mass), in value units for min/max problems
+// (whose residual is a count). An exact round calibrates the judge; a
+// learned round below 0.8 x the last exact round's figure hands the next
+// kFallback rounds back to exact selection, and after kWindow learned rounds
+// one exact round recalibrates.
+template <bool SUM>
+__global__ void k_learned_post(Ctl* ctl) {
+  constexpr uint32_t kFallback = 4, kWindow = 16;
+  if (ctl->rounds == ctl->l_rounds0) return;  // no round was run
+  ctl->l_rounds0 = ctl->rounds;
+  const double r0 = ctl->l_r0;
+  double eff = ctl->l_gain / (double)(ctl->round_pushed > 1 ? ctl->round_pushed : 1);
+  if (SUM) eff /= r0 > 1e-300 ? r0 : 1e-300;
+  if (!ctl->use_score) {
+    ctl->l_exact_eff = eff;
+    ctl->l_exact_rounds += 1;
+    if (ctl->l_exact_left > 0) ctl->l_exact_left -= 1;
+    ctl->l_run = 0;
+  } else if (eff < 0.8 * ctl->l_exact_eff) {
+    ctl->l_exact_left = kFallback;
+    ctl->l_fallbacks += 1;
+  } else if (++ctl->l_run >= kWindow) {
+    ctl->l_exact_left = 1;
+  }
+  ctl->use_score = 1;
 }
 
 // The stop flags are recomputed by the next residual.
@@ -534,6 +584,7 @@ static __global__ __launch_bounds__(256) void k_topk_init(Ctl* ctl, uint32_t* rh
 // k_radix_pick then picks the digit.
 template <int ST>
 __global__ __launch_bounds__(256) void k_radix_pass(KArgs a, int pass) {
+  if (a.score != nullptr && !a.ctl->use_score) a.score = nullptr;  // an exact round of a learned run
   using S = typename Tr<ST>::S;
   using Key = typename Tr<ST>::Key;
   Ctl* ctl = a.ctl;
@@ -645,6 +696,7 @@ __global__ __launch_bounds__(256) void k_radix_pick(KArgs a, int pass) {
 
 template <int ST>
 __global__ __launch_bounds__(256) void k_tie_count(KArgs a) {
+  if (a.score != nullptr && !a.ctl->use_score) a.score = nullptr;  // an exact round of a learned run
   using S = typename Tr<ST>::S;
   using Key = typename Tr<ST>::Key;
   Ctl* ctl = a.ctl;
@@ -742,6 +794,7 @@ static __global__ __launch_bounds__(1024) void k_tie_scan(KArgs a) {
 // ---------------------------------------------------------------------------
 template <int ST, int G, typename RowT, bool DRY>
 __global__ __launch_bounds__(256) void k_claim(KArgs a) {
+  if (a.score != nullptr && !a.ctl->use_score) a.score = nullptr;  // an exact round of a learned run
   using S = typename Tr<ST>::S;
   using Key = typename Tr<ST>::Key;
   Ctl* ctl = a.ctl;
@@ -760,6 +813,8 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
   const uint64_t large_base = DRY ? 0 : a.large_off[b];
   const bool pull = !DRY && ctl->pull != 0;
   uint64_t ties_seen = 0, n_small = 0, n_large = 0, act = 0, pushed = 0, pushed_large = 0;
+  double gain = 0.0;  // learned runs (update rounds tracked): priority realized by the selected vertices
+  const bool track = !DRY && a.last_upd != nullptr;
 
   // Dense rounds without tie counting (sum problems): no bins and no block
   // scans, so a thread takes four vertices per step with every load of the
@@ -822,7 +877,10 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
             else coef = a.alpha_pv ? (double)static_cast<const S*>(a.alpha_pv)[j] : a.alpha;
             mu = (S)(coef * (double)delta);
             send = delta != (S)0 && deg > 0;
-            if (a.last_upd) a.last_upd[j] = (uint32_t)ctl->rounds + 1u;
+            if (track) {
+              a.last_upd[j] = (uint32_t)ctl->rounds + 1u;
+              gain += (double)prio_value<ST>(vj[u], dj[u]);
+            }
           }
           if (pj[u] < a.n_src) mu_pi[pj[u]] = send ? mu : (S)0;  // no reader otherwise
           act += sel ? 1 : 0;
@@ -866,7 +924,10 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
       beg = row_at<RowT>(a.row, j);
       deg = row_at<RowT>(a.row, j + 1) - beg;
       send = claim_fold<ST, G>(a, j, deg, vj, dj, mu) && deg > 0;
-      if (a.last_upd) a.last_upd[j] = (uint32_t)ctl->rounds + 1u;
+      if (track) {
+        a.last_upd[j] = (uint32_t)ctl->rounds + 1u;
+        gain += (double)prio_value<ST>(vj, dj);
+      }
     }
     if (pull) {  // dense round: every sender publishes its message base (0 if silent)
       if constexpr (Tr<ST>::sum) {
@@ -909,6 +970,10 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
     act = block_sum256(act);
     pushed = block_sum256(pushed);
     pushed_large = block_sum256(pushed_large);
+    if (track) {  // kernel-uniform; the residual's partial slots are free until the round's residual
+      gain = block_sum256(gain);
+      if (threadIdx.x == 0) a.part_r[b] = gain;
+    }
     if (threadIdx.x == 0) {
       a.blk_small[b] = (uint32_t)n_small;
       a.blk_large[b] = (uint32_t)n_large;
@@ -933,6 +998,19 @@ static __global__ __launch_bounds__(1024) void k_bin_scan(KArgs a) {
   } else if (threadIdx.x == 0) {
     ctl->n_small = 0;
     ctl->n_large = 0;
+  }
+  if (a.last_upd != nullptr) {  // learned runs: the realized priority, summed in a fixed order
+    double g = 0.0;
+    for (uint32_t i = threadIdx.x; i < a.blocks; i += 1024) g += a.part_r[i];
+    g = wave_sum(g);
+    __shared__ double s_g[16];
+    if (lane_id() == 0) s_g[threadIdx.x >> 6] = g;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < 16; ++w) t += s_g[w];
+      ctl->l_gain = t;
+    }
   }
   uint64_t act = 0, push = 0, pl = 0;
   for (uint32_t i = threadIdx.x; i < a.blocks; i += 1024) {

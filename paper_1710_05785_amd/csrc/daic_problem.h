@@ -26,10 +26,13 @@ struct GraphCacheKey {
   uint32_t K = 0;
   const void* stream = nullptr;
   const float* score = nullptr;
+  const void* model = nullptr;   // learned rounds: the network and its version (weights,
+  uint64_t model_version = 0;    // feature scales and BF16 copies captured by the graph)
   uint64_t k_sel = 0, pull_min = 0;
   bool operator==(const GraphCacheKey& o) const {
     return sched == o.sched && k == o.k && S == o.S && q == o.q && seed == o.seed && K == o.K &&
-           stream == o.stream && score == o.score && k_sel == o.k_sel && pull_min == o.pull_min;
+           stream == o.stream && score == o.score && k_sel == o.k_sel && pull_min == o.pull_min &&
+           model == o.model && model_version == o.model_version;
   }
 };
 
@@ -75,7 +78,6 @@ struct daic_problem {
   uint32_t* last_upd = nullptr;  // 1 + round of the last update of each vertex, 0 = never updated
   uint32_t* indeg = nullptr;     // in-degree of each vertex
   float* score = nullptr;        // selection multiplier of each vertex
-  uint64_t learned_fallbacks = 0;  // learned rounds that handed back to exact selection
   daic::SweepState* sweep = nullptr;
   void* cst = nullptr;           // constant c of the update function (fourth-condition check), or null
 };

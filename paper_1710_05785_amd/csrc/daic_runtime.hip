@@ -882,7 +882,6 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
   if (o->sched == DAIC_SCHED_LEARNED) {
     rc = learned_prepare(p, o->model, s);
     if (rc) return rc;
-    p->learned_fallbacks = 0;
   }
 
   rc = dense_rounds_setup(p, o, s);
@@ -891,7 +890,31 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
   ops.residual(p, s, 0);
   DAIC_HIP(hipEventRecord(p->ev0, s));
 
-  const bool use_graph = o->sched != DAIC_SCHED_LEARNED && std::getenv("DAIC_NO_GRAPH") == nullptr;
+  const bool learned = o->sched == DAIC_SCHED_LEARNED;
+  const bool use_graph = std::getenv("DAIC_NO_GRAPH") == nullptr;
+  // Learned rounds rank by priority x sigmoid(score). Exact top-k is the
+  // fallback and the judge, decided on the device each round (k_learned_pre /
+  // k_learned_post): one exact round calibrates the priority realized per
+  // message, a learned round below 0.8 x that figure hands the next 4 rounds
+  // back to exact selection, and every 16 learned rounds are followed by a
+  // fresh calibration round. So learned rounds are captured like the others.
+  const bool sum_state = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
+  const float* sc = nullptr;
+  if (learned) {
+    rc = learned_scores_array(p, o->model, &sc);
+    if (rc) return rc;
+  }
+  auto one_round = [&]() {
+    if (learned) {
+      hipLaunchKernelGGL(k_learned_pre, dim3(1), dim3(1), 0, s, p->a.ctl);
+      learned_scores_enqueue(p, o->model, s);
+      ops.round(p, o, s, sc, nullptr);
+      if (sum_state) hipLaunchKernelGGL(k_learned_post<true>, dim3(1), dim3(1), 0, s, p->a.ctl);
+      else hipLaunchKernelGGL(k_learned_post<false>, dim3(1), dim3(1), 0, s, p->a.ctl);
+    } else {
+      ops.round(p, o, s, nullptr, nullptr);
+    }
+  };
   GraphCacheKey key;
   key.sched = o->sched;
   key.k = (uint64_t)std::ceil(o->priority_fraction * (double)n);
@@ -902,60 +925,22 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
   key.stream = s;
   key.k_sel = p->k_sel;
   key.pull_min = p->pull_min;
+  key.score = sc;
+  key.model = learned ? o->model : nullptr;
+  key.model_version = learned ? learned_model_version(o->model) : 0;
   if (use_graph && !(p->exec && p->key == key)) {
     if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
     if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
     DAIC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (uint32_t r = 0; r < K; ++r) ops.round(p, o, s, nullptr, nullptr);
+    for (uint32_t r = 0; r < K; ++r) one_round();
     hipGraph_t graph;
     DAIC_HIP(hipStreamEndCapture(s, &graph));
     p->graph = graph;
     DAIC_HIP(hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0));
     p->key = key;
   }
-  if (o->sched == DAIC_SCHED_LEARNED) {
-    // Rounds ranked by priority x sigmoid(score). Exact top-k is the fallback:
-    // one exact round calibrates the residual drop per pushed edge, and a
-    // learned round that does worse than 0.8 x that figure hands the next
-    // kFallback rounds back to exact selection; every kWindow learned rounds
-    // are followed by a fresh calibration round. (Sum problems; min/max
-    // problems have no residual mass to compare and always use the network.)
-    constexpr uint32_t kFallback = 4, kWindow = 16;
-    const bool sum = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
-    uint32_t exact_left = sum ? 1 : 0, learned_run = 0;
-    double exact_eff = 0.0;
-    DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    DAIC_HIP(hipStreamSynchronize(s));
-    while (!p->h_ctl->done && !p->h_ctl->stop) {
-      const double r0 = p->h_ctl->r;
-      const bool learned = exact_left == 0;
-      const float* sc = nullptr;
-      if (learned) {
-        rc = learned_scores(p, o->model, s, &sc);
-        if (rc) return rc;
-      }
-      ops.round(p, o, s, sc, nullptr);
-      DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-      DAIC_HIP(hipStreamSynchronize(s));
-      if (!sum) continue;
-      const double drop = (r0 - p->h_ctl->r) / std::max(r0, 1e-300);
-      const double eff = drop / std::max(1.0, (double)p->h_ctl->round_pushed);
-      if (!learned) {
-        exact_eff = eff;
-        --exact_left;
-        learned_run = 0;
-      } else if (eff < 0.8 * exact_eff) {
-        exact_left = kFallback;
-        ++p->learned_fallbacks;
-      } else if (++learned_run >= kWindow) {
-        exact_left = 1;
-      }
-    }
-  }
-  p->a.last_upd = nullptr;  // captured plain rounds do not track updates
   // Fused dense rounds (every pending vertex, sum problems, in-edge form):
   // entered when a dense round is next and at least two rounds remain.
-  const bool sum_state = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
   const bool fuse = use_graph && o->sched == DAIC_SCHED_ALL && sum_state && p->pull_ready &&
                     std::getenv("DAIC_NO_FUSE") == nullptr;
   bool fused = false;
@@ -964,7 +949,7 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
     DAIC_HIP(hipStreamSynchronize(s));
   }
   uint64_t seen_rounds = ~0ull;
-  for (; o->sched != DAIC_SCHED_LEARNED;) {
+  for (;;) {
     if (fuse && !fused) {
       const Ctl& c = *p->h_ctl;
       if (!c.done && !c.stop && c.pull && c.rounds < max_rounds) {
@@ -989,7 +974,7 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
     } else if (use_graph) {
       DAIC_HIP(hipGraphLaunch(p->exec, s));
     } else {
-      for (uint32_t r = 0; r < K; ++r) ops.round(p, o, s, nullptr, nullptr);
+      for (uint32_t r = 0; r < K; ++r) one_round();
     }
     DAIC_HIP(hipMemcpyAsync(p->h_ctl, p->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     DAIC_HIP(hipStreamSynchronize(s));
@@ -1002,6 +987,7 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
   }
   DAIC_HIP(hipEventRecord(p->ev1, s));
   DAIC_HIP(hipEventSynchronize(p->ev1));
+  p->a.last_upd = nullptr;  // rounds of the other rules do not track updates
   float ms = 0.f;
   DAIC_HIP(hipEventElapsedTime(&ms, p->ev0, p->ev1));
   const Ctl& c = *p->h_ctl;
@@ -1014,6 +1000,8 @@ daic_status daic_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats)
     stats->gteps = ms > 0 ? (double)c.pushed / (ms * 1e-3) / 1e9 : 0.0;
     stats->alg_bytes = (double)c.pushed * per_edge_bytes(p) + (double)c.activations * per_vertex_bytes(p) +
                        (double)c.rounds * (double)n * (double)state_size(p->st) * 2.0;
+    stats->learned_fallbacks = learned ? c.l_fallbacks : 0;
+    stats->learned_exact_rounds = learned ? c.l_exact_rounds : 0;
   }
   return c.done ? DAIC_OK : DAIC_NOT_CONVERGED;
 }

@@ -399,6 +399,7 @@ struct daic_sched_model {
   float fmean[3] = {0, 0, 0};  // feature standardization
   float fstd[3] = {1, 1, 1};
   uint64_t adam_t = 0;
+  uint64_t version = 0;        // bumped on every change of parameters or scales
   MlpDev dev() const {
     MlpDev m;
     m.W1b = W1b;
@@ -436,6 +437,7 @@ constexpr float kAdamB1 = 0.9f, kAdamB2 = 0.999f, kAdamEps = 1e-8f;
 // moments and FP32 master weights updated, then the BF16 copies refreshed.
 static daic_status adam_apply(daic_sched_model* m, const float* dgrad, float lr, hipStream_t s) {
   m->adam_t += 1;
+  m->version += 1;
   const float bc1 = 1.f - std::pow(kAdamB1, (float)m->adam_t);
   const float bc2 = 1.f - std::pow(kAdamB2, (float)m->adam_t);
   hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, m->w, m->m1, m->m2, dgrad, lr, kAdamB1,
@@ -518,6 +520,7 @@ daic_status daic_sched_model_set_features(daic_sched_model* m, const float* feat
     if (!(feat_std[i] > 0.f)) return fail(DAIC_E_INVALID, "feature scales must be positive");
   std::memcpy(m->fmean, feat_mean, sizeof m->fmean);
   std::memcpy(m->fstd, feat_std, sizeof m->fstd);
+  m->version += 1;
   return DAIC_OK;
 }
 
@@ -706,7 +709,7 @@ __device__ __forceinline__ float tile_logit(const MlpRegs& R, bf16x4 bx) {
 template <int ST, typename RowT>
 __global__ __launch_bounds__(256) void k_score(KArgs a, MlpDev m, FeatNorm fn, const uint32_t* indeg,
                                                const uint32_t* last_upd, float* score) {
-  if (ctl_halted(a.ctl)) return;
+  if (ctl_halted(a.ctl) || !a.ctl->use_score) return;  // no multipliers for an exact round
   const uint32_t round = (uint32_t)a.ctl->rounds;
   const uint32_t lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
   const uint64_t waves = (uint64_t)gridDim.x * 4;
@@ -881,13 +884,17 @@ daic_status learned_prepare(daic_problem* p, const daic_sched_model* model, hipS
   return learned_arrays(p, s);
 }
 
-daic_status learned_scores(daic_problem* p, const daic_sched_model* model, hipStream_t s, const float** score) {
-  learned_ops(p).score(p, model, norm_of(model), s);
+daic_status learned_scores_array(daic_problem* p, const daic_sched_model* model, const float** score) {
+  if (!model || !p->score) return fail(DAIC_E_INVALID, "LEARNED needs a model and its prepared arrays");
   *score = p->score;
   return DAIC_OK;
 }
 
-void learned_after_round(daic_problem*, hipStream_t) {}
+void learned_scores_enqueue(daic_problem* p, const daic_sched_model* model, hipStream_t s) {
+  learned_ops(p).score(p, model, norm_of(model), s);
+}
+
+uint64_t learned_model_version(const daic_sched_model* model) { return model ? model->version : 0; }
 
 }  // namespace daic
 
@@ -1182,6 +1189,7 @@ daic_status daic_sched_train(const daic_trace* const* traces, uint32_t n_traces,
     m->fmean[k] = (float)mean[k];
     m->fstd[k] = (float)std::max(1e-6, std::sqrt(var[k] / (double)N));
   }
+  m->version += 1;
   // shuffle with a seeded Fisher-Yates on SplitMix64 draws, then standardize
   std::vector<uint64_t> perm(N);
   for (uint64_t i = 0; i < N; ++i) perm[i] = i;

@@ -47,7 +47,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_uint64), ("activations", ctypes.c_uint64),
                 ("pushed_edges", ctypes.c_uint64), ("final_residual", ctypes.c_double),
                 ("time_ms", ctypes.c_double), ("gteps", ctypes.c_double),
-                ("alg_bytes", ctypes.c_double)]
+                ("alg_bytes", ctypes.c_double), ("learned_exact_rounds", ctypes.c_uint64),
+                ("learned_fallbacks", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -370,3 +370,24 @@ def test_batch_checkpoint_resume(daic, tmp_path):
     other = daic.Batch([daic.Graph(g.row_ptr, g.col) for g in gs[:2]], rhs, alpha=d, state="f32_kahan")
     with pytest.raises(daic.DaicError):
         other.load(path)
+
+
+def test_batched_single_launch(daic):
+    """rounds_per_check = 0: the solve is one launch of 128 captured rounds
+    (rounds after every instance finished return at once); the same rounds
+    and state as checks every 4 rounds."""
+    say("case batch single launch")
+    d, rhs = 0.85, 32
+    gs = [daic_gen.rmat(s, 8, seed=1400 + s) for s in (10, 12, 9)]
+    out = []
+    for rpc in (4, 0):
+        b = daic.Batch([daic.Graph(g.row_ptr, g.col) for g in gs], rhs, alpha=d, state="f32_kahan")
+        inits = [ppr_inputs(g, 6, i * 64, rhs, d) for i, g in enumerate(gs)]
+        for i, g in enumerate(gs):
+            b.set_init(i, np.zeros((g.n, rhs)), inits[i])
+        r, inst = b.run(eps=1e-7, rounds_per_check=rpc)
+        assert r.converged and inst.max() <= 1e-7
+        out.append((r.stats["rounds"], [b.get(i) for i in range(len(gs))]))
+    assert out[0][0] == out[1][0] <= 128
+    for va, vb in zip(out[0][1], out[1][1]):
+        assert np.abs(va - vb).sum() <= 1e-6 * np.abs(va).sum()

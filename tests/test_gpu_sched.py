@@ -287,6 +287,96 @@ def test_learned_sssp_is_bit_exact(daic):
     np.testing.assert_array_equal(p.get(), ref)
 
 
+def inverted_model(daic):
+    """A network that ranks against the priority: logit = -10 relu(feature 0),
+    feature 0 being log2 of the priority, so the learned order prefers the
+    pending vertices of smallest priority."""
+    prm = {k: np.zeros(shp, np.float32) for k, shp in daic._PARAM_SHAPES}
+    prm["W1"][0, 0] = 1.0
+    prm["W2"][0, 0] = 1.0
+    prm["W3"][0, 0] = -10.0
+    m = daic.SchedModel(prm)
+    m.set_features(np.array([-30.0, 0.0, 0.0], np.float32), np.ones(3, np.float32))
+    return m
+
+
+@pytest.mark.parametrize("kind", ["pagerank", "sssp"])
+def test_learned_fallback_on_a_bad_network(daic, kind):
+    """The device-side judge hands rounds back to exact top-k when the
+    learned order drops the residual (pending count for min problems) per
+    message below 0.8 x the exact round's: with an inverted network the run
+    still converges to the oracle's result, with fallbacks recorded."""
+    say("case learned fallback", kind)
+    m = inverted_model(daic)
+    g = daic_gen.rmat(14, 16, seed=130)
+    if kind == "pagerank":
+        ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.8, np.full(g.n, 0.2), eps=1e-13)
+        pe, pl = pr_problem(daic, g), pr_problem(daic, g)
+        re = pe.run(eps=1e-6, q=0.1, sched="exact")
+        rl = pl.run(eps=1e-6, q=0.1, sched="learned", model=m)
+        assert re.converged and rl.converged
+        assert np.abs(pl.get() - ref).sum() / ref.sum() <= 1e-5
+    else:
+        w = daic_gen.sssp_weights(g.m, seed=131)
+        ref = oracle.dijkstra(g, w, 0)
+        pe, pl = sssp_problem(daic, g, w), sssp_problem(daic, g, w)
+        re = pe.run(q=0.1, sched="exact")
+        rl = pl.run(q=0.1, sched="learned", model=m)
+        assert re.converged and rl.converged
+        np.testing.assert_array_equal(pl.get(), ref)
+    st = rl.stats
+    say("exact pushed", re.stats["pushed_edges"], "rounds", re.stats["rounds"], "learned pushed",
+        st["pushed_edges"], "rounds", st["rounds"], "fallbacks", st["learned_fallbacks"], "exact rounds",
+        st["learned_exact_rounds"])
+    assert st["learned_exact_rounds"] >= 1
+    assert st["learned_fallbacks"] >= 1
+    assert st["learned_exact_rounds"] < st["rounds"]
+
+
+def test_learned_rounds_captured_equal_eager(daic, trained_pr, monkeypatch):
+    """Learned rounds (scoring, selection, judge) captured in a graph give
+    the same rounds, messages and state, bit for bit, as the same rounds
+    launched one by one; a change of the network's parameters is seen by
+    the next run (the captured graph is rebuilt)."""
+    say("case learned captured vs eager")
+    m, _, _ = trained_pr
+    g = daic_gen.rmat(14, 16, seed=140)
+    runs = []
+    for eager in (False, True):
+        if eager:
+            monkeypatch.setenv("DAIC_NO_GRAPH", "1")
+        p = pr_problem(daic, g)
+        r = p.run(eps=1e-6, q=0.1, sched="learned", model=m, rounds_per_check=8)
+        assert r.converged
+        runs.append((r.stats, p.get(with_dv=True)))
+    monkeypatch.delenv("DAIC_NO_GRAPH")
+    (sa, (va, da)), (sb, (vb, db)) = runs
+    for k in ("rounds", "pushed_edges", "activations", "learned_fallbacks", "learned_exact_rounds"):
+        assert sa[k] == sb[k], k
+    np.testing.assert_array_equal(va, vb)
+    np.testing.assert_array_equal(da, db)
+    # the same problem object re-run after the network changed: the result
+    # must follow the new network (the inverted one), not a stale capture
+    p = pr_problem(daic, g)
+    r1 = p.run(eps=1e-6, q=0.1, sched="learned", model=m)
+    bad = inverted_model(daic)
+    p.set_init(*oracle.pagerank_init(g.n, 0.8))
+    r2 = p.run(eps=1e-6, q=0.1, sched="learned", model=bad)
+    q = pr_problem(daic, g)
+    r3 = q.run(eps=1e-6, q=0.1, sched="learned", model=bad)
+    assert r2.stats["pushed_edges"] == r3.stats["pushed_edges"]
+    assert r2.stats["learned_fallbacks"] == r3.stats["learned_fallbacks"]
+    # the same network object with new feature scales (every score 0.5)
+    bad.set_features(np.array([100.0, 0.0, 0.0], np.float32), np.ones(3, np.float32))
+    p.set_init(*oracle.pagerank_init(g.n, 0.8))
+    r4 = p.run(eps=1e-6, q=0.1, sched="learned", model=bad)
+    q2 = pr_problem(daic, g)
+    r5 = q2.run(eps=1e-6, q=0.1, sched="learned", model=bad)
+    assert r4.stats["pushed_edges"] == r5.stats["pushed_edges"]
+    assert r4.stats["pushed_edges"] != r2.stats["pushed_edges"]
+    say("runs", r1.stats["pushed_edges"], r2.stats["pushed_edges"], r4.stats["pushed_edges"])
+
+
 # ---------------------------------------------------------------------------
 # Trace rule, Adam step, trainer and model serialization against the oracle
 # ---------------------------------------------------------------------------
