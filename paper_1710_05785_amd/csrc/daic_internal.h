@@ -151,8 +151,8 @@ namespace daic {
 // cut into tiles of at most kTileE; a partition with one tile is summed and
 // finished by one workgroup, the tiles of a larger one store partial sums that
 // a finishing kernel adds in tile order.
-constexpr uint32_t kTileT = 8192;      // targets per partition (local ids fit 13 bits)
-constexpr uint32_t kTileE = 131072;    // in-edges per tile
+constexpr uint32_t kTileT = 16384;     // targets per partition (local ids fit 14 bits)
+constexpr uint32_t kTileE = 196608;    // in-edges per tile
 constexpr uint16_t kPairStart = 0x8000;  // flag of a pair's first in-edge in tloc
 struct TileGraph {
   bool ready = false;

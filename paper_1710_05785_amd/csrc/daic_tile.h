@@ -8,7 +8,8 @@
 //   k_tile_pull  : a workgroup per tile. Each run of in-edges from one source
 //                  into the partition gathers that source's base once; every
 //                  in-edge adds it (times its weight) into an FP64 LDS
-//                  accumulator of its target. A partition of one tile is then
+//                  accumulator of its target (128 KiB: one 1024-thread
+//                  workgroup per CU). A partition of one tile is then
 //                  finished by the same workgroup; a tile of a larger one
 //                  stores its accumulators as a partial-sum slot.
 //   k_tile_finish: targets of partitions with several tiles: their slots added
@@ -50,11 +51,13 @@ struct TileArgs {
   uint64_t* spart_p;
 };
 
-constexpr uint32_t kTileThreads = 512;
+// FP64 LDS atomics run at about twice the rate of FP32 ones here, so the
+// accumulators are FP64 whatever the state type.
+constexpr uint32_t kTileThreads = 1024;
 constexpr uint32_t kTileWaves = kTileThreads / 64;
 constexpr uint32_t kTileU = 12;  // 64-in-edge segments a wave has in flight per step
 
-// Finishes targets [base + i] for i = tid, tid + 512, ... < count with new
+// Finishes targets [base + i] for i = tid, tid + nthreads, ... < count with new
 // deltas d(i), four targets per step with their operands loaded first.
 template <int ST, int G, bool FUSED, typename D>
 __device__ __forceinline__ void tile_finish_targets(const KArgs& a, typename Tr<ST>::S* mu_out, uint64_t base,
@@ -198,6 +201,7 @@ __global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
     if (ctl_halted(ctl) || (!FUSED && !ctl->last_pull)) return;
     const bool odd = FUSED && ((ctl->rounds - ctl->fuse_base) & 1) != 0;
     S* mu_out = static_cast<S*>(odd ? a.mu_pi : a.mu_pi2);
+    const double* pbuf = t.pbuf;
     const uint32_t tid = threadIdx.x;
     constexpr uint32_t kChunks = kTileT / 256;
     double r_part = 0.0;
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
       for (uint32_t k = k0; k < k1; k += 16) {
         double x[16];
 #pragma unroll
-        for (uint32_t u = 0; u < 16; ++u) x[u] = t.pbuf[(uint64_t)min(k + u, k1 - 1) * kTileT + i];
+        for (uint32_t u = 0; u < 16; ++u) x[u] = pbuf[(uint64_t)min(k + u, k1 - 1) * kTileT + i];
 #pragma unroll
         for (uint32_t u = 0; u < 16; ++u)
           if (k + u < k1) sum += x[u];

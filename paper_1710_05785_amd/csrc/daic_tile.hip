@@ -15,7 +15,7 @@ namespace daic {
 
 namespace {
 
-constexpr uint32_t kLocBits = 13;  // log2(kTileT)
+constexpr uint32_t kLocBits = 14;  // log2(kTileT)
 static_assert((1u << kLocBits) == kTileT, "partition width");
 
 uint32_t tgrid(uint64_t count) {

@@ -124,7 +124,7 @@ def test_fused_dense_rounds_match_plain_rounds(daic, monkeypatch, state, gk, til
     counters: to convergence and when stopped by the round limit. RMAT-16
     with edge factor 16 has targets with more than 2,048 in-edges, which the
     fused round finishes through per-group tickets. tiled: the fused round
-    walks partitions of 8,192 targets in source order (one gather per
+    walks partitions of 16,384 targets in source order (one gather per
     source and partition); RMAT-16 has partitions cut into several tiles,
     whose partial sums a finishing kernel adds."""
     say("case fused vs plain", state, gk, "tiled", tiled)
