@@ -608,7 +608,7 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="only run the sync / round-robin / priority comparison")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="run one plain 1 GiB device copy (counter calibration)")
+                    help="run one plain 1 GiB device copy and one 1 GiB line-permuted gather (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -664,8 +664,15 @@ def main():
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         torch.mul(a, 2.0, out=b)
+        # a gather of known footprint: every 128-byte line of a read once, by
+        # 32 consecutive lanes, the lines in random order (1 GiB gathered, the
+        # 2 GiB index array streamed, 1 GiB written)
+        lines = torch.randperm(1 << 23, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+        idx = (lines.repeat_interleave(32) * 32 + torch.arange(32, device="cuda").repeat(1 << 23))
         torch.cuda.synchronize()
-        del a, b
+        torch.index_select(a, 0, idx, out=b)
+        torch.cuda.synchronize()
+        del a, b, lines, idx
 
     for _ in range(args.warmup):
         P.set_init_device(v0, dv1)

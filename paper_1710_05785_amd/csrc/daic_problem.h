@@ -70,7 +70,7 @@ struct daic_problem {
   uint64_t* spart_a = nullptr;
   uint64_t* spart_p = nullptr;
   uint32_t tile_grid = 2048;     // workgroups of k_tile_pull (at most)
-  uint32_t tfin_grid = 1024;     // workgroups of k_tile_finish (at most)
+  uint32_t tfin_grid = 4096;     // workgroups of k_tile_finish (at most)
   uint64_t k_sel = 0;      // dense-round rule of the current run (see k_residual)
   uint64_t pull_min = 0;
   // learned scheduler state (allocated on first use)

@@ -55,7 +55,7 @@ struct TileArgs {
 // accumulators are FP64 whatever the state type.
 constexpr uint32_t kTileThreads = 1024;
 constexpr uint32_t kTileWaves = kTileThreads / 64;
-constexpr uint32_t kTileU = 12;  // 64-in-edge segments a wave has in flight per step
+constexpr uint32_t kTileU = 16;  // 64-in-edge segments a wave has in flight per step
 
 // Finishes targets [base + i] for i = tid, tid + nthreads, ... < count with new
 // deltas d(i), four targets per step with their operands loaded first.
