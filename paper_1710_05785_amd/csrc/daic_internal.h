@@ -143,19 +143,21 @@ struct PullGraph {
 }  // namespace daic
 
 namespace daic {
-// Partition-tiled in-edge form of the fused dense round. Targets are cut into
-// partitions of kTileT consecutive ids. Inside a partition the in-edges are
+// Partition-tiled in-edge form of dense rounds. Targets are cut into
+// partitions of 2^tbits consecutive ids (kTileT, or narrower for graphs with
+// fewer than 1,024 kTileT-wide partitions, so that a round has enough tiles). Inside a partition the in-edges are
 // sorted by (renumbered source, target), so the in-edges one source sends
 // into the partition are consecutive: such a run is a "pair" (source,
 // partition) whose message base is gathered once. A partition's in-edges are
 // cut into tiles of at most kTileE; a partition with one tile is summed and
 // finished by one workgroup, the tiles of a larger one store partial sums that
 // a finishing kernel adds in tile order.
-constexpr uint32_t kTileT = 16384;     // targets per partition (local ids fit 14 bits)
+constexpr uint32_t kTileT = 16384;     // most targets per partition (local ids fit 14 bits)
 constexpr uint32_t kTileE = 196608;    // in-edges per tile
 constexpr uint16_t kPairStart = 0x8000;  // flag of a pair's first in-edge in tloc
 struct TileGraph {
   bool ready = false;
+  uint32_t tbits = 14;             // partition width 2^tbits (at most kTileT; smaller graphs get narrower ones)
   uint64_t n_part = 0, n_tiles = 0, n_pairs = 0, n_split = 0, n_slots = 0, n_seg = 0;
   uint16_t* tloc = nullptr;        // [m] target - partition base, | kPairStart at a pair's first in-edge
   uint32_t* psrc = nullptr;        // [n_pairs] renumbered source of each pair

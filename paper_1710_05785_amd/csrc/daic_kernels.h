@@ -7,12 +7,17 @@
 //                             the message base mu_j, compact into degree bins
 //                             (sparse rounds) or publish mu_j (dense rounds)
 //   k_bin_scan              : prefix of the per-block bin counts
-//   A5 k_push_small/large   : atomic (+) of g(mu_j) into dv_k for every out-edge
-//      k_pull_stream        : dense rounds: every target sums its in-neighbours'
-//                             bases (then k_pull_finish: residual and stop rule)
+//   A5 k_push               : atomic (+) of g(mu_j) into dv_k for every out-edge
+//                             (small and large bins in one launch)
+//      dense rounds         : every target combines its in-neighbours' bases,
+//                             through the tiled in-edges (daic_tile.h: sum, min
+//                             and max problems) or, without them, k_pull_stream
+//                             (sum problems; then k_pull_finish: residual and
+//                             stop rule)
 //   A1 k_residual + k_residual_final : residual of the new state and the stop rule
-// Fused dense rounds (every pending vertex, sum problems): k_pull_fused +
-// k_fused_finish per round after one priming claim.
+// Fused dense rounds (every pending vertex, sum problems): the tiled kernels
+// with FUSED = true, or k_pull_fused + k_fused_finish, per round after one
+// priming claim.
 // The claim happens in a kernel of its own, before any push of the round, so
 // every message of the round lands in dv after the claim: it is folded in a
 // later round and never lost (the receive/update split of Eq. async).
@@ -323,7 +328,15 @@ __global__ __launch_bounds__(256) void k_residual(KArgs a, int skip_dense = 0) {
         r += x;
         cnt += x > 0.0;
       } else {
-        cnt += prio_key<ST>(vj[u], dj[u]) != 0;
+        const bool pend = prio_key<ST>(vj[u], dj[u]) != 0;
+        cnt += pend;
+        // with dense rounds set up (32-bit row offsets): the out-edges of the
+        // pending vertices, from which the next round's direction is chosen
+        if (pend && a.perm != nullptr) {
+          const uint32_t* row = static_cast<const uint32_t*>(a.row);
+          const uint64_t j = j0 + 256 * u;
+          r += (double)(row[j + 1] - row[j]);
+        }
       }
     }
   }
@@ -335,10 +348,27 @@ __global__ __launch_bounds__(256) void k_residual(KArgs a, int skip_dense = 0) {
   }
 }
 
+// The direction of the next round: a dense round (pull over in-edges) when
+// the next round is expected to do enough work. Sum problems: at least
+// pull_min vertices expected to update (min(pending, k_sel)). Min and max
+// problems: at least pull_min messages expected, estimated from the
+// out-edges of the pending vertices (pend_edges) scaled to the share of
+// them the next round selects. k_sel = 0 disables dense rounds.
+template <int ST>
+__device__ __forceinline__ uint32_t next_is_dense(uint64_t nn, double pend_edges, uint64_t k_sel, uint64_t pull_min) {
+  const uint64_t k_next = nn < k_sel ? nn : k_sel;
+  if (k_sel == 0) return 0u;
+  if constexpr (Tr<ST>::sum) {
+    return k_next >= pull_min ? 1u : 0u;
+  } else {
+    const double est = nn ? pend_edges * ((double)k_next / (double)nn) : 0.0;
+    return est >= (double)pull_min ? 1u : 0u;
+  }
+}
+
 // Besides the residual, k_residual_final picks the direction of the next
-// round: a dense round (pull over in-edges) when at least pull_min vertices
-// are expected to update (min(pending, k_sel)); k_sel = 0 disables dense
-// rounds. One block; it returns in the cases where k_residual returned.
+// round (next_is_dense). One block; it returns in the cases where k_residual
+// returned.
 template <int ST>
 __global__ __launch_bounds__(256) void k_residual_final(KArgs a, int count_round, uint64_t k_sel,
                                                         uint64_t pull_min, int skip_dense = 0) {
@@ -372,7 +402,7 @@ __global__ __launch_bounds__(256) void k_residual_final(KArgs a, int count_round
     bool done = Tr<ST>::sum ? (rr <= ctl->eps || nn == 0) : (nn == 0);
     ctl->done = done ? 1u : 0u;
     ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
-    ctl->pull = (k_sel != 0 && (nn < k_sel ? nn : k_sel) >= pull_min) ? 1u : 0u;
+    ctl->pull = next_is_dense<ST>(nn, rr, k_sel, pull_min);  // rr: pending vertices' out-edges (min/max)
   }
 }
 
@@ -929,11 +959,16 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
         gain += (double)prio_value<ST>(vj, dj);
       }
     }
-    if (pull) {  // dense round: every sender publishes its message base (0 if silent)
-      if constexpr (Tr<ST>::sum) {
-        if (in) {
-          const uint32_t pj = a.perm[j];
-          if (pj < a.n_src) static_cast<S*>(a.mu_pi)[pj] = send ? mu : (S)0;  // no reader otherwise
+    if (pull) {  // dense round: every sender publishes its message base (the identity if silent)
+      if (in) {
+        const uint32_t pj = a.perm[j];
+        if (pj < a.n_src) {  // no reader otherwise
+          S silent;
+          if constexpr (Tr<ST>::sum) silent = (S)0;
+          else if constexpr (ST == ST_U32) silent = kInfU32;
+          else if constexpr (ST == ST_F64MIN) silent = __builtin_huge_val();
+          else silent = -1;
+          static_cast<S*>(a.mu_pi)[pj] = send ? mu : silent;
         }
       }
       act += sel ? 1 : 0;
@@ -984,63 +1019,98 @@ __global__ __launch_bounds__(256) void k_claim(KArgs a) {
   }
 }
 
-// Prefix of the bin counts and the round's work counters (one block).
+// Prefix of the bin counts and the round's work counters (one block of 1024
+// threads, two per-block entries per thread: every load is issued before any
+// scan step, so the kernel pays one memory round trip).
+static_assert(kMaxScanBlocks <= 2048, "k_bin_scan takes two per-block entries per thread");
 static __global__ __launch_bounds__(1024) void k_bin_scan(KArgs a) {
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
   const uint32_t pull = ctl->pull;
-  if (threadIdx.x == 0) ctl->last_pull = pull;
-  if (!pull) {  // the bins feed the push kernels only
-    excl_prefix_1024(a.blk_small, a.off_small, a.blocks, &ctl->n_small);
-    __syncthreads();
-    excl_prefix_1024(a.blk_large, a.off_large, a.blocks, &ctl->n_large);
-    __syncthreads();
-  } else if (threadIdx.x == 0) {
-    ctl->n_small = 0;
-    ctl->n_large = 0;
-  }
-  if (a.last_upd != nullptr) {  // learned runs: the realized priority, summed in a fixed order
-    double g = 0.0;
-    for (uint32_t i = threadIdx.x; i < a.blocks; i += 1024) g += a.part_r[i];
-    g = wave_sum(g);
-    __shared__ double s_g[16];
-    if (lane_id() == 0) s_g[threadIdx.x >> 6] = g;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < 16; ++w) t += s_g[w];
-      ctl->l_gain = t;
+  const uint32_t nb = a.blocks, tid = threadIdx.x, i0 = 2 * tid, i1 = 2 * tid + 1;
+  const uint32_t lane = lane_id(), wave = tid >> 6;
+  const bool learned = a.last_upd != nullptr;  // learned runs: the realized priority, summed in a fixed order
+  uint32_t bs[2] = {0, 0}, bl[2] = {0, 0};
+  uint64_t act = 0, push = 0, pl = 0;
+  double g = 0.0;
+#pragma unroll
+  for (uint32_t u = 0; u < 2; ++u) {
+    const uint32_t i = i0 + u;
+    if (i < nb) {
+      bs[u] = a.blk_small[i];
+      bl[u] = a.blk_large[i];
+      act += a.blk_act[i];
+      push += a.blk_push[i];
+      pl += a.blk_push_large[i];
+      if (learned) g += a.part_r[i];
     }
   }
-  uint64_t act = 0, push = 0, pl = 0;
-  for (uint32_t i = threadIdx.x; i < a.blocks; i += 1024) {
-    act += a.blk_act[i];
-    push += a.blk_push[i];
-    pl += a.blk_push_large[i];
+  const uint64_t xs = (uint64_t)bs[0] + bs[1], xl = (uint64_t)bl[0] + bl[1];
+  uint64_t ss = xs, sl = xl;  // wave inclusive scans
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t ys = __shfl_up(ss, d, 64), yl = __shfl_up(sl, d, 64);
+    if (lane >= (uint32_t)d) {
+      ss += ys;
+      sl += yl;
+    }
   }
   act = wave_sum(act);
   push = wave_sum(push);
   pl = wave_sum(pl);
-  __shared__ uint64_t s_a[16], s_p[16], s_l[16];
-  if (lane_id() == 0) {
-    s_a[threadIdx.x >> 6] = act;
-    s_p[threadIdx.x >> 6] = push;
-    s_l[threadIdx.x >> 6] = pl;
+  g = wave_sum(g);
+  __shared__ uint64_t w_s[16], w_l[16], w_a[16], w_p[16], w_pl[16];
+  __shared__ double w_g[16];
+  if (lane == 63) {
+    w_s[wave] = ss;
+    w_l[wave] = sl;
+    w_a[wave] = act;
+    w_p[wave] = push;
+    w_pl[wave] = pl;
+    w_g[wave] = g;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t ta = 0, tp = 0, tl = 0;
-    for (int w = 0; w < 16; ++w) {
-      ta += s_a[w];
-      tp += s_p[w];
-      tl += s_l[w];
+  if (!pull) {  // the bins feed the push kernels only
+    uint64_t os = 0, ol = 0;
+    for (uint32_t w = 0; w < wave; ++w) {
+      os += w_s[w];
+      ol += w_l[w];
     }
+    const uint64_t es = os + ss - xs, el = ol + sl - xl;
+    if (i0 < nb) {
+      a.off_small[i0] = es;
+      a.off_large[i0] = el;
+    }
+    if (i1 < nb) {
+      a.off_small[i1] = es + bs[0];
+      a.off_large[i1] = el + bl[0];
+    }
+  }
+  if (tid == 0) {
+    uint64_t ts = 0, tl = 0, ta = 0, tp = 0, tpl = 0;
+    double tg = 0.0;
+    for (int w = 0; w < 16; ++w) {
+      ts += w_s[w];
+      tl += w_l[w];
+      ta += w_a[w];
+      tp += w_p[w];
+      tpl += w_pl[w];
+      tg += w_g[w];
+    }
+    ctl->last_pull = pull;
+    if (!pull) {
+      a.off_small[nb] = ts;
+      a.off_large[nb] = tl;
+    }
+    ctl->n_small = pull ? 0 : ts;
+    ctl->n_large = pull ? 0 : tl;
+    if (learned) ctl->l_gain = tg;
     ctl->activations += ta;
     ctl->pushed += tp;
-    ctl->pushed_large += tl;
+    ctl->pushed_large += tpl;
     ctl->round_act = ta;
     ctl->round_pushed = tp;
-    ctl->round_pushed_large = tl;
+    ctl->round_pushed_large = tpl;
   }
 }
 
@@ -1050,10 +1120,9 @@ static __global__ __launch_bounds__(1024) void k_bin_scan(KArgs a) {
 // busy whatever the degree mix and column reads stay contiguous.
 // ---------------------------------------------------------------------------
 template <int ST, int G, typename RowT>
-__global__ __launch_bounds__(64) void k_push_small(KArgs a) {
+__device__ __forceinline__ void push_small_items(const KArgs& a, uint64_t bid, uint64_t nb) {
   using S = typename Tr<ST>::S;
   Ctl* ctl = a.ctl;
-  if (ctl_halted(ctl) || ctl->pull) return;
   const uint64_t total = ctl->n_small;
   __shared__ uint8_t owner[64 * kSmallMaxDeg];
   __shared__ uint32_t s_excl[64];
@@ -1061,7 +1130,7 @@ __global__ __launch_bounds__(64) void k_push_small(KArgs a) {
   __shared__ S s_mu[64];
   const uint32_t lane = threadIdx.x;
   const S* small_mu = static_cast<const S*>(a.small_mu);
-  for (uint64_t g = blockIdx.x; g * 64 < total; g += gridDim.x) {
+  for (uint64_t g = bid; g * 64 < total; g += nb) {
     const uint64_t i = g * 64 + lane;
     uint32_t deg = 0;
     uint64_t beg = 0;
@@ -1092,13 +1161,12 @@ __global__ __launch_bounds__(64) void k_push_small(KArgs a) {
 
 // A5, large bin: one wave per item of up to kChunk consecutive out-edges.
 template <int ST, int G, typename RowT>
-__global__ __launch_bounds__(64) void k_push_large(KArgs a) {
+__device__ __forceinline__ void push_large_items(const KArgs& a, uint64_t bid, uint64_t nb) {
   using S = typename Tr<ST>::S;
   Ctl* ctl = a.ctl;
-  if (ctl_halted(ctl) || ctl->pull) return;
   const uint64_t total = ctl->n_large;
   const S* large_mu = static_cast<const S*>(a.large_mu);
-  for (uint64_t i = blockIdx.x; i < total; i += gridDim.x) {
+  for (uint64_t i = bid; i < total; i += nb) {
     uint32_t blk = find_block(a.off_large, a.blocks, i);
     uint64_t idx = a.large_off[blk] + (i - a.off_large[blk]);
     uint32_t vid = a.large_vid[idx];
@@ -1110,6 +1178,16 @@ __global__ __launch_bounds__(64) void k_push_large(KArgs a) {
     uint64_t end = min(re, beg + kChunk);
     for (uint64_t e = beg + threadIdx.x; e < end; e += 64) push_edge<ST, G>(a, e, mu);
   }
+}
+
+// A5: both bins in one launch, the first small_blocks one-wave workgroups on
+// the small bin and the others on the large bin.
+template <int ST, int G, typename RowT>
+__global__ __launch_bounds__(64) void k_push(KArgs a, uint32_t small_blocks) {
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl) || ctl->pull) return;
+  if (blockIdx.x < small_blocks) push_small_items<ST, G, RowT>(a, blockIdx.x, small_blocks);
+  else push_large_items<ST, G, RowT>(a, blockIdx.x - small_blocks, gridDim.x - small_blocks);
 }
 
 // ---------------------------------------------------------------------------

@@ -130,22 +130,35 @@ struct Impl {
   static void round(daic_problem* p, const daic_run_opts* o, hipStream_t s, const float* score, Prof* pr) {
     KArgs a = p->a;
     a.score = score;
-    threshold(p, o, s, a, ~0ull, pr);
+    // every pending vertex: the control block keeps mode 0 from the run's
+    // start, so the rounds need no threshold kernel
+    if (o->sched != DAIC_SCHED_ALL) threshold(p, o, s, a, ~0ull, pr);
     launch(pr, "claim", s, [&] {
       hipLaunchKernelGGL((k_claim<ST, G, RowT, false>), dim3(a.blocks), dim3(256), 0, s, a);
     });
     launch(pr, "bin_scan", s, [&] { hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a); });
-    launch(pr, "push_small", s, [&] {
-      hipLaunchKernelGGL((k_push_small<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
+    launch(pr, "push_edges", s, [&] {
+      hipLaunchKernelGGL((k_push<ST, G, RowT>), dim3(2 * push_grid()), dim3(64), 0, s, a, push_grid());
     });
-    launch(pr, "push_large", s, [&] {
-      hipLaunchKernelGGL((k_push_large<ST, G, RowT>), dim3(push_grid()), dim3(64), 0, s, a);
-    });
-    if (p->pull_ready && p->tile_ready) {  // dense rounds through the tiled in-edges
+    if (p->pull_ready && p->tile_ready && !Tr<ST>::sum) {  // dense rounds of min and max problems
       const TileArgs t = tile_args(p);
       const uint32_t np = tile_pull_grid(p), nfin = tile_finish_grid(p);
       launch(pr, "pull_tile", s, [&] {
-        hipLaunchKernelGGL((k_tile_pull<ST, G, false>), dim3(np), dim3(kTileThreads), 0, s, a, t);
+        if (t.tw > kNarrowTW) hipLaunchKernelGGL((k_tile_pull_mm<ST, G, 1024>), dim3(np), dim3(1024), 0, s, a, t);
+        else hipLaunchKernelGGL((k_tile_pull_mm<ST, G, 256>), dim3(np), dim3(256), 0, s, a, t);
+      });
+      launch(pr, "pull_tile_finish", s, [&] {
+        hipLaunchKernelGGL((k_tile_finish_mm<ST, G>), dim3(nfin), dim3(256), 0, s, a, t);
+      });
+      launch(pr, "pull_tile_total", s, [&] {
+        hipLaunchKernelGGL((k_tile_total<ST, false>), dim3(1), dim3(256), 0, s, a, t, np, nfin, p->k_sel, p->pull_min);
+      });
+    } else if (p->pull_ready && p->tile_ready) {  // dense rounds through the tiled in-edges
+      const TileArgs t = tile_args(p);
+      const uint32_t np = tile_pull_grid(p), nfin = tile_finish_grid(p);
+      launch(pr, "pull_tile", s, [&] {
+        if (t.tw > kNarrowTW) hipLaunchKernelGGL((k_tile_pull<ST, G, false, 1024>), dim3(np), dim3(1024), 0, s, a, t);
+        else hipLaunchKernelGGL((k_tile_pull<ST, G, false, 256>), dim3(np), dim3(256), 0, s, a, t);
       });
       launch(pr, "pull_tile_finish", s, [&] {
         hipLaunchKernelGGL((k_tile_finish<ST, G, false>), dim3(nfin), dim3(256), 0, s, a, t);
@@ -212,6 +225,7 @@ struct Impl {
     t.n_tiles = T.n_tiles;
     t.n_split = T.n_split;
     t.n_seg = T.n_seg;
+    t.tw = 1u << T.tbits;
     t.tpart_r = p->tpart_r;
     t.tpart_a = p->tpart_a;
     t.tpart_p = p->tpart_p;
@@ -224,7 +238,8 @@ struct Impl {
     return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->g->tile.n_tiles, p->tile_grid));
   }
   static uint32_t tile_finish_grid(const daic_problem* p) {
-    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(p->g->tile.n_split * (kTileT / 256), p->tfin_grid));
+    return (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>(p->g->tile.n_split * ((1ull << p->g->tile.tbits) / 256), p->tfin_grid));
   }
 
   static void fused_round(daic_problem* p, hipStream_t s, Prof* pr) {
@@ -233,7 +248,10 @@ struct Impl {
         const TileArgs t = tile_args(p);
         const uint32_t np = tile_pull_grid(p), nfin = tile_finish_grid(p);
         launch(pr, "tile_pull", s, [&] {
-          hipLaunchKernelGGL((k_tile_pull<ST, G, true>), dim3(np), dim3(kTileThreads), 0, s, p->a, t);
+          if (t.tw > kNarrowTW)
+            hipLaunchKernelGGL((k_tile_pull<ST, G, true, 1024>), dim3(np), dim3(1024), 0, s, p->a, t);
+          else
+            hipLaunchKernelGGL((k_tile_pull<ST, G, true, 256>), dim3(np), dim3(256), 0, s, p->a, t);
         });
         launch(pr, "tile_finish", s, [&] {
           hipLaunchKernelGGL((k_tile_finish<ST, G, true>), dim3(nfin), dim3(256), 0, s, p->a, t);
@@ -402,7 +420,9 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
   p->pull_min = 0;
   const bool sum = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
   const GraphDev& d = p->g->dev;
-  if (!sum || std::getenv("DAIC_NO_PULL") || !d.row32 || d.m > 0x7FFFFFFFull || d.n > 0x7FFFFFFFull)
+  // min and max problems take dense rounds through the tiled in-edges only
+  if ((!sum && std::getenv("DAIC_NO_TILE")) || std::getenv("DAIC_NO_PULL") || !d.row32 || d.m > 0x7FFFFFFFull ||
+      d.n > 0x7FFFFFFFull)
     return DAIC_OK;
   if (!p->pull_ready) {
     daic_graph* g = const_cast<daic_graph*>(p->g);
@@ -485,7 +505,7 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
       p->allocs.push_back(*q);
       return DAIC_OK;
     };
-    if ((rc = grab((void**)&p->tile_pbuf, T.n_slots * (uint64_t)kTileT * 8)) ||
+    if ((rc = grab((void**)&p->tile_pbuf, T.n_slots * (1ull << T.tbits) * 8)) ||
         (rc = grab((void**)&p->tpart_r, (uint64_t)p->tile_grid * 8)) ||
         (rc = grab((void**)&p->tpart_a, (uint64_t)p->tile_grid * 8)) ||
         (rc = grab((void**)&p->tpart_p, (uint64_t)p->tile_grid * 8)) ||
@@ -493,6 +513,17 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
         (rc = grab((void**)&p->spart_a, (uint64_t)p->tfin_grid * 8)) ||
         (rc = grab((void**)&p->spart_p, (uint64_t)p->tfin_grid * 8)))
       return rc;
+    if (p->gk == DAIC_G_EDGE_ADD) {  // weights in tile order: uint32 (U32 state) or double
+      if (p->st == ST_U32) {
+        if ((rc = grab(&p->tile_w, d.m * 4))) return rc;
+        hipLaunchKernelGGL(k_gather_weights<uint32_t>, dim3(grid_for(d.m)), dim3(256), 0, s,
+                           static_cast<const uint32_t*>(p->a.w), T.eid, d.m, static_cast<uint32_t*>(p->tile_w));
+      } else {
+        if ((rc = grab(&p->tile_w, d.m * 8))) return rc;
+        hipLaunchKernelGGL(k_gather_weights<double>, dim3(grid_for(d.m)), dim3(256), 0, s,
+                           static_cast<const double*>(p->a.w), T.eid, d.m, static_cast<double*>(p->tile_w));
+      }
+    }
     if (p->gk == DAIC_G_EDGE_SCALE) {
       const size_t S = state_size(p->st);
       if ((rc = grab(&p->tile_w, d.m * S))) return rc;
@@ -510,11 +541,16 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
       p->exec_fused = nullptr;
     }
   }
-  uint64_t div = 32;
-  if (const char* e = std::getenv("DAIC_PULL_DIV")) div = std::max<uint64_t>(1, std::strtoull(e, nullptr, 10));
+  // the dense-round threshold: sum problems n / 32 vertices expected to
+  // update; min and max problems m / 4 messages expected (their pushes are
+  // filtered by v and dv and cheap per message, so a pull over every in-edge
+  // pays only for wide frontiers)
+  uint64_t div = sum ? 32 : 4;
+  if (const char* e = std::getenv(sum ? "DAIC_PULL_DIV" : "DAIC_PULL_EDGE_DIV"))
+    div = std::max<uint64_t>(1, std::strtoull(e, nullptr, 10));
   const uint64_t n = d.n;
   p->k_sel = o->sched == DAIC_SCHED_ALL ? n : std::max<uint64_t>(1, (uint64_t)std::ceil(o->priority_fraction * (double)n));
-  p->pull_min = std::max<uint64_t>(1, (n + div - 1) / div);
+  p->pull_min = std::max<uint64_t>(1, ((sum ? n : d.m) + div - 1) / div);
   return DAIC_OK;
 }
 
@@ -1026,10 +1062,9 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
   const double e = per_edge_bytes(p);
   const double n = (double)p->g->dev.n;
   const double small_edges = (double)(c.round_pushed - c.round_pushed_large);
-  if (!std::strcmp(name, "push_small"))
-    return small_edges * e + (double)c.n_small * (4.0 + S + 2.0 * R);
-  if (!std::strcmp(name, "push_large"))
-    return (double)c.round_pushed_large * e + (double)c.n_large * (8.0 + S + 2.0 * R);
+  if (!std::strcmp(name, "push_edges"))  // per edge as per_edge_bytes; per item vid, base and row offsets (+ chunk)
+    return (small_edges + (double)c.round_pushed_large) * e + (double)c.n_small * (4.0 + S + 2.0 * R) +
+           (double)c.n_large * (8.0 + S + 2.0 * R);
   if (!std::strcmp(name, "claim")) {
     double kahan = p->st == ST_F32K ? 8.0 : 0.0;
     double out = c.last_pull ? n * (4.0 + S) : (double)(c.n_small + c.n_large) * (4.0 + S);
@@ -1064,14 +1099,20 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
   }
   if (!std::strcmp(name, "pull_tile") || !std::strcmp(name, "pull_tile_finish")) {
     // as tile_pull / tile_finish below with a target's finish reduced to its
-    // dv read and written (2S): the claim of these rounds ran before
+    // dv read and written (2S; min and max problems also read v: 3S): the
+    // claim of these rounds ran before. Weights in tile order: S (EDGE_SCALE)
+    // or the weight type (EDGE_ADD) per in-edge.
     const TileGraph& T = p->g->tile;
-    const double split_targets = (double)T.n_split * kTileT;
-    const double slots = (double)T.n_slots * kTileT * 8.0;
+    const bool sum = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
+    const double tw = (double)(1ull << T.tbits);
+    const double split_targets = (double)T.n_split * tw;
+    const double slots = (double)T.n_slots * tw * (sum ? 8.0 : S);
+    const double wb = p->gk == DAIC_G_EDGE_SCALE ? S : p->gk == DAIC_G_EDGE_ADD ? (p->st == ST_U32 ? 4.0 : 8.0) : 0.0;
+    const double fin = (sum ? 2.0 : 3.0) * S;
     if (!std::strcmp(name, "pull_tile"))
-      return (double)p->g->dev.m * (2.0 + (p->gk == DAIC_G_EDGE_SCALE ? S : 0.0)) + (double)T.n_pairs * (4.0 + S) +
-             (double)T.n_seg * 4.0 + (double)T.n_tiles * 12.0 + std::max(0.0, n - split_targets) * 2.0 * S + slots;
-    return slots + std::min(n, split_targets) * 2.0 * S;
+      return (double)p->g->dev.m * (2.0 + wb) + (double)T.n_pairs * (4.0 + S) + (double)T.n_seg * 4.0 +
+             (double)T.n_tiles * 12.0 + std::max(0.0, n - split_targets) * fin + slots;
+    return slots + std::min(n, split_targets) * fin;
   }
   if (!std::strcmp(name, "tile_pull") || !std::strcmp(name, "tile_finish")) {
     // tile_pull: per in-edge its local target 2 (+ weight S), per (source,
@@ -1085,8 +1126,9 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
     const TileGraph& T = p->g->tile;
     const double kahan = p->st == ST_F32K ? 8.0 : 0.0;
     const double fin = 2.0 * S + 2.0 * S + kahan + 2.0 * R + 4.0 + S;
-    const double split_targets = (double)T.n_split * kTileT;  // upper bound (the last partition may be short)
-    const double slots = (double)T.n_slots * kTileT * 8.0;
+    const double tw = (double)(1ull << T.tbits);
+    const double split_targets = (double)T.n_split * tw;  // upper bound (the last partition may be short)
+    const double slots = (double)T.n_slots * tw * 8.0;
     if (name[5] == 'p')
       return (double)p->g->dev.m * (2.0 + (p->gk == DAIC_G_EDGE_SCALE ? S : 0.0)) + (double)T.n_pairs * (4.0 + S) +
              (double)T.n_seg * 4.0 + (double)T.n_tiles * 12.0 + std::max(0.0, n - split_targets) * fin + slots;
@@ -1173,8 +1215,7 @@ daic_status daic_profile(daic_problem* p, const daic_run_opts* o, uint32_t cap, 
       k.launches += 1;
       k.total_ms += ms;
       k.alg_bytes += kernel_bytes(p, r.name, c);
-      if (!std::strcmp(r.name, "push_small")) k.edges += (double)(c.round_pushed - c.round_pushed_large);
-      if (!std::strcmp(r.name, "push_large")) k.edges += (double)c.round_pushed_large;
+      if (!std::strcmp(r.name, "push_edges")) k.edges += (double)c.round_pushed;
       if (!std::strcmp(r.name, "pull_stream") || !std::strcmp(r.name, "pull_fused") || !std::strcmp(r.name, "tile_pull") ||
           !std::strcmp(r.name, "pull_tile"))
         k.edges += (double)p->g->dev.m;

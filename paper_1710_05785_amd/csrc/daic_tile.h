@@ -41,8 +41,9 @@ struct TileArgs {
   const uint32_t* tile_slot;
   const uint32_t* split_part;
   const uint32_t* split_slot;
-  double* pbuf;               // [n_slots][kTileT] partial sums of the tiles of split partitions
+  double* pbuf;               // [n_slots][tw] partial sums of the tiles of split partitions
   uint64_t m, n_tiles, n_split, n_seg;
+  uint32_t tw;                // partition width (a power of two, 1,024..kTileT)
   double* tpart_r;            // per-workgroup partials of k_tile_pull: |new delta|,
   uint64_t* tpart_a;          //   vertex updates,
   uint64_t* tpart_p;          //   messages
@@ -53,8 +54,15 @@ struct TileArgs {
 
 // FP64 LDS atomics run at about twice the rate of FP32 ones here, so the
 // accumulators are FP64 whatever the state type.
-constexpr uint32_t kTileThreads = 1024;
-constexpr uint32_t kTileWaves = kTileThreads / 64;
+// Workgroup shapes: partitions wider than kNarrowTW take 1024 threads and
+// LDS for kTileT accumulators (one workgroup per CU); narrower ones (graphs
+// below about 2 M vertices) 256 threads and LDS for kNarrowTW accumulators,
+// so several workgroups share a CU and hide each other's latency.
+constexpr uint32_t kNarrowTW = 2048;
+template <uint32_t NT>
+struct TileShape {
+  static constexpr uint32_t threads = NT, waves = NT / 64, cap = NT == 1024 ? kTileT : kNarrowTW;
+};
 constexpr uint32_t kTileU = 16;  // 64-in-edge segments a wave has in flight per step
 
 // Finishes targets [base + i] for i = tid, tid + nthreads, ... < count with new
@@ -112,13 +120,14 @@ __device__ __forceinline__ void tile_finish_targets(const KArgs& a, typename Tr<
   }
 }
 
-template <int ST, int G, bool FUSED>
-__global__ __launch_bounds__(kTileThreads) void k_tile_pull(KArgs a, TileArgs t) {
+template <int ST, int G, bool FUSED, uint32_t NT>
+__global__ __launch_bounds__(NT) void k_tile_pull(KArgs a, TileArgs t) {
   using S = typename Tr<ST>::S;
+  constexpr uint32_t kTileThreads = NT, kTileWaves = TileShape<NT>::waves;
   if constexpr (Tr<ST>::sum) {
     Ctl* ctl = a.ctl;
     if (ctl_halted(ctl) || (!FUSED && !ctl->last_pull)) return;
-    __shared__ double acc[kTileT];
+    __shared__ double acc[TileShape<NT>::cap];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool odd = FUSED && ((ctl->rounds - ctl->fuse_base) & 1) != 0;
     const S* mu_in = static_cast<const S*>(odd ? a.mu_pi2 : a.mu_pi);
@@ -130,7 +139,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pull(KArgs a, TileArgs t)
     uint64_t act = 0, pushed = 0;
     for (uint64_t tile = blockIdx.x; tile < t.n_tiles; tile += gridDim.x) {
       const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
-      for (uint32_t i = tid; i < kTileT; i += kTileThreads) acc[i] = 0.0;
+      for (uint32_t i = tid; i < t.tw; i += kTileThreads) acc[i] = 0.0;
       __syncthreads();
       const uint64_t s0 = e0 >> 6, s1 = (e1 + 63) >> 6;  // 64-in-edge segments overlapping the tile
       for (uint64_t sg = s0 + (uint64_t)wave * kTileU; sg < s1; sg += (uint64_t)kTileWaves * kTileU) {
@@ -165,17 +174,17 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pull(KArgs a, TileArgs t)
         for (uint32_t u = 0; u < kTileU; ++u) {
           double x = (double)mu[u];
           if constexpr (G == DAIC_G_EDGE_SCALE) x *= (double)w[u];
-          if (in[u] && x != 0.0) atomicAdd(&acc[loc[u] & (kTileT - 1)], x);
+          if (in[u] && x != 0.0) atomicAdd(&acc[loc[u] & (TileShape<NT>::cap - 1)], x);  // loc < tw <= cap
         }
       }
       __syncthreads();
-      const uint64_t base = (uint64_t)part * kTileT;
-      const uint32_t count = (uint32_t)min((uint64_t)kTileT, a.n - base);
+      const uint64_t base = (uint64_t)part * t.tw;
+      const uint32_t count = (uint32_t)min((uint64_t)t.tw, a.n - base);
       if (slot == 0xFFFFFFFFu) {
         tile_finish_targets<ST, G, FUSED>(a, mu_out, base, count, tid, kTileThreads,
                                           [&](uint32_t i) { return acc[i]; }, r_part, act, pushed);
       } else {
-        double* dst = t.pbuf + (uint64_t)slot * kTileT;
+        double* dst = t.pbuf + (uint64_t)slot * t.tw;
         for (uint32_t i = tid; i < count; i += kTileThreads) dst[i] = acc[i];
       }
       __syncthreads();
@@ -203,14 +212,14 @@ __global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
     S* mu_out = static_cast<S*>(odd ? a.mu_pi : a.mu_pi2);
     const double* pbuf = t.pbuf;
     const uint32_t tid = threadIdx.x;
-    constexpr uint32_t kChunks = kTileT / 256;
+    const uint32_t kChunks = t.tw / 256;
     double r_part = 0.0;
     uint64_t act = 0, pushed = 0;
     for (uint64_t item = blockIdx.x; item < t.n_split * kChunks; item += gridDim.x) {
       const uint64_t sp = item / kChunks;
       const uint32_t chunk = (uint32_t)(item % kChunks);
       const uint32_t part = t.split_part[sp], k0 = t.split_slot[sp], k1 = t.split_slot[sp + 1];
-      const uint64_t base = (uint64_t)part * kTileT + chunk * 256;
+      const uint64_t base = (uint64_t)part * t.tw + chunk * 256;
       if (base >= a.n) continue;  // uniform
       const uint32_t count = (uint32_t)min((uint64_t)256, a.n - base);
       const uint32_t i = chunk * 256 + min(tid, count - 1);
@@ -218,7 +227,7 @@ __global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
       for (uint32_t k = k0; k < k1; k += 16) {
         double x[16];
 #pragma unroll
-        for (uint32_t u = 0; u < 16; ++u) x[u] = pbuf[(uint64_t)min(k + u, k1 - 1) * kTileT + i];
+        for (uint32_t u = 0; u < 16; ++u) x[u] = pbuf[(uint64_t)min(k + u, k1 - 1) * t.tw + i];
 #pragma unroll
         for (uint32_t u = 0; u < 16; ++u)
           if (k + u < k1) sum += x[u];
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
 template <int ST, bool FUSED>
 __global__ __launch_bounds__(256) void k_tile_total(KArgs a, TileArgs t, uint32_t np, uint32_t nf, uint64_t k_sel,
                                                     uint64_t pull_min) {
-  if constexpr (Tr<ST>::sum) {
+  if constexpr (Tr<ST>::sum || !FUSED) {
     Ctl* ctl = a.ctl;
     if (ctl_halted(ctl) || (!FUSED && !ctl->last_pull)) return;
     double rr = 0.0;
@@ -263,7 +272,7 @@ __global__ __launch_bounds__(256) void k_tile_total(KArgs a, TileArgs t, uint32_
     aa = block_sum256(aa);
     ps = block_sum256(ps);
     if (threadIdx.x == 0) {
-      ctl->r = rr;
+      ctl->r = Tr<ST>::sum ? rr : (double)aa;  // min/max: rr holds the pending vertices' out-edges
       ctl->rounds += 1;
       if constexpr (FUSED) {
         ctl->activations += aa;
@@ -276,11 +285,214 @@ __global__ __launch_bounds__(256) void k_tile_total(KArgs a, TileArgs t, uint32_
       } else {
         const uint64_t nn = aa;  // pending vertices of the new state
         ctl->pending = nn;
-        const bool done = rr <= ctl->eps || nn == 0;
+        const bool done = Tr<ST>::sum ? (rr <= ctl->eps || nn == 0) : nn == 0;
         ctl->done = done ? 1u : 0u;
         ctl->stop = (!done && ctl->rounds >= ctl->max_rounds) ? 1u : 0u;
-        ctl->pull = (k_sel != 0 && (nn < k_sel ? nn : k_sel) >= pull_min) ? 1u : 0u;
+        ctl->pull = next_is_dense<ST>(nn, rr, k_sel, pull_min);
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense rounds of min and max problems (SSSP, connected components): the same
+// walk over the tiled in-edges, with the messages combined by (+) itself.
+// The round's claim has published each sender's message base (its new value
+// when it improved, else the identity); an in-edge's message is g of it
+// (base + weight, saturating, for EDGE_ADD; the base for COPY), combined into
+// an LDS accumulator of its target with an LDS atomic min or max (integer
+// bits; non-negative doubles order like their bit patterns). A target then
+// takes the combined message into dv when it improves both v and dv, which
+// is what the pushes of the same messages would leave (each push is filtered
+// by v and dv), and counts as pending when dv improves v. Min and max are
+// exact, so the result equals the push rounds' bit for bit.
+// ---------------------------------------------------------------------------
+template <int ST>
+struct TileMM;
+template <>
+struct TileMM<ST_U32> {
+  using L = uint32_t;
+  static constexpr L ident = kInfU32;
+  static __device__ __forceinline__ bool better(L a, L b) { return a < b; }
+  static __device__ __forceinline__ void combine(L* p, L x) { atomicMin(p, x); }
+  static __device__ __forceinline__ L enc(uint32_t s) { return s; }
+  static __device__ __forceinline__ uint32_t dec(L x) { return x; }
+};
+template <>
+struct TileMM<ST_F64MIN> {
+  using L = unsigned long long;
+  static constexpr L ident = 0x7FF0000000000000ull;  // +inf
+  static __device__ __forceinline__ bool better(L a, L b) { return a < b; }
+  static __device__ __forceinline__ void combine(L* p, L x) { atomicMin(p, x); }
+  static __device__ __forceinline__ L enc(double s) { return (L)__double_as_longlong(s); }
+  static __device__ __forceinline__ double dec(L x) { return __longlong_as_double((long long)x); }
+};
+template <>
+struct TileMM<ST_I32> {
+  using L = int32_t;
+  static constexpr L ident = -1;
+  static __device__ __forceinline__ bool better(L a, L b) { return a > b; }
+  static __device__ __forceinline__ void combine(L* p, L x) { atomicMax(p, x); }
+  static __device__ __forceinline__ L enc(int32_t s) { return s; }
+  static __device__ __forceinline__ int32_t dec(L x) { return x; }
+};
+
+// The message an in-edge carries from base mu (weight w for EDGE_ADD), as an
+// accumulator value; the identity when the source is silent.
+template <int ST, int G>
+__device__ __forceinline__ typename TileMM<ST>::L tile_mm_msg(typename Tr<ST>::S mu, const void* wt, uint64_t e) {
+  using M = TileMM<ST>;
+  if constexpr (ST == ST_U32) {
+    if (mu == kInfU32) return M::ident;
+    const uint64_t x = (uint64_t)mu + static_cast<const uint32_t*>(wt)[e];
+    return x >= kInfU32 ? M::ident : (uint32_t)x;
+  } else if constexpr (ST == ST_F64MIN) {
+    if (isinf(mu)) return M::ident;
+    return M::enc(mu + static_cast<const double*>(wt)[e]);
+  } else {
+    return mu;  // COPY; -1 (silent) is the identity
+  }
+}
+
+// Takes the combined message x of target t into dv and counts t when
+// pending, with its out-edges (for the next round's direction) in r_part.
+template <int ST>
+__device__ __forceinline__ void tile_mm_finish(const KArgs& a, uint64_t t, typename TileMM<ST>::L x,
+                                               typename Tr<ST>::S vt, typename Tr<ST>::S dvt, double& r_part,
+                                               uint64_t& act) {
+  using M = TileMM<ST>;
+  using S = typename Tr<ST>::S;
+  const typename M::L lv = M::enc(vt), ld = M::enc(dvt);
+  typename M::L nd = ld;
+  if (M::better(x, lv) && M::better(x, ld)) {
+    nd = x;
+    static_cast<S*>(a.dv)[t] = (S)M::dec(x);
+  }
+  const bool pend = M::better(nd, lv);
+  act += pend ? 1 : 0;
+  if (pend) {
+    const uint32_t* row = static_cast<const uint32_t*>(a.row);  // dense rounds need 32-bit offsets
+    r_part += (double)(row[t + 1] - row[t]);
+  }
+}
+
+template <int ST, int G, uint32_t NT>
+__global__ __launch_bounds__(NT) void k_tile_pull_mm(KArgs a, TileArgs t) {
+  constexpr uint32_t kTileThreads = NT, kTileWaves = TileShape<NT>::waves;
+  if constexpr (!Tr<ST>::sum) {
+    using S = typename Tr<ST>::S;
+    using M = TileMM<ST>;
+    using L = typename M::L;
+    Ctl* ctl = a.ctl;
+    if (ctl_halted(ctl) || !ctl->last_pull) return;
+    __shared__ L acc[TileShape<NT>::cap];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const S* mu_in = static_cast<const S*>(a.mu_pi);
+    const S* v = static_cast<const S*>(a.v);
+    const S* dv = static_cast<const S*>(a.dv);
+    const uint64_t upto = (lane == 63 ? ~0ull : ((2ull << lane) - 1)) & ~1ull;
+    double r_part = 0.0;
+    uint64_t act = 0;
+    for (uint64_t tile = blockIdx.x; tile < t.n_tiles; tile += gridDim.x) {
+      const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
+      for (uint32_t i = tid; i < t.tw; i += kTileThreads) acc[i] = M::ident;
+      __syncthreads();
+      const uint64_t s0 = e0 >> 6, s1 = (e1 + 63) >> 6;
+      for (uint64_t sg = s0 + (uint64_t)wave * kTileU; sg < s1; sg += (uint64_t)kTileWaves * kTileU) {
+        uint32_t loc[kTileU], sp[kTileU];
+        uint64_t ec[kTileU];
+        bool in[kTileU];
+#pragma unroll
+        for (uint32_t u = 0; u < kTileU; ++u) {
+          const uint64_t seg = min(sg + u, t.n_seg - 1);
+          const uint64_t e = (sg + u) * 64 + lane;
+          in[u] = sg + u < s1 && e >= e0 && e < e1;
+          ec[u] = min(e, t.m - 1);
+          loc[u] = t.tloc[ec[u]];
+          sp[u] = t.segpair[seg];
+        }
+        uint32_t src[kTileU];
+#pragma unroll
+        for (uint32_t u = 0; u < kTileU; ++u) {
+          const uint64_t e = (sg + u) * 64 + lane;
+          const uint64_t flags = __ballot(e < t.m && (loc[u] & kPairStart) != 0);
+          const uint32_t pr = sp[u] + (uint32_t)__popcll(flags & upto);
+          src[u] = t.psrc[in[u] ? pr : sp[u]];
+        }
+        S mu[kTileU];
+#pragma unroll
+        for (uint32_t u = 0; u < kTileU; ++u) mu[u] = mu_in[src[u]];
+#pragma unroll
+        for (uint32_t u = 0; u < kTileU; ++u) {
+          const L x = tile_mm_msg<ST, G>(mu[u], t.wtile, ec[u]);
+          if (in[u] && x != M::ident) M::combine(&acc[loc[u] & (TileShape<NT>::cap - 1)], x);  // loc < tw <= cap
+        }
+      }
+      __syncthreads();
+      const uint64_t base = (uint64_t)part * t.tw;
+      const uint32_t count = (uint32_t)min((uint64_t)t.tw, a.n - base);
+      if (slot == 0xFFFFFFFFu) {
+        for (uint32_t i = tid; i < count; i += kTileThreads)
+          tile_mm_finish<ST>(a, base + i, acc[i], v[base + i], dv[base + i], r_part, act);
+      } else {
+        L* dst = reinterpret_cast<L*>(t.pbuf) + (uint64_t)slot * t.tw;
+        for (uint32_t i = tid; i < count; i += kTileThreads) dst[i] = acc[i];
+      }
+      __syncthreads();
+    }
+    r_part = block_sum_waves<kTileWaves>(r_part);
+    act = block_sum_waves<kTileWaves>(act);
+    if (tid == 0) {
+      t.tpart_r[blockIdx.x] = r_part;
+      t.tpart_a[blockIdx.x] = act;
+      t.tpart_p[blockIdx.x] = 0;
+    }
+  }
+}
+
+// Targets of split partitions: their slots combined in tile order, then
+// taken into dv as above.
+template <int ST, int G>
+__global__ __launch_bounds__(256) void k_tile_finish_mm(KArgs a, TileArgs t) {
+  if constexpr (!Tr<ST>::sum) {
+    using S = typename Tr<ST>::S;
+    using M = TileMM<ST>;
+    using L = typename M::L;
+    Ctl* ctl = a.ctl;
+    if (ctl_halted(ctl) || !ctl->last_pull) return;
+    const L* pbuf = reinterpret_cast<const L*>(t.pbuf);
+    const S* v = static_cast<const S*>(a.v);
+    const S* dv = static_cast<const S*>(a.dv);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t kChunks = t.tw / 256;
+    double r_part = 0.0;
+    uint64_t act = 0;
+    for (uint64_t item = blockIdx.x; item < t.n_split * kChunks; item += gridDim.x) {
+      const uint64_t sp = item / kChunks;
+      const uint32_t chunk = (uint32_t)(item % kChunks);
+      const uint32_t part = t.split_part[sp], k0 = t.split_slot[sp], k1 = t.split_slot[sp + 1];
+      const uint64_t base = (uint64_t)part * t.tw + chunk * 256;
+      if (base >= a.n) continue;  // uniform
+      const uint32_t count = (uint32_t)min((uint64_t)256, a.n - base);
+      if (tid >= count) continue;
+      const uint32_t i = chunk * 256 + tid;
+      L x = M::ident;
+      for (uint32_t k = k0; k < k1; k += 16) {
+        L y[16];
+#pragma unroll
+        for (uint32_t u = 0; u < 16; ++u) y[u] = pbuf[(uint64_t)min(k + u, k1 - 1) * t.tw + i];
+#pragma unroll
+        for (uint32_t u = 0; u < 16; ++u)
+          if (k + u < k1 && M::better(y[u], x)) x = y[u];
+      }
+      tile_mm_finish<ST>(a, base + tid, x, v[base + tid], dv[base + tid], r_part, act);
+    }
+    r_part = block_sum256(r_part);
+    act = block_sum256(act);
+    if (tid == 0) {
+      t.spart_r[blockIdx.x] = r_part;
+      t.spart_a[blockIdx.x] = act;
+      t.spart_p[blockIdx.x] = 0;
     }
   }
 }

@@ -15,16 +15,16 @@ namespace daic {
 
 namespace {
 
-constexpr uint32_t kLocBits = 14;  // log2(kTileT)
-static_assert((1u << kLocBits) == kTileT, "partition width");
+static_assert(kTileT == 1u << 14, "local target offsets and the pair flag share 16 bits");
 
 uint32_t tgrid(uint64_t count) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((count + 255) / 256, 8192));
 }
 
-// One wave per source row: key = (partition << (sbits + 13)) | (rank << 13) | local target.
+// One wave per source row: key = (partition << (sbits + lb)) | (rank << lb) | local target.
 __global__ __launch_bounds__(256) void k_tile_keys(const uint32_t* row, const uint32_t* col, const uint32_t* perm,
-                                                   uint64_t n, uint32_t sbits, uint64_t* keys, uint32_t* vals) {
+                                                   uint64_t n, uint32_t sbits, uint32_t lb, uint64_t* keys,
+                                                   uint32_t* vals) {
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_tile_keys(const uint32_t* row, const ui
     const uint64_t rank = perm[j];
     for (uint32_t e = row[j] + lane; e < row[j + 1]; e += 64) {
       const uint64_t t = col[e];
-      keys[e] = ((t >> kLocBits) << (sbits + kLocBits)) | (rank << kLocBits) | (t & (kTileT - 1));
+      keys[e] = ((t >> lb) << (sbits + lb)) | (rank << lb) | (t & ((1ull << lb) - 1));
       vals[e] = e;
     }
   }
@@ -40,13 +40,13 @@ __global__ __launch_bounds__(256) void k_tile_keys(const uint32_t* row, const ui
 
 // Pair flags (a new (partition, source) run starts), local targets and edge
 // indices in sorted order.
-__global__ void k_tile_flags(const uint64_t* keys, const uint32_t* vals, uint64_t m, uint32_t* flag, uint16_t* tloc,
-                             uint32_t* eid) {
+__global__ void k_tile_flags(const uint64_t* keys, const uint32_t* vals, uint64_t m, uint32_t lb, uint32_t* flag,
+                             uint16_t* tloc, uint32_t* eid) {
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t k = keys[p];
-    const bool start = p == 0 || (keys[p - 1] >> kLocBits) != (k >> kLocBits);
+    const bool start = p == 0 || (keys[p - 1] >> lb) != (k >> lb);
     flag[p] = start ? 1u : 0u;
-    tloc[p] = (uint16_t)((k & (kTileT - 1)) | (start ? kPairStart : 0));
+    tloc[p] = (uint16_t)((k & ((1ull << lb) - 1)) | (start ? kPairStart : 0));
     eid[p] = vals[p];
   }
 }
@@ -54,12 +54,13 @@ __global__ void k_tile_flags(const uint64_t* keys, const uint32_t* vals, uint64_
 // Pair sources, the pair of each 64-in-edge segment's first in-edge, and the
 // first in-edge of every partition.
 __global__ void k_tile_pairs(const uint64_t* keys, const uint32_t* flag, const uint32_t* incl, uint64_t m,
-                             uint32_t sbits, uint64_t n_part, uint32_t* psrc, uint32_t* segpair, uint32_t* pstart) {
+                             uint32_t sbits, uint32_t lb, uint64_t n_part, uint32_t* psrc, uint32_t* segpair,
+                             uint32_t* pstart) {
   const uint64_t smask = (1ull << sbits) - 1;
-  const uint32_t pshift = sbits + kLocBits;
+  const uint32_t pshift = sbits + lb;
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t k = keys[p];
-    if (flag[p]) psrc[incl[p] - 1] = (uint32_t)((k >> kLocBits) & smask);
+    if (flag[p]) psrc[incl[p] - 1] = (uint32_t)((k >> lb) & smask);
     if ((p & 63) == 0) segpair[p >> 6] = incl[p] - 1;
     const uint64_t part = k >> pshift;
     const uint64_t prev = p == 0 ? 0 : (keys[p - 1] >> pshift) + 1;
@@ -88,8 +89,18 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
   const uint32_t* row = static_cast<const uint32_t*>(d.row);
   uint32_t sbits = 1;
   while ((1ull << sbits) < n) ++sbits;
-  T.n_part = (n + kTileT - 1) / kTileT;
-  const uint32_t pbits_end = sbits + kLocBits + [&] {
+  // partition width: kTileT, narrowed (to at least 1,024) until the graph has
+  // 1,024 partitions, so that small graphs still give every CU tiles
+  uint32_t lb = 14;
+  while (lb > 10 && (n >> lb) < 1024) --lb;
+  T.tbits = lb;
+  const uint64_t TW = 1ull << lb;
+  // in-edges per tile: kTileE, or about two partitions' average for smaller
+  // graphs (at least 16,384), so that hub partitions split into tiles of the
+  // common size
+  const uint64_t ecap = std::max<uint64_t>(16384, std::min<uint64_t>(kTileE, 2 * m / std::max<uint64_t>(1, (n + TW - 1) / TW)));
+  T.n_part = (n + TW - 1) / TW;
+  const uint32_t pbits_end = sbits + lb + [&] {
     uint32_t b = 1;
     while ((1ull << b) < T.n_part + 1) ++b;
     return b;
@@ -124,7 +135,7 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
     TCHK(hipMalloc(&v0, m * sizeof(uint32_t)));
     TCHK(hipMalloc(&v1, m * sizeof(uint32_t)));
     hipLaunchKernelGGL(k_tile_keys, dim3(std::max<uint64_t>(1, std::min<uint64_t>((n + 3) / 4, 8192))), dim3(256), 0,
-                       s, row, d.col, g->pull.perm, n, sbits, k0, v0);
+                       s, row, d.col, g->pull.perm, n, sbits, lb, k0, v0);
     hipcub::DoubleBuffer<uint64_t> kb(k0, k1);
     hipcub::DoubleBuffer<uint32_t> vb(v0, v1);
     size_t need = 0;
@@ -135,8 +146,8 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
     // the buffers not holding the sorted data take the flags and their scan
     flag = kb.Current() == k0 ? reinterpret_cast<uint32_t*>(k1) : reinterpret_cast<uint32_t*>(k0);
     incl = flag + m;  // the other half of the 8-byte-per-edge buffer
-    hipLaunchKernelGGL(k_tile_flags, dim3(tgrid(m)), dim3(256), 0, s, kb.Current(), vb.Current(), m, flag, T.tloc,
-                       T.eid);
+    hipLaunchKernelGGL(k_tile_flags, dim3(tgrid(m)), dim3(256), 0, s, kb.Current(), vb.Current(), m, lb, flag,
+                       T.tloc, T.eid);
     size_t need2 = 0;
     TCHK(hipcub::DeviceScan::InclusiveSum(nullptr, need2, flag, incl, (int)m, s));
     if (need2 > tmp_bytes) {
@@ -157,8 +168,8 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
       TCHK(hipMalloc(&own_pstart, (T.n_part + 1) * sizeof(uint32_t)));
       dpstart = own_pstart;
     }
-    hipLaunchKernelGGL(k_tile_pairs, dim3(tgrid(m)), dim3(256), 0, s, kb.Current(), flag, incl, m, sbits, T.n_part,
-                       T.psrc, T.segpair, dpstart);
+    hipLaunchKernelGGL(k_tile_pairs, dim3(tgrid(m)), dim3(256), 0, s, kb.Current(), flag, incl, m, sbits, lb,
+                       T.n_part, T.psrc, T.segpair, dpstart);
     hipError_t e = hipMemcpyAsync(pstart.data(), dpstart, (T.n_part + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (own_pstart) (void)hipFree(own_pstart);
@@ -171,19 +182,19 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
   v0 = v1 = nullptr;
   tmp = nullptr;
   // tiles: every partition has at least one (its targets are finished by
-  // it); a partition with more than kTileE in-edges gets consecutive slots
+  // it); a partition with more than ecap in-edges gets consecutive slots
   std::vector<uint32_t> tp, te, ts, sp, ss;
   uint32_t slots = 0;
   for (uint64_t p = 0; p < T.n_part; ++p) {
     const uint64_t a = pstart[p], b = pstart[p + 1];
-    const uint64_t nt = std::max<uint64_t>(1, (b - a + kTileE - 1) / kTileE);
+    const uint64_t nt = std::max<uint64_t>(1, (b - a + ecap - 1) / ecap);
     if (nt > 1) {
       sp.push_back((uint32_t)p);
       ss.push_back(slots);
     }
     for (uint64_t k = 0; k < nt; ++k) {
       tp.push_back((uint32_t)p);
-      te.push_back((uint32_t)(a + k * kTileE));
+      te.push_back((uint32_t)(a + k * ecap));
       ts.push_back(nt > 1 ? slots++ : 0xFFFFFFFFu);
     }
   }

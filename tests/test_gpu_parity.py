@@ -171,6 +171,66 @@ def test_fused_dense_rounds_match_plain_rounds(daic, monkeypatch, state, gk, til
         assert abs(rb.stats["final_residual"] - ra.stats["final_residual"]) <= tol * np.abs(va).sum()
 
 
+@pytest.mark.parametrize("kind", ["sssp_u32", "sssp_f64", "cc_i32"])
+@pytest.mark.parametrize("sched,q", [("all", 1.0), ("exact", 0.1), ("sampled", 0.1)])
+def test_minmax_dense_rounds_match_push(daic, monkeypatch, kind, sched, q):
+    """Dense rounds of min and max problems (the tiled pull with LDS atomic
+    min/max) against push-only rounds: the same rounds, vertex updates and
+    messages, and the same state bit for bit (min and max are exact), and the
+    oracle's answer. RMAT-16 has split partitions; the all-pending SSSP run
+    takes several dense rounds in its middle."""
+    say("case minmax dense vs push", kind, sched, q)
+    g = daic_gen.rmat(16, 16, seed=47)
+    if kind == "cc_i32":
+        src = np.repeat(np.arange(g.n), g.outdeg())
+        g = daic_gen.from_edges(g.n, np.concatenate([src, g.col.astype(np.int64)]),
+                                np.concatenate([g.col.astype(np.int64), src]))
+    w = None
+    if kind == "sssp_u32":
+        w = daic_gen.sssp_weights(g.m, seed=48)
+        ref = oracle.dijkstra(g, w, 0)
+    elif kind == "sssp_f64":
+        w = daic_gen.lognormal_f64(49, g.m, 0.0, 1.0)
+        ref = oracle.dijkstra_f64(g, w, 0)
+    else:
+        ref = oracle.maxlabel(g)
+
+    def make():
+        G = daic.Graph(g.row_ptr, g.col, w)
+        if kind == "cc_i32":
+            P = daic.Problem(G, daic.MAX, daic.G_COPY, state="i32")
+            P.set_init(*oracle.cc_init(g.n))
+        else:
+            P = daic.Problem(G, daic.MIN, daic.G_EDGE_ADD, state="u32" if kind == "sssp_u32" else "f64")
+            v0 = np.full(g.n, 0xFFFFFFFF if kind == "sssp_u32" else np.inf)
+            dv1 = v0.copy()
+            dv1[0] = 0
+            P.set_init(v0.astype(np.uint32) if kind == "sssp_u32" else v0, dv1.astype(np.uint32) if kind == "sssp_u32" else dv1)
+        return P
+
+    out = []
+    for push_only in (True, False):
+        if push_only:
+            monkeypatch.setenv("DAIC_NO_PULL", "1")
+        else:
+            monkeypatch.delenv("DAIC_NO_PULL", raising=False)
+        P = make()
+        r = P.run(q=q, sched=sched, rounds_per_check=4)
+        assert r.converged
+        out.append((r, P.get()))
+        if not push_only:
+            rp, ks = make().profile(q=q, sched=sched)
+            names = {k["name"]: k for k in ks}
+            say("  dense rounds", names.get("pull_tile", {}).get("launches", 0), "of", rp.stats["rounds"])
+            if sched == "all":
+                assert names["pull_tile"]["launches"] >= 1
+    (ra, va), (rb, vb) = out
+    for key in ("rounds", "activations", "pushed_edges"):
+        assert rb.stats[key] == ra.stats[key], (key, ra.stats, rb.stats)
+    np.testing.assert_array_equal(vb, va)
+    np.testing.assert_array_equal(vb, ref)
+
+
 @pytest.mark.parametrize("state,gk", [("f32_kahan", "deg"), ("f64", "deg"), ("f32", "edge")])
 def test_tiled_unfused_dense_rounds_match_streamed(daic, monkeypatch, state, gk):
     """Dense rounds that are not fused (the claim folds and publishes, the
