@@ -170,6 +170,14 @@ struct TileGraph {
   uint32_t* split_slot = nullptr;  // [n_split + 1] their first slot (slots of one partition are consecutive)
 };
 daic_status tile_prepare(daic_graph* g, hipStream_t s);
+// The tiled form of g's in-edges with sources numbered by perm (a device
+// array, perm[j] = number of vertex j) and partitions of 2^lb targets
+// (8 <= lb <= 14), tiles of at most max_edges in-edges when nonzero, into T;
+// tile_free releases it.
+daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uint64_t max_edges, TileGraph& T,
+                       hipStream_t s);
+void tile_free(TileGraph& T);
+uint32_t tile_default_bits(uint64_t n);
 void tile_release(daic_graph* g);
 }  // namespace daic
 

@@ -505,6 +505,7 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
       p->allocs.push_back(*q);
       return DAIC_OK;
     };
+    // slots: 8 bytes per entry covers every slot type (min/max accumulators too)
     if ((rc = grab((void**)&p->tile_pbuf, T.n_slots * (1ull << T.tbits) * 8)) ||
         (rc = grab((void**)&p->tpart_r, (uint64_t)p->tile_grid * 8)) ||
         (rc = grab((void**)&p->tpart_a, (uint64_t)p->tile_grid * 8)) ||
@@ -1106,7 +1107,7 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
     const bool sum = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
     const double tw = (double)(1ull << T.tbits);
     const double split_targets = (double)T.n_split * tw;
-    const double slots = (double)T.n_slots * tw * (sum ? 8.0 : S);
+    const double slots = (double)T.n_slots * tw * (sum ? (double)slot_size(p->st) : S);
     const double wb = p->gk == DAIC_G_EDGE_SCALE ? S : p->gk == DAIC_G_EDGE_ADD ? (p->st == ST_U32 ? 4.0 : 8.0) : 0.0;
     const double fin = (sum ? 2.0 : 3.0) * S;
     if (!std::strcmp(name, "pull_tile"))
@@ -1119,8 +1120,9 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
     // partition) pair the source 4 and its base S, per 64 in-edges the
     // segment's pair 4, per tile 12, and the finish of every target of the
     // partitions of one tile as below; the tiles of split partitions store
-    // their partial sums 8 per target. tile_finish: the slots read back 8 per
-    // target and tile, and the finish of those targets. The finish of a
+    // their partial sums (4 per target for FP32 states, 8 for FP64 ones).
+    // tile_finish: the slots read back per target and tile, and the finish of
+    // those targets. The finish of a
     // target: dv read and write 2S, v read and write 2S (+ Kahan term 8),
     // out-edge offsets 2R, renumbering 4, base written S.
     const TileGraph& T = p->g->tile;
@@ -1128,7 +1130,7 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
     const double fin = 2.0 * S + 2.0 * S + kahan + 2.0 * R + 4.0 + S;
     const double tw = (double)(1ull << T.tbits);
     const double split_targets = (double)T.n_split * tw;  // upper bound (the last partition may be short)
-    const double slots = (double)T.n_slots * tw * 8.0;
+    const double slots = (double)T.n_slots * tw * (double)slot_size(p->st);
     if (name[5] == 'p')
       return (double)p->g->dev.m * (2.0 + (p->gk == DAIC_G_EDGE_SCALE ? S : 0.0)) + (double)T.n_pairs * (4.0 + S) +
              (double)T.n_seg * 4.0 + (double)T.n_tiles * 12.0 + std::max(0.0, n - split_targets) * fin + slots;

@@ -76,6 +76,11 @@ struct SweepState {
   uint64_t max_block_verts = 0;
   std::vector<uint32_t> block_sb_off;  // [P+1]: edge blocks of block c
   uint64_t sb_total = 0;           // edge blocks of all blocks
+  // the tiled in-edges with sources in sweep numbers (when B is a multiple of
+  // a partition width of at least 256): block c's tiles and split partitions
+  TileGraph tiles;
+  TileArgs ta{};
+  std::vector<uint32_t> tile_off, split_off;  // [P+1]
   std::vector<void*> allocs;
   SweepArgs a{};
 };
@@ -83,6 +88,7 @@ struct SweepState {
 namespace {
 
 constexpr uint32_t kResGrid = 2048;
+constexpr uint32_t kSweepFinishGrid = 2048;  // workgroups of k_sweep_tile_finish (at most)
 
 // Block c: streamed pull of the block's targets. An in-edge from a source
 // at position s reads the base published in this sweep when s lies in an
@@ -120,11 +126,54 @@ __global__ __launch_bounds__(256) void k_sweep_stream(SweepArgs a, uint32_t c, u
   }
 }
 
+// The claim of vertex j in its block's round: d = its delta with this
+// round's received sum included (dv_old is the delta before the pull). A
+// nonzero delta is folded into v (Kahan for the compensated state) and its
+// message base published into the slot of this sweep (0 when silent; only
+// vertices with out-edges have readers).
+template <int ST, int G>
+__device__ __forceinline__ void sweep_claim_vertex(const SweepArgs& a, uint32_t j, typename Tr<ST>::S d,
+                                                   typename Tr<ST>::S dv_old, uint64_t cur, uint64_t& act,
+                                                   uint64_t& pushed) {
+  using S = typename Tr<ST>::S;
+  S* mu2 = static_cast<S*>(a.mu2);
+  S* v = static_cast<S*>(a.v);
+  S* dv = static_cast<S*>(a.dv);
+  const uint32_t deg = a.row[j + 1] - a.row[j];
+  S mu = (S)0;
+  if (d != (S)0) {
+    dv[j] = (S)0;
+    const S vj = v[j];
+    if constexpr (Tr<ST>::kahan) {
+      // compensated fold (Kahan 1965), as in the round kernels
+#pragma clang fp contract(off)
+      const float cj = a.c[j];
+      const float y = d - cj;
+      const float t = vj + y;
+      a.c[j] = (t - vj) - y;
+      v[j] = t;
+    } else {
+      v[j] = vj + d;
+    }
+    double coef;
+    if constexpr (G == DAIC_G_DEG_SCALE) {
+      coef = deg ? a.alpha / (double)deg : 0.0;
+    } else {
+      coef = a.alpha_pv ? (double)static_cast<const S*>(a.alpha_pv)[j] : a.alpha;
+    }
+    mu = (S)(coef * (double)d);
+    act += 1;
+    pushed += deg;
+  } else if (dv_old != (S)0) {
+    dv[j] = (S)0;  // the received sum cancelled the delta
+  }
+  if (deg) mu2[cur + a.perm[j]] = mu;
+}
+
 // Block c: fold the received sum (dv, filled by k_sweep_stream) into the
 // state and publish the message base. Vertices without in-edges receive
 // nothing, so after their claim of the first sweep and the clearing of both
-// slots (sweeps 1 and 2) they are skipped; vertices without out-edges have
-// no reader and publish nothing.
+// slots (sweeps 1 and 2) they are skipped.
 template <int ST, int G>
 __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
   using S = typename Tr<ST>::S;
@@ -132,9 +181,7 @@ __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
   if (ctl_halted(ctl)) return;
   const uint64_t k = ctl->rounds / a.P;
   const uint64_t cur = (k & 1) * a.n;
-  S* mu2 = static_cast<S*>(a.mu2);
-  S* v = static_cast<S*>(a.v);
-  S* dv = static_cast<S*>(a.dv);
+  const S* dv = static_cast<const S*>(a.dv);
   const bool all = k < 3;
   const uint64_t vb = all ? a.voff[c] : a.roff[c], ve = all ? a.voff[c + 1] : a.roff[c + 1];
   uint64_t act = 0, pushed = 0;
@@ -142,33 +189,7 @@ __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t j = all ? (uint32_t)i : a.rv[i];
     const S d = dv[j];
-    const uint32_t deg = a.row[j + 1] - a.row[j];
-    S mu = (S)0;
-    if (d != (S)0) {
-      dv[j] = (S)0;
-      const S vj = v[j];
-      if constexpr (Tr<ST>::kahan) {
-        // compensated fold (Kahan 1965), as in the round kernels
-#pragma clang fp contract(off)
-        const float cj = a.c[j];
-        const float y = d - cj;
-        const float t = vj + y;
-        a.c[j] = (t - vj) - y;
-        v[j] = t;
-      } else {
-        v[j] = vj + d;
-      }
-      double coef;
-      if constexpr (G == DAIC_G_DEG_SCALE) {
-        coef = deg ? a.alpha / (double)deg : 0.0;
-      } else {
-        coef = a.alpha_pv ? (double)static_cast<const S*>(a.alpha_pv)[j] : a.alpha;
-      }
-      mu = (S)(coef * (double)d);
-      act += 1;
-      pushed += deg;
-    }
-    if (deg) mu2[cur + a.perm[j]] = mu;
+    sweep_claim_vertex<ST, G>(a, j, d, d, cur, act, pushed);
   }
   act = block_sum256(act);
   pushed = block_sum256(pushed);
@@ -178,14 +199,113 @@ __global__ __launch_bounds__(256) void k_sweep_claim(SweepArgs a, uint32_t c) {
   }
 }
 
+// Block c through the tiled in-edges (sources in sweep numbers): tiles
+// [tb, te) of the block's partitions; the message of an in-edge from source
+// s is the base published in this sweep when s < c B, else the previous
+// sweep's (times the weight for EDGE_SCALE), summed per target in FP64 LDS
+// accumulators. A workgroup then claims the targets of an unsplit partition
+// with their sums included (every vertex of the block lies in one partition,
+// so this is the block's claim); the tiles of split partitions store slots,
+// whose targets k_sweep_tile_finish claims. The update counts go to the
+// claim partials (tile workgroups first, then the finishing workgroups).
+template <int ST, int G, uint32_t NT>
+__global__ __launch_bounds__(NT) void k_sweep_tile(SweepArgs a, TileArgs t, uint32_t c, uint32_t tb, uint32_t te) {
+  using S = typename Tr<ST>::S;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  uint64_t act = 0, pushed = 0;
+  __shared__ double acc[TileShape<NT>::cap];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t k = ctl->rounds / a.P;
+  const uint64_t cur = (k & 1) * a.n, prev = ((k + 1) & 1) * a.n, lo = (uint64_t)c * a.B;
+  const S* mu2 = static_cast<const S*>(a.mu2);
+  const S* wt = static_cast<const S*>(t.wtile);
+  const S* dv = static_cast<const S*>(a.dv);
+  auto msg = [&](uint32_t src, uint64_t e) -> double {
+    double x = (double)mu2[(src < lo ? cur : prev) + src];
+    if constexpr (G == DAIC_G_EDGE_SCALE) x *= (double)wt[e];
+    return x;
+  };
+  auto add = [&](uint32_t l, double x) {
+    if (x != 0.0) atomicAdd(&acc[l], x);
+  };
+  for (uint64_t tile = tb + blockIdx.x; tile < te; tile += gridDim.x) {
+    const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
+    for (uint32_t i = tid; i < t.tw; i += NT) acc[i] = 0.0;
+    __syncthreads();
+    tile_walk<NT, double>(t, e0, e1, msg, add);
+    __syncthreads();
+    const uint64_t base = (uint64_t)part * t.tw;
+    const uint32_t count = (uint32_t)min((uint64_t)t.tw, a.n - base);
+    if (slot == 0xFFFFFFFFu) {
+      for (uint32_t i = tid; i < count; i += NT) {
+        const S old = dv[base + i];
+        sweep_claim_vertex<ST, G>(a, (uint32_t)(base + i), (S)((double)old + acc[i]), old, cur, act, pushed);
+      }
+    } else {
+      SlotT<ST>* dst = reinterpret_cast<SlotT<ST>*>(t.pbuf) + (uint64_t)slot * t.tw;
+      for (uint32_t i = tid; i < count; i += NT) dst[i] = (SlotT<ST>)acc[i];
+    }
+    __syncthreads();
+  }
+  act = block_sum_waves<NT / 64>(act);
+  pushed = block_sum_waves<NT / 64>(pushed);
+  if (threadIdx.x == 0) {
+    a.part_a[blockIdx.x] = act;
+    a.part_m[blockIdx.x] = pushed;
+  }
+}
+
+// Targets of block c's split partitions [sb, se): their slots added in tile
+// order (FP64), then claimed with the sum included. Partials at
+// part_a/part_m[poff + workgroup].
+template <int ST, int G>
+__global__ __launch_bounds__(256) void k_sweep_tile_finish(SweepArgs a, TileArgs t, uint32_t sb, uint32_t se,
+                                                           uint32_t poff) {
+  using S = typename Tr<ST>::S;
+  Ctl* ctl = a.ctl;
+  if (ctl_halted(ctl)) return;
+  const S* dv = static_cast<const S*>(a.dv);
+  const SlotT<ST>* pbuf = reinterpret_cast<const SlotT<ST>*>(t.pbuf);
+  const uint64_t cur = ((ctl->rounds / a.P) & 1) * a.n;
+  uint64_t act = 0, pushed = 0;
+  const uint32_t chunks = t.tw / 256;
+  for (uint64_t item = (uint64_t)sb * chunks + blockIdx.x; item < (uint64_t)se * chunks; item += gridDim.x) {
+    const uint64_t sp = item / chunks;
+    const uint32_t chunk = (uint32_t)(item % chunks);
+    const uint32_t part = t.split_part[sp], k0 = t.split_slot[sp], k1 = t.split_slot[sp + 1];
+    const uint64_t base = (uint64_t)part * t.tw + chunk * 256;
+    if (base + threadIdx.x >= a.n) continue;
+    const uint32_t i = chunk * 256 + threadIdx.x;
+    double sum = 0.0;
+    for (uint32_t q = k0; q < k1; q += 16) {
+      double x[16];
+#pragma unroll
+      for (uint32_t u = 0; u < 16; ++u) x[u] = (double)pbuf[(uint64_t)min(q + u, k1 - 1) * t.tw + i];
+#pragma unroll
+      for (uint32_t u = 0; u < 16; ++u)
+        if (q + u < k1) sum += x[u];
+    }
+    const uint32_t j = (uint32_t)(base + threadIdx.x);
+    const S old = dv[j];
+    sweep_claim_vertex<ST, G>(a, j, (S)((double)old + sum), old, cur, act, pushed);
+  }
+  act = block_sum256(act);
+  pushed = block_sum256(pushed);
+  if (threadIdx.x == 0) {
+    a.part_a[poff + blockIdx.x] = act;
+    a.part_m[poff + blockIdx.x] = pushed;
+  }
+}
+
 // After each round: add the claim's per-block counts to the totals; when the
 // round does not end a sweep, count it and apply the round limit (the sweep's
 // last round is counted by k_sweep_residual_final).
-__global__ __launch_bounds__(256) void k_sweep_step(SweepArgs a, int sweep_end) {
+__global__ __launch_bounds__(256) void k_sweep_step(SweepArgs a, int sweep_end, uint32_t nparts) {
   Ctl* ctl = a.ctl;
   if (ctl_halted(ctl)) return;
   uint64_t act = 0, msg = 0;
-  for (uint32_t i = threadIdx.x; i < a.claim_blocks; i += 256) {
+  for (uint32_t i = threadIdx.x; i < nparts; i += 256) {
     act += a.part_a[i];
     msg += a.part_m[i];
   }
@@ -351,13 +471,28 @@ template <int ST, int G>
 struct SweepImpl {
   static void round(const SweepState& w, hipStream_t s, uint32_t c) {
     const SweepArgs& a = w.a;
-    // one workgroup per edge block of block c, at most 16384
-    const uint32_t bb = w.block_sb_off[c], be = w.block_sb_off[c + 1];
-    if (be > bb)
-      hipLaunchKernelGGL((k_sweep_stream<ST, G>), dim3(sgrid(be - bb, 1, 16384)), dim3(256), 0, s, a, c, bb, be);
-    hipLaunchKernelGGL((k_sweep_claim<ST, G>), dim3(a.claim_blocks), dim3(256), 0, s, a, c);
+    uint32_t nparts = a.claim_blocks;
+    if (w.tiles.ready) {  // the block's tiles, then its split partitions, each claiming its targets
+      const uint32_t tb = w.tile_off[c], te = w.tile_off[c + 1], sb = w.split_off[c], se = w.split_off[c + 1];
+      const uint32_t fg = se > sb ? sgrid((uint64_t)(se - sb) * (w.ta.tw / 256), 1, kSweepFinishGrid) : 0;
+      if (te > tb) {
+        if (w.ta.tw > kNarrowTW)
+          hipLaunchKernelGGL((k_sweep_tile<ST, G, 1024>), dim3(te - tb), dim3(1024), 0, s, a, w.ta, c, tb, te);
+        else
+          hipLaunchKernelGGL((k_sweep_tile<ST, G, 256>), dim3(te - tb), dim3(256), 0, s, a, w.ta, c, tb, te);
+      }
+      if (fg)
+        hipLaunchKernelGGL((k_sweep_tile_finish<ST, G>), dim3(fg), dim3(256), 0, s, a, w.ta, sb, se, te - tb);
+      nparts = (te - tb) + fg;
+    } else {
+      // one workgroup per edge block of block c, at most 16384
+      const uint32_t bb = w.block_sb_off[c], be = w.block_sb_off[c + 1];
+      if (be > bb)
+        hipLaunchKernelGGL((k_sweep_stream<ST, G>), dim3(sgrid(be - bb, 1, 16384)), dim3(256), 0, s, a, c, bb, be);
+      hipLaunchKernelGGL((k_sweep_claim<ST, G>), dim3(a.claim_blocks), dim3(256), 0, s, a, c);
+    }
     const bool end = c + 1 == a.P;
-    hipLaunchKernelGGL(k_sweep_step, dim3(1), dim3(256), 0, s, a, end ? 1 : 0);
+    hipLaunchKernelGGL(k_sweep_step, dim3(1), dim3(256), 0, s, a, end ? 1 : 0, nparts);
     if (end) {
       const uint32_t g = sgrid(a.n, 256, kResGrid);
       hipLaunchKernelGGL(k_sweep_residual<ST>, dim3(g), dim3(256), 0, s, a);
@@ -517,6 +652,72 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
                        (const float*)nullptr, a.perm, n, B, cl);
   }
   DAIC_HIP(hipStreamSynchronize(s));
+  // the tiled in-edges in sweep numbers, when the blocks are whole
+  // partitions (B a multiple of a width of at least 2^8); DAIC_NO_TILE=1
+  // keeps the streamed pull
+  uint32_t lb = tile_default_bits(n);
+  if (const char* e = std::getenv("DAIC_SWEEP_TILE_BITS")) lb = (uint32_t)std::min(14ul, std::strtoul(e, nullptr, 10));
+  while (lb >= 8 && B % (1ull << lb) != 0) --lb;
+  if (lb >= 8 && !std::getenv("DAIC_NO_TILE") && d.m > 0) {
+    // tiles of about 3/4 of a block's in-edges per CU, so that a block's
+    // pull keeps every CU busy and its largest tiles do not trail
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    uint64_t max_edges = std::max<uint64_t>(16384, d.m / P * 3 / (4 * (uint64_t)std::max(cus, 1)));
+    if (const char* e = std::getenv("DAIC_SWEEP_TILE_EDGES")) max_edges = std::strtoull(e, nullptr, 10);
+    if ((rc = tile_build(d, a.perm, lb, max_edges, w->tiles, s))) return rc;
+    const TileGraph& T = w->tiles;
+    const uint64_t TW = 1ull << T.tbits;
+    std::vector<uint32_t> tp(T.n_tiles), sp(T.n_split);
+    DAIC_HIP(hipMemcpy(tp.data(), T.tile_part, T.n_tiles * 4, hipMemcpyDeviceToHost));
+    if (T.n_split) DAIC_HIP(hipMemcpy(sp.data(), T.split_part, T.n_split * 4, hipMemcpyDeviceToHost));
+    w->tile_off.assign(P + 1, 0);
+    w->split_off.assign(P + 1, 0);
+    uint32_t max_tiles = 0;
+    for (uint32_t c = 0; c <= P; ++c) {
+      const uint64_t first_part = std::min<uint64_t>((uint64_t)c * B / TW, T.n_part);
+      w->tile_off[c] = (uint32_t)(std::lower_bound(tp.begin(), tp.end(), (uint32_t)first_part) - tp.begin());
+      w->split_off[c] = (uint32_t)(std::lower_bound(sp.begin(), sp.end(), (uint32_t)first_part) - sp.begin());
+      if (c) max_tiles = std::max(max_tiles, w->tile_off[c] - w->tile_off[c - 1]);
+    }
+    // claim partials of a round: its tile workgroups, then its finishing ones
+    if (max_tiles + kSweepFinishGrid > a.claim_blocks) {
+      void *pa = nullptr, *pm = nullptr;
+      if ((rc = grab(&pa, (max_tiles + kSweepFinishGrid) * 8)) || (rc = grab(&pm, (max_tiles + kSweepFinishGrid) * 8)))
+        return rc;
+      a.part_a = static_cast<uint64_t*>(pa);
+      a.part_m = static_cast<uint64_t*>(pm);
+    }
+    TileArgs& t = w->ta;
+    t.tloc = T.tloc;
+    t.psrc = T.psrc;
+    t.segpair = T.segpair;
+    t.tile_part = T.tile_part;
+    t.tile_e = T.tile_e;
+    t.tile_slot = T.tile_slot;
+    t.split_part = T.split_part;
+    t.split_slot = T.split_slot;
+    t.m = d.m;
+    t.n_tiles = T.n_tiles;
+    t.n_split = T.n_split;
+    t.n_seg = T.n_seg;
+    t.tw = (uint32_t)TW;
+    void* pb = nullptr;
+    if ((rc = grab(&pb, std::max<uint64_t>(T.n_slots, 1) * TW * 8))) return rc;
+    t.pbuf = static_cast<double*>(pb);
+    if (p->gk == DAIC_G_EDGE_SCALE) {  // weights in the tiles' in-edge order
+      void* wt = nullptr;
+      if ((rc = grab(&wt, d.m * S))) return rc;
+      if (p->st == ST_F64)
+        hipLaunchKernelGGL(k_gather_weights<double>, dim3(sgrid(d.m)), dim3(256), 0, s,
+                           static_cast<const double*>(p->a.w), T.eid, d.m, static_cast<double*>(wt));
+      else
+        hipLaunchKernelGGL(k_gather_weights<float>, dim3(sgrid(d.m)), dim3(256), 0, s,
+                           static_cast<const float*>(p->a.w), T.eid, d.m, static_cast<float*>(wt));
+      t.wtile = wt;
+    }
+    DAIC_HIP(hipStreamSynchronize(s));
+  }
   return DAIC_OK;
 }
 
@@ -524,6 +725,7 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
 
 void sweep_release(daic_problem* p) {
   if (!p->sweep) return;
+  tile_free(p->sweep->tiles);
   for (void* q : p->sweep->allocs)
     if (q) (void)hipFree(q);
   delete p->sweep;

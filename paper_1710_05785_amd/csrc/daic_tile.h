@@ -41,7 +41,7 @@ struct TileArgs {
   const uint32_t* tile_slot;
   const uint32_t* split_part;
   const uint32_t* split_slot;
-  double* pbuf;               // [n_slots][tw] partial sums of the tiles of split partitions
+  double* pbuf;               // [n_slots][tw] partial sums of the tiles of split partitions (SlotT<ST>)
   uint64_t m, n_tiles, n_split, n_seg;
   uint32_t tw;                // partition width (a power of two, 1,024..kTileT)
   double* tpart_r;            // per-workgroup partials of k_tile_pull: |new delta|,
@@ -120,6 +120,59 @@ __device__ __forceinline__ void tile_finish_targets(const KArgs& a, typename Tr<
   }
 }
 
+// Type of the partial-sum slots of split partitions: FP32 for FP32 states
+// (whose messages are FP32; each slot holds an FP64 sum rounded once),
+// FP64 otherwise. The slots are added in FP64.
+template <int ST>
+using SlotT = typename std::conditional<ST == ST_F32 || ST == ST_F32K, float, double>::type;
+inline uint32_t slot_size(int st) { return st == ST_F32 || st == ST_F32K ? 4u : 8u; }
+
+// Walks the in-edges [e0, e1) of one tile, kTileU segments of 64 in-edges
+// per wave and step (every wave of the workgroup calls it): a lane loads its
+// in-edge's local target; a ballot of the pair-start bits and a popcount give
+// its pair (the segment's first pair plus the starts among the lanes before
+// it), whose source indexes the message load msg(source, in-edge), issued for
+// all kTileU segments before any is combined; add(local target, message)
+// then runs for the in-edges inside the tile. Local targets are below the
+// partition width, so masking the flag bit leaves an index below kTileT.
+template <uint32_t NT, typename V, typename Msg, typename Add>
+__device__ __forceinline__ void tile_walk(const TileArgs& t, uint32_t e0, uint32_t e1, const Msg& msg,
+                                          const Add& add) {
+  constexpr uint32_t kWaves = NT / 64;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // flags of segment positions 1..lane (position 0 belongs to the segment's pair)
+  const uint64_t upto = (lane == 63 ? ~0ull : ((2ull << lane) - 1)) & ~1ull;
+  const uint64_t s0 = e0 >> 6, s1 = (e1 + 63) >> 6;  // 64-in-edge segments overlapping the tile
+  for (uint64_t sg = s0 + (uint64_t)wave * kTileU; sg < s1; sg += (uint64_t)kWaves * kTileU) {
+    uint32_t loc[kTileU], sp[kTileU];
+    uint64_t ec[kTileU];
+    bool in[kTileU];
+#pragma unroll
+    for (uint32_t u = 0; u < kTileU; ++u) {
+      const uint64_t seg = min(sg + u, t.n_seg - 1);
+      const uint64_t e = (sg + u) * 64 + lane;
+      in[u] = sg + u < s1 && e >= e0 && e < e1;
+      ec[u] = min(e, t.m - 1);
+      loc[u] = t.tloc[ec[u]];
+      sp[u] = t.segpair[seg];  // the same for the whole wave
+    }
+    uint32_t src[kTileU];
+#pragma unroll
+    for (uint32_t u = 0; u < kTileU; ++u) {
+      const uint64_t e = (sg + u) * 64 + lane;
+      const uint64_t flags = __ballot(e < t.m && (loc[u] & kPairStart) != 0);
+      const uint32_t pr = sp[u] + (uint32_t)__popcll(flags & upto);
+      src[u] = t.psrc[in[u] ? pr : sp[u]];
+    }
+    V x[kTileU];
+#pragma unroll
+    for (uint32_t u = 0; u < kTileU; ++u) x[u] = msg(src[u], ec[u]);
+#pragma unroll
+    for (uint32_t u = 0; u < kTileU; ++u)
+      if (in[u]) add(loc[u] & (kTileT - 1), x[u]);
+  }
+}
+
 template <int ST, int G, bool FUSED, uint32_t NT>
 __global__ __launch_bounds__(NT) void k_tile_pull(KArgs a, TileArgs t) {
   using S = typename Tr<ST>::S;
@@ -128,55 +181,26 @@ __global__ __launch_bounds__(NT) void k_tile_pull(KArgs a, TileArgs t) {
     Ctl* ctl = a.ctl;
     if (ctl_halted(ctl) || (!FUSED && !ctl->last_pull)) return;
     __shared__ double acc[TileShape<NT>::cap];
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t tid = threadIdx.x;
     const bool odd = FUSED && ((ctl->rounds - ctl->fuse_base) & 1) != 0;
     const S* mu_in = static_cast<const S*>(odd ? a.mu_pi2 : a.mu_pi);
     S* mu_out = static_cast<S*>(odd ? a.mu_pi : a.mu_pi2);
     const S* wt = static_cast<const S*>(t.wtile);
-    // flags of segment positions 1..lane (position 0 belongs to the segment's pair)
-    const uint64_t upto = (lane == 63 ? ~0ull : ((2ull << lane) - 1)) & ~1ull;
     double r_part = 0.0;
     uint64_t act = 0, pushed = 0;
+    auto msg = [&](uint32_t src, uint64_t e) -> double {
+      double x = (double)mu_in[src];
+      if constexpr (G == DAIC_G_EDGE_SCALE) x *= (double)wt[e];
+      return x;
+    };
+    auto add = [&](uint32_t l, double x) {
+      if (x != 0.0) atomicAdd(&acc[l], x);
+    };
     for (uint64_t tile = blockIdx.x; tile < t.n_tiles; tile += gridDim.x) {
       const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
       for (uint32_t i = tid; i < t.tw; i += kTileThreads) acc[i] = 0.0;
       __syncthreads();
-      const uint64_t s0 = e0 >> 6, s1 = (e1 + 63) >> 6;  // 64-in-edge segments overlapping the tile
-      for (uint64_t sg = s0 + (uint64_t)wave * kTileU; sg < s1; sg += (uint64_t)kTileWaves * kTileU) {
-        uint32_t loc[kTileU], sp[kTileU];
-        uint64_t ec[kTileU];
-        bool in[kTileU];
-#pragma unroll
-        for (uint32_t u = 0; u < kTileU; ++u) {
-          const uint64_t seg = min(sg + u, t.n_seg - 1);
-          const uint64_t e = (sg + u) * 64 + lane;
-          in[u] = sg + u < s1 && e >= e0 && e < e1;
-          ec[u] = min(e, t.m - 1);
-          loc[u] = t.tloc[ec[u]];
-          sp[u] = t.segpair[seg];  // the same for the whole wave
-        }
-        uint32_t src[kTileU];
-#pragma unroll
-        for (uint32_t u = 0; u < kTileU; ++u) {
-          const uint64_t e = (sg + u) * 64 + lane;
-          const uint64_t flags = __ballot(e < t.m && (loc[u] & kPairStart) != 0);
-          const uint32_t pr = sp[u] + (uint32_t)__popcll(flags & upto);
-          src[u] = t.psrc[in[u] ? pr : sp[u]];
-        }
-        S mu[kTileU];
-        S w[kTileU];
-#pragma unroll
-        for (uint32_t u = 0; u < kTileU; ++u) {
-          mu[u] = mu_in[src[u]];
-          if constexpr (G == DAIC_G_EDGE_SCALE) w[u] = wt[ec[u]];
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < kTileU; ++u) {
-          double x = (double)mu[u];
-          if constexpr (G == DAIC_G_EDGE_SCALE) x *= (double)w[u];
-          if (in[u] && x != 0.0) atomicAdd(&acc[loc[u] & (TileShape<NT>::cap - 1)], x);  // loc < tw <= cap
-        }
-      }
+      tile_walk<NT, double>(t, e0, e1, msg, add);
       __syncthreads();
       const uint64_t base = (uint64_t)part * t.tw;
       const uint32_t count = (uint32_t)min((uint64_t)t.tw, a.n - base);
@@ -184,8 +208,8 @@ __global__ __launch_bounds__(NT) void k_tile_pull(KArgs a, TileArgs t) {
         tile_finish_targets<ST, G, FUSED>(a, mu_out, base, count, tid, kTileThreads,
                                           [&](uint32_t i) { return acc[i]; }, r_part, act, pushed);
       } else {
-        double* dst = t.pbuf + (uint64_t)slot * t.tw;
-        for (uint32_t i = tid; i < count; i += kTileThreads) dst[i] = acc[i];
+        SlotT<ST>* dst = reinterpret_cast<SlotT<ST>*>(t.pbuf) + (uint64_t)slot * t.tw;
+        for (uint32_t i = tid; i < count; i += kTileThreads) dst[i] = (SlotT<ST>)acc[i];
       }
       __syncthreads();
     }
@@ -210,7 +234,7 @@ __global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
     if (ctl_halted(ctl) || (!FUSED && !ctl->last_pull)) return;
     const bool odd = FUSED && ((ctl->rounds - ctl->fuse_base) & 1) != 0;
     S* mu_out = static_cast<S*>(odd ? a.mu_pi : a.mu_pi2);
-    const double* pbuf = t.pbuf;
+    const SlotT<ST>* pbuf = reinterpret_cast<const SlotT<ST>*>(t.pbuf);
     const uint32_t tid = threadIdx.x;
     const uint32_t kChunks = t.tw / 256;
     double r_part = 0.0;
@@ -227,7 +251,7 @@ __global__ __launch_bounds__(256) void k_tile_finish(KArgs a, TileArgs t) {
       for (uint32_t k = k0; k < k1; k += 16) {
         double x[16];
 #pragma unroll
-        for (uint32_t u = 0; u < 16; ++u) x[u] = pbuf[(uint64_t)min(k + u, k1 - 1) * t.tw + i];
+        for (uint32_t u = 0; u < 16; ++u) x[u] = (double)pbuf[(uint64_t)min(k + u, k1 - 1) * t.tw + i];
 #pragma unroll
         for (uint32_t u = 0; u < 16; ++u)
           if (k + u < k1) sum += x[u];
@@ -386,48 +410,21 @@ __global__ __launch_bounds__(NT) void k_tile_pull_mm(KArgs a, TileArgs t) {
     Ctl* ctl = a.ctl;
     if (ctl_halted(ctl) || !ctl->last_pull) return;
     __shared__ L acc[TileShape<NT>::cap];
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t tid = threadIdx.x;
     const S* mu_in = static_cast<const S*>(a.mu_pi);
     const S* v = static_cast<const S*>(a.v);
     const S* dv = static_cast<const S*>(a.dv);
-    const uint64_t upto = (lane == 63 ? ~0ull : ((2ull << lane) - 1)) & ~1ull;
     double r_part = 0.0;
     uint64_t act = 0;
+    auto msg = [&](uint32_t src, uint64_t e) -> L { return tile_mm_msg<ST, G>(mu_in[src], t.wtile, e); };
+    auto add = [&](uint32_t l, L x) {
+      if (x != M::ident) M::combine(&acc[l], x);
+    };
     for (uint64_t tile = blockIdx.x; tile < t.n_tiles; tile += gridDim.x) {
       const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
       for (uint32_t i = tid; i < t.tw; i += kTileThreads) acc[i] = M::ident;
       __syncthreads();
-      const uint64_t s0 = e0 >> 6, s1 = (e1 + 63) >> 6;
-      for (uint64_t sg = s0 + (uint64_t)wave * kTileU; sg < s1; sg += (uint64_t)kTileWaves * kTileU) {
-        uint32_t loc[kTileU], sp[kTileU];
-        uint64_t ec[kTileU];
-        bool in[kTileU];
-#pragma unroll
-        for (uint32_t u = 0; u < kTileU; ++u) {
-          const uint64_t seg = min(sg + u, t.n_seg - 1);
-          const uint64_t e = (sg + u) * 64 + lane;
-          in[u] = sg + u < s1 && e >= e0 && e < e1;
-          ec[u] = min(e, t.m - 1);
-          loc[u] = t.tloc[ec[u]];
-          sp[u] = t.segpair[seg];
-        }
-        uint32_t src[kTileU];
-#pragma unroll
-        for (uint32_t u = 0; u < kTileU; ++u) {
-          const uint64_t e = (sg + u) * 64 + lane;
-          const uint64_t flags = __ballot(e < t.m && (loc[u] & kPairStart) != 0);
-          const uint32_t pr = sp[u] + (uint32_t)__popcll(flags & upto);
-          src[u] = t.psrc[in[u] ? pr : sp[u]];
-        }
-        S mu[kTileU];
-#pragma unroll
-        for (uint32_t u = 0; u < kTileU; ++u) mu[u] = mu_in[src[u]];
-#pragma unroll
-        for (uint32_t u = 0; u < kTileU; ++u) {
-          const L x = tile_mm_msg<ST, G>(mu[u], t.wtile, ec[u]);
-          if (in[u] && x != M::ident) M::combine(&acc[loc[u] & (TileShape<NT>::cap - 1)], x);  // loc < tw <= cap
-        }
-      }
+      tile_walk<NT, L>(t, e0, e1, msg, add);
       __syncthreads();
       const uint64_t base = (uint64_t)part * t.tw;
       const uint32_t count = (uint32_t)min((uint64_t)t.tw, a.n - base);

@@ -72,33 +72,44 @@ __global__ void k_tile_pairs(const uint64_t* keys, const uint32_t* flag, const u
 
 }  // namespace
 
-void tile_release(daic_graph* g) {
-  TileGraph& t = g->tile;
+void tile_free(TileGraph& t) {
   for (void* q : {(void*)t.tloc, (void*)t.psrc, (void*)t.segpair, (void*)t.eid, (void*)t.tile_part, (void*)t.tile_e,
                   (void*)t.tile_slot, (void*)t.split_part, (void*)t.split_slot})
     if (q) (void)hipFree(q);
   t = TileGraph();
 }
 
+void tile_release(daic_graph* g) { tile_free(g->tile); }
+
+uint32_t tile_default_bits(uint64_t n) {
+  // kTileT, narrowed (to at least 1,024) until the graph has 1,024
+  // partitions, so that small graphs still give every CU tiles
+  uint32_t lb = 14;
+  while (lb > 10 && (n >> lb) < 1024) --lb;
+  return lb;
+}
+
 daic_status tile_prepare(daic_graph* g, hipStream_t s) {
-  TileGraph& T = g->tile;
-  if (T.ready) return DAIC_OK;
+  if (g->tile.ready) return DAIC_OK;
   if (!g->pull.ready) return fail(DAIC_E_INVALID, "tiled rounds need the renumbering of the in-edge form");
-  const GraphDev& d = g->dev;
+  return tile_build(g->dev, g->pull.perm, tile_default_bits(g->dev.n), 0, g->tile, s);
+}
+
+daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uint64_t max_edges, TileGraph& T,
+                       hipStream_t s) {
+  if (T.ready) return DAIC_OK;
+  if (lb < 8 || lb > 14) return fail(DAIC_E_INVALID, "partition width 2^%u outside 2^8..2^14", lb);
   const uint64_t n = d.n, m = d.m;
   const uint32_t* row = static_cast<const uint32_t*>(d.row);
   uint32_t sbits = 1;
   while ((1ull << sbits) < n) ++sbits;
-  // partition width: kTileT, narrowed (to at least 1,024) until the graph has
-  // 1,024 partitions, so that small graphs still give every CU tiles
-  uint32_t lb = 14;
-  while (lb > 10 && (n >> lb) < 1024) --lb;
   T.tbits = lb;
   const uint64_t TW = 1ull << lb;
   // in-edges per tile: kTileE, or about two partitions' average for smaller
   // graphs (at least 16,384), so that hub partitions split into tiles of the
   // common size
-  const uint64_t ecap = std::max<uint64_t>(16384, std::min<uint64_t>(kTileE, 2 * m / std::max<uint64_t>(1, (n + TW - 1) / TW)));
+  uint64_t ecap = std::max<uint64_t>(16384, std::min<uint64_t>(kTileE, 2 * m / std::max<uint64_t>(1, (n + TW - 1) / TW)));
+  if (max_edges) ecap = std::max<uint64_t>(1024, std::min<uint64_t>(ecap, max_edges));
   T.n_part = (n + TW - 1) / TW;
   const uint32_t pbits_end = sbits + lb + [&] {
     uint32_t b = 1;
@@ -118,7 +129,7 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
     hipError_t _e = (call);                                                                      \
     if (_e != hipSuccess) {                                                                      \
       cleanup();                                                                                 \
-      tile_release(g);                                                                           \
+      tile_free(T);                                                                              \
       return fail(_e == hipErrorOutOfMemory ? DAIC_E_OOM : DAIC_E_DEVICE, "tiled-round set-up: %s: %s", #call, \
                   hipGetErrorString(_e));                                                        \
     }                                                                                            \
@@ -135,7 +146,7 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
     TCHK(hipMalloc(&v0, m * sizeof(uint32_t)));
     TCHK(hipMalloc(&v1, m * sizeof(uint32_t)));
     hipLaunchKernelGGL(k_tile_keys, dim3(std::max<uint64_t>(1, std::min<uint64_t>((n + 3) / 4, 8192))), dim3(256), 0,
-                       s, row, d.col, g->pull.perm, n, sbits, lb, k0, v0);
+                       s, row, d.col, perm, n, sbits, lb, k0, v0);
     hipcub::DoubleBuffer<uint64_t> kb(k0, k1);
     hipcub::DoubleBuffer<uint32_t> vb(v0, v1);
     size_t need = 0;

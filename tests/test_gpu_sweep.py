@@ -249,11 +249,13 @@ def test_sweep_rejects_min_problems(daic):
         p.run(q=0.5, sched="sweep")
 
 
-@pytest.mark.parametrize("q", [1.0, 0.3, 0.05])
+@pytest.mark.parametrize("q", [1.0, 0.3, 0.25, 0.0625, 0.05])
 def test_sweep_trajectory_matches_block_oracle(daic, q):
     """Round by round, the GPU state (messages in flight delivered) equals the
     oracle's block-sequential DAIC with the same blocks: checks the order of
-    updates and that every message is delivered exactly once."""
+    updates and that every message is delivered exactly once. Blocks of 4,096,
+    1,024 and 256 ids are whole partitions of the tiled in-edges (pulled
+    through the tiles), the others take the streamed pull."""
     say("case sweep trajectory", q)
     g = daic_gen.rmat(12, 16, seed=71)
     d = 0.8
@@ -269,15 +271,17 @@ def test_sweep_trajectory_matches_block_oracle(daic, q):
         np.testing.assert_allclose(dv, dvo, rtol=1e-11, atol=1e-13)
 
 
-def test_sweep_trajectory_edge_scale(daic):
-    say("case sweep trajectory edge scale")
+@pytest.mark.parametrize("B", [300, 512])
+def test_sweep_trajectory_edge_scale(daic, B):
+    """As above with per-source coefficients and edge weights; 512-id blocks
+    take the tiled pull (weights in the tiles' in-edge order)."""
+    say("case sweep trajectory edge scale", B)
     g = daic_gen.rmat(11, 8, seed=72)
     w = daic_gen.lognormal_f64(73, g.m, 0.4, 0.8)
     deg = g.outdeg()
     rs = np.bincount(np.repeat(np.arange(g.n), deg), weights=w, minlength=g.n)
     a = 0.85 / np.where(deg > 0, rs, 1.0)
     c = daic_gen.lognormal_f64(74, g.n, 0.0, 1.0)
-    B = 300
     for rounds in (3, 8, 21):
         p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.SUM, daic.G_EDGE_SCALE, alpha_pv=a, state="f64")
         p.set_init(np.zeros(g.n), c)
@@ -286,3 +290,31 @@ def test_sweep_trajectory_edge_scale(daic):
         vo, dvo = oracle.sweep_blocks(g, oracle.G_EDGE_SCALE, 0.0, np.zeros(g.n), c, B, rounds, w=w, alpha_pv=a)
         np.testing.assert_allclose(v, vo, rtol=1e-11, atol=1e-13)
         np.testing.assert_allclose(dv, dvo, rtol=1e-11, atol=1e-13)
+
+
+@pytest.mark.parametrize("state", ["f32_kahan", "f64"])
+def test_sweep_tiled_matches_streamed(daic, monkeypatch, state):
+    """The tiled pull of sweep blocks (RMAT-16, 8 blocks of 8,192 ids) against
+    the streamed pull: the same rounds, vertex updates and messages, states
+    equal to rounding, and both within the tolerance of the oracle."""
+    say("case sweep tiled vs streamed", state)
+    g = daic_gen.rmat(16, 16, seed=75)
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.8, np.full(g.n, 0.2), eps=1e-13)
+    eps = 1e-10 if state == "f64" else 1e-6
+    out = []
+    for tiled in (False, True):
+        if tiled:
+            monkeypatch.delenv("DAIC_NO_TILE", raising=False)
+        else:
+            monkeypatch.setenv("DAIC_NO_TILE", "1")
+        p = pr_problem(daic, g, state=state)
+        r = p.run(eps=eps, q=0.125, sched="sweep", rounds_per_check=8)
+        assert r.converged
+        out.append((r, p.get()))
+    (ra, va), (rb, vb) = out
+    for key in ("rounds", "activations", "pushed_edges"):
+        assert rb.stats[key] == ra.stats[key], (key, ra.stats, rb.stats)
+    tol = 1e-12 if state == "f64" else 2e-6
+    assert np.abs(vb - va).sum() <= tol * np.abs(va).sum()
+    bound = 1e-9 if state == "f64" else 1e-5 * ref.sum()
+    assert np.abs(vb - ref).sum() <= bound
