@@ -23,10 +23,10 @@ Contents
 * ``sampled_threshold`` / ``topk_exact`` -- the two selection rules of a round.
 * ``mlp_*``          -- FP64 forward/backward of the scheduler network.
 * ``adam_step``      -- one Adam update (Kingma and Ba 2015) in FP64.
-* ``trace_exact_topk`` -- rounds of exact top-k scheduling on an integer
-  (min or max) problem with the learned scheduler's training samples: the
-  features of sampled vertices and the label "not pending again within H
-  rounds" (numpy).
+* ``trace_exact_topk`` -- rounds of exact top-k scheduling with the learned
+  scheduler's training samples: the features of sampled vertices and the
+  label "not pending again within H rounds" (integer min/max problems) or
+  "priority not back to half within H rounds" (sum problems, FP64) (numpy).
 
 Parity status: every function here is pinned by tests under ``tests/`` except
 the ones listed as "parity unpinned" in their docstrings.
@@ -430,12 +430,15 @@ def _prio_f32(op, v, dv):
 
 
 def trace_exact_topk(g, op, v0, dv1, q, samples_per_round, horizon, seed, w=None,
-                     max_rounds=4096):
-    """Rounds of exact top-k priority scheduling on an integer problem (op =
-    OP_MIN with g(x) = x + w_jk saturating at 0xFFFFFFFF, uint32 state; or
-    OP_MAX with g(x) = x, int32 state), recording the learned scheduler's
-    training samples. Sec. 3.5 (priority scheduling), Eq. async (update);
-    the trace rule itself is not in the paper.
+                     max_rounds=4096, gk=G_DEG_SCALE, alpha=0.0, alpha_pv=None, eps=0.0):
+    """Rounds of exact top-k priority scheduling, recording the learned
+    scheduler's training samples: on an integer problem (op = OP_MIN with
+    g(x) = x + w_jk saturating at 0xFFFFFFFF, uint32 state; or OP_MAX with
+    g(x) = x, int32 state) or on a sum problem in FP64 (op = OP_SUM with g of
+    kind gk: DEG_SCALE alpha x / outdeg_j, SRC_SCALE a_j x, EDGE_SCALE
+    a_j w_jk x, a_j = alpha_pv[j] or alpha; the run also stops when the
+    residual sum |dv| is at most eps). Sec. 3.5 (priority scheduling), Eq.
+    async (update); the trace rule itself is not in the paper.
 
     Round t (t = 0, 1, ...) runs while some vertex is pending and t <
     max_rounds:
@@ -456,6 +459,10 @@ def trace_exact_topk(g, op, v0, dv1, q, samples_per_round, horizon, seed, w=None
     every later start), else 1. Labels are given for every sampled round when
     the run ends with nothing pending, otherwise for rounds t < T - horizon.
 
+    For sum problems the label is 0 when, at the start of one of the next
+    `horizon` rounds (the final state standing for later starts), the
+    vertex's priority in FP32 reaches half its FP32 priority when sampled.
+
     Returns dict(x [N,3] float32, y [N] float32, vid, round, value (the value
     the update stored in v), rounds T, v, dv)."""
     n = g.n
@@ -472,20 +479,28 @@ def trace_exact_topk(g, op, v0, dv1, q, samples_per_round, horizon, seed, w=None
         v = np.array(v0, dtype=np.int32, copy=True)
         dv = np.array(dv1, dtype=np.int32, copy=True)
     else:
-        raise ValueError("trace_exact_topk takes the integer problems (min, max)")
+        v = np.array(v0, dtype=np.float64, copy=True)
+        dv = np.array(dv1, dtype=np.float64, copy=True)
+        a = np.full(n, float(alpha)) if alpha_pv is None else np.asarray(alpha_pv, dtype=np.float64)
+        if gk == G_DEG_SCALE:
+            a = float(alpha) / np.maximum(outdeg, 1).astype(np.float64)
+        wf = np.asarray(w, dtype=np.float64) if gk == G_EDGE_SCALE else None
     last = np.full(n, -1, dtype=np.int64)           # round of the last update, -1 = none
     k = int(np.ceil(q * n))
     f1 = np.log2((np.float32(1) + indeg.astype(np.float32)) /
                  (np.float32(1) + outdeg.astype(np.float32))).astype(np.float32)
     rec = []                                        # per round: vid, feat, p0, sel, value
     pend_hist = []                                  # pending mask at the start of each round
+    pf_hist = []                                    # FP32 priorities at the start of each round (sum)
     t = 0
     while t < max_rounds:
         p = priority(op, v, dv)
         pending = p > 0
-        if not pending.any():
+        if not pending.any() or (op == OP_SUM and p.sum() <= eps):
             break
         pend_hist.append(pending.copy())
+        if op == OP_SUM:
+            pf_hist.append(np.where(pending, _prio_f32(op, v, dv), np.float32(0)))
         # 1. samples and their features
         c = np.uint64(t) * np.uint64(S) + np.arange(S, dtype=np.uint64)
         vid = (splitmix64(seed ^ TRACE_SEED_XOR, c) % np.uint64(n)).astype(np.int64)
@@ -497,18 +512,26 @@ def trace_exact_topk(g, op, v0, dv1, q, samples_per_round, horizon, seed, w=None
         # 2. the round: select, claim, send
         sel = topk_exact(p, q) if pending.sum() > k else np.flatnonzero(pending)
         delta = dv[sel].copy()
-        if op == OP_MIN:
+        if op == OP_SUM:
+            dv[sel] = 0.0
+            v[sel] += delta
+            improves = delta != 0.0
+        elif op == OP_MIN:
             dv[sel] = INF_U32
             improves = delta < v[sel]
+            v[sel[improves]] = delta[improves]
         else:
             dv[sel] = -1
             improves = delta > v[sel]
-        v[sel[improves]] = delta[improves]
+            v[sel[improves]] = delta[improves]
         last[sel] = t
         senders = sel[improves]
         for j, d in zip(senders, delta[improves]):
             e0, e1 = rp[j], rp[j + 1]
-            if op == OP_MIN:
+            if op == OP_SUM:
+                m = a[j] * d * (wf[e0:e1] if wf is not None else np.ones(e1 - e0))
+                np.add.at(dv, col[e0:e1], m)
+            elif op == OP_MIN:
                 if int(d) == INF_U32:
                     continue
                 msg = np.minimum(np.uint64(d) + wu[e0:e1], np.uint64(INF_U32)).astype(np.uint32)
@@ -517,21 +540,29 @@ def trace_exact_topk(g, op, v0, dv1, q, samples_per_round, horizon, seed, w=None
                 np.maximum.at(dv, col[e0:e1], np.int32(d))
         chosen = np.zeros(n, dtype=bool)
         chosen[sel] = True
-        rec.append((vid, feat, pending[vid], chosen[vid], v[vid].copy()))
+        rec.append((vid, feat, pending[vid], chosen[vid], v[vid].copy(), pf))
         t += 1
     T = t
-    final_pending = priority(op, v, dv) > 0
-    done = not final_pending.any()
+    pfin = priority(op, v, dv)
+    final_pending = pfin > 0
+    final_pf = np.where(final_pending, _prio_f32(op, v, dv), np.float32(0)) if op == OP_SUM else None
+    done = not final_pending.any() or (op == OP_SUM and pfin.sum() <= eps)
     full = T if done else max(T - H, 0)
     xs, ys, vids, rounds, vals = [], [], [], [], []
     for r in range(full):
-        vid, feat, p0, chosen, val = rec[r]
+        vid, feat, p0, chosen, val, pf0 = rec[r]
         for i in range(S):
             if not (p0[i] and chosen[i]):
                 continue
             j = vid[i]
             again = False
             for s in range(r + 1, r + H + 1):
+                if op == OP_SUM:
+                    later = pf_hist[s][j] if s < T else final_pf[j]
+                    if later >= np.float32(0.5) * pf0[i]:
+                        again = True
+                        break
+                    continue
                 mask = pend_hist[s] if s < T else final_pending
                 if mask[j]:
                     again = True

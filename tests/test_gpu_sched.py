@@ -414,6 +414,49 @@ def test_trace_matches_oracle(daic, kind, scale, q, S, H):
     np.testing.assert_array_equal(p.get(), want["v"])
 
 
+@pytest.mark.parametrize("gk,q,H", [("deg", 0.1, 4), ("edge", 0.2, 2)])
+def test_trace_sum_problem_matches_oracle(daic, gk, q, H):
+    """The sum-problem trace (FP64 state; label 0 when the vertex's FP32
+    priority reaches half its sampled priority within H round starts)
+    against the oracle's FP64 exact top-k rounds: the same samples and
+    rounds, features within a few FP32 units, labels equal except where the
+    later priority lies within 1e-6 (relative) of the half threshold, and
+    the state after the run within rounding of the oracle's. Random initial
+    deltas keep the exact top-k free of ties."""
+    say("case sum trace parity", gk, q, H)
+    g = daic_gen.rmat(11, 8, seed=90)
+    rng = np.random.default_rng(91)
+    dv1 = rng.uniform(0.1, 1.0, g.n)
+    seed, S = 33, 700
+    if gk == "deg":
+        p = daic.Problem(daic.Graph(g.row_ptr, g.col), daic.SUM, daic.G_DEG_SCALE, alpha=0.8, state="f64")
+        want = oracle.trace_exact_topk(g, oracle.OP_SUM, np.zeros(g.n), dv1, q, S, H, seed,
+                                       gk=oracle.G_DEG_SCALE, alpha=0.8, eps=1e-9)
+    else:
+        deg = g.outdeg()
+        w = daic_gen.lognormal_f64(92, g.m, 0.4, 0.8)
+        rs = np.bincount(np.repeat(np.arange(g.n), deg), weights=w, minlength=g.n)
+        a = 0.85 / np.where(deg > 0, rs, 1.0)
+        p = daic.Problem(daic.Graph(g.row_ptr, g.col, w), daic.SUM, daic.G_EDGE_SCALE, alpha_pv=a, state="f64")
+        want = oracle.trace_exact_topk(g, oracle.OP_SUM, np.zeros(g.n), dv1, q, S, H, seed, w=w,
+                                       gk=oracle.G_EDGE_SCALE, alpha_pv=a, eps=1e-9)
+    p.set_init(np.zeros(g.n), dv1)
+    tr = daic.Trace.record(p, samples_per_round=S, horizon=H, q=q, seed=seed, eps=1e-9)
+    x, y = tr.get()
+    vid, rnd = tr.samples()
+    say("rounds", want["rounds"], "samples", len(y), "positive", float(y.mean()) if len(y) else 0)
+    assert len(y) == len(want["y"]) > 100
+    np.testing.assert_array_equal(rnd, want["round"])
+    np.testing.assert_array_equal(vid, want["vid"])
+    np.testing.assert_allclose(x, want["x"], rtol=1e-5, atol=1e-5)
+    mism = np.flatnonzero(y != want["y"])
+    say("label mismatches", len(mism))
+    assert len(mism) <= max(1, len(y) // 1000)
+    assert 0.0 < y.mean() < 1.0
+    v = p.get()
+    assert np.abs(v - want["v"]).sum() <= 1e-12 * np.abs(want["v"]).sum()
+
+
 def test_sched_step_matches_oracle_adam(daic):
     """Two training steps (gradient on the MFMA kernels, then Adam) against
     the oracle: each applied gradient element-wise against the oracle

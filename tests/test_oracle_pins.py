@@ -663,10 +663,10 @@ def test_golden_adam_steps():
 # Trace rule of the learned scheduler (exact top-k rounds, integer problems)
 # ---------------------------------------------------------------------------
 
-def _golden_trace():
+def _golden_trace(name="trace_sssp_4node.txt"):
     gd = {}
     ups = []
-    with open(os.path.join(GOLDEN, "trace_sssp_4node.txt")) as f:
+    with open(os.path.join(GOLDEN, name)) as f:
         for line in f:
             line = line.split("#", 1)[0].strip()
             if not line:
@@ -708,6 +708,53 @@ def test_golden_trace_sssp_4node(H):
                                    atol=1e-7)
         assert r["y"][i] == float(u[5] if H == 4 else u[6])
         assert r["value"][i] == int(u[7])
+
+
+@pytest.mark.parametrize("H", [1, 2])
+def test_golden_trace_pagerank_2cycle(H):
+    """The sum-problem trace rule against the hand-worked 2-vertex run: the
+    state after 4 rounds, and features, labels and stored values of every
+    sampled update (labels only for rounds before T - H)."""
+    gd, ups = _golden_trace("trace_pr_2cycle.txt")
+    n = int(gd["n"][0])
+    e = list(map(int, gd["edges"]))
+    g = daic_gen.from_edges(n, e[0::2], e[1::2])
+    dv1 = np.array(list(map(float, gd["dv1"])))
+    S, seed = 16, 5
+    r = oracle.trace_exact_topk(g, oracle.OP_SUM, np.zeros(n), dv1, float(gd["q"][0]), S, H, seed,
+                                max_rounds=int(gd["rounds"][0]), gk=oracle.G_DEG_SCALE,
+                                alpha=float(gd["d"][0]))
+    assert r["rounds"] == int(gd["rounds"][0])
+    np.testing.assert_allclose(r["v"], list(map(float, gd["v"])), rtol=1e-14)
+    np.testing.assert_allclose(r["dv"], list(map(float, gd["dv"])), rtol=1e-14, atol=1e-15)
+    col = 5 if H == 1 else 6
+    want = {(int(u[0]), int(u[1])): u for u in ups if u[col] != "-"}
+    expect_count = 0
+    for t in range(r["rounds"] - H):
+        ids = oracle.sample_indices(n, S, seed ^ oracle.TRACE_SEED_XOR, t)
+        expect_count += sum(1 for j in ids if (t, int(j)) in want)
+    assert expect_count > 0
+    assert len(r["y"]) == expect_count
+    for i in range(len(r["y"])):
+        u = want[(int(r["round"][i]), int(r["vid"][i]))]
+        np.testing.assert_allclose(r["x"][i], np.array(u[2:5], dtype=np.float64), rtol=1e-6, atol=1e-6)
+        assert r["y"][i] == float(u[col])
+        assert abs(r["value"][i] - float(u[7])) <= 1e-14
+
+
+def test_trace_sum_rounds_reach_the_dense_solve():
+    """The sum branch of the trace's exact top-k rounds, run to a tiny
+    residual, reaches the fixed point of the dense solve (Theorem 1): a wrong
+    claim (delta not cleared, not folded) or message (coefficient, target)
+    breaks it."""
+    g = random_graph(120, 700, 4)
+    d = 0.8
+    want = dense_pagerank(g, d)
+    r = oracle.trace_exact_topk(g, oracle.OP_SUM, np.zeros(g.n), np.full(g.n, 1 - d), 0.1, 32, 3, 9,
+                                gk=oracle.G_DEG_SCALE, alpha=d, eps=1e-13)
+    assert np.abs(r["dv"]).sum() <= 1e-13
+    assert np.abs(r["v"] - want).sum() <= 1e-11 * g.n
+    assert 0.0 < r["y"].mean() < 1.0
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
