@@ -55,6 +55,18 @@ def host_info():
     return {"nproc": os.cpu_count(), "cpu": model}
 
 
+def printable(obj):
+    """obj without the result vectors the forms carry for the oracle
+    comparison (keys starting with an underscore, numpy arrays)."""
+    import numpy as np
+
+    if isinstance(obj, dict):
+        return {k: printable(v) for k, v in obj.items() if not str(k).startswith("_") and not isinstance(v, np.ndarray)}
+    if isinstance(obj, list):
+        return [printable(v) for v in obj]
+    return obj
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("daic_kernels.h", "daic_device.h", "daic_tile.h", "daic_runtime.hip", "daic_pull.hip", "daic_tile.hip"):
@@ -329,7 +341,7 @@ def priority_form(torch, P, v0, dv1, eps, rounds_per_check, q=0.1):
 
 
 def sssp_form(daic, torch, rounds_per_check):
-    """The single-source shortest-path workload (push rounds, integer min):
+    """The single-source shortest-path workload (push and dense rounds, integer min):
     RMAT-20, edge factor 16 (seed 2), weights U{1..255} (seed 3), source 0,
     sampled top-10 % and all-pending scheduling, each warmed up and timed; the
     per-kernel profile of the sampled run with the push kernels' algorithmic
@@ -630,11 +642,11 @@ def main():
         print(json.dumps({"ablation": ablation(daic, torch), "host": host_info()}), flush=True)
         return
     if args.form == "batched":
-        print(json.dumps({"batched_ppr_64x64": batched_form(daic, torch, args.eps, args.rounds_per_check)}),
+        print(json.dumps(printable({"batched_ppr_64x64": batched_form(daic, torch, args.eps, args.rounds_per_check)})),
               flush=True)
         return
     if args.form == "sssp":
-        print(json.dumps({"sssp_rmat20": sssp_form(daic, torch, args.rounds_per_check)}), flush=True)
+        print(json.dumps(printable({"sssp_rmat20": sssp_form(daic, torch, args.rounds_per_check)})), flush=True)
         return
     d = 0.8
     t = time.perf_counter()
@@ -642,20 +654,18 @@ def main():
     log(f"generated RMAT-{args.scale} n={g.n} m={g.m} in {time.perf_counter() - t:.1f}s")
     if args.form == "learned":
         lf = learned_form(daic, torch, g, args.eps, args.rounds_per_check)
-        lf["pagerank_rmat24"].pop("_v")
-        print(json.dumps({"learned_sched": lf}), flush=True)
+        print(json.dumps(printable({"learned_sched": lf})), flush=True)
         return
     if args.form == "sweep":
         sw = sweep_form(daic, torch, g, d, args.eps, args.rounds_per_check)
-        sw.pop("_v")
-        print(json.dumps({"sweep_8_blocks": sw}), flush=True)
+        print(json.dumps(printable({"sweep_8_blocks": sw})), flush=True)
         return
     G = daic.Graph(g.row_ptr, g.col)
     P = daic.Problem(G, daic.SUM, daic.G_DEG_SCALE, alpha=d, state="f32_kahan")
     v0 = torch.zeros(g.n, dtype=torch.float32, device="cuda")
     dv1 = torch.full((g.n,), 1.0 - d, dtype=torch.float32, device="cuda")
     if args.form == "priority":
-        print(json.dumps(priority_form(torch, P, v0, dv1, args.eps, args.rounds_per_check)), flush=True)
+        print(json.dumps(printable(priority_form(torch, P, v0, dv1, args.eps, args.rounds_per_check))), flush=True)
         return
     run_kw = dict(eps=args.eps, q=1.0, sched="all", rounds_per_check=args.rounds_per_check)
 
