@@ -233,7 +233,7 @@ __global__ __launch_bounds__(NT) void k_sweep_tile(SweepArgs a, TileArgs t, uint
     const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
     for (uint32_t i = tid; i < t.tw; i += NT) acc[i] = 0.0;
     __syncthreads();
-    tile_walk<NT, double>(t, e0, e1, msg, add);
+    tile_walk<NT, G != DAIC_G_EDGE_SCALE, double>(t, e0, e1, msg, add);
     __syncthreads();
     const uint64_t base = (uint64_t)part * t.tw;
     const uint32_t count = (uint32_t)min((uint64_t)t.tw, a.n - base);
