@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "daic_device.h"
 #include "daic_internal.h"
 
 namespace daic {
@@ -30,20 +31,19 @@ __global__ void k_perm_from_sorted(const uint64_t* sorted, uint64_t n, uint32_t*
   for (uint64_t r = i; r < n; r += st) perm[(uint32_t)sorted[r]] = (uint32_t)r;
 }
 
-// One wave per source row (lanes stride its out-edges, so hub rows do not
-// serialize on one thread): key = (target << 32) | perm[source], value = edge.
-__global__ __launch_bounds__(256) void k_edge_keys(const uint32_t* row, const uint32_t* col, const uint32_t* perm,
-                                                   uint64_t n, uint64_t* keys, uint32_t* vals) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t j = wave; j < n; j += nwaves) {
-    const uint64_t pj = perm[j];
-    for (uint32_t e = row[j] + lane; e < row[j + 1]; e += 64) {
-      keys[e] = ((uint64_t)col[e] << 32) | pj;
-      vals[e] = e;
-    }
-  }
+// key = (target << 32) | perm[source], value = edge, for every edge (rows
+// walked by lane groups, hub rows by whole waves).
+__global__ __launch_bounds__(256) void k_edge_keys(const uint32_t* __restrict__ row, const uint32_t* __restrict__ col,
+                                                   const uint32_t* __restrict__ perm, uint64_t n,
+                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  rows_by_groups<false>(
+      row, n, [&](uint64_t, uint32_t e) { return col[e]; },
+      [&](uint64_t j, uint32_t e, uint32_t t) {
+        keys[e] = ((uint64_t)t << 32) | perm[j];
+        vals[e] = e;
+        return 0.0;
+      },
+      [](uint64_t, double) {});
 }
 
 // srcT from the sorted keys, and the in-edge offsets: rowT[t] = first position

@@ -11,6 +11,7 @@
 #include <limits>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "daic_internal.h"
@@ -59,6 +60,28 @@ static Partition make_partition(uint64_t n) {
   p.per_block = per;
   p.blocks = (uint32_t)((n + per - 1) / per);
   return p;
+}
+
+// The first index i < count with bad(i) (count when none), the range split
+// over the host's threads (the checks of a large host CSR take a fraction of
+// a second on one core).
+template <typename Bad>
+static uint64_t first_index_where(uint64_t count, const Bad& bad) {
+  const uint64_t nt = count < (1u << 20) ? 1 : std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  std::vector<uint64_t> first(nt, count);
+  auto scan = [&](uint64_t t) {
+    const uint64_t lo = count * t / nt, hi = count * (t + 1) / nt;
+    for (uint64_t i = lo; i < hi; ++i)
+      if (bad(i)) {
+        first[t] = i;
+        return;
+      }
+  };
+  std::vector<std::thread> pool;
+  for (uint64_t t = 1; t < nt; ++t) pool.emplace_back(scan, t);
+  scan(0);
+  for (auto& th : pool) th.join();
+  return *std::min_element(first.begin(), first.end());
 }
 
 template <typename T>
@@ -572,10 +595,10 @@ daic_status daic_graph_create(uint64_t n, uint64_t m, const uint64_t* row_ptr, c
   if (m > 0 && !col) return fail(DAIC_E_INVALID, "col is null");
   if (n >= 0xFFFFFFFFull) return fail(DAIC_E_INVALID, "n must be below 2^32-1");
   if (row_ptr[0] != 0 || row_ptr[n] != m) return fail(DAIC_E_INVALID, "row_ptr[0] must be 0 and row_ptr[n] must be m");
-  for (uint64_t j = 0; j < n; ++j)
-    if (row_ptr[j + 1] < row_ptr[j]) return fail(DAIC_E_INVALID, "row_ptr not monotone at %llu", (unsigned long long)j);
-  for (uint64_t e = 0; e < m; ++e)
-    if (col[e] >= n) return fail(DAIC_E_INVALID, "col[%llu] = %u out of range", (unsigned long long)e, col[e]);
+  const uint64_t bad_row = first_index_where(n, [&](uint64_t j) { return row_ptr[j + 1] < row_ptr[j]; });
+  if (bad_row < n) return fail(DAIC_E_INVALID, "row_ptr not monotone at %llu", (unsigned long long)bad_row);
+  const uint64_t bad_col = first_index_where(m, [&](uint64_t e) { return col[e] >= n; });
+  if (bad_col < m) return fail(DAIC_E_INVALID, "col[%llu] = %u out of range", (unsigned long long)bad_col, col[bad_col]);
   size_t wsz = 0;
   if (w) {
     if (w_type == DAIC_F64) wsz = 8;

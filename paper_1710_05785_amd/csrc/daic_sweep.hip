@@ -427,22 +427,19 @@ __global__ __launch_bounds__(256) void k_sweep_deliver_stream(SweepArgs a, uint6
 }
 
 // coef_le[perm[j]] = sum over out-edges (j, t) with block(t) <= block(j) of
-// |w_jt| (1 per edge when unweighted); one wave per source vertex.
+// |w_jt| (1 per edge when unweighted); rows walked by lane groups.
 template <typename S, bool W>
-__global__ __launch_bounds__(256) void k_sweep_coef(const uint32_t* row, const uint32_t* col, const S* w,
-                                                    const uint32_t* perm, uint64_t n, uint64_t B, double* coef_le) {
-  const uint32_t lane = lane_id();
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t j = wave; j < n; j += nwaves) {
-    const uint64_t bj = perm[j] / B;
-    double acc = 0.0;
-    for (uint32_t e = row[j] + lane; e < row[j + 1]; e += 64) {
-      if ((uint64_t)perm[col[e]] / B <= bj) acc += W ? fabs((double)w[e]) : 1.0;
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) coef_le[perm[j]] = acc;
-  }
+__global__ __launch_bounds__(256) void k_sweep_coef(const uint32_t* __restrict__ row, const uint32_t* __restrict__ col,
+                                                    const S* __restrict__ w, const uint32_t* __restrict__ perm,
+                                                    uint64_t n, uint64_t B, double* __restrict__ coef_le) {
+  struct Edge {
+    uint32_t rank;  // perm of the edge's target
+    double weight;
+  };
+  rows_by_groups<true>(
+      row, n, [&](uint64_t, uint32_t e) { return Edge{perm[col[e]], W ? fabs((double)w[e]) : 1.0}; },
+      [&](uint64_t j, uint32_t, const Edge& x) { return (uint64_t)x.rank / B <= (uint64_t)perm[j] / B ? x.weight : 0.0; },
+      [&](uint64_t j, double acc) { coef_le[perm[j]] = acc; });
 }
 
 // srcT_sweep[p] = psw[inv[srcT[p]]]: from dense-round numbers to sweep numbers.

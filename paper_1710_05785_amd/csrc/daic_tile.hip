@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "daic_device.h"
 #include "daic_internal.h"
 
 namespace daic {
@@ -21,21 +22,21 @@ uint32_t tgrid(uint64_t count) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((count + 255) / 256, 8192));
 }
 
-// One wave per source row: key = (partition << (sbits + lb)) | (rank << lb) | local target.
-__global__ __launch_bounds__(256) void k_tile_keys(const uint32_t* row, const uint32_t* col, const uint32_t* perm,
-                                                   uint64_t n, uint32_t sbits, uint32_t lb, uint64_t* keys,
-                                                   uint32_t* vals) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t j = wave; j < n; j += nwaves) {
-    const uint64_t rank = perm[j];
-    for (uint32_t e = row[j] + lane; e < row[j + 1]; e += 64) {
-      const uint64_t t = col[e];
-      keys[e] = ((t >> lb) << (sbits + lb)) | (rank << lb) | (t & ((1ull << lb) - 1));
-      vals[e] = e;
-    }
-  }
+// key = (partition << (sbits + lb)) | (rank << lb) | local target, value =
+// the edge, for every edge (rows walked by lane groups).
+__global__ __launch_bounds__(256) void k_tile_keys(const uint32_t* __restrict__ row, const uint32_t* __restrict__ col,
+                                                   const uint32_t* __restrict__ perm, uint64_t n, uint32_t sbits,
+                                                   uint32_t lb, uint64_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals) {
+  rows_by_groups<false>(
+      row, n, [&](uint64_t, uint32_t e) { return col[e]; },
+      [&](uint64_t j, uint32_t e, uint64_t t) {
+        const uint64_t rank = perm[j];
+        keys[e] = ((t >> lb) << (sbits + lb)) | (rank << lb) | (t & ((1ull << lb) - 1));
+        vals[e] = e;
+        return 0.0;
+      },
+      [](uint64_t, double) {});
 }
 
 // Pair flags (a new (partition, source) run starts), local targets and edge
