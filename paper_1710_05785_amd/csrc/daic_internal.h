@@ -155,13 +155,18 @@ namespace daic {
 constexpr uint32_t kTileT = 16384;     // most targets per partition (local ids fit 14 bits)
 constexpr uint32_t kTileE = 196608;    // in-edges per tile
 constexpr uint16_t kPairStart = 0x8000;  // flag of a pair's first in-edge in tloc
+// Segments of padding after the tiled per-in-edge arrays (tloc, segpair and
+// weights in tile order): zero local targets with no pair start, segment
+// pair 0 and weight 0, so a walk's whole step of segments loads in bounds
+// with 32-bit unclamped indices.
+constexpr uint32_t kTilePadSeg = 32;
 struct TileGraph {
   bool ready = false;
   uint32_t tbits = 14;             // partition width 2^tbits (at most kTileT; smaller graphs get narrower ones)
   uint64_t n_part = 0, n_tiles = 0, n_pairs = 0, n_split = 0, n_slots = 0, n_seg = 0;
-  uint16_t* tloc = nullptr;        // [m] target - partition base, | kPairStart at a pair's first in-edge
+  uint16_t* tloc = nullptr;        // [m, padded] target - partition base, | kPairStart at a pair's first in-edge
   uint32_t* psrc = nullptr;        // [n_pairs] renumbered source of each pair
-  uint32_t* segpair = nullptr;     // [n_seg] pair of the first in-edge of each 64-in-edge segment
+  uint32_t* segpair = nullptr;     // [n_seg, padded] pair of the first in-edge of each 64-in-edge segment
   uint32_t* eid = nullptr;         // [m] original edge index (weights in tile order)
   uint32_t* tile_part = nullptr;   // [n_tiles] partition of each tile
   uint32_t* tile_e = nullptr;      // [n_tiles + 1] first in-edge of each tile (tiles are contiguous)
@@ -170,6 +175,11 @@ struct TileGraph {
   uint32_t* split_slot = nullptr;  // [n_split + 1] their first slot (slots of one partition are consecutive)
 };
 daic_status tile_prepare(daic_graph* g, hipStream_t s);
+// Entries of the per-in-edge arrays in tile order with their padding.
+inline uint64_t tile_padded_edges(const TileGraph& T) { return (T.n_seg + kTilePadSeg) * 64; }
+// The tiled kernels index in-edges (with the padding) in 32 bits; larger
+// graphs keep the streamed (sum) or push-only (min/max) rounds.
+inline bool tile_fits(uint64_t m) { return m + 64ull * (kTilePadSeg + 1) <= 0xFFFFFFFFull; }
 // The tiled form of g's in-edges with sources numbered by perm (a device
 // array, perm[j] = number of vertex j) and partitions of 2^lb targets
 // (8 <= lb <= 14), tiles of at most max_edges in-edges when nonzero, into T;

@@ -1628,12 +1628,13 @@ __global__ __launch_bounds__(256) void k_fused_finish(KArgs a, uint32_t nf) {
 // Start of fused dense rounds: the bases just published went to buffer A.
 static __global__ void k_fuse_begin(Ctl* ctl) { ctl->fuse_base = ctl->rounds; }
 
-// Weights in in-edge order: wT[p] = w[eidT[p]].
+// Weights in in-edge order: wT[p] = w[eidT[p]] for p < m, 0 up to total
+// (the padding of the tiled arrays).
 template <typename S>
-__global__ void k_gather_weights(const S* w, const uint32_t* eidT, uint64_t m, S* wT) {
+__global__ void k_gather_weights(const S* w, const uint32_t* eidT, uint64_t m, uint64_t total, S* wT) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t st = (uint64_t)gridDim.x * blockDim.x;
-  for (; i < m; i += st) wT[i] = w[eidT[i]];
+  for (; i < total; i += st) wT[i] = i < m ? w[eidT[i]] : (S)0;
 }
 
 // ---------------------------------------------------------------------------

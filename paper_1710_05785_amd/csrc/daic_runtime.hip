@@ -444,8 +444,8 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
   const bool sum = p->st == ST_F64 || p->st == ST_F32 || p->st == ST_F32K;
   const GraphDev& d = p->g->dev;
   // min and max problems take dense rounds through the tiled in-edges only
-  if ((!sum && std::getenv("DAIC_NO_TILE")) || std::getenv("DAIC_NO_PULL") || !d.row32 || d.m > 0x7FFFFFFFull ||
-      d.n > 0x7FFFFFFFull)
+  if ((!sum && (std::getenv("DAIC_NO_TILE") || !tile_fits(d.m))) || std::getenv("DAIC_NO_PULL") || !d.row32 ||
+      d.m > 0x7FFFFFFFull || d.n > 0x7FFFFFFFull)
     return DAIC_OK;
   if (!p->pull_ready) {
     daic_graph* g = const_cast<daic_graph*>(p->g);
@@ -464,10 +464,10 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
       p->allocs.push_back(wt);
       if (p->st == ST_F64)
         hipLaunchKernelGGL(k_gather_weights<double>, dim3(grid_for(d.m)), dim3(256), 0, s,
-                           static_cast<const double*>(a.w), g->pull.eidT, d.m, static_cast<double*>(wt));
+                           static_cast<const double*>(a.w), g->pull.eidT, d.m, d.m, static_cast<double*>(wt));
       else
         hipLaunchKernelGGL(k_gather_weights<float>, dim3(grid_for(d.m)), dim3(256), 0, s,
-                           static_cast<const float*>(a.w), g->pull.eidT, d.m, static_cast<float*>(wt));
+                           static_cast<const float*>(a.w), g->pull.eidT, d.m, d.m, static_cast<float*>(wt));
       a.wT = wt;
     }
     a.perm = g->pull.perm;
@@ -518,7 +518,7 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
   }
   // the tiled in-edge form of dense rounds (fused and not); DAIC_NO_TILE=1
   // keeps the streamed form
-  if (!p->tile_ready && !std::getenv("DAIC_NO_TILE")) {
+  if (!p->tile_ready && !std::getenv("DAIC_NO_TILE") && tile_fits(d.m)) {
     daic_graph* g = const_cast<daic_graph*>(p->g);
     daic_status rc = tile_prepare(g, s);
     if (rc) return rc;
@@ -537,26 +537,27 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
         (rc = grab((void**)&p->spart_a, (uint64_t)p->tfin_grid * 8)) ||
         (rc = grab((void**)&p->spart_p, (uint64_t)p->tfin_grid * 8)))
       return rc;
+    const uint64_t pe = tile_padded_edges(T);
     if (p->gk == DAIC_G_EDGE_ADD) {  // weights in tile order: uint32 (U32 state) or double
       if (p->st == ST_U32) {
-        if ((rc = grab(&p->tile_w, d.m * 4))) return rc;
-        hipLaunchKernelGGL(k_gather_weights<uint32_t>, dim3(grid_for(d.m)), dim3(256), 0, s,
-                           static_cast<const uint32_t*>(p->a.w), T.eid, d.m, static_cast<uint32_t*>(p->tile_w));
+        if ((rc = grab(&p->tile_w, pe * 4))) return rc;
+        hipLaunchKernelGGL(k_gather_weights<uint32_t>, dim3(grid_for(pe)), dim3(256), 0, s,
+                           static_cast<const uint32_t*>(p->a.w), T.eid, d.m, pe, static_cast<uint32_t*>(p->tile_w));
       } else {
-        if ((rc = grab(&p->tile_w, d.m * 8))) return rc;
-        hipLaunchKernelGGL(k_gather_weights<double>, dim3(grid_for(d.m)), dim3(256), 0, s,
-                           static_cast<const double*>(p->a.w), T.eid, d.m, static_cast<double*>(p->tile_w));
+        if ((rc = grab(&p->tile_w, pe * 8))) return rc;
+        hipLaunchKernelGGL(k_gather_weights<double>, dim3(grid_for(pe)), dim3(256), 0, s,
+                           static_cast<const double*>(p->a.w), T.eid, d.m, pe, static_cast<double*>(p->tile_w));
       }
     }
     if (p->gk == DAIC_G_EDGE_SCALE) {
       const size_t S = state_size(p->st);
-      if ((rc = grab(&p->tile_w, d.m * S))) return rc;
+      if ((rc = grab(&p->tile_w, pe * S))) return rc;
       if (p->st == ST_F64)
-        hipLaunchKernelGGL(k_gather_weights<double>, dim3(grid_for(d.m)), dim3(256), 0, s,
-                           static_cast<const double*>(p->a.w), T.eid, d.m, static_cast<double*>(p->tile_w));
+        hipLaunchKernelGGL(k_gather_weights<double>, dim3(grid_for(pe)), dim3(256), 0, s,
+                           static_cast<const double*>(p->a.w), T.eid, d.m, pe, static_cast<double*>(p->tile_w));
       else
-        hipLaunchKernelGGL(k_gather_weights<float>, dim3(grid_for(d.m)), dim3(256), 0, s,
-                           static_cast<const float*>(p->a.w), T.eid, d.m, static_cast<float*>(p->tile_w));
+        hipLaunchKernelGGL(k_gather_weights<float>, dim3(grid_for(pe)), dim3(256), 0, s,
+                           static_cast<const float*>(p->a.w), T.eid, d.m, pe, static_cast<float*>(p->tile_w));
     }
     DAIC_HIP(hipStreamSynchronize(s));
     p->tile_ready = true;

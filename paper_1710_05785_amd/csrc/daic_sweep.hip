@@ -221,14 +221,12 @@ __global__ __launch_bounds__(NT) void k_sweep_tile(SweepArgs a, TileArgs t, uint
   const S* mu2 = static_cast<const S*>(a.mu2);
   const S* wt = static_cast<const S*>(t.wtile);
   const S* dv = static_cast<const S*>(a.dv);
-  auto msg = [&](uint32_t src, uint64_t e) -> double {
+  auto msg = [&](uint32_t src, uint32_t e) -> double {
     double x = (double)mu2[(src < lo ? cur : prev) + src];
     if constexpr (G == DAIC_G_EDGE_SCALE) x *= (double)wt[e];
     return x;
   };
-  auto add = [&](uint32_t l, double x) {
-    if (x != 0.0) atomicAdd(&acc[l], x);
-  };
+  auto add = [&](uint32_t l, double x) { atomicAdd(&acc[l], x); };  // adding 0 leaves a sum as it is
   for (uint64_t tile = tb + blockIdx.x; tile < te; tile += gridDim.x) {
     const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
     for (uint32_t i = tid; i < t.tw; i += NT) acc[i] = 0.0;
@@ -655,7 +653,7 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
   uint32_t lb = tile_default_bits(n);
   if (const char* e = std::getenv("DAIC_SWEEP_TILE_BITS")) lb = (uint32_t)std::min(14ul, std::strtoul(e, nullptr, 10));
   while (lb >= 8 && B % (1ull << lb) != 0) --lb;
-  if (lb >= 8 && !std::getenv("DAIC_NO_TILE") && d.m > 0) {
+  if (lb >= 8 && !std::getenv("DAIC_NO_TILE") && d.m > 0 && tile_fits(d.m)) {
     // tiles of about 3/4 of a block's in-edges per CU, so that a block's
     // pull keeps every CU busy and its largest tiles do not trail
     int dev = 0, cus = 256;
@@ -704,13 +702,14 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
     t.pbuf = static_cast<double*>(pb);
     if (p->gk == DAIC_G_EDGE_SCALE) {  // weights in the tiles' in-edge order
       void* wt = nullptr;
-      if ((rc = grab(&wt, d.m * S))) return rc;
+      const uint64_t pe = tile_padded_edges(T);
+      if ((rc = grab(&wt, pe * S))) return rc;
       if (p->st == ST_F64)
-        hipLaunchKernelGGL(k_gather_weights<double>, dim3(sgrid(d.m)), dim3(256), 0, s,
-                           static_cast<const double*>(p->a.w), T.eid, d.m, static_cast<double*>(wt));
+        hipLaunchKernelGGL(k_gather_weights<double>, dim3(sgrid(pe)), dim3(256), 0, s,
+                           static_cast<const double*>(p->a.w), T.eid, d.m, pe, static_cast<double*>(wt));
       else
-        hipLaunchKernelGGL(k_gather_weights<float>, dim3(sgrid(d.m)), dim3(256), 0, s,
-                           static_cast<const float*>(p->a.w), T.eid, d.m, static_cast<float*>(wt));
+        hipLaunchKernelGGL(k_gather_weights<float>, dim3(sgrid(pe)), dim3(256), 0, s,
+                           static_cast<const float*>(p->a.w), T.eid, d.m, pe, static_cast<float*>(wt));
       t.wtile = wt;
     }
     DAIC_HIP(hipStreamSynchronize(s));

@@ -135,65 +135,65 @@ inline uint32_t slot_size(int st) { return st == ST_F32 || st == ST_F32K ? 4u : 
 // all kTileU segments before any is combined; add(local target, message)
 // then runs for the in-edges inside the tile. With PIPE the next step's
 // local targets are loaded after this step's messages, so they arrive while
-// the messages do (one memory round trip of three per step hidden; RMAT-24
-// pull 0.815 -> 0.795 ms); the weighted walks, whose messages also load a
-// weight, run without it (with it they would spill registers at 1,024
-// threads). Local targets are below the partition width, so masking the
-// flag bit leaves an index below kTileT.
+// the messages do (one memory round trip of three per step hidden); the
+// weighted walks, whose messages also load a weight, run without it (with it
+// they would spill registers at 1,024 threads). The index arithmetic is 32-bit
+// and unclamped: the tiled arrays hold kTilePadSeg segments of padding (no
+// pair starts, segment pair 0), so every load of a step stays inside them and
+// a padded lane's pair is a real one. Local targets are below the partition
+// width, so masking the flag bit leaves an index below kTileT.
+static_assert(kTileU <= kTilePadSeg, "a step's segments must stay inside the padded arrays");
 template <uint32_t NT, bool PIPE, typename V, typename Msg, typename Add>
 __device__ __forceinline__ void tile_walk(const TileArgs& t, uint32_t e0, uint32_t e1, const Msg& msg,
                                           const Add& add) {
   constexpr uint32_t kWaves = NT / 64;
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // flags of segment positions 1..lane (position 0 belongs to the segment's pair)
-  const uint64_t upto = (lane == 63 ? ~0ull : ((2ull << lane) - 1)) & ~1ull;
-  const uint64_t s0 = e0 >> 6, s1 = (e1 + 63) >> 6;  // 64-in-edge segments overlapping the tile
-  const uint64_t stride = (uint64_t)kWaves * kTileU;
-  uint64_t sg = s0 + (uint64_t)wave * kTileU;
-  uint32_t ploc[kTileU], psp[kTileU];  // PIPE: the offsets of the coming step
+  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t s1 = (e1 + 63) >> 6, span = e1 - e0;  // segments end; in-edges of the tile
+  constexpr uint32_t stride = kWaves * kTileU;
+  uint32_t sg = (e0 >> 6) + wave * kTileU;
+  uint32_t ploc[kTileU], psp[kTileU];  // PIPE: the coming step's local targets and segment pairs
   if (PIPE && sg < s1) {
 #pragma unroll
     for (uint32_t u = 0; u < kTileU; ++u) {
-      ploc[u] = t.tloc[min((sg + u) * 64 + lane, t.m - 1)];
-      psp[u] = t.segpair[min(sg + u, t.n_seg - 1)];
+      ploc[u] = t.tloc[(sg + u) * 64 + lane];
+      psp[u] = t.segpair[sg + u];
     }
   }
   for (; sg < s1; sg += stride) {
     uint32_t loc[kTileU], sp[kTileU];
-    uint64_t ec[kTileU];
     bool in[kTileU];
 #pragma unroll
     for (uint32_t u = 0; u < kTileU; ++u) {
-      const uint64_t e = (sg + u) * 64 + lane;
-      in[u] = sg + u < s1 && e >= e0 && e < e1;
-      ec[u] = min(e, t.m - 1);
+      const uint32_t e = (sg + u) * 64 + lane;
+      in[u] = e - e0 < span;
       if constexpr (PIPE) {
         loc[u] = ploc[u];
         sp[u] = psp[u];
       } else {
-        loc[u] = t.tloc[ec[u]];
-        sp[u] = t.segpair[min(sg + u, t.n_seg - 1)];  // the same for the whole wave
+        loc[u] = t.tloc[(sg + u) * 64 + lane];
+        sp[u] = t.segpair[sg + u];  // the same for the whole wave
       }
     }
     uint32_t src[kTileU];
 #pragma unroll
     for (uint32_t u = 0; u < kTileU; ++u) {
-      const uint64_t e = (sg + u) * 64 + lane;
-      const uint64_t flags = __ballot(e < t.m && (loc[u] & kPairStart) != 0);
-      const uint32_t pr = sp[u] + (uint32_t)__popcll(flags & upto);
-      src[u] = t.psrc[in[u] ? pr : sp[u]];
+      // pair starts at segment positions 1..lane (position 0 belongs to the
+      // segment's pair): the starts shifted down one, counted below the lane
+      const uint64_t flags = __ballot(loc[u] >= kPairStart) >> 1;
+      src[u] = t.psrc[__builtin_amdgcn_mbcnt_hi((uint32_t)(flags >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)flags, sp[u]))];
     }
     V x[kTileU];
 #pragma unroll
-    for (uint32_t u = 0; u < kTileU; ++u) x[u] = msg(src[u], ec[u]);
+    for (uint32_t u = 0; u < kTileU; ++u) x[u] = msg(src[u], (sg + u) * 64 + lane);
     if constexpr (PIPE) {
       // the next step's offsets, in flight while this step's messages arrive
-      const uint64_t ng = sg + stride;
+      const uint32_t ng = sg + stride;
       if (ng < s1) {
 #pragma unroll
         for (uint32_t u = 0; u < kTileU; ++u) {
-          ploc[u] = t.tloc[min((ng + u) * 64 + lane, t.m - 1)];
-          psp[u] = t.segpair[min(ng + u, t.n_seg - 1)];
+          ploc[u] = t.tloc[(ng + u) * 64 + lane];
+          psp[u] = t.segpair[ng + u];
         }
       }
     }
@@ -218,14 +218,12 @@ __global__ __launch_bounds__(NT) void k_tile_pull(KArgs a, TileArgs t) {
     const S* wt = static_cast<const S*>(t.wtile);
     double r_part = 0.0;
     uint64_t act = 0, pushed = 0;
-    auto msg = [&](uint32_t src, uint64_t e) -> double {
+    auto msg = [&](uint32_t src, uint32_t e) -> double {
       double x = (double)mu_in[src];
       if constexpr (G == DAIC_G_EDGE_SCALE) x *= (double)wt[e];
       return x;
     };
-    auto add = [&](uint32_t l, double x) {
-      if (x != 0.0) atomicAdd(&acc[l], x);
-    };
+    auto add = [&](uint32_t l, double x) { atomicAdd(&acc[l], x); };  // adding 0 leaves a sum as it is
     for (uint64_t tile = blockIdx.x; tile < t.n_tiles; tile += gridDim.x) {
       const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
       for (uint32_t i = tid; i < t.tw; i += kTileThreads) acc[i] = 0.0;
@@ -446,7 +444,7 @@ __global__ __launch_bounds__(NT) void k_tile_pull_mm(KArgs a, TileArgs t) {
     const S* dv = static_cast<const S*>(a.dv);
     double r_part = 0.0;
     uint64_t act = 0;
-    auto msg = [&](uint32_t src, uint64_t e) -> L { return tile_mm_msg<ST, G>(mu_in[src], t.wtile, e); };
+    auto msg = [&](uint32_t src, uint32_t e) -> L { return tile_mm_msg<ST, G>(mu_in[src], t.wtile, e); };
     auto add = [&](uint32_t l, L x) {
       if (x != M::ident) M::combine(&acc[l], x);
     };

@@ -101,6 +101,7 @@ daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uin
   if (T.ready) return DAIC_OK;
   if (lb < 8 || lb > 14) return fail(DAIC_E_INVALID, "partition width 2^%u outside 2^8..2^14", lb);
   const uint64_t n = d.n, m = d.m;
+  if (!tile_fits(m)) return fail(DAIC_E_INVALID, "tiled rounds index in-edges in 32 bits: m = %llu", (unsigned long long)m);
   const uint32_t* row = static_cast<const uint32_t*>(d.row);
   uint32_t sbits = 1;
   while ((1ull << sbits) < n) ++sbits;
@@ -136,10 +137,13 @@ daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uin
     }                                                                                            \
   } while (0)
   const uint64_t mm = std::max<uint64_t>(m, 1);
-  TCHK(hipMalloc(&T.tloc, mm * sizeof(uint16_t)));
-  TCHK(hipMalloc(&T.eid, mm * sizeof(uint32_t)));
   T.n_seg = (m + 63) / 64;
-  TCHK(hipMalloc(&T.segpair, std::max<uint64_t>(T.n_seg, 1) * sizeof(uint32_t)));
+  const uint64_t padded = tile_padded_edges(T);
+  TCHK(hipMalloc(&T.tloc, padded * sizeof(uint16_t)));
+  TCHK(hipMemsetAsync(T.tloc + m, 0, (padded - m) * sizeof(uint16_t), s));
+  TCHK(hipMalloc(&T.eid, mm * sizeof(uint32_t)));
+  TCHK(hipMalloc(&T.segpair, (T.n_seg + kTilePadSeg) * sizeof(uint32_t)));
+  TCHK(hipMemsetAsync(T.segpair + T.n_seg, 0, kTilePadSeg * sizeof(uint32_t), s));
   std::vector<uint32_t> pstart(T.n_part + 1, 0);
   if (m > 0) {
     TCHK(hipMalloc(&k0, m * sizeof(uint64_t)));
