@@ -171,6 +171,8 @@ struct TileGraph {
   uint32_t* tile_part = nullptr;   // [n_tiles] partition of each tile
   uint32_t* tile_e = nullptr;      // [n_tiles + 1] first in-edge of each tile (tiles are contiguous)
   uint32_t* tile_slot = nullptr;   // [n_tiles] partial-sum slot, or 0xFFFFFFFF (partition of one tile)
+  uint32_t* tile_order = nullptr;  // [n_tiles] launch order: largest tiles first (by in-edges, plus the
+                                   // targets an unsplit tile finishes), within groups of partitions
   uint32_t* split_part = nullptr;  // [n_split] partitions of several tiles
   uint32_t* split_slot = nullptr;  // [n_split + 1] their first slot (slots of one partition are consecutive)
 };
@@ -183,9 +185,10 @@ inline bool tile_fits(uint64_t m) { return m + 64ull * (kTilePadSeg + 1) <= 0xFF
 // The tiled form of g's in-edges with sources numbered by perm (a device
 // array, perm[j] = number of vertex j) and partitions of 2^lb targets
 // (8 <= lb <= 14), tiles of at most max_edges in-edges when nonzero, into T;
-// tile_free releases it.
-daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uint64_t max_edges, TileGraph& T,
-                       hipStream_t s);
+// tile_order sorts the tiles within each group of group_parts consecutive
+// partitions (all of them when 0); tile_free releases it.
+daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uint64_t max_edges,
+                       uint64_t group_parts, TileGraph& T, hipStream_t s);
 void tile_free(TileGraph& T);
 uint32_t tile_default_bits(uint64_t n);
 void tile_release(daic_graph* g);

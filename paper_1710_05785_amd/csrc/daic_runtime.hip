@@ -241,6 +241,7 @@ struct Impl {
     t.tile_part = T.tile_part;
     t.tile_e = T.tile_e;
     t.tile_slot = T.tile_slot;
+    t.tile_order = T.tile_order;
     t.split_part = T.split_part;
     t.split_slot = T.split_slot;
     t.pbuf = p->tile_pbuf;

@@ -227,7 +227,8 @@ __global__ __launch_bounds__(NT) void k_sweep_tile(SweepArgs a, TileArgs t, uint
     return x;
   };
   auto add = [&](uint32_t l, double x) { atomicAdd(&acc[l], x); };  // adding 0 leaves a sum as it is
-  for (uint64_t tile = tb + blockIdx.x; tile < te; tile += gridDim.x) {
+  for (uint64_t i = tb + blockIdx.x; i < te; i += gridDim.x) {
+    const uint32_t tile = t.tile_order[i];
     const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
     for (uint32_t i = tid; i < t.tw; i += NT) acc[i] = 0.0;
     __syncthreads();
@@ -660,7 +661,7 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     uint64_t max_edges = std::max<uint64_t>(16384, d.m / P * 3 / (4 * (uint64_t)std::max(cus, 1)));
     if (const char* e = std::getenv("DAIC_SWEEP_TILE_EDGES")) max_edges = std::strtoull(e, nullptr, 10);
-    if ((rc = tile_build(d, a.perm, lb, max_edges, w->tiles, s))) return rc;
+    if ((rc = tile_build(d, a.perm, lb, max_edges, B >> lb, w->tiles, s))) return rc;
     const TileGraph& T = w->tiles;
     const uint64_t TW = 1ull << T.tbits;
     std::vector<uint32_t> tp(T.n_tiles), sp(T.n_split);
@@ -690,6 +691,7 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
     t.tile_part = T.tile_part;
     t.tile_e = T.tile_e;
     t.tile_slot = T.tile_slot;
+    t.tile_order = T.tile_order;
     t.split_part = T.split_part;
     t.split_slot = T.split_slot;
     t.m = d.m;
