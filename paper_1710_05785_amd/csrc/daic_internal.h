@@ -149,11 +149,12 @@ namespace daic {
 // sorted by (renumbered source, target), so the in-edges one source sends
 // into the partition are consecutive: such a run is a "pair" (source,
 // partition) whose message base is gathered once. A partition's in-edges are
-// cut into tiles of at most kTileE; a partition with one tile is summed and
-// finished by one workgroup, the tiles of a larger one store partial sums that
-// a finishing kernel adds in tile order.
+// cut into tiles (of up to one CU's share of the in-edges for dense rounds, a
+// fraction of a block's for sweeps, at least tile_default_edges); a partition
+// with one tile is summed and finished by one workgroup, the tiles of a larger
+// one store partial sums that a finishing kernel adds in tile order.
 constexpr uint32_t kTileT = 16384;     // most targets per partition (local ids fit 14 bits)
-constexpr uint32_t kTileE = 196608;    // in-edges per tile
+constexpr uint32_t kTileE = 196608;    // in-edges per tile by default (smaller graphs: fewer)
 constexpr uint16_t kPairStart = 0x8000;  // flag of a pair's first in-edge in tloc
 // Segments of padding after the tiled per-in-edge arrays (tloc, segpair and
 // weights in tile order): zero local targets with no pair start, segment
@@ -184,13 +185,15 @@ inline uint64_t tile_padded_edges(const TileGraph& T) { return (T.n_seg + kTileP
 inline bool tile_fits(uint64_t m) { return m + 64ull * (kTilePadSeg + 1) <= 0xFFFFFFFFull; }
 // The tiled form of g's in-edges with sources numbered by perm (a device
 // array, perm[j] = number of vertex j) and partitions of 2^lb targets
-// (8 <= lb <= 14), tiles of at most max_edges in-edges when nonzero, into T;
+// (8 <= lb <= 14), tiles of at most max_edges in-edges (when nonzero; else
+// tile_default_edges), into T;
 // tile_order sorts the tiles within each group of group_parts consecutive
 // partitions (all of them when 0); tile_free releases it.
 daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uint64_t max_edges,
                        uint64_t group_parts, TileGraph& T, hipStream_t s);
 void tile_free(TileGraph& T);
 uint32_t tile_default_bits(uint64_t n);
+uint64_t tile_default_edges(uint64_t n, uint64_t m, uint32_t lb);
 void tile_release(daic_graph* g);
 }  // namespace daic
 

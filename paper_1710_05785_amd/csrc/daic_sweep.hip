@@ -659,7 +659,7 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
     // pull keeps every CU busy and its largest tiles do not trail
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    uint64_t max_edges = std::max<uint64_t>(16384, d.m / P * 3 / (4 * (uint64_t)std::max(cus, 1)));
+    uint64_t max_edges = std::min<uint64_t>(kTileE, std::max<uint64_t>(16384, d.m / P * 3 / (4 * (uint64_t)std::max(cus, 1))));
     if (const char* e = std::getenv("DAIC_SWEEP_TILE_EDGES")) max_edges = std::strtoull(e, nullptr, 10);
     if ((rc = tile_build(d, a.perm, lb, max_edges, B >> lb, w->tiles, s))) return rc;
     const TileGraph& T = w->tiles;
