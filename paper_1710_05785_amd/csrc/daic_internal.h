@@ -155,6 +155,10 @@ namespace daic {
 // one store partial sums that a finishing kernel adds in tile order.
 constexpr uint32_t kTileT = 16384;     // most targets per partition (local ids fit 14 bits)
 constexpr uint32_t kTileE = 196608;    // in-edges per tile by default (smaller graphs: fewer)
+constexpr uint32_t kNarrowTW = 2048;   // widest partition of the 256-thread tile workgroups
+// resident tile workgroups per CU: one of 1024 threads (128 KiB of LDS), or
+// about four of 256 threads (their registers)
+inline uint32_t tile_wgs_per_cu(uint32_t lb) { return (1u << lb) > kNarrowTW ? 1u : 4u; }
 constexpr uint16_t kPairStart = 0x8000;  // flag of a pair's first in-edge in tloc
 // Segments of padding after the tiled per-in-edge arrays (tloc, segpair and
 // weights in tile order): zero local targets with no pair start, segment

@@ -58,8 +58,8 @@ struct TileArgs {
 // Workgroup shapes: partitions wider than kNarrowTW take 1024 threads and
 // LDS for kTileT accumulators (one workgroup per CU); narrower ones (graphs
 // below about 2 M vertices) 256 threads and LDS for kNarrowTW accumulators,
-// so several workgroups share a CU and hide each other's latency.
-constexpr uint32_t kNarrowTW = 2048;
+// so several workgroups share a CU and hide each other's latency (kNarrowTW
+// and the resident workgroups per CU are in daic_internal.h).
 template <uint32_t NT>
 struct TileShape {
   static constexpr uint32_t threads = NT, waves = NT / 64, cap = NT == 1024 ? kTileT : kNarrowTW;

@@ -101,18 +101,20 @@ uint32_t tile_default_bits(uint64_t n) {
 daic_status tile_prepare(daic_graph* g, hipStream_t s) {
   if (g->tile.ready) return DAIC_OK;
   if (!g->pull.ready) return fail(DAIC_E_INVALID, "tiled rounds need the renumbering of the in-edge form");
-  // tiles of up to one CU's share of the in-edges (at least the default
-  // size): with the largest launched first, the few big tiles of the hub
-  // partitions run beside the many whole partitions, and a round has fewer
-  // split partitions to finish (RMAT-24, 256 CUs: 1 M in-edges per tile,
-  // pull 0.692 -> 0.635 ms and finish 0.055 -> 0.024 ms against tiles of
-  // 196,608; 0.75x or 1.25x that size was 2-4 % slower, 2x was 30 % slower);
-  // DAIC_TILE_EDGES overrides it
+  // tiles of up to one resident workgroup's share of the in-edges (at least
+  // the default size): with the largest launched first, the few big tiles of
+  // the hub partitions run beside the many whole partitions, and a round has
+  // fewer split partitions to finish (RMAT-24, 256 CUs, one workgroup each:
+  // 1 M in-edges per tile, pull 0.692 -> 0.635 ms and finish 0.055 ->
+  // 0.024 ms against tiles of 196,608; 0.75x or 1.25x that size was 2-4 %
+  // slower, 2x was 30 % slower; RMAT-20 SSSP, whose 256-thread workgroups
+  // share the CUs, lost 25 % with tiles of one CU's share); DAIC_TILE_EDGES
+  // overrides it
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const uint64_t n = g->dev.n, m = g->dev.m;
   const uint32_t lb = tile_default_bits(n);
-  uint64_t max_edges = std::max<uint64_t>(tile_default_edges(n, m, lb), m / (uint64_t)std::max(cus, 1));
+  uint64_t max_edges = std::max<uint64_t>(tile_default_edges(n, m, lb), m / ((uint64_t)std::max(cus, 1) * tile_wgs_per_cu(lb)));
   if (const char* e = std::getenv("DAIC_TILE_EDGES")) max_edges = std::strtoull(e, nullptr, 10);
   return tile_build(g->dev, g->pull.perm, lb, max_edges, 0, g->tile, s);
 }
