@@ -277,6 +277,65 @@ def test_tiled_unfused_dense_rounds_match_streamed(daic, monkeypatch, state, gk)
         assert np.abs(dvb - dva).sum() <= tol * max(np.abs(va).sum(), 1.0)
 
 
+@pytest.mark.parametrize("kind", ["pagerank_f64", "pagerank_f32_kahan", "sssp_u32", "cc_i32"])
+def test_tile_sizes_agree(daic, monkeypatch, kind):
+    """The tiled dense rounds with tiles of at most 2,048 in-edges (almost
+    every partition split, hundreds of slots per hub partition, the launch
+    order largest first), with the default size, and with one tile per
+    partition (nothing split): the same rounds, updates and messages, the
+    same min/max state bit for bit and the same sum state to rounding (the
+    tiles change the order of the FP64 additions), and the sum states within
+    the oracle's bound."""
+    say("case tile sizes", kind)
+    g = daic_gen.rmat(16, 16, seed=47)
+    w = daic_gen.sssp_weights(g.m, seed=48) if kind == "sssp_u32" else None
+    out = []
+    for te in ("2048", None, "1073741824"):
+        if te is None:
+            monkeypatch.delenv("DAIC_TILE_EDGES", raising=False)
+        else:
+            monkeypatch.setenv("DAIC_TILE_EDGES", te)
+        G = daic.Graph(g.row_ptr, g.col, w)  # the tiles are built per graph
+        if kind.startswith("pagerank"):
+            P = daic.Problem(G, daic.SUM, daic.G_DEG_SCALE, alpha=0.85, state=kind.split("_", 1)[1])
+            P.set_init(np.zeros(g.n), np.full(g.n, 0.15))
+            kw = dict(eps=1e-10 if kind == "pagerank_f64" else 1e-6, q=1.0, sched="all", rounds_per_check=4)
+        elif kind == "sssp_u32":
+            P = daic.Problem(G, daic.MIN, daic.G_EDGE_ADD, state="u32")
+            v0, dv1 = oracle.sssp_init(g.n, 0)
+            P.set_init(v0, dv1)
+            kw = dict(q=1.0, sched="all", rounds_per_check=4)
+        else:
+            P = daic.Problem(G, daic.MAX, daic.G_COPY, state="i32")
+            v0, dv1 = oracle.cc_init(g.n)
+            P.set_init(v0, dv1)
+            kw = dict(q=1.0, sched="all", rounds_per_check=4)
+        r = P.run(**kw)
+        assert r.converged, (te, r.stats)
+        out.append((r, P.get()))
+    monkeypatch.delenv("DAIC_TILE_EDGES", raising=False)
+    ra, va = out[1]
+    for rb, vb in (out[0], out[2]):
+        for key in ("rounds", "activations", "pushed_edges"):
+            assert rb.stats[key] == ra.stats[key], (kind, key, ra.stats, rb.stats)
+        if kind in ("sssp_u32", "cc_i32"):
+            assert np.array_equal(vb, va)
+        else:
+            tol = 1e-12 if kind == "pagerank_f64" else 2e-6
+            assert np.abs(vb - va).sum() <= tol * np.abs(va).sum()
+    if kind.startswith("pagerank"):
+        ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.85, np.full(g.n, 0.15), eps=1e-13)
+        for _, v in out:
+            if kind == "pagerank_f64":
+                assert np.abs(v - ref).sum() <= 1e-10 / (1 - 0.85) * 1.01
+            else:
+                assert np.abs(v - ref).sum() <= 1e-5 * np.abs(ref).sum()
+    elif kind == "sssp_u32":
+        assert np.array_equal(out[1][1], oracle.dijkstra(g, w, 0))
+    else:
+        assert np.array_equal(out[1][1], oracle.maxlabel(g))
+
+
 @pytest.mark.parametrize("n,ef", [(5, 2), (300, 3), (3000, 6)])
 def test_fused_pull_small_graphs(daic, monkeypatch, n, ef):
     """Fused dense rounds on graphs with fewer edge blocks than the grid
