@@ -183,11 +183,19 @@ daic_status daic_problem_set_init(daic_problem* p, const void* v0, const void* d
 daic_status daic_problem_set_init_device(daic_problem* p, const void* d_v0, const void* d_dv1,
                                          void* hip_stream);
 /* Run rounds until the stop rule holds (DAIC_OK) or max_rounds (warning).
- * Sum problems run a round as a pull over in-edges when at least n/32
- * vertices update (env DAIC_PULL_DIV sets 32, DAIC_NO_PULL=1 always pushes);
- * under DAIC_SCHED_ALL such rounds fuse the next round's claim into the pull
- * (DAIC_NO_FUSE=1 keeps them apart). Every form ends in the same state after
- * the same rounds (up to FP32 summation order). */
+ * A round whose messages reach most of the graph runs as a pull over the
+ * in-edges (Eq. sync read per receiver; the same state as the pushes): sum
+ * problems when at least n/32 vertices update (env DAIC_PULL_DIV sets 32),
+ * min and max problems when the pending vertices' out-edges reach m/4
+ * (DAIC_PULL_EDGE_DIV sets 4); DAIC_NO_PULL=1 always pushes. Under
+ * DAIC_SCHED_ALL sum rounds fuse the next round's claim into the pull
+ * (DAIC_NO_FUSE=1 keeps them apart). The pulls walk the in-edges in
+ * partition tiles built once per graph (DAIC_NO_TILE=1 keeps the streamed
+ * pull for sum problems and pushes for min/max; DAIC_TILE_EDGES, read when a
+ * graph's tiles are built, caps the in-edges per tile; the sweep schedule's
+ * tiles take DAIC_SWEEP_TILE_EDGES and DAIC_SWEEP_TILE_BITS). Every form
+ * ends in the same state after the same rounds (min/max bit for bit, sums up
+ * to the order of their FP additions). */
 daic_status daic_run(daic_problem* p, const daic_run_opts* opts, daic_stats* stats);
 /* Copy the state out: v_out (n values; double for FP states, where F32_KAHAN
  * reports v - c in FP64), dv_out nullable (same type). */
