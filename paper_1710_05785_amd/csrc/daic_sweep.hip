@@ -437,7 +437,12 @@ __global__ __launch_bounds__(256) void k_sweep_coef(const uint32_t* __restrict__
   };
   rows_by_groups<true>(
       row, n, [&](uint64_t, uint32_t e) { return Edge{perm[col[e]], W ? fabs((double)w[e]) : 1.0}; },
-      [&](uint64_t j, uint32_t, const Edge& x) { return (uint64_t)x.rank / B <= (uint64_t)perm[j] / B ? x.weight : 0.0; },
+      [&](uint64_t j, uint32_t, const Edge& x) {
+        // block(t) <= block(j) <=> t's number is below the end of j's block
+        // (one 32-bit division per row once hoisted, none per edge)
+        const uint64_t end = (uint64_t)(perm[j] / (uint32_t)B + 1) * B;
+        return x.rank < end ? x.weight : 0.0;
+      },
       [&](uint64_t j, double acc) { coef_le[perm[j]] = acc; });
 }
 
