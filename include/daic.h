@@ -191,9 +191,10 @@ daic_status daic_problem_set_init_device(daic_problem* p, const void* d_v0, cons
  * DAIC_SCHED_ALL sum rounds fuse the next round's claim into the pull
  * (DAIC_NO_FUSE=1 keeps them apart). The pulls walk the in-edges in
  * partition tiles built once per graph (DAIC_NO_TILE=1 keeps the streamed
- * pull for sum problems and pushes for min/max; DAIC_TILE_EDGES, read when a
- * graph's tiles are built, caps the in-edges per tile; the sweep schedule's
- * tiles take DAIC_SWEEP_TILE_EDGES and DAIC_SWEEP_TILE_BITS). Every form
+ * pull for sum problems and pushes for min/max; DAIC_TILE_EDGES and
+ * DAIC_TILE_BITS, read when a graph's tiles are built, set the in-edges per
+ * tile and the partition width 2^bits; the sweep schedule's tiles take
+ * DAIC_SWEEP_TILE_EDGES and DAIC_SWEEP_TILE_BITS). Every form
  * ends in the same state after the same rounds (min/max bit for bit, sums up
  * to the order of their FP additions). */
 daic_status daic_run(daic_problem* p, const daic_run_opts* opts, daic_stats* stats);

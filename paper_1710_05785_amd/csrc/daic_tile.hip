@@ -113,7 +113,12 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const uint64_t n = g->dev.n, m = g->dev.m;
-  const uint32_t lb = tile_default_bits(n);
+  // the partition width: RMAT-20 (1,024 partitions of 2^10) took 6.7 ms per
+  // PageRank solve and 1.03 / 2.26 ms per SSSP solve (all / sampled), with
+  // 2^12: 9.6 ms and 1.03 / 2.23 ms, with 2^14: 12.9 ms and 1.19 / 2.53 ms
+  // (DAIC_TILE_BITS overrides it)
+  uint32_t lb = tile_default_bits(n);
+  if (const char* e = std::getenv("DAIC_TILE_BITS")) lb = (uint32_t)std::max(8ul, std::min(14ul, std::strtoul(e, nullptr, 10)));
   uint64_t max_edges = std::max<uint64_t>(tile_default_edges(n, m, lb), m / ((uint64_t)std::max(cus, 1) * tile_wgs_per_cu(lb)));
   if (const char* e = std::getenv("DAIC_TILE_EDGES")) max_edges = std::strtoull(e, nullptr, 10);
   return tile_build(g->dev, g->pull.perm, lb, max_edges, 0, g->tile, s);
