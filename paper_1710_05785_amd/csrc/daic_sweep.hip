@@ -227,8 +227,8 @@ __global__ __launch_bounds__(NT) void k_sweep_tile(SweepArgs a, TileArgs t, uint
     return x;
   };
   auto add = [&](uint32_t l, double x) { atomicAdd(&acc[l], x); };  // adding 0 leaves a sum as it is
-  for (uint64_t i = tb + blockIdx.x; i < te; i += gridDim.x) {
-    const uint32_t tile = t.tile_order[i];
+  for (uint64_t pos = tb + blockIdx.x; pos < te; pos += gridDim.x) {
+    const uint32_t tile = t.tile_order[pos];
     const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
     for (uint32_t i = tid; i < t.tw; i += NT) acc[i] = 0.0;
     __syncthreads();

@@ -39,7 +39,7 @@ struct TileArgs {
   const uint32_t* tile_part;
   const uint32_t* tile_e;
   const uint32_t* tile_slot;
-  const uint32_t* tile_order;  // dense rounds take tile tile_order[i] for i = workgroup, workgroup + grid, ...
+  const uint32_t* tile_order;  // launch order: a workgroup takes tiles tile_order[workgroup], [workgroup + grid], ...
   const uint32_t* split_part;
   const uint32_t* split_slot;
   double* pbuf;               // [n_slots][tw] partial sums of the tiles of split partitions (SlotT<ST>)
@@ -225,8 +225,8 @@ __global__ __launch_bounds__(NT) void k_tile_pull(KArgs a, TileArgs t) {
       return x;
     };
     auto add = [&](uint32_t l, double x) { atomicAdd(&acc[l], x); };  // adding 0 leaves a sum as it is
-    for (uint64_t i = blockIdx.x; i < t.n_tiles; i += gridDim.x) {
-      const uint32_t tile = t.tile_order[i];
+    for (uint64_t pos = blockIdx.x; pos < t.n_tiles; pos += gridDim.x) {
+      const uint32_t tile = t.tile_order[pos];
       const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
       for (uint32_t i = tid; i < t.tw; i += kTileThreads) acc[i] = 0.0;
       __syncthreads();
@@ -450,8 +450,8 @@ __global__ __launch_bounds__(NT) void k_tile_pull_mm(KArgs a, TileArgs t) {
     auto add = [&](uint32_t l, L x) {
       if (x != M::ident) M::combine(&acc[l], x);
     };
-    for (uint64_t i = blockIdx.x; i < t.n_tiles; i += gridDim.x) {
-      const uint32_t tile = t.tile_order[i];
+    for (uint64_t pos = blockIdx.x; pos < t.n_tiles; pos += gridDim.x) {
+      const uint32_t tile = t.tile_order[pos];
       const uint32_t part = t.tile_part[tile], e0 = t.tile_e[tile], e1 = t.tile_e[tile + 1], slot = t.tile_slot[tile];
       for (uint32_t i = tid; i < t.tw; i += kTileThreads) acc[i] = M::ident;
       __syncthreads();

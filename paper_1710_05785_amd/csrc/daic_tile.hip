@@ -254,7 +254,7 @@ daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uin
   if (!sp.empty()) TCHK(hipMemcpy(T.split_part, sp.data(), sp.size() * 4, hipMemcpyHostToDevice));
   TCHK(hipMemcpy(T.split_slot, ss.data(), ss.size() * 4, hipMemcpyHostToDevice));
   // largest tiles first, so that the last workgroups of a round are small
-  // ones and its tail is short (RMAT-24 pull 0.758 -> 0.705 ms): the work of
+  // ones and its tail is short (RMAT-24 pull 0.758 -> 0.692 ms): the work of
   // a tile is its in-edges plus, for an unsplit partition, finishing its
   // targets (about two in-edges' worth each); sweeps sort within each block
   std::vector<uint32_t> order(T.n_tiles);
