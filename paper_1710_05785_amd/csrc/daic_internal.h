@@ -190,11 +190,12 @@ inline bool tile_fits(uint64_t m) { return m + 64ull * (kTilePadSeg + 1) <= 0xFF
 // The tiled form of g's in-edges with sources numbered by perm (a device
 // array, perm[j] = number of vertex j) and partitions of 2^lb targets
 // (8 <= lb <= 14), tiles of at most max_edges in-edges (when nonzero; else
-// tile_default_edges), into T;
-// tile_order sorts the tiles within each group of group_parts consecutive
-// partitions (all of them when 0); tile_free releases it.
+// tile_default_edges); with share_div nonzero, of at most 1/share_div of
+// their group's in-edges (and max_edges when nonzero), into T; tile_order
+// sorts the tiles within each group of group_parts consecutive partitions
+// (all of them when 0); tile_free releases it.
 daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uint64_t max_edges,
-                       uint64_t group_parts, TileGraph& T, hipStream_t s);
+                       uint64_t group_parts, uint32_t share_div, TileGraph& T, hipStream_t s);
 void tile_free(TileGraph& T);
 uint32_t tile_default_bits(uint64_t n);
 uint64_t tile_default_edges(uint64_t n, uint64_t m, uint32_t lb);

@@ -660,13 +660,21 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
   if (const char* e = std::getenv("DAIC_SWEEP_TILE_BITS")) lb = (uint32_t)std::min(14ul, std::strtoul(e, nullptr, 10));
   while (lb >= 8 && B % (1ull << lb) != 0) --lb;
   if (lb >= 8 && !std::getenv("DAIC_NO_TILE") && d.m > 0 && tile_fits(d.m)) {
-    // tiles of about 3/4 of a block's in-edges per CU, so that a block's
-    // pull keeps every CU busy and its largest tiles do not trail
+    // tiles of up to one resident workgroup's share of their own block's
+    // in-edges: RMAT-24's id blocks hold very different numbers of in-edges
+    // (4 blocks: 58, 18, 18 and 6 %), so one size for all either splits the
+    // light blocks' partitions too little (their largest tile then outlasts
+    // the rest) or the heavy block's too much (4 blocks: 81.5 ms per solve
+    // against 86.8 ms with tiles of at most 196,608 for all blocks; a half
+    // or 3/4 share: 84-86 ms). DAIC_SWEEP_TILE_SHARE sets the divisor,
+    // DAIC_SWEEP_TILE_EDGES caps the tiles.
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    uint64_t max_edges = std::min<uint64_t>(kTileE, std::max<uint64_t>(16384, d.m / P * 3 / (4 * (uint64_t)std::max(cus, 1))));
+    uint64_t max_edges = 0;
     if (const char* e = std::getenv("DAIC_SWEEP_TILE_EDGES")) max_edges = std::strtoull(e, nullptr, 10);
-    if ((rc = tile_build(d, a.perm, lb, max_edges, B >> lb, w->tiles, s))) return rc;
+    uint32_t share = (uint32_t)std::max(cus, 1) * tile_wgs_per_cu(lb);
+    if (const char* e = std::getenv("DAIC_SWEEP_TILE_SHARE")) share = (uint32_t)std::strtoul(e, nullptr, 10);
+    if ((rc = tile_build(d, a.perm, lb, max_edges, B >> lb, share, w->tiles, s))) return rc;
     const TileGraph& T = w->tiles;
     const uint64_t TW = 1ull << T.tbits;
     std::vector<uint32_t> tp(T.n_tiles), sp(T.n_split);

@@ -121,11 +121,11 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
   if (const char* e = std::getenv("DAIC_TILE_BITS")) lb = (uint32_t)std::max(8ul, std::min(14ul, std::strtoul(e, nullptr, 10)));
   uint64_t max_edges = std::max<uint64_t>(tile_default_edges(n, m, lb), m / ((uint64_t)std::max(cus, 1) * tile_wgs_per_cu(lb)));
   if (const char* e = std::getenv("DAIC_TILE_EDGES")) max_edges = std::strtoull(e, nullptr, 10);
-  return tile_build(g->dev, g->pull.perm, lb, max_edges, 0, g->tile, s);
+  return tile_build(g->dev, g->pull.perm, lb, max_edges, 0, 0, g->tile, s);
 }
 
 daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uint64_t max_edges,
-                       uint64_t group_parts, TileGraph& T, hipStream_t s) {
+                       uint64_t group_parts, uint32_t share_div, TileGraph& T, hipStream_t s) {
   if (T.ready) return DAIC_OK;
   if (lb < 8 || lb > 14) return fail(DAIC_E_INVALID, "partition width 2^%u outside 2^8..2^14", lb);
   const uint64_t n = d.n, m = d.m;
@@ -225,16 +225,23 @@ daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uin
   // it); a partition with more than ecap in-edges gets consecutive slots
   std::vector<uint32_t> tp, te, ts, sp, ss;
   uint32_t slots = 0;
+  const uint64_t gp = group_parts ? group_parts : T.n_part;
+  uint64_t gcap = ecap;  // the cap of the current group
   for (uint64_t p = 0; p < T.n_part; ++p) {
+    if (share_div && p % gp == 0) {  // 1/share_div of the group's in-edges, under max_edges if given
+      const uint64_t g1 = std::min<uint64_t>(T.n_part, p + gp);
+      gcap = std::max<uint64_t>(1024, (pstart[g1] - pstart[p]) / share_div);
+      if (max_edges) gcap = std::min(gcap, ecap);
+    }
     const uint64_t a = pstart[p], b = pstart[p + 1];
-    const uint64_t nt = std::max<uint64_t>(1, (b - a + ecap - 1) / ecap);
+    const uint64_t nt = std::max<uint64_t>(1, (b - a + gcap - 1) / gcap);
     if (nt > 1) {
       sp.push_back((uint32_t)p);
       ss.push_back(slots);
     }
     for (uint64_t k = 0; k < nt; ++k) {
       tp.push_back((uint32_t)p);
-      te.push_back((uint32_t)(a + k * ecap));
+      te.push_back((uint32_t)(a + k * gcap));
       ts.push_back(nt > 1 ? slots++ : 0xFFFFFFFFu);
     }
   }
@@ -260,7 +267,6 @@ daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uin
   std::vector<uint32_t> order(T.n_tiles);
   for (uint32_t i = 0; i < T.n_tiles; ++i) order[i] = i;
   auto work = [&](uint32_t x) { return (uint64_t)(te[x + 1] - te[x]) + (ts[x] == 0xFFFFFFFFu ? 2 * TW : 0); };
-  const uint64_t gp = group_parts ? group_parts : T.n_part;
   for (uint32_t b = 0; b < T.n_tiles;) {
     uint32_t e = b;
     while (e < T.n_tiles && tp[e] / gp == tp[b] / gp) ++e;
