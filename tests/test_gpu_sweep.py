@@ -318,3 +318,38 @@ def test_sweep_tiled_matches_streamed(daic, monkeypatch, state):
     assert np.abs(vb - va).sum() <= tol * np.abs(va).sum()
     bound = 1e-9 if state == "f64" else 1e-5 * ref.sum()
     assert np.abs(vb - ref).sum() <= bound
+
+
+@pytest.mark.parametrize("state", ["f32_kahan", "f64"])
+def test_sweep_tile_sizes_agree(daic, monkeypatch, state):
+    """Tiled sweeps (RMAT-16, 4 blocks) with the default tiles (a CU's share
+    of each block's in-edges), with one tile per partition (share 1: nothing
+    split) and with tiles of at most 2,048 in-edges (most partitions split,
+    slots added by the finishing kernel): the same rounds, vertex updates and
+    messages, states equal to rounding, within the oracle's tolerance."""
+    say("case sweep tile sizes", state)
+    g = daic_gen.rmat(16, 16, seed=76)
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_DEG_SCALE, 0.8, np.full(g.n, 0.2), eps=1e-13)
+    eps = 1e-10 if state == "f64" else 1e-6
+    out = []
+    for share, edges in ((None, None), ("1", None), (None, "2048")):
+        for key, val in (("DAIC_SWEEP_TILE_SHARE", share), ("DAIC_SWEEP_TILE_EDGES", edges)):
+            if val is None:
+                monkeypatch.delenv(key, raising=False)
+            else:
+                monkeypatch.setenv(key, val)
+        p = pr_problem(daic, g, state=state)  # a new problem builds its sweep tiles
+        r = p.run(eps=eps, q=0.25, sched="sweep", rounds_per_check=8)
+        assert r.converged
+        out.append((r, p.get()))
+    monkeypatch.delenv("DAIC_SWEEP_TILE_SHARE", raising=False)
+    monkeypatch.delenv("DAIC_SWEEP_TILE_EDGES", raising=False)
+    ra, va = out[0]
+    tol = 1e-12 if state == "f64" else 2e-6
+    for rb, vb in out[1:]:
+        for key in ("rounds", "activations", "pushed_edges"):
+            assert rb.stats[key] == ra.stats[key], (key, ra.stats, rb.stats)
+        assert np.abs(vb - va).sum() <= tol * np.abs(va).sum()
+    bound = 1e-9 if state == "f64" else 1e-5 * ref.sum()
+    for _, v in out:
+        assert np.abs(v - ref).sum() <= bound
