@@ -312,16 +312,30 @@ __global__ __launch_bounds__(256) void k_tile_total(KArgs a, TileArgs t, uint32_
     if (ctl_halted(ctl) || (!FUSED && !ctl->last_pull)) return;
     double rr = 0.0;
     uint64_t aa = 0, ps = 0;
-    for (uint32_t i = threadIdx.x; i < np; i += 256) {
-      rr += t.tpart_r[i];
-      aa += t.tpart_a[i];
-      ps += t.tpart_p[i];
-    }
-    for (uint32_t i = threadIdx.x; i < nf; i += 256) {
-      rr += t.spart_r[i];
-      aa += t.spart_a[i];
-      ps += t.spart_p[i];
-    }
+    // eight partials per thread at a time, their loads in flight together
+    // and added in the same order as one at a time
+    auto add_partials = [&](const double* pr, const uint64_t* pa, const uint64_t* pp, uint32_t count) {
+      for (uint32_t i0 = threadIdx.x; i0 < count; i0 += 8 * 256) {
+        double xr[8];
+        uint64_t xa[8], xp[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) {
+          const uint32_t i = min(i0 + u * 256, count - 1);
+          xr[u] = pr[i];
+          xa[u] = pa[i];
+          xp[u] = pp[i];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u)
+          if (i0 + u * 256 < count) {
+            rr += xr[u];
+            aa += xa[u];
+            ps += xp[u];
+          }
+      }
+    };
+    add_partials(t.tpart_r, t.tpart_a, t.tpart_p, np);
+    add_partials(t.spart_r, t.spart_a, t.spart_p, nf);
     rr = block_sum256(rr);
     aa = block_sum256(aa);
     ps = block_sum256(ps);
