@@ -89,25 +89,32 @@ __device__ __forceinline__ T block_sum_waves(T x) {
 // (most rows of power-law graphs hold a few dozen edges, which a whole wave
 // per row would leave mostly idle); a row of more than 1,024 edges is taken
 // afterwards by the whole wave, eight edges per lane at a time with their
-// loads issued together (a hub row of a few hundred thousand edges would
-// otherwise hold its wave for one memory latency per 64 edges, far longer
-// than the rest of the graph takes). Each edge e of row j is handled in two
-// calls: load(j, e) only reads memory and returns what the edge needs, then
-// use(j, e, loaded) computes, may store, and returns the edge's contribution;
-// with REDUCE, done(j, sum) is called once per row (by one lane) with the
-// row's sum of contributions.
+// loads issued together. The rows are dealt to the groups in a scrambled
+// order (row = x times an odd constant modulo the next power of two above
+// n, a bijection; logical indices that land at or beyond n are skipped):
+// on RMAT graphs the heavy rows recur at id strides that are powers of two,
+// so a plain strided deal gave one wave millions of edges of heavy rows
+// (4.3 M of RMAT-24's 125 M) while most waves had none. Each edge e of row
+// j is handled in two calls: load(j, e) only reads memory and returns what
+// the edge needs, then use(j, e, loaded) computes, may store, and returns
+// the edge's contribution; with REDUCE, done(j, sum) is called once per row
+// (by one lane) with the row's sum of contributions.
 template <bool REDUCE, typename Load, typename Use, typename Done>
 __device__ __forceinline__ void rows_by_groups(const uint32_t* row, uint64_t n, const Load& load, const Use& use,
                                                const Done& done) {
   constexpr uint32_t kGroup = 16, kHeavy = 1024, kIlp = 8;
+  constexpr uint64_t kMix = 0x9E3779B97F4A7C15ull;  // odd: x -> x kMix is a bijection modulo 2^k
   using T = decltype(load(uint64_t{0}, uint32_t{0}));
   const uint32_t lane = lane_id(), sub = lane & (kGroup - 1), grp = lane / kGroup;
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t j0 = wave * (64 / kGroup); j0 < n; j0 += nwaves * (64 / kGroup)) {
-    const uint64_t j = j0 + grp;
+  const uint64_t span = n <= 1 ? n : 1ull << (64 - __clzll((long long)(n - 1)));  // next power of two >= n
+  for (uint64_t x0 = wave * (64 / kGroup); x0 < span; x0 += nwaves * (64 / kGroup)) {
+    const uint64_t x = x0 + grp;
+    const uint64_t j = (x * kMix) & (span - 1);
+    const bool valid = x < span && j < n;
     uint32_t b = 0, e1 = 0;
-    if (j < n) {
+    if (valid) {
       b = row[j];
       e1 = row[j + 1];
     }
@@ -118,7 +125,7 @@ __device__ __forceinline__ void rows_by_groups(const uint32_t* row, uint64_t n, 
     if constexpr (REDUCE) {
 #pragma unroll
       for (uint32_t d = kGroup / 2; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
-      if (j < n && !heavy && sub == 0) done(j, acc);
+      if (valid && !heavy && sub == 0) done(j, acc);
     }
     // heavy rows of this wave, one at a time by all 64 lanes
     uint64_t hm = __ballot(heavy && sub == 0);
@@ -126,7 +133,7 @@ __device__ __forceinline__ void rows_by_groups(const uint32_t* row, uint64_t n, 
       const uint32_t src = (uint32_t)__ffsll((unsigned long long)hm) - 1;
       hm &= hm - 1;
       const uint32_t hb = __shfl(b, src, 64), he = __shfl(e1, src, 64);
-      const uint64_t hj = j0 + src / kGroup;
+      const uint64_t hj = __shfl(j, src, 64);
       double h = 0.0;
       for (uint32_t e = hb + lane; e < he; e += 64 * kIlp) {
         T v[kIlp];
