@@ -189,7 +189,8 @@ daic_status daic_problem_set_init_device(daic_problem* p, const void* d_v0, cons
  * min and max problems when the pending vertices' out-edges reach m/4
  * (DAIC_PULL_EDGE_DIV sets 4); DAIC_NO_PULL=1 always pushes. Under
  * DAIC_SCHED_ALL sum rounds fuse the next round's claim into the pull
- * (DAIC_NO_FUSE=1 keeps them apart). The pulls walk the in-edges in
+ * (DAIC_NO_FUSE=1 keeps them apart, and so does DAIC_NO_GRAPH=1, which
+ * launches every round eagerly instead of replaying captured groups). The pulls walk the in-edges in
  * partition tiles built once per graph (DAIC_NO_TILE=1 keeps the streamed
  * pull for sum problems and pushes for min/max; DAIC_TILE_EDGES and
  * DAIC_TILE_BITS, read when a graph's tiles are built, set the in-edges per

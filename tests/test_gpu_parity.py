@@ -9,6 +9,7 @@ Tolerances:
 Every case is seeded; sizes span many blocks of the per-vertex kernels, end on
 a ragged tail, and include hubs split into several large-bin chunks.
 """
+import os
 import sys
 
 import numpy as np
@@ -384,7 +385,7 @@ def test_profile_matches_run_and_accounts_the_pull(daic, monkeypatch):
         va, vb = a.get(), b.get()
         assert np.abs(va - vb).sum() <= 2e-6 * np.abs(va).sum()
         names = {k["name"]: k for k in ks}
-        if fuse:
+        if fuse and not os.environ.get("DAIC_NO_GRAPH"):  # eager rounds (DAIC_NO_GRAPH=1) are not fused
             pull = names["tile_pull" if "tile_pull" in names else "pull_fused"]
         else:
             pull = names["pull_tile" if "pull_tile" in names else "pull_stream"]
