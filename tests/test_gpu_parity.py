@@ -225,7 +225,8 @@ def test_minmax_dense_rounds_match_push(daic, monkeypatch, graph, kind, sched, q
             rp, ks = make().profile(q=q, sched=sched)
             names = {k["name"]: k for k in ks}
             say("  dense rounds", names.get("pull_tile", {}).get("launches", 0), "of", rp.stats["rounds"])
-            if sched == "all" and graph == "rmat16":
+            # min and max problems take dense rounds through the tiles only
+            if sched == "all" and graph == "rmat16" and not os.environ.get("DAIC_NO_TILE"):
                 assert names["pull_tile"]["launches"] >= 1
     (ra, va), (rb, vb) = out
     for key in ("rounds", "activations", "pushed_edges"):

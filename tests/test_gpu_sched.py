@@ -12,6 +12,7 @@ can move it.
 The trace rule (sampling, features, labels) and the Adam step are compared
 with the oracle's exact top-k rounds and Adam update: labels bit-exact,
 features within a few FP32 units."""
+import os
 import sys
 
 import numpy as np
@@ -353,8 +354,14 @@ def test_learned_rounds_captured_equal_eager(daic, trained_pr, monkeypatch):
     (sa, (va, da)), (sb, (vb, db)) = runs
     for k in ("rounds", "pushed_edges", "activations", "learned_fallbacks", "learned_exact_rounds"):
         assert sa[k] == sb[k], k
-    np.testing.assert_array_equal(va, vb)
-    np.testing.assert_array_equal(da, db)
+    if os.environ.get("DAIC_NO_TILE"):
+        # the streamed pull adds the pieces of cut targets with FP32 atomics,
+        # so its sums vary in the last bits from run to run
+        np.testing.assert_allclose(va, vb, rtol=1e-6, atol=0)
+        np.testing.assert_allclose(da, db, rtol=1e-5, atol=1e-9)
+    else:
+        np.testing.assert_array_equal(va, vb)
+        np.testing.assert_array_equal(da, db)
     # the same problem object re-run after the network changed: the result
     # must follow the new network (the inverted one), not a stale capture
     p = pr_problem(daic, g)
