@@ -755,7 +755,10 @@ daic_status sweep_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats
   if (!get_ops(p, &ops) || !sweep_ops(p, &sw)) return fail(DAIC_E_UNSUPPORTED, "no kernel for this combination");
   const uint64_t B = std::max<uint64_t>(1, std::min<uint64_t>(n, (uint64_t)std::ceil(o->priority_fraction * (double)n)));
   rc = sweep_setup(p, B, s);
-  if (rc) return rc;
+  if (rc) {
+    sweep_release(p);  // a half-built state must not pass for a finished one on the next run
+    return rc;
+  }
   const SweepState& w = *p->sweep;
   const uint32_t P = w.P;
   // rounds captured per launch: whole sweeps, at least rounds_per_check rounds

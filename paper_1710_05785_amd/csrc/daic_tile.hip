@@ -129,7 +129,9 @@ daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uin
   if (T.ready) return DAIC_OK;
   if (lb < 8 || lb > 14) return fail(DAIC_E_INVALID, "partition width 2^%u outside 2^8..2^14", lb);
   const uint64_t n = d.n, m = d.m;
-  if (!tile_fits(m)) return fail(DAIC_E_INVALID, "tiled rounds index in-edges in 32 bits: m = %llu", (unsigned long long)m);
+  // the sorts and scans below count in int, the walk indexes in 32 bits
+  if (!tile_fits(m) || m > 0x7FFFFFFFull)
+    return fail(DAIC_E_INVALID, "tiled rounds take fewer than 2^31 in-edges: m = %llu", (unsigned long long)m);
   const uint32_t* row = static_cast<const uint32_t*>(d.row);
   uint32_t sbits = 1;
   while ((1ull << sbits) < n) ++sbits;
