@@ -1840,6 +1840,7 @@ daic_status daic_batch_run(daic_batch* b, const daic_run_opts* o, daic_stats* st
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     if (b->exec_sw) { (void)hipGraphExecDestroy(b->exec_sw); b->exec_sw = nullptr; }
     if (b->graph_sw) { (void)hipGraphDestroy(b->graph_sw); b->graph_sw = nullptr; }
+    b->exec_K = 0;  // no match until both captures below have succeeded
     DAIC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     for (uint32_t r = 0; r < K; ++r) enqueue_round(b, s);
     hipGraph_t graph;
