@@ -463,6 +463,31 @@ typedef struct {
 daic_status daic_profile(daic_problem* p, const daic_run_opts* opts, uint32_t cap,
                          daic_kernel_time* out, uint32_t* n_out, daic_stats* stats);
 
+/* The tile table that dense rounds build over the partition-tiled in-edges
+ * (the synchronous pull of Eq. sync, walked partition by partition), computed
+ * on the host alone and exposed for unit tests of its invariants; no device
+ * is touched. Input: pstart[p], the first in-edge of partition p in the
+ * sorted in-edge order (n_part + 1 host entries, non-decreasing, the last
+ * one the in-edge count, below 2^31), and the partition width 2^lb (lb in
+ * 8..14). Every partition gets at least one tile; one with more in-edges
+ * than its cap is cut into cap-sized tiles and a remainder, numbered in
+ * order and given consecutive partial-sum slots. The cap is max_edges (at
+ * least 1,024), or with share_div > 0 the in-edges of each group of
+ * group_parts consecutive partitions (all partitions when 0) divided by
+ * share_div (at least 1,024; under max_edges when both are given).
+ * Outputs, host arrays of cap entries each: tile_part[t] (partition of tile
+ * t), tile_e (n_tiles + 1 entries; tile t holds in-edges [tile_e[t],
+ * tile_e[t + 1])), tile_slot[t] (0xFFFFFFFF for the single tile of an
+ * unsplit partition) and order (the launch order: within each group the
+ * tiles by work, largest first, ties in tile order; work = in-edges, plus
+ * 2 * 2^lb for an unsplit partition, whose targets the tile finishes).
+ * *n_tiles, *n_split (partitions with several tiles) and *n_slots are
+ * written even when cap < n_tiles + 1, which returns DAIC_E_INVALID.      */
+daic_status daic_tile_table(const uint32_t* pstart, uint64_t n_part, uint32_t lb, uint64_t max_edges,
+                            uint64_t group_parts, uint32_t share_div, uint64_t cap, uint32_t* tile_part,
+                            uint32_t* tile_e, uint32_t* tile_slot, uint32_t* order, uint64_t* n_tiles,
+                            uint64_t* n_split, uint64_t* n_slots);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,6 +71,62 @@ __global__ void k_tile_pairs(const uint64_t* keys, const uint32_t* flag, const u
   }
 }
 
+// The tile table of a partitioned in-edge order, on the host: pstart[p] is
+// the first in-edge of partition p (n_part + 1 entries, non-decreasing).
+// Every partition gets at least one tile (its targets are finished by it);
+// one with more in-edges than its cap is cut into cap-sized tiles and a
+// remainder, which get consecutive slots. The cap is ecap, or with share_div
+// 1/share_div of the in-edges of its group of group_parts partitions (at
+// least 1,024; under ecap when max_edges is given). The launch order sorts
+// the tiles within each group by work, largest first: a tile's in-edges
+// plus, for an unsplit partition, about two in-edges' worth per target for
+// finishing them.
+struct TileTable {
+  std::vector<uint32_t> tp, te, ts, sp, ss, order;  // te and ss carry one closing entry
+  uint32_t slots = 0;
+};
+
+TileTable tile_table(const uint32_t* pstart, uint64_t n_part, uint64_t TW, uint64_t ecap, uint64_t max_edges,
+                     uint64_t group_parts, uint32_t share_div) {
+  TileTable X;
+  const uint64_t gp = group_parts ? group_parts : n_part;
+  uint64_t gcap = ecap;  // the cap of the current group
+  for (uint64_t p = 0; p < n_part; ++p) {
+    if (share_div && p % gp == 0) {
+      const uint64_t g1 = std::min<uint64_t>(n_part, p + gp);
+      gcap = std::max<uint64_t>(1024, (pstart[g1] - pstart[p]) / share_div);
+      if (max_edges) gcap = std::min(gcap, ecap);
+    }
+    const uint64_t a = pstart[p], b = pstart[p + 1];
+    const uint64_t nt = std::max<uint64_t>(1, (b - a + gcap - 1) / gcap);
+    if (nt > 1) {
+      X.sp.push_back((uint32_t)p);
+      X.ss.push_back(X.slots);
+    }
+    for (uint64_t k = 0; k < nt; ++k) {
+      X.tp.push_back((uint32_t)p);
+      X.te.push_back((uint32_t)(a + k * gcap));
+      X.ts.push_back(nt > 1 ? X.slots++ : 0xFFFFFFFFu);
+    }
+  }
+  X.te.push_back(pstart[n_part]);
+  X.ss.push_back(X.slots);
+  const uint32_t n_tiles = (uint32_t)X.tp.size();
+  X.order.resize(n_tiles);
+  for (uint32_t i = 0; i < n_tiles; ++i) X.order[i] = i;
+  auto work = [&](uint32_t x) {
+    return (uint64_t)(X.te[x + 1] - X.te[x]) + (X.ts[x] == 0xFFFFFFFFu ? 2 * TW : 0);
+  };
+  for (uint32_t b = 0; b < n_tiles;) {
+    uint32_t e = b;
+    while (e < n_tiles && X.tp[e] / gp == X.tp[b] / gp) ++e;
+    std::stable_sort(X.order.begin() + b, X.order.begin() + e,
+                     [&](uint32_t x, uint32_t y) { return work(x) > work(y); });
+    b = e;
+  }
+  return X;
+}
+
 }  // namespace
 
 void tile_free(TileGraph& t) {
@@ -223,35 +279,14 @@ daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uin
   k0 = k1 = nullptr;
   v0 = v1 = nullptr;
   tmp = nullptr;
-  // tiles: every partition has at least one (its targets are finished by
-  // it); a partition with more than ecap in-edges gets consecutive slots
-  std::vector<uint32_t> tp, te, ts, sp, ss;
-  uint32_t slots = 0;
-  const uint64_t gp = group_parts ? group_parts : T.n_part;
-  uint64_t gcap = ecap;  // the cap of the current group
-  for (uint64_t p = 0; p < T.n_part; ++p) {
-    if (share_div && p % gp == 0) {  // 1/share_div of the group's in-edges, under max_edges if given
-      const uint64_t g1 = std::min<uint64_t>(T.n_part, p + gp);
-      gcap = std::max<uint64_t>(1024, (pstart[g1] - pstart[p]) / share_div);
-      if (max_edges) gcap = std::min(gcap, ecap);
-    }
-    const uint64_t a = pstart[p], b = pstart[p + 1];
-    const uint64_t nt = std::max<uint64_t>(1, (b - a + gcap - 1) / gcap);
-    if (nt > 1) {
-      sp.push_back((uint32_t)p);
-      ss.push_back(slots);
-    }
-    for (uint64_t k = 0; k < nt; ++k) {
-      tp.push_back((uint32_t)p);
-      te.push_back((uint32_t)(a + k * gcap));
-      ts.push_back(nt > 1 ? slots++ : 0xFFFFFFFFu);
-    }
-  }
-  te.push_back((uint32_t)m);
-  ss.push_back(slots);
+  // the tile table and its launch order: largest tiles first, so that the
+  // last workgroups of a round are small ones and its tail is short (RMAT-24
+  // pull 0.758 -> 0.692 ms); sweeps sort within each block
+  const TileTable X = tile_table(pstart.data(), T.n_part, TW, ecap, max_edges, group_parts, share_div);
+  const std::vector<uint32_t>&tp = X.tp, &te = X.te, &ts = X.ts, &sp = X.sp, &ss = X.ss, &order = X.order;
   T.n_tiles = tp.size();
   T.n_split = sp.size();
-  T.n_slots = slots;
+  T.n_slots = X.slots;
   TCHK(hipMalloc(&T.tile_part, tp.size() * 4));
   TCHK(hipMalloc(&T.tile_e, te.size() * 4));
   TCHK(hipMalloc(&T.tile_slot, ts.size() * 4));
@@ -262,19 +297,6 @@ daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uin
   TCHK(hipMemcpy(T.tile_slot, ts.data(), ts.size() * 4, hipMemcpyHostToDevice));
   if (!sp.empty()) TCHK(hipMemcpy(T.split_part, sp.data(), sp.size() * 4, hipMemcpyHostToDevice));
   TCHK(hipMemcpy(T.split_slot, ss.data(), ss.size() * 4, hipMemcpyHostToDevice));
-  // largest tiles first, so that the last workgroups of a round are small
-  // ones and its tail is short (RMAT-24 pull 0.758 -> 0.692 ms): the work of
-  // a tile is its in-edges plus, for an unsplit partition, finishing its
-  // targets (about two in-edges' worth each); sweeps sort within each block
-  std::vector<uint32_t> order(T.n_tiles);
-  for (uint32_t i = 0; i < T.n_tiles; ++i) order[i] = i;
-  auto work = [&](uint32_t x) { return (uint64_t)(te[x + 1] - te[x]) + (ts[x] == 0xFFFFFFFFu ? 2 * TW : 0); };
-  for (uint32_t b = 0; b < T.n_tiles;) {
-    uint32_t e = b;
-    while (e < T.n_tiles && tp[e] / gp == tp[b] / gp) ++e;
-    std::stable_sort(order.begin() + b, order.begin() + e, [&](uint32_t x, uint32_t y) { return work(x) > work(y); });
-    b = e;
-  }
   TCHK(hipMalloc(&T.tile_order, order.size() * 4));
   TCHK(hipMemcpy(T.tile_order, order.data(), order.size() * 4, hipMemcpyHostToDevice));
 #undef TCHK
@@ -283,3 +305,30 @@ daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uin
 }
 
 }  // namespace daic
+
+extern "C" daic_status daic_tile_table(const uint32_t* pstart, uint64_t n_part, uint32_t lb, uint64_t max_edges,
+                                       uint64_t group_parts, uint32_t share_div, uint64_t cap, uint32_t* tile_part,
+                                       uint32_t* tile_e, uint32_t* tile_slot, uint32_t* order, uint64_t* n_tiles,
+                                       uint64_t* n_split, uint64_t* n_slots) {
+  using namespace daic;
+  if (!pstart || !n_tiles || !n_split || !n_slots) return fail(DAIC_E_INVALID, "null argument");
+  if (n_part == 0) return fail(DAIC_E_INVALID, "n_part must be at least 1");
+  if (lb < 8 || lb > 14) return fail(DAIC_E_INVALID, "partition width 2^%u outside 2^8..2^14", lb);
+  if (!max_edges && !share_div) return fail(DAIC_E_INVALID, "give max_edges or share_div");
+  for (uint64_t p = 0; p < n_part; ++p)
+    if (pstart[p + 1] < pstart[p]) return fail(DAIC_E_INVALID, "pstart decreases at %llu", (unsigned long long)p);
+  if (pstart[n_part] > 0x7FFFFFFFu) return fail(DAIC_E_INVALID, "at most 2^31 - 1 in-edges");
+  const uint64_t ecap = max_edges ? std::max<uint64_t>(1024, max_edges) : ~0ull;
+  const TileTable X = tile_table(pstart, n_part, 1ull << lb, ecap, max_edges, group_parts, share_div);
+  *n_tiles = X.tp.size();
+  *n_split = X.sp.size();
+  *n_slots = X.slots;
+  if (cap < X.tp.size() + 1) return fail(DAIC_E_INVALID, "output capacity %llu below n_tiles + 1 = %llu",
+                                         (unsigned long long)cap, (unsigned long long)(X.tp.size() + 1));
+  if (!tile_part || !tile_e || !tile_slot || !order) return fail(DAIC_E_INVALID, "null output array");
+  std::copy(X.tp.begin(), X.tp.end(), tile_part);
+  std::copy(X.te.begin(), X.te.end(), tile_e);
+  std::copy(X.ts.begin(), X.ts.end(), tile_slot);
+  std::copy(X.order.begin(), X.order.end(), order);
+  return DAIC_OK;
+}

@@ -121,6 +121,9 @@ def lib():
         L.daic_sched_destroy.restype = None
         L.daic_mlp_forward.argtypes = [_vp, _vp, ctypes.c_uint64, _vp]
         L.daic_sched_score.argtypes = [_vp, _vp, _vp]
+        _u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.daic_tile_table.argtypes = [_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, _vp, _vp, _u64p, _u64p, _u64p]
         L.daic_mlp_grad.argtypes = [_vp, _vp, _vp, ctypes.c_uint64, _vp,
                                     ctypes.POINTER(ctypes.c_double)]
         L.daic_trace_record.argtypes = [_vp, ctypes.POINTER(RunOpts), ctypes.c_uint32,
@@ -656,6 +659,23 @@ def sched_train(traces, model: SchedModel, epochs=10, batch=65536, lr=1e-3, seed
     check(lib().daic_sched_train(arr, len(traces), ctypes.byref(o), model.handle, ctypes.byref(st)),
           "daic_sched_train")
     return {k: getattr(st, k) for k, _ in TrainStats._fields_}
+
+
+def tile_table(pstart, lb, max_edges=0, group_parts=0, share_div=0) -> dict:
+    """Host-only tile table of a partitioned in-edge order (daic_tile_table)."""
+    ps = np.ascontiguousarray(pstart, dtype=np.uint32)
+    n_part = ps.size - 1
+    cnt = [ctypes.c_uint64(0) for _ in range(3)]
+    args = (_addr(ps), n_part, lb, max_edges, group_parts, share_div)
+    rc = lib().daic_tile_table(*args, 0, None, None, None, None, *[ctypes.byref(c) for c in cnt])
+    if rc != 0 and cnt[0].value == 0:
+        check(rc, "daic_tile_table")
+    nt = cnt[0].value
+    tp, te, ts, order = (np.zeros(nt + 1, dtype=np.uint32) for _ in range(4))
+    check(lib().daic_tile_table(*args, nt + 1, _addr(tp), _addr(te), _addr(ts), _addr(order),
+                                *[ctypes.byref(c) for c in cnt]), "daic_tile_table")
+    return {"tile_part": tp[:nt], "tile_e": te, "tile_slot": ts[:nt], "order": order[:nt],
+            "n_split": cnt[1].value, "n_slots": cnt[2].value}
 
 
 def select_frontier_noalloc(op, state, v, dv, sel_out, tau_out=None, round_no=0, **kw):
