@@ -195,7 +195,8 @@ daic_status daic_problem_set_init_device(daic_problem* p, const void* d_v0, cons
  * pull for sum problems and pushes for min/max; DAIC_TILE_EDGES and
  * DAIC_TILE_BITS, read when a graph's tiles are built, set the in-edges per
  * tile and the partition width 2^bits; the sweep schedule's tiles take
- * DAIC_SWEEP_TILE_EDGES and DAIC_SWEEP_TILE_BITS). Every form
+ * DAIC_SWEEP_TILE_EDGES, DAIC_SWEEP_TILE_BITS and DAIC_SWEEP_TILE_SHARE,
+ * the divisor of a block's in-edges that sizes its tiles). Every form
  * ends in the same state after the same rounds (min/max bit for bit, sums up
  * to the order of their FP additions). */
 daic_status daic_run(daic_problem* p, const daic_run_opts* opts, daic_stats* stats);
@@ -283,7 +284,8 @@ daic_status daic_select_frontier_noalloc(daic_op op, daic_dtype state, uint64_t 
  * receiver's continuation probability folded into w); state DAIC_F32 or
  * F32_KAHAN.
  * The graphs are copied into one block-diagonal graph; they may be destroyed
- * after the call.                                                           */
+ * after the call. Dense rounds pull targets of in-degree above a threshold
+ * (env DAIC_HUB_DEG, read here) in chunks of in-edges of their own.        */
 daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs,
                               const uint32_t* rhs_per_graph, daic_op op, daic_g gk, double alpha,
                               daic_dtype state, daic_batch** out);
