@@ -285,7 +285,7 @@ daic_status daic_select_frontier_noalloc(daic_op op, daic_dtype state, uint64_t 
  * F32_KAHAN.
  * The graphs are copied into one block-diagonal graph; they may be destroyed
  * after the call. Dense rounds pull targets of in-degree above a threshold
- * (env DAIC_HUB_DEG, read here) in chunks of in-edges of their own.        */
+ * (64; env DAIC_HUB_DEG, read here) in chunks of in-edges of their own.        */
 daic_status daic_batch_create(uint32_t n_graphs, const daic_graph* const* graphs,
                               const uint32_t* rhs_per_graph, daic_op op, daic_g gk, double alpha,
                               daic_dtype state, daic_batch** out);
