@@ -180,8 +180,18 @@ struct TileGraph {
                                    // targets an unsplit tile finishes), within groups of partitions
   uint32_t* split_part = nullptr;  // [n_split] partitions of several tiles
   uint32_t* split_slot = nullptr;  // [n_split + 1] their first slot (slots of one partition are consecutive)
+  // Targets numbered by in-degree, highest first (the layout of fused dense
+  // rounds): a partition then holds targets of similar in-degree, so the hub
+  // partitions take the senders' in-edges in long pairs (RMAT-20: 31 % fewer
+  // pairs than id ranges with partitions of 2^10). Null for partitions of
+  // consecutive ids. The fused rounds keep the state in this numbering.
+  uint32_t* tinv = nullptr;        // [n] vertex of each target number
+  uint32_t* rowP = nullptr;        // [n + 1] out-edge offsets in target-number order
+  uint32_t* permP = nullptr;       // [n] source number of the vertex of each target number
 };
 daic_status tile_prepare(daic_graph* g, hipStream_t s);
+// The same form with targets numbered by in-degree (g->tile_r).
+daic_status tile_prepare_ranked(daic_graph* g, hipStream_t s);
 // Entries of the per-in-edge arrays in tile order with their padding.
 inline uint64_t tile_padded_edges(const TileGraph& T) { return (T.n_seg + kTilePadSeg) * 64; }
 // The tiled kernels index in-edges (with the padding) in 32 bits; larger
@@ -193,9 +203,11 @@ inline bool tile_fits(uint64_t m) { return m + 64ull * (kTilePadSeg + 1) <= 0xFF
 // tile_default_edges); with share_div nonzero, of at most 1/share_div of
 // their group's in-edges (and max_edges when nonzero), into T; tile_order
 // sorts the tiles within each group of group_parts consecutive partitions
-// (all of them when 0); tile_free releases it.
+// (all of them when 0); with trank (a device array, or null for target
+// ids), targets are placed by trank[t] instead of t; tile_free releases it.
 daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uint64_t max_edges,
-                       uint64_t group_parts, uint32_t share_div, TileGraph& T, hipStream_t s);
+                       uint64_t group_parts, uint32_t share_div, TileGraph& T, hipStream_t s,
+                       const uint32_t* trank = nullptr);
 void tile_free(TileGraph& T);
 uint32_t tile_default_bits(uint64_t n);
 uint64_t tile_default_edges(uint64_t n, uint64_t m, uint32_t lb);
@@ -206,6 +218,7 @@ struct daic_graph {
   daic::GraphDev dev;
   daic::PullGraph pull;
   daic::TileGraph tile;
+  daic::TileGraph tile_r;       // targets numbered by in-degree (fused dense rounds)
   void* own_row = nullptr;      // owned allocations (null when borrowed)
   void* own_col = nullptr;
   void* own_w = nullptr;

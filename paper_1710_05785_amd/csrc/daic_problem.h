@@ -69,6 +69,17 @@ struct daic_problem {
   double* spart_r = nullptr;
   uint64_t* spart_a = nullptr;
   uint64_t* spart_p = nullptr;
+  // fused dense rounds over the tiles of in-degree-numbered targets: while
+  // they run (from the priming claim to the end of the run) v, dv and c live
+  // in target-number order in these arrays
+  bool ranked_ready = false;
+  bool ranked_active = false;
+  void* vP = nullptr;
+  void* dvP = nullptr;
+  float* cP = nullptr;
+  void* alphaP = nullptr;        // per-vertex alpha in target-number order (when given)
+  double* tile_pbuf_r = nullptr; // partial-sum slots of their split partitions
+  void* tile_wr = nullptr;       // weights in their tile order (EDGE_SCALE)
   uint32_t tile_grid = 2048;     // workgroups of k_tile_pull (at most)
   uint32_t tfin_grid = 4096;     // workgroups of k_tile_finish (at most)
   uint64_t k_sel = 0;      // dense-round rule of the current run (see k_residual)

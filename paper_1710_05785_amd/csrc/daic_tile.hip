@@ -23,14 +23,17 @@ uint32_t tgrid(uint64_t count) {
 }
 
 // key = (partition << (sbits + lb)) | (rank << lb) | local target, value =
-// the edge, for every edge (rows walked by lane groups).
+// the edge, for every edge (rows walked by lane groups); targets placed by
+// their number trank[t] when given.
 __global__ __launch_bounds__(256) void k_tile_keys(const uint32_t* __restrict__ row, const uint32_t* __restrict__ col,
-                                                   const uint32_t* __restrict__ perm, uint64_t n, uint32_t sbits,
+                                                   const uint32_t* __restrict__ perm,
+                                                   const uint32_t* __restrict__ trank, uint64_t n, uint32_t sbits,
                                                    uint32_t lb, uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
   rows_by_groups<false>(
       row, n, [&](uint64_t, uint32_t e) { return col[e]; },
-      [&](uint64_t j, uint32_t e, uint64_t t) {
+      [&](uint64_t j, uint32_t e, uint64_t t0) {
+        const uint64_t t = trank ? trank[t0] : t0;
         const uint64_t rank = perm[j];
         keys[e] = ((t >> lb) << (sbits + lb)) | (rank << lb) | (t & ((1ull << lb) - 1));
         vals[e] = e;
@@ -127,16 +130,42 @@ TileTable tile_table(const uint32_t* pstart, uint64_t n_part, uint64_t TW, uint6
   return X;
 }
 
+// Sort keys of the in-degree numbering: in-degree descending, then id (the
+// radix sort is stable and the values start in id order).
+__global__ void k_indeg_keys(const uint32_t* rowT, uint64_t n, uint32_t* key, uint32_t* val) {
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x) {
+    key[j] = 0xFFFFFFFFu - (rowT[j + 1] - rowT[j]);
+    val[j] = (uint32_t)j;
+  }
+}
+
+// From the numbering's inverse tinv: the number of each vertex, and per
+// number its vertex's out-degree and source number.
+__global__ void k_rank_tables(const uint32_t* tinv, const uint32_t* row, const uint32_t* perm, uint64_t n,
+                              uint32_t* trank, uint32_t* degP, uint32_t* permP) {
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = tinv[r];
+    trank[j] = (uint32_t)r;
+    degP[r] = row[j + 1] - row[j];
+    permP[r] = perm[j];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) degP[n] = 0;
+}
+
 }  // namespace
 
 void tile_free(TileGraph& t) {
   for (void* q : {(void*)t.tloc, (void*)t.psrc, (void*)t.segpair, (void*)t.eid, (void*)t.tile_part, (void*)t.tile_e,
-                  (void*)t.tile_slot, (void*)t.tile_order, (void*)t.split_part, (void*)t.split_slot})
+                  (void*)t.tile_slot, (void*)t.tile_order, (void*)t.split_part, (void*)t.split_slot, (void*)t.tinv,
+                  (void*)t.rowP, (void*)t.permP})
     if (q) (void)hipFree(q);
   t = TileGraph();
 }
 
-void tile_release(daic_graph* g) { tile_free(g->tile); }
+void tile_release(daic_graph* g) {
+  tile_free(g->tile);
+  tile_free(g->tile_r);
+}
 
 // in-edges per tile by default: kTileE, or about two partitions' average for
 // smaller graphs (at least 16,384), so that hub partitions split into tiles
@@ -154,9 +183,84 @@ uint32_t tile_default_bits(uint64_t n) {
   return lb;
 }
 
+static void tile_shape(const daic_graph* g, uint32_t* lb_out, uint64_t* max_edges_out);
+
 daic_status tile_prepare(daic_graph* g, hipStream_t s) {
   if (g->tile.ready) return DAIC_OK;
   if (!g->pull.ready) return fail(DAIC_E_INVALID, "tiled rounds need the renumbering of the in-edge form");
+  uint32_t lb;
+  uint64_t max_edges;
+  tile_shape(g, &lb, &max_edges);
+  return tile_build(g->dev, g->pull.perm, lb, max_edges, 0, 0, g->tile, s);
+}
+
+daic_status tile_prepare_ranked(daic_graph* g, hipStream_t s) {
+  TileGraph& T = g->tile_r;
+  if (T.ready) return DAIC_OK;
+  if (!g->pull.ready) return fail(DAIC_E_INVALID, "tiled rounds need the renumbering of the in-edge form");
+  const uint64_t n = g->dev.n;
+  uint32_t *key0 = nullptr, *key1 = nullptr, *val0 = nullptr, *val1 = nullptr, *trank = nullptr, *degP = nullptr;
+  uint32_t *tinv = nullptr, *rowP = nullptr, *permP = nullptr;
+  void* tmp = nullptr;
+  auto release = [&](bool all) {
+    for (void* q : {(void*)key0, (void*)key1, (void*)val0, (void*)val1, (void*)trank, (void*)degP, tmp})
+      if (q) (void)hipFree(q);
+    if (all)
+      for (void* q : {(void*)tinv, (void*)rowP, (void*)permP})
+        if (q) (void)hipFree(q);
+  };
+#define RCHK(call)                                                                                          \
+  do {                                                                                                      \
+    hipError_t _e = (call);                                                                                 \
+    if (_e != hipSuccess) {                                                                                 \
+      release(true);                                                                                        \
+      return fail(_e == hipErrorOutOfMemory ? DAIC_E_OOM : DAIC_E_DEVICE, "ranked tiles: %s: %s", #call,   \
+                  hipGetErrorString(_e));                                                                   \
+    }                                                                                                       \
+  } while (0)
+  const uint64_t nn = std::max<uint64_t>(n, 1);
+  RCHK(hipMalloc(&key0, nn * 4));
+  RCHK(hipMalloc(&key1, nn * 4));
+  RCHK(hipMalloc(&val0, nn * 4));
+  RCHK(hipMalloc(&val1, nn * 4));
+  RCHK(hipMalloc(&trank, nn * 4));
+  RCHK(hipMalloc(&degP, (n + 1) * 4));
+  RCHK(hipMalloc(&rowP, (n + 1) * 4));
+  RCHK(hipMalloc(&permP, nn * 4));
+  hipLaunchKernelGGL(k_indeg_keys, dim3(tgrid(n)), dim3(256), 0, s, static_cast<const uint32_t*>(g->pull.rowT), n,
+                     key0, val0);
+  hipcub::DoubleBuffer<uint32_t> kb(key0, key1), vb(val0, val1);
+  size_t need = 0, need2 = 0;
+  RCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kb, vb, (int)n, 0, 32, s));
+  RCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, need2, degP, rowP, (int)(n + 1), s));
+  RCHK(hipMalloc(&tmp, std::max<size_t>(std::max(need, need2), 1)));
+  RCHK(hipcub::DeviceRadixSort::SortPairs(tmp, need, kb, vb, (int)n, 0, 32, s));
+  // the sorted values are the numbering's inverse; keep that buffer
+  tinv = vb.Current();
+  if (tinv == val0) val0 = nullptr;
+  else val1 = nullptr;
+  hipLaunchKernelGGL(k_rank_tables, dim3(tgrid(n)), dim3(256), 0, s, tinv, static_cast<const uint32_t*>(g->dev.row),
+                     g->pull.perm, n, trank, degP, permP);
+  RCHK(hipcub::DeviceScan::ExclusiveSum(tmp, need2, degP, rowP, (int)(n + 1), s));
+  RCHK(hipStreamSynchronize(s));
+  uint32_t lb;
+  uint64_t max_edges;
+  tile_shape(g, &lb, &max_edges);
+  const daic_status rc = tile_build(g->dev, g->pull.perm, lb, max_edges, 0, 0, T, s, trank);
+  if (rc) {
+    release(true);
+    return rc;
+  }
+  release(false);
+  T.tinv = tinv;
+  T.rowP = rowP;
+  T.permP = permP;
+  return DAIC_OK;
+#undef RCHK
+}
+
+// Partition width and tile size of dense rounds on g.
+static void tile_shape(const daic_graph* g, uint32_t* lb_out, uint64_t* max_edges_out) {
   // tiles of up to one resident workgroup's share of the in-edges (at least
   // the default size): with the largest launched first, the few big tiles of
   // the hub partitions run beside the many whole partitions, and a round has
@@ -177,11 +281,13 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
   if (const char* e = std::getenv("DAIC_TILE_BITS")) lb = (uint32_t)std::max(8ul, std::min(14ul, std::strtoul(e, nullptr, 10)));
   uint64_t max_edges = std::max<uint64_t>(tile_default_edges(n, m, lb), m / ((uint64_t)std::max(cus, 1) * tile_wgs_per_cu(lb)));
   if (const char* e = std::getenv("DAIC_TILE_EDGES")) max_edges = std::strtoull(e, nullptr, 10);
-  return tile_build(g->dev, g->pull.perm, lb, max_edges, 0, 0, g->tile, s);
+  *lb_out = lb;
+  *max_edges_out = max_edges;
 }
 
 daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uint64_t max_edges,
-                       uint64_t group_parts, uint32_t share_div, TileGraph& T, hipStream_t s) {
+                       uint64_t group_parts, uint32_t share_div, TileGraph& T, hipStream_t s,
+                       const uint32_t* trank) {
   if (T.ready) return DAIC_OK;
   if (lb < 8 || lb > 14) return fail(DAIC_E_INVALID, "partition width 2^%u outside 2^8..2^14", lb);
   const uint64_t n = d.n, m = d.m;
@@ -233,7 +339,7 @@ daic_status tile_build(const GraphDev& d, const uint32_t* perm, uint32_t lb, uin
     TCHK(hipMalloc(&v0, m * sizeof(uint32_t)));
     TCHK(hipMalloc(&v1, m * sizeof(uint32_t)));
     hipLaunchKernelGGL(k_tile_keys, dim3(std::max<uint64_t>(1, std::min<uint64_t>((n + 3) / 4, 8192))), dim3(256), 0,
-                       s, row, d.col, perm, n, sbits, lb, k0, v0);
+                       s, row, d.col, perm, trank, n, sbits, lb, k0, v0);
     hipcub::DoubleBuffer<uint64_t> kb(k0, k1);
     hipcub::DoubleBuffer<uint32_t> vb(v0, v1);
     size_t need = 0;
