@@ -116,6 +116,69 @@ def test_pagerank_rmat_f64_and_kahan(daic, scale, ef, seed):
     assert np.abs(pk.get() - ref).sum() / ref.sum() <= 1e-5
 
 
+@pytest.mark.parametrize("state,gk", [("f32_kahan", "deg"), ("f64", "edge_pv"), ("f32", "edge")])
+def test_ranked_tiles_match_id_tiles(daic, monkeypatch, state, gk):
+    """Fused dense rounds walk tiles whose targets are numbered by in-degree,
+    with v, dv (and the Kahan term) moved into that order while they run.
+    Against the same rounds over partitions of consecutive ids: the same
+    round, update and message counts and the same state to rounding, after a
+    stop by the round limit (the state must be back in vertex order), after
+    resuming from it, and at convergence, which the oracle's FP64 iteration
+    checks. RMAT-16 with edge factor 16: its hub partition is cut into
+    several tiles."""
+    say("case ranked vs id tiles", state, gk)
+    monkeypatch.delenv("DAIC_NO_TILE", raising=False)
+    g = daic_gen.rmat(16, 16, seed=43)
+    rng = np.random.default_rng(44)
+    n = g.n
+    outdeg = np.diff(g.row_ptr).astype(np.float64)
+    src = np.repeat(np.arange(n), np.diff(g.row_ptr).astype(np.int64))
+    w = a_pv = None
+    if gk != "deg":
+        w = rng.uniform(0.1, 1.0, g.m) / np.maximum(outdeg[src], 1.0)
+        w = w.astype(np.float64 if state == "f64" else np.float32)
+    if gk == "edge_pv":
+        a_pv = rng.uniform(0.5, 0.9, n)
+    alpha = 0.85
+    dv1 = rng.uniform(0.0, 0.3, n)
+
+    def make():
+        G = daic.Graph(g.row_ptr, g.col, w)
+        kwp = dict(alpha_pv=a_pv) if a_pv is not None else dict(alpha=alpha)
+        P = daic.Problem(G, daic.SUM, daic.G_DEG_SCALE if gk == "deg" else daic.G_EDGE_SCALE, state=state, **kwp)
+        P.set_init(np.zeros(n), dv1)
+        return P
+
+    eps = 1e-10 if state == "f64" else 1e-5
+    kw = dict(eps=eps, q=1.0, sched="all", rounds_per_check=4)
+    runs = {}
+    for order in ("id", "ranked"):
+        if order == "id":
+            monkeypatch.setenv("DAIC_TILE_ID_ORDER", "1")
+        else:
+            monkeypatch.delenv("DAIC_TILE_ID_ORDER", raising=False)
+        P = make()
+        r1 = P.run(max_rounds=6, **kw)
+        s1 = P.get(with_dv=True)
+        r2 = P.run(**kw)  # resumes from the stopped state
+        runs[order] = (r1, s1, r2, P.get(with_dv=True))
+    (a1, sa1, a2, sa2), (b1, sb1, b2, sb2) = runs["id"], runs["ranked"]
+    for x, y in ((a1, b1), (a2, b2)):
+        for k in ("rounds", "activations", "pushed_edges"):
+            assert x.stats[k] == y.stats[k], (k, x.stats, y.stats)
+    assert not b1.converged and b2.converged
+    tol = 1e-12 if state == "f64" else 2e-6
+    for (va, dva), (vb, dvb) in ((sa1, sb1), (sa2, sb2)):
+        scale = np.abs(va).sum()
+        assert np.abs(vb - va).sum() <= tol * scale
+        assert np.abs(dvb - dva).sum() <= tol * max(scale, 1.0)
+    d = alpha if a_pv is None else 0.0
+    ref, _, _ = oracle.jacobi_sum(g, oracle.G_EDGE_SCALE if gk != "deg" else oracle.G_DEG_SCALE, d, dv1,
+                                  w=w.astype(np.float64) if w is not None else None, alpha_pv=a_pv, eps=1e-13)
+    vb = sb2[0]
+    assert np.abs(vb - ref).sum() <= (1e-9 if state == "f64" else 1e-5) * np.abs(ref).sum()
+
+
 @pytest.mark.parametrize("tiled", [True, False])
 @pytest.mark.parametrize("state,gk", [("f32_kahan", "deg"), ("f64", "deg"), ("f32", "edge")])
 def test_fused_dense_rounds_match_plain_rounds(daic, monkeypatch, state, gk, tiled):
