@@ -1258,8 +1258,9 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
     // tile_finish: the slots read back per target and tile, and the finish of
     // those targets. The finish of a
     // target: dv read and write 2S, v read and write 2S (+ Kahan term 8),
-    // out-edge offsets 2R, renumbering 4, base written S.
-    const TileGraph& T = p->g->tile;
+    // out-edge offsets 2R, renumbering 4, base written S. Fused rounds walk
+    // the layout with targets numbered by in-degree when it is built.
+    const TileGraph& T = ranked_on(p) ? p->g->tile_r : p->g->tile;
     const double kahan = p->st == ST_F32K ? 8.0 : 0.0;
     const double fin = 2.0 * S + 2.0 * S + kahan + 2.0 * R + 4.0 + S;
     const double tw = (double)(1ull << T.tbits);
