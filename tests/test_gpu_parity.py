@@ -177,6 +177,14 @@ def test_ranked_tiles_match_id_tiles(daic, monkeypatch, state, gk):
                                   w=w.astype(np.float64) if w is not None else None, alpha_pv=a_pv, eps=1e-13)
     vb = sb2[0]
     assert np.abs(vb - ref).sum() <= (1e-9 if state == "f64" else 1e-5) * np.abs(ref).sum()
+    # daic_profile runs the fused rounds eagerly and must hand the state back
+    # in vertex order too
+    P = make()
+    rp, _ = P.profile(**kw)
+    vp, dvp = P.get(with_dv=True)
+    assert rp.stats["rounds"] == a2.stats["rounds"] + a1.stats["rounds"]
+    assert np.abs(vp - vb).sum() <= tol * np.abs(vb).sum()
+    assert np.abs(dvp - sb2[1]).sum() <= tol * max(np.abs(vb).sum(), 1.0)
 
 
 @pytest.mark.parametrize("tiled", [True, False])
