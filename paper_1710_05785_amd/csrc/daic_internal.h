@@ -180,17 +180,18 @@ struct TileGraph {
                                    // targets an unsplit tile finishes), within groups of partitions
   uint32_t* split_part = nullptr;  // [n_split] partitions of several tiles
   uint32_t* split_slot = nullptr;  // [n_split + 1] their first slot (slots of one partition are consecutive)
-  // Targets numbered by in-degree, highest first (the layout of fused dense
-  // rounds): a partition then holds targets of similar in-degree, so the hub
-  // partitions take the senders' in-edges in long pairs (RMAT-20: 31 % fewer
-  // pairs than id ranges with partitions of 2^10). Null for partitions of
-  // consecutive ids. The fused rounds keep the state in this numbering.
+  // Targets numbered by in-degree octave, highest first, ids ascending within
+  // an octave (the layout of fused dense rounds): a partition then holds
+  // targets of similar in-degree and nearby ids, so the hub partitions take
+  // the senders' in-edges in long pairs (RMAT-24: 72 M pairs instead of 123 M
+  // with id ranges). Null for partitions of consecutive ids. The fused rounds
+  // keep the state in this numbering.
   uint32_t* tinv = nullptr;        // [n] vertex of each target number
   uint32_t* rowP = nullptr;        // [n + 1] out-edge offsets in target-number order
   uint32_t* permP = nullptr;       // [n] source number of the vertex of each target number
 };
 daic_status tile_prepare(daic_graph* g, hipStream_t s);
-// The same form with targets numbered by in-degree (g->tile_r).
+// The same form with targets numbered by in-degree octave (g->tile_r).
 daic_status tile_prepare_ranked(daic_graph* g, hipStream_t s);
 // Entries of the per-in-edge arrays in tile order with their padding.
 inline uint64_t tile_padded_edges(const TileGraph& T) { return (T.n_seg + kTilePadSeg) * 64; }
@@ -218,7 +219,7 @@ struct daic_graph {
   daic::GraphDev dev;
   daic::PullGraph pull;
   daic::TileGraph tile;
-  daic::TileGraph tile_r;       // targets numbered by in-degree (fused dense rounds)
+  daic::TileGraph tile_r;       // targets numbered by in-degree octave (fused dense rounds)
   void* own_row = nullptr;      // owned allocations (null when borrowed)
   void* own_col = nullptr;
   void* own_w = nullptr;

@@ -108,8 +108,8 @@ namespace daic {
 
 static uint32_t push_grid() { return 256 * 16; }
 
-// Per-vertex arrays through the in-degree numbering of targets: dst[r] =
-// src[tinv[r]] (gather) or dst[tinv[r]] = src[r] (scatter).
+// Per-vertex arrays through the numbering of targets by in-degree octave:
+// dst[r] = src[tinv[r]] (gather) or dst[tinv[r]] = src[r] (scatter).
 template <typename T, bool GATHER>
 __global__ void k_perm_copy(const T* __restrict__ src, const uint32_t* __restrict__ tinv, uint64_t n,
                             T* __restrict__ dst) {
@@ -282,7 +282,7 @@ struct Impl {
     }
   }
 
-  // ranked: the layout of fused rounds with targets numbered by in-degree
+  // ranked: the layout of fused rounds with targets numbered by in-degree octave
   static TileArgs tile_args(const daic_problem* p, bool ranked = false) {
     const TileGraph& T = ranked ? p->g->tile_r : p->g->tile;
     TileArgs t{};
@@ -637,9 +637,9 @@ daic_status dense_rounds_setup(daic_problem* p, const daic_run_opts* o, hipStrea
     }
   }
   // fused rounds (every pending vertex, sum problems) walk tiles whose
-  // targets are numbered by in-degree, with the state moved into that order
-  // while they run (RMAT-24 dense round 0.667 -> 0.581 ms, solve 81.0 ->
-  // 70.8 ms); DAIC_TILE_ID_ORDER=1 keeps them on the id-ordered tiles
+  // targets are numbered by in-degree octave, with the state moved into that
+  // order while they run (RMAT-24 dense round 0.667 -> 0.52 ms, solve 81.0 ->
+  // 63.1 ms); DAIC_TILE_ID_ORDER=1 keeps them on the id-ordered tiles
   if (sum && p->tile_ready && !p->ranked_ready && o->sched == DAIC_SCHED_ALL && !std::getenv("DAIC_TILE_ID_ORDER")) {
     daic_graph* g = const_cast<daic_graph*>(p->g);
     daic_status rc = tile_prepare_ranked(g, s);
@@ -1259,7 +1259,7 @@ static double kernel_bytes(const daic_problem* p, const char* name, const Ctl& c
     // those targets. The finish of a
     // target: dv read and write 2S, v read and write 2S (+ Kahan term 8),
     // out-edge offsets 2R, renumbering 4, base written S. Fused rounds walk
-    // the layout with targets numbered by in-degree when it is built.
+    // the layout with targets numbered by in-degree octave when it is built.
     const TileGraph& T = ranked_on(p) ? p->g->tile_r : p->g->tile;
     const double kahan = p->st == ST_F32K ? 8.0 : 0.0;
     const double fin = 2.0 * S + 2.0 * S + kahan + 2.0 * R + 4.0 + S;

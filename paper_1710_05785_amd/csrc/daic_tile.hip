@@ -130,11 +130,15 @@ TileTable tile_table(const uint32_t* pstart, uint64_t n_part, uint64_t TW, uint6
   return X;
 }
 
-// Sort keys of the in-degree numbering: in-degree descending, then id (the
-// radix sort is stable and the values start in id order).
+// Sort keys of the target numbering: the in-degree's octave, highest first
+// (the leading zeros of in-degree + 1), then id (the radix sort is stable
+// and the values start in id order). On RMAT-24 octaves gave a 0.49 ms pull,
+// exact in-degrees 0.55 ms (as many pairs, but the id order inside an octave
+// keeps targets of nearby ids, which share senders, in one partition),
+// half-octaves 0.50 ms, quarter-range (powers of 4) 0.53 ms, ids alone 0.63 ms.
 __global__ void k_indeg_keys(const uint32_t* rowT, uint64_t n, uint32_t* key, uint32_t* val) {
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x) {
-    key[j] = 0xFFFFFFFFu - (rowT[j + 1] - rowT[j]);
+    key[j] = (uint32_t)__clz(rowT[j + 1] - rowT[j] + 1);
     val[j] = (uint32_t)j;
   }
 }
@@ -231,10 +235,10 @@ daic_status tile_prepare_ranked(daic_graph* g, hipStream_t s) {
                      key0, val0);
   hipcub::DoubleBuffer<uint32_t> kb(key0, key1), vb(val0, val1);
   size_t need = 0, need2 = 0;
-  RCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kb, vb, (int)n, 0, 32, s));
+  RCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kb, vb, (int)n, 0, 6, s));  // keys < 33
   RCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, need2, degP, rowP, (int)(n + 1), s));
   RCHK(hipMalloc(&tmp, std::max<size_t>(std::max(need, need2), 1)));
-  RCHK(hipcub::DeviceRadixSort::SortPairs(tmp, need, kb, vb, (int)n, 0, 32, s));
+  RCHK(hipcub::DeviceRadixSort::SortPairs(tmp, need, kb, vb, (int)n, 0, 6, s));
   // the sorted values are the numbering's inverse; keep that buffer
   tinv = vb.Current();
   if (tinv == val0) val0 = nullptr;

@@ -118,8 +118,9 @@ def test_pagerank_rmat_f64_and_kahan(daic, scale, ef, seed):
 
 @pytest.mark.parametrize("state,gk", [("f32_kahan", "deg"), ("f64", "edge_pv"), ("f32", "edge")])
 def test_ranked_tiles_match_id_tiles(daic, monkeypatch, state, gk):
-    """Fused dense rounds walk tiles whose targets are numbered by in-degree,
-    with v, dv (and the Kahan term) moved into that order while they run.
+    """Fused dense rounds walk tiles whose targets are numbered by in-degree
+    octave (highest first, ids ascending within an octave), with v, dv (and
+    the Kahan term) moved into that order while they run.
     Against the same rounds over partitions of consecutive ids: the same
     round, update and message counts and the same state to rounding, after a
     stop by the round limit (the state must be back in vertex order), after
