@@ -193,6 +193,16 @@ struct TileGraph {
 daic_status tile_prepare(daic_graph* g, hipStream_t s);
 // The same form with targets numbered by in-degree octave (g->tile_r).
 daic_status tile_prepare_ranked(daic_graph* g, hipStream_t s);
+// The numbering of targets by in-degree octave within blocks of `block`
+// consecutive ids (a block's targets keep its id range): trank (vertex ->
+// number) and, per number, its vertex (tinv), out-edge offsets (rowP, n + 1)
+// and source number perm[vertex] (permP); device arrays the caller frees.
+daic_status rank_targets(const daic_graph* g, const uint32_t* perm, uint64_t block, uint32_t** trank,
+                         uint32_t** tinv, uint32_t** rowP, uint32_t** permP, hipStream_t s);
+// dst[r] = src[tinv[r]] (gather) or dst[tinv[r]] = src[r] (scatter) for r < n,
+// elements of 4 or 8 bytes, enqueued on s.
+void perm_gather(const void* src, void* dst, size_t elem, const uint32_t* tinv, uint64_t n, hipStream_t s);
+void perm_scatter(const void* src, void* dst, size_t elem, const uint32_t* tinv, uint64_t n, hipStream_t s);
 // Entries of the per-in-edge arrays in tile order with their padding.
 inline uint64_t tile_padded_edges(const TileGraph& T) { return (T.n_seg + kTilePadSeg) * 64; }
 // The tiled kernels index in-edges (with the padding) in 32 bits; larger

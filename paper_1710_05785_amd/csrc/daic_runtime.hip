@@ -130,6 +130,13 @@ static void perm_copy(const void* src, void* dst, size_t elem, const uint32_t* t
                        tinv, n, static_cast<uint32_t*>(dst));
 }
 
+void perm_gather(const void* src, void* dst, size_t elem, const uint32_t* tinv, uint64_t n, hipStream_t s) {
+  perm_copy<true>(src, dst, elem, tinv, n, s);
+}
+void perm_scatter(const void* src, void* dst, size_t elem, const uint32_t* tinv, uint64_t n, hipStream_t s) {
+  perm_copy<false>(src, dst, elem, tinv, n, s);
+}
+
 // Fused rounds over the ranked tiles keep v, dv and c in target-number order:
 // they move there after the priming claim and back when the run ends.
 static void ranked_enter(daic_problem* p, hipStream_t s) {

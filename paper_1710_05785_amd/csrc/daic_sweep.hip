@@ -83,6 +83,12 @@ struct SweepState {
   std::vector<uint32_t> tile_off, split_off;  // [P+1]
   std::vector<void*> allocs;
   SweepArgs a{};
+  // targets numbered by in-degree octave within each block (the tiles'
+  // numbering): the block pulls take `ar`, whose state, out-edge offsets,
+  // sweep numbers (and per-vertex alpha) are in that order; the state moves
+  // there for the run's sweeps and back before the final delivery
+  bool numbered = false;
+  SweepArgs ar{};
 };
 
 namespace {
@@ -476,14 +482,15 @@ struct SweepImpl {
     if (w.tiles.ready) {  // the block's tiles, then its split partitions, each claiming its targets
       const uint32_t tb = w.tile_off[c], te = w.tile_off[c + 1], sb = w.split_off[c], se = w.split_off[c + 1];
       const uint32_t fg = se > sb ? sgrid((uint64_t)(se - sb) * (w.ta.tw / 256), 1, kSweepFinishGrid) : 0;
+      const SweepArgs& at = w.numbered ? w.ar : w.a;
       if (te > tb) {
         if (w.ta.tw > kNarrowTW)
-          hipLaunchKernelGGL((k_sweep_tile<ST, G, 1024>), dim3(te - tb), dim3(1024), 0, s, a, w.ta, c, tb, te);
+          hipLaunchKernelGGL((k_sweep_tile<ST, G, 1024>), dim3(te - tb), dim3(1024), 0, s, at, w.ta, c, tb, te);
         else
-          hipLaunchKernelGGL((k_sweep_tile<ST, G, 256>), dim3(te - tb), dim3(256), 0, s, a, w.ta, c, tb, te);
+          hipLaunchKernelGGL((k_sweep_tile<ST, G, 256>), dim3(te - tb), dim3(256), 0, s, at, w.ta, c, tb, te);
       }
       if (fg)
-        hipLaunchKernelGGL((k_sweep_tile_finish<ST, G>), dim3(fg), dim3(256), 0, s, a, w.ta, sb, se, te - tb);
+        hipLaunchKernelGGL((k_sweep_tile_finish<ST, G>), dim3(fg), dim3(256), 0, s, at, w.ta, sb, se, te - tb);
       nparts = (te - tb) + fg;
     } else {
       // one workgroup per edge block of block c, at most 16384
@@ -674,7 +681,22 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
     if (const char* e = std::getenv("DAIC_SWEEP_TILE_EDGES")) max_edges = std::strtoull(e, nullptr, 10);
     uint32_t share = (uint32_t)std::max(cus, 1) * tile_wgs_per_cu(lb);
     if (const char* e = std::getenv("DAIC_SWEEP_TILE_SHARE")) share = (uint32_t)std::strtoul(e, nullptr, 10);
-    if ((rc = tile_build(d, a.perm, lb, max_edges, B >> lb, share, w->tiles, s))) return rc;
+    // targets numbered by in-degree octave within each block, as for the
+    // fused rounds; DAIC_TILE_ID_ORDER=1 keeps id order
+    uint32_t *trank = nullptr, *tinv = nullptr, *rowP = nullptr, *permP = nullptr;
+    if (!std::getenv("DAIC_TILE_ID_ORDER") &&
+        (rc = rank_targets(p->g, a.perm, B, &trank, &tinv, &rowP, &permP, s)))
+      return rc;
+    rc = tile_build(d, a.perm, lb, max_edges, B >> lb, share, w->tiles, s, trank);
+    if (trank) (void)hipFree(trank);
+    if (rc) {
+      for (void* q : {(void*)tinv, (void*)rowP, (void*)permP})
+        if (q) (void)hipFree(q);
+      return rc;
+    }
+    w->tiles.tinv = tinv;
+    w->tiles.rowP = rowP;
+    w->tiles.permP = permP;
     const TileGraph& T = w->tiles;
     const uint64_t TW = 1ull << T.tbits;
     std::vector<uint32_t> tp(T.n_tiles), sp(T.n_split);
@@ -715,6 +737,21 @@ daic_status sweep_setup(daic_problem* p, uint64_t B, hipStream_t s) {
     void* pb = nullptr;
     if ((rc = grab(&pb, std::max<uint64_t>(T.n_slots, 1) * TW * 8))) return rc;
     t.pbuf = static_cast<double*>(pb);
+    if (T.tinv) {
+      SweepArgs& r = w->ar;
+      r = a;
+      void *vp = nullptr, *dvp = nullptr, *cp = nullptr, *ap = nullptr;
+      if ((rc = grab(&vp, n * S)) || (rc = grab(&dvp, n * S))) return rc;
+      if (a.c && (rc = grab(&cp, n * 4))) return rc;
+      if (a.alpha_pv && (rc = grab(&ap, n * S))) return rc;
+      r.v = vp;
+      r.dv = dvp;
+      r.c = static_cast<float*>(cp);
+      r.alpha_pv = ap;
+      r.row = T.rowP;
+      r.perm = T.permP;
+      w->numbered = true;
+    }
     if (p->gk == DAIC_G_EDGE_SCALE) {  // weights in the tiles' in-edge order
       void* wt = nullptr;
       const uint64_t pe = tile_padded_edges(T);
@@ -770,6 +807,20 @@ daic_status sweep_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats
   hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(1), 0, s, p->a.ctl, o->eps, max_rounds);
   ops.residual(p, s, 0);
   DAIC_HIP(hipEventRecord(p->ev0, s));
+  const size_t SS = sweep_state_size(p->st);
+  const uint32_t* tinv = w.tiles.tinv;
+  if (w.numbered) {  // the state into the block pulls' target numbering
+    perm_gather(w.a.v, w.ar.v, SS, tinv, n, s);
+    perm_gather(w.a.dv, w.ar.dv, SS, tinv, n, s);
+    if (w.a.c) perm_gather(w.a.c, w.ar.c, 4, tinv, n, s);
+    if (w.a.alpha_pv) perm_gather(w.a.alpha_pv, const_cast<void*>(w.ar.alpha_pv), SS, tinv, n, s);
+  }
+  auto unnumber = [&]() {
+    if (!w.numbered) return;
+    perm_scatter(w.ar.v, w.a.v, SS, tinv, n, s);
+    perm_scatter(w.ar.dv, w.a.dv, SS, tinv, n, s);
+    if (w.a.c) perm_scatter(w.ar.c, w.a.c, 4, tinv, n, s);
+  };
   const bool use_graph = std::getenv("DAIC_NO_GRAPH") == nullptr;
   GraphCacheKey key;
   key.sched = DAIC_SCHED_SWEEP;
@@ -794,8 +845,10 @@ daic_status sweep_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats
     DAIC_HIP(hipStreamSynchronize(s));
     if (p->h_ctl->done || p->h_ctl->stop) break;
     // every launch advances the round count; fail instead of spinning if not
-    if (p->h_ctl->rounds == seen_rounds)
+    if (p->h_ctl->rounds == seen_rounds) {
+      unnumber();
       return fail(DAIC_E_DEVICE, "sweep run made no progress (round %llu)", (unsigned long long)seen_rounds);
+    }
     seen_rounds = p->h_ctl->rounds;
     if (use_graph) {
       DAIC_HIP(hipGraphLaunch(p->exec, s));
@@ -804,6 +857,7 @@ daic_status sweep_run(daic_problem* p, const daic_run_opts* o, daic_stats* stats
     }
   }
   // deliver the messages in flight, then the exact residual of (v, dv)
+  unnumber();
   sw.deliver(w, s);
   hipLaunchKernelGGL(k_sweep_reopen, dim3(1), dim3(1), 0, s, p->a.ctl);
   ops.residual(p, s, 0);

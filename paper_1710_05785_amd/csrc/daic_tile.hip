@@ -136,9 +136,11 @@ TileTable tile_table(const uint32_t* pstart, uint64_t n_part, uint64_t TW, uint6
 // exact in-degrees 0.55 ms (as many pairs, but the id order inside an octave
 // keeps targets of nearby ids, which share senders, in one partition),
 // half-octaves 0.50 ms, quarter-range (powers of 4) 0.53 ms, ids alone 0.63 ms.
-__global__ void k_indeg_keys(const uint32_t* rowT, uint64_t n, uint32_t* key, uint32_t* val) {
+// Blocks of `block` ids come first in the key, so a block's targets keep its
+// id range (one block of all ids for fused rounds).
+__global__ void k_indeg_keys(const uint32_t* rowT, uint64_t n, uint64_t block, uint32_t* key, uint32_t* val) {
   for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x) {
-    key[j] = (uint32_t)__clz(rowT[j + 1] - rowT[j] + 1);
+    key[j] = (uint32_t)((j / block) << 6) | (uint32_t)__clz(rowT[j + 1] - rowT[j] + 1);
     val[j] = (uint32_t)j;
   }
 }
@@ -198,19 +200,17 @@ daic_status tile_prepare(daic_graph* g, hipStream_t s) {
   return tile_build(g->dev, g->pull.perm, lb, max_edges, 0, 0, g->tile, s);
 }
 
-daic_status tile_prepare_ranked(daic_graph* g, hipStream_t s) {
-  TileGraph& T = g->tile_r;
-  if (T.ready) return DAIC_OK;
-  if (!g->pull.ready) return fail(DAIC_E_INVALID, "tiled rounds need the renumbering of the in-edge form");
+daic_status rank_targets(const daic_graph* g, const uint32_t* perm, uint64_t block, uint32_t** trank_out,
+                         uint32_t** tinv_out, uint32_t** rowP_out, uint32_t** permP_out, hipStream_t s) {
   const uint64_t n = g->dev.n;
   uint32_t *key0 = nullptr, *key1 = nullptr, *val0 = nullptr, *val1 = nullptr, *trank = nullptr, *degP = nullptr;
   uint32_t *tinv = nullptr, *rowP = nullptr, *permP = nullptr;
   void* tmp = nullptr;
   auto release = [&](bool all) {
-    for (void* q : {(void*)key0, (void*)key1, (void*)val0, (void*)val1, (void*)trank, (void*)degP, tmp})
+    for (void* q : {(void*)key0, (void*)key1, (void*)val0, (void*)val1, (void*)degP, tmp})
       if (q) (void)hipFree(q);
     if (all)
-      for (void* q : {(void*)tinv, (void*)rowP, (void*)permP})
+      for (void* q : {(void*)trank, (void*)tinv, (void*)rowP, (void*)permP})
         if (q) (void)hipFree(q);
   };
 #define RCHK(call)                                                                                          \
@@ -218,11 +218,15 @@ daic_status tile_prepare_ranked(daic_graph* g, hipStream_t s) {
     hipError_t _e = (call);                                                                                 \
     if (_e != hipSuccess) {                                                                                 \
       release(true);                                                                                        \
-      return fail(_e == hipErrorOutOfMemory ? DAIC_E_OOM : DAIC_E_DEVICE, "ranked tiles: %s: %s", #call,   \
+      return fail(_e == hipErrorOutOfMemory ? DAIC_E_OOM : DAIC_E_DEVICE, "target numbering: %s: %s", #call, \
                   hipGetErrorString(_e));                                                                   \
     }                                                                                                       \
   } while (0)
   const uint64_t nn = std::max<uint64_t>(n, 1);
+  block = std::max<uint64_t>(block, 1);
+  uint32_t end_bit = 6;
+  while ((1ull << (end_bit - 6)) < (n + block - 1) / block) ++end_bit;
+  if (end_bit > 32) return fail(DAIC_E_INVALID, "target numbering: too many blocks");
   RCHK(hipMalloc(&key0, nn * 4));
   RCHK(hipMalloc(&key1, nn * 4));
   RCHK(hipMalloc(&val0, nn * 4));
@@ -232,35 +236,50 @@ daic_status tile_prepare_ranked(daic_graph* g, hipStream_t s) {
   RCHK(hipMalloc(&rowP, (n + 1) * 4));
   RCHK(hipMalloc(&permP, nn * 4));
   hipLaunchKernelGGL(k_indeg_keys, dim3(tgrid(n)), dim3(256), 0, s, static_cast<const uint32_t*>(g->pull.rowT), n,
-                     key0, val0);
+                     block, key0, val0);
   hipcub::DoubleBuffer<uint32_t> kb(key0, key1), vb(val0, val1);
   size_t need = 0, need2 = 0;
-  RCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kb, vb, (int)n, 0, 6, s));  // keys < 33
+  RCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kb, vb, (int)n, 0, (int)end_bit, s));
   RCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, need2, degP, rowP, (int)(n + 1), s));
   RCHK(hipMalloc(&tmp, std::max<size_t>(std::max(need, need2), 1)));
-  RCHK(hipcub::DeviceRadixSort::SortPairs(tmp, need, kb, vb, (int)n, 0, 6, s));
+  RCHK(hipcub::DeviceRadixSort::SortPairs(tmp, need, kb, vb, (int)n, 0, (int)end_bit, s));
   // the sorted values are the numbering's inverse; keep that buffer
   tinv = vb.Current();
   if (tinv == val0) val0 = nullptr;
   else val1 = nullptr;
   hipLaunchKernelGGL(k_rank_tables, dim3(tgrid(n)), dim3(256), 0, s, tinv, static_cast<const uint32_t*>(g->dev.row),
-                     g->pull.perm, n, trank, degP, permP);
+                     perm, n, trank, degP, permP);
   RCHK(hipcub::DeviceScan::ExclusiveSum(tmp, need2, degP, rowP, (int)(n + 1), s));
   RCHK(hipStreamSynchronize(s));
+#undef RCHK
+  release(false);
+  *trank_out = trank;
+  *tinv_out = tinv;
+  *rowP_out = rowP;
+  *permP_out = permP;
+  return DAIC_OK;
+}
+
+daic_status tile_prepare_ranked(daic_graph* g, hipStream_t s) {
+  TileGraph& T = g->tile_r;
+  if (T.ready) return DAIC_OK;
+  if (!g->pull.ready) return fail(DAIC_E_INVALID, "tiled rounds need the renumbering of the in-edge form");
+  uint32_t *trank = nullptr, *tinv = nullptr, *rowP = nullptr, *permP = nullptr;
+  daic_status rc = rank_targets(g, g->pull.perm, g->dev.n, &trank, &tinv, &rowP, &permP, s);
+  if (rc) return rc;
   uint32_t lb;
   uint64_t max_edges;
   tile_shape(g, &lb, &max_edges);
-  const daic_status rc = tile_build(g->dev, g->pull.perm, lb, max_edges, 0, 0, T, s, trank);
+  rc = tile_build(g->dev, g->pull.perm, lb, max_edges, 0, 0, T, s, trank);
+  (void)hipFree(trank);
   if (rc) {
-    release(true);
+    for (void* q : {(void*)tinv, (void*)rowP, (void*)permP}) (void)hipFree(q);
     return rc;
   }
-  release(false);
   T.tinv = tinv;
   T.rowP = rowP;
   T.permP = permP;
   return DAIC_OK;
-#undef RCHK
 }
 
 // Partition width and tile size of dense rounds on g.
