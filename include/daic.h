@@ -191,11 +191,12 @@ daic_status daic_problem_set_init_device(daic_problem* p, const void* d_v0, cons
  * DAIC_SCHED_ALL sum rounds fuse the next round's claim into the pull
  * (DAIC_NO_FUSE=1 keeps them apart, and so does DAIC_NO_GRAPH=1, which
  * launches every round eagerly instead of replaying captured groups). The pulls walk the in-edges in
- * partition tiles built once per graph (fused rounds: with targets numbered
- * by in-degree octave, highest first and ids ascending within an octave, the
- * state moved into that order while they run and back
- * before daic_run returns; DAIC_TILE_ID_ORDER=1 keeps partitions of
- * consecutive ids for them too; DAIC_NO_TILE=1 keeps the streamed
+ * partition tiles built once per graph (fused rounds and the sweep's block
+ * pulls: with targets numbered by in-degree octave, highest first and ids
+ * ascending within an octave, within each id block for the sweep, the state
+ * moved into that order while they run and back before daic_run returns;
+ * DAIC_TILE_ID_ORDER=1 keeps partitions of consecutive ids for them too;
+ * DAIC_NO_TILE=1 keeps the streamed
  * pull for sum problems and pushes for min/max; DAIC_TILE_EDGES and
  * DAIC_TILE_BITS, read when a graph's tiles are built, set the in-edges per
  * tile and the partition width 2^bits; the sweep schedule's tiles take
